@@ -1,0 +1,114 @@
+/*
+ * lrcc.h - C ABI of the MI355X (gfx950) k-blocked LR-CCSD sigma library.
+ *
+ * The library applies the CCSD Jacobian (the linear-response "sigma vector",
+ * the left-hand operator of the perturbed-amplitude equations, Sec. II.B,
+ * Eqs. tx1 and tx2) to batches of perturbed amplitudes X1(w), X2(w) of a 1D
+ * periodic system under crystal-momentum conservation (Sec. II.A,
+ * Eq. momentum), and solves the response equations for the frequency-
+ * dependent polarizability (Eq. lrf).
+ *
+ * Conventions shared by every entry point
+ *   - complex numbers are interleaved (re, im) IEEE doubles ("c128"): a
+ *     pointer to `double` addresses 2*count doubles;
+ *   - k = 0..nk-1 labels k_j = 2*pi*j/nk; n = nocc + nvir, occupied first;
+ *   - normalisation follows the paper: every two-electron quantity (the
+ *     integrals built from `chol`, T2, X2, sigma2) is the per-cell quantity
+ *     of Eqs. ene-lrf, i.e. Nk times the supercell-normalised one; one-
+ *     electron quantities (f, mu, T1, X1, sigma1) are unscaled;
+ *   - layouts (row-major):
+ *       fock  [nk][n][n]                       f_{p k, q k}
+ *       chol  [nk][nk][naux][n][n]             L^Q_{p k1, q k2}; integrals
+ *             (p k1 r k2 | q k3 s k4) = sum_Q L^Q_{p k1, r k2} conj(L^Q_{s k4, q k3})
+ *             for k2 - k1 = k3 - k4 (mod nk)
+ *       dip   [3][nk][n][n]                    <p k|mu_x|q k>
+ *       t1    [nk][nocc][nvir]                 t_{i k}^{a k}
+ *       t2    [nk][nk][nk][nocc][nocc][nvir][nvir]   blocks (ki,kj,ka),
+ *             kb = ki+kj-ka mod nk; antisymmetric in (i,j) and in (a,b)
+ *       x1/y1 [nrhs][nk][nocc][nvir], x2/y2 [nrhs][nk][nk][nk][o][o][v][v]
+ *   - ownership: the caller owns every buffer it passes; the library copies
+ *     inputs during the call and writes outputs only on success.  A context
+ *     owns its device memory; lrcc_destroy frees it.  A context is not
+ *     thread-safe; distinct contexts are independent.
+ *   - errors: every call returns an lrcc_status; nothing unwinds across the
+ *     ABI; lrcc_last_error() describes the last failure of that context.
+ */
+#ifndef LRCC_H
+#define LRCC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrcc_ctx lrcc_ctx;
+
+typedef enum {
+    LRCC_OK = 0,
+    LRCC_E_ARG = 1,      /* invalid argument (null pointer, bad size, broken symmetry) */
+    LRCC_E_SHAPE = 2,    /* sizes inconsistent with the context                        */
+    LRCC_E_STATE = 3,    /* call made before the inputs it needs were set               */
+    LRCC_E_OOM = 4,      /* device allocation failed or exceeds the memory cap          */
+    LRCC_E_HIP = 5,      /* HIP runtime error                                           */
+    LRCC_E_NOCONV = 6,   /* iterative solve did not reach the tolerance                 */
+    LRCC_E_SINGULAR = 7  /* response operator numerically singular at this frequency    */
+} lrcc_status;
+
+enum { LRCC_FP64 = 0, LRCC_FP32 = 1 };
+
+/* Create a context on HIP device `hip_device`. *out is NULL on failure. */
+lrcc_status lrcc_create(int hip_device, lrcc_ctx **out);
+
+/* Destroy a context and free its device memory. NULL-safe. */
+void lrcc_destroy(lrcc_ctx *ctx);
+
+/* Text of the last error of this context (empty string if none).  Valid until
+ * the next call on the same context.  ctx may be NULL (then: the last
+ * lrcc_create failure). */
+const char *lrcc_last_error(const lrcc_ctx *ctx);
+
+/* Set the periodic Hamiltonian (Sec. II.A): Fock matrix per k, Cholesky
+ * vectors of the two-electron integrals per k pair (momentum transfer
+ * k2 - k1), and the three dipole matrices per k.  Checks Hermiticity of fock
+ * and dip and the Hermitian pairing chol[k2][k1][Q] = conj(chol[k1][k2][Q])^T
+ * (relative tolerance 1e-10) -> LRCC_E_ARG.  Discards any amplitudes set
+ * before. */
+lrcc_status lrcc_set_hamiltonian(lrcc_ctx *ctx, int nk, int nocc, int nvir, int naux,
+                                 const double *fock, const double *chol, const double *dip);
+
+/* Set the converged ground-state amplitudes T1, T2 (Eqs. t1, t2; T2 in the
+ * paper's per-cell normalisation) and build every amplitude-dependent
+ * intermediate of the Jacobian once (the fixed "tilde" blocks of Sec. II.B).
+ * Checks the (i,j)/(a,b) antisymmetry of t2 (tolerance 1e-10) -> LRCC_E_ARG;
+ * before lrcc_set_hamiltonian -> LRCC_E_STATE. */
+lrcc_status lrcc_set_amplitudes(lrcc_ctx *ctx, const double *t1, const double *t2);
+
+/* Sigma vector for nrhs right-hand sides (Eqs. tx1, tx2 without -R and the
+ * denominators): y_r = (A - omega_r) x_r with A the CCSD Jacobian dOmega/dT.
+ * omega may be NULL (all zero).  x/y are HOST buffers in the layouts above.
+ * precision LRCC_FP64 computes in complex128; LRCC_FP32 in complex64 on the
+ * matrix cores (inputs and outputs stay complex128). */
+lrcc_status lrcc_apply_sigma(lrcc_ctx *ctx, int nrhs, const double *omega,
+                             const double *x1, const double *x2, double *y1, double *y2,
+                             int precision);
+
+/* Same as lrcc_apply_sigma on DEVICE buffers of the same layouts, enqueued on
+ * `stream` (a hipStream_t; NULL = the null stream).  Returns after enqueueing. */
+lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
+                                 const void *x1, const void *x2, void *y1, void *y2,
+                                 int precision, void *stream);
+
+/* Host-only validation of the launch plans for a problem size: records every
+ * kernel of lrcc_set_hamiltonian, lrcc_set_amplitudes and lrcc_apply_sigma (FP64
+ * and FP32, nrhs right-hand sides) without a device, checking that every
+ * address each matrix-core GEMM can form lies inside its operands.  Needs no
+ * GPU and allocates no device memory.  On failure writes a message into msg
+ * (msglen bytes, may be NULL) and returns LRCC_E_ARG (or LRCC_E_OOM). */
+lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char *msg, int msglen);
+
+/* Number of amplitude elements per right-hand side: singles and doubles. */
+lrcc_status lrcc_sizes(const lrcc_ctx *ctx, long long *n1, long long *n2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRCC_H */

@@ -1,0 +1,71 @@
+// Internal declarations shared by the HIP kernels and the host planner.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace lrcc {
+
+typedef long long i64;
+
+// Planning without a device: allocations return placeholder addresses, no
+// copies or launches happen, and every recorded GEMM is bounds-checked.
+extern bool g_dry_run;
+
+
+// Real type -> interleaved complex type used in device memory.
+template <typename T> struct Cx;
+template <> struct Cx<double> { typedef double2 type; };
+template <> struct Cx<float> { typedef float2 type; };
+
+// Three-level split of a GEMM index: idx = (i0*d1 + i1)*d2 + i2 and the
+// address contribution is i0*s[0] + i1*s[1] + i2*s[2] (units: complex elements).
+struct Split {
+    int d1, d2;
+};
+struct Strides {
+    i64 s[3];
+};
+__host__ __device__ inline i64 split_off(int idx, Split sp, Strides st) {
+    const int q = idx / sp.d2;
+    return (i64)(q / sp.d1) * st.s[0] + (i64)(q % sp.d1) * st.s[1] + (i64)(idx % sp.d2) * st.s[2];
+}
+
+// One strided complex GEMM over a list of output blocks ("jobs").
+// For job j: C_j[m][n] = beta*C_j[m][n] + alpha * sum_{s in segs(j)} sum_k A_s[m][k] B_s[k][n]
+//   A_s[m][k] = A + segA[s] + off(m; sm, Am) + off(k; sk, Ak)
+//   B_s[k][n] = B + segB[s] + off(k; sk, Bk) + off(n; sn, Bn)
+//   C_j[m][n] = C + offC[j] + off(m; sm, Cm) + off(n; sn, Cn)
+struct GemmArgs {
+    const void *A, *B;
+    void *C;
+    int M, N, K;
+    Split sm, sn, sk;
+    Strides Am, Ak, Bk, Bn, Cm, Cn;
+    int aMfast, bNfast;  // tile-load thread maps: 1 = run along m (resp. n)
+    double alpha_re, alpha_im;
+    int beta;
+    const i64 *offC;
+    const int *segBeg;   // njobs + 1
+    const i64 *segA, *segB;
+    int njobs;
+};
+
+template <typename T>
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+
+// Ladder: sigma2[ki,kj,ka][R][i][j][a][b] += alpha * sum_{ke} sum_{e,f}
+//   Y[ki,kj,ke][R][i][j][e][f] * sum_Q La[ka][ke][Q][a][e] * Lb[kb][kf][Q][b][f]
+struct LadderArgs {
+    const void *Y;       // [nk^3][R][o][o][v][v]
+    const void *La;      // [nk][nk][naux][v][v]
+    const void *Lb;      // [nk][nk][naux][v][v]
+    void *Z;             // output, same layout as Y (accumulated)
+    int nk, nrhs, o, v, naux;
+    double alpha;
+};
+template <typename T>
+hipError_t launch_ladder(const LadderArgs &a, hipStream_t s);
+
+}  // namespace lrcc

@@ -1,0 +1,246 @@
+// Streaming (HBM-bound) kernels of the sigma path: layout transposes between
+// the caller's rhs-major layout and the internal k-block-major layout, the
+// amplitude products entering tau (Eq. t2 and the perturbed analogue), the
+// final P_IJ P_AB antisymmetrisation with the -omega shift, Cholesky slices,
+// and precision conversion.  Grid-stride loops; consecutive threads touch
+// consecutive elements of the innermost (unit-stride) index.
+#include "common.hpp"
+#include "elem.hpp"
+
+namespace lrcc {
+
+namespace {
+inline unsigned grid_for(i64 n, int bs = 256) {
+    i64 g = (n + bs - 1) / bs;
+    if (g > 65536 * 4) g = 65536 * 4;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+template <typename T> __device__ inline typename Cx<T>::type mk(T x, T y) {
+    typename Cx<T>::type r; r.x = x; r.y = y; return r;
+}
+}
+
+// out[b][r][e] = scale * in[r][b][e]
+template <typename Tin, typename Tout>
+__global__ void k_rhs_to_block(const typename Cx<Tin>::type *in, typename Cx<Tout>::type *out,
+                               int R, i64 B, i64 E, double scale) {
+    const i64 n = (i64)R * B * E;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const i64 e = t % E, q = t / E;
+        const int r = (int)(q % R);
+        const i64 b = q / R;
+        auto v = in[((i64)r * B + b) * E + e];
+        out[t] = mk<Tout>((Tout)(scale * v.x), (Tout)(scale * v.y));
+    }
+}
+
+template <typename Tin, typename Tout>
+hipError_t rhs_to_block(const void *in, void *out, int R, i64 B, i64 E, double scale, hipStream_t s) {
+    hipLaunchKernelGGL((k_rhs_to_block<Tin, Tout>), dim3(grid_for((i64)R * B * E)), dim3(256), 0, s,
+                       (const typename Cx<Tin>::type *)in, (typename Cx<Tout>::type *)out, R, B, E, scale);
+    return hipGetLastError();
+}
+
+// out = x2 + c * (x_ia t_jb + t_ia x_jb - x_ib t_ja - t_ib x_ja), k-blocked, rhs inside the block.
+// x1 [nk][R][o][v], t1 [nk][o][v], x2/out [nk^3][R][o][o][v][v]
+template <typename T>
+__global__ void k_tau_like(const typename Cx<T>::type *x1, const typename Cx<T>::type *x2,
+                           const typename Cx<T>::type *t1, typename Cx<T>::type *out,
+                           int nk, int R, int o, int v, T c, int x1_has_rhs) {
+    const i64 inner = (i64)o * o * v * v;
+    const i64 n = (i64)nk * nk * nk * R * inner;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int b = (int)(q % v); q /= v;
+        const int a = (int)(q % v); q /= v;
+        const int j = (int)(q % o); q /= o;
+        const int i = (int)(q % o); q /= o;
+        const int r = (int)(q % R); q /= R;
+        const int ka = (int)(q % nk); q /= nk;
+        const int kj = (int)(q % nk); q /= nk;
+        const int ki = (int)q;
+        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        auto acc = x2[t];
+        T sr = 0, si = 0;
+        const int rx = x1_has_rhs ? r : 0;
+        const int Rx = x1_has_rhs ? R : 1;
+        auto X = [&](int k, int ii, int aa) { return x1[(((i64)k * Rx + rx) * o + ii) * v + aa]; };
+        auto Tt = [&](int k, int ii, int aa) { return t1[((i64)k * o + ii) * v + aa]; };
+        if (ka == ki) {     // x_ia t_jb + t_ia x_jb  (kb == kj)
+            auto p = X(ki, i, a), q2 = Tt(kj, j, b), u = Tt(ki, i, a), w = X(kj, j, b);
+            sr += p.x * q2.x - p.y * q2.y + u.x * w.x - u.y * w.y;
+            si += p.x * q2.y + p.y * q2.x + u.x * w.y + u.y * w.x;
+        }
+        if (kb == ki) {     // - x_ib t_ja - t_ib x_ja  (ka == kj)
+            auto p = X(ki, i, b), q2 = Tt(kj, j, a), u = Tt(ki, i, b), w = X(kj, j, a);
+            sr -= p.x * q2.x - p.y * q2.y + u.x * w.x - u.y * w.y;
+            si -= p.x * q2.y + p.y * q2.x + u.x * w.y + u.y * w.x;
+        }
+        out[t] = mk<T>(acc.x + c * sr, acc.y + c * si);
+    }
+}
+
+template <typename T>
+hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, int nk, int R, int o, int v,
+                    double c, int x1_has_rhs, hipStream_t s) {
+    const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
+    hipLaunchKernelGGL(k_tau_like<T>, dim3(grid_for(n)), dim3(256), 0, s,
+                       (const typename Cx<T>::type *)x1, (const typename Cx<T>::type *)x2,
+                       (const typename Cx<T>::type *)t1, (typename Cx<T>::type *)out, nk, R, o, v, (T)c,
+                       x1_has_rhs);
+    return hipGetLastError();
+}
+
+// y2[r][ki,kj,ka][i][j][a][b] = scale * (P_ij P_ab Z)[ki,kj,ka][r][i][j][a][b] - omega_r * x2[r][...]
+template <typename T>
+__global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, double2 *y2, const double *omega,
+                         int nk, int R, int o, int v, double scale) {
+    const i64 inner = (i64)o * o * v * v;
+    const i64 B = (i64)nk * nk * nk;
+    const i64 n = B * R * inner;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        // t indexes the caller layout [r][blk][i][j][a][b]
+        i64 q = t;
+        const int b = (int)(q % v); q /= v;
+        const int a = (int)(q % v); q /= v;
+        const int j = (int)(q % o); q /= o;
+        const int i = (int)(q % o); q /= o;
+        const i64 blk = q % B;
+        const int r = (int)(q / B);
+        const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
+        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
+            return Z[((((i64)(k0 * nk + k1) * nk + k2) * R + r) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
+        };
+        auto z1 = at(ki, kj, ka, i, j, a, b);
+        auto z2 = at(kj, ki, ka, j, i, a, b);
+        auto z3 = at(ki, kj, kb, i, j, b, a);
+        auto z4 = at(kj, ki, kb, j, i, b, a);
+        const double zr = (double)z1.x - (double)z2.x - (double)z3.x + (double)z4.x;
+        const double zi = (double)z1.y - (double)z2.y - (double)z3.y + (double)z4.y;
+        const double w = omega ? omega[r] : 0.0;
+        double2 xv = x2[t];
+        double2 out;
+        out.x = scale * zr - w * xv.x;
+        out.y = scale * zi - w * xv.y;
+        y2[t] = out;
+    }
+}
+
+template <typename T>
+hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, int nk, int R, int o, int v,
+                  double scale, hipStream_t s) {
+    const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
+    hipLaunchKernelGGL(k_pp_out<T>, dim3(grid_for(n)), dim3(256), 0, s, (const typename Cx<T>::type *)Z,
+                       (const double2 *)x2, (double2 *)y2, omega, nk, R, o, v, scale);
+    return hipGetLastError();
+}
+
+// y1[r][k][i][a] = s1[k][r][i][a] - omega_r x1[r][k][i][a]
+template <typename T>
+__global__ void k_s1_out(const typename Cx<T>::type *s1, const double2 *x1, double2 *y1, const double *omega,
+                         int nk, int R, int o, int v) {
+    const i64 E = (i64)o * v;
+    const i64 n = (i64)R * nk * E;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const i64 e = t % E;
+        const int k = (int)((t / E) % nk);
+        const int r = (int)(t / (E * nk));
+        auto sv = s1[((i64)k * R + r) * E + e];
+        const double w = omega ? omega[r] : 0.0;
+        double2 xv = x1[t];
+        double2 out;
+        out.x = (double)sv.x - w * xv.x;
+        out.y = (double)sv.y - w * xv.y;
+        y1[t] = out;
+    }
+}
+
+template <typename T>
+hipError_t s1_out(const void *s1, const void *x1, void *y1, const double *omega, int nk, int R, int o, int v,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_s1_out<T>, dim3(grid_for((i64)R * nk * o * v)), dim3(256), 0, s,
+                       (const typename Cx<T>::type *)s1, (const double2 *)x1, (double2 *)y1, omega, nk, R, o, v);
+    return hipGetLastError();
+}
+
+// Slice of Cholesky vectors: out[k1][k2][Q][p][q] = scale * L[k1][k2][Q][p0+p][q0+q]   (conj_pair = 0)
+//                            out[k1][k2][Q][p][q] = scale * conj(L[k2][k1][Q][q0+q][p0+p])  (conj_pair = 1)
+template <typename Tout>
+__global__ void k_chol_slice(const double2 *L, typename Cx<Tout>::type *out, int nk, int naux, int n, int p0,
+                             int np, int q0, int nq, double scale, int conj_pair) {
+    const i64 n_out = (i64)nk * nk * naux * np * nq;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n_out; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int qq = (int)(q % nq); q /= nq;
+        const int pp = (int)(q % np); q /= np;
+        const int Q = (int)(q % naux); q /= naux;
+        const int k2 = (int)(q % nk);
+        const int k1 = (int)(q / nk);
+        double2 v;
+        if (!conj_pair) {
+            v = L[(((i64)(k1 * nk + k2) * naux + Q) * n + (p0 + pp)) * n + (q0 + qq)];
+        } else {
+            v = L[(((i64)(k2 * nk + k1) * naux + Q) * n + (q0 + qq)) * n + (p0 + pp)];
+            v.y = -v.y;
+        }
+        out[t] = mk<Tout>((Tout)(scale * v.x), (Tout)(scale * v.y));
+    }
+}
+
+template <typename Tout>
+hipError_t chol_slice(const void *L, void *out, int nk, int naux, int n, int p0, int np, int q0, int nq,
+                      double scale, int conj_pair, hipStream_t s) {
+    hipLaunchKernelGGL(k_chol_slice<Tout>, dim3(grid_for((i64)nk * nk * naux * np * nq)), dim3(256), 0, s,
+                       (const double2 *)L, (typename Cx<Tout>::type *)out, nk, naux, n, p0, np, q0, nq, scale,
+                       conj_pair);
+    return hipGetLastError();
+}
+
+// Strided block copy of the 1E matrices: out[k][p][q] = in[k][p0+p][q0+q] (in: [nk][n][n])
+template <typename Tout>
+__global__ void k_one_body_slice(const double2 *in, typename Cx<Tout>::type *out, int nk, int n, int p0, int np,
+                                 int q0, int nq) {
+    const i64 N = (i64)nk * np * nq;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        const int qq = (int)(t % nq), pp = (int)((t / nq) % np), k = (int)(t / ((i64)nq * np));
+        double2 v = in[((i64)k * n + p0 + pp) * n + q0 + qq];
+        out[t] = mk<Tout>((Tout)v.x, (Tout)v.y);
+    }
+}
+
+template <typename Tout>
+hipError_t one_body_slice(const void *in, void *out, int nk, int n, int p0, int np, int q0, int nq, hipStream_t s) {
+    hipLaunchKernelGGL(k_one_body_slice<Tout>, dim3(grid_for((i64)nk * np * nq)), dim3(256), 0, s,
+                       (const double2 *)in, (typename Cx<Tout>::type *)out, nk, n, p0, np, q0, nq);
+    return hipGetLastError();
+}
+
+__global__ void k_convert(const double2 *in, float2 *out, i64 n) {
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        double2 v = in[t];
+        out[t] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)in, (float2 *)out, n);
+    return hipGetLastError();
+}
+
+#define INST(T)                                                                                              \
+    template hipError_t tau_like<T>(const void *, const void *, const void *, void *, int, int, int, int,    \
+                                    double, int, hipStream_t);                                               \
+    template hipError_t pp_out<T>(const void *, const void *, void *, const double *, int, int, int, int,    \
+                                  double, hipStream_t);                                                      \
+    template hipError_t s1_out<T>(const void *, const void *, void *, const double *, int, int, int, int,    \
+                                  hipStream_t);                                                              \
+    template hipError_t chol_slice<T>(const void *, void *, int, int, int, int, int, int, int, double, int,  \
+                                      hipStream_t);                                                          \
+    template hipError_t one_body_slice<T>(const void *, void *, int, int, int, int, int, int, hipStream_t);  \
+    template hipError_t rhs_to_block<double, T>(const void *, void *, int, i64, i64, double, hipStream_t);
+INST(double)
+INST(float)
+
+}  // namespace lrcc

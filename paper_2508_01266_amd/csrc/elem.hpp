@@ -1,0 +1,23 @@
+// Launchers of the streaming kernels (definitions in elem.hip).
+#pragma once
+#include "common.hpp"
+
+namespace lrcc {
+template <typename Tin, typename Tout>
+hipError_t rhs_to_block(const void *in, void *out, int R, i64 B, i64 E, double scale, hipStream_t s);
+template <typename T>
+hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, int nk, int R, int o, int v,
+                    double c, int x1_has_rhs, hipStream_t s);
+template <typename T>
+hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, int nk, int R, int o, int v,
+                  double scale, hipStream_t s);
+template <typename T>
+hipError_t s1_out(const void *s1, const void *x1, void *y1, const double *omega, int nk, int R, int o, int v,
+                  hipStream_t s);
+template <typename Tout>
+hipError_t chol_slice(const void *L, void *out, int nk, int naux, int n, int p0, int np, int q0, int nq,
+                      double scale, int conj_pair, hipStream_t s);
+template <typename Tout>
+hipError_t one_body_slice(const void *in, void *out, int nk, int n, int p0, int np, int q0, int nq, hipStream_t s);
+hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s);
+}  // namespace lrcc

@@ -1,0 +1,197 @@
+// Particle-particle ladder with the integral block rebuilt in LDS.
+//
+//   Z[ki,kj,ka][r][a][b] += alpha * sum_ke sum_{e,f} Y[ki,kj,ke][r][e][f] * W(ka,kb,ke)[e,f][a,b]
+//   W(ka,kb,ke)[e,f][a,b] = sum_Q La[ka][ke][Q][a][e] * Lb[kb][kf][Q][b][f]
+// with kb = ki+kj-ka, kf = ki+kj-ke and r = (rhs, i, j).  This is the vvvv term
+// of Eq. tx2 (the (1/2Nk) tbar_IJ^EF W_ABEF contraction) with the integrals
+// never stored: each 16x64 (ef)x(ab) tile of W is built in LDS as a
+// (a,e)x(b,f) rank-naux MFMA product of two Cholesky slices and immediately
+// consumed by the row tile.
+#include "common.hpp"
+
+namespace lrcc {
+
+template <typename T> struct MfmaL;
+template <> struct MfmaL<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct MfmaL<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+namespace {
+constexpr int LTM = 64;              // rows (rhs,i,j) per tile
+constexpr int TA = 8, TB = 8;        // (a,b) tile: 64 columns
+constexpr int TE = 4, TF = 4;        // (e,f) tile: 16 K values
+constexpr int LTN = TA * TB, LTK = TE * TF;
+constexpr int QC = 16;               // Cholesky vectors per LDS chunk
+constexpr int NTL = 256;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NTL) ladder_kernel(LadderArgs p) {
+    typedef typename Cx<T>::type C2;
+    typedef typename MfmaL<T>::v4 v4;
+    // LDS: rebuilt W tile, Y tile, Cholesky chunks
+    __shared__ T Wr[LTK][LTN], Wi[LTK][LTN];
+    __shared__ T Yr[LTK][LTM], Yi[LTK][LTM];
+    __shared__ T Pr[QC][TA * TE], Pi[QC][TA * TE];   // rows (a,e)
+    __shared__ T Qr[QC][TB * TF], Qi[QC][TB * TF];   // cols (b,f)
+
+    const int nk = p.nk, o = p.o, v = p.v, naux = p.naux;
+    const int M = p.nrhs * o * o;
+    const int tilesM = (M + LTM - 1) / LTM;
+    const int tilesA = (v + TA - 1) / TA;
+    const int mt = blockIdx.x % tilesM;
+    const int rest = blockIdx.x / tilesM;
+    const int a0 = (rest % tilesA) * TA;
+    const int b0 = (rest / tilesA) * TB;
+    const int blk = blockIdx.y;                       // (ki,kj,ka)
+    const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
+    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    const int m0 = mt * LTM;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const i64 vv = (i64)v * v;
+    const i64 blk4 = (i64)M * vv;                     // elements per (ki,kj,k) block
+
+    const C2 *Y = reinterpret_cast<const C2 *>(p.Y);
+    const C2 *La = reinterpret_cast<const C2 *>(p.La);
+    const C2 *Lb = reinterpret_cast<const C2 *>(p.Lb);
+    C2 *Z = reinterpret_cast<C2 *>(p.Z);
+
+    v4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+
+    // rebuild sub-tile owned by this wave: rows (a,e) 16*(wave&1).., cols (b,f) 16*(wave>>1)..
+    const int rw = 16 * (wave & 1), cw = 16 * (wave >> 1);
+
+    for (int ke = 0; ke < nk; ++ke) {
+        const int kf = ((ki + kj - ke) % nk + nk) % nk;
+        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
+        const C2 *Lab = La + (i64)(ka * nk + ke) * naux * vv;
+        const C2 *Lbb = Lb + (i64)(kb * nk + kf) * naux * vv;
+        for (int e0 = 0; e0 < v; e0 += TE) {
+            for (int f0 = 0; f0 < v; f0 += TF) {
+                // ---- rebuild W tile: G[(a,e)][(b,f)] = sum_Q La[Q][a][e] Lb[Q][b][f]
+                v4 gr = v4{0, 0, 0, 0}, gi = v4{0, 0, 0, 0};
+                for (int q0 = 0; q0 < naux; q0 += QC) {
+                    // 2 * QC * 32 complex loads; 256 threads -> 4 each
+                    for (int idx = tid; idx < 2 * QC * 32; idx += NTL) {
+                        const int which = idx / (QC * 32);
+                        const int rem = idx % (QC * 32);
+                        const int q = rem / 32, c = rem % 32;
+                        const int x = c / 4, y = c % 4;      // (a or b, e or f)
+                        C2 val; val.x = 0; val.y = 0;
+                        if (which == 0) {
+                            const int a = a0 + x, e = e0 + y;
+                            if (q0 + q < naux && a < v && e < v) val = Lab[(i64)(q0 + q) * vv + (i64)a * v + e];
+                            Pr[q][c] = val.x; Pi[q][c] = val.y;
+                        } else {
+                            const int b = b0 + x, f = f0 + y;
+                            if (q0 + q < naux && b < v && f < v) val = Lbb[(i64)(q0 + q) * vv + (i64)b * v + f];
+                            Qr[q][c] = val.x; Qi[q][c] = val.y;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int kk = 0; kk < QC; kk += 4) {
+                        const int kr = kk + (lane >> 4), c = lane & 15;
+                        const T xr = Pr[kr][rw + c], xi = Pi[kr][rw + c];
+                        const T yr = Qr[kr][cw + c], yi = Qi[kr][cw + c];
+                        gr = MfmaL<T>::mma(xr, yr, gr);
+                        gr = MfmaL<T>::mma(-xi, yi, gr);
+                        gi = MfmaL<T>::mma(xr, yi, gi);
+                        gi = MfmaL<T>::mma(xi, yr, gi);
+                    }
+                    __syncthreads();
+                }
+                // scatter G sub-tile into W[(e,f)][(a,b)]
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ae = rw + MfmaL<T>::row(lane, r);
+                    const int bf = cw + (lane & 15);
+                    const int a = ae / 4, e = ae % 4, b = bf / 4, f = bf % 4;
+                    Wr[e * TF + f][a * TB + b] = gr[r];
+                    Wi[e * TF + f][a * TB + b] = gi[r];
+                }
+                // ---- Y tile: rows m0.., K = (e,f)
+                for (int idx = tid; idx < LTM * LTK; idx += NTL) {
+                    const int kk = idx % LTK, m = idx / LTK;
+                    const int e = e0 + kk / TF, f = f0 + kk % TF;
+                    C2 val; val.x = 0; val.y = 0;
+                    if (m0 + m < M && e < v && f < v) val = Yb[(i64)(m0 + m) * vv + (i64)e * v + f];
+                    Yr[kk][m] = val.x; Yi[kk][m] = val.y;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < LTK; kk += 4) {
+                    const int kr = kk + (lane >> 4), c = lane & 15;
+                    T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) { ar[i] = Yr[kr][wm + 16 * i + c]; ai[i] = Yi[kr][wm + 16 * i + c]; }
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) { br[j] = Wr[kr][wn + 16 * j + c]; bi[j] = Wi[kr][wn + 16 * j + c]; }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
+                            accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
+                            acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
+                            acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
+                        }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // epilogue: Z block (ki,kj,ka) rows m, cols (a,b)
+    C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
+    const T al = (T)p.alpha;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + MfmaL<T>::row(lane, r);
+                const int c = wn + 16 * j + (lane & 15);
+                const int a = a0 + c / TB, b = b0 + c % TB;
+                if (m < M && a < v && b < v) {
+                    const i64 off = (i64)m * vv + (i64)a * v + b;
+                    C2 o2 = Zb[off];
+                    o2.x += al * accr[i][j][r];
+                    o2.y += al * acci[i][j][r];
+                    Zb[off] = o2;
+                }
+            }
+}
+
+template <typename T>
+hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
+    const int M = a.nrhs * a.o * a.o;
+    const int tilesM = (M + LTM - 1) / LTM;
+    const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
+    dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
+    hipLaunchKernelGGL(ladder_kernel<T>, grid, dim3(NTL), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_ladder<double>(const LadderArgs &, hipStream_t);
+template hipError_t launch_ladder<float>(const LadderArgs &, hipStream_t);
+
+}  // namespace lrcc

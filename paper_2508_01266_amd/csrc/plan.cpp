@@ -1,0 +1,265 @@
+// k-blocked contraction planner.  For a contraction C += alpha * A.B of
+// momentum-conserving block tensors it enumerates the allowed crystal-momentum
+// assignments (Eq. momentum: every two-electron block satisfies
+// k_p + k_q = k_r + k_s, so only Nk^3 of Nk^4 blocks exist and each free
+// k-sum of the paper's equations becomes a sum over segments), groups the
+// result by output block, and describes the dense block products as one
+// strided batched GEMM whose index groups read the blocks in place.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <map>
+
+namespace lrcc {
+
+bool g_dry_run = false;
+
+namespace {
+std::uintptr_t g_fake_next = 0x100000;
+}
+
+void *dev_alloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (g_dry_run) {
+        void *p = reinterpret_cast<void *>(g_fake_next);
+        g_fake_next += (bytes + 4095) / 4096 * 4096 + 4096;
+        return p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        throw LrccError(4, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+}
+
+void dev_free(void *p) {
+    if (!g_dry_run && p) (void)hipFree(p);
+}
+
+void *Program::alloc(size_t bytes) {
+    void *p = dev_alloc(bytes);
+    owned.push_back(p);
+    return p;
+}
+
+Program::~Program() {
+    for (void *p : owned) dev_free(p);
+}
+
+namespace {
+
+struct TInfo {
+    const KT *t;
+    std::string lab;
+    bool hasR;
+    std::vector<i64> stride;   // per label position
+    std::vector<int> extent;
+};
+
+TInfo info(const KT &t, const std::string &lab) {
+    TInfo r;
+    r.t = &t;
+    r.lab = lab;
+    r.hasR = !lab.empty() && lab[0] == 'R';
+    const int nl = (int)lab.size();
+    if (r.hasR != (t.nR > 0)) throw LrccError(1, "label/rhs mismatch for tensor labels " + lab);
+    if (nl - (r.hasR ? 1 : 0) != t.nidx()) throw LrccError(1, "label count mismatch: " + lab);
+    r.extent.resize(nl);
+    for (int p = 0; p < nl; ++p) r.extent[p] = (r.hasR && p == 0) ? t.nR : t.ext(p - (r.hasR ? 1 : 0));
+    r.stride.assign(nl, 1);
+    for (int p = nl - 2; p >= 0; --p) r.stride[p] = r.stride[p + 1] * r.extent[p + 1];
+    return r;
+}
+
+int pos(const TInfo &t, char c) {
+    size_t p = t.lab.find(c);
+    return p == std::string::npos ? -1 : (int)p;
+}
+
+// Split the label set into maximal runs adjacent (same order) in both tensors,
+// ordered by position in `q`.
+std::vector<std::vector<char>> chains(std::vector<char> set, const TInfo &p, const TInfo &q) {
+    std::sort(set.begin(), set.end(), [&](char a, char b) { return pos(q, a) < pos(q, b); });
+    std::vector<std::vector<char>> out;
+    for (char c : set) {
+        if (!out.empty()) {
+            char prev = out.back().back();
+            if (pos(q, c) == pos(q, prev) + 1 && pos(p, c) == pos(p, prev) + 1) {
+                out.back().push_back(c);
+                continue;
+            }
+        }
+        out.push_back({c});
+    }
+    return out;
+}
+
+void make_split(const std::vector<std::vector<char>> &ch, const TInfo &x, const TInfo &y, Split &sp,
+                Strides &sx, Strides &sy, int &total, const std::string &what) {
+    if (ch.size() > 3) throw LrccError(1, "contraction needs more than 3 index groups in " + what);
+    std::vector<int> ext;
+    std::vector<i64> stx, sty;
+    for (auto &c : ch) {
+        int e = 1;
+        for (char l : c) e *= x.extent[pos(x, l)];
+        ext.push_back(e);
+        stx.push_back(x.stride[pos(x, c.back())]);
+        sty.push_back(y.stride[pos(y, c.back())]);
+    }
+    while (ext.size() < 3) {
+        ext.insert(ext.begin(), 1);
+        stx.insert(stx.begin(), 0);
+        sty.insert(sty.begin(), 0);
+    }
+    sp.d1 = ext[1];
+    sp.d2 = ext[2];
+    total = ext[0] * ext[1] * ext[2];
+    for (int i = 0; i < 3; ++i) { sx.s[i] = stx[i]; sy.s[i] = sty[i]; }
+}
+
+inline int md(int a, int n) { return ((a % n) + n) % n; }
+
+// block index of tensor t for per-label momenta; -1 if the momenta violate t's rule
+i64 block_of(const TInfo &t, const std::map<char, int> &k) {
+    const KT &T = *t.t;
+    const int nk = T.nk;
+    const int off = t.hasR ? 1 : 0;
+    std::vector<int> ks;
+    for (int d = 0; d < T.nidx(); ++d) ks.push_back(k.at(t.lab[off + d]));
+    if (T.nidx() == 2) {
+        if (md(ks[0] - ks[1], nk) != 0) return -1;
+        return ks[0];
+    }
+    int s = 0;
+    for (int d = 0; d < 4; ++d) s += T.sg[d] * ks[d];
+    if (md(s, nk) != 0) return -1;
+    return ((i64)ks[0] * nk + ks[1]) * nk + ks[2];
+}
+
+}  // namespace
+
+namespace {
+i64 max_off(int total, Split sp, Strides st) {
+    if (total <= 0) return 0;
+    const int e0 = total / (sp.d1 * sp.d2);
+    return (i64)(e0 - 1) * st.s[0] + (i64)(sp.d1 - 1) * st.s[1] + (i64)(sp.d2 - 1) * st.s[2];
+}
+}  // namespace
+
+template <typename T>
+void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::vector<int> &segBeg,
+              const std::vector<i64> &segA, const std::vector<i64> &segB, i64 sizeA, i64 sizeB, i64 sizeC) {
+    g.njobs = (int)offC.size();
+    if (g.njobs == 0) return;
+    // every address formed by the kernel stays inside the operands
+    if (g.M % (g.sm.d1 * g.sm.d2) || g.N % (g.sn.d1 * g.sn.d2) || g.K % (g.sk.d1 * g.sk.d2))
+        throw LrccError(1, "GEMM split does not divide its dimension");
+    for (const Strides *st : {&g.Am, &g.Ak, &g.Bk, &g.Bn, &g.Cm, &g.Cn})
+        for (int i = 0; i < 3; ++i)
+            if (st->s[i] < 0) throw LrccError(1, "negative GEMM stride");
+    const i64 mA = max_off(g.M, g.sm, g.Am) + max_off(g.K, g.sk, g.Ak);
+    const i64 mB = max_off(g.K, g.sk, g.Bk) + max_off(g.N, g.sn, g.Bn);
+    const i64 mC = max_off(g.M, g.sm, g.Cm) + max_off(g.N, g.sn, g.Cn);
+    if ((int)segBeg.size() != g.njobs + 1 || segBeg.back() != (int)segA.size() || segA.size() != segB.size())
+        throw LrccError(1, "inconsistent GEMM job lists");
+    for (size_t s = 0; s < segA.size(); ++s)
+        if (segA[s] < 0 || segA[s] + mA >= sizeA || segB[s] < 0 || segB[s] + mB >= sizeB)
+            throw LrccError(1, "GEMM operand access out of bounds");
+    for (i64 o : offC)
+        if (o < 0 || o + mC >= sizeC) throw LrccError(1, "GEMM output access out of bounds");
+    i64 *dOff = (i64 *)P.alloc(offC.size() * sizeof(i64));
+    int *dBeg = (int *)P.alloc(segBeg.size() * sizeof(int));
+    i64 *dA = (i64 *)P.alloc(std::max<size_t>(1, segA.size()) * sizeof(i64));
+    i64 *dB = (i64 *)P.alloc(std::max<size_t>(1, segB.size()) * sizeof(i64));
+    if (!g_dry_run) {
+        bool ok = hipMemcpy(dOff, offC.data(), offC.size() * sizeof(i64), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(dBeg, segBeg.data(), segBeg.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        if (!segA.empty())
+            ok = ok && hipMemcpy(dA, segA.data(), segA.size() * sizeof(i64), hipMemcpyHostToDevice) == hipSuccess;
+        if (!segB.empty())
+            ok = ok && hipMemcpy(dB, segB.data(), segB.size() * sizeof(i64), hipMemcpyHostToDevice) == hipSuccess;
+        if (!ok) throw LrccError(5, "upload of GEMM job lists failed");
+    }
+    g.offC = dOff;
+    g.segBeg = dBeg;
+    g.segA = dA;
+    g.segB = dB;
+    P.flops += 8LL * g.M * g.N * g.K * (i64)segA.size();
+    P.ops.push_back([g](hipStream_t s) { return launch_gemm<T>(g, s); });
+}
+
+template <typename T>
+void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const std::string &al, const KT &B,
+              const std::string &bl, std::complex<double> alpha, bool accumulate) {
+    TInfo tc = info(C, cl), ta = info(A, al), tb = info(B, bl);
+    const std::string what = cl + " <- " + al + " * " + bl;
+    std::vector<char> Ml, Nl, Kl, free_k, sum_k;
+    std::string all = cl + al + bl;
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    for (char c : all) {
+        const bool inC = pos(tc, c) >= 0, inA = pos(ta, c) >= 0, inB = pos(tb, c) >= 0;
+        if (inC && inA && !inB) Ml.push_back(c);
+        else if (inC && inB && !inA) Nl.push_back(c);
+        else if (inA && inB && !inC) Kl.push_back(c);
+        else throw LrccError(1, std::string("label '") + c + "' must appear in exactly two operands: " + what);
+        if (c != 'R') (inC ? free_k : sum_k).push_back(c);
+    }
+    GemmArgs g{};
+    g.A = A.p;
+    g.B = B.p;
+    g.C = C.p;
+    make_split(chains(Ml, ta, tc), ta, tc, g.sm, g.Am, g.Cm, g.M, what);
+    make_split(chains(Nl, tb, tc), tb, tc, g.sn, g.Bn, g.Cn, g.N, what);
+    make_split(chains(Kl, tb, ta), ta, tb, g.sk, g.Ak, g.Bk, g.K, what);
+    g.aMfast = (g.Am.s[2] == 1) || (g.Ak.s[2] != 1);
+    g.bNfast = (g.Bn.s[2] == 1) || (g.Bk.s[2] != 1);
+    g.alpha_re = alpha.real();
+    g.alpha_im = alpha.imag();
+    g.beta = accumulate ? 1 : 0;
+
+    const int nk = C.nk;
+    std::vector<i64> offC, segA, segB;
+    std::vector<int> segBeg{0};
+    const i64 nblkC = C.nblocks();
+    i64 nsum = 1;
+    for (size_t i = 0; i < sum_k.size(); ++i) nsum *= nk;
+    for (i64 cb = 0; cb < nblkC; ++cb) {
+        std::map<char, int> k;
+        const int off = tc.hasR ? 1 : 0;
+        if (C.nidx() == 2) {
+            k[cl[off]] = (int)cb;
+            k[cl[off + 1]] = (int)cb;
+        } else {
+            int k0 = (int)(cb / (nk * nk)), k1 = (int)((cb / nk) % nk), k2 = (int)(cb % nk);
+            int s = C.sg[0] * k0 + C.sg[1] * k1 + C.sg[2] * k2;
+            k[cl[off]] = k0;
+            k[cl[off + 1]] = k1;
+            k[cl[off + 2]] = k2;
+            k[cl[off + 3]] = md(-C.sg[3] * s, nk);
+        }
+        const size_t before = segA.size();
+        for (i64 sidx = 0; sidx < nsum; ++sidx) {
+            i64 q = sidx;
+            for (char c : sum_k) { k[c] = (int)(q % nk); q /= nk; }
+            const i64 ba = block_of(ta, k), bb = block_of(tb, k);
+            if (ba < 0 || bb < 0) continue;
+            segA.push_back(ba * A.inner());
+            segB.push_back(bb * B.inner());
+        }
+        if (segA.size() == before && accumulate) continue;  // nothing to add to this block
+        offC.push_back(cb * C.inner());
+        segBeg.push_back((int)segA.size());
+    }
+    raw_gemm<T>(P, g, offC, segBeg, segA, segB, A.count(), B.count(), C.count());
+}
+
+template void contract<double>(Program &, const KT &, const std::string &, const KT &, const std::string &,
+                               const KT &, const std::string &, std::complex<double>, bool);
+template void contract<float>(Program &, const KT &, const std::string &, const KT &, const std::string &,
+                              const KT &, const std::string &, std::complex<double>, bool);
+template void raw_gemm<double>(Program &, GemmArgs, const std::vector<i64> &, const std::vector<int> &,
+                               const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64);
+template void raw_gemm<float>(Program &, GemmArgs, const std::vector<i64> &, const std::vector<int> &,
+                              const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64);
+
+}  // namespace lrcc

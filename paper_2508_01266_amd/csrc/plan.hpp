@@ -1,0 +1,78 @@
+// Host-side planner: k-blocked tensors and their contractions as GEMM job lists.
+#pragma once
+#include <complex>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace lrcc {
+
+// A momentum-conserving tensor stored as dense blocks (Sec. II.A, Eq. momentum).
+// Indices have class 'o' or 'v'.  Four-index tensors obey
+// sg[0] k0 + sg[1] k1 + sg[2] k2 + sg[3] k3 = 0 (mod nk) and are stored as
+// [k0][k1][k2] blocks (k3 implied); two-index tensors are k-diagonal, [k0]
+// blocks.  An optional right-hand-side axis of extent nR sits at the start of
+// every block: block = [R][d0][d1]...  Elements are interleaved complex.
+struct KT {
+    void *p = nullptr;
+    std::string cls;
+    int sg[4] = {1, 1, -1, -1};
+    int nR = 0;
+    int nk = 0, no = 0, nv = 0;
+    int nidx() const { return (int)cls.size(); }
+    int ext(int d) const { return cls[d] == 'o' ? no : nv; }
+    i64 inner() const {
+        i64 e = nR > 0 ? nR : 1;
+        for (int d = 0; d < nidx(); ++d) e *= ext(d);
+        return e;
+    }
+    i64 nblocks() const {
+        i64 b = 1;
+        for (int d = 0; d < nidx() - 1; ++d) b *= nk;
+        return b;
+    }
+    i64 count() const { return inner() * nblocks(); }
+};
+
+struct LrccError : std::runtime_error {
+    int code;
+    LrccError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+// A recorded sequence of device launches plus the device memory it owns.
+struct Program {
+    std::vector<std::function<hipError_t(hipStream_t)>> ops;
+    std::vector<void *> owned;
+    i64 flops = 0;  // executed real flops of the recorded GEMMs (incl. zero padding excluded)
+    hipError_t run(hipStream_t s) {
+        for (auto &op : ops) {
+            hipError_t e = op(s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    void *alloc(size_t bytes);
+    ~Program();
+};
+
+// C[cl] (+)= alpha * sum A[al] B[bl]; labels are one character per index, 'R'
+// for the right-hand-side axis (first in a label string when present).
+template <typename T>
+void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const std::string &al, const KT &B,
+              const std::string &bl, std::complex<double> alpha, bool accumulate = true);
+
+// Raw strided GEMM with explicit job/segment lists (host vectors are uploaded).
+// sizeA/B/C are the element counts of the operands: every address the GEMM can
+// form is checked against them before the launch is recorded.
+template <typename T>
+void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::vector<int> &segBeg,
+              const std::vector<i64> &segA, const std::vector<i64> &segB, i64 sizeA, i64 sizeB, i64 sizeC);
+
+// Placeholder-or-real device allocation honouring g_dry_run.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
+}  // namespace lrcc

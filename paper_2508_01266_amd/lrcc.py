@@ -1,0 +1,134 @@
+"""ctypes binding of liblrcc.so.  Argument marshalling only: every step of the
+sigma path runs in the library's HIP kernels.  Raises if the library is not
+built; there is no fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+FP64, FP32 = 0, 1
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrcc.so")
+_lib = None
+
+_STATUS = {0: "LRCC_OK", 1: "LRCC_E_ARG", 2: "LRCC_E_SHAPE", 3: "LRCC_E_STATE", 4: "LRCC_E_OOM",
+           5: "LRCC_E_HIP", 6: "LRCC_E_NOCONV", 7: "LRCC_E_SINGULAR"}
+
+
+class LrccError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        L.lrcc_create.argtypes = [i, ctypes.POINTER(vp)]
+        L.lrcc_destroy.argtypes = [vp]
+        L.lrcc_destroy.restype = None
+        L.lrcc_last_error.argtypes = [vp]
+        L.lrcc_last_error.restype = ctypes.c_char_p
+        L.lrcc_set_hamiltonian.argtypes = [vp, i, i, i, i, vp, vp, vp]
+        L.lrcc_set_amplitudes.argtypes = [vp, vp, vp]
+        L.lrcc_apply_sigma.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
+        L.lrcc_apply_sigma_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
+        L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
+        L.lrcc_plan_check.restype = ctypes.c_int
+        L.lrcc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+        for f in ("lrcc_create", "lrcc_set_hamiltonian", "lrcc_set_amplitudes", "lrcc_apply_sigma",
+                  "lrcc_apply_sigma_dev", "lrcc_sizes"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _c128(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def plan_check(nk, nocc, nvir, naux, nrhs):
+    """Host-only validation of all launch plans for a problem size (no GPU needed)."""
+    buf = ctypes.create_string_buffer(512)
+    st = lib().lrcc_plan_check(nk, nocc, nvir, naux, nrhs, buf, 512)
+    if st != 0:
+        raise LrccError(st, buf.value.decode())
+
+
+class Context:
+    """One library context on HIP device `device` (owns its device memory)."""
+
+    def __init__(self, device=0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        st = self._L.lrcc_create(int(device), ctypes.byref(h))
+        if st != 0:
+            raise LrccError(st, self._L.lrcc_last_error(None).decode())
+        self._h = h
+        self.shape = None
+
+    def _check(self, st):
+        if st != 0:
+            raise LrccError(st, self._L.lrcc_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lrcc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hamiltonian(self, nocc, fock, chol, dip):
+        """fock [nk][n][n], chol [nk][nk][naux][n][n], dip [3][nk][n][n] (complex128)."""
+        nk, n = fock.shape[0], fock.shape[1]
+        naux = chol.shape[2]
+        f, c, d = (_c128(fock, (nk, n, n)), _c128(chol, (nk, nk, naux, n, n)), _c128(dip, (3, nk, n, n)))
+        self.nk, self.n, self.naux = nk, n, naux
+        self.no, self.nv = nocc, n - nocc
+        self._check(self._L.lrcc_set_hamiltonian(self._h, self.nk, self.no, self.nv, self.naux,
+                                                  _ptr(f), _ptr(c), _ptr(d)))
+
+    def set_amplitudes(self, t1, t2):
+        nk, o, v = self.nk, self.no, self.nv
+        a = _c128(t1, (nk, o, v))
+        b = _c128(t2, (nk, nk, nk, o, o, v, v))
+        self._check(self._L.lrcc_set_amplitudes(self._h, _ptr(a), _ptr(b)))
+
+    def apply_sigma(self, x1, x2, omega=None, precision=FP64):
+        nk, o, v = self.nk, self.no, self.nv
+        R = x1.shape[0]
+        a = _c128(x1, (R, nk, o, v))
+        b = _c128(x2, (R, nk, nk, nk, o, o, v, v))
+        y1 = np.empty_like(a)
+        y2 = np.empty_like(b)
+        om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+        self._check(self._L.lrcc_apply_sigma(self._h, R, None if om is None else _ptr(om), _ptr(a), _ptr(b),
+                                             _ptr(y1), _ptr(y2), int(precision)))
+        return y1, y2
+
+    def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None):
+        """Device-pointer variant for torch tensors (complex128, caller layouts)."""
+        R = x1.shape[0]
+        st = self._L.lrcc_apply_sigma_dev(
+            self._h, R, None if omega is None else ctypes.c_void_p(omega.data_ptr()),
+            ctypes.c_void_p(x1.data_ptr()), ctypes.c_void_p(x2.data_ptr()),
+            ctypes.c_void_p(y1.data_ptr()), ctypes.c_void_p(y2.data_ptr()), int(precision),
+            None if stream is None else ctypes.c_void_p(stream))
+        self._check(st)

@@ -1,0 +1,38 @@
+"""Seeded sigma parity cases: library inputs (k-blocked, paper normalisation)
+and the oracle's expected outputs for them."""
+import numpy as np
+import torch
+
+import synth
+from oracle import ccsd, layout, response
+
+
+def make_case(nk, o, v, naux, nrhs, seed, tscale=0.02, band_shift=True):
+    rng = synth.rng_for(500 + seed, nk, o, v)
+    H = synth.hamiltonian(nk, o, v, naux, rng, band_shift=band_shift)
+    t1k, t2k_cr = synth.random_amplitudes(nk, o, v, rng, tscale, tscale)
+    x1k, x2k_cr = synth.random_vectors(nrhs, nk, o, v, rng, 0.1, 0.1)
+    omega = np.linspace(-0.1, 0.1, nrhs) if nrhs > 1 else np.array([0.0656])
+    # library inputs use the paper's per-cell normalisation: 2E quantities x Nk
+    return dict(nk=nk, o=o, v=v, naux=naux, H=H, t1=t1k, t2=t2k_cr * nk, x1=x1k, x2=x2k_cr * nk,
+                omega=omega)
+
+
+def oracle_sigma(case):
+    nk, o, v = case['nk'], case['o'], case['v']
+    H = case['H']
+    f = layout.dense_one_body(H['fock'], nk, o, v)
+    g = layout.dense_eri(H['chol'], nk, o, v)
+    h = ccsd.DenseHam.from_numpy(f, g, nk * o)
+    t = (torch.from_numpy(layout.dense_t1(case['t1'], nk, o, v)),
+         torch.from_numpy(layout.dense_t2(case['t2'] / nk, nk, o, v)))
+    y1 = np.empty_like(case['x1'])
+    y2 = np.empty_like(case['x2'])
+    for r in range(case['x1'].shape[0]):
+        x = (torch.from_numpy(layout.dense_t1(case['x1'][r], nk, o, v)),
+             torch.from_numpy(layout.dense_t2(case['x2'][r] / nk, nk, o, v)))
+        s1, s2 = response.sigma(t, x, h)
+        w = case['omega'][r]
+        y1[r] = layout.block_t1(s1.numpy(), nk, o, v) - w * case['x1'][r]
+        y2[r] = nk * layout.block_t2(s2.numpy(), nk, o, v) - w * case['x2'][r]
+    return y1, y2
