@@ -1,0 +1,178 @@
+"""Benchmark of the k-blocked LR-CCSD sigma path on one MI355X.
+
+A step is one application of the CCSD Jacobian (the sigma vector of the
+perturbed-amplitude equations) to the whole batch of right-hand sides of the
+workload, with inputs resident in HBM.  The default workload is the batched
+one: Nk=5, nocc=8, nvir=40, Naux=144, 3 axes x +-omega x 8 frequencies = 48
+right-hand sides in one launch, computed on the matrix cores in complex64
+(split into real fp32 MFMA products).  The FP64 form of the same batch is
+timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1 GPU"
+PEAK = {"f32": 157.3, "f64": 78.6}          # MI355X dense matrix-core TFLOP/s
+
+
+def sigma_alg_flops(nk, o, v):
+    """Algorithmic real flops of one sigma for one right-hand side: 8 per complex
+    multiply-add over full index ranges of the ladder (Nk^4 o^2 v^4), ring and
+    t1/tau dressing (2 Nk^4 o^3 v^3), hole-hole terms (3 Nk^4 o^4 v^2) and the
+    remaining one- and two-index terms (4 Nk^3 (o^2 v^3 + o^3 v^2))."""
+    return 8.0 * nk ** 4 * (o ** 2 * v ** 4 + 2 * o ** 3 * v ** 3 + 3 * o ** 4 * v ** 2) \
+        + 32.0 * nk ** 3 * (o ** 2 * v ** 3 + o ** 3 * v ** 2)
+
+
+def ladder_alg_flops(nk, o, v):
+    return 8.0 * nk ** 4 * o ** 2 * v ** 4
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload_inputs(name):
+    import numpy as np
+    import synth
+    w = synth.WORKLOADS[name]
+    rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift)
+    # synthetic amplitudes with the structure (antisymmetry, momentum) of CCSD ones
+    t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
+    pairs = synth.omega_grid(w)
+    nrhs = 3 * len(pairs)
+    x1, x2 = synth.random_vectors(nrhs, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
+    omega = np.array([s * om for _ in range(3) for (om, s) in pairs])
+    return w, H, t1, t2 * w.nk, x1, x2 * w.nk, omega
+
+
+def time_sigma(ctx, x1, x2, y1, y2, om, prec, steps, warmup, torch):
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(warmup):
+        ctx.apply_sigma_dev(x1, x2, y1, y2, om, prec, stream)
+    torch.cuda.synchronize()
+    ctx.read_profile()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.apply_sigma_dev(x1, x2, y1, y2, om, prec, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    prof = ctx.read_profile()
+    return (t1 - t0) / steps, prof
+
+
+def cpu_baseline(w, H, t1, t2, x1, x2, nrhs):
+    """The oracle's sigma on a bounded sample: the oracle computes A x as the exact
+    5-point stencil of the CCSD residual, i.e. four residual evaluations per
+    right-hand side.  One of those four evaluations (for one right-hand side) is
+    timed after the integral blocks are built (their build, like the library's
+    set-up, is outside the timed region) and the rate is scaled by 4."""
+    import torch
+    from oracle import kblock
+    nk = w.nk
+    ham = kblock.KHam(H['fock'], H['chol'], w.nocc)
+    for cls in ('oovv', 'ovvv', 'ooov', 'ovvo', 'ovoo', 'oooo', 'vvvo', 'vvoo', 'vvvv', 'vovv', 'oovo', 'ovov'):
+        ham.eri(cls)
+    T1 = kblock.t1_kt(t1 + 1e-3 * x1, nk)
+    T2 = kblock.t2_kt((t2 + 1e-3 * x2) / nk, nk)
+    t0 = time.perf_counter()
+    kblock.residual(ham, T1, T2)
+    dt = 4 * (time.perf_counter() - t0)
+    flops = sigma_alg_flops(nk, w.nocc, w.nvir)
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"1 of {nrhs} right-hand sides of the same workload, fp64: one of the four residual "
+                      f"evaluations of the oracle's 5-point stencil sigma (k-blocked oracle tier) timed "
+                      f"({dt / 4:.1f} s) and scaled by 4"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
+              "not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2508_01266_amd as lr
+
+    log(f"generating inputs for {args.workload}")
+    w, H, t1, t2, x1, x2, omega = workload_inputs(args.workload)
+    nk, o, v = w.nk, w.nocc, w.nvir
+    log("inputs ready; building library context")
+    nrhs = len(omega)
+    dev = torch.device("cuda:0")
+    ctx = lr.Context(0)
+    ctx.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+    ctx.set_amplitudes(t1, t2)
+    X1 = torch.from_numpy(x1).to(dev)
+    X2 = torch.from_numpy(x2).to(dev)
+    sample = (x1[0].copy(), x2[0].copy())
+    Y1 = torch.empty_like(X1)
+    Y2 = torch.empty_like(X2)
+    OM = torch.from_numpy(omega).to(dev)
+    del x1, x2
+
+    alg = nrhs * sigma_alg_flops(nk, o, v)
+    lad = nrhs * ladder_alg_flops(nk, o, v)
+    log("context ready; timing complex64 sigma")
+    dt32, prof32 = time_sigma(ctx, X1, X2, Y1, Y2, OM, lr.FP32, args.steps, args.warmup, torch)
+    log(f"complex64 sigma {dt32*1e3:.1f} ms; timing complex128 sigma")
+    dt64, prof64 = time_sigma(ctx, X1, X2, Y1, Y2, OM, lr.FP64, args.fp64_steps, 1, torch)
+    lad_ms, lad_n = prof32["ladder"]
+    lad_avg = lad_ms / max(lad_n, 1) / 1e3
+    lad64_ms, lad64_n = prof64["ladder"]
+    achieved = lad / lad_avg / 1e12
+    out = {
+        "metric": METRIC,
+        "value": alg / dt32 / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 1D chain Nk={nk}, nocc={o}, nvir={v}, Naux={w.naux}, "
+                               f"{nrhs} right-hand sides (3 axes x +-omega x {len(w.omegas)} frequencies) "
+                               f"in one sigma launch, complex64 on the matrix cores",
+                   "nk": nk, "nocc": o, "nvir": v, "naux": w.naux, "nrhs": nrhs},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["f32"], "traffic": None, "kernel": "ladder",
+                     "ladder_ms_avg": lad_avg * 1e3},
+        "fp64": {"value": alg / dt64 / 1e12, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
+                 "ladder_achieved": lad / (lad64_ms / max(lad64_n, 1) / 1e3) / 1e12, "peak": PEAK["f64"]},
+        "executed_flops_per_step": {"f32": ctx.sigma_flops(nrhs, lr.FP32), "f64": ctx.sigma_flops(nrhs, lr.FP64)},
+        "algorithmic_flops_per_step": alg,
+        "speedup_mixed_vs_fp64_sigma": dt64 / dt32,
+    }
+    log(f"complex128 sigma {dt64*1e3:.1f} ms")
+    if not args.no_cpu:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(w, H, t1, t2, sample[0], sample[1], nrhs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,20 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
                                  const void *x1, const void *x2, void *y1, void *y2,
                                  int precision, void *stream);
 
+/* Kernel timing with HIP events recorded on the launch stream.  While enabled,
+ * every sigma application records an event pair around each ladder launch and
+ * around the whole application.  lrcc_read_profile waits for the recorded
+ * events and returns, per category, the summed milliseconds and the number of
+ * timed launches: index 0 unused, 1 = ladder kernel, 2 = whole sigma
+ * application (arrays of 3); it then clears the record. */
+lrcc_status lrcc_set_profiling(lrcc_ctx *ctx, int enable);
+lrcc_status lrcc_read_profile(lrcc_ctx *ctx, double *ms, long long *count);
+
+/* Real floating-point operations executed by one sigma application for nrhs
+ * right-hand sides (matrix-core GEMMs and ladder, including the in-LDS
+ * integral rebuild; streaming kernels excluded). */
+lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
+
 /* Host-only validation of the launch plans for a problem size: records every
  * kernel of lrcc_set_hamiltonian, lrcc_set_amplitudes and lrcc_apply_sigma (FP64
  * and FP32, nrhs right-hand sides) without a device, checking that every

@@ -67,5 +67,7 @@ struct LadderArgs {
 };
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s);
+// real flops the ladder kernel executes (tile padding and LDS rebuild included)
+double ladder_executed_flops(const LadderArgs &a);
 
 }  // namespace lrcc

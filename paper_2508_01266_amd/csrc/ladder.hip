@@ -191,6 +191,17 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+double ladder_executed_flops(const LadderArgs &a) {
+    const int M = a.nrhs * a.o * a.o;
+    const double tilesM = (M + LTM - 1) / LTM, tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
+    const double kt = (double)((a.v + TE - 1) / TE) * ((a.v + TF - 1) / TF) * a.nk;
+    const double nb = (double)a.nk * a.nk * a.nk;
+    const double qpad = (double)((a.naux + QC - 1) / QC) * QC;
+    const double main = nb * tilesM * tA * tB * kt * 8.0 * LTM * LTN * LTK;
+    const double rebuild = nb * tilesM * tA * tB * kt * 8.0 * (TA * TE) * (TB * TF) * qpad;
+    return main + rebuild;
+}
+
 template hipError_t launch_ladder<double>(const LadderArgs &, hipStream_t);
 template hipError_t launch_ladder<float>(const LadderArgs &, hipStream_t);
 

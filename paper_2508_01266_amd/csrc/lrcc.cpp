@@ -85,6 +85,7 @@ struct lrcc_ctx {
     DevMem stage;
     size_t stage_bytes = 0;
     void *st_x1 = nullptr, *st_x2 = nullptr, *st_y1 = nullptr, *st_y2 = nullptr, *st_om = nullptr;
+    Profiler prof;
 };
 
 static std::string g_create_err;
@@ -426,7 +427,8 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, int prec) {
         la.naux = naux;
         la.alpha = 0.25;
         P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
-        P->flops += 8LL * nk * nk * nk * nk * R * o * o * (i64)v * v * v * v;
+        P->tag_last(TAG_LADDER);
+        P->flops += (i64)ladder_executed_flops(la);
     }
     contract<T>(*P, Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false);
     contract<T>(*P, Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16);
@@ -637,7 +639,7 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *c, int nrhs, const double *omega, con
         if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
         Program *p = sigma_program(c, precision, nrhs);
         c->io_x1 = x1; c->io_x2 = x2; c->io_y1 = y1; c->io_y2 = y2; c->io_omega = omega;
-        HIPCHK(p->run((hipStream_t)stream));
+        HIPCHK(p->run((hipStream_t)stream, &c->prof));
     });
 }
 
@@ -667,6 +669,25 @@ lrcc_status lrcc_apply_sigma(lrcc_ctx *c, int nrhs, const double *omega, const d
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(y1, c->st_y1, b1, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(y2, c->st_y2, b2, hipMemcpyDeviceToHost));
+    });
+}
+
+lrcc_status lrcc_set_profiling(lrcc_ctx *c, int enable) {
+    return guarded(c, [&] { c->prof.on = enable != 0; });
+}
+
+lrcc_status lrcc_read_profile(lrcc_ctx *c, double *ms, long long *count) {
+    return guarded(c, [&] {
+        if (!ms || !count) throw LrccError(LRCC_E_ARG, "null output");
+        c->prof.read(ms, count);
+    });
+}
+
+lrcc_status lrcc_sigma_flops(lrcc_ctx *c, int nrhs, int precision, double *executed) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!executed || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
+        *executed = (double)sigma_program(c, precision, nrhs)->flops;
     });
 }
 

@@ -32,7 +32,10 @@ void *dev_alloc(size_t bytes) {
 }
 
 void dev_free(void *p) {
-    if (!g_dry_run && p) (void)hipFree(p);
+    if (!g_dry_run && p) {
+        hipError_t e = hipFree(p);
+        (void)e;
+    }
 }
 
 void *Program::alloc(size_t bytes) {
@@ -43,6 +46,71 @@ void *Program::alloc(size_t bytes) {
 
 Program::~Program() {
     for (void *p : owned) dev_free(p);
+}
+
+hipError_t Program::run(hipStream_t s, Profiler *prof) {
+    tags.resize(ops.size(), TAG_NONE);
+    const bool timed = prof && prof->on;
+    hipEvent_t p0 = nullptr, p1 = nullptr;
+    if (timed) {
+        p0 = prof->ev();
+        p1 = prof->ev();
+        hipError_t e = hipEventRecord(p0, s);
+        if (e != hipSuccess) return e;
+    }
+    for (size_t i = 0; i < ops.size(); ++i) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (timed && tags[i] != TAG_NONE) {
+            a = prof->ev();
+            b = prof->ev();
+            hipError_t e = hipEventRecord(a, s);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = ops[i](s);
+        if (e != hipSuccess) return e;
+        if (a) {
+            e = hipEventRecord(b, s);
+            if (e != hipSuccess) return e;
+            prof->record(tags[i], a, b);
+        }
+    }
+    if (timed) {
+        hipError_t e = hipEventRecord(p1, s);
+        if (e != hipSuccess) return e;
+        prof->record(TAG_PROGRAM, p0, p1);
+    }
+    return hipSuccess;
+}
+
+hipEvent_t Profiler::ev() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) throw LrccError(5, "hipEventCreate failed");
+    return e;
+}
+
+void Profiler::read(double *ms, long long *cnt) {
+    for (int t = 0; t < NTAGS; ++t) { ms[t] = 0; cnt[t] = 0; }
+    for (auto &m : marks) {
+        float x = 0;
+        if (hipEventSynchronize(m.second.second) != hipSuccess ||
+            hipEventElapsedTime(&x, m.second.first, m.second.second) != hipSuccess)
+            throw LrccError(5, "event timing failed");
+        ms[m.first] += x;
+        cnt[m.first] += 1;
+        pool.push_back(m.second.first);
+        pool.push_back(m.second.second);
+    }
+    marks.clear();
+}
+
+Profiler::~Profiler() {
+    for (auto &m : marks) { pool.push_back(m.second.first); pool.push_back(m.second.second); }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
 namespace {

@@ -42,18 +42,34 @@ struct LrccError : std::runtime_error {
     LrccError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// Event timing of recorded launches: pairs of events recorded on the launch
+// stream around every op with a given tag (and around whole program runs).
+enum { TAG_NONE = 0, TAG_LADDER = 1, TAG_PROGRAM = 2, NTAGS = 3 };
+struct Profiler {
+    bool on = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t ev();
+    hipError_t record(int tag, hipEvent_t a, hipEvent_t b) {
+        marks.push_back({tag, {a, b}});
+        return hipSuccess;
+    }
+    // sums (ms, count) per tag, recycles the events
+    void read(double *ms, long long *cnt);
+    ~Profiler();
+};
+
 // A recorded sequence of device launches plus the device memory it owns.
 struct Program {
     std::vector<std::function<hipError_t(hipStream_t)>> ops;
+    std::vector<int> tags;  // per op (TAG_NONE unless set by tag_last)
     std::vector<void *> owned;
-    i64 flops = 0;  // executed real flops of the recorded GEMMs (incl. zero padding excluded)
-    hipError_t run(hipStream_t s) {
-        for (auto &op : ops) {
-            hipError_t e = op(s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+    i64 flops = 0;  // executed real flops of the recorded GEMMs and ladder
+    void tag_last(int t) {
+        tags.resize(ops.size(), TAG_NONE);
+        tags.back() = t;
     }
+    hipError_t run(hipStream_t s, Profiler *prof = nullptr);
     void *alloc(size_t bytes);
     ~Program();
 };

@@ -39,6 +39,11 @@ def lib():
         L.lrcc_set_amplitudes.argtypes = [vp, vp, vp]
         L.lrcc_apply_sigma.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
         L.lrcc_apply_sigma_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
+        L.lrcc_set_profiling.argtypes = [vp, i]
+        L.lrcc_read_profile.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.lrcc_sigma_flops.argtypes = [vp, i, i, dp]
+        for f in ("lrcc_set_profiling", "lrcc_read_profile", "lrcc_sigma_flops"):
+            getattr(L, f).restype = ctypes.c_int
         L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
         L.lrcc_plan_check.restype = ctypes.c_int
         L.lrcc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
@@ -122,6 +127,21 @@ class Context:
         self._check(self._L.lrcc_apply_sigma(self._h, R, None if om is None else _ptr(om), _ptr(a), _ptr(b),
                                              _ptr(y1), _ptr(y2), int(precision)))
         return y1, y2
+
+    def set_profiling(self, on=True):
+        self._check(self._L.lrcc_set_profiling(self._h, int(bool(on))))
+
+    def read_profile(self):
+        """{'ladder': (ms_total, launches), 'sigma': (ms_total, applications)} since the last read."""
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_longlong * 3)()
+        self._check(self._L.lrcc_read_profile(self._h, ms, cnt))
+        return {"ladder": (ms[1], cnt[1]), "sigma": (ms[2], cnt[2])}
+
+    def sigma_flops(self, nrhs, precision=FP64):
+        out = ctypes.c_double()
+        self._check(self._L.lrcc_sigma_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
+        return out.value
 
     def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None):
         """Device-pointer variant for torch tensors (complex128, caller layouts)."""
