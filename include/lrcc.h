@@ -55,6 +55,28 @@ typedef enum {
 
 enum { LRCC_FP64 = 0, LRCC_FP32 = 1 };
 
+/* Options of the iterative response solver (lrcc_solve_opts_default fills them). */
+typedef struct {
+    double tol;            /* stop when ||b - (A - w) x|| <= tol ||b|| for every RHS (default 1e-10);
+                              norm: sum |u1|^2 + 1/4 sum |u2|^2 over full arrays                      */
+    int max_iter;          /* FP64 GMRES: maximum operator applications (default 400)                */
+    int krylov;            /* GMRES restart length (default 8)                                       */
+    int precision;         /* LRCC_FP64: GMRES in complex128; LRCC_FP32: complex64 matrix-core inner
+                              GMRES corrections inside complex128 iterative refinement                */
+    double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4)  */
+    int max_outer;         /* maximum refinement steps (default 30)                                  */
+    long long mem_cap_bytes; /* > 0: refuse (LRCC_E_OOM) if solver vectors would exceed this         */
+} lrcc_solve_opts;
+
+typedef struct {
+    int converged;           /* 1 if every RHS met tol                                               */
+    int outer;               /* refinement steps (1 for LRCC_FP64)                                    */
+    int sigma_fp64;          /* complex128 sigma applications (batched launches)                     */
+    int sigma_fp32;          /* complex64 sigma applications (batched launches)                      */
+    double max_rel_residual; /* largest final relative residual over the RHS                         */
+    double seconds;          /* wall time of the solve                                               */
+} lrcc_solve_report;
+
 /* Create a context on HIP device `hip_device`. *out is NULL on failure. */
 lrcc_status lrcc_create(int hip_device, lrcc_ctx **out);
 
@@ -118,6 +140,37 @@ lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *exe
  * GPU and allocates no device memory.  On failure writes a message into msg
  * (msglen bytes, may be NULL) and returns LRCC_E_ARG (or LRCC_E_OOM). */
 lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char *msg, int msglen);
+
+/* Transpose product (the operator of the lambda equations l1, l2, Sec. II.B):
+ * y_r = (A - omega_r)^T x_r, the transpose taken with respect to the bilinear
+ * pairing <u, w> = sum_singles u1 w1 + 1/4 sum_doubles u2 w2 over full arrays
+ * in the layouts and normalisation above, so that <z, (A - w) x> =
+ * <(A - w)^T z, x> for antisymmetric x, z.  The adjoint reuses the ladder
+ * kernel with pair-transposed Cholesky slices; nothing of vvvv size is stored.
+ * Host-buffer and device-buffer variants as for the sigma. */
+lrcc_status lrcc_apply_sigma_adjoint(lrcc_ctx *ctx, int nrhs, const double *omega,
+                                     const double *x1, const double *x2, double *y1, double *y2,
+                                     int precision);
+lrcc_status lrcc_apply_sigma_adjoint_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
+                                         const void *x1, const void *x2, void *y1, void *y2,
+                                         int precision, void *stream);
+
+void lrcc_solve_opts_default(lrcc_solve_opts *opts);
+
+/* Solve the perturbed-amplitude equations (Eqs. tx1, tx2 in operator form,
+ * the Jacobi/DIIS iteration of Sec. II.C replaced by preconditioned GMRES with
+ * the same orbital-energy denominators of Eq. D): (A - omega_r) x_r = b_r for
+ * nrhs right-hand sides at once, each with its own frequency.  x holds the
+ * initial guess on entry (zeros for none) and the solution on exit.  opts may
+ * be NULL (defaults).  Returns LRCC_E_NOCONV (x and report still written) if
+ * the tolerance is not reached.  Host-buffer variant (omega host) and device
+ * variant (omega, b, x device; enqueued on stream, returns after completion). */
+lrcc_status lrcc_solve_response(lrcc_ctx *ctx, int nrhs, const double *omega,
+                                const double *b1, const double *b2, double *x1, double *x2,
+                                const lrcc_solve_opts *opts, lrcc_solve_report *report);
+lrcc_status lrcc_solve_response_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
+                                    const void *b1, const void *b2, void *x1, void *x2,
+                                    const lrcc_solve_opts *opts, lrcc_solve_report *report, void *stream);
 
 /* Number of amplitude elements per right-hand side: singles and doubles. */
 lrcc_status lrcc_sizes(const lrcc_ctx *ctx, long long *n1, long long *n2);

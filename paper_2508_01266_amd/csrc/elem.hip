@@ -229,7 +229,93 @@ hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Z[ki,kj,ka][r][i][j][a][b] = scale * (P_ij P_ab y)[r][ki,kj,ka][i][j][a][b]  (caller layout in, block layout out)
+template <typename T>
+__global__ void k_pp_in(const double2 *y, typename Cx<T>::type *Z, int nk, int R, int o, int v, double scale) {
+    const i64 inner = (i64)o * o * v * v;
+    const i64 B = (i64)nk * nk * nk;
+    const i64 n = B * R * inner;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        // t indexes the block layout [blk][r][i][j][a][b]
+        i64 q = t;
+        const int b = (int)(q % v); q /= v;
+        const int a = (int)(q % v); q /= v;
+        const int j = (int)(q % o); q /= o;
+        const int i = (int)(q % o); q /= o;
+        const int r = (int)(q % R);
+        const i64 blk = q / R;
+        const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
+        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
+            return y[(((i64)r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
+        };
+        double2 z1 = at(ki, kj, ka, i, j, a, b), z2 = at(kj, ki, ka, j, i, a, b);
+        double2 z3 = at(ki, kj, kb, i, j, b, a), z4 = at(kj, ki, kb, j, i, b, a);
+        Z[t] = mk<T>((T)(scale * (z1.x - z2.x - z3.x + z4.x)), (T)(scale * (z1.y - z2.y - z3.y + z4.y)));
+    }
+}
+
+template <typename T>
+hipError_t pp_in(const void *y, void *Z, int nk, int R, int o, int v, double scale, hipStream_t s) {
+    const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
+    hipLaunchKernelGGL(k_pp_in<T>, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y,
+                       (typename Cx<T>::type *)Z, nk, R, o, v, scale);
+    return hipGetLastError();
+}
+
+// y += x (complex, n elements)
+template <typename T>
+__global__ void k_add(typename Cx<T>::type *y, const typename Cx<T>::type *x, i64 n) {
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        auto a = y[t], b = x[t];
+        y[t] = mk<T>(a.x + b.x, a.y + b.y);
+    }
+}
+template <typename T>
+hipError_t add_inplace(void *y, const void *x, i64 n, hipStream_t s) {
+    hipLaunchKernelGGL(k_add<T>, dim3(grid_for(n)), dim3(256), 0, s, (typename Cx<T>::type *)y,
+                       (const typename Cx<T>::type *)x, n);
+    return hipGetLastError();
+}
+
+// zero fill (a kernel rather than a memset so that programs stay capturable)
+template <typename T>
+__global__ void k_zero(typename Cx<T>::type *y, i64 n) {
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) y[t] = mk<T>(0, 0);
+}
+template <typename T>
+hipError_t zero_fill(void *y, i64 n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(n)), dim3(256), 0, s, (typename Cx<T>::type *)y, n);
+    return hipGetLastError();
+}
+
+// out[k2][k1][Q][q][p] = in[k1][k2][Q][p][q]   ([nk][nk][naux][m][m] blocks)
+template <typename T>
+__global__ void k_pair_transpose(const typename Cx<T>::type *in, typename Cx<T>::type *out, int nk, int naux, int m) {
+    const i64 n = (i64)nk * nk * naux * m * m;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int p = (int)(q % m); q /= m;
+        const int qq = (int)(q % m); q /= m;
+        const int Q = (int)(q % naux); q /= naux;
+        const int k1 = (int)(q % nk);
+        const int k2 = (int)(q / nk);
+        // t = [k2][k1][Q][qq][p]
+        out[t] = in[(((i64)(k1 * nk + k2) * naux + Q) * m + p) * m + qq];
+    }
+}
+template <typename T>
+hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_transpose<T>, dim3(grid_for((i64)nk * nk * naux * m * m)), dim3(256), 0, s,
+                       (const typename Cx<T>::type *)in, (typename Cx<T>::type *)out, nk, naux, m);
+    return hipGetLastError();
+}
+
 #define INST(T)                                                                                              \
+    template hipError_t pp_in<T>(const void *, void *, int, int, int, int, double, hipStream_t);             \
+    template hipError_t add_inplace<T>(void *, const void *, i64, hipStream_t);                              \
+    template hipError_t zero_fill<T>(void *, i64, hipStream_t);                                              \
+    template hipError_t pair_transpose<T>(const void *, void *, int, int, int, hipStream_t);                                                                                              \
     template hipError_t tau_like<T>(const void *, const void *, const void *, void *, int, int, int, int,    \
                                     double, int, hipStream_t);                                               \
     template hipError_t pp_out<T>(const void *, const void *, void *, const double *, int, int, int, int,    \

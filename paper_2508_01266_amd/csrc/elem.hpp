@@ -20,4 +20,12 @@ hipError_t chol_slice(const void *L, void *out, int nk, int naux, int n, int p0,
 template <typename Tout>
 hipError_t one_body_slice(const void *in, void *out, int nk, int n, int p0, int np, int q0, int nq, hipStream_t s);
 hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s);
+template <typename T>
+hipError_t pp_in(const void *y, void *Z, int nk, int R, int o, int v, double scale, hipStream_t s);
+template <typename T>
+hipError_t add_inplace(void *y, const void *x, i64 n, hipStream_t s);
+template <typename T>
+hipError_t zero_fill(void *y, i64 n, hipStream_t s);
+template <typename T>
+hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hipStream_t s);
 }  // namespace lrcc

@@ -22,6 +22,9 @@
 #include "common.hpp"
 #include "elem.hpp"
 #include "plan.hpp"
+#include "solver.hpp"
+#include <chrono>
+#include <algorithm>
 
 using namespace lrcc;
 typedef std::complex<double> cd;
@@ -58,7 +61,8 @@ struct State {
     KT fov, t1, t2, tau;
     KT g_oovv, g_ooov, g_ovov, g_ovvv, g_ovoo;
     KT Fae, Fmi, Fme, Fbe, Fmj, Wp, Wbar, Q, R, S, U, Yp, H, G2;
-    void *La = nullptr, *Lb = nullptr;
+    void *La = nullptr, *Lb = nullptr;      // dressed virtual Cholesky slices (ladder)
+    void *LaT = nullptr, *LbT = nullptr;    // pair-transposed copies (adjoint ladder)
     bool ready = false;
 };
 
@@ -86,6 +90,9 @@ struct lrcc_ctx {
     size_t stage_bytes = 0;
     void *st_x1 = nullptr, *st_x2 = nullptr, *st_y1 = nullptr, *st_y2 = nullptr, *st_om = nullptr;
     Profiler prof;
+    void *eps_o = nullptr, *eps_v = nullptr;   // diagonal of fock per k (preconditioner)
+    DevMem solmem;                             // solver work vectors
+    size_t sol_bytes = 0;
 };
 
 static std::string g_create_err;
@@ -331,6 +338,13 @@ void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
         build_dressing(c, P, Ls, La, S.t1.p);
         build_dressing(c, P, Lcs, Lb, S.t1.p);
     }
+    S.LaT = m.get(lvv * 16);
+    S.LbT = m.get(lvv * 16);
+    {
+        void *La = S.La, *Lb = S.Lb, *LaT = S.LaT, *LbT = S.LbT;
+        P.ops.push_back([=](hipStream_t s) { return pair_transpose<double>(La, LaT, nk, naux, v, s); });
+        P.ops.push_back([=](hipStream_t s) { return pair_transpose<double>(Lb, LbT, nk, naux, v, s); });
+    }
     if (!g_dry_run) {
         HIPCHK(P.run(nullptr));
         HIPCHK(hipDeviceSynchronize());
@@ -349,10 +363,12 @@ void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
     cv(F.Yp, S.Yp); cv(F.H, S.H); cv(F.G2, S.G2);
     F.La = F.mem.get(lvv * 8);
     F.Lb = F.mem.get(lvv * 8);
-    {
-        void *a = S.La, *b = S.Lb, *fa = F.La, *fb = F.Lb;
+    F.LaT = F.mem.get(lvv * 8);
+    F.LbT = F.mem.get(lvv * 8);
+    for (int w = 0; w < 4; ++w) {
+        void *a = w == 0 ? S.La : w == 1 ? S.Lb : w == 2 ? S.LaT : S.LbT;
+        void *fa = w == 0 ? F.La : w == 1 ? F.Lb : w == 2 ? F.LaT : F.LbT;
         P2.ops.push_back([=](hipStream_t s) { return convert_f64_f32(a, fa, lvv, s); });
-        P2.ops.push_back([=](hipStream_t s) { return convert_f64_f32(b, fb, lvv, s); });
     }
     if (!g_dry_run) {
         HIPCHK(P2.run(nullptr));
@@ -362,112 +378,495 @@ void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
 }
 
 // ---------------------------------------------------------------- sigma program
+// The Jacobian product is recorded once as a list of symbolic operations, each
+// linear in exactly one X-dependent ("active") tensor.  The forward program
+// executes the list; the adjoint program (transpose Jacobian, the operator of
+// the lambda equations l1, l2 and of the gradients) runs the list backwards,
+// propagating cotangents through the transposed contractions.
+struct SymOp {
+    enum Kind { CON, COPY, TAU, LADDER } kind;
+    KT C, A, B;
+    std::string cl, al, bl;
+    cd alpha = 1.0;
+    bool acc = true;
+    bool actA = false, actB = false;
+};
+
+struct SigmaGraph {
+    std::vector<SymOp> ops;
+    std::vector<KT> active;  // active[0] = x1, active[1] = x2, then intermediates
+    KT x1, x2, Z, s1;
+};
+
 template <typename T>
-Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, int prec) {
-    const int nk = c->nk, o = c->no, v = c->nv, naux = c->naux;
-    auto P = new Program();
-    auto A = [&](const char *cls) { return alloc_kt<T>(c, wm, cls, R); };
+SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
+    SigmaGraph G;
+    auto A = [&](const char *cls) {
+        KT t = alloc_kt<T>(c, wm, cls, R);
+        G.active.push_back(t);
+        return t;
+    };
+    auto is_act = [&](const KT &t) {
+        for (auto &a : G.active)
+            if (a.p == t.p) return true;
+        return false;
+    };
+    auto con = [&](const KT &C, const char *cl, const KT &Aa, const char *al, const KT &Bb, const char *bl,
+                   cd alpha, bool acc = true) {
+        SymOp op;
+        op.kind = SymOp::CON;
+        op.C = C; op.A = Aa; op.B = Bb;
+        op.cl = cl; op.al = al; op.bl = bl;
+        op.alpha = alpha;
+        op.acc = acc;
+        op.actA = is_act(Aa);
+        op.actB = is_act(Bb);
+        if (op.actA == op.actB) throw LrccError(LRCC_E_ARG, std::string("term not linear in X: ") + cl);
+        G.ops.push_back(op);
+    };
+    auto copy = [&](const KT &C, const KT &Aa) {
+        SymOp op;
+        op.kind = SymOp::COPY;
+        op.C = C; op.A = Aa; op.actA = true;
+        G.ops.push_back(op);
+    };
     KT x1 = A("ov"), x2 = A("oovv"), dtau = A("oovv"), Z = A("oovv"), s1 = A("ov");
     KT dFae = A("vv"), dFmi = A("oo"), dFme = A("ov"), dFbe = A("vv"), dFmj = A("oo");
     KT Zmn = A("oooo"), Vx = A("oooo"), Yx = A("oovo");
+    G.x1 = x1; G.x2 = x2; G.Z = Z; G.s1 = s1;
+    {
+        SymOp op;
+        op.kind = SymOp::TAU;
+        op.C = dtau; op.A = x1; op.B = x2; op.actA = op.actB = true;
+        G.ops.push_back(op);
+    }
+    const KT &t1 = S.t1, &t2 = S.t2;
+    // X-dependent one-body intermediates (derivatives of F_ae, F_mi, F_me)
+    con(dFae, "Rae", x1, "Rma", S.fov, "me", -0.5, false);
+    con(dFae, "Rae", x1, "Rmf", S.g_ovvv, "mafe", 1.0);
+    con(dFae, "Rae", x2, "Rmnaf", S.g_oovv, "mnef", -0.25);
+    con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.25);
+    con(dFmi, "Rmi", x1, "Rie", S.fov, "me", 0.5, false);
+    con(dFmi, "Rmi", x1, "Rne", S.g_ooov, "mnie", 1.0);
+    con(dFmi, "Rmi", x2, "Rinef", S.g_oovv, "mnef", 0.25);
+    con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.25);
+    con(dFme, "Rme", x1, "Rnf", S.g_oovv, "mnef", 1.0, false);
+    // singles (operator part of Eq. tx1)
+    con(s1, "Ria", x1, "Rie", S.Fae, "ae", 1.0, false);
+    con(s1, "Ria", t1, "ie", dFae, "Rae", 1.0);
+    con(s1, "Ria", x1, "Rma", S.Fmi, "mi", -1.0);
+    con(s1, "Ria", t1, "ma", dFmi, "Rmi", -1.0);
+    con(s1, "Ria", x2, "Rimae", S.Fme, "me", 1.0);
+    con(s1, "Ria", t2, "imae", dFme, "Rme", 1.0);
+    con(s1, "Ria", x1, "Rnf", S.g_ovov, "naif", -1.0);
+    con(s1, "Ria", x2, "Rimef", S.g_ovvv, "maef", -0.5);
+    con(s1, "Ria", x2, "Rmnae", S.g_ooov, "nmie", 0.5);
+    // dressed one-body derivatives entering the doubles
+    copy(dFbe, dFae);
+    con(dFbe, "Rbe", x1, "Rmb", S.Fme, "me", -0.5);
+    con(dFbe, "Rbe", t1, "mb", dFme, "Rme", -0.5);
+    copy(dFmj, dFmi);
+    con(dFmj, "Rmj", x1, "Rje", S.Fme, "me", 0.5);
+    con(dFmj, "Rmj", t1, "je", dFme, "Rme", 0.5);
+    // doubles (operator part of Eq. tx2): Z collects every term, sigma2 = P(ij)P(ab) Z.
+    // Terms antisymmetric in both pairs enter with 1/4, in one pair with 1/2.
+    con(Z, "Rijab", x2, "Rijae", S.Fbe, "be", 0.5, false);
+    con(Z, "Rijab", t2, "ijae", dFbe, "Rbe", 0.5);
+    con(Z, "Rijab", x2, "Rimab", S.Fmj, "mj", -0.5);
+    con(Z, "Rijab", t2, "imab", dFmj, "Rmj", -0.5);
+    {
+        SymOp op;
+        op.kind = SymOp::LADDER;
+        op.C = Z; op.A = dtau; op.alpha = 0.25; op.actA = true;
+        G.ops.push_back(op);
+    }
+    con(Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false);
+    con(Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16);
+    con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8);
+    con(Vx, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 1.0, false);
+    con(Vx, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -1.0);
+    con(Z, "Rijab", Vx, "Rijmn", S.tau, "mnab", 1.0 / 8);
+    con(Z, "Rijab", S.Q, "ijam", x1, "Rmb", -0.25);
+    // ring terms (P(ij)P(ab))
+    con(Z, "Rijab", x2, "Rimae", S.Wbar, "mbej", 1.0);
+    con(Z, "Rijab", S.R, "iabf", x1, "Rjf", 1.0);
+    con(Z, "Rijab", S.S, "ijan", x1, "Rnb", -1.0);
+    con(Yx, "Rijan", x1, "Rjf", S.U, "ianf", 1.0, false);
+    con(Z, "Rijab", Yx, "Rijan", t1, "nb", -1.0);
+    con(Z, "Rijab", S.Yp, "ijan", x1, "Rnb", -1.0);
+    con(Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);
+    con(Z, "Rijab", S.G2, "ijbm", x1, "Rma", -1.0);
+    con(Z, "Rijab", S.g_ovoo, "mbij", x1, "Rma", -0.5);
+    return G;
+}
+
+template <typename T>
+LadderArgs ladder_args(lrcc_ctx *c, const void *Y, const void *La, const void *Lb, void *Z, int R, double alpha) {
+    LadderArgs la{};
+    la.Y = Y; la.La = La; la.Lb = Lb; la.Z = Z;
+    la.nk = c->nk; la.nrhs = R; la.o = c->no; la.v = c->nv; la.naux = c->naux;
+    la.alpha = alpha;
+    return la;
+}
+
+template <typename T>
+Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
+    const int nk = c->nk, o = c->no, v = c->nv;
+    auto P = new Program();
+    SigmaGraph G = record_sigma<T>(c, S, R, wm);
     const i64 nb3 = (i64)nk * nk * nk;
+    KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
     // caller layout -> internal (paper -> crystal normalisation for doubles)
     P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, T>(c->io_x1, x1.p, R, nk, (i64)o * v, 1.0, s); });
     P->ops.push_back([=](hipStream_t s) {
         return rhs_to_block<double, T>(c->io_x2, x2.p, R, nb3, (i64)o * o * v * v, 1.0 / nk, s);
     });
-    {
-        void *t1p = S.t1.p;
-        P->ops.push_back([=](hipStream_t s) { return tau_like<T>(x1.p, x2.p, t1p, dtau.p, nk, R, o, v, 1.0, 1, s); });
+    for (const SymOp &op : G.ops) {
+        switch (op.kind) {
+        case SymOp::CON:
+            contract<T>(*P, op.C, op.cl, op.A, op.al, op.B, op.bl, op.alpha, op.acc);
+            break;
+        case SymOp::COPY:
+            kt_copy<T>(*P, op.C, op.A);
+            break;
+        case SymOp::TAU: {
+            void *t1p = S.t1.p, *xa = op.A.p, *xb = op.B.p, *out = op.C.p;
+            P->ops.push_back([=](hipStream_t s) { return tau_like<T>(xa, xb, t1p, out, nk, R, o, v, 1.0, 1, s); });
+            break;
+        }
+        case SymOp::LADDER: {
+            LadderArgs la = ladder_args<T>(c, op.A.p, S.La, S.Lb, op.C.p, R, op.alpha.real());
+            P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
+            P->tag_last(TAG_LADDER);
+            P->flops += (i64)ladder_executed_flops(la);
+            break;
+        }
+        }
     }
-    const KT &t1 = S.t1, &t2 = S.t2;
-    // X-dependent one-body intermediates (derivatives of F_ae, F_mi, F_me)
-    contract<T>(*P, dFae, "Rae", x1, "Rma", S.fov, "me", -0.5, false);
-    contract<T>(*P, dFae, "Rae", x1, "Rmf", S.g_ovvv, "mafe", 1.0);
-    contract<T>(*P, dFae, "Rae", x2, "Rmnaf", S.g_oovv, "mnef", -0.25);
-    contract<T>(*P, dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.25);
-    contract<T>(*P, dFmi, "Rmi", x1, "Rie", S.fov, "me", 0.5, false);
-    contract<T>(*P, dFmi, "Rmi", x1, "Rne", S.g_ooov, "mnie", 1.0);
-    contract<T>(*P, dFmi, "Rmi", x2, "Rinef", S.g_oovv, "mnef", 0.25);
-    contract<T>(*P, dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.25);
-    contract<T>(*P, dFme, "Rme", x1, "Rnf", S.g_oovv, "mnef", 1.0, false);
-    // singles (Eq. tx1 operator part)
-    contract<T>(*P, s1, "Ria", x1, "Rie", S.Fae, "ae", 1.0, false);
-    contract<T>(*P, s1, "Ria", t1, "ie", dFae, "Rae", 1.0);
-    contract<T>(*P, s1, "Ria", x1, "Rma", S.Fmi, "mi", -1.0);
-    contract<T>(*P, s1, "Ria", t1, "ma", dFmi, "Rmi", -1.0);
-    contract<T>(*P, s1, "Ria", x2, "Rimae", S.Fme, "me", 1.0);
-    contract<T>(*P, s1, "Ria", t2, "imae", dFme, "Rme", 1.0);
-    contract<T>(*P, s1, "Ria", x1, "Rnf", S.g_ovov, "naif", -1.0);
-    contract<T>(*P, s1, "Ria", x2, "Rimef", S.g_ovvv, "maef", -0.5);
-    contract<T>(*P, s1, "Ria", x2, "Rmnae", S.g_ooov, "nmie", 0.5);
-    // dressed one-body derivatives entering the doubles
-    kt_copy<T>(*P, dFbe, dFae);
-    contract<T>(*P, dFbe, "Rbe", x1, "Rmb", S.Fme, "me", -0.5);
-    contract<T>(*P, dFbe, "Rbe", t1, "mb", dFme, "Rme", -0.5);
-    kt_copy<T>(*P, dFmj, dFmi);
-    contract<T>(*P, dFmj, "Rmj", x1, "Rje", S.Fme, "me", 0.5);
-    contract<T>(*P, dFmj, "Rmj", t1, "je", dFme, "Rme", 0.5);
-    // doubles: Z collects every term; sigma2 = P(ij)P(ab) Z.  Terms antisymmetric in
-    // both pairs enter with 1/4, terms antisymmetric in one pair with 1/2.
-    contract<T>(*P, Z, "Rijab", x2, "Rijae", S.Fbe, "be", 0.5, false);
-    contract<T>(*P, Z, "Rijab", t2, "ijae", dFbe, "Rbe", 0.5);
-    contract<T>(*P, Z, "Rijab", x2, "Rimab", S.Fmj, "mj", -0.5);
-    contract<T>(*P, Z, "Rijab", t2, "imab", dFmj, "Rmj", -0.5);
-    {
-        LadderArgs la{};
-        la.Y = dtau.p;
-        la.La = S.La;
-        la.Lb = S.Lb;
-        la.Z = Z.p;
-        la.nk = nk;
-        la.nrhs = R;
-        la.o = o;
-        la.v = v;
-        la.naux = naux;
-        la.alpha = 0.25;
-        P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
-        P->tag_last(TAG_LADDER);
-        P->flops += (i64)ladder_executed_flops(la);
-    }
-    contract<T>(*P, Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false);
-    contract<T>(*P, Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16);
-    contract<T>(*P, Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8);
-    contract<T>(*P, Vx, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 1.0, false);
-    contract<T>(*P, Vx, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -1.0);
-    contract<T>(*P, Z, "Rijab", Vx, "Rijmn", S.tau, "mnab", 1.0 / 8);
-    contract<T>(*P, Z, "Rijab", S.Q, "ijam", x1, "Rmb", -0.25);
-    // ring terms (P(ij)P(ab))
-    contract<T>(*P, Z, "Rijab", x2, "Rimae", S.Wbar, "mbej", 1.0);
-    contract<T>(*P, Z, "Rijab", S.R, "iabf", x1, "Rjf", 1.0);
-    contract<T>(*P, Z, "Rijab", S.S, "ijan", x1, "Rnb", -1.0);
-    contract<T>(*P, Yx, "Rijan", x1, "Rjf", S.U, "ianf", 1.0, false);
-    contract<T>(*P, Z, "Rijab", Yx, "Rijan", t1, "nb", -1.0);
-    contract<T>(*P, Z, "Rijab", S.Yp, "ijan", x1, "Rnb", -1.0);
-    contract<T>(*P, Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);
-    contract<T>(*P, Z, "Rijab", S.G2, "ijbm", x1, "Rma", -1.0);
-    contract<T>(*P, Z, "Rijab", S.g_ovoo, "mbij", x1, "Rma", -0.5);
     // outputs in the caller layout: y = (A - omega) x, paper normalisation
     P->ops.push_back([=](hipStream_t s) { return s1_out<T>(s1.p, c->io_x1, c->io_y1, c->io_omega, nk, R, o, v, s); });
     P->ops.push_back([=](hipStream_t s) {
         return pp_out<T>(Z.p, c->io_x2, c->io_y2, c->io_omega, nk, R, o, v, (double)nk, s);
     });
-    (void)prec;
     return P;
 }
 
-Program *sigma_program(lrcc_ctx *c, int prec, int R) {
-    auto key = std::make_pair(prec, R);
+// Transpose product y = (A - omega)^T z with respect to the pairing
+// <u, v> = sum u1 v1 + 1/4 sum u2 v2 (amplitude arrays in the caller's normalisation).
+template <typename T>
+Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
+    const int nk = c->nk, o = c->no, v = c->nv;
+    auto P = new Program();
+    SigmaGraph G = record_sigma<T>(c, S, R, wm);
+    // adjoint buffer for every active tensor (the forward buffers are reused as adjoints)
+    for (const KT &a : G.active) {
+        void *p = a.p;
+        i64 n = a.count();
+        P->ops.push_back([=](hipStream_t s) { return zero_fill<T>(p, n, s); });
+    }
+    KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
+    // cotangent of the outputs: s1bar = z1, Zbar = (Nk/4) P(ij)P(ab) z2
+    P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, T>(c->io_x1, s1.p, R, nk, (i64)o * v, 1.0, s); });
+    P->ops.push_back([=](hipStream_t s) { return pp_in<T>(c->io_x2, Z.p, nk, R, o, v, 0.25 * nk, s); });
+    for (auto it = G.ops.rbegin(); it != G.ops.rend(); ++it) {
+        const SymOp &op = *it;
+        switch (op.kind) {
+        case SymOp::CON:
+            if (op.actA) contract<T>(*P, op.A, op.al, op.C, op.cl, op.B, op.bl, op.alpha, true);
+            if (op.actB) contract<T>(*P, op.B, op.bl, op.A, op.al, op.C, op.cl, op.alpha, true);
+            break;
+        case SymOp::COPY: {
+            void *a = op.A.p, *cc = op.C.p;
+            i64 n = op.A.count();
+            P->ops.push_back([=](hipStream_t s) { return add_inplace<T>(a, cc, n, s); });
+            break;
+        }
+        case SymOp::TAU: {
+            // dtau = x2 + (x_ia t_jb + t_ia x_jb - x_ib t_ja - t_ib x_ja)
+            void *a = op.B.p, *cc = op.C.p;
+            i64 n = op.B.count();
+            P->ops.push_back([=](hipStream_t s) { return add_inplace<T>(a, cc, n, s); });
+            const KT &dt = op.C, &xx1 = op.A, &t1 = S.t1;
+            contract<T>(*P, xx1, "Ria", dt, "Rijab", t1, "jb", 1.0, true);
+            contract<T>(*P, xx1, "Rjb", dt, "Rijab", t1, "ia", 1.0, true);
+            contract<T>(*P, xx1, "Rib", dt, "Rijab", t1, "ja", -1.0, true);
+            contract<T>(*P, xx1, "Rja", dt, "Rijab", t1, "ib", -1.0, true);
+            break;
+        }
+        case SymOp::LADDER: {
+            LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
+            P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
+            P->tag_last(TAG_LADDER);
+            P->flops += (i64)ladder_executed_flops(la);
+            break;
+        }
+        }
+    }
+    // y1 = x1bar - omega z1 ; y2 = P(ij)P(ab) x2bar / Nk - omega z2
+    P->ops.push_back([=](hipStream_t s) { return s1_out<T>(x1.p, c->io_x1, c->io_y1, c->io_omega, nk, R, o, v, s); });
+    P->ops.push_back([=](hipStream_t s) {
+        return pp_out<T>(x2.p, c->io_x2, c->io_y2, c->io_omega, nk, R, o, v, 1.0 / nk, s);
+    });
+    return P;
+}
+
+Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false) {
+    auto key = std::make_pair(prec * 2 + (adjoint ? 1 : 0), R);
     auto it = c->progs.find(key);
     if (it != c->progs.end()) return it->second.get();
     auto mem = std::make_unique<DevMem>();
-    Program *p = prec == LRCC_FP64 ? build_sigma<double>(c, c->s64, R, *mem, prec)
-                                   : build_sigma<float>(c, c->s32, R, *mem, prec);
+    Program *p;
+    if (!adjoint)
+        p = prec == LRCC_FP64 ? build_sigma<double>(c, c->s64, R, *mem) : build_sigma<float>(c, c->s32, R, *mem);
+    else
+        p = prec == LRCC_FP64 ? build_sigma_adjoint<double>(c, c->s64, R, *mem)
+                              : build_sigma_adjoint<float>(c, c->s32, R, *mem);
     c->progs[key].reset(p);
     c->progmem[key] = std::move(mem);
     return p;
 }
 
+
+// ---------------------------------------------------------------- response solver
+// Batched right-preconditioned restarted GMRES (one Krylov space per right-hand
+// side, all advanced together so that each step is one multi-RHS sigma launch),
+// and FP32-inner / FP64-residual iterative refinement.  Inner products weight
+// the doubles by 1/4 so that every independent amplitude counts once.
+struct Vecs {
+    void *s = nullptr, *d = nullptr;  // singles [R][n1], doubles [R][n2] (complex128, caller layout)
+};
+
+struct SolveCtx {
+    lrcc_ctx *c;
+    int R;
+    i64 n1, n2;
+    hipStream_t st;
+    const double *omega;  // device
+    void *part = nullptr, *dout = nullptr, *alpha = nullptr;  // reduction / coefficient scratch
+    int nsig64 = 0, nsig32 = 0;
+    std::vector<cd> dot(const Vecs &u, const Vecs &v) {
+        std::vector<cd> a(R), b(R);
+        HIPCHK(batched_dot(u.s, v.s, R, n1, 1.0, part, dout, st));
+        HIPCHK(hipMemcpyAsync(a.data(), dout, R * 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(batched_dot(u.d, v.d, R, n2, 0.25, part, dout, st));
+        HIPCHK(hipMemcpyAsync(b.data(), dout, R * 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int r = 0; r < R; ++r) a[r] += b[r];
+        return a;
+    }
+    std::vector<double> norm(const Vecs &u) {
+        auto d = dot(u, u);
+        std::vector<double> n(R);
+        for (int r = 0; r < R; ++r) n[r] = std::sqrt(std::max(0.0, d[r].real()));
+        return n;
+    }
+    // y = beta y + a_r x
+    void axpby(const Vecs &y, const Vecs &x, const std::vector<cd> &a, double beta) {
+        HIPCHK(hipMemcpyAsync(alpha, a.data(), R * 16, hipMemcpyHostToDevice, st));
+        HIPCHK(batched_axpby(y.s, x.s, alpha, beta, R, n1, st));
+        HIPCHK(batched_axpby(y.d, x.d, alpha, beta, R, n2, st));
+        HIPCHK(hipStreamSynchronize(st));  // alpha buffer is reused by the next call
+    }
+    void copy(const Vecs &y, const Vecs &x) {
+        HIPCHK(hipMemcpyAsync(y.s, x.s, R * n1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(y.d, x.d, R * n2 * 16, hipMemcpyDeviceToDevice, st));
+    }
+    void zero(const Vecs &y) {
+        HIPCHK(hipMemsetAsync(y.s, 0, R * n1 * 16, st));
+        HIPCHK(hipMemsetAsync(y.d, 0, R * n2 * 16, st));
+    }
+    void prec(const Vecs &out, const Vecs &in) {
+        HIPCHK(precond(out.s, out.d, in.s, in.d, (const double *)c->eps_o, (const double *)c->eps_v, omega, c->nk,
+                       R, c->no, c->nv, st));
+    }
+    // y = (A - omega) x
+    void op(const Vecs &y, const Vecs &x, int precision) {
+        Program *p = sigma_program(c, precision, R);
+        c->io_x1 = x.s; c->io_x2 = x.d; c->io_y1 = y.s; c->io_y2 = y.d; c->io_omega = omega;
+        HIPCHK(p->run(st, &c->prof));
+        (precision == LRCC_FP64 ? nsig64 : nsig32)++;
+    }
+};
+
+// GMRES on (A - omega) x = b starting from x (in/out).  Stops when every
+// right-hand side reaches ||r|| <= tol ||b|| or after max_apply operator
+// applications.  Returns per-RHS relative residual estimates.
+std::vector<double> gmres(SolveCtx &S, const Vecs &b, const Vecs &x, int precision, double tol, int max_apply,
+                          int m, std::vector<Vecs> &V, const Vecs &w, const Vecs &z, bool x_is_zero) {
+    const int R = S.R;
+    auto bn = S.norm(b);
+    std::vector<double> rel(R, 0.0);
+    int applied = 0;
+    bool first = true;
+    while (true) {
+        // r = b - A x  (into V[0])
+        if (first && x_is_zero) {
+            S.copy(V[0], b);
+        } else {
+            S.op(w, x, precision);
+            ++applied;
+            S.copy(V[0], b);
+            S.axpby(V[0], w, std::vector<cd>(R, cd(-1.0, 0.0)), 1.0);
+        }
+        first = false;
+        auto beta = S.norm(V[0]);
+        bool all = true;
+        for (int r = 0; r < R; ++r) {
+            rel[r] = bn[r] > 0 ? beta[r] / bn[r] : 0.0;
+            if (rel[r] > tol) all = false;
+        }
+        if (all || applied >= max_apply) return rel;
+        std::vector<cd> inv(R);
+        for (int r = 0; r < R; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+        S.axpby(V[0], V[0], inv, 0.0);
+        // per-RHS Hessenberg with Givens rotations
+        std::vector<std::vector<cd>> H(R, std::vector<cd>((m + 1) * m, 0.0));
+        std::vector<std::vector<cd>> g(R, std::vector<cd>(m + 1, 0.0)), cs(R, std::vector<cd>(m)), sn(R, std::vector<cd>(m));
+        std::vector<int> kr(R, 0);           // Arnoldi steps that count per RHS
+        std::vector<bool> act(R, true);
+        for (int r = 0; r < R; ++r) {
+            g[r][0] = beta[r];
+            if (rel[r] <= tol || beta[r] == 0) act[r] = false;
+        }
+        int j = 0;
+        for (; j < m && applied < max_apply; ++j) {
+            S.prec(z, V[j]);
+            S.op(w, z, precision);
+            ++applied;
+            for (int i = 0; i <= j; ++i) {
+                auto h = S.dot(V[i], w);
+                std::vector<cd> mh(R);
+                for (int r = 0; r < R; ++r) {
+                    H[r][i * m + j] = h[r];
+                    mh[r] = act[r] ? -h[r] : 0.0;
+                }
+                S.axpby(w, V[i], mh, 1.0);
+            }
+            auto hn = S.norm(w);
+            std::vector<cd> sc(R);
+            for (int r = 0; r < R; ++r) {
+                H[r][(j + 1) * m + j] = hn[r];
+                sc[r] = (act[r] && hn[r] > 0) ? 1.0 / hn[r] : 0.0;
+            }
+            S.axpby(V[j + 1], w, sc, 0.0);
+            bool any = false;
+            for (int r = 0; r < R; ++r) {
+                if (!act[r]) continue;
+                // apply previous rotations to column j, then a new one
+                for (int i = 0; i < j; ++i) {
+                    cd a = H[r][i * m + j], bb = H[r][(i + 1) * m + j];
+                    H[r][i * m + j] = std::conj(cs[r][i]) * a + std::conj(sn[r][i]) * bb;
+                    H[r][(i + 1) * m + j] = -sn[r][i] * a + cs[r][i] * bb;
+                }
+                cd a = H[r][j * m + j], bb = H[r][(j + 1) * m + j];
+                double den = std::sqrt(std::norm(a) + std::norm(bb));
+                cs[r][j] = den > 0 ? a / den : 1.0;
+                sn[r][j] = den > 0 ? bb / den : 0.0;
+                H[r][j * m + j] = den;
+                H[r][(j + 1) * m + j] = 0.0;
+                cd gj = g[r][j];
+                g[r][j] = std::conj(cs[r][j]) * gj;
+                g[r][j + 1] = -sn[r][j] * gj;
+                kr[r] = j + 1;
+                rel[r] = bn[r] > 0 ? std::abs(g[r][j + 1]) / bn[r] : 0.0;
+                if (rel[r] <= tol || hn[r] == 0) act[r] = false;
+                else any = true;
+            }
+            if (!any) { ++j; break; }
+        }
+        // x += M^-1 sum_i y_i V_i
+        std::vector<std::vector<cd>> y(R);
+        int kmax = 0;
+        for (int r = 0; r < R; ++r) {
+            const int k = kr[r];
+            kmax = std::max(kmax, k);
+            y[r].assign(m, 0.0);
+            for (int i = k - 1; i >= 0; --i) {
+                cd acc = g[r][i];
+                for (int l = i + 1; l < k; ++l) acc -= H[r][i * m + l] * y[r][l];
+                y[r][i] = H[r][i * m + i] != cd(0.0) ? acc / H[r][i * m + i] : 0.0;
+            }
+        }
+        S.zero(w);
+        for (int i = 0; i < kmax; ++i) {
+            std::vector<cd> yi(R);
+            for (int r = 0; r < R; ++r) yi[r] = y[r][i];
+            S.axpby(w, V[i], yi, 1.0);
+        }
+        S.prec(z, w);
+        S.axpby(x, z, std::vector<cd>(R, cd(1.0, 0.0)), 1.0);
+        x_is_zero = false;
+        if (applied >= max_apply) return rel;  // estimates from the rotations
+    }
+}
+
+void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, const Vecs &x,
+                    const lrcc_solve_opts &o, lrcc_solve_report &rep, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    SolveCtx S;
+    S.c = c; S.R = R; S.st = st; S.omega = omega_dev;
+    S.n1 = (i64)c->nk * c->no * c->nv;
+    S.n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
+    const int m = std::max(1, o.krylov);
+    const bool mixed = o.precision == LRCC_FP32;
+    const int nvec = (m + 1) + 2 + (mixed ? 2 : 0);
+    const size_t per = (size_t)R * (S.n1 + S.n2) * 16;
+    const size_t need = per * nvec + (size_t)R * (dot_blocks(S.n2) + 4) * 16 * 2;
+    if (o.mem_cap_bytes > 0 && need > (size_t)o.mem_cap_bytes)
+        throw LrccError(LRCC_E_OOM, "solver work vectors exceed the memory cap");
+    c->solmem.release();
+    std::vector<Vecs> V(m + 1);
+    auto mk = [&]() { Vecs v; v.s = c->solmem.get((size_t)R * S.n1 * 16); v.d = c->solmem.get((size_t)R * S.n2 * 16); return v; };
+    for (auto &v : V) v = mk();
+    Vecs w = mk(), z = mk();
+    S.part = c->solmem.get((size_t)R * dot_blocks(S.n2) * 16);
+    S.dout = c->solmem.get((size_t)R * 16);
+    S.alpha = c->solmem.get((size_t)R * 16);
+    std::vector<double> rel;
+    rep = lrcc_solve_report{};
+    if (!mixed) {
+        rel = gmres(S, b, x, LRCC_FP64, o.tol, o.max_iter, m, V, w, z, false);
+        rep.outer = 1;
+    } else {
+        Vecs r = mk(), dx = mk();
+        auto bn = S.norm(b);
+        for (int it = 0; it < o.max_outer; ++it) {
+            // FP64 residual r = b - (A - w) x
+            S.op(w, x, LRCC_FP64);
+            S.copy(r, b);
+            S.axpby(r, w, std::vector<cd>(R, cd(-1.0, 0.0)), 1.0);
+            auto rn = S.norm(r);
+            rel.assign(R, 0.0);
+            bool all = true;
+            for (int q = 0; q < R; ++q) {
+                rel[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
+                if (rel[q] > o.tol) all = false;
+            }
+            rep.outer = it + 1;
+            if (all) break;
+            // FP32 correction solve (A - w) dx = r to inner_tol
+            S.zero(dx);
+            gmres(S, r, dx, LRCC_FP32, o.inner_tol, m, m, V, w, z, true);
+            S.axpby(x, dx, std::vector<cd>(R, cd(1.0, 0.0)), 1.0);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    rep.sigma_fp64 = S.nsig64;
+    rep.sigma_fp32 = S.nsig32;
+    rep.max_rel_residual = rel.empty() ? 0.0 : *std::max_element(rel.begin(), rel.end());
+    rep.converged = rep.max_rel_residual <= o.tol;
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void default_opts(lrcc_solve_opts &o) {
+    o.tol = 1e-10;
+    o.max_iter = 400;
+    o.krylov = 8;
+    o.precision = LRCC_FP64;
+    o.inner_tol = 1e-4;
+    o.max_outer = 30;
+    o.mem_cap_bytes = 0;
+}
 
 // Device copies of the Hamiltonian and the stored integral blocks (all but vvvv).
 void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const double *fock, const double *chol) {
@@ -482,6 +881,18 @@ void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const 
     const i64 nL = (i64)nk * nk * naux * n * n;
     c->fock = c->hmem.get((size_t)nk * n * n * 16);
     if (!g_dry_run) HIPCHK(hipMemcpy(c->fock, fock, (size_t)nk * n * n * 16, hipMemcpyHostToDevice));
+    c->eps_o = c->hmem.get((size_t)nk * nocc * 8);
+    c->eps_v = c->hmem.get((size_t)nk * nvir * 8);
+    if (!g_dry_run) {
+        std::vector<double> eo((size_t)nk * nocc), ev((size_t)nk * nvir);
+        for (int k = 0; k < nk; ++k)
+            for (int p = 0; p < n; ++p) {
+                const double d = fock[2 * (((size_t)k * n + p) * n + p)];
+                if (p < nocc) eo[(size_t)k * nocc + p] = d; else ev[(size_t)k * nvir + p - nocc] = d;
+            }
+        HIPCHK(hipMemcpy(c->eps_o, eo.data(), eo.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->eps_v, ev.data(), ev.size() * 8, hipMemcpyHostToDevice));
+    }
     void *Lraw = c->hmem.get(nL * 16);
     if (!g_dry_run) HIPCHK(hipMemcpy(Lraw, chol, nL * 16, hipMemcpyHostToDevice));
     c->Ls = c->hmem.get(nL * 16);
@@ -643,8 +1054,33 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *c, int nrhs, const double *omega, con
     });
 }
 
+lrcc_status lrcc_apply_sigma_adjoint_dev(lrcc_ctx *c, int nrhs, const double *omega, const void *x1, const void *x2,
+                                         void *y1, void *y2, int precision, void *stream) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nrhs < 1 || !x1 || !x2 || !y1 || !y2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
+        if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        Program *p = sigma_program(c, precision, nrhs, true);
+        c->io_x1 = x1; c->io_x2 = x2; c->io_y1 = y1; c->io_y2 = y2; c->io_omega = omega;
+        HIPCHK(p->run((hipStream_t)stream, &c->prof));
+    });
+}
+
+static lrcc_status apply_host(lrcc_ctx *c, int nrhs, const double *omega, const double *x1, const double *x2,
+                              double *y1, double *y2, int precision, bool adjoint);
+
+lrcc_status lrcc_apply_sigma_adjoint(lrcc_ctx *c, int nrhs, const double *omega, const double *x1,
+                                     const double *x2, double *y1, double *y2, int precision) {
+    return apply_host(c, nrhs, omega, x1, x2, y1, y2, precision, true);
+}
+
 lrcc_status lrcc_apply_sigma(lrcc_ctx *c, int nrhs, const double *omega, const double *x1, const double *x2,
                              double *y1, double *y2, int precision) {
+    return apply_host(c, nrhs, omega, x1, x2, y1, y2, precision, false);
+}
+
+static lrcc_status apply_host(lrcc_ctx *c, int nrhs, const double *omega, const double *x1, const double *x2,
+                              double *y1, double *y2, int precision, bool adjoint) {
     return guarded(c, [&] {
         if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
         if (nrhs < 1 || !x1 || !x2 || !y1 || !y2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
@@ -663,12 +1099,63 @@ lrcc_status lrcc_apply_sigma(lrcc_ctx *c, int nrhs, const double *omega, const d
         std::vector<double> om(nrhs, 0.0);
         if (omega) for (int r = 0; r < nrhs; ++r) om[r] = omega[r];
         HIPCHK(hipMemcpy(c->st_om, om.data(), nrhs * 8, hipMemcpyHostToDevice));
-        lrcc_status s = lrcc_apply_sigma_dev(c, nrhs, (const double *)c->st_om, c->st_x1, c->st_x2, c->st_y1,
-                                             c->st_y2, precision, nullptr);
+        lrcc_status s = adjoint ? lrcc_apply_sigma_adjoint_dev(c, nrhs, (const double *)c->st_om, c->st_x1,
+                                                               c->st_x2, c->st_y1, c->st_y2, precision, nullptr)
+                                : lrcc_apply_sigma_dev(c, nrhs, (const double *)c->st_om, c->st_x1, c->st_x2,
+                                                       c->st_y1, c->st_y2, precision, nullptr);
         if (s != LRCC_OK) throw LrccError(s, c->err);
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(y1, c->st_y1, b1, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(y2, c->st_y2, b2, hipMemcpyDeviceToHost));
+    });
+}
+
+void lrcc_solve_opts_default(lrcc_solve_opts *o) {
+    if (o) default_opts(*o);
+}
+
+lrcc_status lrcc_solve_response_dev(lrcc_ctx *c, int nrhs, const double *omega, const void *b1, const void *b2,
+                                    void *x1, void *x2, const lrcc_solve_opts *opts, lrcc_solve_report *report,
+                                    void *stream) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nrhs < 1 || !b1 || !b2 || !x1 || !x2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        if (o.precision != LRCC_FP64 && o.precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        if (!(o.tol > 0) || o.krylov < 1 || o.max_iter < 1) throw LrccError(LRCC_E_ARG, "bad solver options");
+        lrcc_solve_report rep;
+        Vecs b{const_cast<void *>(b1), const_cast<void *>(b2)}, x{x1, x2};
+        solve_response(c, nrhs, omega, b, x, o, rep, (hipStream_t)stream);
+        if (report) *report = rep;
+        if (!rep.converged)
+            throw LrccError(LRCC_E_NOCONV, "response solve stopped at relative residual " +
+                                               std::to_string(rep.max_rel_residual));
+    });
+}
+
+lrcc_status lrcc_solve_response(lrcc_ctx *c, int nrhs, const double *omega, const double *b1, const double *b2,
+                                double *x1, double *x2, const lrcc_solve_opts *opts, lrcc_solve_report *report) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nrhs < 1 || !b1 || !b2 || !x1 || !x2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
+        const int nk = c->nk, o = c->no, v = c->nv;
+        const size_t s1 = (size_t)nrhs * nk * o * v * 16, s2 = (size_t)nrhs * nk * nk * nk * o * o * v * v * 16;
+        DevMem m;
+        void *db1 = m.get(s1), *db2 = m.get(s2), *dx1 = m.get(s1), *dx2 = m.get(s2), *dom = m.get(nrhs * 8);
+        HIPCHK(hipMemcpy(db1, b1, s1, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(db2, b2, s2, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dx1, x1, s1, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dx2, x2, s2, hipMemcpyHostToDevice));
+        std::vector<double> om(nrhs, 0.0);
+        if (omega) for (int r = 0; r < nrhs; ++r) om[r] = omega[r];
+        HIPCHK(hipMemcpy(dom, om.data(), nrhs * 8, hipMemcpyHostToDevice));
+        lrcc_status st = lrcc_solve_response_dev(c, nrhs, (const double *)dom, db1, db2, dx1, dx2, opts, report, nullptr);
+        if (st != LRCC_OK && st != LRCC_E_NOCONV) throw LrccError(st, c->err);
+        HIPCHK(hipMemcpy(x1, dx1, s1, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(x2, dx2, s2, hipMemcpyDeviceToHost));
+        if (st == LRCC_E_NOCONV) throw LrccError(st, c->err);
     });
 }
 
@@ -704,6 +1191,8 @@ lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char
         c.amp = true;
         (void)sigma_program(&c, LRCC_FP64, nrhs);
         (void)sigma_program(&c, LRCC_FP32, nrhs);
+        (void)sigma_program(&c, LRCC_FP64, nrhs, true);
+        (void)sigma_program(&c, LRCC_FP32, nrhs, true);
     } catch (LrccError &e) {
         st = (lrcc_status)e.code;
         if (msg && msglen > 0) snprintf(msg, msglen, "%s", e.what());

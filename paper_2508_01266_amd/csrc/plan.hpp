@@ -50,10 +50,7 @@ struct Profiler {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
     std::vector<hipEvent_t> pool;
     hipEvent_t ev();
-    hipError_t record(int tag, hipEvent_t a, hipEvent_t b) {
-        marks.push_back({tag, {a, b}});
-        return hipSuccess;
-    }
+    void record(int tag, hipEvent_t a, hipEvent_t b) { marks.push_back({tag, {a, b}}); }
     // sums (ms, count) per tag, recycles the events
     void read(double *ms, long long *cnt);
     ~Profiler();

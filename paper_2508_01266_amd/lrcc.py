@@ -39,19 +39,43 @@ def lib():
         L.lrcc_set_amplitudes.argtypes = [vp, vp, vp]
         L.lrcc_apply_sigma.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
         L.lrcc_apply_sigma_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
+        L.lrcc_apply_sigma_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
+        L.lrcc_apply_sigma_adjoint_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_set_profiling.argtypes = [vp, i]
         L.lrcc_read_profile.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         L.lrcc_sigma_flops.argtypes = [vp, i, i, dp]
         for f in ("lrcc_set_profiling", "lrcc_read_profile", "lrcc_sigma_flops"):
             getattr(L, f).restype = ctypes.c_int
+        L.lrcc_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+        L.lrcc_solve_opts_default.restype = None
+        L.lrcc_solve_response.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                          ctypes.POINTER(SolveReport)]
+        L.lrcc_solve_response.restype = ctypes.c_int
+        L.lrcc_solve_response_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                              ctypes.POINTER(SolveReport), vp]
+        L.lrcc_solve_response_dev.restype = ctypes.c_int
         L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
         L.lrcc_plan_check.restype = ctypes.c_int
         L.lrcc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
         for f in ("lrcc_create", "lrcc_set_hamiltonian", "lrcc_set_amplitudes", "lrcc_apply_sigma",
-                  "lrcc_apply_sigma_dev", "lrcc_sizes"):
+                  "lrcc_apply_sigma_dev", "lrcc_apply_sigma_adjoint", "lrcc_apply_sigma_adjoint_dev", "lrcc_sizes"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("krylov", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("mem_cap_bytes", ctypes.c_longlong)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int), ("outer", ctypes.c_int), ("sigma_fp64", ctypes.c_int),
+                ("sigma_fp32", ctypes.c_int), ("max_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def _c128(a, shape=None):
@@ -116,7 +140,11 @@ class Context:
         b = _c128(t2, (nk, nk, nk, o, o, v, v))
         self._check(self._L.lrcc_set_amplitudes(self._h, _ptr(a), _ptr(b)))
 
-    def apply_sigma(self, x1, x2, omega=None, precision=FP64):
+    def apply_sigma_adjoint(self, x1, x2, omega=None, precision=FP64):
+        """y = (A - omega)^T x for the pairing sum u1 w1 + 1/4 sum u2 w2."""
+        return self.apply_sigma(x1, x2, omega, precision, adjoint=True)
+
+    def apply_sigma(self, x1, x2, omega=None, precision=FP64, adjoint=False):
         nk, o, v = self.nk, self.no, self.nv
         R = x1.shape[0]
         a = _c128(x1, (R, nk, o, v))
@@ -124,9 +152,32 @@ class Context:
         y1 = np.empty_like(a)
         y2 = np.empty_like(b)
         om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
-        self._check(self._L.lrcc_apply_sigma(self._h, R, None if om is None else _ptr(om), _ptr(a), _ptr(b),
-                                             _ptr(y1), _ptr(y2), int(precision)))
+        f = self._L.lrcc_apply_sigma_adjoint if adjoint else self._L.lrcc_apply_sigma
+        self._check(f(self._h, R, None if om is None else _ptr(om), _ptr(a), _ptr(b), _ptr(y1), _ptr(y2),
+                      int(precision)))
         return y1, y2
+
+    def solve_options(self, **kw):
+        o = SolveOpts()
+        self._L.lrcc_solve_opts_default(ctypes.byref(o))
+        for k, val in kw.items():
+            setattr(o, k, val)
+        return o
+
+    def solve_response(self, b1, b2, omega, x1=None, x2=None, **opts):
+        """Solve (A - omega_r) x_r = b_r (host arrays, caller layouts). Returns (x1, x2, report dict)."""
+        nk, o, v = self.nk, self.no, self.nv
+        R = b1.shape[0]
+        a = _c128(b1, (R, nk, o, v))
+        b = _c128(b2, (R, nk, nk, nk, o, o, v, v))
+        y1 = np.zeros_like(a) if x1 is None else _c128(x1, a.shape).copy()
+        y2 = np.zeros_like(b) if x2 is None else _c128(x2, b.shape).copy()
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        oo = self.solve_options(**opts)
+        rep = SolveReport()
+        self._check(self._L.lrcc_solve_response(self._h, R, _ptr(om), _ptr(a), _ptr(b), _ptr(y1), _ptr(y2),
+                                                ctypes.byref(oo), ctypes.byref(rep)))
+        return y1, y2, rep.as_dict()
 
     def set_profiling(self, on=True):
         self._check(self._L.lrcc_set_profiling(self._h, int(bool(on))))
@@ -143,10 +194,11 @@ class Context:
         self._check(self._L.lrcc_sigma_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
         return out.value
 
-    def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None):
+    def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None, adjoint=False):
         """Device-pointer variant for torch tensors (complex128, caller layouts)."""
         R = x1.shape[0]
-        st = self._L.lrcc_apply_sigma_dev(
+        f = self._L.lrcc_apply_sigma_adjoint_dev if adjoint else self._L.lrcc_apply_sigma_dev
+        st = f(
             self._h, R, None if omega is None else ctypes.c_void_p(omega.data_ptr()),
             ctypes.c_void_p(x1.data_ptr()), ctypes.c_void_p(x2.data_ptr()),
             ctypes.c_void_p(y1.data_ptr()), ctypes.c_void_p(y2.data_ptr()), int(precision),

@@ -36,3 +36,47 @@ def oracle_sigma(case):
         y1[r] = layout.block_t1(s1.numpy(), nk, o, v) - w * case['x1'][r]
         y2[r] = nk * layout.block_t2(s2.numpy(), nk, o, v) - w * case['x2'][r]
     return y1, y2
+
+
+def oracle_sigma_adjoint(case, z1, z2):
+    """y = (A_p - w)^T z in the library's (per-cell) normalisation: with S = diag(1, Nk)
+    the per-cell operator is A_p = S A_c S^-1, so A_p^T = S^-1 A_c^T S, A_c^T being the
+    oracle's transpose product (pairing sum u1 w1 + 1/4 sum u2 w2)."""
+    nk, o, v = case['nk'], case['o'], case['v']
+    H = case['H']
+    f = layout.dense_one_body(H['fock'], nk, o, v)
+    g = layout.dense_eri(H['chol'], nk, o, v)
+    h = ccsd.DenseHam.from_numpy(f, g, nk * o)
+    t = (torch.from_numpy(layout.dense_t1(case['t1'], nk, o, v)),
+         torch.from_numpy(layout.dense_t2(case['t2'] / nk, nk, o, v)))
+    y1 = np.empty_like(z1)
+    y2 = np.empty_like(z2)
+    for r in range(z1.shape[0]):
+        zc = (torch.from_numpy(layout.dense_t1(z1[r], nk, o, v)),
+              torch.from_numpy(layout.dense_t2(z2[r] * nk, nk, o, v)))
+        g1, g2 = response.transpose_product(t, zc, h)
+        w = case['omega'][r]
+        y1[r] = layout.block_t1(g1.numpy(), nk, o, v) - w * z1[r]
+        y2[r] = layout.block_t2(g2.numpy(), nk, o, v) / nk - w * z2[r]
+    return y1, y2
+
+
+def oracle_solve(case, b1, b2, tol=1e-12):
+    """Oracle solution of (A_p - w_r) x_r = b_r in the library normalisation:
+    (A_c - w) S^-1 x = S^-1 b with S = diag(1, Nk)."""
+    nk, o, v = case['nk'], case['o'], case['v']
+    H = case['H']
+    f = layout.dense_one_body(H['fock'], nk, o, v)
+    g = layout.dense_eri(H['chol'], nk, o, v)
+    h = ccsd.DenseHam.from_numpy(f, g, nk * o)
+    t = (torch.from_numpy(layout.dense_t1(case['t1'], nk, o, v)),
+         torch.from_numpy(layout.dense_t2(case['t2'] / nk, nk, o, v)))
+    x1 = np.empty_like(b1)
+    x2 = np.empty_like(b2)
+    for r in range(b1.shape[0]):
+        rhs = (torch.from_numpy(layout.dense_t1(b1[r], nk, o, v)),
+               torch.from_numpy(layout.dense_t2(b2[r] / nk, nk, o, v)))
+        sol, rel, _ = response.solve_response(t, h, rhs, case['omega'][r], tol=tol)
+        x1[r] = layout.block_t1(sol[0].numpy(), nk, o, v)
+        x2[r] = nk * layout.block_t2(sol[1].numpy(), nk, o, v)
+    return x1, x2
