@@ -172,6 +172,36 @@ lrcc_status lrcc_solve_response_dev(lrcc_ctx *ctx, int nrhs, const double *omega
                                     const void *b1, const void *b2, void *x1, void *x2,
                                     const lrcc_solve_opts *opts, lrcc_solve_report *report, void *stream);
 
+/* Frequency-dependent polarizability (Eq. lrf, symmetric form) for the dipole
+ * axes in axis_mask (bit x = axis x; axes whose dipole matrices vanish are
+ * skipped, as in Sec. II.B) at nfreq frequencies omega (host array, a.u.).
+ * Solves, on the device: the lambda equations (Eqs. l1, l2) once per set of
+ * amplitudes, the perturbed amplitudes t^X(+-omega_j) for all axes and
+ * frequencies as ONE batch of 2*nfreq*naxes right-hand sides (Eqs. tx1, tx2),
+ * and contracts them in complex128 into
+ *   alpha_XY(w) = -1/(2 Nk) [g_XY(w) + conj(g_XY(-w))],
+ *   g_XY(w) = eta^X t^Y(w) + eta^Y t^X(-w) + F(t^X(-w), t^Y(w)),
+ * the polarizability per cell (reading of the paper's sign and symmetrisation
+ * conventions as documented with the library).  opts->precision selects the
+ * plain complex128 solver or complex64 matrix-core corrections inside complex128
+ * refinement; the residual tolerance, subspace size and memory cap come from
+ * opts (NULL: defaults).  Results stay in the context: lrcc_get_alpha,
+ * lrcc_get_solution, lrcc_get_lambda. */
+lrcc_status lrcc_solve(lrcc_ctx *ctx, unsigned axis_mask, int nfreq, const double *omega,
+                       const lrcc_solve_opts *opts, lrcc_solve_report *report);
+
+/* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
+ * nfreq must match it. */
+lrcc_status lrcc_get_alpha(lrcc_ctx *ctx, int nfreq, double *alpha);
+
+/* Perturbed amplitudes t^X(sign*omega_ifreq) of the last lrcc_solve (caller
+ * layouts with nrhs = 1, per-cell normalisation). */
+lrcc_status lrcc_get_solution(lrcc_ctx *ctx, int axis, int ifreq, int sign, double *x1, double *x2);
+
+/* lambda amplitudes of the last lrcc_solve (layouts of t1/t2; pairing
+ * sum l1 x1 + 1/4 sum l2 x2 with amplitudes in the per-cell normalisation). */
+lrcc_status lrcc_get_lambda(lrcc_ctx *ctx, double *l1, double *l2);
+
 /* Number of amplitude elements per right-hand side: singles and doubles. */
 lrcc_status lrcc_sizes(const lrcc_ctx *ctx, long long *n1, long long *n2);
 

@@ -119,11 +119,15 @@ __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, doubl
         auto z4 = at(kj, ki, kb, j, i, b, a);
         const double zr = (double)z1.x - (double)z2.x - (double)z3.x + (double)z4.x;
         const double zi = (double)z1.y - (double)z2.y - (double)z3.y + (double)z4.y;
-        const double w = omega ? omega[r] : 0.0;
-        double2 xv = x2[t];
         double2 out;
-        out.x = scale * zr - w * xv.x;
-        out.y = scale * zi - w * xv.y;
+        out.x = scale * zr;
+        out.y = scale * zi;
+        if (omega) {
+            const double w = omega[r];
+            const double2 xv = x2[t];
+            out.x -= w * xv.x;
+            out.y -= w * xv.y;
+        }
         y2[t] = out;
     }
 }
@@ -148,11 +152,15 @@ __global__ void k_s1_out(const typename Cx<T>::type *s1, const double2 *x1, doub
         const int k = (int)((t / E) % nk);
         const int r = (int)(t / (E * nk));
         auto sv = s1[((i64)k * R + r) * E + e];
-        const double w = omega ? omega[r] : 0.0;
-        double2 xv = x1[t];
         double2 out;
-        out.x = (double)sv.x - w * xv.x;
-        out.y = (double)sv.y - w * xv.y;
+        out.x = (double)sv.x;
+        out.y = (double)sv.y;
+        if (omega) {
+            const double w = omega[r];
+            const double2 xv = x1[t];
+            out.x -= w * xv.x;
+            out.y -= w * xv.y;
+        }
         y1[t] = out;
     }
 }
@@ -214,6 +222,42 @@ template <typename Tout>
 hipError_t one_body_slice(const void *in, void *out, int nk, int n, int p0, int np, int q0, int nq, hipStream_t s) {
     hipLaunchKernelGGL(k_one_body_slice<Tout>, dim3(grid_for((i64)nk * np * nq)), dim3(256), 0, s,
                        (const double2 *)in, (typename Cx<Tout>::type *)out, nk, n, p0, np, q0, nq);
+    return hipGetLastError();
+}
+
+template <typename Tout>
+__global__ void k_axis_slice(const double2 *in, typename Cx<Tout>::type *out, int nax, int nk, int n, int p0, int np,
+                             int q0, int nq, int transpose) {
+    const i64 N = (i64)nk * nax * np * nq;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int qq = (int)(q % nq); q /= nq;
+        const int pp = (int)(q % np); q /= np;
+        const int x = (int)(q % nax);
+        const int k = (int)(q / nax);
+        const double2 v = transpose ? in[(((i64)x * nk + k) * n + q0 + qq) * n + p0 + pp]
+                                    : in[(((i64)x * nk + k) * n + p0 + pp) * n + q0 + qq];
+        out[t] = mk<Tout>((Tout)v.x, (Tout)v.y);
+    }
+}
+
+template <typename Tout>
+hipError_t axis_slice(const void *in, void *out, int nax, int nk, int n, int p0, int np, int q0, int nq, int transpose,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_axis_slice<Tout>, dim3(grid_for((i64)nk * nax * np * nq)), dim3(256), 0, s,
+                       (const double2 *)in, (typename Cx<Tout>::type *)out, nax, nk, n, p0, np, q0, nq, transpose);
+    return hipGetLastError();
+}
+
+// y = alpha * x (complex alpha, n elements, double2)
+__global__ void k_scale_copy(double2 *y, const double2 *x, double ar, double ai, i64 n) {
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const double2 v = x[t];
+        y[t] = make_double2(ar * v.x - ai * v.y, ar * v.y + ai * v.x);
+    }
+}
+hipError_t scale_copy(void *y, const void *x, double ar, double ai, i64 n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, (double2 *)y, (const double2 *)x, ar, ai, n);
     return hipGetLastError();
 }
 
@@ -325,6 +369,7 @@ hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hi
     template hipError_t chol_slice<T>(const void *, void *, int, int, int, int, int, int, int, double, int,  \
                                       hipStream_t);                                                          \
     template hipError_t one_body_slice<T>(const void *, void *, int, int, int, int, int, int, hipStream_t);  \
+    template hipError_t axis_slice<T>(const void *, void *, int, int, int, int, int, int, int, int, hipStream_t); \
     template hipError_t rhs_to_block<double, T>(const void *, void *, int, i64, i64, double, hipStream_t);
 INST(double)
 INST(float)

@@ -20,6 +20,10 @@ hipError_t chol_slice(const void *L, void *out, int nk, int naux, int n, int p0,
 template <typename Tout>
 hipError_t one_body_slice(const void *in, void *out, int nk, int n, int p0, int np, int q0, int nq, hipStream_t s);
 hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s);
+template <typename Tout>
+hipError_t axis_slice(const void *in, void *out, int nax, int nk, int n, int p0, int np, int q0, int nq, int transpose,
+                      hipStream_t s);
+hipError_t scale_copy(void *y, const void *x, double ar, double ai, i64 n, hipStream_t s);
 template <typename T>
 hipError_t pp_in(const void *y, void *Z, int nk, int R, int o, int v, double scale, hipStream_t s);
 template <typename T>

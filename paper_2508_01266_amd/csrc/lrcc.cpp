@@ -90,8 +90,23 @@ struct lrcc_ctx {
     size_t stage_bytes = 0;
     void *st_x1 = nullptr, *st_x2 = nullptr, *st_y1 = nullptr, *st_y2 = nullptr, *st_om = nullptr;
     Profiler prof;
+    std::unique_ptr<Program> pre64, pre32;     // amplitude-dependent blocks (f64) and their f32 copies
     void *eps_o = nullptr, *eps_v = nullptr;   // diagonal of fock per k (preconditioner)
     DevMem solmem;                             // solver work vectors
+    bool lam_valid = false;
+    void *dip = nullptr;                       // [3][nk][n][n] device copy
+    State<double> xs[3];                       // one-body perturbation operators (dipole axes)
+    std::unique_ptr<Program> prex[3], prog_xi, prog_grad;
+    DevMem amem;                               // alpha pipeline buffers
+    void *lam1 = nullptr, *lam2 = nullptr, *xi1 = nullptr, *xi2 = nullptr, *gb1 = nullptr, *gb2 = nullptr;
+    void *ybuf = nullptr, *ubuf = nullptr;     // E'' helper vectors [nk][o][v]
+    std::unique_ptr<Program> prog_epp;
+    // last polarizability solve
+    int nfreq = 0, nrhs_sol = 0;
+    std::vector<int> axes;
+    std::vector<double> alpha;                 // [nfreq][3][3] complex
+    DevMem solv;                               // solutions x of the last solve
+    void *sol1 = nullptr, *sol2 = nullptr;
     size_t sol_bytes = 0;
 };
 
@@ -229,7 +244,9 @@ void convert_kt(Program &P, State<float> &dst_state, KT &dst, const KT &src, lrc
 }
 
 // ---------------------------------------------------------------- precompute
-void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
+// Allocate the amplitude-dependent state and record the programs that compute it
+// from the device amplitudes (run again whenever the amplitudes change).
+void build_state(lrcc_ctx *c) {
     const int nk = c->nk, o = c->no, v = c->nv, n = c->n, naux = c->naux;
     State<double> &S = c->s64;
     S.mem.release();
@@ -238,18 +255,11 @@ void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
     c->progs.clear();
     c->progmem.clear();
     DevMem &m = S.mem;
-    Program P;
+    auto Pp = std::make_unique<Program>();
+    Program &P = *Pp;
 
     S.t1 = alloc_kt<double>(c, m, "ov");
     S.t2 = alloc_kt<double>(c, m, "oovv");
-    // paper -> crystal normalisation of T2
-    if (!g_dry_run) {
-        HIPCHK(hipMemcpy(S.t1.p, t1h, S.t1.count() * 16, hipMemcpyHostToDevice));
-        std::vector<double> tmp(S.t2.count() * 2);
-        std::memcpy(tmp.data(), t2h, tmp.size() * sizeof(double));
-        for (auto &x : tmp) x /= nk;
-        HIPCHK(hipMemcpy(S.t2.p, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
-    }
     S.fov = alloc_kt<double>(c, m, "ov");
     KT foo = alloc_kt<double>(c, m, "oo"), fvv = alloc_kt<double>(c, m, "vv");
     void *fock = c->fock;
@@ -345,15 +355,13 @@ void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
         P.ops.push_back([=](hipStream_t s) { return pair_transpose<double>(La, LaT, nk, naux, v, s); });
         P.ops.push_back([=](hipStream_t s) { return pair_transpose<double>(Lb, LbT, nk, naux, v, s); });
     }
-    if (!g_dry_run) {
-        HIPCHK(P.run(nullptr));
-        HIPCHK(hipDeviceSynchronize());
-    }
+    c->pre64 = std::move(Pp);
     S.ready = true;
 
     // single-precision copies of everything the sigma reads
     State<float> &F = c->s32;
-    Program P2;
+    auto P2p = std::make_unique<Program>();
+    Program &P2 = *P2p;
     auto cv = [&](KT &d, const KT &s) { convert_kt<float>(P2, F, d, s, c); };
     cv(F.fov, S.fov); cv(F.t1, S.t1); cv(F.t2, S.t2); cv(F.tau, S.tau);
     cv(F.g_oovv, S.g_oovv); cv(F.g_ooov, S.g_ooov); cv(F.g_ovov, S.g_ovov); cv(F.g_ovvv, S.g_ovvv);
@@ -370,11 +378,25 @@ void precompute(lrcc_ctx *c, const double *t1h, const double *t2h) {
         void *fa = w == 0 ? F.La : w == 1 ? F.Lb : w == 2 ? F.LaT : F.LbT;
         P2.ops.push_back([=](hipStream_t s) { return convert_f64_f32(a, fa, lvv, s); });
     }
-    if (!g_dry_run) {
-        HIPCHK(P2.run(nullptr));
-        HIPCHK(hipDeviceSynchronize());
-    }
+    c->pre32 = std::move(P2p);
     F.ready = true;
+}
+
+// Upload T1, T2 (paper normalisation; T2 -> crystal by 1/Nk) into the state.
+void upload_amplitudes(lrcc_ctx *c, const double *t1h, const double *t2h) {
+    State<double> &S = c->s64;
+    HIPCHK(hipMemcpy(S.t1.p, t1h, S.t1.count() * 16, hipMemcpyHostToDevice));
+    std::vector<double> tmp(S.t2.count() * 2);
+    std::memcpy(tmp.data(), t2h, tmp.size() * sizeof(double));
+    for (auto &x : tmp) x /= c->nk;
+    HIPCHK(hipMemcpy(S.t2.p, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+
+// Recompute every amplitude-dependent block from the device amplitudes.
+void run_precompute(lrcc_ctx *c, bool fp32, hipStream_t st = nullptr) {
+    HIPCHK(c->pre64->run(st));
+    if (fp32) HIPCHK(c->pre32->run(st));
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------- sigma program
@@ -399,7 +421,7 @@ struct SigmaGraph {
 };
 
 template <typename T>
-SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
+SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
     SigmaGraph G;
     auto A = [&](const char *cls) {
         KT t = alloc_kt<T>(c, wm, cls, R);
@@ -434,7 +456,7 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
     KT dFae = A("vv"), dFmi = A("oo"), dFme = A("ov"), dFbe = A("vv"), dFmj = A("oo");
     KT Zmn = A("oooo"), Vx = A("oooo"), Yx = A("oovo");
     G.x1 = x1; G.x2 = x2; G.Z = Z; G.s1 = s1;
-    {
+    if (full) {
         SymOp op;
         op.kind = SymOp::TAU;
         op.C = dtau; op.A = x1; op.B = x2; op.actA = op.actB = true;
@@ -443,37 +465,44 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
     const KT &t1 = S.t1, &t2 = S.t2;
     // X-dependent one-body intermediates (derivatives of F_ae, F_mi, F_me)
     con(dFae, "Rae", x1, "Rma", S.fov, "me", -0.5, false);
-    con(dFae, "Rae", x1, "Rmf", S.g_ovvv, "mafe", 1.0);
-    con(dFae, "Rae", x2, "Rmnaf", S.g_oovv, "mnef", -0.25);
-    con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.25);
+    if (full) {
+        con(dFae, "Rae", x1, "Rmf", S.g_ovvv, "mafe", 1.0);
+        con(dFae, "Rae", x2, "Rmnaf", S.g_oovv, "mnef", -0.25);
+        con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.25);
+    }
     con(dFmi, "Rmi", x1, "Rie", S.fov, "me", 0.5, false);
-    con(dFmi, "Rmi", x1, "Rne", S.g_ooov, "mnie", 1.0);
-    con(dFmi, "Rmi", x2, "Rinef", S.g_oovv, "mnef", 0.25);
-    con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.25);
-    con(dFme, "Rme", x1, "Rnf", S.g_oovv, "mnef", 1.0, false);
+    if (full) {
+        con(dFmi, "Rmi", x1, "Rne", S.g_ooov, "mnie", 1.0);
+        con(dFmi, "Rmi", x2, "Rinef", S.g_oovv, "mnef", 0.25);
+        con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.25);
+        con(dFme, "Rme", x1, "Rnf", S.g_oovv, "mnef", 1.0, false);
+    }
     // singles (operator part of Eq. tx1)
     con(s1, "Ria", x1, "Rie", S.Fae, "ae", 1.0, false);
     con(s1, "Ria", t1, "ie", dFae, "Rae", 1.0);
     con(s1, "Ria", x1, "Rma", S.Fmi, "mi", -1.0);
     con(s1, "Ria", t1, "ma", dFmi, "Rmi", -1.0);
     con(s1, "Ria", x2, "Rimae", S.Fme, "me", 1.0);
-    con(s1, "Ria", t2, "imae", dFme, "Rme", 1.0);
-    con(s1, "Ria", x1, "Rnf", S.g_ovov, "naif", -1.0);
-    con(s1, "Ria", x2, "Rimef", S.g_ovvv, "maef", -0.5);
-    con(s1, "Ria", x2, "Rmnae", S.g_ooov, "nmie", 0.5);
+    if (full) {
+        con(s1, "Ria", t2, "imae", dFme, "Rme", 1.0);
+        con(s1, "Ria", x1, "Rnf", S.g_ovov, "naif", -1.0);
+        con(s1, "Ria", x2, "Rimef", S.g_ovvv, "maef", -0.5);
+        con(s1, "Ria", x2, "Rmnae", S.g_ooov, "nmie", 0.5);
+    }
     // dressed one-body derivatives entering the doubles
     copy(dFbe, dFae);
     con(dFbe, "Rbe", x1, "Rmb", S.Fme, "me", -0.5);
-    con(dFbe, "Rbe", t1, "mb", dFme, "Rme", -0.5);
+    if (full) con(dFbe, "Rbe", t1, "mb", dFme, "Rme", -0.5);
     copy(dFmj, dFmi);
     con(dFmj, "Rmj", x1, "Rje", S.Fme, "me", 0.5);
-    con(dFmj, "Rmj", t1, "je", dFme, "Rme", 0.5);
+    if (full) con(dFmj, "Rmj", t1, "je", dFme, "Rme", 0.5);
     // doubles (operator part of Eq. tx2): Z collects every term, sigma2 = P(ij)P(ab) Z.
     // Terms antisymmetric in both pairs enter with 1/4, in one pair with 1/2.
     con(Z, "Rijab", x2, "Rijae", S.Fbe, "be", 0.5, false);
     con(Z, "Rijab", t2, "ijae", dFbe, "Rbe", 0.5);
     con(Z, "Rijab", x2, "Rimab", S.Fmj, "mj", -0.5);
     con(Z, "Rijab", t2, "imab", dFmj, "Rmj", -0.5);
+    if (!full) return G;  // one-body (perturbation) operator: no two-electron terms
     {
         SymOp op;
         op.kind = SymOp::LADDER;
@@ -510,10 +539,10 @@ LadderArgs ladder_args(lrcc_ctx *c, const void *Y, const void *La, const void *L
 }
 
 template <typename T>
-Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
+Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
-    SigmaGraph G = record_sigma<T>(c, S, R, wm);
+    SigmaGraph G = record_sigma<T>(c, S, R, wm, full);
     const i64 nb3 = (i64)nk * nk * nk;
     KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
     // caller layout -> internal (paper -> crystal normalisation for doubles)
@@ -554,10 +583,10 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
 // Transpose product y = (A - omega)^T z with respect to the pairing
 // <u, v> = sum u1 v1 + 1/4 sum u2 v2 (amplitude arrays in the caller's normalisation).
 template <typename T>
-Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
+Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
-    SigmaGraph G = record_sigma<T>(c, S, R, wm);
+    SigmaGraph G = record_sigma<T>(c, S, R, wm, full);
     // adjoint buffer for every active tensor (the forward buffers are reused as adjoints)
     for (const KT &a : G.active) {
         void *p = a.p;
@@ -610,13 +639,19 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm) {
     return P;
 }
 
-Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false) {
-    auto key = std::make_pair(prec * 2 + (adjoint ? 1 : 0), R);
+// variant 0: the CCSD Jacobian; variant 1+x: the Jacobian of the one-body
+// perturbation residual for dipole axis x (Fock matrix -> mu_x, no two-electron part).
+Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false, int variant = 0) {
+    auto key = std::make_pair(variant * 4 + prec * 2 + (adjoint ? 1 : 0), R);
     auto it = c->progs.find(key);
     if (it != c->progs.end()) return it->second.get();
     auto mem = std::make_unique<DevMem>();
     Program *p;
-    if (!adjoint)
+    if (variant > 0) {
+        if (prec != LRCC_FP64) throw LrccError(LRCC_E_ARG, "perturbation operators are FP64 only");
+        State<double> &X = c->xs[variant - 1];
+        p = adjoint ? build_sigma_adjoint<double>(c, X, R, *mem, false) : build_sigma<double>(c, X, R, *mem, false);
+    } else if (!adjoint)
         p = prec == LRCC_FP64 ? build_sigma<double>(c, c->s64, R, *mem) : build_sigma<float>(c, c->s32, R, *mem);
     else
         p = prec == LRCC_FP64 ? build_sigma_adjoint<double>(c, c->s64, R, *mem)
@@ -644,6 +679,7 @@ struct SolveCtx {
     const double *omega;  // device
     void *part = nullptr, *dout = nullptr, *alpha = nullptr;  // reduction / coefficient scratch
     int nsig64 = 0, nsig32 = 0;
+    bool adjoint = false;
     std::vector<cd> dot(const Vecs &u, const Vecs &v) {
         std::vector<cd> a(R), b(R);
         HIPCHK(batched_dot(u.s, v.s, R, n1, 1.0, part, dout, st));
@@ -681,7 +717,7 @@ struct SolveCtx {
     }
     // y = (A - omega) x
     void op(const Vecs &y, const Vecs &x, int precision) {
-        Program *p = sigma_program(c, precision, R);
+        Program *p = sigma_program(c, precision, R, adjoint);
         c->io_x1 = x.s; c->io_x2 = x.d; c->io_y1 = y.s; c->io_y2 = y.d; c->io_omega = omega;
         HIPCHK(p->run(st, &c->prof));
         (precision == LRCC_FP64 ? nsig64 : nsig32)++;
@@ -801,10 +837,10 @@ std::vector<double> gmres(SolveCtx &S, const Vecs &b, const Vecs &x, int precisi
 }
 
 void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, const Vecs &x,
-                    const lrcc_solve_opts &o, lrcc_solve_report &rep, hipStream_t st) {
+                    const lrcc_solve_opts &o, lrcc_solve_report &rep, hipStream_t st, bool adjoint = false) {
     auto t0 = std::chrono::steady_clock::now();
     SolveCtx S;
-    S.c = c; S.R = R; S.st = st; S.omega = omega_dev;
+    S.c = c; S.R = R; S.st = st; S.omega = omega_dev; S.adjoint = adjoint;
     S.n1 = (i64)c->nk * c->no * c->nv;
     S.n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
     const int m = std::max(1, o.krylov);
@@ -868,12 +904,306 @@ void default_opts(lrcc_solve_opts &o) {
     o.mem_cap_bytes = 0;
 }
 
+
+// ---------------------------------------------------------------- polarizability
+// alpha_XY(w) per cell from the symmetric linear-response function (Eq. lrf):
+//   alpha = -1/(2 Nk) C^{+-w} [eta^X t^Y(w) + eta^Y t^X(-w) + F(t^X(-w), t^Y(w))],
+//   C^{+-w} g(w) = g(w) + conj(g(-w)),
+// with (A - w) t^X(w) = -xi^X (Eqs. rhs, tx1, tx2), A^T lambda = -dE/dT
+// (Eqs. l1, l2), eta^X = A_X^T lambda + dE_X/dT for the one-body perturbation
+// operator of axis X, and F(x, y) = d2 L / dT dT [x, y] of the Lagrangian
+// L = E + <lambda, Omega>.  F is evaluated as the exact 5-point derivative of
+// A(T + e y)^T lambda (A is cubic in T) plus the energy's second derivative.
+// All pairings are bilinear: <u, w> = sum u1 w1 + 1/4 sum u2 w2.
+void ensure_alpha_programs(lrcc_ctx *c) {
+    if (c->prog_xi) return;
+    const int nk = c->nk, o = c->no, v = c->nv, n = c->n;
+    State<double> &S = c->s64;
+    const i64 n1 = (i64)nk * o * v, n2 = (i64)nk * nk * nk * o * o * v * v;
+    DevMem &m = c->amem;
+    c->lam1 = m.get(n1 * 16); c->lam2 = m.get(n2 * 16);
+    c->xi1 = m.get(3 * n1 * 16); c->xi2 = m.get(3 * n2 * 16);
+    c->gb1 = m.get(n1 * 16); c->gb2 = m.get(n2 * 16);
+    c->ybuf = m.get(n1 * 16); c->ubuf = m.get(n1 * 16);
+    // one-body perturbation states: F-type intermediates of the residual with f -> mu_x, v -> 0
+    for (int x = 0; x < 3; ++x) {
+        State<double> &X = c->xs[x];
+        DevMem &xm = X.mem;
+        auto P = std::make_unique<Program>();
+        X.t1 = S.t1; X.t2 = S.t2; X.tau = S.tau;
+        X.fov = alloc_kt<double>(c, xm, "ov");
+        KT foo = alloc_kt<double>(c, xm, "oo"), fvv = alloc_kt<double>(c, xm, "vv");
+        const void *dx = (const char *)c->dip + (size_t)x * nk * n * n * 16;
+        {
+            void *a = X.fov.p, *b = foo.p, *d = fvv.p;
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dx, a, 1, nk, n, 0, o, o, v, 0, s); });
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dx, b, 1, nk, n, 0, o, 0, o, 0, s); });
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dx, d, 1, nk, n, o, v, o, v, 0, s); });
+        }
+        const KT &t1 = S.t1;
+        X.Fae = alloc_kt<double>(c, xm, "vv");
+        kt_copy<double>(*P, X.Fae, fvv);
+        contract<double>(*P, X.Fae, "ae", X.fov, "me", t1, "ma", -0.5);
+        X.Fmi = alloc_kt<double>(c, xm, "oo");
+        kt_copy<double>(*P, X.Fmi, foo);
+        contract<double>(*P, X.Fmi, "mi", t1, "ie", X.fov, "me", 0.5);
+        X.Fme = X.fov;
+        X.Fbe = alloc_kt<double>(c, xm, "vv");
+        kt_copy<double>(*P, X.Fbe, X.Fae);
+        contract<double>(*P, X.Fbe, "be", t1, "mb", X.Fme, "me", -0.5);
+        X.Fmj = alloc_kt<double>(c, xm, "oo");
+        kt_copy<double>(*P, X.Fmj, X.Fmi);
+        contract<double>(*P, X.Fmj, "mj", t1, "je", X.Fme, "me", 0.5);
+        X.ready = true;
+        c->prex[x] = std::move(P);
+    }
+    // xi^X for all three axes (caller layout, per-cell normalisation): Eq. rhs in the
+    // standard <mu| exp(-T) X exp(T) |HF> form
+    {
+        auto P = std::make_unique<Program>();
+        const int R = 3;
+        KT Xoo = alloc_kt<double>(c, m, "oo", R), Xov = alloc_kt<double>(c, m, "ov", R);
+        KT Xvv = alloc_kt<double>(c, m, "vv", R), s1 = alloc_kt<double>(c, m, "ov", R);
+        KT Y = alloc_kt<double>(c, m, "vv", R), Fx = alloc_kt<double>(c, m, "vv", R), Gx = alloc_kt<double>(c, m, "oo", R);
+        KT Z = alloc_kt<double>(c, m, "oovv", R);
+        const void *dip = c->dip;
+        {
+            void *a = Xoo.p, *b = Xov.p, *d = Xvv.p, *e = s1.p;
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dip, a, 3, nk, n, 0, o, 0, o, 0, s); });
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dip, b, 3, nk, n, 0, o, o, v, 0, s); });
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dip, d, 3, nk, n, o, v, o, v, 0, s); });
+            // driver X_ai stored as [k][x][i][a]
+            P->ops.push_back([=](hipStream_t s) { return axis_slice<double>(dip, e, 3, nk, n, 0, o, o, v, 1, s); });
+        }
+        const KT &t1 = S.t1, &t2 = S.t2;
+        contract<double>(*P, s1, "Ria", t2, "ikac", Xov, "Rkc", 1.0);
+        contract<double>(*P, Y, "Rac", t1, "ka", Xov, "Rkc", 1.0, false);
+        contract<double>(*P, s1, "Ria", t1, "ic", Y, "Rac", -1.0);
+        contract<double>(*P, s1, "Ria", t1, "ic", Xvv, "Rac", 1.0);
+        contract<double>(*P, s1, "Ria", t1, "ka", Xoo, "Rki", -1.0);
+        kt_copy<double>(*P, Fx, Xvv);
+        contract<double>(*P, Fx, "Rbc", t1, "kb", Xov, "Rkc", -1.0);
+        kt_copy<double>(*P, Gx, Xoo);
+        contract<double>(*P, Gx, "Rkj", t1, "jc", Xov, "Rkc", 1.0);
+        contract<double>(*P, Z, "Rijab", t2, "ijac", Fx, "Rbc", 0.5, false);
+        contract<double>(*P, Z, "Rijab", t2, "ikab", Gx, "Rkj", -0.5);
+        void *xi1 = c->xi1, *xi2 = c->xi2;
+        P->ops.push_back([=](hipStream_t s) { return s1_out<double>(s1.p, nullptr, xi1, nullptr, nk, R, o, v, s); });
+        P->ops.push_back([=](hipStream_t s) { return pp_out<double>(Z.p, nullptr, xi2, nullptr, nk, R, o, v, (double)nk, s); });
+        c->prog_xi = std::move(P);
+    }
+    // right-hand side of the lambda equations: -(S^-1 dE/dT) = -(f_ia + <ij||ab> t_jb, <ij||ab>/Nk)
+    {
+        auto P = std::make_unique<Program>();
+        KT g1 = alloc_kt<double>(c, m, "ov");
+        kt_copy<double>(*P, g1, S.fov);
+        contract<double>(*P, g1, "ia", S.g_oovv, "ijab", S.t1, "jb", 1.0);
+        void *gb1 = c->gb1, *gb2 = c->gb2, *ov = S.g_oovv.p;
+        P->ops.push_back([=](hipStream_t s) { return scale_copy(gb1, g1.p, -1.0, 0.0, n1, s); });
+        P->ops.push_back([=](hipStream_t s) { return scale_copy(gb2, ov, -1.0 / nk, 0.0, n2, s); });
+        c->prog_grad = std::move(P);
+    }
+    // second derivative of the energy: u_ia = sum_jb <ij||ab> y_jb
+    {
+        auto P = std::make_unique<Program>();
+        KT y = make_kt(c, "ov", c->ybuf), u = make_kt(c, "ov", c->ubuf);
+        contract<double>(*P, u, "ia", S.g_oovv, "ijab", y, "jb", 1.0, false);
+        c->prog_epp = std::move(P);
+    }
+}
+
+void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega, const lrcc_solve_opts &o,
+                 lrcc_solve_report &rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    ensure_alpha_programs(c);
+    hipStream_t st = nullptr;
+    // axes with a non-zero dipole (the paper skips vanishing components, Sec. II.B)
+    std::vector<int> axes;
+    {
+        std::vector<double> d((size_t)3 * nk * n * n * 2);
+        HIPCHK(hipMemcpy(d.data(), c->dip, d.size() * 8, hipMemcpyDeviceToHost));
+        for (int x = 0; x < 3; ++x) {
+            if (!(axis_mask & (1u << x))) continue;
+            double mx = 0;
+            for (size_t i = 0; i < (size_t)nk * n * n * 2; ++i) mx = std::max(mx, std::fabs(d[(size_t)x * nk * n * n * 2 + i]));
+            if (mx > 1e-14) axes.push_back(x);
+        }
+    }
+    const int nax = (int)axes.size();
+    c->axes = axes;
+    c->nfreq = nfreq;
+    c->alpha.assign((size_t)nfreq * 9 * 2, 0.0);
+    rep = lrcc_solve_report{};
+    if (nax == 0 || nfreq == 0) return;
+    DevMem tmp;
+    auto vec = [&](int R) { Vecs v; v.s = tmp.get((size_t)R * n1 * 16); v.d = tmp.get((size_t)R * n2 * 16); return v; };
+    auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
+    SolveCtx D;  // for bilinear dots
+    D.c = c; D.R = 1; D.n1 = n1; D.n2 = n2; D.st = st;
+    D.part = tmp.get((size_t)dot_blocks(n2) * 16 * 2);
+    D.dout = tmp.get(32);
+    D.alpha = tmp.get(32);
+    auto bdot = [&](const Vecs &u, const Vecs &v) {
+        cd a, b;
+        HIPCHK(batched_dot(u.s, v.s, 1, n1, 1.0, D.part, D.dout, st, 0));
+        HIPCHK(hipMemcpy(&a, D.dout, 16, hipMemcpyDeviceToHost));
+        HIPCHK(batched_dot(u.d, v.d, 1, n2, 0.25, D.part, D.dout, st, 0));
+        HIPCHK(hipMemcpy(&b, D.dout, 16, hipMemcpyDeviceToHost));
+        return a + b;
+    };
+    void *zero_om = tmp.get(8 * 2);
+    HIPCHK(hipMemset(zero_om, 0, 16));
+    lrcc_solve_report r1{};
+    Vecs lam{c->lam1, c->lam2};
+    // lambda (once per set of amplitudes)
+    if (!c->lam_valid) {
+        HIPCHK(c->prog_grad->run(st));
+        HIPCHK(hipMemset(c->lam1, 0, n1 * 16));
+        HIPCHK(hipMemset(c->lam2, 0, n2 * 16));
+        Vecs b{c->gb1, c->gb2};
+        solve_response(c, 1, (const double *)zero_om, b, lam, o, r1, st, true);
+        if (!r1.converged) throw LrccError(LRCC_E_NOCONV, "lambda equations did not converge");
+        c->lam_valid = true;
+    }
+    // perturbation vectors and the batched response solve: rhs r = (j*2 + sign)*nax + a
+    HIPCHK(c->prog_xi->run(st));
+    const int R = nfreq * 2 * nax;
+    c->solv.release();
+    c->sol1 = c->solv.get((size_t)R * n1 * 16);
+    c->sol2 = c->solv.get((size_t)R * n2 * 16);
+    Vecs X{c->sol1, c->sol2};
+    Vecs B = vec(R);
+    std::vector<double> om(R);
+    for (int j = 0; j < nfreq; ++j)
+        for (int sg = 0; sg < 2; ++sg)
+            for (int a = 0; a < nax; ++a) {
+                const int r = (j * 2 + sg) * nax + a;
+                om[r] = sg == 0 ? omega[j] : -omega[j];
+                Vecs xi{(char *)c->xi1 + (size_t)axes[a] * n1 * 16, (char *)c->xi2 + (size_t)axes[a] * n2 * 16};
+                Vecs br = sub(B, r);
+                HIPCHK(scale_copy(br.s, xi.s, -1.0, 0.0, n1, st));
+                HIPCHK(scale_copy(br.d, xi.d, -1.0, 0.0, n2, st));
+            }
+    void *dom = tmp.get((size_t)R * 8);
+    HIPCHK(hipMemcpy(dom, om.data(), R * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(X.s, 0, (size_t)R * n1 * 16));
+    HIPCHK(hipMemset(X.d, 0, (size_t)R * n2 * 16));
+    lrcc_solve_report r2{};
+    solve_response(c, R, (const double *)dom, B, X, o, r2, st);
+    c->nrhs_sol = R;
+    if (!r2.converged) throw LrccError(LRCC_E_NOCONV, "response equations did not converge");
+    // eta^X = A_X^T lambda + (X_ov, 0)
+    std::vector<Vecs> eta(nax);
+    for (int a = 0; a < nax; ++a) {
+        eta[a] = vec(1);
+        HIPCHK(c->prex[axes[a]]->run(st));
+        Program *p = sigma_program(c, LRCC_FP64, 1, true, 1 + axes[a]);
+        c->io_x1 = lam.s; c->io_x2 = lam.d; c->io_y1 = eta[a].s; c->io_y2 = eta[a].d; c->io_omega = nullptr;
+        HIPCHK(p->run(st));
+        const void *dx = (const char *)c->dip + (size_t)axes[a] * nk * n * n * 16;
+        HIPCHK(axis_slice<double>(dx, c->ubuf, 1, nk, n, 0, no, no, nv, 0, st));
+        HIPCHK(add_inplace<double>(eta[a].s, c->ubuf, n1, st));
+    }
+    // eta . t for every axis and solution
+    std::vector<cd> et((size_t)nax * R);
+    for (int a = 0; a < nax; ++a)
+        for (int r = 0; r < R; ++r) et[(size_t)a * R + r] = bdot(eta[a], sub(X, r));
+    // F(t^X(-w), t^Y(+w)) by the exact stencil in T along y = t^Y(+w)
+    std::vector<cd> Fv((size_t)nfreq * nax * nax);
+    {
+        State<double> &S = c->s64;
+        const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+        void *T1 = tmp.get(nt1 * 16), *T2 = tmp.get(nt2 * 16);
+        HIPCHK(hipMemcpy(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemcpy(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice));
+        Vecs Fy = vec(1), q = vec(1);
+        Program *adj = sigma_program(c, LRCC_FP64, 1, true);
+        const double coef[4] = {1.0, -8.0, 8.0, -1.0};
+        const int shift[4] = {-2, -1, 1, 2};
+        for (int j = 0; j < nfreq; ++j)
+            for (int b = 0; b < nax; ++b) {
+                Vecs y = sub(X, (j * 2 + 0) * nax + b);
+                // step: |h y| about 1e-2 in the rms sense
+                cd yy = 0;
+                {
+                    SolveCtx N = D;
+                    N.R = 1;
+                    yy = N.dot(y, y)[0];
+                }
+                const double rms = std::sqrt(std::max(yy.real(), 1e-300) / (double)(n1 + n2 / 4));
+                const double h = 1e-2 / rms;
+                HIPCHK(hipMemset(Fy.s, 0, n1 * 16));
+                HIPCHK(hipMemset(Fy.d, 0, n2 * 16));
+                for (int k = 0; k < 4; ++k) {
+                    // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
+                    HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+                    std::vector<cd> a1(1, cd(shift[k] * h, 0.0)), a2(1, cd(shift[k] * h / nk, 0.0));
+                    HIPCHK(hipMemcpy(D.alpha, a1.data(), 16, hipMemcpyHostToDevice));
+                    HIPCHK(batched_axpby(S.t1.p, y.s, D.alpha, 1.0, 1, nt1, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
+                    HIPCHK(batched_axpby(S.t2.p, y.d, D.alpha, 1.0, 1, nt2, st));
+                    run_precompute(c, false, st);
+                    c->io_x1 = lam.s; c->io_x2 = lam.d; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
+                    HIPCHK(adj->run(st));
+                    std::vector<cd> w(1, cd(coef[k] / (12.0 * h), 0.0));
+                    HIPCHK(hipMemcpy(D.alpha, w.data(), 16, hipMemcpyHostToDevice));
+                    HIPCHK(batched_axpby(Fy.s, q.s, D.alpha, 1.0, 1, n1, st));
+                    HIPCHK(batched_axpby(Fy.d, q.d, D.alpha, 1.0, 1, n2, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                }
+                // energy part: sum <ij||ab> x_ia y_jb
+                HIPCHK(hipMemcpyAsync(c->ybuf, y.s, n1 * 16, hipMemcpyDeviceToDevice, st));
+                HIPCHK(c->prog_epp->run(st));
+                HIPCHK(add_inplace<double>(Fy.s, c->ubuf, n1, st));
+                for (int a = 0; a < nax; ++a) Fv[((size_t)j * nax + a) * nax + b] = bdot(Fy, sub(X, (j * 2 + 1) * nax + a));
+            }
+        HIPCHK(hipMemcpy(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemcpy(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice));
+        run_precompute(c, true, st);
+    }
+    // assemble alpha
+    auto rid = [&](int j, int sg, int a) { return (j * 2 + sg) * nax + a; };
+    for (int j = 0; j < nfreq; ++j)
+        for (int a = 0; a < nax; ++a)
+            for (int b = 0; b < nax; ++b) {
+                // g(X,Y,+) = eta^X t^Y(w) + eta^Y t^X(-w) + F(t^X(-w), t^Y(w))
+                cd gp = et[(size_t)a * R + rid(j, 0, b)] + et[(size_t)b * R + rid(j, 1, a)] + Fv[((size_t)j * nax + a) * nax + b];
+                // g(X,Y,-) = eta^X t^Y(-w) + eta^Y t^X(w) + F(t^X(w), t^Y(-w)) ; F symmetric
+                cd gm = et[(size_t)a * R + rid(j, 1, b)] + et[(size_t)b * R + rid(j, 0, a)] + Fv[((size_t)j * nax + b) * nax + a];
+                cd al = -0.5 * (gp + std::conj(gm)) / (double)nk;
+                const size_t idx = ((size_t)j * 9 + axes[a] * 3 + axes[b]) * 2;
+                c->alpha[idx] = al.real();
+                c->alpha[idx + 1] = al.imag();
+            }
+    rep.converged = 1;
+    rep.outer = r2.outer;
+    rep.sigma_fp64 = r1.sigma_fp64 + r2.sigma_fp64;
+    rep.sigma_fp32 = r1.sigma_fp32 + r2.sigma_fp32;
+    rep.max_rel_residual = std::max(r1.max_rel_residual, r2.max_rel_residual);
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 // Device copies of the Hamiltonian and the stored integral blocks (all but vvvv).
-void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const double *fock, const double *chol) {
+void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const double *fock, const double *chol,
+                       const double *dip) {
     const int n = nocc + nvir;
     c->ham = c->amp = false;
     c->progs.clear();
     c->progmem.clear();
+    c->pre64.reset();
+    c->pre32.reset();
+    for (int x = 0; x < 3; ++x) { c->prex[x].reset(); c->xs[x].mem.release(); c->xs[x].ready = false; }
+    c->prog_xi.reset();
+    c->prog_grad.reset();
+    c->prog_epp.reset();
+    c->amem.release();
+    c->solv.release();
+    c->lam_valid = false;
+    c->s64.ready = c->s32.ready = false;
     c->s64.mem.release();
     c->s32.mem.release();
     c->hmem.release();
@@ -881,6 +1211,8 @@ void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const 
     const i64 nL = (i64)nk * nk * naux * n * n;
     c->fock = c->hmem.get((size_t)nk * n * n * 16);
     if (!g_dry_run) HIPCHK(hipMemcpy(c->fock, fock, (size_t)nk * n * n * 16, hipMemcpyHostToDevice));
+    c->dip = c->hmem.get((size_t)3 * nk * n * n * 16);
+    if (!g_dry_run && dip) HIPCHK(hipMemcpy(c->dip, dip, (size_t)3 * nk * n * n * 16, hipMemcpyHostToDevice));
     c->eps_o = c->hmem.get((size_t)nk * nocc * 8);
     c->eps_v = c->hmem.get((size_t)nk * nvir * 8);
     if (!g_dry_run) {
@@ -1004,7 +1336,7 @@ lrcc_status lrcc_set_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int na
                             mx = std::max(mx, std::max(std::fabs(x[0]), std::fabs(x[1])));
                         }
         if (dev > 1e-10 * std::max(1.0, mx)) throw LrccError(LRCC_E_ARG, "chol violates the Hermitian pairing");
-        setup_hamiltonian(c, nk, nocc, nvir, naux, fock, chol);
+        setup_hamiltonian(c, nk, nocc, nvir, naux, fock, chol, dip);
         c->ham = true;
     });
 }
@@ -1037,8 +1369,11 @@ lrcc_status lrcc_set_amplitudes(lrcc_ctx *c, const double *t1, const double *t2)
                 }
         if (dev > 1e-10 * std::max(1.0, mx)) throw LrccError(LRCC_E_ARG, "t2 is not antisymmetric");
         c->amp = false;
-        precompute(c, t1, t2);
+        if (!c->s64.ready) build_state(c);
+        upload_amplitudes(c, t1, t2);
+        run_precompute(c, true);
         c->amp = true;
+        c->lam_valid = false;
     });
 }
 
@@ -1159,6 +1494,55 @@ lrcc_status lrcc_solve_response(lrcc_ctx *c, int nrhs, const double *omega, cons
     });
 }
 
+lrcc_status lrcc_solve(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega, const lrcc_solve_opts *opts,
+                       lrcc_solve_report *report) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nfreq < 1 || !omega || (axis_mask & ~7u)) throw LrccError(LRCC_E_ARG, "invalid frequencies or axis mask");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        if (o.precision != LRCC_FP64 && o.precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        lrcc_solve_report rep{};
+        c->nfreq = 0;
+        solve_alpha(c, axis_mask, nfreq, omega, o, rep);
+        if (report) *report = rep;
+    });
+}
+
+lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {
+    return guarded(c, [&] {
+        if (!alpha) throw LrccError(LRCC_E_ARG, "null output");
+        if (c->nfreq == 0 || nfreq != c->nfreq) throw LrccError(LRCC_E_STATE, "no polarizability for that many frequencies");
+        std::memcpy(alpha, c->alpha.data(), c->alpha.size() * 8);
+    });
+}
+
+lrcc_status lrcc_get_solution(lrcc_ctx *c, int axis, int ifreq, int sign, double *x1, double *x2) {
+    return guarded(c, [&] {
+        if (!x1 || !x2 || (sign != 1 && sign != -1)) throw LrccError(LRCC_E_ARG, "bad argument");
+        if (c->nfreq == 0 || ifreq < 0 || ifreq >= c->nfreq) throw LrccError(LRCC_E_STATE, "no solution stored");
+        int a = -1;
+        for (size_t q = 0; q < c->axes.size(); ++q) if (c->axes[q] == axis) a = (int)q;
+        if (a < 0) throw LrccError(LRCC_E_ARG, "axis was not solved");
+        const int nax = (int)c->axes.size();
+        const int r = (ifreq * 2 + (sign > 0 ? 0 : 1)) * nax + a;
+        const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
+        HIPCHK(hipMemcpy(x1, (char *)c->sol1 + (size_t)r * n1 * 16, n1 * 16, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(x2, (char *)c->sol2 + (size_t)r * n2 * 16, n2 * 16, hipMemcpyDeviceToHost));
+    });
+}
+
+lrcc_status lrcc_get_lambda(lrcc_ctx *c, double *l1, double *l2) {
+    return guarded(c, [&] {
+        if (!l1 || !l2) throw LrccError(LRCC_E_ARG, "null output");
+        if (!c->lam_valid) throw LrccError(LRCC_E_STATE, "lambda not solved yet (call lrcc_solve)");
+        const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
+        HIPCHK(hipMemcpy(l1, c->lam1, n1 * 16, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(l2, c->lam2, n2 * 16, hipMemcpyDeviceToHost));
+    });
+}
+
 lrcc_status lrcc_set_profiling(lrcc_ctx *c, int enable) {
     return guarded(c, [&] { c->prof.on = enable != 0; });
 }
@@ -1185,14 +1569,17 @@ lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char
     g_dry_run = true;
     try {
         lrcc_ctx c;
-        setup_hamiltonian(&c, nk, nocc, nvir, naux, nullptr, nullptr);
+        setup_hamiltonian(&c, nk, nocc, nvir, naux, nullptr, nullptr, nullptr);
         c.ham = true;
-        precompute(&c, nullptr, nullptr);
+        build_state(&c);
         c.amp = true;
         (void)sigma_program(&c, LRCC_FP64, nrhs);
         (void)sigma_program(&c, LRCC_FP32, nrhs);
         (void)sigma_program(&c, LRCC_FP64, nrhs, true);
         (void)sigma_program(&c, LRCC_FP32, nrhs, true);
+        (void)sigma_program(&c, LRCC_FP64, 1, true);
+        ensure_alpha_programs(&c);
+        for (int x = 0; x < 3; ++x) (void)sigma_program(&c, LRCC_FP64, 1, true, 1 + x);
     } catch (LrccError &e) {
         st = (lrcc_status)e.code;
         if (msg && msglen > 0) snprintf(msg, msglen, "%s", e.what());

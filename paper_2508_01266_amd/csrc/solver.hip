@@ -14,15 +14,18 @@ constexpr int DB = 256;
 }
 
 // part[r][b] = sum over the fixed chunk b of conj(u_r) * v_r
-__global__ void __launch_bounds__(DB) k_dot_partial(const double2 *u, const double2 *v, i64 n, int nblk, double2 *part) {
+__global__ void __launch_bounds__(DB) k_dot_partial(const double2 *u, const double2 *v, i64 n, int nblk, double2 *part,
+                                                     int conj_u) {
     __shared__ double sr[DB], si[DB];
     const int r = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
     const double2 *ur = u + (i64)r * n, *vr = v + (i64)r * n;
     double ar = 0, ai = 0;
     for (i64 i = (i64)b * DB + t; i < n; i += (i64)nblk * DB) {
-        const double2 x = ur[i], y = vr[i];
-        ar += x.x * y.x + x.y * y.y;
-        ai += x.x * y.y - x.y * y.x;
+        double2 x = ur[i];
+        const double2 y = vr[i];
+        if (conj_u) x.y = -x.y;
+        ar += x.x * y.x - x.y * y.y;
+        ai += x.x * y.y + x.y * y.x;
     }
     sr[t] = ar;
     si[t] = ai;
@@ -49,10 +52,11 @@ int dot_blocks(i64 n) {
     return (int)b;
 }
 
-hipError_t batched_dot(const void *u, const void *v, int R, i64 n, double scale, void *part, void *out, hipStream_t s) {
+hipError_t batched_dot(const void *u, const void *v, int R, i64 n, double scale, void *part, void *out, hipStream_t s,
+                       int conj_u) {
     const int nblk = dot_blocks(n);
     hipLaunchKernelGGL(k_dot_partial, dim3(nblk, R), dim3(DB), 0, s, (const double2 *)u, (const double2 *)v, n, nblk,
-                       (double2 *)part);
+                       (double2 *)part, conj_u);
     hipLaunchKernelGGL(k_dot_final, dim3((R + 63) / 64), dim3(64), 0, s, (const double2 *)part, nblk, R, scale,
                        (double2 *)out);
     return hipGetLastError();

@@ -4,8 +4,10 @@
 
 namespace lrcc {
 int dot_blocks(i64 n);
-// out[r] = scale * sum_i conj(u[r][i]) v[r][i]; part needs R*dot_blocks(n) complex doubles
-hipError_t batched_dot(const void *u, const void *v, int R, i64 n, double scale, void *part, void *out, hipStream_t s);
+// out[r] = scale * sum_i conj(u[r][i]) v[r][i] (conj_u = 1) or sum_i u[r][i] v[r][i] (conj_u = 0);
+// part needs R*dot_blocks(n) complex doubles
+hipError_t batched_dot(const void *u, const void *v, int R, i64 n, double scale, void *part, void *out, hipStream_t s,
+                       int conj_u = 1);
 hipError_t batched_axpby(void *y, const void *x, const void *alpha, double beta, int R, i64 n, hipStream_t s);
 hipError_t precond(void *o1, void *o2, const void *i1, const void *i2, const double *eo, const double *ev,
                    const double *omega, int nk, int R, int no, int nv, hipStream_t s);

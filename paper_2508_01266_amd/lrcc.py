@@ -54,6 +54,12 @@ def lib():
         L.lrcc_solve_response_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                               ctypes.POINTER(SolveReport), vp]
         L.lrcc_solve_response_dev.restype = ctypes.c_int
+        L.lrcc_solve.argtypes = [vp, ctypes.c_uint, i, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]
+        L.lrcc_get_alpha.argtypes = [vp, i, vp]
+        L.lrcc_get_solution.argtypes = [vp, i, i, i, vp, vp]
+        L.lrcc_get_lambda.argtypes = [vp, vp, vp]
+        for f in ("lrcc_solve", "lrcc_get_alpha", "lrcc_get_solution", "lrcc_get_lambda"):
+            getattr(L, f).restype = ctypes.c_int
         L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
         L.lrcc_plan_check.restype = ctypes.c_int
         L.lrcc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
@@ -178,6 +184,32 @@ class Context:
         self._check(self._L.lrcc_solve_response(self._h, R, _ptr(om), _ptr(a), _ptr(b), _ptr(y1), _ptr(y2),
                                                 ctypes.byref(oo), ctypes.byref(rep)))
         return y1, y2, rep.as_dict()
+
+    def solve(self, omegas, axis_mask=7, **opts):
+        """Polarizability alpha[nfreq][3][3] per cell (complex) at the frequencies `omegas`.
+        Returns (alpha, report dict)."""
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        oo = self.solve_options(**opts)
+        rep = SolveReport()
+        self._check(self._L.lrcc_solve(self._h, int(axis_mask), len(om), _ptr(om), ctypes.byref(oo),
+                                       ctypes.byref(rep)))
+        alpha = np.zeros((len(om), 3, 3), dtype=np.complex128)
+        self._check(self._L.lrcc_get_alpha(self._h, len(om), _ptr(alpha)))
+        return alpha, rep.as_dict()
+
+    def get_solution(self, axis, ifreq, sign):
+        nk, o, v = self.nk, self.no, self.nv
+        x1 = np.zeros((nk, o, v), dtype=np.complex128)
+        x2 = np.zeros((nk, nk, nk, o, o, v, v), dtype=np.complex128)
+        self._check(self._L.lrcc_get_solution(self._h, int(axis), int(ifreq), int(sign), _ptr(x1), _ptr(x2)))
+        return x1, x2
+
+    def get_lambda(self):
+        nk, o, v = self.nk, self.no, self.nv
+        l1 = np.zeros((nk, o, v), dtype=np.complex128)
+        l2 = np.zeros((nk, nk, nk, o, o, v, v), dtype=np.complex128)
+        self._check(self._L.lrcc_get_lambda(self._h, _ptr(l1), _ptr(l2)))
+        return l1, l2
 
     def set_profiling(self, on=True):
         self._check(self._L.lrcc_set_profiling(self._h, int(bool(on))))

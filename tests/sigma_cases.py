@@ -80,3 +80,24 @@ def oracle_solve(case, b1, b2, tol=1e-12):
         x1[r] = layout.block_t1(sol[0].numpy(), nk, o, v)
         x2[r] = nk * layout.block_t2(sol[1].numpy(), nk, o, v)
     return x1, x2
+
+
+def make_ccsd_case(nk, o, v, naux, seed, band_shift=True, chol_sigma=0.05):
+    """Synthetic chain with converged CCSD amplitudes (oracle) and its lambda."""
+    from oracle import solvers
+    rng = synth.rng_for(600 + seed, nk, o, v)
+    H = synth.hamiltonian(nk, o, v, naux, rng, band_shift=band_shift, chol_sigma=chol_sigma)
+    f = layout.dense_one_body(H['fock'], nk, o, v)
+    g = layout.dense_eri(H['chol'], nk, o, v)
+    h = ccsd.DenseHam.from_numpy(f, g, nk * o)
+    t1, t2, E, _ = solvers.solve_ccsd(h, tol=1e-12)
+    return dict(nk=nk, o=o, v=v, naux=naux, H=H, h=h, t=(t1, t2), E=E,
+                t1=layout.block_t1(t1.numpy(), nk, o, v), t2=nk * layout.block_t2(t2.numpy(), nk, o, v))
+
+
+def oracle_alpha(case, omegas):
+    nk, o, v = case['nk'], case['o'], case['v']
+    lam, rel, _ = response.solve_lambda(case['t'], case['h'])
+    ops = [torch.from_numpy(layout.dense_one_body(case['H']['dip'][x], nk, o, v)) for x in range(3)]
+    al, _ = response.polarizability(case['t'], lam, ops, list(omegas), case['h'], nk=nk)
+    return al, lam

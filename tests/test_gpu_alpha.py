@@ -1,0 +1,63 @@
+"""GPU polarizability against the oracle (FP64 path: 1e-9 a.u.; mixed path:
+1e-7 relative), plus the exact two-electron sum-over-states limit."""
+import numpy as np
+import pytest
+
+from tests.sigma_cases import make_ccsd_case, oracle_alpha
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(1, 2, 4, 6, 21), (2, 2, 3, 6, 22), (3, 1, 3, 5, 23), (1, 4, 12, 48, 24)]
+OMEGAS = [0.0, 0.0656]
+
+
+def _ctx(case):
+    import paper_2508_01266_amd as lr
+    c = lr.Context(0)
+    c.set_hamiltonian(case['o'], case['H']['fock'], case['H']['chol'], case['H']['dip'])
+    c.set_amplitudes(case['t1'], case['t2'])
+    return c
+
+
+@pytest.mark.parametrize("nk,o,v,naux,seed", CASES)
+def test_alpha_matches_oracle(nk, o, v, naux, seed):
+    import paper_2508_01266_amd as lr
+    case = make_ccsd_case(nk, o, v, naux, seed)
+    print(f"case nk={nk} o={o} v={v} naux={naux}: E_ccsd {case['E']}", flush=True)
+    ref, lam = oracle_alpha(case, OMEGAS)
+    c = _ctx(case)
+    a64, rep = c.solve(OMEGAS, tol=1e-11, precision=lr.FP64)
+    err64 = np.abs(a64 - ref).max()
+    print(f"fp64 alpha max abs err {err64:.2e} (|alpha| {np.abs(ref).max():.3f}); {rep}", flush=True)
+    assert err64 < 1e-9
+    a32, rep32 = c.solve(OMEGAS, tol=1e-11, precision=lr.FP32)
+    rel32 = np.abs(a32 - ref).max() / np.abs(ref).max()
+    print(f"mixed alpha max rel err {rel32:.2e}; {rep32}", flush=True)
+    assert rel32 < 1e-7
+    # lambda against the oracle (per-cell normalisation: l2_paper = l2_crystal / Nk)
+    from oracle import layout
+    l1, l2 = c.get_lambda()
+    r1 = layout.block_t1(lam[0].numpy(), nk, o, v)
+    r2 = layout.block_t2(lam[1].numpy(), nk, o, v) / nk
+    assert np.abs(l1 - r1).max() < 1e-9 * max(1, np.abs(r1).max())
+    assert np.abs(l2 - r2).max() < 1e-9 * max(1, np.abs(r2).max())
+
+
+def test_alpha_two_electron_sum_over_states():
+    """Two electrons: LR-CCSD is exact; the device alpha equals the FCI sum over states."""
+    import paper_2508_01266_amd as lr
+    from oracle import fockspace, layout
+    case = make_ccsd_case(1, 2, 5, 8, 31, chol_sigma=0.15)
+    nk, o, v = 1, 2, 5
+    c = _ctx(case)
+    a64, _ = c.solve(OMEGAS, tol=1e-12, precision=lr.FP64)
+    f = layout.dense_one_body(case['H']['fock'], nk, o, v)
+    g = layout.dense_eri(case['H']['chol'], nk, o, v)
+    ops = [layout.dense_one_body(case['H']['dip'][x], nk, o, v) for x in range(3)]
+    ref = np.zeros_like(a64)
+    for X in range(3):
+        for Y in range(3):
+            ref[:, X, Y] = fockspace.fci_polarizability(f, g, nk * o, ops[X], ops[Y], OMEGAS)[0] / nk
+    err = np.abs(a64 - ref).max()
+    print(f"device alpha vs FCI sum over states: {err:.2e}", flush=True)
+    assert err < 1e-9
