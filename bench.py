@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-alpha", action="store_true", help="skip the two converged-alpha solves")
+    ap.add_argument("--alpha-tol", type=float, default=1e-10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
@@ -168,6 +170,31 @@ def main():
         "speedup_mixed_vs_fp64_sigma": dt64 / dt32,
     }
     log(f"complex128 sigma {dt64*1e3:.1f} ms")
+    del X1, X2, Y1, Y2, OM
+    torch.cuda.empty_cache()
+    if not args.no_alpha:
+        res = {}
+        for name, prec in (("mixed", lr.FP32), ("fp64", lr.FP64)):
+            log(f"solving for alpha ({name})")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            al, rep = ctx.solve(list(w.omegas), axis_mask=7, tol=args.alpha_tol, precision=prec,
+                                reuse_lambda=0, krylov=6)
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0, al, rep)
+            log(f"alpha ({name}) in {res[name][0]:.1f} s: {rep}")
+        am, af = res["mixed"][1], res["fp64"][1]
+        out["alpha"] = {
+            "s_to_alpha_mixed": res["mixed"][0], "s_to_alpha_fp64": res["fp64"][0],
+            "speedup_mixed_vs_fp64": res["fp64"][0] / res["mixed"][0],
+            "tol": args.alpha_tol,
+            "mixed_vs_fp64_max_abs": float(np.abs(am - af).max()),
+            "mixed_vs_fp64_max_rel": float(np.abs(am - af).max() / np.abs(af).max()),
+            "alpha_xx_over_freqs_fp64": [float(x) for x in af[:, 0, 0].real],
+            "effective_sigma_tflops": {k: res[k][2]["rhs_sigmas"] * sigma_alg_flops(nk, o, v) / res[k][0] / 1e12
+                                       for k in res},
+            "reports": {k: res[k][2] for k in res},
+        }
     if not args.no_cpu:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(w, H, t1, t2, sample[0], sample[1], nrhs)

@@ -66,6 +66,7 @@ typedef struct {
     double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4)  */
     int max_outer;         /* maximum refinement steps (default 30)                                  */
     long long mem_cap_bytes; /* > 0: refuse (LRCC_E_OOM) if solver vectors would exceed this         */
+    int reuse_lambda;      /* lrcc_solve: 1 (default) reuses lambda of the same amplitudes, 0 re-solves */
 } lrcc_solve_opts;
 
 typedef struct {
@@ -75,6 +76,8 @@ typedef struct {
     int sigma_fp32;          /* complex64 sigma applications (batched launches)                      */
     double max_rel_residual; /* largest final relative residual over the RHS                         */
     double seconds;          /* wall time of the solve                                               */
+    long long rhs_sigmas;    /* full-Jacobian products counted per right-hand side (forward, adjoint,
+                                both precisions): work in units of one single-RHS sigma               */
 } lrcc_solve_report;
 
 /* Create a context on HIP device `hip_device`. *out is NULL on failure. */

@@ -181,23 +181,196 @@ __global__ void __launch_bounds__(NTL) ladder_kernel(LadderArgs p) {
             }
 }
 
+
+// Large-batch variant: 256 rows per workgroup (8 waves in a 4x2 grid, each a
+// 64x32 sub-tile), so every rebuilt W tile serves 4x more rows and the
+// rebuild costs naux/256 of the product instead of naux/64.  The four 16x16
+// blocks of the (a,e)x(b,f) rebuild are split over wave pairs by halves of the
+// Cholesky range and summed through LDS.
+namespace {
+constexpr int BTM = 256;
+constexpr int NTB = 512;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NTB) ladder_kernel_big(LadderArgs p) {
+    typedef typename Cx<T>::type C2;
+    typedef typename MfmaL<T>::v4 v4;
+    __shared__ T Wr[LTK][LTN], Wi[LTK][LTN];
+    __shared__ T Yr[LTK][BTM], Yi[LTK][BTM];
+    __shared__ T Pr[2][QC][TA * TE], Pi[2][QC][TA * TE];
+    __shared__ T Qr[2][QC][TB * TF], Qi[2][QC][TB * TF];
+    __shared__ T Gr[4][64][4], Gi[4][64][4];   // partial rebuild blocks of waves 4..7
+
+    const int nk = p.nk, o = p.o, v = p.v, naux = p.naux;
+    const int M = p.nrhs * o * o;
+    const int tilesM = (M + BTM - 1) / BTM;
+    const int tilesA = (v + TA - 1) / TA;
+    const int mt = blockIdx.x % tilesM;
+    const int rest = blockIdx.x / tilesM;
+    const int a0 = (rest % tilesA) * TA;
+    const int b0 = (rest / tilesA) * TB;
+    const int blk = blockIdx.y;
+    const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
+    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    const int m0 = mt * BTM;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 3) * 64, wn = (wave >> 2) * 32;
+    const i64 vv = (i64)v * v;
+    const i64 blk4 = (i64)M * vv;
+
+    const C2 *Y = reinterpret_cast<const C2 *>(p.Y);
+    const C2 *La = reinterpret_cast<const C2 *>(p.La);
+    const C2 *Lb = reinterpret_cast<const C2 *>(p.Lb);
+    C2 *Z = reinterpret_cast<C2 *>(p.Z);
+
+    v4 accr[4][2], acci[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+
+    // rebuild block of this wave (waves w and w+4 share block w&3, halves of the Q chunks)
+    const int gb = wave & 3, half = wave >> 2;
+    const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
+
+    for (int ke = 0; ke < nk; ++ke) {
+        const int kf = ((ki + kj - ke) % nk + nk) % nk;
+        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
+        const C2 *Lab = La + (i64)(ka * nk + ke) * naux * vv;
+        const C2 *Lbb = Lb + (i64)(kb * nk + kf) * naux * vv;
+        for (int e0 = 0; e0 < v; e0 += TE) {
+            for (int f0 = 0; f0 < v; f0 += TF) {
+                v4 gr = v4{0, 0, 0, 0}, gi = v4{0, 0, 0, 0};
+                for (int q0 = 0; q0 < naux; q0 += 2 * QC) {
+                    // two Cholesky chunks: chunk h covers [q0 + h*QC, q0 + (h+1)*QC)
+                    for (int idx = tid; idx < 2 * 2 * QC * 32; idx += NTB) {
+                        const int h = idx / (2 * QC * 32);
+                        const int rem0 = idx % (2 * QC * 32);
+                        const int which = rem0 / (QC * 32);
+                        const int rem = rem0 % (QC * 32);
+                        const int q = rem / 32, cc = rem % 32;
+                        const int x = cc / 4, y = cc % 4;
+                        const int qq = q0 + h * QC + q;
+                        C2 val; val.x = 0; val.y = 0;
+                        if (which == 0) {
+                            const int a = a0 + x, e = e0 + y;
+                            if (qq < naux && a < v && e < v) val = Lab[(i64)qq * vv + (i64)a * v + e];
+                            Pr[h][q][cc] = val.x; Pi[h][q][cc] = val.y;
+                        } else {
+                            const int b = b0 + x, f = f0 + y;
+                            if (qq < naux && b < v && f < v) val = Lbb[(i64)qq * vv + (i64)b * v + f];
+                            Qr[h][q][cc] = val.x; Qi[h][q][cc] = val.y;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int kk = 0; kk < QC; kk += 4) {
+                        const int kr = kk + (lane >> 4), c = lane & 15;
+                        const T xr = Pr[half][kr][rw + c], xi = Pi[half][kr][rw + c];
+                        const T yr = Qr[half][kr][cw + c], yi = Qi[half][kr][cw + c];
+                        gr = MfmaL<T>::mma(xr, yr, gr);
+                        gr = MfmaL<T>::mma(-xi, yi, gr);
+                        gi = MfmaL<T>::mma(xr, yi, gi);
+                        gi = MfmaL<T>::mma(xi, yr, gi);
+                    }
+                    __syncthreads();
+                }
+                if (half == 1) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) { Gr[gb][lane][r] = gr[r]; Gi[gb][lane][r] = gi[r]; }
+                }
+                __syncthreads();
+                if (half == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ae = rw + MfmaL<T>::row(lane, r);
+                        const int bf = cw + (lane & 15);
+                        const int a = ae / 4, e = ae % 4, b = bf / 4, f = bf % 4;
+                        Wr[e * TF + f][a * TB + b] = gr[r] + Gr[gb][lane][r];
+                        Wi[e * TF + f][a * TB + b] = gi[r] + Gi[gb][lane][r];
+                    }
+                }
+                for (int idx = tid; idx < BTM * LTK; idx += NTB) {
+                    const int kk = idx % LTK, m = idx / LTK;
+                    const int e = e0 + kk / TF, f = f0 + kk % TF;
+                    C2 val; val.x = 0; val.y = 0;
+                    if (m0 + m < M && e < v && f < v) val = Yb[(i64)(m0 + m) * vv + (i64)e * v + f];
+                    Yr[kk][m] = val.x; Yi[kk][m] = val.y;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < LTK; kk += 4) {
+                    const int kr = kk + (lane >> 4), c = lane & 15;
+                    T ar[4], ai[4], br[2], bi[2];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) { ar[i] = Yr[kr][wm + 16 * i + c]; ai[i] = Yi[kr][wm + 16 * i + c]; }
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) { br[j] = Wr[kr][wn + 16 * j + c]; bi[j] = Wi[kr][wn + 16 * j + c]; }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
+                            accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
+                            acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
+                            acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
+                        }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
+    const T al = (T)p.alpha;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + MfmaL<T>::row(lane, r);
+                const int c = wn + 16 * j + (lane & 15);
+                const int a = a0 + c / TB, b = b0 + c % TB;
+                if (m < M && a < v && b < v) {
+                    const i64 off = (i64)m * vv + (i64)a * v + b;
+                    C2 o2 = Zb[off];
+                    o2.x += al * accr[i][j][r];
+                    o2.y += al * acci[i][j][r];
+                    Zb[off] = o2;
+                }
+            }
+}
+
+static bool use_big(const LadderArgs &a) { return a.nrhs * a.o * a.o >= 192; }
+
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     const int M = a.nrhs * a.o * a.o;
-    const int tilesM = (M + LTM - 1) / LTM;
     const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
-    dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
-    hipLaunchKernelGGL(ladder_kernel<T>, grid, dim3(NTL), 0, s, a);
+    if (use_big(a)) {
+        const int tilesM = (M + BTM - 1) / BTM;
+        dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
+        hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
+    } else {
+        const int tilesM = (M + LTM - 1) / LTM;
+        dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
+        hipLaunchKernelGGL(ladder_kernel<T>, grid, dim3(NTL), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 double ladder_executed_flops(const LadderArgs &a) {
     const int M = a.nrhs * a.o * a.o;
-    const double tilesM = (M + LTM - 1) / LTM, tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
+    const int tm = use_big(a) ? BTM : LTM;
+    const double tilesM = (M + tm - 1) / tm, tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
     const double kt = (double)((a.v + TE - 1) / TE) * ((a.v + TF - 1) / TF) * a.nk;
     const double nb = (double)a.nk * a.nk * a.nk;
-    const double qpad = (double)((a.naux + QC - 1) / QC) * QC;
-    const double main = nb * tilesM * tA * tB * kt * 8.0 * LTM * LTN * LTK;
+    const int qc = use_big(a) ? 2 * QC : QC;
+    const double qpad = (double)((a.naux + qc - 1) / qc) * qc;
+    const double main = nb * tilesM * tA * tB * kt * 8.0 * tm * LTN * LTK;
     const double rebuild = nb * tilesM * tA * tB * kt * 8.0 * (TA * TE) * (TB * TF) * qpad;
     return main + rebuild;
 }

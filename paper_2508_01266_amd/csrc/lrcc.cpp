@@ -679,6 +679,7 @@ struct SolveCtx {
     const double *omega;  // device
     void *part = nullptr, *dout = nullptr, *alpha = nullptr;  // reduction / coefficient scratch
     int nsig64 = 0, nsig32 = 0;
+    long long rhs_sig = 0;
     bool adjoint = false;
     std::vector<cd> dot(const Vecs &u, const Vecs &v) {
         std::vector<cd> a(R), b(R);
@@ -721,6 +722,7 @@ struct SolveCtx {
         c->io_x1 = x.s; c->io_x2 = x.d; c->io_y1 = y.s; c->io_y2 = y.d; c->io_omega = omega;
         HIPCHK(p->run(st, &c->prof));
         (precision == LRCC_FP64 ? nsig64 : nsig32)++;
+        rhs_sig += R;
     }
 };
 
@@ -889,6 +891,7 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
     HIPCHK(hipStreamSynchronize(st));
     rep.sigma_fp64 = S.nsig64;
     rep.sigma_fp32 = S.nsig32;
+    rep.rhs_sigmas = S.rhs_sig;
     rep.max_rel_residual = rel.empty() ? 0.0 : *std::max_element(rel.begin(), rel.end());
     rep.converged = rep.max_rel_residual <= o.tol;
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -902,6 +905,7 @@ void default_opts(lrcc_solve_opts &o) {
     o.inner_tol = 1e-4;
     o.max_outer = 30;
     o.mem_cap_bytes = 0;
+    o.reuse_lambda = 1;
 }
 
 
@@ -1058,6 +1062,8 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     lrcc_solve_report r1{};
     Vecs lam{c->lam1, c->lam2};
     // lambda (once per set of amplitudes)
+    if (!o.reuse_lambda) c->lam_valid = false;
+    long long extra_rhs_sig = 0;
     if (!c->lam_valid) {
         HIPCHK(c->prog_grad->run(st));
         HIPCHK(hipMemset(c->lam1, 0, n1 * 16));
@@ -1149,6 +1155,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
                     run_precompute(c, false, st);
                     c->io_x1 = lam.s; c->io_x2 = lam.d; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
                     HIPCHK(adj->run(st));
+                    ++extra_rhs_sig;
                     std::vector<cd> w(1, cd(coef[k] / (12.0 * h), 0.0));
                     HIPCHK(hipMemcpy(D.alpha, w.data(), 16, hipMemcpyHostToDevice));
                     HIPCHK(batched_axpby(Fy.s, q.s, D.alpha, 1.0, 1, n1, st));
@@ -1184,6 +1191,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     rep.sigma_fp64 = r1.sigma_fp64 + r2.sigma_fp64;
     rep.sigma_fp32 = r1.sigma_fp32 + r2.sigma_fp32;
     rep.max_rel_residual = std::max(r1.max_rel_residual, r2.max_rel_residual);
+    rep.rhs_sigmas = r1.rhs_sigmas + r2.rhs_sigmas + extra_rhs_sig;
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

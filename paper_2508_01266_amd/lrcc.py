@@ -73,12 +73,13 @@ def lib():
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("krylov", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("mem_cap_bytes", ctypes.c_longlong)]
+                ("mem_cap_bytes", ctypes.c_longlong), ("reuse_lambda", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int), ("outer", ctypes.c_int), ("sigma_fp64", ctypes.c_int),
-                ("sigma_fp32", ctypes.c_int), ("max_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("sigma_fp32", ctypes.c_int), ("max_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("rhs_sigmas", ctypes.c_longlong)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -14,6 +14,8 @@ CASES = [
     (2, 3, 5, 7, 3, 3),
     (1, 4, 12, 48, 3, 4),      # molecular-limit workload sizes (c1)
     (3, 4, 20, 72, 2, 5),      # three-k chain workload sizes (c2)
+    (2, 3, 5, 7, 24, 6),       # >= 192 (rhs, i, j) rows: 256-row ladder tiles, ragged
+    (1, 4, 12, 48, 12, 7),     # c1 sizes with 12 right-hand sides (192 rows)
 ]
 
 
