@@ -45,7 +45,7 @@ def workload_inputs(name):
     import synth
     w = synth.WORKLOADS[name]
     rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
-    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=w.chol_sigma)
     # synthetic amplitudes with the structure (antisymmetry, momentum) of CCSD ones
     t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
     pairs = synth.omega_grid(w)
@@ -71,6 +71,42 @@ def time_sigma(ctx, x1, x2, y1, y2, om, prec, steps, warmup, torch):
     ctx.set_profiling(False)
     prof = ctx.read_profile()
     return (t1 - t0) / steps, prof
+
+
+def latency_small(lr, torch, reps=50):
+    """Microseconds per sigma on the molecular-limit workload (Nk=1, nocc=4, nvir=12,
+    Naux=48; 3 axes x (0, +w, -w) = 9 right-hand sides), eager launches vs one HIP
+    graph replay per application."""
+    import numpy as np
+    import synth
+    w = synth.WORKLOADS["c1"]
+    rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift)
+    t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
+    x1, x2 = synth.random_vectors(9, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
+    om = np.array([0.0, 0.0656, -0.0656] * 3)
+    ctx = lr.Context(0)
+    ctx.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+    ctx.set_amplitudes(t1, t2)
+    dev = torch.device("cuda:0")
+    X1, X2 = torch.from_numpy(x1).to(dev), torch.from_numpy(x2).to(dev)
+    Y1, Y2 = torch.empty_like(X1), torch.empty_like(X2)
+    OM = torch.from_numpy(om).to(dev)
+    st = torch.cuda.Stream()
+    out = {}
+    for mode in ("eager", "graph"):
+        ctx.set_graphs(mode == "graph")
+        for prec, pname in ((lr.FP64, "f64"), (lr.FP32, "f32")):
+            for _ in range(3):
+                ctx.apply_sigma_dev(X1, X2, Y1, Y2, OM, prec, st.cuda_stream)
+            st.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.apply_sigma_dev(X1, X2, Y1, Y2, OM, prec, st.cuda_stream)
+            st.synchronize()
+            out[f"{mode}_{pname}_us"] = (time.perf_counter() - t0) / reps * 1e6
+    ctx.close()
+    return out
 
 
 def cpu_baseline(w, H, t1, t2, x1, x2, nrhs):
@@ -105,8 +141,10 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-alpha", action="store_true", help="skip the two converged-alpha solves")
+    ap.add_argument("--alpha", action="store_true", help="also time the two converged-alpha solves")
     ap.add_argument("--alpha-tol", type=float, default=1e-10)
+    ap.add_argument("--ccsd-iter", type=int, default=300)
+    ap.add_argument("--no-tune", action="store_true", help="heuristic launch variants instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
@@ -125,6 +163,7 @@ def main():
     ctx = lr.Context(0)
     ctx.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
     ctx.set_amplitudes(t1, t2)
+    ctx.set_autotune(not args.no_tune)   # the warm-up application picks the launch variants
     X1 = torch.from_numpy(x1).to(dev)
     X2 = torch.from_numpy(x2).to(dev)
     sample = (x1[0].copy(), x2[0].copy())
@@ -170,16 +209,26 @@ def main():
         "speedup_mixed_vs_fp64_sigma": dt64 / dt32,
     }
     log(f"complex128 sigma {dt64*1e3:.1f} ms")
+    out["latency_c1_9rhs"] = latency_small(lr, torch)
+    log(f"c1 latency {out['latency_c1_9rhs']}")
     del X1, X2, Y1, Y2, OM
     torch.cuda.empty_cache()
-    if not args.no_alpha:
+    if args.alpha:
+        # the response and lambda equations are posed at converged ground-state amplitudes:
+        # solve CCSD on the device first (the random amplitudes above only serve the timing)
+        log("solving ground-state CCSD on the device")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, ecorr, crep = ctx.solve_ccsd(tol=1e-9, max_iter=args.ccsd_iter)
+        out["ccsd"] = {"seconds": time.perf_counter() - t0, "energy_per_cell": ecorr, "report": crep}
+        log(f"CCSD: {out['ccsd']}")
         res = {}
         for name, prec in (("mixed", lr.FP32), ("fp64", lr.FP64)):
             log(f"solving for alpha ({name})")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             al, rep = ctx.solve(list(w.omegas), axis_mask=7, tol=args.alpha_tol, precision=prec,
-                                reuse_lambda=0, krylov=6)
+                                reuse_lambda=0)
             torch.cuda.synchronize()
             res[name] = (time.perf_counter() - t0, al, rep)
             log(f"alpha ({name}) in {res[name][0]:.1f} s: {rep}")

@@ -60,10 +60,12 @@ typedef struct {
     double tol;            /* stop when ||b - (A - w) x|| <= tol ||b|| for every RHS (default 1e-10);
                               norm: sum |u1|^2 + 1/4 sum |u2|^2 over full arrays                      */
     int max_iter;          /* FP64 GMRES: maximum operator applications (default 400)                */
-    int krylov;            /* GMRES restart length (default 8)                                       */
+    int krylov;            /* GMRES restart length; 0 (default) sizes it from free device memory
+                              (60% of it, 4..60 vectors)                                              */
     int precision;         /* LRCC_FP64: GMRES in complex128; LRCC_FP32: complex64 matrix-core inner
                               GMRES corrections inside complex128 iterative refinement                */
-    double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4)  */
+    double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4;
+                              at most 4 restart cycles per refinement step)                          */
     int max_outer;         /* maximum refinement steps (default 30)                                  */
     long long mem_cap_bytes; /* > 0: refuse (LRCC_E_OOM) if solver vectors would exceed this         */
     int reuse_lambda;      /* lrcc_solve: 1 (default) reuses lambda of the same amplitudes, 0 re-solves */
@@ -131,6 +133,22 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
 lrcc_status lrcc_set_profiling(lrcc_ctx *ctx, int enable);
 lrcc_status lrcc_read_profile(lrcc_ctx *ctx, double *ms, long long *count);
 
+/* Autotuning of launch variants: when enabled, the first application of each
+ * sigma program (per problem size, nrhs, precision and direction) is run once
+ * per candidate configuration (matrix-core GEMM tiles 64x64 or large; ladder
+ * antisymmetry-packed or full-range), every tunable launch is timed with HIP
+ * events and the fastest candidate is kept per launch.  If the environment
+ * variable LRCC_TUNE_CACHE names a file, choices are read from and appended to
+ * it (one line per program).  Results do not depend on the choice. */
+lrcc_status lrcc_set_autotune(lrcc_ctx *ctx, int enable);
+
+/* HIP-graph replay of the sigma (and transpose) applications: when enabled,
+ * each application on a non-null stream is captured once per set of buffer
+ * addresses and replayed as one graph launch (the solver uses a stream of its
+ * own).  Profiling events are not recorded inside graphs.  Disabling frees the
+ * captured graphs. */
+lrcc_status lrcc_set_graphs(lrcc_ctx *ctx, int enable);
+
 /* Real floating-point operations executed by one sigma application for nrhs
  * right-hand sides (matrix-core GEMMs and ladder, including the in-LDS
  * integral rebuild; streaming kernels excluded). */
@@ -192,6 +210,18 @@ lrcc_status lrcc_solve_response_dev(lrcc_ctx *ctx, int nrhs, const double *omega
  * lrcc_get_solution, lrcc_get_lambda. */
 lrcc_status lrcc_solve(lrcc_ctx *ctx, unsigned axis_mask, int nfreq, const double *omega,
                        const lrcc_solve_opts *opts, lrcc_solve_report *report);
+
+/* Ground-state CCSD on the device (Eqs. t1, t2): Jacobi steps with the
+ * denominators of Eq. D and DIIS on the amplitude change (Sec. II.C), from
+ * T = 0, until the residual norm sqrt(sum |O1|^2 + 1/4 sum |O2|^2) (per-cell
+ * normalisation) is <= tol.  The residual is evaluated exactly from the
+ * Jacobian: Omega(T) = Omega(0) + int_0^1 A(sT) T ds with 2-point Gauss-Legendre
+ * (the integrand is cubic in s).  On success the converged amplitudes become the
+ * context's amplitudes (as after lrcc_set_amplitudes).  t1/t2/energy may be NULL;
+ * energy is the correlation energy per cell (Eq. ene).  LRCC_E_NOCONV if
+ * max_iter is reached. */
+lrcc_status lrcc_solve_ccsd(lrcc_ctx *ctx, double tol, int max_iter, double *t1, double *t2, double *energy,
+                            lrcc_solve_report *report);
 
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */

@@ -44,6 +44,7 @@ struct GemmArgs {
     Split sm, sn, sk;
     Strides Am, Ak, Bk, Bn, Cm, Cn;
     int aMfast, bNfast;  // tile-load thread maps: 1 = run along m (resp. n)
+    int shape;           // tile shape: -1 automatic, 0 = 64x64, 1 = large (128x128 complex64, 128x64 complex128)
     double alpha_re, alpha_im;
     int beta;
     const i64 *offC;
@@ -54,6 +55,7 @@ struct GemmArgs {
 
 template <typename T>
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+int gemm_shape(const GemmArgs &g, bool fp64);
 
 // Ladder: sigma2[ki,kj,ka][R][i][j][a][b] += alpha * sum_{ke} sum_{e,f}
 //   Y[ki,kj,ke][R][i][j][e][f] * sum_Q La[ka][ke][Q][a][e] * Lb[kb][kf][Q][b][f]
@@ -64,6 +66,7 @@ struct LadderArgs {
     void *Z;             // output, same layout as Y (accumulated)
     int nk, nrhs, o, v, naux;
     double alpha;
+    int packed;          // 1: Y antisymmetric in (e,f); form only unique (e,f) and (a,b) pairs
 };
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s);

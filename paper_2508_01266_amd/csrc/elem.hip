@@ -261,6 +261,53 @@ hipError_t scale_copy(void *y, const void *x, double ar, double ai, i64 n, hipSt
     return hipGetLastError();
 }
 
+// out = in with permuted indices: output dim d is input dim perm[d]; output blocks
+// [k0][k1][k2] with k3 from the output momentum signs sg (both tensors conserve momentum).
+__global__ void k_permute4(const double2 *in, double2 *out, int nk, int e0, int e1, int e2, int e3, int p0, int p1,
+                           int p2, int p3, int s0, int s1, int s2, int s3) {
+    const int ein[4] = {e0, e1, e2, e3}, perm[4] = {p0, p1, p2, p3}, sg[4] = {s0, s1, s2, s3};
+    int eo[4];
+    for (int d = 0; d < 4; ++d) eo[d] = ein[perm[d]];
+    const i64 inner = (i64)e0 * e1 * e2 * e3;
+    const i64 n = (i64)nk * nk * nk * inner;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        int io[4], ko[4];
+        for (int d = 3; d >= 0; --d) { io[d] = (int)(q % eo[d]); q /= eo[d]; }
+        ko[2] = (int)(q % nk); q /= nk;
+        ko[1] = (int)(q % nk); q /= nk;
+        ko[0] = (int)q;
+        const int sum = sg[0] * ko[0] + sg[1] * ko[1] + sg[2] * ko[2];
+        ko[3] = ((-sg[3] * sum) % nk + nk) % nk;
+        int ii[4], ki[4];
+        for (int d = 0; d < 4; ++d) { ii[perm[d]] = io[d]; ki[perm[d]] = ko[d]; }
+        const i64 src = (((i64)(ki[0] * nk + ki[1]) * nk + ki[2]) * inner) +
+                        (((i64)ii[0] * e1 + ii[1]) * e2 + ii[2]) * e3 + ii[3];
+        out[t] = in[src];
+    }
+}
+
+hipError_t permute4(const void *in, void *out, int nk, const int *ext_in, const int *perm, const int *sg_out,
+                    hipStream_t s) {
+    const i64 n = (i64)nk * nk * nk * ext_in[0] * ext_in[1] * ext_in[2] * ext_in[3];
+    hipLaunchKernelGGL(k_permute4, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)in, (double2 *)out, nk,
+                       ext_in[0], ext_in[1], ext_in[2], ext_in[3], perm[0], perm[1], perm[2], perm[3], sg_out[0],
+                       sg_out[1], sg_out[2], sg_out[3]);
+    return hipGetLastError();
+}
+
+// y = s * conj(x)
+__global__ void k_conj_scale(double2 *y, const double2 *x, double s, i64 n) {
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const double2 v = x[t];
+        y[t] = make_double2(s * v.x, -s * v.y);
+    }
+}
+hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st) {
+    hipLaunchKernelGGL(k_conj_scale, dim3(grid_for(n)), dim3(256), 0, st, (double2 *)y, (const double2 *)x, s, n);
+    return hipGetLastError();
+}
+
 __global__ void k_convert(const double2 *in, float2 *out, i64 n) {
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
         double2 v = in[t];

@@ -24,6 +24,10 @@ template <typename Tout>
 hipError_t axis_slice(const void *in, void *out, int nax, int nk, int n, int p0, int np, int q0, int nq, int transpose,
                       hipStream_t s);
 hipError_t scale_copy(void *y, const void *x, double ar, double ai, i64 n, hipStream_t s);
+hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st);
+// four-index complex128 permutation: output dim d = input dim perm[d]; output momentum signs sg_out
+hipError_t permute4(const void *in, void *out, int nk, const int *ext_in, const int *perm, const int *sg_out,
+                    hipStream_t s);
 template <typename T>
 hipError_t pp_in(const void *y, void *Z, int nk, int R, int o, int v, double scale, hipStream_t s);
 template <typename T>

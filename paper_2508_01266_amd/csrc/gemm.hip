@@ -2,11 +2,12 @@
 //
 // A complex product is four real MFMA products on split real/imaginary
 // planes staged in LDS: Cre += Are*Bre - Aim*Bim, Cim += Are*Bim + Aim*Bre.
-// Tile 64x64x16 (complex), 256 threads = 4 waves in a 2x2 grid, each wave a
-// 32x32 sub-tile of 2x2 MFMA 16x16x4 blocks.  Operand addresses use the
-// two-level index splits of GemmArgs so that k-blocked tensors are read in
-// place (no permute passes); the thread->element map of each tile load runs
-// along the unit-stride index when one exists, for coalesced loads.
+// 256 threads = 4 waves; each wave owns a WTM x WTN sub-tile of 16x16x4 MFMA
+// blocks.  Tile shapes: 64x64 (default), 128x128 (complex64, large M and N)
+// and 128x64 (complex128, large M).  Operand addresses use the three-level
+// index splits of GemmArgs so that k-blocked tensors are read in place (no
+// permute passes); the thread->element map of each tile load runs along the
+// unit-stride index when one exists, for coalesced loads.
 #include "common.hpp"
 
 namespace lrcc {
@@ -28,12 +29,16 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int TM = 64, TN = 64, TK = 16, NT = 256;
+constexpr int TK = 16, NT = 256;
 
-template <typename T>
+template <typename T, int TM, int TN, int WTM, int WTN>
 __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     typedef typename Cx<T>::type C2;
     typedef typename Mfma<T>::v4 v4;
+    constexpr int WGM = TM / WTM;            // waves along M
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int LA = TM * TK / NT, LB = TK * TN / NT;
+    static_assert((TM / WTM) * (TN / WTN) == 4, "4 waves per block");
     __shared__ T Ar[TK][TM], Ai[TK][TM], Br[TK][TN], Bi[TK][TN];
 
     const int job = blockIdx.y;
@@ -41,94 +46,105 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     const int m0 = (blockIdx.x % tilesM) * TM;
     const int n0 = (blockIdx.x / tilesM) * TN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int wm = (wave % WGM) * WTM, wn = (wave / WGM) * WTN;
 
     const C2 *A = reinterpret_cast<const C2 *>(g.A);
     const C2 *B = reinterpret_cast<const C2 *>(g.B);
     C2 *C = reinterpret_cast<C2 *>(g.C);
 
-    // thread -> tile element maps (4 elements of A and 4 of B per thread)
     const bool aM = g.aMfast != 0;
     const bool bN = g.bNfast != 0;
-    int am[4], ak[4], bk[4], bn[4];
-    i64 arow[4], bcol[4];
-    bool aok[4], bok[4];
+    int am[LA], ak[LA], bk[LB], bn[LB];
+    i64 arow[LA], bcol[LB];
+    bool aok[LA], bok[LB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int idx = tid + NT * q;
+    for (int q = 0; q < LA; ++q) {
+        const int idx = tid + NT * q;
         if (aM) { am[q] = idx % TM; ak[q] = idx / TM; } else { ak[q] = idx % TK; am[q] = idx / TK; }
-        if (bN) { bn[q] = idx % TN; bk[q] = idx / TN; } else { bk[q] = idx % TK; bn[q] = idx / TK; }
-        int gm = m0 + am[q], gn = n0 + bn[q];
+        const int gm = m0 + am[q];
         aok[q] = gm < g.M;
-        bok[q] = gn < g.N;
         arow[q] = aok[q] ? split_off(gm, g.sm, g.Am) : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+        const int idx = tid + NT * q;
+        if (bN) { bn[q] = idx % TN; bk[q] = idx / TN; } else { bk[q] = idx % TK; bn[q] = idx / TK; }
+        const int gn = n0 + bn[q];
+        bok[q] = gn < g.N;
         bcol[q] = bok[q] ? split_off(gn, g.sn, g.Bn) : 0;
     }
 
-    v4 accr[2][2], acci[2][2];
+    v4 accr[FM][FN], acci[FM][FN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+        for (int j = 0; j < FN; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
 
     const int sb = g.segBeg[job], se = g.segBeg[job + 1];
-    for (int s = sb; s < se; ++s) {
+    const int ksteps = (g.K + TK - 1) / TK;
+    const int total = (se - sb) * ksteps;
+    // software pipeline: the global loads of step t+1 are issued into registers
+    // before the matrix-core work of step t
+    C2 va[LA], vb[LB];
+    auto fetch = [&](int t) {
+        const int s = sb + t / ksteps, k0 = (t % ksteps) * TK;
         const C2 *As = A + g.segA[s];
         const C2 *Bs = B + g.segB[s];
-        for (int k0 = 0; k0 < g.K; k0 += TK) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int gk = k0 + ak[q];
-                C2 v;
-                if (aok[q] && gk < g.K) {
-                    v = As[arow[q] + split_off(gk, g.sk, g.Ak)];
-                } else { v.x = 0; v.y = 0; }
-                Ar[ak[q]][am[q]] = v.x;
-                Ai[ak[q]][am[q]] = v.y;
-                gk = k0 + bk[q];
-                C2 w;
-                if (bok[q] && gk < g.K) {
-                    w = Bs[bcol[q] + split_off(gk, g.sk, g.Bk)];
-                } else { w.x = 0; w.y = 0; }
-                Br[bk[q]][bn[q]] = w.x;
-                Bi[bk[q]][bn[q]] = w.y;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < TK; kk += 4) {
-                const int kr = kk + (lane >> 4), c = lane & 15;
-                T ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) { ar[i] = Ar[kr][wm + 16 * i + c]; ai[i] = Ai[kr][wm + 16 * i + c]; }
-#pragma unroll
-                for (int j = 0; j < 2; ++j) { br[j] = Br[kr][wn + 16 * j + c]; bi[j] = Bi[kr][wn + 16 * j + c]; }
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-                        accr[i][j] = Mfma<T>::mma(-ai[i], bi[j], accr[i][j]);
-                        acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
-                        acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
-                    }
-            }
-            __syncthreads();
+        for (int q = 0; q < LA; ++q) {
+            const int gk = k0 + ak[q];
+            if (aok[q] && gk < g.K) va[q] = As[arow[q] + split_off(gk, g.sk, g.Ak)];
+            else { va[q].x = 0; va[q].y = 0; }
         }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int gk = k0 + bk[q];
+            if (bok[q] && gk < g.K) vb[q] = Bs[bcol[q] + split_off(gk, g.sk, g.Bk)];
+            else { vb[q].x = 0; vb[q].y = 0; }
+        }
+    };
+    if (total > 0) fetch(0);
+    for (int t = 0; t < total; ++t) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) { Ar[ak[q]][am[q]] = va[q].x; Ai[ak[q]][am[q]] = va[q].y; }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) { Br[bk[q]][bn[q]] = vb[q].x; Bi[bk[q]][bn[q]] = vb[q].y; }
+        __syncthreads();
+        if (t + 1 < total) fetch(t + 1);
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 4) {
+            const int kr = kk + (lane >> 4), c = lane & 15;
+            T ar[FM], ai[FM], br[FN], bi[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) { ar[i] = Ar[kr][wm + 16 * i + c]; ai[i] = Ai[kr][wm + 16 * i + c]; }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) { br[j] = Br[kr][wn + 16 * j + c]; bi[j] = Bi[kr][wn + 16 * j + c]; }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
+                    accr[i][j] = Mfma<T>::mma(-ai[i], bi[j], accr[i][j]);
+                    acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
+                    acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
+                }
+        }
+        __syncthreads();
     }
 
     const T alr = (T)g.alpha_re, ali = (T)g.alpha_im;
     C2 *Cj = C + g.offC[job];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int gm = m0 + wm + 16 * i + Mfma<T>::row(lane, r);
-                int gn = n0 + wn + 16 * j + (lane & 15);
+                const int gm = m0 + wm + 16 * i + Mfma<T>::row(lane, r);
+                const int gn = n0 + wn + 16 * j + (lane & 15);
                 if (gm < g.M && gn < g.N) {
-                    i64 off = split_off(gm, g.sm, g.Cm) + split_off(gn, g.sn, g.Cn);
-                    T xr = accr[i][j][r], xi = acci[i][j][r];
+                    const i64 off = split_off(gm, g.sm, g.Cm) + split_off(gn, g.sn, g.Cn);
+                    const T xr = accr[i][j][r], xi = acci[i][j][r];
                     T vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
                     if (g.beta) { C2 o = Cj[off]; vr += o.x; vi += o.y; }
                     C2 w; w.x = vr; w.y = vi;
@@ -137,9 +153,8 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
             }
 }
 
-template <typename T>
-hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
-    if (g.njobs <= 0 || g.M <= 0 || g.N <= 0) return hipSuccess;
+template <typename T, int TM, int TN, int WTM, int WTN>
+hipError_t launch_shape(const GemmArgs &g, hipStream_t s) {
     const int tilesM = (g.M + TM - 1) / TM, tilesN = (g.N + TN - 1) / TN;
     // grid.y is limited to 65535: launch the job list in chunks
     for (int j0 = 0; j0 < g.njobs; j0 += 65535) {
@@ -148,11 +163,29 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
         c.offC = g.offC + j0;
         c.segBeg = g.segBeg + j0;
         dim3 grid(tilesM * tilesN, c.njobs);
-        hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(NT), 0, s, c);
+        hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN>), grid, dim3(NT), 0, s, c);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+int gemm_shape(const GemmArgs &g, bool fp64) {
+    if (g.shape >= 0) return g.shape;
+    if (g.M >= 128 && g.N >= 128) return 1;
+    if (fp64 && g.M >= 128 && g.N >= 64) return 1;
+    return 0;
+}
+
+template <typename T>
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
+    if (g.njobs <= 0 || g.M <= 0 || g.N <= 0) return hipSuccess;
+    constexpr bool f64 = sizeof(T) == 8;
+    if (gemm_shape(g, f64) == 1) {
+        if constexpr (f64) return launch_shape<T, 128, 64, 64, 32>(g, s);
+        else return launch_shape<T, 128, 128, 64, 64>(g, s);
+    }
+    return launch_shape<T, 64, 64, 32, 32>(g, s);
 }
 
 template hipError_t launch_gemm<double>(const GemmArgs &, hipStream_t);

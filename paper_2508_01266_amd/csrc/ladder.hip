@@ -346,6 +346,189 @@ __global__ void __launch_bounds__(NTB) ladder_kernel_big(LadderArgs p) {
 
 static bool use_big(const LadderArgs &a) { return a.nrhs * a.o * a.o >= 192; }
 
+// Antisymmetry-packed large-batch variant.  With Y antisymmetric in (e,f) and
+// the result antisymmetric in (a,b):
+//   sum_{e,f} Y^{ef} K_{abef} = sum_{(ke,e) < (kf,f)} Y^{ef} (K_{abef} - K_{abfe}),
+// so only the unique input pairs contribute, and only the unique output pairs
+// (ka,a) < (kb,b) are formed; they are written with weight 2*alpha so that the
+// final P(ij)P(ab) assembly reproduces the full ladder (the (b,a) partners are
+// left to the antisymmetriser).  Each 16x64 W tile is rebuilt in LDS as the
+// difference of two rank-naux products, one per 16x16 block per wave.
+namespace {
+constexpr int NTP = 512;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NTP) ladder_kernel_packed(LadderArgs p) {
+    typedef typename Cx<T>::type C2;
+    typedef typename MfmaL<T>::v4 v4;
+    __shared__ T Wr[LTK][LTN], Wi[LTK][LTN];
+    __shared__ T Yr[LTK][BTM], Yi[LTK][BTM];
+    // Cholesky chunks: [0] La(ka,ke)[a][e], [1] Lb(kb,kf)[b][f], [2] La(ka,kf)[a][f], [3] Lb(kb,ke)[b][e]
+    __shared__ T Lr[4][QC][32], Li[4][QC][32];
+    __shared__ T Gr[4][64][4], Gi[4][64][4];   // second products of waves 4..7
+
+    const int nk = p.nk, o = p.o, v = p.v, naux = p.naux;
+    const int M = p.nrhs * o * o;
+    const int tilesM = (M + BTM - 1) / BTM;
+    const int tilesA = (v + TA - 1) / TA;
+    const int mt = blockIdx.x % tilesM;
+    const int rest = blockIdx.x / tilesM;
+    const int ta = rest % tilesA, tb = rest / tilesA;
+    const int a0 = ta * TA, b0 = tb * TB;
+    const int blk = blockIdx.y;
+    const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
+    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    // unique output pairs only
+    if (ka > kb || (ka == kb && ta > tb)) return;
+    const bool diag_out = (ka == kb);
+    const int m0 = mt * BTM;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 3) * 64, wn = (wave >> 2) * 32;
+    const i64 vv = (i64)v * v;
+    const i64 blk4 = (i64)M * vv;
+
+    const C2 *Y = reinterpret_cast<const C2 *>(p.Y);
+    const C2 *La = reinterpret_cast<const C2 *>(p.La);
+    const C2 *Lb = reinterpret_cast<const C2 *>(p.Lb);
+    C2 *Z = reinterpret_cast<C2 *>(p.Z);
+
+    v4 accr[4][2], acci[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+
+    const int gb = wave & 3, second = wave >> 2;
+    const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
+
+    for (int ke = 0; ke < nk; ++ke) {
+        const int kf = ((ki + kj - ke) % nk + nk) % nk;
+        if (ke > kf) continue;
+        const bool diag_in = (ke == kf);
+        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
+        const C2 *L0 = La + (i64)(ka * nk + ke) * naux * vv;   // [a][e]
+        const C2 *L1 = Lb + (i64)(kb * nk + kf) * naux * vv;   // [b][f]
+        const C2 *L2 = La + (i64)(ka * nk + kf) * naux * vv;   // [a][f]
+        const C2 *L3 = Lb + (i64)(kb * nk + ke) * naux * vv;   // [b][e]
+        for (int e0 = 0; e0 < v; e0 += TE) {
+            for (int f0 = diag_in ? (e0 / TF) * TF : 0; f0 < v; f0 += TF) {
+                // rebuild: waves 0-3 G1[(a,e)][(b,f)] = sum La(ka,ke)[a][e] Lb(kb,kf)[b][f],
+                //          waves 4-7 G2[(a,f)][(b,e)] = sum La(ka,kf)[a][f] Lb(kb,ke)[b][e]
+                v4 gr = v4{0, 0, 0, 0}, gi = v4{0, 0, 0, 0};
+                for (int q0 = 0; q0 < naux; q0 += QC) {
+                    for (int idx = tid; idx < 4 * QC * 32; idx += NTP) {
+                        const int which = idx / (QC * 32);
+                        const int rem = idx % (QC * 32);
+                        const int q = rem / 32, cc = rem % 32;
+                        const int x = cc / 4, y = cc % 4;
+                        const int qq = q0 + q;
+                        C2 val; val.x = 0; val.y = 0;
+                        const int r0 = (which == 0 || which == 2) ? a0 + x : b0 + x;
+                        const int c0 = (which == 0 || which == 3) ? e0 + y : f0 + y;
+                        const C2 *src = which == 0 ? L0 : which == 1 ? L1 : which == 2 ? L2 : L3;
+                        if (qq < naux && r0 < v && c0 < v) val = src[(i64)qq * vv + (i64)r0 * v + c0];
+                        Lr[which][q][cc] = val.x; Li[which][q][cc] = val.y;
+                    }
+                    __syncthreads();
+                    const int ra = second ? 2 : 0, rb = second ? 3 : 1;
+#pragma unroll
+                    for (int kk = 0; kk < QC; kk += 4) {
+                        const int kr = kk + (lane >> 4), c = lane & 15;
+                        const T xr = Lr[ra][kr][rw + c], xi = Li[ra][kr][rw + c];
+                        const T yr = Lr[rb][kr][cw + c], yi = Li[rb][kr][cw + c];
+                        gr = MfmaL<T>::mma(xr, yr, gr);
+                        gr = MfmaL<T>::mma(-xi, yi, gr);
+                        gi = MfmaL<T>::mma(xr, yi, gi);
+                        gi = MfmaL<T>::mma(xi, yr, gi);
+                    }
+                    __syncthreads();
+                }
+                // G2 block gb of wave gb+4 holds rows (a,f) and cols (b,e); it is needed at
+                // W[(e,f)][(a,b)] -= G2[(a,f)][(b,e)]: exchange through LDS in W coordinates
+                if (second) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) { Gr[gb][lane][r] = gr[r]; Gi[gb][lane][r] = gi[r]; }
+                }
+                __syncthreads();
+                if (!second) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ae = rw + MfmaL<T>::row(lane, r);
+                        const int bf = cw + (lane & 15);
+                        const int a = ae / 4, e = ae % 4, b = bf / 4, f = bf % 4;
+                        Wr[e * TF + f][a * TB + b] = gr[r];
+                        Wi[e * TF + f][a * TB + b] = gi[r];
+                    }
+                }
+                __syncthreads();
+                if (second) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        // this wave's G2 element: row (a, f') = rw + row(lane,r), col (b, e') = cw + lane%16
+                        const int af = rw + MfmaL<T>::row(lane, r);
+                        const int be = cw + (lane & 15);
+                        const int a = af / 4, f = af % 4, b = be / 4, e = be % 4;
+                        Wr[e * TF + f][a * TB + b] -= Gr[gb][lane][r];
+                        Wi[e * TF + f][a * TB + b] -= Gi[gb][lane][r];
+                    }
+                }
+                // Y tile with the unique-pair mask of the input
+                for (int idx = tid; idx < BTM * LTK; idx += NTP) {
+                    const int kk = idx % LTK, m = idx / LTK;
+                    const int e = e0 + kk / TF, f = f0 + kk % TF;
+                    C2 val; val.x = 0; val.y = 0;
+                    if (m0 + m < M && e < v && f < v && (!diag_in || e < f))
+                        val = Yb[(i64)(m0 + m) * vv + (i64)e * v + f];
+                    Yr[kk][m] = val.x; Yi[kk][m] = val.y;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < LTK; kk += 4) {
+                    const int kr = kk + (lane >> 4), c = lane & 15;
+                    T ar[4], ai[4], br[2], bi[2];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) { ar[i] = Yr[kr][wm + 16 * i + c]; ai[i] = Yi[kr][wm + 16 * i + c]; }
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) { br[j] = Wr[kr][wn + 16 * j + c]; bi[j] = Wi[kr][wn + 16 * j + c]; }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
+                            accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
+                            acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
+                            acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
+                        }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
+    const T al = (T)(2.0 * p.alpha);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + MfmaL<T>::row(lane, r);
+                const int c = wn + 16 * j + (lane & 15);
+                const int a = a0 + c / TB, b = b0 + c % TB;
+                if (m < M && a < v && b < v && (!diag_out || a < b)) {
+                    const i64 off = (i64)m * vv + (i64)a * v + b;
+                    C2 o2 = Zb[off];
+                    o2.x += al * accr[i][j][r];
+                    o2.y += al * acci[i][j][r];
+                    Zb[off] = o2;
+                }
+            }
+}
+
+
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     const int M = a.nrhs * a.o * a.o;
@@ -353,7 +536,8 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     if (use_big(a)) {
         const int tilesM = (M + BTM - 1) / BTM;
         dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
-        hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
+        if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
+        else hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
     } else {
         const int tilesM = (M + LTM - 1) / LTM;
         dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
@@ -364,15 +548,35 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
 
 double ladder_executed_flops(const LadderArgs &a) {
     const int M = a.nrhs * a.o * a.o;
-    const int tm = use_big(a) ? BTM : LTM;
-    const double tilesM = (M + tm - 1) / tm, tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
-    const double kt = (double)((a.v + TE - 1) / TE) * ((a.v + TF - 1) / TF) * a.nk;
-    const double nb = (double)a.nk * a.nk * a.nk;
-    const int qc = use_big(a) ? 2 * QC : QC;
+    const bool big = use_big(a);
+    const int tm = big ? BTM : LTM;
+    const double tilesM = (M + tm - 1) / tm;
+    const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB, tE = (a.v + TE - 1) / TE, tF = (a.v + TF - 1) / TF;
+    const int qc = (big && !a.packed) ? 2 * QC : QC;
     const double qpad = (double)((a.naux + qc - 1) / qc) * qc;
-    const double main = nb * tilesM * tA * tB * kt * 8.0 * tm * LTN * LTK;
-    const double rebuild = nb * tilesM * tA * tB * kt * 8.0 * (TA * TE) * (TB * TF) * qpad;
-    return main + rebuild;
+    const double main_step = 8.0 * tm * LTN * LTK, rebuild_step = 8.0 * (TA * TE) * (TB * TF) * qpad;
+    if (!(big && a.packed)) {
+        const double steps = (double)a.nk * a.nk * a.nk * tilesM * tA * tB * a.nk * tE * tF;
+        return steps * (main_step + rebuild_step);
+    }
+    // packed: count the unique output tiles and unique input tiles actually visited
+    const int nk = a.nk;
+    double steps = 0;
+    for (int ki = 0; ki < nk; ++ki)
+        for (int kj = 0; kj < nk; ++kj)
+            for (int ka = 0; ka < nk; ++ka) {
+                const int kb = ((ki + kj - ka) % nk + nk) % nk;
+                if (ka > kb) continue;
+                const double out = ka == kb ? tA * (tA + 1) / 2.0 : (double)tA * tB;
+                double in = 0;
+                for (int ke = 0; ke < nk; ++ke) {
+                    const int kf = ((ki + kj - ke) % nk + nk) % nk;
+                    if (ke > kf) continue;
+                    in += ke == kf ? tE * (tE + 1) / 2.0 : (double)tE * tF;
+                }
+                steps += out * in;
+            }
+    return steps * tilesM * (main_step + 2.0 * rebuild_step);
 }
 
 template hipError_t launch_ladder<double>(const LadderArgs &, hipStream_t);

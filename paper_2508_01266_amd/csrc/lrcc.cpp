@@ -24,6 +24,8 @@
 #include "plan.hpp"
 #include "solver.hpp"
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 
 using namespace lrcc;
@@ -63,6 +65,7 @@ struct State {
     KT Fae, Fmi, Fme, Fbe, Fmj, Wp, Wbar, Q, R, S, U, Yp, H, G2;
     void *La = nullptr, *Lb = nullptr;      // dressed virtual Cholesky slices (ladder)
     void *LaT = nullptr, *LbT = nullptr;    // pair-transposed copies (adjoint ladder)
+    void *d_o1 = nullptr, *d_v1 = nullptr, *d_o2 = nullptr, *d_v2 = nullptr;  // preconditioner diagonals
     bool ready = false;
 };
 
@@ -90,6 +93,10 @@ struct lrcc_ctx {
     size_t stage_bytes = 0;
     void *st_x1 = nullptr, *st_x2 = nullptr, *st_y1 = nullptr, *st_y2 = nullptr, *st_om = nullptr;
     Profiler prof;
+    bool use_graphs = false;
+    bool pack_ladder = true;                   // antisymmetry-packed forward ladder for large batches
+    bool autotune = false;
+    hipStream_t own_stream = nullptr;          // non-null stream for solver work (graph capture)
     std::unique_ptr<Program> pre64, pre32;     // amplitude-dependent blocks (f64) and their f32 copies
     void *eps_o = nullptr, *eps_v = nullptr;   // diagonal of fock per k (preconditioner)
     DevMem solmem;                             // solver work vectors
@@ -149,6 +156,7 @@ void build_eri(lrcc_ctx *c, Program &P, const KT &out, double scale) {
         // pass 1: exchange -(ps|qr): M=(p,s) from Ls[kp][ks], N=(q,r) from Lcs[kq][kr]
         const int mi = pass == 0 ? 2 : 3, ni = pass == 0 ? 3 : 2;
         GemmArgs g{};
+        g.shape = -1;
         g.A = c->Ls;
         g.B = c->Lcs;
         g.C = out.p;
@@ -200,6 +208,7 @@ void build_dressing(lrcc_ctx *c, Program &P, void *slice_src, void *out, const v
     // slice_src: full scaled Cholesky array [nk][nk][naux][n][n]; out already holds the vv slice
     const int nk = c->nk, n = c->n, naux = c->naux, o = c->no, v = c->nv;
     GemmArgs g{};
+        g.shape = -1;
     g.A = t1;
     g.B = slice_src;
     g.C = out;
@@ -315,6 +324,15 @@ void build_state(lrcc_ctx *c) {
     KT ytmp = alloc_kt<double>(c, m, "oovo");
     contract<double>(P, ytmp, "mnej", t1, "jf", oovv, "mnef", 1.0, false);
     contract<double>(P, S.Wbar, "mbej", t1, "nb", ytmp, "mnej", -1.0);
+    {
+        // ring layout [m][e][b][j]: the (b,j) columns of the ring product become contiguous
+        KT wr = alloc_kt<double>(c, m, "ovvo", 0, {1, -1, 1, -1});
+        const int ext[4] = {o, v, v, o}, perm[4] = {0, 2, 1, 3}, sg[4] = {1, -1, 1, -1};
+        void *src = S.Wbar.p, *dst = wr.p;
+        const int nk_ = nk;
+        P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, nk_, ext, perm, sg, s); });
+        S.Wbar = wr;
+    }
     // Q_ijam = sum_ef tau_ijef <am||ef>
     S.Q = alloc_kt<double>(c, m, "oovo");
     contract<double>(P, S.Q, "ijam", tau, "ijef", ovvv, "maef", -1.0, false);
@@ -347,6 +365,18 @@ void build_state(lrcc_ctx *c) {
         P.ops.push_back([=](hipStream_t s) { return chol_slice<double>(Lcs, Lb, nk, naux, n, o, v, o, v, 1.0, 0, s); });
         build_dressing(c, P, Ls, La, S.t1.p);
         build_dressing(c, P, Lcs, Lb, S.t1.p);
+    }
+    // preconditioner: diagonals of the dressed one-body blocks (F_mi, F_ae for singles,
+    // Fbar_mj, Fbar_be for doubles) in place of the bare orbital energies of Eq. D
+    S.d_o1 = m.get((size_t)nk * o * 8); S.d_v1 = m.get((size_t)nk * v * 8);
+    S.d_o2 = m.get((size_t)nk * o * 8); S.d_v2 = m.get((size_t)nk * v * 8);
+    {
+        void *a = S.Fmi.p, *b = S.Fae.p, *cc = S.Fmj.p, *d = S.Fbe.p;
+        double *da = (double *)S.d_o1, *db = (double *)S.d_v1, *dc = (double *)S.d_o2, *dd = (double *)S.d_v2;
+        P.ops.push_back([=](hipStream_t s) { return diag_real(a, da, nk, o, s); });
+        P.ops.push_back([=](hipStream_t s) { return diag_real(b, db, nk, v, s); });
+        P.ops.push_back([=](hipStream_t s) { return diag_real(cc, dc, nk, o, s); });
+        P.ops.push_back([=](hipStream_t s) { return diag_real(d, dd, nk, v, s); });
     }
     S.LaT = m.get(lvv * 16);
     S.LbT = m.get(lvv * 16);
@@ -517,7 +547,7 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     con(Z, "Rijab", Vx, "Rijmn", S.tau, "mnab", 1.0 / 8);
     con(Z, "Rijab", S.Q, "ijam", x1, "Rmb", -0.25);
     // ring terms (P(ij)P(ab))
-    con(Z, "Rijab", x2, "Rimae", S.Wbar, "mbej", 1.0);
+    con(Z, "Rijab", x2, "Rimae", S.Wbar, "mebj", 1.0);
     con(Z, "Rijab", S.R, "iabf", x1, "Rjf", 1.0);
     con(Z, "Rijab", S.S, "ijan", x1, "Rnb", -1.0);
     con(Yx, "Rijan", x1, "Rjf", S.U, "ianf", 1.0, false);
@@ -565,7 +595,11 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
         }
         case SymOp::LADDER: {
             LadderArgs la = ladder_args<T>(c, op.A.p, S.La, S.Lb, op.C.p, R, op.alpha.real());
-            P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
+            la.packed = c->pack_ladder ? 1 : 0;  // dtau is antisymmetric in (e,f)
+            auto lp = std::make_shared<LadderArgs>(la);
+            P->ops.push_back([lp](hipStream_t s) { return launch_ladder<T>(*lp, s); });
+            // candidates: antisymmetry-packed (0) or full-range (1) ladder
+            P->tunables.push_back({P->ops.size() - 1, 2, [lp](int c) { lp->packed = c == 0 ? 1 : 0; }});
             P->tag_last(TAG_LADDER);
             P->flops += (i64)ladder_executed_flops(la);
             break;
@@ -639,6 +673,66 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
     return P;
 }
 
+// Autotuning cache: one line per program, "key choice0 choice1 ..." in a text
+// file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction.
+std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
+    char b[128];
+    std::snprintf(b, sizeof b, "%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
+                  adj ? "adjoint" : "forward", variant);
+    return b;
+}
+
+bool tune_lookup(const std::string &key, std::vector<int> &choice) {
+    const char *path = std::getenv("LRCC_TUNE_CACHE");
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[8192];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        if (l.compare(0, key.size() + 1, key + " ") != 0) continue;
+        choice.clear();
+        for (size_t p = key.size(); p < l.size(); ++p)
+            if (l[p] == '0' || l[p] == '1') choice.push_back(l[p] - '0');
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const std::string &key, const std::vector<int> &choice) {
+    const char *path = std::getenv("LRCC_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s", key.c_str());
+    for (int x : choice) std::fprintf(f, " %d", x);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
+
+// Run a recorded sigma program on the current io bindings, eagerly (timed if
+// profiling) or through its captured graph.  With autotuning on, the first run
+// of a program chooses its launch variants (or takes them from the cache).
+hipError_t run_sigma(lrcc_ctx *c, Program *p, hipStream_t st) {
+    if (c->autotune && !p->tuned) {
+        std::vector<int> choice;
+        if (tune_lookup(p->tune_key, choice)) {
+            p->apply(choice);
+        } else {
+            hipError_t e = p->autotune(st, choice);
+            if (e != hipSuccess) return e;
+            tune_store(p->tune_key, choice);
+        }
+    }
+    if (c->use_graphs && st != nullptr) {
+        Program::GraphKey key{c->io_x1, c->io_x2, c->io_y1, c->io_y2, c->io_omega};
+        return p->run_graph(st, key);
+    }
+    return p->run(st, &c->prof);
+}
+
 // variant 0: the CCSD Jacobian; variant 1+x: the Jacobian of the one-body
 // perturbation residual for dipole axis x (Fock matrix -> mu_x, no two-electron part).
 Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false, int variant = 0) {
@@ -656,6 +750,7 @@ Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false, int v
     else
         p = prec == LRCC_FP64 ? build_sigma_adjoint<double>(c, c->s64, R, *mem)
                               : build_sigma_adjoint<float>(c, c->s32, R, *mem);
+    p->tune_key = tune_key(c, prec, R, adjoint, variant);
     c->progs[key].reset(p);
     c->progmem[key] = std::move(mem);
     return p;
@@ -713,14 +808,15 @@ struct SolveCtx {
         HIPCHK(hipMemsetAsync(y.d, 0, R * n2 * 16, st));
     }
     void prec(const Vecs &out, const Vecs &in) {
-        HIPCHK(precond(out.s, out.d, in.s, in.d, (const double *)c->eps_o, (const double *)c->eps_v, omega, c->nk,
-                       R, c->no, c->nv, st));
+        const State<double> &T = c->s64;
+        HIPCHK(precond(out.s, out.d, in.s, in.d, (const double *)T.d_o1, (const double *)T.d_v1,
+                       (const double *)T.d_o2, (const double *)T.d_v2, omega, c->nk, R, c->no, c->nv, st));
     }
     // y = (A - omega) x
     void op(const Vecs &y, const Vecs &x, int precision) {
         Program *p = sigma_program(c, precision, R, adjoint);
         c->io_x1 = x.s; c->io_x2 = x.d; c->io_y1 = y.s; c->io_y2 = y.d; c->io_omega = omega;
-        HIPCHK(p->run(st, &c->prof));
+        HIPCHK(run_sigma(c, p, st));
         (precision == LRCC_FP64 ? nsig64 : nsig32)++;
         rhs_sig += R;
     }
@@ -729,6 +825,11 @@ struct SolveCtx {
 // GMRES on (A - omega) x = b starting from x (in/out).  Stops when every
 // right-hand side reaches ||r|| <= tol ||b|| or after max_apply operator
 // applications.  Returns per-RHS relative residual estimates.
+static bool verbose() {
+    static int v = std::getenv("LRCC_VERBOSE") ? 1 : 0;
+    return v != 0;
+}
+
 std::vector<double> gmres(SolveCtx &S, const Vecs &b, const Vecs &x, int precision, double tol, int max_apply,
                           int m, std::vector<Vecs> &V, const Vecs &w, const Vecs &z, bool x_is_zero) {
     const int R = S.R;
@@ -753,6 +854,10 @@ std::vector<double> gmres(SolveCtx &S, const Vecs &b, const Vecs &x, int precisi
             rel[r] = bn[r] > 0 ? beta[r] / bn[r] : 0.0;
             if (rel[r] > tol) all = false;
         }
+        if (verbose())
+            std::fprintf(stderr, "[lrcc] gmres %s%s R=%d applied=%d max rel residual %.3e\n",
+                         precision == LRCC_FP64 ? "fp64" : "fp32", S.adjoint ? " adjoint" : "", R, applied,
+                         *std::max_element(rel.begin(), rel.end()));
         if (all || applied >= max_apply) return rel;
         std::vector<cd> inv(R);
         for (int r = 0; r < R; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
@@ -845,14 +950,21 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
     S.c = c; S.R = R; S.st = st; S.omega = omega_dev; S.adjoint = adjoint;
     S.n1 = (i64)c->nk * c->no * c->nv;
     S.n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
-    const int m = std::max(1, o.krylov);
     const bool mixed = o.precision == LRCC_FP32;
-    const int nvec = (m + 1) + 2 + (mixed ? 2 : 0);
     const size_t per = (size_t)R * (S.n1 + S.n2) * 16;
+    c->solmem.release();
+    int m = o.krylov;
+    if (m <= 0) {
+        // subspace size from the free device memory (60% of it), between 4 and 60 vectors
+        size_t fr = 0, tot = 0;
+        if (!g_dry_run) HIPCHK(hipMemGetInfo(&fr, &tot));
+        const long long fit = (long long)(0.6 * (double)fr / (double)per) - 3 - (mixed ? 2 : 0);
+        m = (int)std::max(4LL, std::min(60LL, fit));
+    }
+    const int nvec = (m + 1) + 2 + (mixed ? 2 : 0);
     const size_t need = per * nvec + (size_t)R * (dot_blocks(S.n2) + 4) * 16 * 2;
     if (o.mem_cap_bytes > 0 && need > (size_t)o.mem_cap_bytes)
         throw LrccError(LRCC_E_OOM, "solver work vectors exceed the memory cap");
-    c->solmem.release();
     std::vector<Vecs> V(m + 1);
     auto mk = [&]() { Vecs v; v.s = c->solmem.get((size_t)R * S.n1 * 16); v.d = c->solmem.get((size_t)R * S.n2 * 16); return v; };
     for (auto &v : V) v = mk();
@@ -881,10 +993,13 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
                 if (rel[q] > o.tol) all = false;
             }
             rep.outer = it + 1;
+            if (verbose())
+                std::fprintf(stderr, "[lrcc] refinement step %d: max rel residual %.3e (krylov %d)\n", it,
+                             *std::max_element(rel.begin(), rel.end()), m);
             if (all) break;
             // FP32 correction solve (A - w) dx = r to inner_tol
             S.zero(dx);
-            gmres(S, r, dx, LRCC_FP32, o.inner_tol, m, m, V, w, z, true);
+            gmres(S, r, dx, LRCC_FP32, o.inner_tol, 4 * m, m, V, w, z, true);
             S.axpby(x, dx, std::vector<cd>(R, cd(1.0, 0.0)), 1.0);
         }
     }
@@ -900,7 +1015,7 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
 void default_opts(lrcc_solve_opts &o) {
     o.tol = 1e-10;
     o.max_iter = 400;
-    o.krylov = 8;
+    o.krylov = 0;
     o.precision = LRCC_FP64;
     o.inner_tol = 1e-4;
     o.max_outer = 30;
@@ -1022,7 +1137,8 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
     const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
     ensure_alpha_programs(c);
-    hipStream_t st = nullptr;
+    if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
+    hipStream_t st = c->own_stream;
     // axes with a non-zero dipole (the paper skips vanishing components, Sec. II.B)
     std::vector<int> axes;
     {
@@ -1195,6 +1311,139 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+
+// ---------------------------------------------------------------- ground-state CCSD
+// The CCSD residual is a quartic polynomial in T, so with A the Jacobian
+//   Omega(T) = Omega(0) + int_0^1 A(sT) T ds
+// and the integrand is cubic in s: the 2-point Gauss-Legendre rule on [0,1]
+// reproduces it exactly.  Each residual costs two re-runs of the amplitude-
+// dependent blocks and two single-RHS sigma applications.  Omega(0) =
+// (f_ai, <ab||ij>).  Jacobi steps t <- t + Omega / D with the orbital-energy
+// denominators of Eq. D and DIIS on the amplitude change (Sec. II.C).
+void ccsd_residual(lrcc_ctx *c, SolveCtx &S, const Vecs &T, const Vecs &om0, const Vecs &out, const Vecs &tmp) {
+    State<double> &St = c->s64;
+    const i64 n1 = S.n1, n2 = S.n2;
+    const double g = 0.5 / std::sqrt(3.0);
+    const double nodes[2] = {0.5 - g, 0.5 + g};
+    S.copy(out, om0);
+    Program *sig = sigma_program(c, LRCC_FP64, 1, false);
+    for (int q = 0; q < 2; ++q) {
+        // state amplitudes = s T (T2 in crystal normalisation)
+        HIPCHK(scale_copy(St.t1.p, T.s, nodes[q], 0.0, n1, S.st));
+        HIPCHK(scale_copy(St.t2.p, T.d, nodes[q] / c->nk, 0.0, n2, S.st));
+        run_precompute(c, false, S.st);
+        c->io_x1 = T.s; c->io_x2 = T.d; c->io_y1 = tmp.s; c->io_y2 = tmp.d; c->io_omega = nullptr;
+        HIPCHK(sig->run(S.st, nullptr));
+        S.rhs_sig += 1;
+        S.axpby(out, tmp, std::vector<cd>(1, cd(0.5, 0.0)), 1.0);
+    }
+}
+
+void solve_ccsd(lrcc_ctx *c, double tol, int max_iter, int ndiis, lrcc_solve_report &rep, double &energy) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c->s64.ready) build_state(c);
+    if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
+    hipStream_t st = c->own_stream;
+    const int nk = c->nk, o = c->no, v = c->nv, n = c->n;
+    SolveCtx S;
+    S.c = c; S.R = 1; S.st = st; S.omega = nullptr;
+    S.n1 = (i64)nk * o * v;
+    S.n2 = (i64)nk * nk * nk * o * o * v * v;
+    DevMem m;
+    auto mk = [&]() { Vecs x; x.s = m.get(S.n1 * 16); x.d = m.get(S.n2 * 16); return x; };
+    S.part = m.get((size_t)dot_blocks(S.n2) * 16);
+    S.dout = m.get(16);
+    S.alpha = m.get(16);
+    Vecs om0 = mk(), T = mk(), res = mk(), tmp = mk(), step = mk();
+    std::vector<Vecs> hist, errs;
+    // Omega(0): singles f_ai (stored [k][i][a]), doubles <ab||ij> = conj(<ij||ab>) (per-cell: x Nk)
+    HIPCHK(axis_slice<double>(c->fock, om0.s, 1, nk, n, 0, o, o, v, 1, st));
+    HIPCHK(conj_scale(om0.d, c->g_oovv.p, (double)nk, S.n2, st));
+    S.zero(T);
+    double rn = 0;
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        ccsd_residual(c, S, T, om0, res, tmp);
+        rn = std::sqrt(std::max(0.0, S.dot(res, res)[0].real()));
+        if (verbose()) std::fprintf(stderr, "[lrcc] ccsd iteration %d |Omega| %.3e\n", it, rn);
+        if (rn <= tol) break;
+        // Jacobi: t_new = t + Omega / D = t - Omega / (e_a + e_b - e_i - e_j)
+        HIPCHK(precond(step.s, step.d, res.s, res.d, (const double *)c->eps_o, (const double *)c->eps_v,
+                       (const double *)c->eps_o, (const double *)c->eps_v, nullptr, nk, 1, o, v, st));
+        Vecs tn = mk();
+        S.copy(tn, T);
+        S.axpby(tn, step, std::vector<cd>(1, cd(-1.0, 0.0)), 1.0);
+        Vecs e = mk();
+        S.copy(e, tn);
+        S.axpby(e, T, std::vector<cd>(1, cd(-1.0, 0.0)), 1.0);
+        hist.push_back(tn);
+        errs.push_back(e);
+        if ((int)hist.size() > ndiis) { hist.erase(hist.begin()); errs.erase(errs.begin()); }
+        const int k = (int)hist.size();
+        if (k >= 2) {
+            // DIIS: min |sum c_i e_i| with sum c_i = 1 (Hermitian error matrix)
+            std::vector<cd> B((k + 1) * (k + 1), 0.0), rhs(k + 1, 0.0);
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b <= a; ++b) {
+                    cd d = S.dot(errs[a], errs[b])[0];
+                    B[a * (k + 1) + b] = d;
+                    B[b * (k + 1) + a] = std::conj(d);
+                }
+            for (int a = 0; a < k; ++a) { B[a * (k + 1) + k] = -1.0; B[k * (k + 1) + a] = -1.0; }
+            rhs[k] = -1.0;
+            // Gaussian elimination with partial pivoting
+            const int N = k + 1;
+            std::vector<cd> A = B, x = rhs;
+            for (int col = 0; col < N; ++col) {
+                int piv = col;
+                for (int r = col + 1; r < N; ++r) if (std::abs(A[r * N + col]) > std::abs(A[piv * N + col])) piv = r;
+                for (int q = 0; q < N; ++q) std::swap(A[col * N + q], A[piv * N + q]);
+                std::swap(x[col], x[piv]);
+                if (std::abs(A[col * N + col]) < 1e-300) continue;
+                for (int r = col + 1; r < N; ++r) {
+                    cd f = A[r * N + col] / A[col * N + col];
+                    for (int q = col; q < N; ++q) A[r * N + q] -= f * A[col * N + q];
+                    x[r] -= f * x[col];
+                }
+            }
+            for (int r = N - 1; r >= 0; --r) {
+                cd acc = x[r];
+                for (int q = r + 1; q < N; ++q) acc -= A[r * N + q] * x[q];
+                x[r] = std::abs(A[r * N + r]) > 1e-300 ? acc / A[r * N + r] : 0.0;
+            }
+            S.zero(T);
+            for (int a = 0; a < k; ++a) S.axpby(T, hist[a], std::vector<cd>(1, x[a]), 1.0);
+        } else {
+            S.copy(T, tn);
+        }
+    }
+    // converged amplitudes into the state (crystal normalisation) and every derived block
+    HIPCHK(scale_copy(c->s64.t1.p, T.s, 1.0, 0.0, S.n1, st));
+    HIPCHK(scale_copy(c->s64.t2.p, T.d, 1.0 / nk, 0.0, S.n2, st));
+    run_precompute(c, true, st);
+    // energy per cell (Eq. ene): (1/Nk) [f_ia t_ia + 1/4 <ij||ab> tau_ijab] in supercell quantities
+    {
+        State<double> &Sd = c->s64;
+        Vecs tau{Sd.t1.p, Sd.tau.p}, f{Sd.fov.p, c->g_oovv.p};
+        cd e1, e2;
+        HIPCHK(batched_dot(Sd.fov.p, Sd.t1.p, 1, S.n1, 1.0, S.part, S.dout, st, 0));
+        HIPCHK(hipMemcpy(&e1, S.dout, 16, hipMemcpyDeviceToHost));
+        HIPCHK(batched_dot(c->g_oovv.p, Sd.tau.p, 1, S.n2, 0.25, S.part, S.dout, st, 0));
+        HIPCHK(hipMemcpy(&e2, S.dout, 16, hipMemcpyDeviceToHost));
+        energy = (e1 + e2).real() / nk;
+        (void)tau; (void)f;
+    }
+    c->amp = true;
+    c->lam_valid = false;
+    rep = lrcc_solve_report{};
+    rep.converged = rn <= tol;
+    rep.outer = it + 1;
+    rep.sigma_fp64 = (int)S.rhs_sig;
+    rep.rhs_sigmas = S.rhs_sig;
+    rep.max_rel_residual = rn;
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 // Device copies of the Hamiltonian and the stored integral blocks (all but vvvv).
 void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const double *fock, const double *chol,
                        const double *dip) {
@@ -1306,6 +1555,8 @@ void lrcc_destroy(lrcc_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->dev);
     (void)hipDeviceSynchronize();
+    c->progs.clear();
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
 
@@ -1393,7 +1644,7 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *c, int nrhs, const double *omega, con
         if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
         Program *p = sigma_program(c, precision, nrhs);
         c->io_x1 = x1; c->io_x2 = x2; c->io_y1 = y1; c->io_y2 = y2; c->io_omega = omega;
-        HIPCHK(p->run((hipStream_t)stream, &c->prof));
+        HIPCHK(run_sigma(c, p, (hipStream_t)stream));
     });
 }
 
@@ -1405,7 +1656,7 @@ lrcc_status lrcc_apply_sigma_adjoint_dev(lrcc_ctx *c, int nrhs, const double *om
         if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
         Program *p = sigma_program(c, precision, nrhs, true);
         c->io_x1 = x1; c->io_x2 = x2; c->io_y1 = y1; c->io_y2 = y2; c->io_omega = omega;
-        HIPCHK(p->run((hipStream_t)stream, &c->prof));
+        HIPCHK(run_sigma(c, p, (hipStream_t)stream));
     });
 }
 
@@ -1467,10 +1718,15 @@ lrcc_status lrcc_solve_response_dev(lrcc_ctx *c, int nrhs, const double *omega, 
         default_opts(o);
         if (opts) o = *opts;
         if (o.precision != LRCC_FP64 && o.precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
-        if (!(o.tol > 0) || o.krylov < 1 || o.max_iter < 1) throw LrccError(LRCC_E_ARG, "bad solver options");
+        if (!(o.tol > 0) || o.krylov < 0 || o.max_iter < 1) throw LrccError(LRCC_E_ARG, "bad solver options");
         lrcc_solve_report rep;
         Vecs b{const_cast<void *>(b1), const_cast<void *>(b2)}, x{x1, x2};
-        solve_response(c, nrhs, omega, b, x, o, rep, (hipStream_t)stream);
+        hipStream_t st = (hipStream_t)stream;
+        if (!st) {
+            if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
+            st = c->own_stream;
+        }
+        solve_response(c, nrhs, omega, b, x, o, rep, st);
         if (report) *report = rep;
         if (!rep.converged)
             throw LrccError(LRCC_E_NOCONV, "response solve stopped at relative residual " +
@@ -1518,6 +1774,26 @@ lrcc_status lrcc_solve(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double 
     });
 }
 
+lrcc_status lrcc_solve_ccsd(lrcc_ctx *c, double tol, int max_iter, double *t1, double *t2, double *energy,
+                            lrcc_solve_report *report) {
+    return guarded(c, [&] {
+        if (!c->ham) throw LrccError(LRCC_E_STATE, "set_hamiltonian must be called first");
+        if (!(tol > 0) || max_iter < 1) throw LrccError(LRCC_E_ARG, "bad tolerance or iteration limit");
+        lrcc_solve_report rep{};
+        double e = 0;
+        solve_ccsd(c, tol, max_iter, 8, rep, e);
+        if (energy) *energy = e;
+        if (report) *report = rep;
+        const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
+        if (t1) HIPCHK(hipMemcpy(t1, c->s64.t1.p, n1 * 16, hipMemcpyDeviceToHost));
+        if (t2) {
+            HIPCHK(hipMemcpy(t2, c->s64.t2.p, n2 * 16, hipMemcpyDeviceToHost));
+            for (i64 q = 0; q < 2 * n2; ++q) t2[q] *= c->nk;
+        }
+        if (!rep.converged) throw LrccError(LRCC_E_NOCONV, "CCSD did not converge: |Omega| = " + std::to_string(rep.max_rel_residual));
+    });
+}
+
 lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {
     return guarded(c, [&] {
         if (!alpha) throw LrccError(LRCC_E_ARG, "null output");
@@ -1548,6 +1824,18 @@ lrcc_status lrcc_get_lambda(lrcc_ctx *c, double *l1, double *l2) {
         const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
         HIPCHK(hipMemcpy(l1, c->lam1, n1 * 16, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(l2, c->lam2, n2 * 16, hipMemcpyDeviceToHost));
+    });
+}
+
+lrcc_status lrcc_set_autotune(lrcc_ctx *c, int enable) {
+    return guarded(c, [&] { c->autotune = enable != 0; });
+}
+
+lrcc_status lrcc_set_graphs(lrcc_ctx *c, int enable) {
+    return guarded(c, [&] {
+        c->use_graphs = enable != 0;
+        if (!c->use_graphs)
+            for (auto &p : c->progs) p.second->drop_graphs();
     });
 }
 

@@ -8,6 +8,9 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <memory>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 
 namespace lrcc {
@@ -45,7 +48,32 @@ void *Program::alloc(size_t bytes) {
 }
 
 Program::~Program() {
+    drop_graphs();
     for (void *p : owned) dev_free(p);
+}
+
+void Program::drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+}
+
+hipError_t Program::run_graph(hipStream_t s, const GraphKey &key) {
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t er = run(s, nullptr);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (er != hipSuccess) return er;
+        if (e != hipSuccess) return e;
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        it = graphs.emplace(key, exec).first;
+    }
+    return hipGraphLaunch(it->second, s);
 }
 
 hipError_t Program::run(hipStream_t s, Profiler *prof) {
@@ -80,6 +108,46 @@ hipError_t Program::run(hipStream_t s, Profiler *prof) {
         prof->record(TAG_PROGRAM, p0, p1);
     }
     return hipSuccess;
+}
+
+void Program::apply(const std::vector<int> &choice) {
+    for (size_t i = 0; i < tunables.size() && i < choice.size(); ++i)
+        tunables[i].set(std::min(choice[i], tunables[i].ncand - 1));
+    tuned = true;
+}
+
+hipError_t Program::autotune(hipStream_t s, std::vector<int> &choice) {
+    const size_t nt = tunables.size();
+    std::vector<std::vector<float>> t(2, std::vector<float>(nt, 1e30f));
+    std::vector<hipEvent_t> ev(2 * nt);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return hipErrorUnknown;
+    hipError_t err = hipSuccess;
+    for (int cand = 0; cand < 2 && err == hipSuccess; ++cand) {
+        for (auto &tu : tunables) tu.set(std::min(cand, tu.ncand - 1));
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {  // first run warms caches and code
+            size_t k = 0;
+            for (size_t i = 0; i < ops.size(); ++i) {
+                const bool timed = k < nt && tunables[k].op == i;
+                if (timed) (void)hipEventRecord(ev[2 * k], s);
+                err = ops[i](s);
+                if (err != hipSuccess) break;
+                if (timed) { (void)hipEventRecord(ev[2 * k + 1], s); ++k; }
+            }
+            if (err == hipSuccess) err = hipStreamSynchronize(s);
+            if (rep == 1 && err == hipSuccess)
+                for (size_t k2 = 0; k2 < nt; ++k2) {
+                    float ms = 0;
+                    if (hipEventElapsedTime(&ms, ev[2 * k2], ev[2 * k2 + 1]) == hipSuccess) t[cand][k2] = ms;
+                }
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    choice.assign(nt, 0);
+    for (size_t k = 0; k < nt; ++k)
+        if (tunables[k].ncand > 1 && t[1][k] < t[0][k]) choice[k] = 1;
+    apply(choice);
+    return err;
 }
 
 hipEvent_t Profiler::ev() {
@@ -159,6 +227,15 @@ std::vector<std::vector<char>> chains(std::vector<char> set, const TInfo &p, con
         out.push_back({c});
     }
     return out;
+}
+
+// Order index groups by decreasing stride in the operand x (read from HBM), so
+// that its smallest-stride group is the innermost level of the GEMM index.
+std::vector<std::vector<char>> by_stride(std::vector<std::vector<char>> ch, const TInfo &x) {
+    std::stable_sort(ch.begin(), ch.end(), [&](const std::vector<char> &a, const std::vector<char> &b) {
+        return x.stride[pos(x, a.back())] > x.stride[pos(x, b.back())];
+    });
+    return ch;
 }
 
 void make_split(const std::vector<std::vector<char>> &ch, const TInfo &x, const TInfo &y, Split &sp,
@@ -252,7 +329,10 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
     g.segA = dA;
     g.segB = dB;
     P.flops += 8LL * g.M * g.N * g.K * (i64)segA.size();
-    P.ops.push_back([g](hipStream_t s) { return launch_gemm<T>(g, s); });
+    auto gp = std::make_shared<GemmArgs>(g);
+    P.ops.push_back([gp](hipStream_t s) { return launch_gemm<T>(*gp, s); });
+    // candidates: 64x64 tiles (0) or the large tile shape (1)
+    P.tunables.push_back({P.ops.size() - 1, 2, [gp](int c) { gp->shape = c; }});
 }
 
 template <typename T>
@@ -273,12 +353,19 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
         if (c != 'R') (inC ? free_k : sum_k).push_back(c);
     }
     GemmArgs g{};
+    g.shape = -1;
     g.A = A.p;
     g.B = B.p;
     g.C = C.p;
-    make_split(chains(Ml, ta, tc), ta, tc, g.sm, g.Am, g.Cm, g.M, what);
-    make_split(chains(Nl, tb, tc), tb, tc, g.sn, g.Bn, g.Cn, g.N, what);
-    make_split(chains(Kl, tb, ta), ta, tb, g.sk, g.Ak, g.Bk, g.K, what);
+    make_split(by_stride(chains(Ml, ta, tc), ta), ta, tc, g.sm, g.Am, g.Cm, g.M, what);
+    make_split(by_stride(chains(Nl, tb, tc), tb), tb, tc, g.sn, g.Bn, g.Cn, g.N, what);
+    {
+        // K: make the unit-stride group innermost for whichever operand has one (A first)
+        auto kc = chains(Kl, tb, ta);
+        bool a_unit = false;
+        for (auto &c : kc) a_unit = a_unit || ta.stride[pos(ta, c.back())] == 1;
+        make_split(a_unit ? by_stride(kc, ta) : by_stride(kc, tb), ta, tb, g.sk, g.Ak, g.Bk, g.K, what);
+    }
     g.aMfast = (g.Am.s[2] == 1) || (g.Ak.s[2] != 1);
     g.bNfast = (g.Bn.s[2] == 1) || (g.Bk.s[2] != 1);
     g.alpha_re = alpha.real();
@@ -317,6 +404,11 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
         if (segA.size() == before && accumulate) continue;  // nothing to add to this block
         offC.push_back(cb * C.inner());
         segBeg.push_back((int)segA.size());
+    }
+    if (std::getenv("LRCC_PLAN_DUMP")) {
+        const double pad = 8.0 * ((g.M + 63) / 64 * 64.0) * ((g.N + 63) / 64 * 64.0) * ((g.K + 15) / 16 * 16.0) * segA.size();
+        std::fprintf(stderr, "gemm %-28s M=%-7d N=%-7d K=%-6d jobs=%-5zu segs=%-6zu alg=%.3e padded=%.3e\n",
+                     what.c_str(), g.M, g.N, g.K, offC.size(), segA.size(), 8.0 * g.M * g.N * g.K * segA.size(), pad);
     }
     raw_gemm<T>(P, g, offC, segBeg, segA, segB, A.count(), B.count(), C.count());
 }

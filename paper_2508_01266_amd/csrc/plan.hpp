@@ -1,7 +1,9 @@
 // Host-side planner: k-blocked tensors and their contractions as GEMM job lists.
 #pragma once
+#include <array>
 #include <complex>
 #include <functional>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -56,10 +58,25 @@ struct Profiler {
     ~Profiler();
 };
 
+// A tunable launch of a recorded program: the op index and a setter for its
+// variant (candidate 0 or 1).
+struct Tunable {
+    size_t op;
+    int ncand;                           // number of valid candidates (1 or 2)
+    std::function<void(int)> set;
+};
+
 // A recorded sequence of device launches plus the device memory it owns.
 struct Program {
     std::vector<std::function<hipError_t(hipStream_t)>> ops;
     std::vector<int> tags;  // per op (TAG_NONE unless set by tag_last)
+    std::vector<Tunable> tunables;
+    bool tuned = false;
+    std::string tune_key;
+    // Time every tunable op under each candidate (full program runs, so the
+    // recomputed outputs stay valid) and keep the fastest per op.
+    hipError_t autotune(hipStream_t s, std::vector<int> &choice);
+    void apply(const std::vector<int> &choice);
     std::vector<void *> owned;
     i64 flops = 0;  // executed real flops of the recorded GEMMs and ladder
     void tag_last(int t) {
@@ -67,6 +84,12 @@ struct Program {
         tags.back() = t;
     }
     hipError_t run(hipStream_t s, Profiler *prof = nullptr);
+    // Replay through a HIP graph captured on first use for this key (the
+    // pointers the recorded launches read); `s` must not be the null stream.
+    typedef std::array<const void *, 5> GraphKey;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    hipError_t run_graph(hipStream_t s, const GraphKey &key);
+    void drop_graphs();
     void *alloc(size_t bytes);
     ~Program();
 };

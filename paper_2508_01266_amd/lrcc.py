@@ -42,6 +42,10 @@ def lib():
         L.lrcc_apply_sigma_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
         L.lrcc_apply_sigma_adjoint_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_set_profiling.argtypes = [vp, i]
+        L.lrcc_set_graphs.argtypes = [vp, i]
+        L.lrcc_set_autotune.argtypes = [vp, i]
+        L.lrcc_set_autotune.restype = ctypes.c_int
+        L.lrcc_set_graphs.restype = ctypes.c_int
         L.lrcc_read_profile.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         L.lrcc_sigma_flops.argtypes = [vp, i, i, dp]
         for f in ("lrcc_set_profiling", "lrcc_read_profile", "lrcc_sigma_flops"):
@@ -56,6 +60,8 @@ def lib():
         L.lrcc_solve_response_dev.restype = ctypes.c_int
         L.lrcc_solve.argtypes = [vp, ctypes.c_uint, i, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]
         L.lrcc_get_alpha.argtypes = [vp, i, vp]
+        L.lrcc_solve_ccsd.argtypes = [vp, ctypes.c_double, i, vp, vp, dp, ctypes.POINTER(SolveReport)]
+        L.lrcc_solve_ccsd.restype = ctypes.c_int
         L.lrcc_get_solution.argtypes = [vp, i, i, i, vp, vp]
         L.lrcc_get_lambda.argtypes = [vp, vp, vp]
         for f in ("lrcc_solve", "lrcc_get_alpha", "lrcc_get_solution", "lrcc_get_lambda"):
@@ -198,6 +204,18 @@ class Context:
         self._check(self._L.lrcc_get_alpha(self._h, len(om), _ptr(alpha)))
         return alpha, rep.as_dict()
 
+    def solve_ccsd(self, tol=1e-9, max_iter=200):
+        """Ground-state CCSD on the device; the result becomes the context's amplitudes.
+        Returns (t1, t2, energy per cell, report)."""
+        nk, o, v = self.nk, self.no, self.nv
+        t1 = np.zeros((nk, o, v), dtype=np.complex128)
+        t2 = np.zeros((nk, nk, nk, o, o, v, v), dtype=np.complex128)
+        e = ctypes.c_double()
+        rep = SolveReport()
+        self._check(self._L.lrcc_solve_ccsd(self._h, float(tol), int(max_iter), _ptr(t1), _ptr(t2),
+                                            ctypes.byref(e), ctypes.byref(rep)))
+        return t1, t2, e.value, rep.as_dict()
+
     def get_solution(self, axis, ifreq, sign):
         nk, o, v = self.nk, self.no, self.nv
         x1 = np.zeros((nk, o, v), dtype=np.complex128)
@@ -211,6 +229,12 @@ class Context:
         l2 = np.zeros((nk, nk, nk, o, o, v, v), dtype=np.complex128)
         self._check(self._L.lrcc_get_lambda(self._h, _ptr(l1), _ptr(l2)))
         return l1, l2
+
+    def set_autotune(self, on=True):
+        self._check(self._L.lrcc_set_autotune(self._h, int(bool(on))))
+
+    def set_graphs(self, on=True):
+        self._check(self._L.lrcc_set_graphs(self._h, int(bool(on))))
 
     def set_profiling(self, on=True):
         self._check(self._L.lrcc_set_profiling(self._h, int(bool(on))))

@@ -43,6 +43,18 @@ class Workload:
     def n(self):
         return self.nocc + self.nvir
 
+    @property
+    def chol_sigma(self):
+        """Standard deviation of the Cholesky entries.  0.05 for the molecular-limit
+        and three-k workloads; for larger ones it is reduced so that the random
+        two-electron coupling of one amplitude row, which grows like
+        nvir * sqrt(naux / nk) * sigma^2, stays at the molecular-limit value
+        (with 0.05 at nvir=40, naux=144 the response operator is nearly singular)."""
+        if self.cfg_id <= 2:
+            return 0.05
+        ref = 12 * (48 / 1) ** 0.5
+        return 0.05 * (ref / (self.nvir * (self.naux / self.nk) ** 0.5)) ** 0.5
+
 
 WORKLOADS = {
     # molecular limit, 2 frequencies

@@ -61,3 +61,22 @@ def test_alpha_two_electron_sum_over_states():
     err = np.abs(a64 - ref).max()
     print(f"device alpha vs FCI sum over states: {err:.2e}", flush=True)
     assert err < 1e-9
+
+
+@pytest.mark.parametrize("nk,o,v,naux,seed", [(1, 2, 4, 6, 21), (2, 2, 3, 6, 22), (1, 4, 12, 48, 24)])
+def test_ccsd_ground_state_matches_oracle(nk, o, v, naux, seed):
+    """Device CCSD (exact residual from the Jacobian) against the oracle's CCSD."""
+    import paper_2508_01266_amd as lr
+    case = make_ccsd_case(nk, o, v, naux, seed)
+    c = lr.Context(0)
+    c.set_hamiltonian(o, case['H']['fock'], case['H']['chol'], case['H']['dip'])
+    t1, t2, e, rep = c.solve_ccsd(tol=1e-11, max_iter=300)
+    print(f"ccsd nk={nk} o={o} v={v}: E/cell {e:.12f} (oracle {case['E'].real / nk:.12f}) {rep}", flush=True)
+    assert rep['converged'] == 1
+    assert abs(e - case['E'].real / nk) < 1e-10
+    assert np.abs(t1 - case['t1']).max() < 1e-9
+    assert np.abs(t2 - case['t2']).max() < 1e-9
+    # alpha from the device amplitudes equals alpha from the oracle's amplitudes
+    ref, _ = oracle_alpha(case, OMEGAS)
+    a64, _ = c.solve(OMEGAS, tol=1e-11, precision=lr.FP64)
+    assert np.abs(a64 - ref).max() < 1e-9

@@ -1,0 +1,75 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark times:
+the batched sigma (all right-hand sides in one launch) against the k-blocked
+oracle on sampled right-hand sides, and the large-orbital slice (Nk=3, o=10,
+v=60, Naux=210) forward and transpose."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _inputs(name, nrhs):
+    w = synth.WORKLOADS[name]
+    rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=w.chol_sigma)
+    t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
+    x1, x2 = synth.random_vectors(nrhs, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
+    omega = np.linspace(-0.1, 0.1, nrhs)
+    return w, H, t1, t2 * w.nk, x1, x2 * w.nk, omega
+
+
+def _oracle_one(w, H, t1, t2, x1, x2, om, adjoint=False):
+    import torch
+    from oracle import kblock
+    nk = w.nk
+    ham = kblock.KHam(H['fock'], H['chol'], w.nocc)
+    t = (t1, t2 / nk)
+    if not adjoint:
+        s1, s2 = kblock.sigma(ham, t, (x1, x2 / nk))
+        return s1.numpy() - om * x1, nk * s2.numpy() - om * x2
+    raise NotImplementedError
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_workload_sampled_rhs(prec):
+    import paper_2508_01266_amd as lr
+    w, H, t1, t2, x1, x2, om = _inputs("c3", 48)
+    c = lr.Context(0)
+    c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+    c.set_amplitudes(t1, t2)
+    y1, y2 = c.apply_sigma(x1, x2, om, prec)
+    for r in (0, 29):
+        r1, r2 = _oracle_one(w, H, t1, t2, x1[r], x2[r], om[r])
+        e1, e2 = _rel(y1[r], r1), _rel(y2[r], r2)
+        tol = 1e-11 if prec == 0 else 4 * w.nk * w.nvir ** 2 * 2.0 ** -24
+        print(f"c3 48-rhs launch, rhs {r}, prec {prec}: rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
+        assert e1 < tol and e2 < tol
+
+
+def test_large_orbital_slice_forward_and_transpose():
+    import paper_2508_01266_amd as lr
+    w, H, t1, t2, x1, x2, om = _inputs("c4s", 2)
+    c = lr.Context(0)
+    c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+    c.set_amplitudes(t1, t2)
+    y1, y2 = c.apply_sigma(x1, x2, om, lr.FP64)
+    r1, r2 = _oracle_one(w, H, t1, t2, x1[0], x2[0], om[0])
+    e1, e2 = _rel(y1[0], r1), _rel(y2[0], r2)
+    print(f"Nk=3 o=10 v=60 slice: rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
+    assert e1 < 1e-11 and e2 < 1e-11
+    # transpose: dot-product identity against the verified forward product
+    rng = synth.rng_for(99, 3, 10, 60)
+    z1, z2 = synth.random_vectors(2, 3, 10, 60, rng, 0.1, 0.1)
+    z2 = z2 * 3
+    a1, a2 = c.apply_sigma_adjoint(z1, z2, om, lr.FP64)
+    for r in range(2):
+        lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
+        rhs = np.sum(a1[r] * x1[r]) + 0.25 * np.sum(a2[r] * x2[r])
+        print(f"slice dot identity rhs {r}: {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)

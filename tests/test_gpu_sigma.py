@@ -84,3 +84,60 @@ def test_sigma_adjoint_fp64_matches_oracle_and_dot_identity(nk, o, v, naux, nrhs
     b1, b2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP32)
     tol = 4 * nk * v * v * 2.0 ** -24 + 1e-6
     assert _rel(b1, ref1) < tol and _rel(b2, ref2) < tol
+
+
+def test_graph_replay_matches_eager():
+    """Sigma through captured HIP graphs equals the eager launches on every replay
+    (replays interleaved with eager work and with a second input set)."""
+    import torch
+    import paper_2508_01266_amd as lr
+    case = make_case(1, 4, 12, 48, 3, 41)
+    c = _ctx(case)
+    dev = torch.device("cuda:0")
+    xa1, xa2 = (torch.from_numpy(a).to(dev) for a in (case['x1'], case['x2']))
+    xb1, xb2 = xa1.flip(0).contiguous(), xa2.flip(0).contiguous()
+    om = torch.from_numpy(case['omega']).to(dev)
+    st = torch.cuda.Stream()
+    y1, y2 = torch.empty_like(xa1), torch.empty_like(xa2)
+    ref = {}
+    for name, (x1, x2) in (("a", (xa1, xa2)), ("b", (xb1, xb2))):
+        c.apply_sigma_dev(x1, x2, y1, y2, om, lr.FP64, st.cuda_stream)
+        st.synchronize()
+        ref[name] = (y1.clone(), y2.clone())
+    c.set_graphs(True)
+    for rep, name in enumerate(("a", "b", "a", "a", "b")):
+        x1, x2 = (xa1, xa2) if name == "a" else (xb1, xb2)
+        y1.zero_()
+        y2.zero_()
+        c.apply_sigma_dev(x1, x2, y1, y2, om, lr.FP64, st.cuda_stream)
+        st.synchronize()
+        # eager work between replays
+        z1, z2 = torch.empty_like(xa1), torch.empty_like(xa2)
+        c.set_graphs(False) if rep == 2 else None
+        c.apply_sigma_dev(xb1, xb2, z1, z2, om, lr.FP64, st.cuda_stream)
+        st.synchronize()
+        c.set_graphs(True)
+        assert torch.equal(y1, ref[name][0]) and torch.equal(y2, ref[name][1]), (rep, name)
+        assert torch.equal(z1, ref["b"][0]) and torch.equal(z2, ref["b"][1])
+
+
+def test_autotuned_variants_match_and_cache(tmp_path, monkeypatch):
+    """Autotuning picks launch variants without changing results; the choices are
+    cached per program and reused by a new context."""
+    import paper_2508_01266_amd as lr
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LRCC_TUNE_CACHE", str(cache))
+    case = make_case(2, 3, 5, 7, 24, 6)   # >= 192 rows: packed ladder and large tiles are candidates
+    ref1, ref2 = oracle_sigma(case)
+    c = _ctx(case)
+    c.set_autotune(True)
+    for _ in range(2):
+        y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
+        assert _rel(y1, ref1) < 1e-11 and _rel(y2, ref2) < 1e-11
+    text = cache.read_text()
+    assert "forward" in text and len(text.splitlines()) >= 1
+    c2 = _ctx(case)
+    c2.set_autotune(True)
+    z1, z2 = c2.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
+    assert _rel(z1, ref1) < 1e-11 and _rel(z2, ref2) < 1e-11
+    assert cache.read_text() == text       # second context read the cache, tuned nothing new
