@@ -176,6 +176,20 @@ lrcc_status lrcc_apply_sigma_adjoint_dev(lrcc_ctx *ctx, int nrhs, const double *
                                          const void *x1, const void *x2, void *y1, void *y2,
                                          int precision, void *stream);
 
+/* Vector-Jacobian product of the sigma map y = (A - omega) x for reverse-mode
+ * differentiation (the transpose operator of the lambda equations l1, l2,
+ * Sec. II.B, in the complex-gradient convention of PyTorch):
+ *   gx = conj((A - omega)^T conj(g)) restricted to antisymmetric doubles,
+ * i.e. Re sum conj(gx) . dx = Re sum conj(g) . (A - omega) dx over full caller
+ * arrays for every dx with antisymmetric doubles.  The doubles part of g is
+ * projected onto the antisymmetric subspace on entry and gx2 is antisymmetric.
+ * g1, gx1: [nrhs][nk][nocc][nvir]; g2, gx2: [nrhs][nk][nk][nk][nocc][nocc][nvir][nvir]
+ * (complex128 device buffers, caller layout of the sigma).  omega: nrhs real
+ * device values or NULL.  Grows a context-owned scratch of 2 x (input size)
+ * on first use with a larger nrhs.  Errors as for the sigma. */
+lrcc_status lrcc_sigma_vjp_dev(lrcc_ctx *ctx, int nrhs, const double *omega, const void *g1, const void *g2,
+                               void *gx1, void *gx2, int precision, void *stream);
+
 void lrcc_solve_opts_default(lrcc_solve_opts *opts);
 
 /* Solve the perturbed-amplitude equations (Eqs. tx1, tx2 in operator form,
@@ -226,6 +240,20 @@ lrcc_status lrcc_solve_ccsd(lrcc_ctx *ctx, double tol, int max_iter, double *t1,
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */
 lrcc_status lrcc_get_alpha(lrcc_ctx *ctx, int nfreq, double *alpha);
+
+/* Gradient of one polarizability element of the last lrcc_solve with respect to
+ * the dipole matrices (the perturbation operators of Eq. rhs, Sec. II.B), at
+ * fixed ground-state amplitudes and lambda (neither depends on the dipoles):
+ *   d alpha_xy(omega_ifreq) = sum_{Z,k,p,q} grad[Z][k][p][q] dmu_Z[k][p][q]
+ * for every Hermitian perturbation dmu_Z of the dipole of axis Z.
+ * grad: host [3][nk][n][n] complex (zeros for axes other than x, y).  alpha is
+ * bilinear in (mu_x, mu_y); the gradient costs one batched transpose solve of
+ * 4 right-hand sides (2 when x == y) with opts (NULL: defaults), 4 F-vector
+ * stencils and a few one-body density evaluations on the device.
+ * LRCC_E_STATE before lrcc_solve; LRCC_E_ARG for an axis the last solve did not
+ * include or an out-of-range ifreq; LRCC_E_NOCONV if the transpose solve fails. */
+lrcc_status lrcc_alpha_dipole_gradient(lrcc_ctx *ctx, int ifreq, int x, int y, const lrcc_solve_opts *opts,
+                                       double *grad);
 
 /* Perturbed amplitudes t^X(sign*omega_ifreq) of the last lrcc_solve (caller
  * layouts with nrhs = 1, per-cell normalisation). */

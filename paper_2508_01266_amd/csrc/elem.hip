@@ -249,6 +249,30 @@ hipError_t axis_slice(const void *in, void *out, int nax, int nk, int n, int p0,
     return hipGetLastError();
 }
 
+// Inverse of axis_slice: out[x][k][p0+p][q0+q] = in[k][x][p][q]
+// (transpose: out[x][k][q0+q][p0+p] = in[k][x][p][q]); complex128.
+__global__ void k_axis_scatter(const double2 *in, double2 *out, int nax, int nk, int n, int p0, int np, int q0,
+                               int nq, int transpose) {
+    const i64 N = (i64)nk * nax * np * nq;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int qq = (int)(q % nq); q /= nq;
+        const int pp = (int)(q % np); q /= np;
+        const int x = (int)(q % nax);
+        const int k = (int)(q / nax);
+        const i64 dst = transpose ? (((i64)x * nk + k) * n + q0 + qq) * n + p0 + pp
+                                  : (((i64)x * nk + k) * n + p0 + pp) * n + q0 + qq;
+        out[dst] = in[t];
+    }
+}
+
+hipError_t axis_scatter(const void *in, void *out, int nax, int nk, int n, int p0, int np, int q0, int nq,
+                        int transpose, hipStream_t s) {
+    hipLaunchKernelGGL(k_axis_scatter, dim3(grid_for((i64)nk * nax * np * nq)), dim3(256), 0, s,
+                       (const double2 *)in, (double2 *)out, nax, nk, n, p0, np, q0, nq, transpose);
+    return hipGetLastError();
+}
+
 // y = alpha * x (complex alpha, n elements, double2)
 __global__ void k_scale_copy(double2 *y, const double2 *x, double ar, double ai, i64 n) {
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
@@ -305,6 +329,39 @@ __global__ void k_conj_scale(double2 *y, const double2 *x, double s, i64 n) {
 }
 hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st) {
     hipLaunchKernelGGL(k_conj_scale, dim3(grid_for(n)), dim3(256), 0, st, (double2 *)y, (const double2 *)x, s, n);
+    return hipGetLastError();
+}
+
+// out = scale * c(y - y(ij swapped) - y(ab swapped) + y(both swapped)) on caller-layout doubles
+// [R][ki][kj][ka][i][j][a][b] (kb implied), c = complex conjugation when conj != 0.  Out of place.
+__global__ void k_antisym(const double2 *y, double2 *out, int R, int nk, int o, int v, double scale, int conj) {
+    const i64 B = (i64)nk * nk * nk, inner = (i64)o * o * v * v;
+    const i64 n = (i64)R * B * inner;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int b = (int)(q % v); q /= v;
+        const int a = (int)(q % v); q /= v;
+        const int j = (int)(q % o); q /= o;
+        const int i = (int)(q % o); q /= o;
+        const int ka = (int)(q % nk); q /= nk;
+        const int kj = (int)(q % nk); q /= nk;
+        const int ki = (int)(q % nk);
+        const i64 r = q / nk;
+        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
+            return y[((r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
+        };
+        const double2 z1 = at(ki, kj, ka, i, j, a, b), z2 = at(kj, ki, ka, j, i, a, b);
+        const double2 z3 = at(ki, kj, kb, i, j, b, a), z4 = at(kj, ki, kb, j, i, b, a);
+        const double re = scale * (z1.x - z2.x - z3.x + z4.x), im = scale * (z1.y - z2.y - z3.y + z4.y);
+        out[t] = make_double2(re, conj ? -im : im);
+    }
+}
+
+hipError_t antisym(const void *y, void *out, int R, int nk, int o, int v, double scale, int conj, hipStream_t s) {
+    const i64 n = (i64)R * nk * nk * nk * o * o * v * v;
+    hipLaunchKernelGGL(k_antisym, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y, (double2 *)out, R, nk, o,
+                       v, scale, conj);
     return hipGetLastError();
 }
 

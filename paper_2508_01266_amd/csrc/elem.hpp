@@ -24,7 +24,12 @@ template <typename Tout>
 hipError_t axis_slice(const void *in, void *out, int nax, int nk, int n, int p0, int np, int q0, int nq, int transpose,
                       hipStream_t s);
 hipError_t scale_copy(void *y, const void *x, double ar, double ai, i64 n, hipStream_t s);
+// inverse of axis_slice (complex128 in and out): out[x][k][p0+p][q0+q] = in[k][x][p][q]
+hipError_t axis_scatter(const void *in, void *out, int nax, int nk, int n, int p0, int np, int q0, int nq,
+                        int transpose, hipStream_t s);
 hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st);
+// caller-layout doubles: out = scale * c(P(ij) P(ab) y), c = conjugation when conj != 0 (out of place)
+hipError_t antisym(const void *y, void *out, int R, int nk, int o, int v, double scale, int conj, hipStream_t s);
 // four-index complex128 permutation: output dim d = input dim perm[d]; output momentum signs sg_out
 hipError_t permute4(const void *in, void *out, int nk, const int *ext_in, const int *perm, const int *sg_out,
                     hipStream_t s);

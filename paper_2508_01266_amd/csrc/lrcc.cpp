@@ -92,6 +92,10 @@ struct lrcc_ctx {
     DevMem stage;
     size_t stage_bytes = 0;
     void *st_x1 = nullptr, *st_x2 = nullptr, *st_y1 = nullptr, *st_y2 = nullptr, *st_om = nullptr;
+    // scratch of the vector-Jacobian product entry (grown on demand)
+    DevMem vjpmem;
+    size_t vjp_bytes = 0;
+    void *vj1 = nullptr, *vj2 = nullptr, *vw1 = nullptr, *vw2 = nullptr;
     Profiler prof;
     bool use_graphs = false;
     bool pack_ladder = true;                   // antisymmetry-packed forward ladder for large batches
@@ -115,6 +119,12 @@ struct lrcc_ctx {
     DevMem solv;                               // solutions x of the last solve
     void *sol1 = nullptr, *sol2 = nullptr;
     size_t sol_bytes = 0;
+    std::vector<double> last_omega;            // frequencies of the last solve
+    // one-body densities of amplitude-space vectors (dipole gradients)
+    DevMem gmem;
+    KT dT1, dT2;                               // amplitudes the density programs read (crystal)
+    std::map<int, std::unique_ptr<Program>> dens;
+    std::map<int, std::unique_ptr<DevMem>> densmem;
 };
 
 static std::string g_create_err;
@@ -601,6 +611,7 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
             // candidates: antisymmetry-packed (0) or full-range (1) ladder
             P->tunables.push_back({P->ops.size() - 1, 2, [lp](int c) { lp->packed = c == 0 ? 1 : 0; }});
             P->tag_last(TAG_LADDER);
+            P->name_last("ladder");
             P->flops += (i64)ladder_executed_flops(la);
             break;
         }
@@ -660,6 +671,7 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
             LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
             P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
             P->tag_last(TAG_LADDER);
+            P->name_last("ladder");
             P->flops += (i64)ladder_executed_flops(la);
             break;
         }
@@ -997,9 +1009,12 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
                 std::fprintf(stderr, "[lrcc] refinement step %d: max rel residual %.3e (krylov %d)\n", it,
                              *std::max_element(rel.begin(), rel.end()), m);
             if (all) break;
-            // FP32 correction solve (A - w) dx = r to inner_tol
+            // FP32 correction solve (A - w) dx = r to inner_tol, or only as far as the
+            // outer tolerance still needs (with a 10x margin) on the last step
+            const double worst = *std::max_element(rel.begin(), rel.end());
+            const double itol = std::max(o.inner_tol, std::min(0.5, 0.1 * o.tol / worst));
             S.zero(dx);
-            gmres(S, r, dx, LRCC_FP32, o.inner_tol, 4 * m, m, V, w, z, true);
+            gmres(S, r, dx, LRCC_FP32, itol, 4 * m, m, V, w, z, true);
             S.axpby(x, dx, std::vector<cd>(R, cd(1.0, 0.0)), 1.0);
         }
     }
@@ -1131,6 +1146,125 @@ void ensure_alpha_programs(lrcc_ctx *c) {
     }
 }
 
+// eta^X = A_X^T lambda + (X_ov, 0) for dipole axis x (caller layout, one vector)
+void eta_vector(lrcc_ctx *c, int x, const Vecs &out, hipStream_t st) {
+    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
+    HIPCHK(c->prex[x]->run(st));
+    Program *p = sigma_program(c, LRCC_FP64, 1, true, 1 + x);
+    c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = out.s; c->io_y2 = out.d; c->io_omega = nullptr;
+    HIPCHK(p->run(st));
+    const void *dx = (const char *)c->dip + (size_t)x * nk * n * n * 16;
+    HIPCHK(axis_slice<double>(dx, c->ubuf, 1, nk, n, 0, no, no, nv, 0, st));
+    HIPCHK(add_inplace<double>(out.s, c->ubuf, (i64)nk * no * nv, st));
+}
+
+// F(., y) = d/de [A(T + e y)^T lambda] + E''(., y): the gradient in x of the
+// bilinear F(x, y) of the response function.  A is cubic in T, so the 5-point
+// derivative is exact; y is in caller layout (per-cell normalisation).  Leaves
+// the device amplitudes shifted: the caller restores them from (T1, T2) and
+// re-runs the amplitude-dependent blocks when all stencils are done.
+void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vecs &q, const void *T1,
+              const void *T2, hipStream_t st) {
+    const int nk = c->nk;
+    const i64 n1 = D.n1, n2 = D.n2;
+    State<double> &S = c->s64;
+    const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+    Program *adj = sigma_program(c, LRCC_FP64, 1, true);
+    const double coef[4] = {1.0, -8.0, 8.0, -1.0};
+    const int shift[4] = {-2, -1, 1, 2};
+    // step: |h y| about 1e-2 in the rms sense
+    cd yy = 0;
+    {
+        SolveCtx N = D;
+        N.R = 1;
+        yy = N.dot(y, y)[0];
+    }
+    const double rms = std::sqrt(std::max(yy.real(), 1e-300) / (double)(n1 + n2 / 4));
+    const double h = 1e-2 / rms;
+    HIPCHK(hipMemsetAsync(Fy.s, 0, n1 * 16, st));
+    HIPCHK(hipMemsetAsync(Fy.d, 0, n2 * 16, st));
+    for (int k = 0; k < 4; ++k) {
+        // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
+        HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        std::vector<cd> a1(1, cd(shift[k] * h, 0.0)), a2(1, cd(shift[k] * h / nk, 0.0));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, a1.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(S.t1.p, y.s, D.alpha, 1.0, 1, nt1, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(S.t2.p, y.d, D.alpha, 1.0, 1, nt2, st));
+        run_precompute(c, false, st);
+        c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
+        HIPCHK(adj->run(st));
+        std::vector<cd> w(1, cd(coef[k] / (12.0 * h), 0.0));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, w.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(Fy.s, q.s, D.alpha, 1.0, 1, n1, st));
+        HIPCHK(batched_axpby(Fy.d, q.d, D.alpha, 1.0, 1, n2, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    // energy part: sum <ij||ab> x_ia y_jb
+    HIPCHK(hipMemcpyAsync(c->ybuf, y.s, n1 * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c->prog_epp->run(st));
+    HIPCHK(add_inplace<double>(Fy.s, c->ubuf, n1, st));
+}
+
+// One-body density of R amplitude-space vectors a (caller layout, per-cell
+// normalisation) with respect to the perturbation operator of Eq. rhs:
+//   D_r[k][p][q] = d <a_r, xi^V> / d V[k][p][q]     (pairing sum a1 xi1 + 1/4 sum a2 xi2)
+// at the amplitudes in (dT1, dT2).  xi^V is linear in V; the program is the
+// transpose of the xi program term by term.  Reads io_x1/io_x2, writes
+// io_y1 = D [R][nk][n][n].
+Program *dens_program(lrcc_ctx *c, int R) {
+    auto it = c->dens.find(R);
+    if (it != c->dens.end()) return it->second.get();
+    const int nk = c->nk, o = c->no, v = c->nv, n = c->n;
+    if (!c->dT1.p) {
+        c->dT1 = alloc_kt<double>(c, c->gmem, "ov");
+        c->dT2 = alloc_kt<double>(c, c->gmem, "oovv");
+    }
+    auto mem = std::make_unique<DevMem>();
+    DevMem &m = *mem;
+    auto P = std::make_unique<Program>();
+    const KT &t1 = c->dT1, &t2 = c->dT2;
+    KT a1 = alloc_kt<double>(c, m, "ov", R), Zb = alloc_kt<double>(c, m, "oovv", R);
+    KT Fb = alloc_kt<double>(c, m, "vv", R), Gb = alloc_kt<double>(c, m, "oo", R), Yb = alloc_kt<double>(c, m, "vv", R);
+    KT Xov = alloc_kt<double>(c, m, "ov", R), Xvv = alloc_kt<double>(c, m, "vv", R), Xoo = alloc_kt<double>(c, m, "oo", R);
+    lrcc_ctx *cc = c;
+    {
+        void *pa = a1.p, *pz = Zb.p;
+        P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, double>(cc->io_x1, pa, R, nk, (i64)o * v, 1.0, s); });
+        // xi2 = Nk P(ij)P(ab) Z and the pairing weight 1/4: Z-bar = (Nk/4) P(ij)P(ab) a2
+        P->ops.push_back([=](hipStream_t s) { return pp_in<double>(cc->io_x2, pz, nk, R, o, v, 0.25 * nk, s); });
+    }
+    // Z = 1/2 t2_ijac Fx_bc - 1/2 t2_ikab Gx_kj
+    contract<double>(*P, Fb, "Rbc", Zb, "Rijab", t2, "ijac", 0.5, false);
+    contract<double>(*P, Gb, "Rkj", Zb, "Rijab", t2, "ikab", -0.5, false);
+    // singles: s1 = t2_ikac X_kc - t1_ic (t1_ka X_kc) + t1_ic X_ac - t1_ka X_ki + X_ai
+    contract<double>(*P, Xov, "Rkc", a1, "Ria", t2, "ikac", 1.0, false);
+    contract<double>(*P, Yb, "Rac", a1, "Ria", t1, "ic", -1.0, false);
+    contract<double>(*P, Xov, "Rkc", Yb, "Rac", t1, "ka", 1.0);
+    // Fx_bc = X_bc - t1_kb X_kc ; Gx_kj = X_kj + t1_jc X_kc
+    contract<double>(*P, Xov, "Rkc", Fb, "Rbc", t1, "kb", -1.0);
+    contract<double>(*P, Xov, "Rkc", Gb, "Rkj", t1, "jc", 1.0);
+    kt_copy<double>(*P, Xvv, Fb);
+    contract<double>(*P, Xvv, "Rac", a1, "Ria", t1, "ic", 1.0);
+    kt_copy<double>(*P, Xoo, Gb);
+    contract<double>(*P, Xoo, "Rki", a1, "Ria", t1, "ka", -1.0);
+    {
+        void *poo = Xoo.p, *pov = Xov.p, *pvv = Xvv.p, *pa = a1.p;
+        P->ops.push_back([=](hipStream_t s) { return axis_scatter(poo, cc->io_y1, R, nk, n, 0, o, 0, o, 0, s); });
+        P->ops.push_back([=](hipStream_t s) { return axis_scatter(pov, cc->io_y1, R, nk, n, 0, o, o, v, 0, s); });
+        P->ops.push_back([=](hipStream_t s) { return axis_scatter(pvv, cc->io_y1, R, nk, n, o, v, o, v, 0, s); });
+        P->ops.push_back([=](hipStream_t s) { return axis_scatter(pa, cc->io_y1, R, nk, n, 0, o, o, v, 1, s); });
+    }
+    Program *raw = P.get();
+    c->dens[R] = std::move(P);
+    c->densmem[R] = std::move(mem);
+    return raw;
+}
+
 void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega, const lrcc_solve_opts &o,
                  lrcc_solve_report &rep) {
     auto t0 = std::chrono::steady_clock::now();
@@ -1139,6 +1273,12 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     ensure_alpha_programs(c);
     if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
     hipStream_t st = c->own_stream;
+    auto phase = [&](const char *what) {
+        if (!verbose()) return;
+        (void)hipStreamSynchronize(st);
+        std::fprintf(stderr, "[lrcc] alpha: %s done at %.2f s\n", what,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    };
     // axes with a non-zero dipole (the paper skips vanishing components, Sec. II.B)
     std::vector<int> axes;
     {
@@ -1154,6 +1294,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     const int nax = (int)axes.size();
     c->axes = axes;
     c->nfreq = nfreq;
+    c->last_omega.assign(omega, omega + nfreq);
     c->alpha.assign((size_t)nfreq * 9 * 2, 0.0);
     rep = lrcc_solve_report{};
     if (nax == 0 || nfreq == 0) return;
@@ -1189,6 +1330,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         if (!r1.converged) throw LrccError(LRCC_E_NOCONV, "lambda equations did not converge");
         c->lam_valid = true;
     }
+    phase("lambda");
     // perturbation vectors and the batched response solve: rhs r = (j*2 + sign)*nax + a
     HIPCHK(c->prog_xi->run(st));
     const int R = nfreq * 2 * nax;
@@ -1220,14 +1362,9 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     std::vector<Vecs> eta(nax);
     for (int a = 0; a < nax; ++a) {
         eta[a] = vec(1);
-        HIPCHK(c->prex[axes[a]]->run(st));
-        Program *p = sigma_program(c, LRCC_FP64, 1, true, 1 + axes[a]);
-        c->io_x1 = lam.s; c->io_x2 = lam.d; c->io_y1 = eta[a].s; c->io_y2 = eta[a].d; c->io_omega = nullptr;
-        HIPCHK(p->run(st));
-        const void *dx = (const char *)c->dip + (size_t)axes[a] * nk * n * n * 16;
-        HIPCHK(axis_slice<double>(dx, c->ubuf, 1, nk, n, 0, no, no, nv, 0, st));
-        HIPCHK(add_inplace<double>(eta[a].s, c->ubuf, n1, st));
+        eta_vector(c, axes[a], eta[a], st);
     }
+    phase("response");
     // eta . t for every axis and solution
     std::vector<cd> et((size_t)nax * R);
     for (int a = 0; a < nax; ++a)
@@ -1241,53 +1378,17 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         HIPCHK(hipMemcpy(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice));
         HIPCHK(hipMemcpy(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice));
         Vecs Fy = vec(1), q = vec(1);
-        Program *adj = sigma_program(c, LRCC_FP64, 1, true);
-        const double coef[4] = {1.0, -8.0, 8.0, -1.0};
-        const int shift[4] = {-2, -1, 1, 2};
         for (int j = 0; j < nfreq; ++j)
             for (int b = 0; b < nax; ++b) {
-                Vecs y = sub(X, (j * 2 + 0) * nax + b);
-                // step: |h y| about 1e-2 in the rms sense
-                cd yy = 0;
-                {
-                    SolveCtx N = D;
-                    N.R = 1;
-                    yy = N.dot(y, y)[0];
-                }
-                const double rms = std::sqrt(std::max(yy.real(), 1e-300) / (double)(n1 + n2 / 4));
-                const double h = 1e-2 / rms;
-                HIPCHK(hipMemset(Fy.s, 0, n1 * 16));
-                HIPCHK(hipMemset(Fy.d, 0, n2 * 16));
-                for (int k = 0; k < 4; ++k) {
-                    // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
-                    HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
-                    HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
-                    std::vector<cd> a1(1, cd(shift[k] * h, 0.0)), a2(1, cd(shift[k] * h / nk, 0.0));
-                    HIPCHK(hipMemcpy(D.alpha, a1.data(), 16, hipMemcpyHostToDevice));
-                    HIPCHK(batched_axpby(S.t1.p, y.s, D.alpha, 1.0, 1, nt1, st));
-                    HIPCHK(hipStreamSynchronize(st));
-                    HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
-                    HIPCHK(batched_axpby(S.t2.p, y.d, D.alpha, 1.0, 1, nt2, st));
-                    run_precompute(c, false, st);
-                    c->io_x1 = lam.s; c->io_x2 = lam.d; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
-                    HIPCHK(adj->run(st));
-                    ++extra_rhs_sig;
-                    std::vector<cd> w(1, cd(coef[k] / (12.0 * h), 0.0));
-                    HIPCHK(hipMemcpy(D.alpha, w.data(), 16, hipMemcpyHostToDevice));
-                    HIPCHK(batched_axpby(Fy.s, q.s, D.alpha, 1.0, 1, n1, st));
-                    HIPCHK(batched_axpby(Fy.d, q.d, D.alpha, 1.0, 1, n2, st));
-                    HIPCHK(hipStreamSynchronize(st));
-                }
-                // energy part: sum <ij||ab> x_ia y_jb
-                HIPCHK(hipMemcpyAsync(c->ybuf, y.s, n1 * 16, hipMemcpyDeviceToDevice, st));
-                HIPCHK(c->prog_epp->run(st));
-                HIPCHK(add_inplace<double>(Fy.s, c->ubuf, n1, st));
+                f_vector(c, D, sub(X, (j * 2 + 0) * nax + b), Fy, q, T1, T2, st);
+                extra_rhs_sig += 4;
                 for (int a = 0; a < nax; ++a) Fv[((size_t)j * nax + a) * nax + b] = bdot(Fy, sub(X, (j * 2 + 1) * nax + a));
             }
         HIPCHK(hipMemcpy(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice));
         HIPCHK(hipMemcpy(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice));
         run_precompute(c, true, st);
     }
+    phase("eta and F");
     // assemble alpha
     auto rid = [&](int j, int sg, int a) { return (j * 2 + sg) * nax + a; };
     for (int j = 0; j < nfreq; ++j)
@@ -1311,6 +1412,146 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+
+// ---------------------------------------------------------------- dipole gradient of alpha
+// alpha_XY(w) = -1/(2 Nk) [g(w) + conj(g(-w))],
+//   g(w) = eta^X t^Y(w) + eta^Y t^X(-w) + F(t^X(-w), t^Y(w)),  t^Z(w) = -(A - w)^-1 xi^Z.
+// It is bilinear in (mu_X, mu_Y) at fixed amplitudes and lambda.  Along a
+// perturbation V of mu_X, with a = (A + w)^-T (eta^Y + F(., t^Y(w))):
+//   d g(w) = eta^V t^Y(w) - <a, xi^V>,
+// and symmetrically for mu_Y and for g(-w).  <a, xi^V> and eta^V t are linear
+// in V: the density program gives them as one-body densities (eta^V t =
+// d/de <lambda, xi^V(T + e t)> + V_ov t1, the derivative exact by central
+// difference since xi is quadratic in T).  The conjugated g(-w) contributes
+// conj(G[k][q][p]) for Hermitian V.
+void alpha_dip_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, double *out) {
+    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    const auto &axes = c->axes;
+    const int nax = (int)axes.size();
+    if (j < 0 || j >= c->nfreq || (int)c->last_omega.size() != c->nfreq)
+        throw LrccError(LRCC_E_ARG, "frequency index out of range of the last solve");
+    const int ax = (int)(std::find(axes.begin(), axes.end(), X) - axes.begin());
+    const int ay = (int)(std::find(axes.begin(), axes.end(), Y) - axes.begin());
+    if (ax >= nax || ay >= nax) throw LrccError(LRCC_E_ARG, "axis not solved in the last solve (zero dipole or masked)");
+    if (!c->lam_valid || !c->sol1 || c->nrhs_sol != c->nfreq * 2 * nax)
+        throw LrccError(LRCC_E_STATE, "lrcc_solve must precede the gradient");
+    hipStream_t st = c->own_stream;
+    const double w = c->last_omega[j];
+    DevMem tmp;
+    auto vec = [&](int R) { Vecs v; v.s = tmp.get((size_t)R * n1 * 16); v.d = tmp.get((size_t)R * n2 * 16); return v; };
+    auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
+    Vecs sol{c->sol1, c->sol2};
+    auto tsol = [&](int sg, int a) { return sub(sol, (j * 2 + sg) * nax + a); };  // sg 0: +w, 1: -w
+    SolveCtx D;
+    D.c = c; D.R = 1; D.n1 = n1; D.n2 = n2; D.st = st;
+    D.part = tmp.get((size_t)dot_blocks(n2) * 16 * 2);
+    D.dout = tmp.get(32);
+    D.alpha = tmp.get(32);
+    // the four adjoint right-hand sides (two when X == Y): slot, vector t, eta axis, solve frequency
+    //   0: mu_X in g(w):  eta^Y + F(., t^Y(w)),   (A + w)^T       uses eta^V t^Y(w)
+    //   1: mu_X in g(-w): eta^Y + F(., t^Y(-w)),  (A - w)^T       uses eta^V t^Y(-w)
+    //   2: mu_Y in g(w):  eta^X + F(., t^X(-w)),  (A - w)^T       uses eta^V t^X(-w)
+    //   3: mu_Y in g(-w): eta^X + F(., t^X(w)),   (A + w)^T       uses eta^V t^X(w)
+    const bool same = X == Y;
+    const int nb = same ? 2 : 4;
+    Vecs tv[4] = {tsol(0, ay), tsol(1, ay), tsol(1, ax), tsol(0, ax)};
+    const int eta_ax[4] = {Y, Y, X, X};
+    const double wsolve[4] = {-w, w, w, -w};
+    Vecs B = vec(nb), A = vec(nb);
+    {
+        Vecs etaY = vec(1), etaX = same ? etaY : vec(1);
+        eta_vector(c, Y, etaY, st);
+        if (!same) eta_vector(c, X, etaX, st);
+        State<double> &S = c->s64;
+        const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+        void *T1 = tmp.get(nt1 * 16), *T2 = tmp.get(nt2 * 16);
+        HIPCHK(hipMemcpyAsync(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        Vecs q = vec(1);
+        for (int b = 0; b < nb; ++b) {
+            Vecs bb = sub(B, b);
+            f_vector(c, D, tv[b], bb, q, T1, T2, st);
+            HIPCHK(add_inplace<double>(bb.s, (eta_ax[b] == Y ? etaY : etaX).s, n1, st));
+            HIPCHK(add_inplace<double>(bb.d, (eta_ax[b] == Y ? etaY : etaX).d, n2, st));
+        }
+        HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        run_precompute(c, true, st);
+    }
+    void *dom = tmp.get((size_t)nb * 8);
+    HIPCHK(hipMemcpy(dom, wsolve, nb * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(A.s, 0, (size_t)nb * n1 * 16));
+    HIPCHK(hipMemset(A.d, 0, (size_t)nb * n2 * 16));
+    lrcc_solve_report r{};
+    solve_response(c, nb, (const double *)dom, B, A, o, r, st, true);
+    if (!r.converged) throw LrccError(LRCC_E_NOCONV, "adjoint response equations did not converge");
+    // densities: D_xi of the adjoint vectors at T, D_eta of the response vectors
+    State<double> &S = c->s64;
+    const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+    const size_t nd = (size_t)nk * n * n;
+    void *dd = tmp.get((size_t)nb * nd * 16);
+    Program *dn = dens_program(c, nb), *d1 = dens_program(c, 1);   // (allocate dT1, dT2 on first use)
+    HIPCHK(hipMemcpyAsync(c->dT1.p, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->dT2.p, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+    c->io_x1 = A.s; c->io_x2 = A.d; c->io_y1 = dd;
+    HIPCHK(dn->run(st));
+    std::vector<cd> Dxi((size_t)nb * nd), Deta((size_t)nb * nd, 0.0), tmpd(nd);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(Dxi.data(), dd, Dxi.size() * 16, hipMemcpyDeviceToHost));
+    std::vector<cd> t1h((size_t)n1);
+    for (int b = 0; b < nb; ++b) {
+        const Vecs &t = tv[b];
+        cd yy = 0;
+        {
+            SolveCtx N = D;
+            N.R = 1;
+            yy = N.dot(t, t)[0];
+        }
+        const double rms = std::sqrt(std::max(yy.real(), 1e-300) / (double)(n1 + n2 / 4));
+        const double h = 1e-2 / rms;
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            HIPCHK(hipMemcpyAsync(c->dT1.p, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(c->dT2.p, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+            std::vector<cd> a1(1, cd(sgn * h, 0.0)), a2(1, cd(sgn * h / nk, 0.0));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(D.alpha, a1.data(), 16, hipMemcpyHostToDevice));
+            HIPCHK(batched_axpby(c->dT1.p, t.s, D.alpha, 1.0, 1, nt1, st));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
+            HIPCHK(batched_axpby(c->dT2.p, t.d, D.alpha, 1.0, 1, nt2, st));
+            c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = dd;
+            HIPCHK(d1->run(st));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(tmpd.data(), dd, nd * 16, hipMemcpyDeviceToHost));
+            for (size_t e = 0; e < nd; ++e) Deta[(size_t)b * nd + e] += (sgn / (2.0 * h)) * tmpd[e];
+        }
+        // (V_ov, 0) part of eta: + V[k][i][o+a] t1[k][i][a]
+        HIPCHK(hipMemcpy(t1h.data(), t.s, n1 * 16, hipMemcpyDeviceToHost));
+        for (int k = 0; k < nk; ++k)
+            for (int i = 0; i < no; ++i)
+                for (int a = 0; a < nv; ++a)
+                    Deta[(size_t)b * nd + ((size_t)k * n + i) * n + no + a] += t1h[((size_t)k * no + i) * nv + a];
+    }
+    // assemble: grad[Z][k][p][q] = -1/(2Nk) (G+[k][p][q] + conj(G-[k][q][p])), G = D_eta - D_xi
+    std::vector<cd> g((size_t)3 * nd, 0.0);
+    auto G = [&](int b, int k, int p, int qq) {
+        const size_t e = (size_t)b * nd + ((size_t)k * n + p) * n + qq;
+        return Deta[e] - Dxi[e];
+    };
+    const int slot_ax[2] = {X, Y};
+    for (int sl = 0; sl < 2; ++sl) {
+        // slot 0 (mu_X): vectors 0 (g(w)) and 1 (g(-w)); slot 1 (mu_Y): 2 and 3, or 1 and 0 when X == Y
+        const int bp = sl == 0 ? 0 : (same ? 1 : 2), bm = sl == 0 ? 1 : (same ? 0 : 3);
+        for (int k = 0; k < nk; ++k)
+            for (int p = 0; p < n; ++p)
+                for (int qq = 0; qq < n; ++qq)
+                    g[(size_t)slot_ax[sl] * nd + ((size_t)k * n + p) * n + qq] +=
+                        -0.5 / nk * (G(bp, k, p, qq) + std::conj(G(bm, k, qq, p)));
+    }
+    std::memcpy(out, g.data(), g.size() * 16);
+}
 
 // ---------------------------------------------------------------- ground-state CCSD
 // The CCSD residual is a quartic polynomial in T, so with A the Jacobian
@@ -1660,6 +1901,35 @@ lrcc_status lrcc_apply_sigma_adjoint_dev(lrcc_ctx *c, int nrhs, const double *om
     });
 }
 
+lrcc_status lrcc_sigma_vjp_dev(lrcc_ctx *c, int nrhs, const double *omega, const void *g1, const void *g2,
+                               void *gx1, void *gx2, int precision, void *stream) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nrhs < 1 || !g1 || !g2 || !gx1 || !gx2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
+        if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        const int nk = c->nk, o = c->no, v = c->nv;
+        const i64 n1 = (i64)nrhs * nk * o * v, n2 = (i64)nrhs * nk * nk * nk * o * o * v * v;
+        const size_t need = (size_t)(2 * n1 + 2 * n2) * 16;
+        if (need > c->vjp_bytes) {
+            c->vjpmem.release();
+            c->vj1 = c->vjpmem.get(n1 * 16); c->vj2 = c->vjpmem.get(n2 * 16);
+            c->vw1 = c->vjpmem.get(n1 * 16); c->vw2 = c->vjpmem.get(n2 * 16);
+            c->vjp_bytes = need;
+        }
+        hipStream_t st = (hipStream_t)stream;
+        // z = (conj g1, P conj g2): the cotangent restricted to antisymmetric doubles, in the
+        // pairing sum z1 y1 + 1/4 sum z2 y2 of the transpose product
+        HIPCHK(conj_scale(c->vj1, g1, 1.0, n1, st));
+        HIPCHK(antisym(g2, c->vj2, nrhs, nk, o, v, 1.0, 1, st));
+        Program *p = sigma_program(c, precision, nrhs, true);
+        c->io_x1 = c->vj1; c->io_x2 = c->vj2; c->io_y1 = c->vw1; c->io_y2 = c->vw2; c->io_omega = omega;
+        HIPCHK(run_sigma(c, p, st));
+        // back to the Euclidean pairing over full arrays, projected on antisymmetric doubles
+        HIPCHK(conj_scale(gx1, c->vw1, 1.0, n1, st));
+        HIPCHK(antisym(c->vw2, gx2, nrhs, nk, o, v, 1.0 / 16.0, 1, st));
+    });
+}
+
 static lrcc_status apply_host(lrcc_ctx *c, int nrhs, const double *omega, const double *x1, const double *x2,
                               double *y1, double *y2, int precision, bool adjoint);
 
@@ -1794,6 +2064,18 @@ lrcc_status lrcc_solve_ccsd(lrcc_ctx *c, double tol, int max_iter, double *t1, d
     });
 }
 
+lrcc_status lrcc_alpha_dipole_gradient(lrcc_ctx *c, int ifreq, int x, int y, const lrcc_solve_opts *opts,
+                                       double *grad) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!grad || x < 0 || x > 2 || y < 0 || y > 2) throw LrccError(LRCC_E_ARG, "invalid axis or null pointer");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        alpha_dip_grad(c, ifreq, x, y, o, grad);
+    });
+}
+
 lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {
     return guarded(c, [&] {
         if (!alpha) throw LrccError(LRCC_E_ARG, "null output");
@@ -1876,6 +2158,8 @@ lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char
         (void)sigma_program(&c, LRCC_FP64, 1, true);
         ensure_alpha_programs(&c);
         for (int x = 0; x < 3; ++x) (void)sigma_program(&c, LRCC_FP64, 1, true, 1 + x);
+        (void)dens_program(&c, 1);
+        (void)dens_program(&c, 4);
     } catch (LrccError &e) {
         st = (lrcc_status)e.code;
         if (msg && msglen > 0) snprintf(msg, msglen, "%s", e.what());

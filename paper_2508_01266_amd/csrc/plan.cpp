@@ -86,8 +86,21 @@ hipError_t Program::run(hipStream_t s, Profiler *prof) {
         hipError_t e = hipEventRecord(p0, s);
         if (e != hipSuccess) return e;
     }
+    // LRCC_OP_TIMES: time every op of a profiled run and print one line per op
+    static const bool per_op = std::getenv("LRCC_OP_TIMES") != nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> opev;
+    if (timed && per_op) names.resize(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) {
         hipEvent_t a = nullptr, b = nullptr;
+        if (timed && per_op) {
+            hipEvent_t x = prof->ev(), y = prof->ev();
+            opev.push_back({x, y});
+            (void)hipEventRecord(x, s);
+            hipError_t e = ops[i](s);
+            if (e != hipSuccess) return e;
+            (void)hipEventRecord(y, s);
+            continue;
+        }
         if (timed && tags[i] != TAG_NONE) {
             a = prof->ev();
             b = prof->ev();
@@ -106,6 +119,16 @@ hipError_t Program::run(hipStream_t s, Profiler *prof) {
         hipError_t e = hipEventRecord(p1, s);
         if (e != hipSuccess) return e;
         prof->record(TAG_PROGRAM, p0, p1);
+    }
+    if (!opev.empty()) {
+        (void)hipEventSynchronize(opev.back().second);
+        for (size_t i = 0; i < opev.size(); ++i) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, opev[i].first, opev[i].second);
+            std::fprintf(stderr, "[lrcc-op] %4zu %10.3f ms  %s\n", i, ms, names[i].c_str());
+            prof->pool.push_back(opev[i].first);
+            prof->pool.push_back(opev[i].second);
+        }
     }
     return hipSuccess;
 }
@@ -411,6 +434,10 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
                      what.c_str(), g.M, g.N, g.K, offC.size(), segA.size(), 8.0 * g.M * g.N * g.K * segA.size(), pad);
     }
     raw_gemm<T>(P, g, offC, segBeg, segA, segB, A.count(), B.count(), C.count());
+    char nm[160];
+    std::snprintf(nm, sizeof nm, "gemm %s M=%d N=%d K=%d jobs=%zu segs=%zu", what.c_str(), g.M, g.N, g.K,
+                  offC.size(), segA.size());
+    P.name_last(nm);
 }
 
 template void contract<double>(Program &, const KT &, const std::string &, const KT &, const std::string &,

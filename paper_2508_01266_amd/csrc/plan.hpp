@@ -70,6 +70,11 @@ struct Tunable {
 struct Program {
     std::vector<std::function<hipError_t(hipStream_t)>> ops;
     std::vector<int> tags;  // per op (TAG_NONE unless set by tag_last)
+    std::vector<std::string> names;  // per op, for the per-op timing report
+    void name_last(const std::string &n) {
+        names.resize(ops.size());
+        names.back() = n;
+    }
     std::vector<Tunable> tunables;
     bool tuned = false;
     std::string tune_key;

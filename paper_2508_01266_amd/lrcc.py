@@ -41,6 +41,7 @@ def lib():
         L.lrcc_apply_sigma_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_apply_sigma_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
         L.lrcc_apply_sigma_adjoint_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
+        L.lrcc_sigma_vjp_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_set_profiling.argtypes = [vp, i]
         L.lrcc_set_graphs.argtypes = [vp, i]
         L.lrcc_set_autotune.argtypes = [vp, i]
@@ -60,6 +61,8 @@ def lib():
         L.lrcc_solve_response_dev.restype = ctypes.c_int
         L.lrcc_solve.argtypes = [vp, ctypes.c_uint, i, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport)]
         L.lrcc_get_alpha.argtypes = [vp, i, vp]
+        L.lrcc_alpha_dipole_gradient.argtypes = [vp, i, i, i, ctypes.POINTER(SolveOpts), vp]
+        L.lrcc_alpha_dipole_gradient.restype = ctypes.c_int
         L.lrcc_solve_ccsd.argtypes = [vp, ctypes.c_double, i, vp, vp, dp, ctypes.POINTER(SolveReport)]
         L.lrcc_solve_ccsd.restype = ctypes.c_int
         L.lrcc_get_solution.argtypes = [vp, i, i, i, vp, vp]
@@ -204,6 +207,16 @@ class Context:
         self._check(self._L.lrcc_get_alpha(self._h, len(om), _ptr(alpha)))
         return alpha, rep.as_dict()
 
+    def alpha_dipole_gradient(self, ifreq, x, y, **opts):
+        """d alpha_xy(omega_ifreq) / d mu: complex [3][nk][n][n] such that the change of
+        alpha_xy under Hermitian dipole perturbations dmu is sum(grad * dmu).  Needs a
+        preceding solve() that included axes x and y."""
+        oo = self.solve_options(**opts)
+        g = np.zeros((3, self.nk, self.n, self.n), dtype=np.complex128)
+        self._check(self._L.lrcc_alpha_dipole_gradient(self._h, int(ifreq), int(x), int(y), ctypes.byref(oo),
+                                                       _ptr(g)))
+        return g
+
     def solve_ccsd(self, tol=1e-9, max_iter=200):
         """Ground-state CCSD on the device; the result becomes the context's amplitudes.
         Returns (t1, t2, energy per cell, report)."""
@@ -259,5 +272,16 @@ class Context:
             self._h, R, None if omega is None else ctypes.c_void_p(omega.data_ptr()),
             ctypes.c_void_p(x1.data_ptr()), ctypes.c_void_p(x2.data_ptr()),
             ctypes.c_void_p(y1.data_ptr()), ctypes.c_void_p(y2.data_ptr()), int(precision),
+            None if stream is None else ctypes.c_void_p(stream))
+        self._check(st)
+
+    def sigma_vjp_dev(self, g1, g2, gx1, gx2, omega=None, precision=FP64, stream=None):
+        """Device-pointer vector-Jacobian product of the sigma (complex128 torch tensors,
+        caller layouts): gx = conj((A - omega)^T conj(g)) on antisymmetric doubles."""
+        R = g1.shape[0]
+        st = self._L.lrcc_sigma_vjp_dev(
+            self._h, R, None if omega is None else ctypes.c_void_p(omega.data_ptr()),
+            ctypes.c_void_p(g1.data_ptr()), ctypes.c_void_p(g2.data_ptr()),
+            ctypes.c_void_p(gx1.data_ptr()), ctypes.c_void_p(gx2.data_ptr()), int(precision),
             None if stream is None else ctypes.c_void_p(stream))
         self._check(st)
