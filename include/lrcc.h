@@ -133,6 +133,16 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
 lrcc_status lrcc_set_profiling(lrcc_ctx *ctx, int enable);
 lrcc_status lrcc_read_profile(lrcc_ctx *ctx, double *ms, long long *count);
 
+/* How the ladder term (the vvvv contraction of Eq. tx2) obtains its integrals:
+ * 0 = automatic (stored when they take at most a quarter of the free device
+ * memory, per precision), 1 = rebuilt in LDS from the t1-dressed Cholesky
+ * vectors inside the ladder kernel (nothing of vvvv size in memory), 2 = stored.
+ * Stored blocks: the antisymmetrised integrals for the unique momentum pairs,
+ * about Nk^3/4 blocks of nvir^4 complex values, rebuilt with the other
+ * amplitude-dependent blocks.  Must precede the first lrcc_set_amplitudes or
+ * lrcc_solve_ccsd (LRCC_E_STATE afterwards); LRCC_E_ARG for other modes. */
+lrcc_status lrcc_set_ladder_mode(lrcc_ctx *ctx, int mode);
+
 /* Autotuning of launch variants: when enabled, the first application of each
  * sigma program (per problem size, nrhs, precision and direction) is run once
  * per candidate configuration (matrix-core GEMM tiles 64x64 or large; ladder
@@ -153,6 +163,12 @@ lrcc_status lrcc_set_graphs(lrcc_ctx *ctx, int enable);
  * right-hand sides (matrix-core GEMMs and ladder, including the in-LDS
  * integral rebuild; streaming kernels excluded). */
 lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
+
+/* Real floating-point operations executed by the ladder launch of one sigma
+ * application (the profiling category 1 of lrcc_read_profile): the matrix-core
+ * product over the unique momentum/index pairs when the integrals are stored,
+ * or the ladder kernel's products including its in-LDS rebuild. */
+lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
 
 /* Host-only validation of the launch plans for a problem size: records every
  * kernel of lrcc_set_hamiltonian, lrcc_set_amplitudes and lrcc_apply_sigma (FP64

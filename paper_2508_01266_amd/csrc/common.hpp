@@ -44,13 +44,24 @@ struct GemmArgs {
     Split sm, sn, sk;
     Strides Am, Ak, Bk, Bn, Cm, Cn;
     int aMfast, bNfast;  // tile-load thread maps: 1 = run along m (resp. n)
-    int shape;           // tile shape: -1 automatic, 0 = 64x64, 1 = large (128x128 complex64, 128x64 complex128)
+    int shape;           // tile shape: -1 automatic, 0 = 64x64, 1 = large (128x128 complex64, 128x64
+                         // complex128), 2 = 16x256 (small M)
+    int alt;             // autotuner candidate: 0 = heuristic shape, 1 = the alternative shape
     double alpha_re, alpha_im;
     int beta;
     const i64 *offC;
     const int *segBeg;   // njobs + 1
     const i64 *segA, *segB;
     int njobs;
+    int job0;            // index of the first job of this launch in the full job list
+    int njobs_all;       // length of the full job list
+    // split-K: ksplit > 1 partitions each job's (segment, K) steps into ksplit ranges; each writes its
+    // partial product to part[split][job][M][N] (dense) and a second kernel sums the ranges in order
+    // and applies alpha/beta (deterministic, no atomics)
+    int ksplit;
+    void *part;
+    const float *jscale; // per-job multiplier of alpha (full job list), or null
+    int kind;            // 0 generic, 1 stored-integral ladder (a separate kernel symbol for profiling)
 };
 
 template <typename T>

@@ -31,7 +31,7 @@ template <> struct Mfma<float> {
 
 constexpr int TK = 16, NT = 256;
 
-template <typename T, int TM, int TN, int WTM, int WTN>
+template <typename T, int TM, int TN, int WTM, int WTN, int KIND>
 __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     typedef typename Cx<T>::type C2;
     typedef typename Mfma<T>::v4 v4;
@@ -39,9 +39,13 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     constexpr int FM = WTM / 16, FN = WTN / 16;
     constexpr int LA = TM * TK / NT, LB = TK * TN / NT;
     static_assert((TM / WTM) * (TN / WTN) == 4, "4 waves per block");
-    __shared__ T Ar[TK][TM], Ai[TK][TM], Br[TK][TN], Bi[TK][TN];
+    // rows padded so that K-fast tile stores (16 lanes along K) and the MFMA operand
+    // reads (4 K rows x 16 lanes) fall into distinct LDS banks
+    constexpr int PAD = sizeof(T) == 8 ? 9 : 17;
+    __shared__ T Ar[TK][TM + PAD], Ai[TK][TM + PAD], Br[TK][TN + PAD], Bi[TK][TN + PAD];
 
     const int job = blockIdx.y;
+    const int split = blockIdx.z;
     const int tilesM = (g.M + TM - 1) / TM;
     const int m0 = (blockIdx.x % tilesM) * TM;
     const int n0 = (blockIdx.x / tilesM) * TN;
@@ -82,7 +86,8 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
 
     const int sb = g.segBeg[job], se = g.segBeg[job + 1];
     const int ksteps = (g.K + TK - 1) / TK;
-    const int total = (se - sb) * ksteps;
+    const i64 nsteps = (i64)(se - sb) * ksteps;
+    const int tbeg = (int)(nsteps * split / g.ksplit), tend = (int)(nsteps * (split + 1) / g.ksplit);
     // software pipeline: the global loads of step t+1 are issued into registers
     // before the matrix-core work of step t
     C2 va[LA], vb[LB];
@@ -103,14 +108,14 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
             else { vb[q].x = 0; vb[q].y = 0; }
         }
     };
-    if (total > 0) fetch(0);
-    for (int t = 0; t < total; ++t) {
+    if (tbeg < tend) fetch(tbeg);
+    for (int t = tbeg; t < tend; ++t) {
 #pragma unroll
         for (int q = 0; q < LA; ++q) { Ar[ak[q]][am[q]] = va[q].x; Ai[ak[q]][am[q]] = va[q].y; }
 #pragma unroll
         for (int q = 0; q < LB; ++q) { Br[bk[q]][bn[q]] = vb[q].x; Bi[bk[q]][bn[q]] = vb[q].y; }
         __syncthreads();
-        if (t + 1 < total) fetch(t + 1);
+        if (t + 1 < tend) fetch(t + 1);
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
             const int kr = kk + (lane >> 4), c = lane & 15;
@@ -132,7 +137,26 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
         __syncthreads();
     }
 
-    const T alr = (T)g.alpha_re, ali = (T)g.alpha_im;
+    if (g.ksplit > 1) {
+        // raw partial sums, reduced by k_gemm_reduce
+        C2 *Pj = reinterpret_cast<C2 *>(g.part) + ((i64)split * g.njobs_all + g.job0 + job) * g.M * g.N;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gm = m0 + wm + 16 * i + Mfma<T>::row(lane, r);
+                    const int gn = n0 + wn + 16 * j + (lane & 15);
+                    if (gm < g.M && gn < g.N) {
+                        C2 w; w.x = accr[i][j][r]; w.y = acci[i][j][r];
+                        Pj[(i64)gm * g.N + gn] = w;
+                    }
+                }
+        return;
+    }
+    const T js = g.jscale ? (T)g.jscale[g.job0 + job] : (T)1;
+    const T alr = js * (T)g.alpha_re, ali = js * (T)g.alpha_im;
     C2 *Cj = C + g.offC[job];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -162,30 +186,70 @@ hipError_t launch_shape(const GemmArgs &g, hipStream_t s) {
         c.njobs = (g.njobs - j0 < 65535) ? g.njobs - j0 : 65535;
         c.offC = g.offC + j0;
         c.segBeg = g.segBeg + j0;
-        dim3 grid(tilesM * tilesN, c.njobs);
-        hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN>), grid, dim3(NT), 0, s, c);
+        c.job0 = j0;
+        dim3 grid(tilesM * tilesN, c.njobs, g.ksplit);
+        if (g.kind == 1) hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 1>), grid, dim3(NT), 0, s, c);
+        else hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 0>), grid, dim3(NT), 0, s, c);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// C[job](m, n) = alpha * sum_split part[split][job][m][n] (+ C), splits summed in order
+template <typename T>
+__global__ void k_gemm_reduce(GemmArgs g) {
+    typedef typename Cx<T>::type C2;
+    const C2 *P = reinterpret_cast<const C2 *>(g.part);
+    C2 *C = reinterpret_cast<C2 *>(g.C);
+    const i64 per = (i64)g.M * g.N, n = (i64)g.njobs * per;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        const int job = (int)(t / per);
+        const T js = g.jscale ? (T)g.jscale[job] : (T)1;
+        const T alr = js * (T)g.alpha_re, ali = js * (T)g.alpha_im;
+        const int gm = (int)((t % per) / g.N), gn = (int)(t % g.N);
+        T xr = 0, xi = 0;
+        for (int z = 0; z < g.ksplit; ++z) {
+            const C2 v = P[(i64)z * n + t];
+            xr += v.x;
+            xi += v.y;
+        }
+        T vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
+        const i64 off = g.offC[job] + split_off(gm, g.sm, g.Cm) + split_off(gn, g.sn, g.Cn);
+        if (g.beta) { C2 o = C[off]; vr += o.x; vi += o.y; }
+        C2 w; w.x = vr; w.y = vi;
+        C[off] = w;
+    }
+}
+
 int gemm_shape(const GemmArgs &g, bool fp64) {
     if (g.shape >= 0) return g.shape;
-    if (g.M >= 128 && g.N >= 128) return 1;
-    if (fp64 && g.M >= 128 && g.N >= 64) return 1;
-    return 0;
+    int h = 0;
+    if (g.M <= 16 && g.N >= 128) h = 2;
+    else if (g.M >= 128 && g.N >= 128) h = 1;
+    else if (fp64 && g.M >= 128 && g.N >= 64) h = 1;
+    if (!g.alt) return h;
+    return h == 0 ? (g.M <= 16 ? 2 : 1) : 0;
 }
 
 template <typename T>
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.njobs <= 0 || g.M <= 0 || g.N <= 0) return hipSuccess;
     constexpr bool f64 = sizeof(T) == 8;
-    if (gemm_shape(g, f64) == 1) {
-        if constexpr (f64) return launch_shape<T, 128, 64, 64, 32>(g, s);
-        else return launch_shape<T, 128, 128, 64, 64>(g, s);
+    hipError_t e;
+    switch (gemm_shape(g, f64)) {
+    case 1:
+        if constexpr (f64) e = launch_shape<T, 128, 64, 64, 32>(g, s);
+        else e = launch_shape<T, 128, 128, 64, 64>(g, s);
+        break;
+    case 2: e = launch_shape<T, 16, 256, 16, 64>(g, s); break;
+    default: e = launch_shape<T, 64, 64, 32, 32>(g, s); break;
     }
-    return launch_shape<T, 64, 64, 32, 32>(g, s);
+    if (e != hipSuccess || g.ksplit <= 1) return e;
+    const i64 n = (i64)g.njobs * g.M * g.N;
+    const unsigned blocks = (unsigned)std::min<i64>((n + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_gemm_reduce<T>, dim3(blocks), dim3(256), 0, s, g);
+    return hipGetLastError();
 }
 
 template hipError_t launch_gemm<double>(const GemmArgs &, hipStream_t);

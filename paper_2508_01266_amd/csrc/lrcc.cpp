@@ -66,6 +66,7 @@ struct State {
     void *La = nullptr, *Lb = nullptr;      // dressed virtual Cholesky slices (ladder)
     void *LaT = nullptr, *LbT = nullptr;    // pair-transposed copies (adjoint ladder)
     void *d_o1 = nullptr, *d_v1 = nullptr, *d_o2 = nullptr, *d_v2 = nullptr;  // preconditioner diagonals
+    void *Wst = nullptr;                    // stored antisymmetrised ladder integrals (null: rebuild in LDS)
     bool ready = false;
 };
 
@@ -99,6 +100,9 @@ struct lrcc_ctx {
     Profiler prof;
     bool use_graphs = false;
     bool pack_ladder = true;                   // antisymmetry-packed forward ladder for large batches
+    int ladder_mode = 0;                       // 0 auto, 1 rebuild integrals in LDS, 2 stored integral blocks
+    std::vector<int> wslot;                    // (ka, kb, ke) -> slot of the stored blocks, -1 if not stored
+    int nwslot = 0;
     bool autotune = false;
     hipStream_t own_stream = nullptr;          // non-null stream for solver work (graph capture)
     std::unique_ptr<Program> pre64, pre32;     // amplitude-dependent blocks (f64) and their f32 copies
@@ -252,6 +256,94 @@ void build_dressing(lrcc_ctx *c, Program &P, void *slice_src, void *out, const v
                      (i64)nk * nk * naux * v * v);
 }
 
+// Stored ladder integrals.  For the unique momentum pairs ka <= kb (output) and
+// ke <= kf (input; kb, kf implied by ka + kb = ke + kf):
+//   W'(ka,kb,ke)[e][f][a][b] = s (K(ka,ke,kb,kf)[a][e][b][f] - K(ka,kf,kb,ke)[a][f][b][e]),
+//   K(k1,k2,k3,k4)[a][e][b][f] = sum_Q La[k1][k2][Q][a][e] Lb[k3][k4][Q][b][f],
+// with s = 1/2 when ke == kf and 1 otherwise, so that for Y antisymmetric in
+// (e,f) the ladder of every output block is sum over ke <= kf of Y(ke) W'.
+void ladder_slots(lrcc_ctx *c) {
+    const int nk = c->nk;
+    c->wslot.assign((size_t)nk * nk * nk, -1);
+    int n = 0;
+    for (int ka = 0; ka < nk; ++ka)
+        for (int kb = ka; kb < nk; ++kb)
+            for (int ke = 0; ke < nk; ++ke) {
+                const int kf = ((ka + kb - ke) % nk + nk) % nk;
+                if (ke <= kf) c->wslot[((size_t)ka * nk + kb) * nk + ke] = n++;
+            }
+    c->nwslot = n;
+}
+
+template <typename T>
+void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void *W) {
+    const int nk = c->nk, v = c->nv, naux = c->naux;
+    const i64 vv = (i64)v * v, v4 = vv * vv, lsz = (i64)nk * nk * naux * vv;
+    for (int part = 0; part < 2; ++part) {
+        GemmArgs g{};
+        g.shape = -1;
+        g.A = La;
+        g.B = Lb;
+        g.C = W;
+        g.M = (int)vv;
+        g.N = (int)vv;
+        g.K = naux;
+        g.sk = Split{1, naux};
+        g.Ak = Strides{{0, 0, vv}};
+        g.Bk = Strides{{0, 0, vv}};
+        g.sm = Split{v, v};
+        g.sn = Split{v, v};
+        if (part == 0) {
+            // rows (a, e), columns (f, b):  + La(ka,ke)[a][e] Lb(kb,kf)[b][f]
+            g.Am = Strides{{0, v, 1}};
+            g.Cm = Strides{{0, v, vv * v}};
+            g.Bn = Strides{{0, 1, v}};
+            g.Cn = Strides{{0, vv, 1}};
+            g.alpha_re = 1.0;
+            g.beta = 0;
+        } else {
+            // rows (a, f), columns (e, b):  - La(ka,kf)[a][f] Lb(kb,ke)[b][e]
+            g.Am = Strides{{0, v, 1}};
+            g.Cm = Strides{{0, v, vv}};
+            g.Bn = Strides{{0, 1, v}};
+            g.Cn = Strides{{0, vv * v, 1}};
+            g.alpha_re = -1.0;
+            g.beta = 1;
+        }
+        g.aMfast = 1;
+        g.bNfast = 1;
+        std::vector<i64> offC, segA, segB;
+        std::vector<int> beg{0};
+        std::vector<float> js;
+        for (int ka = 0; ka < nk; ++ka)
+            for (int kb = ka; kb < nk; ++kb)
+                for (int ke = 0; ke < nk; ++ke) {
+                    const int kf = ((ka + kb - ke) % nk + nk) % nk;
+                    const int sl = c->wslot[((size_t)ka * nk + kb) * nk + ke];
+                    if (sl < 0) continue;
+                    offC.push_back(sl * v4);
+                    const int k2 = part == 0 ? ke : kf, k4 = part == 0 ? kf : ke;
+                    segA.push_back(((i64)ka * nk + k2) * naux * vv);
+                    segB.push_back(((i64)kb * nk + k4) * naux * vv);
+                    beg.push_back((int)segA.size());
+                    js.push_back(ke == kf ? 0.5f : 1.0f);
+                }
+        raw_gemm<T>(P, g, offC, beg, segA, segB, lsz, lsz, (i64)c->nwslot * v4, js);
+        P.name_last(part == 0 ? "ladder integrals (direct)" : "ladder integrals (exchange)");
+    }
+}
+
+// Decide, per precision, whether the ladder integrals are stored: forced by
+// ladder_mode, else stored when they take at most a quarter of the free memory.
+bool store_ladder(lrcc_ctx *c, size_t elem_bytes, size_t also) {
+    if (c->ladder_mode == 1) return false;
+    if (c->ladder_mode == 2 || g_dry_run) return true;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+    const size_t bytes = (size_t)c->nwslot * c->nv * c->nv * c->nv * c->nv * elem_bytes;
+    return bytes + also <= fr / 4;
+}
+
 template <typename T>
 void convert_kt(Program &P, State<float> &dst_state, KT &dst, const KT &src, lrcc_ctx *c) {
     dst = src;
@@ -376,6 +468,12 @@ void build_state(lrcc_ctx *c) {
         build_dressing(c, P, Ls, La, S.t1.p);
         build_dressing(c, P, Lcs, Lb, S.t1.p);
     }
+    ladder_slots(c);
+    const size_t wbytes32 = (size_t)c->nwslot * v * v * v * v * 8;
+    if (store_ladder(c, 16, wbytes32)) {
+        S.Wst = m.get((size_t)c->nwslot * v * v * v * v * 16);
+        build_wstore<double>(c, P, S.La, S.Lb, S.Wst);
+    }
     // preconditioner: diagonals of the dressed one-body blocks (F_mi, F_ae for singles,
     // Fbar_mj, Fbar_be for doubles) in place of the bare orbital energies of Eq. D
     S.d_o1 = m.get((size_t)nk * o * 8); S.d_v1 = m.get((size_t)nk * v * 8);
@@ -417,6 +515,10 @@ void build_state(lrcc_ctx *c) {
         void *a = w == 0 ? S.La : w == 1 ? S.Lb : w == 2 ? S.LaT : S.LbT;
         void *fa = w == 0 ? F.La : w == 1 ? F.Lb : w == 2 ? F.LaT : F.LbT;
         P2.ops.push_back([=](hipStream_t s) { return convert_f64_f32(a, fa, lvv, s); });
+    }
+    if (store_ladder(c, 8, 0)) {
+        F.Wst = F.mem.get(wbytes32);
+        build_wstore<float>(c, P2, F.La, F.Lb, F.Wst);
     }
     c->pre32 = std::move(P2p);
     F.ready = true;
@@ -604,15 +706,67 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
             break;
         }
         case SymOp::LADDER: {
+            if (S.Wst) {
+                // stored integrals: Z(ki,kj,ka) += alpha' sum_{ke <= kf} Y(ki,kj,ke) W'(ka,kb,ke) for
+                // ka <= kb, alpha' = 2 alpha when ka < kb (the (kb,ka) partner block is left to the
+                // P(ij)P(ab) assembly, which reproduces it from antisymmetry), alpha when ka == kb
+                const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv;
+                GemmArgs g{};
+                g.shape = -1;
+                g.kind = 1;
+                g.A = op.A.p;
+                g.B = S.Wst;
+                g.C = op.C.p;
+                g.M = R * o * o;
+                g.N = (int)vv;
+                g.K = (int)vv;
+                g.sm = Split{1, g.M};
+                g.Am = Strides{{0, 0, vv}};
+                g.Cm = Strides{{0, 0, vv}};
+                g.sk = Split{1, g.K};
+                g.Ak = Strides{{0, 0, 1}};
+                g.Bk = Strides{{0, 0, vv}};
+                g.sn = Split{1, g.N};
+                g.Bn = Strides{{0, 0, 1}};
+                g.Cn = Strides{{0, 0, 1}};
+                g.aMfast = 0;
+                g.bNfast = 1;
+                g.alpha_re = op.alpha.real();
+                g.alpha_im = op.alpha.imag();
+                g.beta = 1;
+                std::vector<i64> offC, segA, segB;
+                std::vector<int> beg{0};
+                std::vector<float> js;
+                for (int ki = 0; ki < nk; ++ki)
+                    for (int kj = 0; kj < nk; ++kj)
+                        for (int ka = 0; ka < nk; ++ka) {
+                            const int kb = ((ki + kj - ka) % nk + nk) % nk;
+                            if (ka > kb) continue;
+                            for (int ke = 0; ke < nk; ++ke) {
+                                const int kf = ((ki + kj - ke) % nk + nk) % nk;
+                                if (ke > kf) continue;
+                                segA.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
+                                segB.push_back((i64)c->wslot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
+                            }
+                            offC.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
+                            beg.push_back((int)segA.size());
+                            js.push_back(ka < kb ? 2.0f : 1.0f);
+                        }
+                raw_gemm<T>(*P, g, offC, beg, segA, segB, op.A.count(), (i64)c->nwslot * vv * vv, op.C.count(), js);
+                P->tag_last(TAG_LADDER);
+                P->name_last("ladder (stored integrals)");
+                break;
+            }
             LadderArgs la = ladder_args<T>(c, op.A.p, S.La, S.Lb, op.C.p, R, op.alpha.real());
             la.packed = c->pack_ladder ? 1 : 0;  // dtau is antisymmetric in (e,f)
             auto lp = std::make_shared<LadderArgs>(la);
             P->ops.push_back([lp](hipStream_t s) { return launch_ladder<T>(*lp, s); });
             // candidates: antisymmetry-packed (0) or full-range (1) ladder
             P->tunables.push_back({P->ops.size() - 1, 2, [lp](int c) { lp->packed = c == 0 ? 1 : 0; }});
+            P->last_flops = (i64)ladder_executed_flops(la);
+            P->flops += P->last_flops;
             P->tag_last(TAG_LADDER);
             P->name_last("ladder");
-            P->flops += (i64)ladder_executed_flops(la);
             break;
         }
         }
@@ -670,9 +824,10 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
         case SymOp::LADDER: {
             LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
             P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
+            P->last_flops = (i64)ladder_executed_flops(la);
+            P->flops += P->last_flops;
             P->tag_last(TAG_LADDER);
             P->name_last("ladder");
-            P->flops += (i64)ladder_executed_flops(la);
             break;
         }
         }
@@ -689,7 +844,8 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
 // file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     char b[128];
-    std::snprintf(b, sizeof b, "%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
+    // "v2": candidate semantics of the GEMM variants (heuristic shape / alternative shape)
+    std::snprintf(b, sizeof b, "v2,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
                   adj ? "adjoint" : "forward", variant);
     return b;
 }
@@ -2109,6 +2265,14 @@ lrcc_status lrcc_get_lambda(lrcc_ctx *c, double *l1, double *l2) {
     });
 }
 
+lrcc_status lrcc_set_ladder_mode(lrcc_ctx *c, int mode) {
+    return guarded(c, [&] {
+        if (mode < 0 || mode > 2) throw LrccError(LRCC_E_ARG, "ladder mode must be 0, 1 or 2");
+        if (c->s64.ready) throw LrccError(LRCC_E_STATE, "the ladder mode is fixed once amplitudes are set");
+        c->ladder_mode = mode;
+    });
+}
+
 lrcc_status lrcc_set_autotune(lrcc_ctx *c, int enable) {
     return guarded(c, [&] { c->autotune = enable != 0; });
 }
@@ -2137,6 +2301,14 @@ lrcc_status lrcc_sigma_flops(lrcc_ctx *c, int nrhs, int precision, double *execu
         if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
         if (!executed || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
         *executed = (double)sigma_program(c, precision, nrhs)->flops;
+    });
+}
+
+lrcc_status lrcc_ladder_flops(lrcc_ctx *c, int nrhs, int precision, double *executed) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!executed || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
+        *executed = (double)sigma_program(c, precision, nrhs)->tag_flops[TAG_LADDER];
     });
 }
 

@@ -315,9 +315,11 @@ i64 max_off(int total, Split sp, Strides st) {
 
 template <typename T>
 void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::vector<int> &segBeg,
-              const std::vector<i64> &segA, const std::vector<i64> &segB, i64 sizeA, i64 sizeB, i64 sizeC) {
+              const std::vector<i64> &segA, const std::vector<i64> &segB, i64 sizeA, i64 sizeB, i64 sizeC,
+              const std::vector<float> &jscale) {
     g.njobs = (int)offC.size();
     if (g.njobs == 0) return;
+    if (!jscale.empty() && jscale.size() != offC.size()) throw LrccError(1, "per-job scale list of the wrong length");
     // every address formed by the kernel stays inside the operands
     if (g.M % (g.sm.d1 * g.sm.d2) || g.N % (g.sn.d1 * g.sn.d2) || g.K % (g.sk.d1 * g.sk.d2))
         throw LrccError(1, "GEMM split does not divide its dimension");
@@ -347,20 +349,50 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
             ok = ok && hipMemcpy(dB, segB.data(), segB.size() * sizeof(i64), hipMemcpyHostToDevice) == hipSuccess;
         if (!ok) throw LrccError(5, "upload of GEMM job lists failed");
     }
+    g.jscale = nullptr;
+    if (!jscale.empty()) {
+        float *dS = (float *)P.alloc(jscale.size() * sizeof(float));
+        if (!g_dry_run && hipMemcpy(dS, jscale.data(), jscale.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            throw LrccError(5, "upload of GEMM job scales failed");
+        g.jscale = dS;
+    }
     g.offC = dOff;
     g.segBeg = dBeg;
     g.segA = dA;
     g.segB = dB;
-    P.flops += 8LL * g.M * g.N * g.K * (i64)segA.size();
+    g.njobs_all = g.njobs;
+    g.job0 = 0;
+    g.alt = 0;
+    // split-K when the job x tile grid cannot fill the chip but the jobs have long reductions
+    {
+        const i64 tn = g.M <= 16 ? (g.N + 255) / 256 : (g.N + 63) / 64;
+        const i64 tiles = (i64)g.njobs * ((g.M + 63) / 64) * tn;
+        const i64 steps = (i64)segA.size() * ((g.K + 15) / 16) / g.njobs;  // average per job
+        i64 ks = 1;
+        if (tiles < 1024 && steps >= 64) {
+            ks = std::min<i64>({(2048 + tiles - 1) / tiles, steps / 16, (i64)256});
+            while (ks > 1 && ks * g.njobs * (i64)g.M * g.N * (i64)sizeof(T) * 2 > ((i64)256 << 20)) ks /= 2;
+        }
+        g.ksplit = (int)std::max<i64>(1, ks);
+        g.part = g.ksplit > 1 ? P.alloc((size_t)g.ksplit * g.njobs * g.M * g.N * sizeof(T) * 2) : nullptr;
+    }
+    P.last_flops = 8LL * g.M * g.N * g.K * (i64)segA.size();
+    P.flops += P.last_flops;
     auto gp = std::make_shared<GemmArgs>(g);
     P.ops.push_back([gp](hipStream_t s) { return launch_gemm<T>(*gp, s); });
-    // candidates: 64x64 tiles (0) or the large tile shape (1)
-    P.tunables.push_back({P.ops.size() - 1, 2, [gp](int c) { gp->shape = c; }});
+    // candidates: the heuristic tile shape (0) or the alternative shape (1)
+    P.tunables.push_back({P.ops.size() - 1, 2, [gp](int c) { gp->alt = c; }});
 }
 
 template <typename T>
 void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const std::string &al, const KT &B,
               const std::string &bl, std::complex<double> alpha, bool accumulate) {
+    // the GEMM stores run along its N index: put the output's unit-stride index there
+    // (operand order does not change a complex product)
+    if (al.find(cl.back()) != std::string::npos && bl.find(cl.back()) == std::string::npos) {
+        contract<T>(P, C, cl, B, bl, A, al, alpha, accumulate);
+        return;
+    }
     TInfo tc = info(C, cl), ta = info(A, al), tb = info(B, bl);
     const std::string what = cl + " <- " + al + " * " + bl;
     std::vector<char> Ml, Nl, Kl, free_k, sum_k;
@@ -381,7 +413,14 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
     g.B = B.p;
     g.C = C.p;
     make_split(by_stride(chains(Ml, ta, tc), ta), ta, tc, g.sm, g.Am, g.Cm, g.M, what);
-    make_split(by_stride(chains(Nl, tb, tc), tb), tb, tc, g.sn, g.Bn, g.Cn, g.N, what);
+    {
+        // N groups by decreasing stride in B, or in C when the reduction is short (the output
+        // traffic then dominates and the small operand B stays in cache)
+        i64 kext = 1;
+        for (char c : Kl) kext *= ta.extent[pos(ta, c)];
+        for (size_t i = 0; i < sum_k.size(); ++i) kext *= C.nk;
+        make_split(by_stride(chains(Nl, tb, tc), kext <= 64 && !tb.hasR ? tc : tb), tb, tc, g.sn, g.Bn, g.Cn, g.N, what);
+    }
     {
         // K: make the unit-stride group innermost for whichever operand has one (A first)
         auto kc = chains(Kl, tb, ta);
@@ -445,8 +484,10 @@ template void contract<double>(Program &, const KT &, const std::string &, const
 template void contract<float>(Program &, const KT &, const std::string &, const KT &, const std::string &,
                               const KT &, const std::string &, std::complex<double>, bool);
 template void raw_gemm<double>(Program &, GemmArgs, const std::vector<i64> &, const std::vector<int> &,
-                               const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64);
+                               const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64,
+                               const std::vector<float> &);
 template void raw_gemm<float>(Program &, GemmArgs, const std::vector<i64> &, const std::vector<int> &,
-                              const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64);
+                              const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64,
+                              const std::vector<float> &);
 
 }  // namespace lrcc

@@ -83,10 +83,13 @@ struct Program {
     hipError_t autotune(hipStream_t s, std::vector<int> &choice);
     void apply(const std::vector<int> &choice);
     std::vector<void *> owned;
-    i64 flops = 0;  // executed real flops of the recorded GEMMs and ladder
+    i64 flops = 0;       // executed real flops of the recorded GEMMs and ladder
+    i64 last_flops = 0;  // executed flops of the op recorded last
+    i64 tag_flops[NTAGS] = {0, 0, 0};
     void tag_last(int t) {
         tags.resize(ops.size(), TAG_NONE);
         tags.back() = t;
+        tag_flops[t] += last_flops;
     }
     hipError_t run(hipStream_t s, Profiler *prof = nullptr);
     // Replay through a HIP graph captured on first use for this key (the
@@ -108,9 +111,11 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
 // Raw strided GEMM with explicit job/segment lists (host vectors are uploaded).
 // sizeA/B/C are the element counts of the operands: every address the GEMM can
 // form is checked against them before the launch is recorded.
+// jscale (optional, one per job) multiplies alpha job by job.
 template <typename T>
 void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::vector<int> &segBeg,
-              const std::vector<i64> &segA, const std::vector<i64> &segB, i64 sizeA, i64 sizeB, i64 sizeC);
+              const std::vector<i64> &segA, const std::vector<i64> &segB, i64 sizeA, i64 sizeB, i64 sizeC,
+              const std::vector<float> &jscale = {});
 
 // Placeholder-or-real device allocation honouring g_dry_run.
 void *dev_alloc(size_t bytes);

@@ -44,11 +44,15 @@ def lib():
         L.lrcc_sigma_vjp_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_set_profiling.argtypes = [vp, i]
         L.lrcc_set_graphs.argtypes = [vp, i]
+        L.lrcc_set_ladder_mode.argtypes = [vp, i]
+        L.lrcc_set_ladder_mode.restype = ctypes.c_int
         L.lrcc_set_autotune.argtypes = [vp, i]
         L.lrcc_set_autotune.restype = ctypes.c_int
         L.lrcc_set_graphs.restype = ctypes.c_int
         L.lrcc_read_profile.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         L.lrcc_sigma_flops.argtypes = [vp, i, i, dp]
+        L.lrcc_ladder_flops.argtypes = [vp, i, i, dp]
+        L.lrcc_ladder_flops.restype = ctypes.c_int
         for f in ("lrcc_set_profiling", "lrcc_read_profile", "lrcc_sigma_flops"):
             getattr(L, f).restype = ctypes.c_int
         L.lrcc_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -243,6 +247,10 @@ class Context:
         self._check(self._L.lrcc_get_lambda(self._h, _ptr(l1), _ptr(l2)))
         return l1, l2
 
+    def set_ladder_mode(self, mode):
+        """0 automatic, 1 integrals rebuilt in LDS, 2 stored integral blocks (before set_amplitudes)."""
+        self._check(self._L.lrcc_set_ladder_mode(self._h, int(mode)))
+
     def set_autotune(self, on=True):
         self._check(self._L.lrcc_set_autotune(self._h, int(bool(on))))
 
@@ -262,6 +270,11 @@ class Context:
     def sigma_flops(self, nrhs, precision=FP64):
         out = ctypes.c_double()
         self._check(self._L.lrcc_sigma_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
+        return out.value
+
+    def ladder_flops(self, nrhs, precision=FP64):
+        out = ctypes.c_double()
+        self._check(self._L.lrcc_ladder_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
         return out.value
 
     def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None, adjoint=False):

@@ -19,11 +19,12 @@ CASES = [
 ]
 
 
-def _ctx(case):
+def _ctx(case, ladder_mode=0):
     import paper_2508_01266_amd as lr
     c = lr.Context(0)
     H = case['H']
     c.set_hamiltonian(case['o'], H['fock'], H['chol'], H['dip'])
+    c.set_ladder_mode(ladder_mode)
     c.set_amplitudes(case['t1'], case['t2'])
     return c
 
@@ -32,18 +33,24 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+# ladder integrals rebuilt in LDS (1) and stored blocks (2)
+MODES = {1: "rebuild", 2: "stored"}
+
+
 @pytest.mark.parametrize("nk,o,v,naux,nrhs,seed", CASES)
 def test_sigma_fp64_matches_oracle(nk, o, v, naux, nrhs, seed):
     import paper_2508_01266_amd as lr
     case = make_case(nk, o, v, naux, nrhs, seed)
     print(f"case nk={nk} o={o} v={v} naux={naux} nrhs={nrhs}", flush=True)
     ref1, ref2 = oracle_sigma(case)
-    c = _ctx(case)
-    y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
-    e1, e2 = _rel(y1, ref1), _rel(y2, ref2)
-    print(f"fp64 rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
-    # FP64 GEMM rounding: well below 1e-11 relative (max-norm)
-    assert e1 < 1e-11 and e2 < 1e-11
+    for mode, name in MODES.items():
+        c = _ctx(case, mode)
+        y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
+        e1, e2 = _rel(y1, ref1), _rel(y2, ref2)
+        print(f"fp64 ({name} ladder) rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
+        # FP64 GEMM rounding: well below 1e-11 relative (max-norm)
+        assert e1 < 1e-11 and e2 < 1e-11
+        c.close()
 
 
 @pytest.mark.parametrize("nk,o,v,naux,nrhs,seed", CASES)
@@ -51,13 +58,24 @@ def test_sigma_fp32_matches_oracle(nk, o, v, naux, nrhs, seed):
     import paper_2508_01266_amd as lr
     case = make_case(nk, o, v, naux, nrhs, seed)
     ref1, ref2 = oracle_sigma(case)
-    c = _ctx(case)
-    y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP32)
-    e1, e2 = _rel(y1, ref1), _rel(y2, ref2)
     # complex64 accumulation over the longest contraction (K = nk*v*v of the ladder)
     tol = 4 * nk * v * v * 2.0 ** -24 + 1e-6
-    print(f"fp32 rel err singles {e1:.2e} doubles {e2:.2e} (tol {tol:.1e})", flush=True)
-    assert e1 < tol and e2 < tol
+    for mode, name in MODES.items():
+        c = _ctx(case, mode)
+        y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP32)
+        e1, e2 = _rel(y1, ref1), _rel(y2, ref2)
+        print(f"fp32 ({name} ladder) rel err singles {e1:.2e} doubles {e2:.2e} (tol {tol:.1e})", flush=True)
+        assert e1 < tol and e2 < tol
+        c.close()
+
+
+def test_ladder_mode_is_fixed_after_amplitudes():
+    import paper_2508_01266_amd as lr
+    case = make_case(1, 2, 4, 6, 1, 1)
+    c = _ctx(case)
+    with pytest.raises(lr.LrccError):
+        c.set_ladder_mode(1)
+    c.close()
 
 
 @pytest.mark.parametrize("nk,o,v,naux,nrhs,seed", CASES)
