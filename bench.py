@@ -109,6 +109,60 @@ def latency_small(lr, torch, reps=50):
     return out
 
 
+def uneven_batch(lr, torch, steps):
+    """Uneven batch of twelve chains (Nk in {3,5,7,9}, 12 right-hand sides each): complex64
+    sigma of every chain, one after another vs all together with one persistent ladder launch."""
+    import numpy as np
+    import synth
+    chains = synth.uneven_batch()
+    dev = torch.device("cuda:0")
+    ctxs, X1, X2, Y1, Y2, OM = [], [], [], [], [], []
+    alg = 0.0
+    for i, w in enumerate(chains):
+        rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir, (i,))
+        H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=0.02)
+        t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
+        x1, x2 = synth.random_vectors(12, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
+        c = lr.Context(0)
+        c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+        c.set_amplitudes(t1, t2 * w.nk)
+        ctxs.append(c)
+        X1.append(torch.from_numpy(x1).to(dev)); X2.append(torch.from_numpy(x2 * w.nk).to(dev))
+        Y1.append(torch.empty_like(X1[-1])); Y2.append(torch.empty_like(X2[-1]))
+        om = np.array([f for _ in range(3) for f in w.omegas])
+        OM.append(torch.from_numpy(om).to(dev))
+        alg += 12 * sigma_alg_flops(w.nk, w.nocc, w.nvir)
+        log(f"chain {i}: Nk={w.nk} nocc={w.nocc} nvir={w.nvir} Naux={w.naux}")
+    st = torch.cuda.current_stream().cuda_stream
+    g = lr.Group(ctxs)
+
+    def seq():
+        for i, c in enumerate(ctxs):
+            c.apply_sigma_dev(X1[i], X2[i], Y1[i], Y2[i], OM[i], lr.FP32, st)
+
+    def grp():
+        g.apply_sigma_dev(X1, X2, Y1, Y2, OM, lr.FP32, st)
+
+    out = {}
+    for name, fn in (("one_after_another", seq), ("one_persistent_ladder", grp)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_step": dt * 1e3, "tflops_algorithmic": alg / dt / 1e12}
+        log(f"uneven batch, {name}: {dt * 1e3:.1f} ms")
+    out["chains"] = [[w.nk, w.nocc, w.nvir, w.naux] for w in chains]
+    out["nrhs_per_chain"] = 12
+    out["speedup"] = out["one_after_another"]["ms_per_step"] / out["one_persistent_ladder"]["ms_per_step"]
+    g.close()
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def cpu_baseline(w, H, t1, t2, x1, x2, nrhs):
     """The oracle's sigma on a bounded sample: the oracle computes A x as the exact
     5-point stencil of the CCSD residual, i.e. four residual evaluations per
@@ -145,6 +199,7 @@ def main():
     ap.add_argument("--alpha-tol", type=float, default=1e-10)
     ap.add_argument("--ccsd-iter", type=int, default=300)
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch variants instead of autotuning")
+    ap.add_argument("--uneven", action="store_true", help="also time the twelve-chain uneven batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
@@ -182,8 +237,8 @@ def main():
     lad_avg = lad_ms / max(lad_n, 1) / 1e3
     lad64_ms, lad64_n = prof64["ladder"]
     lad64_avg = lad64_ms / max(lad64_n, 1) / 1e3
-    # roofline of the ladder launch: the products it executes (antisymmetry-packed, so about a
-    # third of the full-range algorithmic count) per second against the matrix-core peak
+    # roofline of the ladder launch: the products it executes (antisymmetry-packed unique pairs
+    # plus the in-LDS integral rebuild) per second against the matrix-core peak
     lad_exec = ctx.ladder_flops(nrhs, lr.FP32)
     lad_exec64 = ctx.ladder_flops(nrhs, lr.FP64)
     achieved = lad_exec / lad_avg / 1e12
@@ -202,7 +257,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: 1D chain Nk={nk}, nocc={o}, nvir={v}, Naux={w.naux}, "
                                f"{nrhs} right-hand sides (3 axes x +-omega x {len(w.omegas)} frequencies) "
-                               f"in one sigma launch, complex64 on the matrix cores",
+                               f"in one sigma launch, complex64 on the matrix cores, ladder integrals rebuilt "
+                               f"in LDS from the Cholesky vectors",
                    "nk": nk, "nocc": o, "nvir": v, "naux": w.naux, "nrhs": nrhs},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["f32"], "traffic": None, "kernel": "ladder",
@@ -217,6 +273,28 @@ def main():
         "speedup_mixed_vs_fp64_sigma": dt64 / dt32,
     }
     log(f"complex128 sigma {dt64*1e3:.1f} ms")
+    # the same sigma with the ladder integrals stored (unique momentum pairs, antisymmetrised)
+    # instead of rebuilt in LDS: one dense matrix-core GEMM for the ladder
+    ctx2 = lr.Context(0)
+    ctx2.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+    ctx2.set_ladder_mode(2)
+    ctx2.set_amplitudes(t1, t2)
+    ctx2.set_autotune(not args.no_tune)
+    s32, sp32 = time_sigma(ctx2, X1, X2, Y1, Y2, OM, lr.FP32, args.steps, args.warmup, torch)
+    s64, sp64 = time_sigma(ctx2, X1, X2, Y1, Y2, OM, lr.FP64, args.fp64_steps, 1, torch)
+    sl32 = sp32["ladder"][0] / max(sp32["ladder"][1], 1) / 1e3
+    sl64 = sp64["ladder"][0] / max(sp64["ladder"][1], 1) / 1e3
+    out["stored_integrals"] = {
+        "ms_per_step": s32 * 1e3, "value": alg / s32 / 1e12, "ladder_ms_avg": sl32 * 1e3,
+        "ladder_achieved": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12,
+        "ladder_frac": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12 / PEAK["f32"],
+        "fp64_ms_per_step": s64 * 1e3, "fp64_value": alg / s64 / 1e12, "fp64_ladder_ms_avg": sl64 * 1e3,
+        "fp64_ladder_frac": ctx2.ladder_flops(nrhs, lr.FP64) / sl64 / 1e12 / PEAK["f64"],
+        "note": "ladder mode 2: antisymmetrised integral blocks stored for unique momentum pairs "
+                "(0.9 GB complex64 + 1.8 GB complex128 here); the headline uses the default mode, "
+                "integrals rebuilt in LDS from the Cholesky vectors, nothing of vvvv size stored"}
+    log(f"stored-integral ladder: complex64 sigma {s32*1e3:.1f} ms, complex128 {s64*1e3:.1f} ms")
+    ctx2.close()
     out["latency_c1_9rhs"] = latency_small(lr, torch)
     log(f"c1 latency {out['latency_c1_9rhs']}")
     del X1, X2, Y1, Y2, OM
@@ -252,6 +330,8 @@ def main():
                                        for k in res},
             "reports": {k: res[k][2] for k in res},
         }
+    if args.uneven:
+        out["uneven_batch"] = uneven_batch(lr, torch, max(1, args.steps))
     if not args.no_cpu:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(w, H, t1, t2, sample[0], sample[1], nrhs)

@@ -61,7 +61,7 @@ typedef struct {
                               norm: sum |u1|^2 + 1/4 sum |u2|^2 over full arrays                      */
     int max_iter;          /* FP64 GMRES: maximum operator applications (default 400)                */
     int krylov;            /* GMRES restart length; 0 (default) sizes it from free device memory
-                              (60% of it, 4..60 vectors)                                              */
+                              (85% of it, 4..60 vectors)                                              */
     int precision;         /* LRCC_FP64: GMRES in complex128; LRCC_FP32: complex64 matrix-core inner
                               GMRES corrections inside complex128 iterative refinement                */
     double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4;
@@ -133,14 +133,16 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
 lrcc_status lrcc_set_profiling(lrcc_ctx *ctx, int enable);
 lrcc_status lrcc_read_profile(lrcc_ctx *ctx, double *ms, long long *count);
 
-/* How the ladder term (the vvvv contraction of Eq. tx2) obtains its integrals:
- * 0 = automatic (stored when they take at most a quarter of the free device
- * memory, per precision), 1 = rebuilt in LDS from the t1-dressed Cholesky
- * vectors inside the ladder kernel (nothing of vvvv size in memory), 2 = stored.
- * Stored blocks: the antisymmetrised integrals for the unique momentum pairs,
- * about Nk^3/4 blocks of nvir^4 complex values, rebuilt with the other
- * amplitude-dependent blocks.  Must precede the first lrcc_set_amplitudes or
- * lrcc_solve_ccsd (LRCC_E_STATE afterwards); LRCC_E_ARG for other modes. */
+/* How the ladder term (the vvvv contraction of Eq. tx2) obtains its integrals.
+ * 0 (default) or 1: rebuilt in LDS from the t1-dressed Cholesky vectors inside
+ * the ladder kernel, so nothing of vvvv size is ever stored.  2: stored blocks,
+ * the antisymmetrised integrals for the unique momentum pairs (about Nk^3/4
+ * blocks of nvir^4 complex values per precision, rebuilt with the other
+ * amplitude-dependent blocks), after which the ladder is one dense matrix-core
+ * GEMM; LRCC_E_OOM at lrcc_set_amplitudes if they would take more than half of
+ * the free device memory.  The transpose product always rebuilds.  Must precede
+ * the first lrcc_set_amplitudes or lrcc_solve_ccsd (LRCC_E_STATE afterwards);
+ * LRCC_E_ARG for other modes. */
 lrcc_status lrcc_set_ladder_mode(lrcc_ctx *ctx, int mode);
 
 /* Autotuning of launch variants: when enabled, the first application of each
@@ -253,6 +255,27 @@ lrcc_status lrcc_solve(lrcc_ctx *ctx, unsigned axis_mask, int nfreq, const doubl
 lrcc_status lrcc_solve_ccsd(lrcc_ctx *ctx, double tol, int max_iter, double *t1, double *t2, double *energy,
                             lrcc_solve_report *report);
 
+/* Several chains (contexts with their own Hamiltonians and sizes, on one device)
+ * whose sigma applications run together: every chain's steps up to the ladder,
+ * then the ladders of all chains as ONE persistent launch that takes
+ * (chain, k block, tile) work items from an atomic queue, most expensive
+ * chains first (uneven batches keep the device busy through the tail), then the
+ * remaining steps.  Chains whose ladder is not the rebuild-in-LDS packed
+ * kernel (stored integrals, or fewer than 192 (rhs, i, j) rows) run their
+ * whole program on their own.  Results are bitwise those of
+ * lrcc_apply_sigma_dev per chain.  The group does not own the contexts; destroy
+ * it before them.  Arrays are indexed by chain; omega may be NULL.  Errors:
+ * LRCC_E_ARG for null arrays, contexts on different devices or a bad precision,
+ * LRCC_E_STATE if a chain has no amplitudes; the message is read with
+ * lrcc_group_last_error. */
+typedef struct lrcc_group lrcc_group;
+lrcc_status lrcc_group_create(lrcc_ctx *const *ctxs, int n, lrcc_group **out);
+void lrcc_group_destroy(lrcc_group *group);
+const char *lrcc_group_last_error(const lrcc_group *group);
+lrcc_status lrcc_group_apply_sigma_dev(lrcc_group *group, const int *nrhs, const double *const *omega,
+                                       const void *const *x1, const void *const *x2, void *const *y1,
+                                       void *const *y2, int precision, void *stream);
+
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */
 lrcc_status lrcc_get_alpha(lrcc_ctx *ctx, int nfreq, double *alpha);
@@ -270,6 +293,19 @@ lrcc_status lrcc_get_alpha(lrcc_ctx *ctx, int nfreq, double *alpha);
  * include or an out-of-range ifreq; LRCC_E_NOCONV if the transpose solve fails. */
 lrcc_status lrcc_alpha_dipole_gradient(lrcc_ctx *ctx, int ifreq, int x, int y, const lrcc_solve_opts *opts,
                                        double *grad);
+
+/* Gradient of one polarizability element of the last lrcc_solve with respect to
+ * the Fock matrix (the one-electron part of the Hamiltonian of Sec. II.A) at
+ * fixed ground-state amplitudes, with lambda re-solved (it depends on f):
+ *   d alpha_xy(omega_ifreq) = sum_{k,p,q} grad[k][p][q] df[k][p][q]
+ * for every Hermitian perturbation df.  grad: host [nk][n][n] complex.  The
+ * residual is linear in f, so every f-dependence enters through one-body
+ * densities of the perturbation residual; the cost is the transpose solves of
+ * the dipole gradient (4 right-hand sides), one forward solve of 2 right-hand
+ * sides, 6 stencils of the sigma and a few density evaluations.  Errors as for
+ * lrcc_alpha_dipole_gradient. */
+lrcc_status lrcc_alpha_fock_gradient(lrcc_ctx *ctx, int ifreq, int x, int y, const lrcc_solve_opts *opts,
+                                     double *grad);
 
 /* Perturbed amplitudes t^X(sign*omega_ifreq) of the last lrcc_solve (caller
  * layouts with nrhs = 1, per-cell normalisation). */

@@ -21,15 +21,40 @@ template <> struct Cx<float> { typedef float2 type; };
 
 // Three-level split of a GEMM index: idx = (i0*d1 + i1)*d2 + i2 and the
 // address contribution is i0*s[0] + i1*s[1] + i2*s[2] (units: complex elements).
+// Three-level index split idx = (i0 * d1 + i1) * d2 + i2.  The divisions use
+// multiply-high magic numbers (exact for 0 <= idx < 2^31): x / d = (x * m) >> (31 + l)
+// with l = ceil(log2 d), m = ceil(2^(31+l) / d); set by split_magic before a launch.
 struct Split {
     int d1, d2;
+    unsigned m1 = 0, m2 = 0;   // magic multipliers for d1, d2
+    int l1 = 0, l2 = 0;        // their shifts
 };
 struct Strides {
     i64 s[3];
 };
+inline void div_magic(int d, unsigned &m, int &l) {
+    l = 0;
+    while ((1LL << l) < d) ++l;
+    m = (unsigned)(((1ULL << (31 + l)) + (unsigned long long)d - 1) / (unsigned long long)d);
+}
+inline Split split_magic(Split s) {
+    div_magic(s.d1, s.m1, s.l1);
+    div_magic(s.d2, s.m2, s.l2);
+    return s;
+}
+__host__ __device__ inline int fdiv(int x, unsigned m, int l) {
+    return (int)(((unsigned long long)(unsigned)x * m) >> (31 + l));
+}
+// 32-bit form for offsets inside one operand block (bounded on the host)
+__host__ __device__ inline int split_off32(int idx, Split sp, int s0, int s1, int s2) {
+    const int q = fdiv(idx, sp.m2, sp.l2);
+    const int q0 = fdiv(q, sp.m1, sp.l1);
+    return q0 * s0 + (q - q0 * sp.d1) * s1 + (idx - q * sp.d2) * s2;
+}
 __host__ __device__ inline i64 split_off(int idx, Split sp, Strides st) {
-    const int q = idx / sp.d2;
-    return (i64)(q / sp.d1) * st.s[0] + (i64)(q % sp.d1) * st.s[1] + (i64)(idx % sp.d2) * st.s[2];
+    const int q = fdiv(idx, sp.m2, sp.l2);
+    const int q0 = fdiv(q, sp.m1, sp.l1);
+    return (i64)q0 * st.s[0] + (i64)(q - q0 * sp.d1) * st.s[1] + (i64)(idx - q * sp.d2) * st.s[2];
 }
 
 // One strided complex GEMM over a list of output blocks ("jobs").
@@ -45,8 +70,8 @@ struct GemmArgs {
     Strides Am, Ak, Bk, Bn, Cm, Cn;
     int aMfast, bNfast;  // tile-load thread maps: 1 = run along m (resp. n)
     int shape;           // tile shape: -1 automatic, 0 = 64x64, 1 = large (128x128 complex64, 128x64
-                         // complex128), 2 = 16x256 (small M)
-    int alt;             // autotuner candidate: 0 = heuristic shape, 1 = the alternative shape
+                         // complex128), 2 = 16x256 (small M), 3 = 128x64 (complex64)
+    int alt;             // unused (kept zero)
     double alpha_re, alpha_im;
     int beta;
     const i64 *offC;
@@ -67,6 +92,8 @@ struct GemmArgs {
 template <typename T>
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 int gemm_shape(const GemmArgs &g, bool fp64);
+// tile shapes the autotuner tries for g (the heuristic one first, at most 3)
+std::vector<int> gemm_candidates(const GemmArgs &g, bool fp64);
 
 // Ladder: sigma2[ki,kj,ka][R][i][j][a][b] += alpha * sum_{ke} sum_{e,f}
 //   Y[ki,kj,ke][R][i][j][e][f] * sum_Q La[ka][ke][Q][a][e] * Lb[kb][kf][Q][b][f]
@@ -77,11 +104,27 @@ struct LadderArgs {
     void *Z;             // output, same layout as Y (accumulated)
     int nk, nrhs, o, v, naux;
     double alpha;
-    int packed;          // 1: Y antisymmetric in (e,f); form only unique (e,f) and (a,b) pairs
+    int packed;          // Y antisymmetric in (e,f): form only unique (e,f) and (a,b) pairs
+                         // (1: 256-row kernel, 2: pipelined kernel); 0: full ranges
 };
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s);
+
+// Several pipelined packed ladders in one persistent launch (device-resident tables):
+// ladder d owns items [start[d], start[d+1]); item = k block * tiles[d] + tile.
+struct LadderGroup {
+    const LadderArgs *args;
+    const long long *start;   // n + 1 prefix sums
+    const long long *tiles;   // tiles per k block of each ladder
+    int n;
+    long long total;
+    unsigned *counter;        // work-queue counter (zeroed by the launcher on the stream)
+};
+template <typename T>
+long long ladder_group_tiles(const LadderArgs &a);
+template <typename T>
+hipError_t launch_ladder_group(const LadderGroup &g, int nblocks, hipStream_t s);
 // real flops the ladder kernel executes (tile padding and LDS rebuild included)
-double ladder_executed_flops(const LadderArgs &a);
+double ladder_executed_flops(const LadderArgs &a, bool fp64);
 
 }  // namespace lrcc

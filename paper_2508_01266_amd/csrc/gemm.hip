@@ -10,6 +10,9 @@
 // unit-stride index when one exists, for coalesced loads.
 #include "common.hpp"
 
+#include <algorithm>
+#include <vector>
+
 namespace lrcc {
 
 template <typename T> struct Mfma;
@@ -59,7 +62,10 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     const bool aM = g.aMfast != 0;
     const bool bN = g.bNfast != 0;
     int am[LA], ak[LA], bk[LB], bn[LB];
-    i64 arow[LA], bcol[LB];
+    // operand offsets inside a segment's blocks fit in 32 bits (checked when the GEMM is recorded)
+    const int ak0 = (int)g.Ak.s[0], ak1 = (int)g.Ak.s[1], ak2 = (int)g.Ak.s[2];
+    const int bk0 = (int)g.Bk.s[0], bk1 = (int)g.Bk.s[1], bk2 = (int)g.Bk.s[2];
+    int arow[LA], bcol[LB];
     bool aok[LA], bok[LB];
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
@@ -67,7 +73,7 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
         if (aM) { am[q] = idx % TM; ak[q] = idx / TM; } else { ak[q] = idx % TK; am[q] = idx / TK; }
         const int gm = m0 + am[q];
         aok[q] = gm < g.M;
-        arow[q] = aok[q] ? split_off(gm, g.sm, g.Am) : 0;
+        arow[q] = aok[q] ? split_off32(gm, g.sm, (int)g.Am.s[0], (int)g.Am.s[1], (int)g.Am.s[2]) : 0;
     }
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
@@ -75,7 +81,7 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
         if (bN) { bn[q] = idx % TN; bk[q] = idx / TN; } else { bk[q] = idx % TK; bn[q] = idx / TK; }
         const int gn = n0 + bn[q];
         bok[q] = gn < g.N;
-        bcol[q] = bok[q] ? split_off(gn, g.sn, g.Bn) : 0;
+        bcol[q] = bok[q] ? split_off32(gn, g.sn, (int)g.Bn.s[0], (int)g.Bn.s[1], (int)g.Bn.s[2]) : 0;
     }
 
     v4 accr[FM][FN], acci[FM][FN];
@@ -98,13 +104,13 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int gk = k0 + ak[q];
-            if (aok[q] && gk < g.K) va[q] = As[arow[q] + split_off(gk, g.sk, g.Ak)];
+            if (aok[q] && gk < g.K) va[q] = As[arow[q] + split_off32(gk, g.sk, ak0, ak1, ak2)];
             else { va[q].x = 0; va[q].y = 0; }
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
             const int gk = k0 + bk[q];
-            if (bok[q] && gk < g.K) vb[q] = Bs[bcol[q] + split_off(gk, g.sk, g.Bk)];
+            if (bok[q] && gk < g.K) vb[q] = Bs[bcol[q] + split_off32(gk, g.sk, bk0, bk1, bk2)];
             else { vb[q].x = 0; vb[q].y = 0; }
         }
     };
@@ -224,12 +230,25 @@ __global__ void k_gemm_reduce(GemmArgs g) {
 
 int gemm_shape(const GemmArgs &g, bool fp64) {
     if (g.shape >= 0) return g.shape;
-    int h = 0;
-    if (g.M <= 16 && g.N >= 128) h = 2;
-    else if (g.M >= 128 && g.N >= 128) h = 1;
-    else if (fp64 && g.M >= 128 && g.N >= 64) h = 1;
-    if (!g.alt) return h;
-    return h == 0 ? (g.M <= 16 ? 2 : 1) : 0;
+    if (g.M <= 16 && g.N >= 128) return 2;
+    if (g.M >= 128 && g.N >= 128) return 1;
+    if (fp64 && g.M >= 128 && g.N >= 64) return 1;
+    return 0;
+}
+
+std::vector<int> gemm_candidates(const GemmArgs &g, bool fp64) {
+    GemmArgs h = g;
+    h.shape = -1;
+    std::vector<int> c{gemm_shape(h, fp64)};
+    const int others[4] = {0, 1, 3, 2};
+    for (int s : others) {
+        if ((int)c.size() == 3) break;
+        if (s == 3 && fp64) continue;             // complex128 large tile is already 128x64
+        if (s == 2 && g.M > 32) continue;         // small-M tile only for short M
+        if (s != 0 && g.M < 64 && s != 2) continue;
+        if (std::find(c.begin(), c.end(), s) == c.end()) c.push_back(s);
+    }
+    return c;
 }
 
 template <typename T>
@@ -243,6 +262,7 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
         else e = launch_shape<T, 128, 128, 64, 64>(g, s);
         break;
     case 2: e = launch_shape<T, 16, 256, 16, 64>(g, s); break;
+    case 3: e = launch_shape<T, 128, 64, 64, 32>(g, s); break;
     default: e = launch_shape<T, 64, 64, 32, 32>(g, s); break;
     }
     if (e != hipSuccess || g.ksplit <= 1) return e;

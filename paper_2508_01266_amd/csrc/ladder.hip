@@ -529,6 +529,251 @@ __global__ void __launch_bounds__(NTP) ladder_kernel_packed(LadderArgs p) {
 }
 
 
+// Pipelined antisymmetry-packed variant (same arithmetic as ladder_kernel_packed):
+// WM x WN waves over a BM x 64 output tile, BM = 64 WM rows, so the rank-naux
+// integral rebuild (one 16x16 block per wave and step) is amortised over more
+// rows.  Global loads run one stage ahead in registers: the Y tile of a step is
+// fetched while its integral tile is rebuilt, each Cholesky chunk while the
+// previous one is multiplied, and the first chunk of the next step while the
+// current step's main product runs.
+template <typename T, int WM, int WN, int QCH>
+__device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int bx, const int blk) {
+    typedef typename Cx<T>::type C2;
+    typedef typename MfmaL<T>::v4 v4;
+    constexpr int FM = 4;                          // 16-row blocks per wave
+    constexpr int FN = LTN / (WN * 16);            // 16-column blocks per wave
+    constexpr int BM = WM * FM * 16;               // rows per tile
+    constexpr int YPT = BM * LTK / NTP;            // Y elements per thread per step
+    constexpr int LPT = 4 * QCH * 32 / NTP;        // Cholesky elements per thread per chunk
+    static_assert(WM * WN == NTP / 64, "8 waves");
+    static_assert(YPT * NTP == BM * LTK && LPT * NTP == 4 * QCH * 32, "even loads");
+    constexpr int PY = 16, PL = 16, PW = sizeof(T) == 8 ? 9 : 17;
+    __shared__ T Wr[LTK][LTN + PW], Wi[LTK][LTN + PW];
+    __shared__ T Yr[LTK][BM + PY], Yi[LTK][BM + PY];
+    __shared__ T Lr[4][QCH][32 + PL], Li[4][QCH][32 + PL];
+
+    const int nk = p.nk, v = p.v, naux = p.naux;
+    const int M = p.nrhs * p.o * p.o;
+    const int tilesM = (M + BM - 1) / BM;
+    const int tilesA = (v + TA - 1) / TA;
+    const int mt = bx % tilesM;
+    const int rest = bx / tilesM;
+    const int ta = rest % tilesA, tb = rest / tilesA;
+    const int a0 = ta * TA, b0 = tb * TB;
+    const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
+    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    if (ka > kb || (ka == kb && ta > tb)) return;
+    const bool diag_out = (ka == kb);
+    const int m0 = mt * BM;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave % WM) * FM * 16, wn = (wave / WM) * FN * 16;
+    const i64 vv = (i64)v * v;
+    const i64 blk4 = (i64)M * vv;
+    const C2 *Y = reinterpret_cast<const C2 *>(p.Y);
+    const C2 *La = reinterpret_cast<const C2 *>(p.La);
+    const C2 *Lb = reinterpret_cast<const C2 *>(p.Lb);
+    C2 *Z = reinterpret_cast<C2 *>(p.Z);
+    const int gb = wave & 3, second = wave >> 2;
+    const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
+
+    // steps (ke <= kf, e0, f0 >= e0 when ke == kf); the step after `s`, or ke = nk when done
+    auto kf_of = [&](int ke) { return ((ki + kj - ke) % nk + nk) % nk; };
+    auto first_valid = [&](int ke) {
+        while (ke < nk && ke > kf_of(ke)) ++ke;
+        return ke;
+    };
+    auto advance = [&](int &ke, int &e0, int &f0) {
+        f0 += TF;
+        if (f0 >= v) {
+            e0 += TE;
+            if (e0 >= v) { ke = first_valid(ke + 1); e0 = 0; }
+            f0 = (ke < nk && ke == kf_of(ke)) ? (e0 / TF) * TF : 0;
+        }
+    };
+
+    C2 lv[LPT], yv[YPT];
+    auto load_chunk = [&](int ke, int e0, int f0, int q0) {
+        const int kf = kf_of(ke);
+        const C2 *L0 = La + (i64)(ka * nk + ke) * naux * vv;
+        const C2 *L1 = Lb + (i64)(kb * nk + kf) * naux * vv;
+        const C2 *L2 = La + (i64)(ka * nk + kf) * naux * vv;
+        const C2 *L3 = Lb + (i64)(kb * nk + ke) * naux * vv;
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int idx = tid + NTP * q;
+            const int which = idx / (QCH * 32), rem = idx % (QCH * 32);
+            const int qq = q0 + rem / 32, cc = rem % 32;
+            const int x = cc / 4, y = cc % 4;
+            const int r0 = (which == 0 || which == 2) ? a0 + x : b0 + x;
+            const int c0 = (which == 0 || which == 3) ? e0 + y : f0 + y;
+            const C2 *src = which == 0 ? L0 : which == 1 ? L1 : which == 2 ? L2 : L3;
+            C2 val; val.x = 0; val.y = 0;
+            if (qq < naux && r0 < v && c0 < v) val = src[(i64)qq * vv + (i64)r0 * v + c0];
+            lv[q] = val;
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const int idx = tid + NTP * q;
+            const int which = idx / (QCH * 32), rem = idx % (QCH * 32);
+            Lr[which][rem / 32][rem % 32] = lv[q].x;
+            Li[which][rem / 32][rem % 32] = lv[q].y;
+        }
+    };
+    auto load_y = [&](int ke, int e0, int f0) {
+        const bool diag_in = ke == kf_of(ke);
+        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
+#pragma unroll
+        for (int q = 0; q < YPT; ++q) {
+            const int idx = tid + NTP * q;
+            const int kk = idx % LTK, m = idx / LTK;
+            const int e = e0 + kk / TF, f = f0 + kk % TF;
+            C2 val; val.x = 0; val.y = 0;
+            if (m0 + m < M && e < v && f < v && (!diag_in || e < f)) val = Yb[(i64)(m0 + m) * vv + (i64)e * v + f];
+            yv[q] = val;
+        }
+    };
+
+    v4 accr[FM][FN], acci[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+
+    int ke = first_valid(0), e0 = 0, f0 = 0;
+    if (ke < nk) load_chunk(ke, e0, f0, 0);
+    while (ke < nk) {
+        load_y(ke, e0, f0);
+        // rebuild: waves 0-3 G1[(a,e)][(b,f)] = sum La(ka,ke)[a][e] Lb(kb,kf)[b][f],
+        //          waves 4-7 G2[(a,f)][(b,e)] = sum La(ka,kf)[a][f] Lb(kb,ke)[b][e]
+        v4 gr = v4{0, 0, 0, 0}, gi = v4{0, 0, 0, 0};
+        const int ra = second ? 2 : 0, rb = second ? 3 : 1;
+        for (int q0 = 0; q0 < naux; q0 += QCH) {
+            store_chunk();
+            __syncthreads();
+            if (q0 + QCH < naux) load_chunk(ke, e0, f0, q0 + QCH);
+#pragma unroll 2
+            for (int kk = 0; kk < QCH; kk += 4) {
+                const int kr = kk + (lane >> 4), c = lane & 15;
+                const T xr = Lr[ra][kr][rw + c], xi = Li[ra][kr][rw + c];
+                const T yr = Lr[rb][kr][cw + c], yi = Li[rb][kr][cw + c];
+                gr = MfmaL<T>::mma(xr, yr, gr);
+                gr = MfmaL<T>::mma(-xi, yi, gr);
+                gi = MfmaL<T>::mma(xr, yi, gi);
+                gi = MfmaL<T>::mma(xi, yr, gi);
+            }
+            __syncthreads();
+        }
+        // W[(e,f)][(a,b)] = G1[(a,e)][(b,f)] - G2[(a,f)][(b,e)]: the G1 waves write, then the G2 waves subtract
+        if (!second) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ae = rw + MfmaL<T>::row(lane, r);
+                const int bf = cw + (lane & 15);
+                Wr[(ae % 4) * TF + bf % 4][(ae / 4) * TB + bf / 4] = gr[r];
+                Wi[(ae % 4) * TF + bf % 4][(ae / 4) * TB + bf / 4] = gi[r];
+            }
+        }
+        __syncthreads();
+        if (second) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int af = rw + MfmaL<T>::row(lane, r);
+                const int be = cw + (lane & 15);
+                Wr[(be % 4) * TF + af % 4][(af / 4) * TB + be / 4] -= gr[r];
+                Wi[(be % 4) * TF + af % 4][(af / 4) * TB + be / 4] -= gi[r];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < YPT; ++q) {
+            const int idx = tid + NTP * q;
+            Yr[idx % LTK][idx / LTK] = yv[q].x;
+            Yi[idx % LTK][idx / LTK] = yv[q].y;
+        }
+        __syncthreads();
+        advance(ke, e0, f0);
+        if (ke < nk) load_chunk(ke, e0, f0, 0);
+#pragma unroll
+        for (int kk = 0; kk < LTK; kk += 4) {
+            const int kr = kk + (lane >> 4), c = lane & 15;
+            T ar[FM], ai[FM], br[FN], bi[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) { ar[i] = Yr[kr][wm + 16 * i + c]; ai[i] = Yi[kr][wm + 16 * i + c]; }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) { br[j] = Wr[kr][wn + 16 * j + c]; bi[j] = Wi[kr][wn + 16 * j + c]; }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
+                    accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
+                    acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
+                    acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+
+    C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
+    const T al = (T)(2.0 * p.alpha);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + MfmaL<T>::row(lane, r);
+                const int c = wn + 16 * j + (lane & 15);
+                const int a = a0 + c / TB, b = b0 + c % TB;
+                if (m < M && a < v && b < v && (!diag_out || a < b)) {
+                    const i64 off = (i64)m * vv + (i64)a * v + b;
+                    C2 o2 = Zb[off];
+                    o2.x += al * accr[i][j][r];
+                    o2.y += al * acci[i][j][r];
+                    Zb[off] = o2;
+                }
+            }
+}
+
+template <typename T, int WM, int WN, int QCH>
+__global__ void __launch_bounds__(NTP) ladder_kernel_pipe(LadderArgs p) {
+    ladder_pipe_tile<T, WM, WN, QCH>(p, blockIdx.x, blockIdx.y);
+}
+
+// Persistent form over several ladders (chains of different shapes): every
+// workgroup takes (ladder, k block, tile) items from one atomic counter until
+// the queue is empty.  The ladders are ordered by decreasing cost per item, so
+// the expensive tiles start first and the cheap ones fill the tail.
+template <typename T, int WM, int WN, int QCH>
+__global__ void __launch_bounds__(NTP) ladder_kernel_pipe_group(LadderGroup g) {
+    __shared__ long long item_s;
+    while (true) {
+        if (threadIdx.x == 0) item_s = (long long)atomicAdd(g.counter, 1u);
+        __syncthreads();
+        const long long item = item_s;
+        __syncthreads();
+        if (item >= g.total) break;
+        int d = 0;
+        while (d + 1 < g.n && g.start[d + 1] <= item) ++d;
+        const LadderArgs p = g.args[d];
+        const long long local = item - g.start[d];
+        const long long ntile = g.tiles[d];
+        ladder_pipe_tile<T, WM, WN, QCH>(p, (int)(local % ntile), (int)(local / ntile));
+    }
+}
+
+__global__ void k_zero_counter(unsigned *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+}
+
+// launch shape of the pipelined kernel per precision (256-row tiles; Cholesky chunks of
+// 32 vectors in complex64 and 8 in complex128, sized to the register file and LDS)
+template <typename T> struct PipeCfg;
+template <> struct PipeCfg<float> { static constexpr int WM = 4, WN = 2, QCH = 32, BM = 256; };
+template <> struct PipeCfg<double> { static constexpr int WM = 4, WN = 2, QCH = 8, BM = 256; };
+
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     const int M = a.nrhs * a.o * a.o;
@@ -536,7 +781,11 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     if (use_big(a)) {
         const int tilesM = (M + BTM - 1) / BTM;
         dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
-        if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
+        if (a.packed == 2) {
+            typedef PipeCfg<T> C;
+            dim3 gp(((M + C::BM - 1) / C::BM) * tA * tB, a.nk * a.nk * a.nk);
+            hipLaunchKernelGGL((ladder_kernel_pipe<T, C::WM, C::WN, C::QCH>), gp, dim3(NTP), 0, s, a);
+        } else if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
         else hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
     } else {
         const int tilesM = (M + LTM - 1) / LTM;
@@ -546,13 +795,34 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-double ladder_executed_flops(const LadderArgs &a) {
+template <typename T>
+long long ladder_group_tiles(const LadderArgs &a) {
+    const int M = a.nrhs * a.o * a.o;
+    const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
+    return (long long)((M + PipeCfg<T>::BM - 1) / PipeCfg<T>::BM) * tA * tB;
+}
+
+template <typename T>
+hipError_t launch_ladder_group(const LadderGroup &g, int nblocks, hipStream_t s) {
+    typedef PipeCfg<T> C;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, g.counter);
+    hipLaunchKernelGGL((ladder_kernel_pipe_group<T, C::WM, C::WN, C::QCH>), dim3(nblocks), dim3(NTP), 0, s, g);
+    return hipGetLastError();
+}
+
+template long long ladder_group_tiles<double>(const LadderArgs &);
+template long long ladder_group_tiles<float>(const LadderArgs &);
+template hipError_t launch_ladder_group<double>(const LadderGroup &, int, hipStream_t);
+template hipError_t launch_ladder_group<float>(const LadderGroup &, int, hipStream_t);
+
+double ladder_executed_flops(const LadderArgs &a, bool fp64) {
     const int M = a.nrhs * a.o * a.o;
     const bool big = use_big(a);
-    const int tm = big ? BTM : LTM;
+    const bool pipe = big && a.packed == 2;
+    const int tm = pipe ? (fp64 ? PipeCfg<double>::BM : PipeCfg<float>::BM) : big ? BTM : LTM;
     const double tilesM = (M + tm - 1) / tm;
     const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB, tE = (a.v + TE - 1) / TE, tF = (a.v + TF - 1) / TF;
-    const int qc = (big && !a.packed) ? 2 * QC : QC;
+    const int qc = pipe ? (fp64 ? PipeCfg<double>::QCH : PipeCfg<float>::QCH) : (big && !a.packed) ? 2 * QC : QC;
     const double qpad = (double)((a.naux + qc - 1) / qc) * qc;
     const double main_step = 8.0 * tm * LTN * LTK, rebuild_step = 8.0 * (TA * TE) * (TB * TF) * qpad;
     if (!(big && a.packed)) {

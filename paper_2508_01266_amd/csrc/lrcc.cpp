@@ -100,7 +100,7 @@ struct lrcc_ctx {
     Profiler prof;
     bool use_graphs = false;
     bool pack_ladder = true;                   // antisymmetry-packed forward ladder for large batches
-    int ladder_mode = 0;                       // 0 auto, 1 rebuild integrals in LDS, 2 stored integral blocks
+    int ladder_mode = 0;                       // 0, 1: rebuild integrals in LDS; 2: stored integral blocks
     std::vector<int> wslot;                    // (ka, kb, ke) -> slot of the stored blocks, -1 if not stored
     int nwslot = 0;
     bool autotune = false;
@@ -333,15 +333,17 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
     }
 }
 
-// Decide, per precision, whether the ladder integrals are stored: forced by
-// ladder_mode, else stored when they take at most a quarter of the free memory.
+// Whether the ladder integrals are stored (ladder mode 2; the plan check covers
+// that path too).  Mode 2 refuses blocks that would take more than half of the
+// free device memory.
 bool store_ladder(lrcc_ctx *c, size_t elem_bytes, size_t also) {
-    if (c->ladder_mode == 1) return false;
-    if (c->ladder_mode == 2 || g_dry_run) return true;
+    if (g_dry_run) return true;
+    if (c->ladder_mode != 2) return false;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
     const size_t bytes = (size_t)c->nwslot * c->nv * c->nv * c->nv * c->nv * elem_bytes;
-    return bytes + also <= fr / 4;
+    if (bytes + also > fr / 2) throw LrccError(LRCC_E_OOM, "stored ladder integrals do not fit in device memory");
+    return true;
 }
 
 template <typename T>
@@ -758,12 +760,14 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
                 break;
             }
             LadderArgs la = ladder_args<T>(c, op.A.p, S.La, S.Lb, op.C.p, R, op.alpha.real());
-            la.packed = c->pack_ladder ? 1 : 0;  // dtau is antisymmetric in (e,f)
+            la.packed = c->pack_ladder ? 2 : 0;  // dtau is antisymmetric in (e,f)
             auto lp = std::make_shared<LadderArgs>(la);
             P->ops.push_back([lp](hipStream_t s) { return launch_ladder<T>(*lp, s); });
-            // candidates: antisymmetry-packed (0) or full-range (1) ladder
-            P->tunables.push_back({P->ops.size() - 1, 2, [lp](int c) { lp->packed = c == 0 ? 1 : 0; }});
-            P->last_flops = (i64)ladder_executed_flops(la);
+            P->ladder_args = lp;
+            P->ladder_op = P->ops.size() - 1;
+            // candidates: pipelined packed (0), 256-row packed (1) or full-range (2) ladder
+            P->tunables.push_back({P->ops.size() - 1, 3, [lp](int c) { lp->packed = c == 0 ? 2 : c == 1 ? 1 : 0; }});
+            P->last_flops = (i64)ladder_executed_flops(la, sizeof(T) == 8);
             P->flops += P->last_flops;
             P->tag_last(TAG_LADDER);
             P->name_last("ladder");
@@ -824,7 +828,7 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
         case SymOp::LADDER: {
             LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
             P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
-            P->last_flops = (i64)ladder_executed_flops(la);
+            P->last_flops = (i64)ladder_executed_flops(la, sizeof(T) == 8);
             P->flops += P->last_flops;
             P->tag_last(TAG_LADDER);
             P->name_last("ladder");
@@ -844,8 +848,8 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
 // file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     char b[128];
-    // "v2": candidate semantics of the GEMM variants (heuristic shape / alternative shape)
-    std::snprintf(b, sizeof b, "v2,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
+    // "v4": candidate semantics (GEMM: heuristic tile shape first, up to three; ladder: three kernels)
+    std::snprintf(b, sizeof b, "v4,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
                   adj ? "adjoint" : "forward", variant);
     return b;
 }
@@ -1123,10 +1127,11 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
     c->solmem.release();
     int m = o.krylov;
     if (m <= 0) {
-        // subspace size from the free device memory (60% of it), between 4 and 60 vectors
+        // subspace size from the free device memory (85% of it, the rest left for the few
+        // single-vector buffers of the alpha contraction), between 4 and 60 vectors
         size_t fr = 0, tot = 0;
         if (!g_dry_run) HIPCHK(hipMemGetInfo(&fr, &tot));
-        const long long fit = (long long)(0.6 * (double)fr / (double)per) - 3 - (mixed ? 2 : 0);
+        const long long fit = (long long)(0.85 * (double)fr / (double)per) - 3 - (mixed ? 2 : 0);
         m = (int)std::max(4LL, std::min(60LL, fit));
     }
     const int nvec = (m + 1) + 2 + (mixed ? 2 : 0);
@@ -1175,6 +1180,7 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
         }
     }
     HIPCHK(hipStreamSynchronize(st));
+    c->solmem.release();   // the Krylov space is not needed after the solve
     rep.sigma_fp64 = S.nsig64;
     rep.sigma_fp32 = S.nsig32;
     rep.rhs_sigmas = S.rhs_sig;
@@ -1709,6 +1715,232 @@ void alpha_dip_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, 
     std::memcpy(out, g.data(), g.size() * 16);
 }
 
+// ---------------------------------------------------------------- Fock-matrix gradient of alpha
+// Helpers: the one-body density of u at shifted amplitudes, and the vector
+// Omega''[x, y] (second derivative of the residual along x and y).
+//
+// Shifted amplitudes T + sx x + sy y into the density program's copy (crystal T2).
+void dens_shift(lrcc_ctx *c, SolveCtx &D, const Vecs *x, double sx, const Vecs *y, double sy, hipStream_t st) {
+    State<double> &S = c->s64;
+    const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+    const int nk = c->nk;
+    HIPCHK(hipMemcpyAsync(c->dT1.p, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->dT2.p, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+    const Vecs *v[2] = {x, y};
+    const double sc[2] = {sx, sy};
+    for (int i = 0; i < 2; ++i) {
+        if (!v[i]) continue;
+        std::vector<cd> a1(1, cd(sc[i], 0.0)), a2(1, cd(sc[i] / nk, 0.0));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, a1.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(c->dT1.p, v[i]->s, D.alpha, 1.0, 1, nt1, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(c->dT2.p, v[i]->d, D.alpha, 1.0, 1, nt2, st));
+    }
+}
+
+// D_xi(u; T + sx x + sy y) on the host, [nk][n][n]
+std::vector<cd> density_at(lrcc_ctx *c, SolveCtx &D, const Vecs &u, const Vecs *x, double sx, const Vecs *y,
+                           double sy, void *dd, hipStream_t st) {
+    Program *d1 = dens_program(c, 1);
+    dens_shift(c, D, x, sx, y, sy, st);
+    c->io_x1 = u.s; c->io_x2 = u.d; c->io_y1 = dd;
+    HIPCHK(d1->run(st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<cd> h((size_t)c->nk * c->n * c->n);
+    HIPCHK(hipMemcpy(h.data(), dd, h.size() * 16, hipMemcpyDeviceToHost));
+    return h;
+}
+
+double step_for(SolveCtx &D, const Vecs &t) {
+    SolveCtx N = D;
+    N.R = 1;
+    const cd tt = N.dot(t, t)[0];
+    const double rms = std::sqrt(std::max(tt.real(), 1e-300) / (double)(D.n1 + D.n2 / 4));
+    return 1e-2 / rms;
+}
+
+// d/de D_xi(u; T + e t): exact central difference (xi is quadratic in T)
+std::vector<cd> density_d1(lrcc_ctx *c, SolveCtx &D, const Vecs &u, const Vecs &t, void *dd, hipStream_t st) {
+    const double h = step_for(D, t);
+    auto p = density_at(c, D, u, &t, h, nullptr, 0, dd, st), m = density_at(c, D, u, &t, -h, nullptr, 0, dd, st);
+    for (size_t e = 0; e < p.size(); ++e) p[e] = (p[e] - m[e]) / (2.0 * h);
+    return p;
+}
+
+// d2/de dd D_xi(u; T + e x + d y): exact four-point mixed difference
+std::vector<cd> density_d2(lrcc_ctx *c, SolveCtx &D, const Vecs &u, const Vecs &x, const Vecs &y, void *dd,
+                           hipStream_t st) {
+    const double hx = step_for(D, x), hy = step_for(D, y);
+    auto pp = density_at(c, D, u, &x, hx, &y, hy, dd, st), pm = density_at(c, D, u, &x, hx, &y, -hy, dd, st);
+    auto mp = density_at(c, D, u, &x, -hx, &y, hy, dd, st), mm = density_at(c, D, u, &x, -hx, &y, -hy, dd, st);
+    for (size_t e = 0; e < pp.size(); ++e) pp[e] = (pp[e] - pm[e] - mp[e] + mm[e]) / (4.0 * hx * hy);
+    return pp;
+}
+
+// out = Omega''[x, y] = d/de A(T + e x) y: the forward product is cubic in T, so the
+// 5-point derivative is exact.  Leaves the amplitudes shifted (caller restores).
+void omega2_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &x, const Vecs &y, const Vecs &out, const Vecs &q,
+                   const void *T1, const void *T2, hipStream_t st) {
+    const int nk = c->nk;
+    const i64 n1 = D.n1, n2 = D.n2;
+    State<double> &S = c->s64;
+    const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+    Program *fwd = sigma_program(c, LRCC_FP64, 1, false);
+    const double coef[4] = {1.0, -8.0, 8.0, -1.0};
+    const int shift[4] = {-2, -1, 1, 2};
+    const double h = step_for(D, x);
+    HIPCHK(hipMemsetAsync(out.s, 0, n1 * 16, st));
+    HIPCHK(hipMemsetAsync(out.d, 0, n2 * 16, st));
+    for (int k = 0; k < 4; ++k) {
+        HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        std::vector<cd> a1(1, cd(shift[k] * h, 0.0)), a2(1, cd(shift[k] * h / nk, 0.0));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, a1.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(S.t1.p, x.s, D.alpha, 1.0, 1, nt1, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(S.t2.p, x.d, D.alpha, 1.0, 1, nt2, st));
+        run_precompute(c, false, st);
+        c->io_x1 = y.s; c->io_x2 = y.d; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
+        HIPCHK(fwd->run(st));
+        std::vector<cd> wv(1, cd(coef[k] / (12.0 * h), 0.0));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(D.alpha, wv.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(out.s, q.s, D.alpha, 1.0, 1, n1, st));
+        HIPCHK(batched_axpby(out.d, q.d, D.alpha, 1.0, 1, n2, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+}
+
+// d alpha_XY(w_j) / d f at fixed amplitudes, lambda re-solved (it depends on f).
+// Every f-dependence is linear (the residual is linear in f), with the one-body
+// part of the residual being xi^f(T) (quadratic in T).  With a the transpose
+// solutions of the dipole gradient and z = A^-1 w, w = A_X t^Y + A_Y t^X(-w) +
+// Omega''[t^X(-w), t^Y(w)] (the lambda-sensitivity of eta and F):
+//   d g(w) = - <a_Y, dA t^Y(w)> - <a_X, dA t^X(-w)> - <lambda, dA z> - <dg, z>
+//            + <lambda, dOmega''[t^X(-w), t^Y(w)]>,     dg = (df_ov, 0),
+// where <u, dA t> = d/de D_xi(u; T + e t) . df and the last term is the mixed
+// second derivative of D_xi(lambda; .) . df.  g(-w) likewise, conjugated.
+void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, double *out) {
+    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    const auto &axes = c->axes;
+    const int nax = (int)axes.size();
+    if (j < 0 || j >= c->nfreq || (int)c->last_omega.size() != c->nfreq)
+        throw LrccError(LRCC_E_ARG, "frequency index out of range of the last solve");
+    const int ax = (int)(std::find(axes.begin(), axes.end(), X) - axes.begin());
+    const int ay = (int)(std::find(axes.begin(), axes.end(), Y) - axes.begin());
+    if (ax >= nax || ay >= nax) throw LrccError(LRCC_E_ARG, "axis not solved in the last solve (zero dipole or masked)");
+    if (!c->lam_valid || !c->sol1 || c->nrhs_sol != c->nfreq * 2 * nax)
+        throw LrccError(LRCC_E_STATE, "lrcc_solve must precede the gradient");
+    hipStream_t st = c->own_stream;
+    const double w = c->last_omega[j];
+    DevMem tmp;
+    auto vec = [&](int R) { Vecs v; v.s = tmp.get((size_t)R * n1 * 16); v.d = tmp.get((size_t)R * n2 * 16); return v; };
+    auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
+    Vecs sol{c->sol1, c->sol2};
+    auto tsol = [&](int sg, int a) { return sub(sol, (j * 2 + sg) * nax + a); };  // sg 0: +w, 1: -w
+    SolveCtx D;
+    D.c = c; D.R = 1; D.n1 = n1; D.n2 = n2; D.st = st;
+    D.part = tmp.get((size_t)dot_blocks(n2) * 16 * 2);
+    D.dout = tmp.get(32);
+    D.alpha = tmp.get(32);
+    (void)dens_program(c, 1);   // allocates the density program's amplitude copy
+    // transpose right-hand sides as in the dipole gradient (all four: X and Y enter symmetrically)
+    //   0: eta^Y + F(., t^Y(w)),  (A + w)^T      1: eta^Y + F(., t^Y(-w)), (A - w)^T
+    //   2: eta^X + F(., t^X(-w)), (A - w)^T      3: eta^X + F(., t^X(w)),  (A + w)^T
+    Vecs tv[4] = {tsol(0, ay), tsol(1, ay), tsol(1, ax), tsol(0, ax)};
+    const bool same = X == Y;
+    const double wsolve[4] = {-w, w, w, -w};
+    Vecs B = vec(4), A = vec(4), W = vec(2), Z = vec(2);
+    {
+        Vecs etaY = vec(1), etaX = same ? etaY : vec(1);
+        eta_vector(c, Y, etaY, st);
+        if (!same) eta_vector(c, X, etaX, st);
+        State<double> &S = c->s64;
+        const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+        void *T1 = tmp.get(nt1 * 16), *T2 = tmp.get(nt2 * 16);
+        HIPCHK(hipMemcpyAsync(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        Vecs q = vec(1);
+        for (int b = 0; b < 4; ++b) {
+            Vecs bb = sub(B, b);
+            f_vector(c, D, tv[b], bb, q, T1, T2, st);
+            const Vecs &e = b < 2 ? etaY : etaX;
+            HIPCHK(add_inplace<double>(bb.s, e.s, n1, st));
+            HIPCHK(add_inplace<double>(bb.d, e.d, n2, st));
+        }
+        // w(+) = Omega''[t^X(-w), t^Y(w)] + A_X t^Y(w) + A_Y t^X(-w);  w(-) with w -> -w
+        for (int sg = 0; sg < 2; ++sg) {
+            const Vecs tx = tsol(1 - sg, ax), ty = tsol(sg, ay);
+            omega2_vector(c, D, tx, ty, sub(W, sg), q, T1, T2, st);
+        }
+        HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        run_precompute(c, true, st);
+        for (int sg = 0; sg < 2; ++sg) {
+            const Vecs tx = tsol(1 - sg, ax), ty = tsol(sg, ay);
+            const int pa[2] = {X, Y};
+            const Vecs vin[2] = {ty, tx};
+            for (int k = 0; k < 2; ++k) {
+                HIPCHK(c->prex[pa[k]]->run(st));
+                Program *p = sigma_program(c, LRCC_FP64, 1, false, 1 + pa[k]);
+                c->io_x1 = vin[k].s; c->io_x2 = vin[k].d; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
+                HIPCHK(p->run(st));
+                HIPCHK(add_inplace<double>(sub(W, sg).s, q.s, n1, st));
+                HIPCHK(add_inplace<double>(sub(W, sg).d, q.d, n2, st));
+            }
+        }
+    }
+    void *dom = tmp.get(4 * 8), *zom = tmp.get(2 * 8);
+    HIPCHK(hipMemcpy(dom, wsolve, 4 * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(zom, 0, 2 * 8));
+    HIPCHK(hipMemset(A.s, 0, (size_t)4 * n1 * 16));
+    HIPCHK(hipMemset(A.d, 0, (size_t)4 * n2 * 16));
+    HIPCHK(hipMemset(Z.s, 0, (size_t)2 * n1 * 16));
+    HIPCHK(hipMemset(Z.d, 0, (size_t)2 * n2 * 16));
+    lrcc_solve_report r{};
+    solve_response(c, 4, (const double *)dom, B, A, o, r, st, true);
+    if (!r.converged) throw LrccError(LRCC_E_NOCONV, "adjoint response equations did not converge");
+    solve_response(c, 2, (const double *)zom, W, Z, o, r, st, false);
+    if (!r.converged) throw LrccError(LRCC_E_NOCONV, "lambda-sensitivity equations did not converge");
+    // densities
+    const size_t nd = (size_t)nk * n * n;
+    void *dd = tmp.get(nd * 16);
+    Vecs lam{c->lam1, c->lam2};
+    std::vector<cd> G[2];
+    std::vector<cd> zh((size_t)n1);
+    for (int sg = 0; sg < 2; ++sg) {
+        // sg 0: g(w) with a_X = A[0] along t^X(-w), a_Y = A[2] along t^Y(w)
+        // sg 1: g(-w) with a_X = A[1] along t^X(w), a_Y = A[3] along t^Y(-w)
+        const Vecs tx = tsol(1 - sg, ax), ty = tsol(sg, ay);
+        const Vecs aX = sub(A, sg == 0 ? 0 : 1), aY = sub(A, sg == 0 ? 2 : 3);
+        const Vecs zz = sub(Z, sg);
+        auto d_ay = density_d1(c, D, aY, ty, dd, st);
+        auto d_ax = density_d1(c, D, aX, tx, dd, st);
+        auto d_lz = density_d1(c, D, lam, zz, dd, st);
+        auto d_2 = density_d2(c, D, lam, tx, ty, dd, st);
+        G[sg].assign(nd, 0.0);
+        for (size_t e = 0; e < nd; ++e) G[sg][e] = -d_ay[e] - d_ax[e] - d_lz[e] + d_2[e];
+        HIPCHK(hipMemcpy(zh.data(), zz.s, n1 * 16, hipMemcpyDeviceToHost));
+        for (int k = 0; k < nk; ++k)
+            for (int i = 0; i < no; ++i)
+                for (int a = 0; a < nv; ++a)
+                    G[sg][((size_t)k * n + i) * n + no + a] -= zh[((size_t)k * no + i) * nv + a];
+    }
+    std::vector<cd> g(nd);
+    for (int k = 0; k < nk; ++k)
+        for (int p = 0; p < n; ++p)
+            for (int qq = 0; qq < n; ++qq)
+                g[((size_t)k * n + p) * n + qq] =
+                    -0.5 / nk * (G[0][((size_t)k * n + p) * n + qq] + std::conj(G[1][((size_t)k * n + qq) * n + p]));
+    std::memcpy(out, g.data(), g.size() * 16);
+}
+
 // ---------------------------------------------------------------- ground-state CCSD
 // The CCSD residual is a quartic polynomial in T, so with A the Jacobian
 //   Omega(T) = Omega(0) + int_0^1 A(sT) T ds
@@ -2230,6 +2462,151 @@ lrcc_status lrcc_alpha_dipole_gradient(lrcc_ctx *c, int ifreq, int x, int y, con
         if (opts) o = *opts;
         alpha_dip_grad(c, ifreq, x, y, o, grad);
     });
+}
+
+lrcc_status lrcc_alpha_fock_gradient(lrcc_ctx *c, int ifreq, int x, int y, const lrcc_solve_opts *opts,
+                                    double *grad) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!grad || x < 0 || x > 2 || y < 0 || y > 2) throw LrccError(LRCC_E_ARG, "invalid axis or null pointer");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        alpha_fock_grad(c, ifreq, x, y, o, grad);
+    });
+}
+
+struct lrcc_group {
+    std::vector<lrcc_ctx *> ctx;
+    std::string err;
+    // per (precision, nrhs list): device tables of the joint ladder launch
+    std::map<std::vector<int>, std::unique_ptr<DevMem>> tabmem;
+    std::map<std::vector<int>, LadderGroup> tab;
+    unsigned *counter = nullptr;
+    DevMem mem;
+    int nblocks = 0;
+};
+
+lrcc_status lrcc_group_create(lrcc_ctx *const *ctxs, int n, lrcc_group **out) {
+    if (!out || !ctxs || n < 1) return LRCC_E_ARG;
+    *out = nullptr;
+    try {
+        auto g = std::make_unique<lrcc_group>();
+        for (int i = 0; i < n; ++i) {
+            if (!ctxs[i]) return LRCC_E_ARG;
+            if (ctxs[i]->dev != ctxs[0]->dev) return LRCC_E_ARG;
+            g->ctx.push_back(ctxs[i]);
+        }
+        if (hipSetDevice(ctxs[0]->dev) != hipSuccess) return LRCC_E_HIP;
+        g->counter = (unsigned *)g->mem.get(256);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctxs[0]->dev) != hipSuccess) return LRCC_E_HIP;
+        g->nblocks = prop.multiProcessorCount;
+        *out = g.release();
+        return LRCC_OK;
+    } catch (...) {
+        return LRCC_E_OOM;
+    }
+}
+
+void lrcc_group_destroy(lrcc_group *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx[0]->dev);
+    delete g;
+}
+
+const char *lrcc_group_last_error(const lrcc_group *g) { return g ? g->err.c_str() : "null group"; }
+
+}  // extern "C"
+
+template <typename T>
+static void group_apply(lrcc_group *g, const int *nrhs, const double *const *omega, const void *const *x1,
+                        const void *const *x2, void *const *y1, void *const *y2, int precision, hipStream_t st) {
+    const int n = (int)g->ctx.size();
+    std::vector<Program *> prog(n);
+    std::vector<int> join;
+    std::vector<int> key{precision};
+    for (int i = 0; i < n; ++i) {
+        lrcc_ctx *c = g->ctx[i];
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called on every chain");
+        if (nrhs[i] < 1 || !x1[i] || !x2[i] || !y1[i] || !y2[i]) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
+        prog[i] = sigma_program(c, precision, nrhs[i]);
+        key.push_back(nrhs[i]);
+        const Program *p = prog[i];
+        if (p->ladder_args && p->ladder_args->packed == 2 && (i64)nrhs[i] * c->no * c->no >= 192) join.push_back(i);
+    }
+    auto io = [&](int i) {
+        lrcc_ctx *c = g->ctx[i];
+        c->io_x1 = x1[i]; c->io_x2 = x2[i]; c->io_y1 = y1[i]; c->io_y2 = y2[i]; c->io_omega = omega ? omega[i] : nullptr;
+    };
+    std::vector<bool> joined(n, false);
+    for (int i : join) joined[i] = true;
+    // everything before the ladder (whole programs for chains that do not join)
+    for (int i = 0; i < n; ++i) {
+        io(i);
+        HIPCHK(prog[i]->run_range(st, 0, joined[i] ? prog[i]->ladder_op : prog[i]->ops.size()));
+    }
+    if (!join.empty()) {
+        auto it = g->tab.find(key);
+        if (it == g->tab.end()) {
+            // ladders by decreasing cost per item
+            std::vector<int> order = join;
+            auto cost = [&](int i) {
+                const LadderArgs &a = *prog[i]->ladder_args;
+                return (double)a.nk * a.v * a.v * (256.0 + a.naux);
+            };
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+            std::vector<LadderArgs> args;
+            std::vector<long long> start{0}, tiles;
+            for (int i : order) {
+                const LadderArgs &a = *prog[i]->ladder_args;
+                args.push_back(a);
+                tiles.push_back(ladder_group_tiles<T>(a));
+                start.push_back(start.back() + tiles.back() * (long long)a.nk * a.nk * a.nk);
+            }
+            auto mem = std::make_unique<DevMem>();
+            LadderGroup lg{};
+            lg.args = (const LadderArgs *)mem->get(args.size() * sizeof(LadderArgs));
+            lg.start = (const long long *)mem->get(start.size() * sizeof(long long));
+            lg.tiles = (const long long *)mem->get(tiles.size() * sizeof(long long));
+            HIPCHK(hipMemcpy((void *)lg.args, args.data(), args.size() * sizeof(LadderArgs), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy((void *)lg.start, start.data(), start.size() * sizeof(long long), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy((void *)lg.tiles, tiles.data(), tiles.size() * sizeof(long long), hipMemcpyHostToDevice));
+            lg.n = (int)args.size();
+            lg.total = start.back();
+            lg.counter = g->counter;
+            g->tabmem[key] = std::move(mem);
+            it = g->tab.emplace(key, lg).first;
+        }
+        HIPCHK(launch_ladder_group<T>(it->second, g->nblocks, st));
+        for (int i : join) {
+            io(i);
+            HIPCHK(prog[i]->run_range(st, prog[i]->ladder_op + 1, prog[i]->ops.size()));
+        }
+    }
+}
+
+extern "C" {
+
+lrcc_status lrcc_group_apply_sigma_dev(lrcc_group *g, const int *nrhs, const double *const *omega,
+                                       const void *const *x1, const void *const *x2, void *const *y1,
+                                       void *const *y2, int precision, void *stream) {
+    if (!g) return LRCC_E_ARG;
+    try {
+        if (!nrhs || !x1 || !x2 || !y1 || !y2) throw LrccError(LRCC_E_ARG, "null argument array");
+        if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        HIPCHK(hipSetDevice(g->ctx[0]->dev));
+        if (precision == LRCC_FP64) group_apply<double>(g, nrhs, omega, x1, x2, y1, y2, precision, (hipStream_t)stream);
+        else group_apply<float>(g, nrhs, omega, x1, x2, y1, y2, precision, (hipStream_t)stream);
+        g->err.clear();
+        return LRCC_OK;
+    } catch (LrccError &e) {
+        g->err = e.what();
+        return (lrcc_status)e.code;
+    } catch (std::exception &e) {
+        g->err = e.what();
+        return LRCC_E_ARG;
+    }
 }
 
 lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -76,6 +77,14 @@ hipError_t Program::run_graph(hipStream_t s, const GraphKey &key) {
     return hipGraphLaunch(it->second, s);
 }
 
+hipError_t Program::run_range(hipStream_t s, size_t begin, size_t end) {
+    for (size_t i = begin; i < end && i < ops.size(); ++i) {
+        hipError_t e = ops[i](s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t Program::run(hipStream_t s, Profiler *prof) {
     tags.resize(ops.size(), TAG_NONE);
     const bool timed = prof && prof->on;
@@ -141,12 +150,14 @@ void Program::apply(const std::vector<int> &choice) {
 
 hipError_t Program::autotune(hipStream_t s, std::vector<int> &choice) {
     const size_t nt = tunables.size();
-    std::vector<std::vector<float>> t(2, std::vector<float>(nt, 1e30f));
+    int maxc = 1;
+    for (auto &tu : tunables) maxc = std::max(maxc, tu.ncand);
+    std::vector<std::vector<float>> t(maxc, std::vector<float>(nt, 1e30f));
     std::vector<hipEvent_t> ev(2 * nt);
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) return hipErrorUnknown;
     hipError_t err = hipSuccess;
-    for (int cand = 0; cand < 2 && err == hipSuccess; ++cand) {
+    for (int cand = 0; cand < maxc && err == hipSuccess; ++cand) {
         for (auto &tu : tunables) tu.set(std::min(cand, tu.ncand - 1));
         for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {  // first run warms caches and code
             size_t k = 0;
@@ -168,7 +179,15 @@ hipError_t Program::autotune(hipStream_t s, std::vector<int> &choice) {
     for (auto &e : ev) (void)hipEventDestroy(e);
     choice.assign(nt, 0);
     for (size_t k = 0; k < nt; ++k)
-        if (tunables[k].ncand > 1 && t[1][k] < t[0][k]) choice[k] = 1;
+        for (int cnd = 1; cnd < tunables[k].ncand; ++cnd)
+            if (t[cnd][k] < t[choice[k]][k]) choice[k] = cnd;
+    if (std::getenv("LRCC_VERBOSE"))
+        for (size_t k = 0; k < nt; ++k) {
+            const size_t op = tunables[k].op;
+            std::fprintf(stderr, "[lrcc] autotune op %zu (%s):", op, op < names.size() ? names[op].c_str() : "");
+            for (int cnd = 0; cnd < tunables[k].ncand; ++cnd) std::fprintf(stderr, " %.3f", t[cnd][k]);
+            std::fprintf(stderr, " ms -> %d\n", choice[k]);
+        }
     apply(choice);
     return err;
 }
@@ -329,6 +348,8 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
     const i64 mA = max_off(g.M, g.sm, g.Am) + max_off(g.K, g.sk, g.Ak);
     const i64 mB = max_off(g.K, g.sk, g.Bk) + max_off(g.N, g.sn, g.Bn);
     const i64 mC = max_off(g.M, g.sm, g.Cm) + max_off(g.N, g.sn, g.Cn);
+    if (mA >= (i64)INT32_MAX || mB >= (i64)INT32_MAX)
+        throw LrccError(1, "GEMM operand block offsets exceed 32 bits");
     if ((int)segBeg.size() != g.njobs + 1 || segBeg.back() != (int)segA.size() || segA.size() != segB.size())
         throw LrccError(1, "inconsistent GEMM job lists");
     for (size_t s = 0; s < segA.size(); ++s)
@@ -362,6 +383,9 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
     g.segB = dB;
     g.njobs_all = g.njobs;
     g.job0 = 0;
+    g.sm = split_magic(g.sm);
+    g.sn = split_magic(g.sn);
+    g.sk = split_magic(g.sk);
     g.alt = 0;
     // split-K when the job x tile grid cannot fill the chip but the jobs have long reductions
     {
@@ -380,8 +404,9 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
     P.flops += P.last_flops;
     auto gp = std::make_shared<GemmArgs>(g);
     P.ops.push_back([gp](hipStream_t s) { return launch_gemm<T>(*gp, s); });
-    // candidates: the heuristic tile shape (0) or the alternative shape (1)
-    P.tunables.push_back({P.ops.size() - 1, 2, [gp](int c) { gp->alt = c; }});
+    // candidates: tile shapes, the heuristic one first
+    const std::vector<int> cand = gemm_candidates(g, sizeof(T) == 8);
+    P.tunables.push_back({P.ops.size() - 1, (int)cand.size(), [gp, cand](int c) { gp->shape = c == 0 ? -1 : cand[c]; }});
 }
 
 template <typename T>

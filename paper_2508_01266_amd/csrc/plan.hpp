@@ -4,6 +4,7 @@
 #include <complex>
 #include <functional>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -92,6 +93,10 @@ struct Program {
         tag_flops[t] += last_flops;
     }
     hipError_t run(hipStream_t s, Profiler *prof = nullptr);
+    hipError_t run_range(hipStream_t s, size_t begin, size_t end);
+    // the rebuild-in-LDS ladder launch of a sigma program (for multi-chain launches)
+    std::shared_ptr<LadderArgs> ladder_args;
+    size_t ladder_op = (size_t)-1;
     // Replay through a HIP graph captured on first use for this key (the
     // pointers the recorded launches read); `s` must not be the null stream.
     typedef std::array<const void *, 5> GraphKey;

@@ -44,6 +44,15 @@ def lib():
         L.lrcc_sigma_vjp_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_set_profiling.argtypes = [vp, i]
         L.lrcc_set_graphs.argtypes = [vp, i]
+        L.lrcc_group_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp)]
+        L.lrcc_group_create.restype = ctypes.c_int
+        L.lrcc_group_destroy.argtypes = [vp]
+        L.lrcc_group_destroy.restype = None
+        L.lrcc_group_last_error.argtypes = [vp]
+        L.lrcc_group_last_error.restype = ctypes.c_char_p
+        L.lrcc_group_apply_sigma_dev.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                                 ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp]
+        L.lrcc_group_apply_sigma_dev.restype = ctypes.c_int
         L.lrcc_set_ladder_mode.argtypes = [vp, i]
         L.lrcc_set_ladder_mode.restype = ctypes.c_int
         L.lrcc_set_autotune.argtypes = [vp, i]
@@ -67,6 +76,8 @@ def lib():
         L.lrcc_get_alpha.argtypes = [vp, i, vp]
         L.lrcc_alpha_dipole_gradient.argtypes = [vp, i, i, i, ctypes.POINTER(SolveOpts), vp]
         L.lrcc_alpha_dipole_gradient.restype = ctypes.c_int
+        L.lrcc_alpha_fock_gradient.argtypes = [vp, i, i, i, ctypes.POINTER(SolveOpts), vp]
+        L.lrcc_alpha_fock_gradient.restype = ctypes.c_int
         L.lrcc_solve_ccsd.argtypes = [vp, ctypes.c_double, i, vp, vp, dp, ctypes.POINTER(SolveReport)]
         L.lrcc_solve_ccsd.restype = ctypes.c_int
         L.lrcc_get_solution.argtypes = [vp, i, i, i, vp, vp]
@@ -221,6 +232,14 @@ class Context:
                                                        _ptr(g)))
         return g
 
+    def alpha_fock_gradient(self, ifreq, x, y, **opts):
+        """d alpha_xy(omega_ifreq) / d f at fixed amplitudes (lambda re-solved): complex
+        [nk][n][n] with d alpha = sum(grad * df) for Hermitian df.  Needs a preceding solve()."""
+        oo = self.solve_options(**opts)
+        g = np.zeros((self.nk, self.n, self.n), dtype=np.complex128)
+        self._check(self._L.lrcc_alpha_fock_gradient(self._h, int(ifreq), int(x), int(y), ctypes.byref(oo), _ptr(g)))
+        return g
+
     def solve_ccsd(self, tol=1e-9, max_iter=200):
         """Ground-state CCSD on the device; the result becomes the context's amplitudes.
         Returns (t1, t2, energy per cell, report)."""
@@ -298,3 +317,41 @@ class Context:
             ctypes.c_void_p(gx1.data_ptr()), ctypes.c_void_p(gx2.data_ptr()), int(precision),
             None if stream is None else ctypes.c_void_p(stream))
         self._check(st)
+
+
+class Group:
+    """Several chains whose sigma applications share one persistent ladder launch
+    (lrcc_group_*).  Holds references to the contexts; close() before them."""
+
+    def __init__(self, contexts):
+        self._L = lib()
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c._h for c in self.contexts])
+        h = ctypes.c_void_p()
+        st = self._L.lrcc_group_create(arr, len(self.contexts), ctypes.byref(h))
+        if st != 0:
+            raise LrccError(st, "lrcc_group_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lrcc_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_sigma_dev(self, xs1, xs2, ys1, ys2, omegas=None, precision=FP64, stream=None):
+        """Per-chain torch tensors (complex128, caller layouts); omegas: per-chain float64 tensors or None."""
+        n = len(self.contexts)
+        vp = ctypes.c_void_p
+        P = lambda ts: (vp * n)(*[t.data_ptr() for t in ts])
+        nr = (ctypes.c_int * n)(*[int(t.shape[0]) for t in xs1])
+        om = None if omegas is None else P(omegas)
+        st = self._L.lrcc_group_apply_sigma_dev(self._h, nr, om, P(xs1), P(xs2), P(ys1), P(ys2), int(precision),
+                                                None if stream is None else vp(stream))
+        if st != 0:
+            raise LrccError(st, self._L.lrcc_group_last_error(self._h).decode())

@@ -24,7 +24,7 @@ from __future__ import annotations
 import dataclasses
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "rng_for", "hamiltonian", "random_amplitudes",
+__all__ = ["Workload", "WORKLOADS", "rng_for", "hamiltonian", "random_amplitudes", "uneven_batch",
            "random_vectors", "kb_of", "omega_grid"]
 
 
@@ -155,3 +155,24 @@ def random_vectors(nrhs, nk, nocc, nvir, rng, s1=1.0, s2=1.0):
 def omega_grid(w: Workload):
     """List of (omega, sign) pairs solved for a workload."""
     return [(om, s) for om in w.omegas for s in w.signs]
+
+
+def uneven_batch(max_elems_per_chain=3.0e8, nrhs=12, seed=1266, max_draws=200):
+    """Twelve chains of an uneven batch: three each with Nk in {3, 5, 7, 9}, nocc drawn
+    from {6..12}, nvir from {30..80}, Naux = 3 (nocc + nvir), nrhs right-hand sides
+    (3 axes x 4 frequencies).  A chain whose doubles vector would exceed
+    max_elems_per_chain complex elements (nrhs * Nk^3 * nocc^2 * nvir^2) is re-drawn,
+    so the larger k meshes end up at the small end of the orbital ranges.  Returns a
+    list of Workload records (cfg_id 5)."""
+    rng = np.random.default_rng([seed, 5])
+    out = []
+    for nk in (3, 3, 3, 5, 5, 5, 7, 7, 7, 9, 9, 9):
+        for _ in range(max_draws):
+            o = int(rng.integers(6, 13))
+            v = int(rng.integers(30, 81))
+            if nrhs * nk ** 3 * o * o * v * v <= max_elems_per_chain:
+                break
+        else:
+            o, v = 6, 30
+        out.append(Workload(5, nk, o, v, 3 * (o + v), (0.02, 0.04, 0.0656, 0.1), (+1, -1), True))
+    return out

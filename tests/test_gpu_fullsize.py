@@ -36,20 +36,30 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_batched_workload_sampled_rhs(prec):
+def test_batched_workload_sampled_rhs():
+    """All 48 right-hand sides in one launch, both precisions, both ladder modes (integrals
+    stored / rebuilt in LDS); sampled right-hand sides against the k-blocked oracle."""
     import paper_2508_01266_amd as lr
     w, H, t1, t2, x1, x2, om = _inputs("c3", 48)
-    c = lr.Context(0)
-    c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
-    c.set_amplitudes(t1, t2)
-    y1, y2 = c.apply_sigma(x1, x2, om, prec)
-    for r in (0, 29):
+    out = {}
+    for mode in (2, 1):
+        c = lr.Context(0)
+        c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+        c.set_ladder_mode(mode)
+        c.set_amplitudes(t1, t2)
+        for prec in (lr.FP64, lr.FP32):
+            y1, y2 = c.apply_sigma(x1, x2, om, prec)
+            out[(mode, prec)] = (y1[[0, 29]], y2[[0, 29]])
+        c.close()
+        print(f"ladder mode {mode}: device sigmas done", flush=True)
+    for i, r in enumerate((0, 29)):
         r1, r2 = _oracle_one(w, H, t1, t2, x1[r], x2[r], om[r])
-        e1, e2 = _rel(y1[r], r1), _rel(y2[r], r2)
-        tol = 1e-11 if prec == 0 else 4 * w.nk * w.nvir ** 2 * 2.0 ** -24
-        print(f"c3 48-rhs launch, rhs {r}, prec {prec}: rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
-        assert e1 < tol and e2 < tol
+        for (mode, prec), (y1, y2) in out.items():
+            e1, e2 = _rel(y1[i], r1), _rel(y2[i], r2)
+            tol = 1e-11 if prec == lr.FP64 else 4 * w.nk * w.nvir ** 2 * 2.0 ** -24
+            print(f"c3 48-rhs launch, rhs {r}, ladder mode {mode}, prec {prec}: rel err singles {e1:.2e} "
+                  f"doubles {e2:.2e} (tol {tol:.1e})", flush=True)
+            assert e1 < tol and e2 < tol
 
 
 def test_large_orbital_slice_forward_and_transpose():
