@@ -236,3 +236,21 @@ def dense_jacobian(t, h: ccsd.DenseHam):
         A[:, k] = to_independent(sigma(t, unit_vector(k, h.no, h.nv, singles, doubles), h),
                                  singles, doubles)
     return A
+
+
+def excitation_energies(t, h: ccsd.DenseHam, nk=1):
+    """EOM-CCSD excitation energies: the eigenvalues of the CCSD Jacobian, i.e. the
+    poles of the linear response function (Sec. II.B), on the excitations that
+    conserve crystal momentum (k_i = k_a, k_i + k_j = k_a + k_b; Eq. momentum), in
+    ascending order of their real part.  Dense: tiny systems only."""
+    no, nv = h.no, h.nv
+    o, v = no // nk, nv // nk
+    singles, doubles = antisym_basis(no, nv)
+    ks = [(i, a) for (i, a) in singles if i // o == a // v]
+    kd = [(i, j, a, b) for (i, j, a, b) in doubles if (i // o + j // o - a // v - b // v) % nk == 0]
+    n = len(ks) + len(kd)
+    A = np.zeros((n, n), dtype=np.complex128)
+    for k in range(n):
+        A[:, k] = to_independent(sigma(t, unit_vector(k, no, nv, ks, kd), h), ks, kd)
+    w = np.linalg.eigvals(A)
+    return w[np.argsort(w.real, kind="stable")]

@@ -202,3 +202,21 @@ def test_paper_rhs_equals_xi_of_transposed_operator():
     y1, y2 = response.xi((t1, t2), Xr, s['h'])
     z1, z2 = response.xi((t1, t2), Xr.T.contiguous(), s['h'])
     assert float((y1 - z1).abs().max()) < 1e-15 and float((y2 - z2).abs().max()) < 1e-15
+
+
+@pytest.mark.parametrize("nk,o,v", [(1, 2, 4), (2, 1, 3)])
+def test_excitation_energies_equal_two_electron_spectrum(nk, o, v):
+    """Two electrons: EOM-CCSD is exact, so the eigenvalues of the CCSD Jacobian on the
+    momentum-conserving excitations are excitation energies of the exact spectrum (all of
+    them at Nk = 1, where singles and doubles span every excited determinant)."""
+    s = tiny_system(nk, o, v, naux=8, seed=12)
+    t1, t2, E, _ = solvers.solve_ccsd(s['h'])
+    w = response.excitation_energies((t1, t2), s['h'], nk=nk)
+    ops = dipoles(s)
+    _, e0, exc = fockspace.fci_polarizability(s['f'], s['g'], nk * o, ops[0].numpy(), ops[0].numpy(), [0.0])
+    assert np.abs(w.imag).max() < 1e-9
+    for x in w.real:
+        assert np.abs(exc - x).min() < 1e-10
+    if nk == 1:
+        assert len(w) == len(exc)
+        assert np.abs(np.sort(w.real) - np.sort(exc)).max() < 1e-10
