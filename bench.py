@@ -331,6 +331,8 @@ def main():
             "reports": {k: res[k][2] for k in res},
         }
     if args.uneven:
+        ctx.close()               # the twelve chains need the memory
+        torch.cuda.empty_cache()
         out["uneven_batch"] = uneven_batch(lr, torch, max(1, args.steps))
     if not args.no_cpu:
         log("timing the CPU oracle sample")

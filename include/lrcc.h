@@ -276,6 +276,18 @@ lrcc_status lrcc_group_apply_sigma_dev(lrcc_group *group, const int *nrhs, const
                                        const void *const *x1, const void *const *x2, void *const *y1,
                                        void *const *y2, int precision, void *stream);
 
+/* EOM-CCSD excitation energies: the nroots eigenvalues of the CCSD Jacobian with
+ * the lowest real parts on the momentum-conserving excitations, i.e. the poles
+ * of the linear response function (Sec. II.B) that alpha(omega) diverges at.
+ * Davidson iteration on the device sigma (complex128) with the dressed diagonal
+ * preconditioner; Rayleigh-Ritz on the small projected matrix on the host.
+ * omega: host [nroots] complex (Hartree), ascending real part.  tol: residual
+ * norm ||(A - theta) x|| for unit x (<= 0: 1e-8); max_iter (<= 0: 200).
+ * LRCC_E_ARG unless 1 <= nroots <= nk*nocc*nvir; LRCC_E_STATE before amplitudes;
+ * LRCC_E_NOCONV when not converged (omega then holds the current estimates). */
+lrcc_status lrcc_eom_roots(lrcc_ctx *ctx, int nroots, double tol, int max_iter, double *omega,
+                           lrcc_solve_report *report);
+
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */
 lrcc_status lrcc_get_alpha(lrcc_ctx *ctx, int nfreq, double *alpha);

@@ -23,6 +23,7 @@
 #include "elem.hpp"
 #include "plan.hpp"
 #include "solver.hpp"
+#include "eig.hpp"
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -1325,15 +1326,23 @@ void eta_vector(lrcc_ctx *c, int x, const Vecs &out, hipStream_t st) {
 // derivative is exact; y is in caller layout (per-cell normalisation).  Leaves
 // the device amplitudes shifted: the caller restores them from (T1, T2) and
 // re-runs the amplitude-dependent blocks when all stencils are done.
+// With p0 = A(T)^T lambda at the unshifted amplitudes (the same for every y), three
+// shifted points suffice: p'(0) = (6 p(h) - 2 p(-h) - p(2h) - 3 p(0)) / (6h) is exact for
+// the cubic p(e) = A(T + e y)^T lambda.
 void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vecs &q, const void *T1,
-              const void *T2, hipStream_t st) {
+              const void *T2, hipStream_t st, const Vecs *p0 = nullptr) {
     const int nk = c->nk;
     const i64 n1 = D.n1, n2 = D.n2;
     State<double> &S = c->s64;
     const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
     Program *adj = sigma_program(c, LRCC_FP64, 1, true);
-    const double coef[4] = {1.0, -8.0, 8.0, -1.0};
-    const int shift[4] = {-2, -1, 1, 2};
+    const double coef5[4] = {1.0 / 12.0, -8.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0};
+    const int shift5[4] = {-2, -1, 1, 2};
+    const double coef3[3] = {-2.0 / 6.0, 6.0 / 6.0, -1.0 / 6.0};
+    const int shift3[3] = {-1, 1, 2};
+    const int npt = p0 ? 3 : 4;
+    const double *coef = p0 ? coef3 : coef5;
+    const int *shift = p0 ? shift3 : shift5;
     // step: |h y| about 1e-2 in the rms sense
     cd yy = 0;
     {
@@ -1343,9 +1352,17 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
     }
     const double rms = std::sqrt(std::max(yy.real(), 1e-300) / (double)(n1 + n2 / 4));
     const double h = 1e-2 / rms;
-    HIPCHK(hipMemsetAsync(Fy.s, 0, n1 * 16, st));
-    HIPCHK(hipMemsetAsync(Fy.d, 0, n2 * 16, st));
-    for (int k = 0; k < 4; ++k) {
+    if (p0) {
+        std::vector<cd> w0(1, cd(-3.0 / (6.0 * h), 0.0));
+        HIPCHK(hipMemcpy(D.alpha, w0.data(), 16, hipMemcpyHostToDevice));
+        HIPCHK(batched_axpby(Fy.s, p0->s, D.alpha, 0.0, 1, n1, st));
+        HIPCHK(batched_axpby(Fy.d, p0->d, D.alpha, 0.0, 1, n2, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } else {
+        HIPCHK(hipMemsetAsync(Fy.s, 0, n1 * 16, st));
+        HIPCHK(hipMemsetAsync(Fy.d, 0, n2 * 16, st));
+    }
+    for (int k = 0; k < npt; ++k) {
         // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
         HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
@@ -1359,7 +1376,7 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         run_precompute(c, false, st);
         c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
         HIPCHK(adj->run(st));
-        std::vector<cd> w(1, cd(coef[k] / (12.0 * h), 0.0));
+        std::vector<cd> w(1, cd(coef[k] / h, 0.0));
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipMemcpy(D.alpha, w.data(), 16, hipMemcpyHostToDevice));
         HIPCHK(batched_axpby(Fy.s, q.s, D.alpha, 1.0, 1, n1, st));
@@ -1370,6 +1387,13 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
     HIPCHK(hipMemcpyAsync(c->ybuf, y.s, n1 * 16, hipMemcpyDeviceToDevice, st));
     HIPCHK(c->prog_epp->run(st));
     HIPCHK(add_inplace<double>(Fy.s, c->ubuf, n1, st));
+}
+
+// p0 = A(T)^T lambda at the current amplitudes (shared by every F stencil)
+void lambda_product(lrcc_ctx *c, const Vecs &p0, hipStream_t st) {
+    Program *adj = sigma_program(c, LRCC_FP64, 1, true);
+    c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = p0.s; c->io_y2 = p0.d; c->io_omega = nullptr;
+    HIPCHK(adj->run(st));
 }
 
 // One-body density of R amplitude-space vectors a (caller layout, per-cell
@@ -1539,11 +1563,13 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         void *T1 = tmp.get(nt1 * 16), *T2 = tmp.get(nt2 * 16);
         HIPCHK(hipMemcpy(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice));
         HIPCHK(hipMemcpy(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice));
-        Vecs Fy = vec(1), q = vec(1);
+        Vecs Fy = vec(1), q = vec(1), p0 = vec(1);
+        lambda_product(c, p0, st);
+        ++extra_rhs_sig;
         for (int j = 0; j < nfreq; ++j)
             for (int b = 0; b < nax; ++b) {
-                f_vector(c, D, sub(X, (j * 2 + 0) * nax + b), Fy, q, T1, T2, st);
-                extra_rhs_sig += 4;
+                f_vector(c, D, sub(X, (j * 2 + 0) * nax + b), Fy, q, T1, T2, st, &p0);
+                extra_rhs_sig += 3;
                 for (int a = 0; a < nax; ++a) Fv[((size_t)j * nax + a) * nax + b] = bdot(Fy, sub(X, (j * 2 + 1) * nax + a));
             }
         HIPCHK(hipMemcpy(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice));
@@ -1631,10 +1657,11 @@ void alpha_dip_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, 
         HIPCHK(hipMemcpyAsync(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
-        Vecs q = vec(1);
+        Vecs q = vec(1), p0 = vec(1);
+        lambda_product(c, p0, st);
         for (int b = 0; b < nb; ++b) {
             Vecs bb = sub(B, b);
-            f_vector(c, D, tv[b], bb, q, T1, T2, st);
+            f_vector(c, D, tv[b], bb, q, T1, T2, st, &p0);
             HIPCHK(add_inplace<double>(bb.s, (eta_ax[b] == Y ? etaY : etaX).s, n1, st));
             HIPCHK(add_inplace<double>(bb.d, (eta_ax[b] == Y ? etaY : etaX).d, n2, st));
         }
@@ -1866,10 +1893,11 @@ void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o,
         HIPCHK(hipMemcpyAsync(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
-        Vecs q = vec(1);
+        Vecs q = vec(1), p0 = vec(1);
+        lambda_product(c, p0, st);
         for (int b = 0; b < 4; ++b) {
             Vecs bb = sub(B, b);
-            f_vector(c, D, tv[b], bb, q, T1, T2, st);
+            f_vector(c, D, tv[b], bb, q, T1, T2, st, &p0);
             const Vecs &e = b < 2 ? etaY : etaX;
             HIPCHK(add_inplace<double>(bb.s, e.s, n1, st));
             HIPCHK(add_inplace<double>(bb.d, e.d, n2, st));
@@ -1939,6 +1967,197 @@ void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o,
                 g[((size_t)k * n + p) * n + qq] =
                     -0.5 / nk * (G[0][((size_t)k * n + p) * n + qq] + std::conj(G[1][((size_t)k * n + qq) * n + p]));
     std::memcpy(out, g.data(), g.size() * 16);
+}
+
+// ---------------------------------------------------------------- EOM-CCSD excitation energies
+// The poles of the linear response function are the eigenvalues of the CCSD
+// Jacobian.  Davidson iteration on the device sigma (complex128, one vector per
+// application) with the Hermitian inner product of the solver (doubles weighted
+// 1/4), Rayleigh-Ritz on the projected matrix G = V^H A V (host, small_eig),
+// residuals r = (A - theta) x, corrections from the dressed diagonal
+// preconditioner at Re(theta), restarts from the current Ritz vectors.
+void eom_roots(lrcc_ctx *c, int nroots, double tol, int max_iter, std::vector<cd> &omega, lrcc_solve_report &rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int nk = c->nk, no = c->no, nv = c->nv;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
+    hipStream_t st = c->own_stream;
+    if (nroots < 1 || nroots > n1) throw LrccError(LRCC_E_ARG, "nroots must lie in 1..nk*nocc*nvir");
+    const int nguess = (int)std::min<i64>(n1, std::max(2 * nroots, nroots + 4));
+    const int mmax = std::max(nguess + 2 * nroots, std::min(80, 6 * nroots + 8));
+    DevMem mem;
+    Vecs Vb{mem.get((size_t)mmax * n1 * 16), mem.get((size_t)mmax * n2 * 16)};
+    Vecs Wb{mem.get((size_t)mmax * n1 * 16), mem.get((size_t)mmax * n2 * 16)};
+    Vecs Rb{mem.get((size_t)nroots * n1 * 16), mem.get((size_t)nroots * n2 * 16)};
+    Vecs Tb{mem.get((size_t)mmax * n1 * 16), mem.get((size_t)mmax * n2 * 16)};   // restart scratch
+    auto at = [&](const Vecs &b, int i) { Vecs u; u.s = (char *)b.s + (size_t)i * n1 * 16; u.d = (char *)b.d + (size_t)i * n2 * 16; return u; };
+    SolveCtx S;
+    S.c = c; S.R = 1; S.n1 = n1; S.n2 = n2; S.st = st;
+    S.part = mem.get((size_t)dot_blocks(n2) * 16 * 2);
+    S.dout = mem.get(32);
+    S.alpha = mem.get(32);
+    void *coef = mem.get((size_t)mmax * mmax * 16);
+    double *dom = (double *)mem.get(8);
+    Program *sig = sigma_program(c, LRCC_FP64, 1);
+    int napply = 0;
+    auto apply = [&](const Vecs &y, const Vecs &x) {
+        c->io_x1 = x.s; c->io_x2 = x.d; c->io_y1 = y.s; c->io_y2 = y.d; c->io_omega = nullptr;
+        HIPCHK(sig->run(st));
+        ++napply;
+    };
+    int m = 0;
+    std::vector<cd> G;   // m x m, row-major, G[i][j] = <V_i, W_j>
+    auto grow = [&](int mnew) {
+        std::vector<cd> H((size_t)mnew * mnew, 0.0);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) H[(size_t)i * mnew + j] = G[(size_t)i * m + j];
+        G.swap(H);
+    };
+    // orthonormalise candidate u (in place) against V[0..m) twice; append it (and A u) if it survives
+    auto add = [&](const Vecs &u) {
+        double n0 = S.norm(u)[0];
+        if (n0 == 0) return false;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < m; ++i) {
+                const cd h = S.dot(at(Vb, i), u)[0];
+                S.axpby(u, at(Vb, i), std::vector<cd>(1, -h), 1.0);
+            }
+        const double nu = S.norm(u)[0];
+        if (nu < 1e-8 * n0 || m >= mmax) return false;
+        S.axpby(at(Vb, m), u, std::vector<cd>(1, cd(1.0 / nu, 0.0)), 0.0);
+        apply(at(Wb, m), at(Vb, m));
+        grow(m + 1);
+        for (int i = 0; i <= m; ++i) {
+            G[(size_t)i * (m + 1) + m] = S.dot(at(Vb, i), at(Wb, m))[0];
+            if (i < m) G[(size_t)m * (m + 1) + i] = S.dot(at(Vb, m), at(Wb, i))[0];
+        }
+        ++m;
+        return true;
+    };
+    // initial guesses: singles at the smallest dressed diagonal differences
+    {
+        std::vector<double> eo((size_t)nk * no), ev((size_t)nk * nv);
+        HIPCHK(hipMemcpy(eo.data(), c->s64.d_o1, eo.size() * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(ev.data(), c->s64.d_v1, ev.size() * 8, hipMemcpyDeviceToHost));
+        std::vector<std::pair<double, i64>> cand;
+        for (int k = 0; k < nk; ++k)
+            for (int i = 0; i < no; ++i)
+                for (int a = 0; a < nv; ++a)
+                    cand.push_back({ev[(size_t)k * nv + a] - eo[(size_t)k * no + i], ((i64)k * no + i) * nv + a});
+        std::stable_sort(cand.begin(), cand.end());
+        Vecs u = at(Rb, 0);
+        for (int g = 0; g < nguess && g < (int)cand.size(); ++g) {
+            HIPCHK(hipMemsetAsync(u.s, 0, n1 * 16, st));
+            HIPCHK(hipMemsetAsync(u.d, 0, n2 * 16, st));
+            const double one[2] = {1.0, 0.0};
+            HIPCHK(hipMemcpyAsync((char *)u.s + cand[g].second * 16, one, 16, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            (void)add(u);
+        }
+    }
+    rep = lrcc_solve_report{};
+    std::vector<cd> theta(nroots);
+    std::vector<double> res(nroots, 1e300);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        std::vector<cd> w, Vs;
+        if (!small_eig(m, G, w, Vs)) throw LrccError(LRCC_E_NOCONV, "subspace eigenproblem did not converge");
+        std::vector<int> ord(m);
+        for (int i = 0; i < m; ++i) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a].real() < w[b].real(); });
+        // residuals r_k = W s_k - theta_k V s_k
+        std::vector<cd> cw((size_t)nroots * m), cv((size_t)nroots * m);
+        for (int k = 0; k < nroots; ++k) {
+            theta[k] = w[ord[k]];
+            for (int i = 0; i < m; ++i) {
+                cw[(size_t)k * m + i] = Vs[(size_t)i * m + ord[k]];
+                cv[(size_t)k * m + i] = -theta[k] * Vs[(size_t)i * m + ord[k]];
+            }
+        }
+        HIPCHK(hipMemcpy(coef, cw.data(), cw.size() * 16, hipMemcpyHostToDevice));
+        HIPCHK(combine(Rb.s, Wb.s, coef, nroots, m, n1, 0.0, st));
+        HIPCHK(combine(Rb.d, Wb.d, coef, nroots, m, n2, 0.0, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(coef, cv.data(), cv.size() * 16, hipMemcpyHostToDevice));
+        HIPCHK(combine(Rb.s, Vb.s, coef, nroots, m, n1, 1.0, st));
+        HIPCHK(combine(Rb.d, Vb.d, coef, nroots, m, n2, 1.0, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool done = true;
+        for (int k = 0; k < nroots; ++k) {
+            res[k] = S.norm(at(Rb, k))[0];
+            if (res[k] > tol) done = false;
+        }
+        if (verbose()) {
+            std::fprintf(stderr, "[lrcc] eom iteration %d subspace %d:", it, m);
+            for (int k = 0; k < nroots; ++k) std::fprintf(stderr, " %.10f(%.1e)", theta[k].real(), res[k]);
+            std::fprintf(stderr, "\n");
+        }
+        if (done) break;
+        // restart from the Ritz vectors when the new directions would not fit
+        int nnew = 0;
+        for (int k = 0; k < nroots; ++k) nnew += res[k] > tol;
+        if (m + nnew > mmax) {
+            const int p = std::min(m, 2 * nroots + 2);
+            // orthonormal combinations of the p lowest Ritz vectors (coefficients in the orthonormal basis)
+            std::vector<cd> C((size_t)p * m);
+            int q = 0;
+            for (int k = 0; k < m && q < p; ++k) {
+                std::vector<cd> x(m);
+                for (int i = 0; i < m; ++i) x[i] = Vs[(size_t)i * m + ord[k]];
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int l = 0; l < q; ++l) {
+                        cd h = 0;
+                        for (int i = 0; i < m; ++i) h += std::conj(C[(size_t)l * m + i]) * x[i];
+                        for (int i = 0; i < m; ++i) x[i] -= h * C[(size_t)l * m + i];
+                    }
+                double nx = 0;
+                for (auto &e : x) nx += std::norm(e);
+                nx = std::sqrt(nx);
+                if (nx < 1e-8) continue;
+                for (int i = 0; i < m; ++i) C[(size_t)q * m + i] = x[i] / nx;
+                ++q;
+            }
+            HIPCHK(hipMemcpy(coef, C.data(), (size_t)q * m * 16, hipMemcpyHostToDevice));
+            HIPCHK(combine(Tb.s, Vb.s, coef, q, m, n1, 0.0, st));
+            HIPCHK(combine(Tb.d, Vb.d, coef, q, m, n2, 0.0, st));
+            HIPCHK(hipMemcpyAsync(Vb.s, Tb.s, (size_t)q * n1 * 16, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(Vb.d, Tb.d, (size_t)q * n2 * 16, hipMemcpyDeviceToDevice, st));
+            HIPCHK(combine(Tb.s, Wb.s, coef, q, m, n1, 0.0, st));
+            HIPCHK(combine(Tb.d, Wb.d, coef, q, m, n2, 0.0, st));
+            HIPCHK(hipMemcpyAsync(Wb.s, Tb.s, (size_t)q * n1 * 16, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(Wb.d, Tb.d, (size_t)q * n2 * 16, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            // G' = C^H G C
+            std::vector<cd> GC((size_t)m * q, 0.0), Gn((size_t)q * q, 0.0);
+            for (int i = 0; i < m; ++i)
+                for (int b = 0; b < q; ++b)
+                    for (int j = 0; j < m; ++j) GC[(size_t)i * q + b] += G[(size_t)i * m + j] * C[(size_t)b * m + j];
+            for (int a = 0; a < q; ++a)
+                for (int b = 0; b < q; ++b)
+                    for (int i = 0; i < m; ++i) Gn[(size_t)a * q + b] += std::conj(C[(size_t)a * m + i]) * GC[(size_t)i * q + b];
+            G.swap(Gn);
+            m = q;
+        }
+        // corrections (D - Re theta)^-1 r for the unconverged roots
+        for (int k = 0; k < nroots; ++k) {
+            if (res[k] <= tol) continue;
+            const double wr = theta[k].real();
+            HIPCHK(hipMemcpy(dom, &wr, 8, hipMemcpyHostToDevice));
+            Vecs u = at(Tb, 0);
+            const State<double> &T = c->s64;
+            HIPCHK(precond(u.s, u.d, at(Rb, k).s, at(Rb, k).d, (const double *)T.d_o1, (const double *)T.d_v1,
+                           (const double *)T.d_o2, (const double *)T.d_v2, dom, nk, 1, no, nv, st));
+            HIPCHK(hipStreamSynchronize(st));
+            (void)add(u);
+        }
+    }
+    omega = theta;
+    rep.converged = *std::max_element(res.begin(), res.end()) <= tol;
+    rep.outer = it + 1;
+    rep.sigma_fp64 = napply;
+    rep.rhs_sigmas = napply;
+    rep.max_rel_residual = *std::max_element(res.begin(), res.end());
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ---------------------------------------------------------------- ground-state CCSD
@@ -2607,6 +2826,20 @@ lrcc_status lrcc_group_apply_sigma_dev(lrcc_group *g, const int *nrhs, const dou
         g->err = e.what();
         return LRCC_E_ARG;
     }
+}
+
+lrcc_status lrcc_eom_roots(lrcc_ctx *c, int nroots, double tol, int max_iter, double *omega,
+                           lrcc_solve_report *report) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!omega) throw LrccError(LRCC_E_ARG, "null output");
+        std::vector<cd> w;
+        lrcc_solve_report rep{};
+        eom_roots(c, nroots, tol > 0 ? tol : 1e-8, max_iter > 0 ? max_iter : 200, w, rep);
+        std::memcpy(omega, w.data(), w.size() * 16);
+        if (report) *report = rep;
+        if (!rep.converged) throw LrccError(LRCC_E_NOCONV, "Davidson iteration did not converge");
+    });
 }
 
 lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {

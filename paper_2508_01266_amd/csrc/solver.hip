@@ -7,6 +7,8 @@
 #include "common.hpp"
 #include "solver.hpp"
 
+#include <algorithm>
+
 namespace lrcc {
 
 namespace {
@@ -146,6 +148,31 @@ __global__ void k_diag_real(const double2 *F, double *d, int nk, int n) {
 
 hipError_t diag_real(const void *F, double *d, int nk, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_diag_real, dim3((nk * n + 255) / 256), dim3(256), 0, s, (const double2 *)F, d, nk, n);
+    return hipGetLastError();
+}
+
+// Y[r] = beta Y[r] + sum_i C[r][i] V[i] for R outputs from m basis vectors of length n
+// (complex128; V and Y contiguous [m][n] and [R][n]; C on the device, [R][m])
+__global__ void k_combine(double2 *Y, const double2 *V, const double2 *C, int R, int m, i64 n, double beta) {
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
+        for (int r = 0; r < R; ++r) {
+            double2 acc = beta == 0.0 ? make_double2(0, 0) : Y[(i64)r * n + t];
+            acc.x *= beta;
+            acc.y *= beta;
+            for (int i = 0; i < m; ++i) {
+                const double2 c = C[r * m + i], v = V[(i64)i * n + t];
+                acc.x += c.x * v.x - c.y * v.y;
+                acc.y += c.x * v.y + c.y * v.x;
+            }
+            Y[(i64)r * n + t] = acc;
+        }
+    }
+}
+
+hipError_t combine(void *Y, const void *V, const void *C, int R, int m, i64 n, double beta, hipStream_t s) {
+    const i64 g = std::min<i64>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s, (double2 *)Y,
+                       (const double2 *)V, (const double2 *)C, R, m, n, beta);
     return hipGetLastError();
 }
 

@@ -14,4 +14,6 @@ hipError_t precond(void *o1, void *o2, const void *i1, const void *i2, const dou
                    const double *eo2, const double *ev2, const double *omega, int nk, int R, int no, int nv,
                    hipStream_t s);
 hipError_t diag_real(const void *F, double *d, int nk, int n, hipStream_t s);
+// Y[r] = beta Y[r] + sum_i C[r][i] V[i]  (complex128; V: [m][n], Y: [R][n], C: device [R][m])
+hipError_t combine(void *Y, const void *V, const void *C, int R, int m, i64 n, double beta, hipStream_t s);
 }  // namespace lrcc

@@ -53,6 +53,8 @@ def lib():
         L.lrcc_group_apply_sigma_dev.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                                  ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp]
         L.lrcc_group_apply_sigma_dev.restype = ctypes.c_int
+        L.lrcc_eom_roots.argtypes = [vp, i, ctypes.c_double, i, vp, ctypes.POINTER(SolveReport)]
+        L.lrcc_eom_roots.restype = ctypes.c_int
         L.lrcc_set_ladder_mode.argtypes = [vp, i]
         L.lrcc_set_ladder_mode.restype = ctypes.c_int
         L.lrcc_set_autotune.argtypes = [vp, i]
@@ -239,6 +241,14 @@ class Context:
         g = np.zeros((self.nk, self.n, self.n), dtype=np.complex128)
         self._check(self._L.lrcc_alpha_fock_gradient(self._h, int(ifreq), int(x), int(y), ctypes.byref(oo), _ptr(g)))
         return g
+
+    def eom_roots(self, nroots, tol=1e-8, max_iter=200):
+        """Lowest nroots EOM-CCSD excitation energies (complex, Hartree) and the report."""
+        w = np.zeros(nroots, dtype=np.complex128)
+        rep = SolveReport()
+        self._check(self._L.lrcc_eom_roots(self._h, int(nroots), float(tol), int(max_iter), _ptr(w),
+                                           ctypes.byref(rep)))
+        return w, rep.as_dict()
 
     def solve_ccsd(self, tol=1e-9, max_iter=200):
         """Ground-state CCSD on the device; the result becomes the context's amplitudes.
