@@ -20,6 +20,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1 GPU"
+
+# HBM traffic of one complex64 ladder launch on the batched workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the counter's reading for a plain 2 GiB copy
+# (fetch x2.0, write x1.0).  Valid only for the ladder sources it was measured on.
+LADDER_TRAFFIC = {"workload": "c3",
+                  "sources_sha256": "ae36c87f1fba76fad6dd59508cc630fa43632cfa601a44aec642592c40d5464b",
+                  "bytes": 949.2e9}
+
+
+def ladder_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ladder.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2508_01266_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 PEAK = {"f32": 157.3, "f64": 78.6}          # MI355X dense matrix-core TFLOP/s
 
 
@@ -242,6 +258,10 @@ def main():
     lad_exec = ctx.ladder_flops(nrhs, lr.FP32)
     lad_exec64 = ctx.ladder_flops(nrhs, lr.FP64)
     achieved = lad_exec / lad_avg / 1e12
+    traffic = None
+    if (args.workload == LADDER_TRAFFIC["workload"] and LADDER_TRAFFIC["bytes"] is not None
+            and LADDER_TRAFFIC["sources_sha256"] == ladder_sources_sha()):
+        traffic = LADDER_TRAFFIC["bytes"]
     out = {
         "metric": METRIC,
         "value": alg / dt32 / 1e12,
@@ -261,7 +281,7 @@ def main():
                                f"in LDS from the Cholesky vectors",
                    "nk": nk, "nocc": o, "nvir": v, "naux": w.naux, "nrhs": nrhs},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32"], "traffic": None, "kernel": "ladder",
+                     "frac": achieved / PEAK["f32"], "traffic": traffic, "kernel": "ladder",
                      "ladder_ms_avg": lad_avg * 1e3, "executed_flops_per_launch": lad_exec,
                      "algorithmic_flops_per_launch": lad, "algorithmic_tflops": lad / lad_avg / 1e12},
         "fp64": {"value": alg / dt64 / 1e12, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,

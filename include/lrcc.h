@@ -237,7 +237,8 @@ lrcc_status lrcc_solve_response_dev(lrcc_ctx *ctx, int nrhs, const double *omega
  * the polarizability per cell (reading of the paper's sign and symmetrisation
  * conventions as documented with the library).  opts->precision selects the
  * plain complex128 solver or complex64 matrix-core corrections inside complex128
- * refinement; the residual tolerance, subspace size and memory cap come from
+ * refinement (the one-vector lambda solve is always complex128); the residual
+ * tolerance, subspace size and memory cap come from
  * opts (NULL: defaults).  Results stay in the context: lrcc_get_alpha,
  * lrcc_get_solution, lrcc_get_lambda. */
 lrcc_status lrcc_solve(lrcc_ctx *ctx, unsigned axis_mask, int nfreq, const double *omega,
@@ -287,6 +288,19 @@ lrcc_status lrcc_group_apply_sigma_dev(lrcc_group *group, const int *nrhs, const
  * LRCC_E_NOCONV when not converged (omega then holds the current estimates). */
 lrcc_status lrcc_eom_roots(lrcc_ctx *ctx, int nroots, double tol, int max_iter, double *omega,
                            lrcc_solve_report *report);
+
+/* alpha [nfreq][3][3] (as lrcc_get_alpha) from the non-symmetric form of the
+ * response function with perturbed multipliers (the formulation of Eq. lrf with
+ * lambda-bar, Sec. II.B): lambda-bar^Y(s w) = (A + s w)^-T (eta^Y + F(., t^Y(s w)))
+ * for every solved axis, frequency and sign in one batched transpose solve
+ * (opts as for lrcc_solve, NULL: defaults), then
+ *   g_XY(s w) = eta^X t^Y(s w) - <lambda-bar^Y(s w), xi^X>,
+ *   alpha_XY(w) = -1/(2 Nk) [g_XY(w) + conj(g_XY(-w))].
+ * Uses the response amplitudes and lambda of the last lrcc_solve (LRCC_E_STATE
+ * without one; LRCC_E_ARG if nfreq differs); equals its symmetric alpha up to
+ * the solver tolerances. */
+lrcc_status lrcc_alpha_lambda_bar(lrcc_ctx *ctx, int nfreq, const lrcc_solve_opts *opts, double *alpha,
+                                  lrcc_solve_report *report);
 
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */

@@ -539,7 +539,18 @@ void upload_amplitudes(lrcc_ctx *c, const double *t1h, const double *t2h) {
 
 // Recompute every amplitude-dependent block from the device amplitudes.
 void run_precompute(lrcc_ctx *c, bool fp32, hipStream_t st = nullptr) {
-    HIPCHK(c->pre64->run(st));
+    static const bool timed = std::getenv("LRCC_PRE_TIMES") != nullptr;   // per-op timing report
+    if (timed) {
+        const bool was = c->prof.on;
+        c->prof.on = true;
+        HIPCHK(c->pre64->run(st, &c->prof));
+        HIPCHK(hipStreamSynchronize(st));
+        double ms[NTAGS];
+        long long cnt[NTAGS];
+        c->prof.read(ms, cnt);
+        c->prof.on = was;
+    } else
+        HIPCHK(c->pre64->run(st));
     if (fp32) HIPCHK(c->pre32->run(st));
     HIPCHK(hipStreamSynchronize(st));
 }
@@ -1512,7 +1523,11 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         HIPCHK(hipMemset(c->lam1, 0, n1 * 16));
         HIPCHK(hipMemset(c->lam2, 0, n2 * 16));
         Vecs b{c->gb1, c->gb2};
-        solve_response(c, 1, (const double *)zero_om, b, lam, o, r1, st, true);
+        // one right-hand side: launch-latency bound, so complex128 throughout (the complex64
+        // corrections only add refinement steps here)
+        lrcc_solve_opts ol = o;
+        ol.precision = LRCC_FP64;
+        solve_response(c, 1, (const double *)zero_om, b, lam, ol, r1, st, true);
         if (!r1.converged) throw LrccError(LRCC_E_NOCONV, "lambda equations did not converge");
         c->lam_valid = true;
     }
@@ -1600,6 +1615,95 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+
+// ---------------------------------------------------------------- non-symmetric (lambda-bar) form of alpha
+// With the perturbed multipliers lambda-bar^Y(s w) = (A + s w)^-T (eta^Y + F(., t^Y(s w)))
+// (one batched transpose solve over all axes, frequencies and signs), the response
+// function needs the amplitudes of one operator only:
+//   g_XY(s w) = eta^X t^Y(s w) - <lambda-bar^Y(s w), xi^X>,
+//   alpha_XY(w) = -1/(2 Nk) [g_XY(w) + conj(g_XY(-w))],
+// which equals the symmetric form for exact solutions (the identity the two
+// formulations share; it checks the F term and the transpose solver).
+void alpha_lambda_bar(lrcc_ctx *c, const lrcc_solve_opts &o, double *out, lrcc_solve_report &rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int nk = c->nk, no = c->no, nv = c->nv;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    const auto &axes = c->axes;
+    const int nax = (int)axes.size(), nfreq = c->nfreq;
+    if (!c->lam_valid || !c->sol1 || c->nrhs_sol != nfreq * 2 * nax || nax == 0)
+        throw LrccError(LRCC_E_STATE, "lrcc_solve must precede the lambda-bar form");
+    hipStream_t st = c->own_stream;
+    const int R = nfreq * 2 * nax;
+    DevMem tmp;
+    auto vec = [&](int r) { Vecs v; v.s = tmp.get((size_t)r * n1 * 16); v.d = tmp.get((size_t)r * n2 * 16); return v; };
+    auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
+    Vecs X{c->sol1, c->sol2};
+    SolveCtx D;
+    D.c = c; D.R = 1; D.n1 = n1; D.n2 = n2; D.st = st;
+    D.part = tmp.get((size_t)dot_blocks(n2) * 16 * 2);
+    D.dout = tmp.get(32);
+    D.alpha = tmp.get(32);
+    auto bdot = [&](const Vecs &u, const Vecs &v) {
+        cd a, b;
+        HIPCHK(batched_dot(u.s, v.s, 1, n1, 1.0, D.part, D.dout, st, 0));
+        HIPCHK(hipMemcpy(&a, D.dout, 16, hipMemcpyDeviceToHost));
+        HIPCHK(batched_dot(u.d, v.d, 1, n2, 0.25, D.part, D.dout, st, 0));
+        HIPCHK(hipMemcpy(&b, D.dout, 16, hipMemcpyDeviceToHost));
+        return a + b;
+    };
+    // right-hand sides, in the layout of the solutions: r = (j*2 + sign)*nax + a
+    std::vector<Vecs> eta(nax);
+    for (int a = 0; a < nax; ++a) { eta[a] = vec(1); eta_vector(c, axes[a], eta[a], st); }
+    Vecs B = vec(R), Lb = vec(R);
+    std::vector<double> om(R);
+    {
+        State<double> &S = c->s64;
+        const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+        void *T1 = tmp.get(nt1 * 16), *T2 = tmp.get(nt2 * 16);
+        HIPCHK(hipMemcpyAsync(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        Vecs q = vec(1), p0 = vec(1);
+        lambda_product(c, p0, st);
+        for (int j = 0; j < nfreq; ++j)
+            for (int sg = 0; sg < 2; ++sg)
+                for (int a = 0; a < nax; ++a) {
+                    const int r = (j * 2 + sg) * nax + a;
+                    // (A + s w)^T: the solver applies (A - omega_r)^T
+                    om[r] = sg == 0 ? -c->last_omega[j] : c->last_omega[j];
+                    Vecs b = sub(B, r);
+                    f_vector(c, D, sub(X, r), b, q, T1, T2, st, &p0);
+                    HIPCHK(add_inplace<double>(b.s, eta[a].s, n1, st));
+                    HIPCHK(add_inplace<double>(b.d, eta[a].d, n2, st));
+                }
+        HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        run_precompute(c, true, st);
+    }
+    void *dom = tmp.get((size_t)R * 8);
+    HIPCHK(hipMemcpy(dom, om.data(), R * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(Lb.s, 0, (size_t)R * n1 * 16));
+    HIPCHK(hipMemset(Lb.d, 0, (size_t)R * n2 * 16));
+    solve_response(c, R, (const double *)dom, B, Lb, o, rep, st, true);
+    if (!rep.converged) throw LrccError(LRCC_E_NOCONV, "perturbed lambda equations did not converge");
+    std::vector<double> al((size_t)nfreq * 9 * 2, 0.0);
+    for (int j = 0; j < nfreq; ++j)
+        for (int x = 0; x < nax; ++x)
+            for (int y = 0; y < nax; ++y) {
+                cd g[2];
+                for (int sg = 0; sg < 2; ++sg) {
+                    const int ry = (j * 2 + sg) * nax + y;
+                    Vecs xi{(char *)c->xi1 + (size_t)axes[x] * n1 * 16, (char *)c->xi2 + (size_t)axes[x] * n2 * 16};
+                    g[sg] = bdot(eta[x], sub(X, ry)) - bdot(sub(Lb, ry), xi);
+                }
+                const cd v = -0.5 * (g[0] + std::conj(g[1])) / (double)nk;
+                const size_t idx = ((size_t)j * 9 + axes[x] * 3 + axes[y]) * 2;
+                al[idx] = v.real();
+                al[idx + 1] = v.imag();
+            }
+    std::memcpy(out, al.data(), al.size() * 8);
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
 
 // ---------------------------------------------------------------- dipole gradient of alpha
 // alpha_XY(w) = -1/(2 Nk) [g(w) + conj(g(-w))],
@@ -2839,6 +2943,21 @@ lrcc_status lrcc_eom_roots(lrcc_ctx *c, int nroots, double tol, int max_iter, do
         std::memcpy(omega, w.data(), w.size() * 16);
         if (report) *report = rep;
         if (!rep.converged) throw LrccError(LRCC_E_NOCONV, "Davidson iteration did not converge");
+    });
+}
+
+lrcc_status lrcc_alpha_lambda_bar(lrcc_ctx *c, int nfreq, const lrcc_solve_opts *opts, double *alpha,
+                                  lrcc_solve_report *report) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!alpha) throw LrccError(LRCC_E_ARG, "null output");
+        if (nfreq != c->nfreq) throw LrccError(LRCC_E_ARG, "nfreq does not match the last solve");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        lrcc_solve_report rep{};
+        alpha_lambda_bar(c, o, alpha, rep);
+        if (report) *report = rep;
     });
 }
 

@@ -53,6 +53,8 @@ def lib():
         L.lrcc_group_apply_sigma_dev.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                                  ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp]
         L.lrcc_group_apply_sigma_dev.restype = ctypes.c_int
+        L.lrcc_alpha_lambda_bar.argtypes = [vp, i, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveReport)]
+        L.lrcc_alpha_lambda_bar.restype = ctypes.c_int
         L.lrcc_eom_roots.argtypes = [vp, i, ctypes.c_double, i, vp, ctypes.POINTER(SolveReport)]
         L.lrcc_eom_roots.restype = ctypes.c_int
         L.lrcc_set_ladder_mode.argtypes = [vp, i]
@@ -241,6 +243,14 @@ class Context:
         g = np.zeros((self.nk, self.n, self.n), dtype=np.complex128)
         self._check(self._L.lrcc_alpha_fock_gradient(self._h, int(ifreq), int(x), int(y), ctypes.byref(oo), _ptr(g)))
         return g
+
+    def alpha_lambda_bar(self, nfreq, **opts):
+        """alpha [nfreq][3][3] of the last solve() from the non-symmetric (perturbed-lambda) form."""
+        oo = self.solve_options(**opts)
+        a = np.zeros((nfreq, 3, 3), dtype=np.complex128)
+        rep = SolveReport()
+        self._check(self._L.lrcc_alpha_lambda_bar(self._h, int(nfreq), ctypes.byref(oo), _ptr(a), ctypes.byref(rep)))
+        return a, rep.as_dict()
 
     def eom_roots(self, nroots, tol=1e-8, max_iter=200):
         """Lowest nroots EOM-CCSD excitation energies (complex, Hartree) and the report."""

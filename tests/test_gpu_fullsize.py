@@ -83,3 +83,69 @@ def test_large_orbital_slice_forward_and_transpose():
         rhs = np.sum(a1[r] * x1[r]) + 0.25 * np.sum(a2[r] * x2[r])
         print(f"slice dot identity rhs {r}: {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
         assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_c4_forward_modes_and_transpose():
+    """Nk=7, o=10, v=60, Naux=210 (2 RHS): the two independent ladder paths (integrals rebuilt
+    in LDS, stored integral blocks) agree, and the transpose product satisfies the dot identity
+    with the forward product (properties that hold at any size; the oracle is too slow here)."""
+    import paper_2508_01266_amd as lr
+    w, H, t1, t2, x1, x2, om = _inputs("c4", 2)
+    ys = {}
+    for mode in (1, 2):
+        c = lr.Context(0)
+        c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+        c.set_ladder_mode(mode)
+        c.set_amplitudes(t1, t2)
+        ys[mode] = c.apply_sigma(x1, x2, om, lr.FP64)
+        if mode == 1:
+            rng = synth.rng_for(98, 7, 10, 60)
+            z1, z2 = synth.random_vectors(2, 7, 10, 60, rng, 0.1, 0.1)
+            z2 = z2 * 7
+            a1, a2 = c.apply_sigma_adjoint(z1, z2, om, lr.FP64)
+        c.close()
+        print(f"c4 ladder mode {mode}: forward done", flush=True)
+    e1, e2 = _rel(ys[1][0], ys[2][0]), _rel(ys[1][1], ys[2][1])
+    print(f"c4 rebuilt vs stored ladder integrals: rel diff singles {e1:.2e} doubles {e2:.2e}", flush=True)
+    assert e1 < 1e-11 and e2 < 1e-11
+    y1, y2 = ys[1]
+    for r in range(2):
+        lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
+        rhs = np.sum(a1[r] * x1[r]) + 0.25 * np.sum(a2[r] * x2[r])
+        print(f"c4 dot identity rhs {r}: {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_c4_dipole_gradient_against_finite_difference():
+    """Nk=7, o=10, v=60, Naux=210: device CCSD ground state, alpha_zz(0.0656) and its dipole
+    gradient; alpha is bilinear in mu_z at fixed amplitudes, so the central difference along a
+    Hermitian perturbation is exact up to the solver tolerance."""
+    import paper_2508_01266_amd as lr
+    w = synth.WORKLOADS["c4"]
+    rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=w.chol_sigma)
+    V = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, synth.rng_for(97, 7, 10, 60))['dip']
+    c = lr.Context(0)
+    c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+    t1, t2, e, rep = c.solve_ccsd(tol=1e-9, max_iter=300)
+    print(f"c4 CCSD: E/cell {e:.10f} {rep}", flush=True)
+    om = [0.0656]
+    a0, r0 = c.solve(om, axis_mask=4, tol=1e-11, precision=lr.FP64)
+    print(f"c4 alpha_zz {a0[0, 2, 2]} {r0}", flush=True)
+    g = c.alpha_dipole_gradient(0, 2, 2, tol=1e-11)
+    got = np.sum(g[2] * V[2])
+    hstep = 0.5
+    vals = []
+    for sgn in (1, -1):
+        dip = H['dip'].copy()
+        dip[2] = dip[2] + sgn * hstep * V[2]
+        c2 = lr.Context(0)
+        c2.set_hamiltonian(w.nocc, H['fock'], H['chol'], dip)
+        c2.set_amplitudes(t1, t2)
+        a, _ = c2.solve(om, axis_mask=4, tol=1e-11, precision=lr.FP64)
+        vals.append(a[0, 2, 2])
+        c2.close()
+    ref = (vals[0] - vals[1]) / (2 * hstep)
+    print(f"c4 d alpha_zz: gradient {got:.10f} central difference {ref:.10f}", flush=True)
+    assert abs(got - ref) < 1e-7 * max(1.0, abs(ref))
+    c.close()
