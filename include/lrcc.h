@@ -102,6 +102,20 @@ const char *lrcc_last_error(const lrcc_ctx *ctx);
 lrcc_status lrcc_set_hamiltonian(lrcc_ctx *ctx, int nk, int nocc, int nvir, int naux,
                                  const double *fock, const double *chol, const double *dip);
 
+/* Crystal-momentum mesh of the k points: n0 x n1 x n2 Monkhorst-Pack points
+ * k = (j0/n0, j1/n1, j2/n2) (reciprocal-lattice units), for three-dimensional
+ * periodicity (the extension of the 1D chains of Sec. II.A that Sec. V plans).
+ * Momentum is conserved modulo a reciprocal-lattice vector (Eq. momentum), so k
+ * points add componentwise modulo (n0, n1, n2).  Every k index of the other
+ * calls is then the flat index k = (j0 n1 + j1) n2 + j2, nk = n0 n1 n2, and
+ * every layout keeps its shape: t2 blocks (ki, kj, ka) with kb = ki + kj - ka on
+ * the mesh, chol[k1][k2] with momentum transfer k2 - k1 on the mesh.  Without
+ * this call (or with (nk, 1, 1)) the k points form a 1D chain.  Takes effect for
+ * the next lrcc_set_hamiltonian, whose nk must equal n0 n1 n2 (else LRCC_E_SHAPE),
+ * and discards the Hamiltonian, amplitudes and solutions set before.
+ * LRCC_E_ARG unless every extent is >= 1. */
+lrcc_status lrcc_set_kmesh(lrcc_ctx *ctx, int n0, int n1, int n2);
+
 /* Set the converged ground-state amplitudes T1, T2 (Eqs. t1, t2; T2 in the
  * paper's per-cell normalisation) and build every amplitude-dependent
  * intermediate of the Jacobian once (the fixed "tilde" blocks of Sec. II.B).
@@ -179,6 +193,10 @@ lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *ex
  * GPU and allocates no device memory.  On failure writes a message into msg
  * (msglen bytes, may be NULL) and returns LRCC_E_ARG (or LRCC_E_OOM). */
 lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char *msg, int msglen);
+/* The same on an n0 x n1 x n2 k mesh (lrcc_set_kmesh); lrcc_plan_check is the
+ * 1D chain (nk, 1, 1). */
+lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int naux, int nrhs, char *msg,
+                                 int msglen);
 
 /* Transpose product (the operator of the lambda equations l1, l2, Sec. II.B):
  * y_r = (A - omega_r)^T x_r, the transpose taken with respect to the bilinear
@@ -301,6 +319,23 @@ lrcc_status lrcc_eom_roots(lrcc_ctx *ctx, int nroots, double tol, int max_iter, 
  * the solver tolerances. */
 lrcc_status lrcc_alpha_lambda_bar(lrcc_ctx *ctx, int nfreq, const lrcc_solve_opts *opts, double *alpha,
                                   lrcc_solve_report *report);
+
+/* Polarizability in the velocity gauge (Sec. V): the perturbation operator is
+ * the momentum operator instead of the dipole.  mom: host [3][nk][n][n] complex,
+ * Hermitian per axis per k (matrix elements of the momentum operator p_x, p_y,
+ * p_z; LRCC_E_ARG otherwise).  One batched solve (as lrcc_solve, with opts) of
+ * the response to p at the frequencies 0, omega_0, ..., omega_{nfreq-1}, then
+ *   alpha^VG_XY(w) = (a_XY(w) - a_XY(0)) / w^2,   a_XY(w) = -<<p_X; p_Y>>_w / Nk,
+ * the symmetric response function of p in the form of lrcc_solve; subtracting
+ * the static response removes the diamagnetic term (which it equals for an exact
+ * state in a complete basis).  alpha: host [nfreq][3][3] complex (zeros for axes
+ * outside axis_mask or with vanishing p).  Every omega must be non-zero
+ * (LRCC_E_ARG).  The dipoles of lrcc_set_hamiltonian are kept for later solves;
+ * the stored solutions of the last lrcc_solve are discarded (lambda is kept:
+ * it does not depend on the perturbation). */
+lrcc_status lrcc_alpha_velocity_gauge(lrcc_ctx *ctx, unsigned axis_mask, int nfreq, const double *omega,
+                                      const double *mom, const lrcc_solve_opts *opts, double *alpha,
+                                      lrcc_solve_report *report);
 
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */

@@ -11,8 +11,9 @@ normalisation, as in `ccsd`.  Tensors are torch complex128 CPU tensors so the
 lambda equations can use reverse-mode derivatives as in `response`.
 
 Storage: a four-index tensor is [k0][k1][k2][d0][d1][d2][d3] with k3 implied by
-its momentum rule s0 k0 + s1 k1 + s2 k2 + s3 k3 = 0 (mod Nk); a two-index
-tensor is [k][d0][d1].
+its momentum rule s0 k0 + s1 k1 + s2 k2 + s3 k3 = 0 on the k mesh (`kmesh`:
+componentwise modulo the mesh extents; for a 1D chain, modulo Nk); a
+two-index tensor is [k][d0][d1].
 """
 from __future__ import annotations
 
@@ -21,6 +22,8 @@ import math
 
 import numpy as np
 import torch
+
+from .kmesh import mesh_of
 
 _C = torch.complex128
 
@@ -31,7 +34,8 @@ class KT:
     def __init__(self, data, sig, nk):
         self.data = data
         self.sig = tuple(sig)
-        self.nk = nk
+        self.mesh = mesh_of(nk)
+        self.nk = self.mesh.size
 
     @property
     def nidx(self):
@@ -39,22 +43,21 @@ class KT:
 
     def implied(self, ks):
         """k of the last index from the first nidx-1."""
-        s = sum(a * b for a, b in zip(self.sig[:-1], ks))
-        return (-self.sig[-1] * s) % self.nk
+        return self.mesh.signed([(-self.sig[-1] * a, b) for a, b in zip(self.sig[:-1], ks)])
 
     def block(self, ks):
         return self.data[tuple(ks[:-1])]
 
     def allowed(self, ks):
-        return sum(a * b for a, b in zip(self.sig, ks)) % self.nk == 0
+        return self.mesh.signed(list(zip(self.sig, ks))) == 0
 
     @staticmethod
     def zeros(nk, shape, sig):
-        pre = (nk,) * (len(sig) - 1)
+        pre = (mesh_of(nk).size,) * (len(sig) - 1)
         return KT(torch.zeros(pre + tuple(shape), dtype=_C), sig, nk)
 
     def new_like(self, data):
-        return KT(data, self.sig, self.nk)
+        return KT(data, self.sig, self.mesh)
 
     def __add__(self, other):
         return self.new_like(self.data + other.data)
@@ -80,7 +83,7 @@ def kein(spec, *ops, out_shape, out_sig):
     lhs, rhs = spec.split('->')
     labs = lhs.split(',')
     nk = ops[0].nk
-    out = KT.zeros(nk, out_shape, out_sig)
+    out = KT.zeros(ops[0].mesh, out_shape, out_sig)
     summed = sorted(set(''.join(labs)) - set(rhs))
     blocks_out = itertools.product(range(nk), repeat=len(rhs) - 1)
     for pre in blocks_out:
@@ -112,7 +115,7 @@ def permute(t: KT, perm, sig=None):
     n = t.nidx
     sig_out = tuple(t.sig[p] for p in perm) if sig is None else sig
     shape = tuple(t.data.shape[n - 1 + p] for p in perm)
-    out = KT.zeros(nk, shape, sig_out)
+    out = KT.zeros(t.mesh, shape, sig_out)
     for pre in itertools.product(range(nk), repeat=n - 1):
         ks = list(pre) + [out.implied(pre)]
         src = [None] * n
@@ -133,11 +136,15 @@ def p_ab(t):
 
 class KHam:
     """k-blocked Hamiltonian in crystal normalisation, built from the inputs of
-    the library boundary: fock [nk][n][n], chol [nk][nk][naux][n][n] (per-cell)."""
+    the library boundary: fock [nk][n][n], chol [nk][nk][naux][n][n] (per-cell),
+    on the k mesh `mesh` (default: a 1D chain of fock.shape[0] points)."""
 
-    def __init__(self, fock, chol, nocc):
+    def __init__(self, fock, chol, nocc, mesh=None):
         fock = np.asarray(fock)
         chol = np.asarray(chol)
+        self.mesh = mesh_of(fock.shape[0] if mesh is None else mesh)
+        if self.mesh.size != fock.shape[0]:
+            raise ValueError(f"{self.mesh} does not have {fock.shape[0]} points")
         self.nk = nk = fock.shape[0]
         self.n = n = fock.shape[1]
         self.no = o = nocc
@@ -155,7 +162,7 @@ class KHam:
     def fblock(self, cls):
         """One-electron block f_{pq} of orbital classes cls (k-diagonal)."""
         a, b = self.slice(cls[0]), self.slice(cls[1])
-        return KT(self.f[:, a, b].clone(), DIAG2, self.nk)
+        return KT(self.f[:, a, b].clone(), DIAG2, self.mesh)
 
     def eri(self, cls):
         """<pq||rs> blocks for orbital classes cls (e.g. 'oovv'), crystal normalised:
@@ -164,9 +171,9 @@ class KHam:
             return self._eri[cls]
         nk = self.nk
         sp, sq, sr, ss = (self.slice(c) for c in cls)
-        out = KT.zeros(nk, tuple(self.ext(c) for c in cls), STD4)
+        out = KT.zeros(self.mesh, tuple(self.ext(c) for c in cls), STD4)
         for kp, kq, kr in itertools.product(range(nk), repeat=3):
-            ks = (kp + kq - kr) % nk
+            ks = self.mesh.comb(kp, kq, kr)
             Lpr = self.L[kp, kr][:, sp, sr]
             Lsq = self.L[ks, kq][:, ss, sq]
             Lps = self.L[kp, ks][:, sp, ss]
@@ -261,7 +268,7 @@ def residual(h: KHam, t1: KT, t2: KT):
 
 def permute_2(t: KT):
     """Transpose of a k-diagonal two-index tensor."""
-    return KT(t.data.transpose(1, 2).clone(), DIAG2, t.nk)
+    return KT(t.data.transpose(1, 2).clone(), DIAG2, t.mesh)
 
 
 def energy(h: KHam, t1: KT, t2: KT):
@@ -277,7 +284,7 @@ def energy(h: KHam, t1: KT, t2: KT):
 def sigma(h: KHam, t, x, step=0.05):
     """A x (Jacobian of the residual) by the exact 5-point central difference.
     t = (t1 [nk][o][v], t2 [nk^3 blocks]) and x likewise, crystal normalisation."""
-    nk = h.nk
+    nk = h.mesh
     T1, T2 = t1_kt(t[0], nk), t2_kt(t[1], nk)
     X1, X2 = t1_kt(x[0], nk), t2_kt(x[1], nk)
     sc = max(float(X1.data.abs().max()), float(X2.data.abs().max()))
@@ -293,5 +300,5 @@ def sigma(h: KHam, t, x, step=0.05):
 def xi(h: KHam, t, op):
     """xi^X: the residual with f -> X (per-k one-body matrices [nk][n][n]) and no two-electron part."""
     hx = h.zero_two_body(op)
-    r1, r2 = residual(hx, t1_kt(t[0], h.nk), t2_kt(t[1], h.nk))
+    r1, r2 = residual(hx, t1_kt(t[0], h.mesh), t2_kt(t[1], h.mesh))
     return r1.data, r2.data

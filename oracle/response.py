@@ -28,6 +28,7 @@ import numpy as np
 import torch
 
 from . import ccsd
+from .kmesh import mesh_of
 from .solvers import gmres
 
 _C = torch.complex128
@@ -195,8 +196,24 @@ def polarizability(t, lam, ops, omegas, h: ccsd.DenseHam, nk=1, tol=1e-12, sols=
                            + f_form(t, lam, tX, tY, h))
         for X in range(nax):
             for Y in range(nax):
-                alpha[iw, X, Y] = -0.5 * (g(X, Y, +1) + np.conj(g(X, Y, -1))) / nk
+                alpha[iw, X, Y] = -0.5 * (g(X, Y, +1) + np.conj(g(X, Y, -1))) / mesh_of(nk).size
     return alpha, sols
+
+
+def polarizability_velocity(t, lam, moms, omegas, h: ccsd.DenseHam, nk=1, tol=1e-12):
+    """Velocity-gauge polarizability from momentum operators `moms` (3 axes, dense N x N).
+
+    With the momentum operator as the perturbation the response function gives
+    <<p_X; p_Y>>_w, and alpha^VG_XY(w) = -(<<p_X; p_Y>>_w - <<p_X; p_Y>>_0) / w^2:
+    the static response is subtracted in place of the diamagnetic term, which equals
+    it for an exact state in a complete basis (the modified velocity gauge of the
+    reference cited with the velocity gauge in Sec. V).  `polarizability` with the
+    momentum operators returns a(w) = -<<p;p>>_w per cell, so alpha^VG = (a(w) - a(0)) / w^2.
+    Every frequency must be non-zero.  Returns alpha[w][X][Y]."""
+    if any(w == 0 for w in omegas):
+        raise ValueError("the velocity-gauge polarizability is defined for non-zero frequencies")
+    a, _ = polarizability(t, lam, moms, [0.0] + list(omegas), h, nk=nk, tol=tol)
+    return np.stack([(a[i + 1] - a[0]) / w ** 2 for i, w in enumerate(omegas)])
 
 
 def antisym_basis(no, nv):
@@ -241,13 +258,15 @@ def dense_jacobian(t, h: ccsd.DenseHam):
 def excitation_energies(t, h: ccsd.DenseHam, nk=1):
     """EOM-CCSD excitation energies: the eigenvalues of the CCSD Jacobian, i.e. the
     poles of the linear response function (Sec. II.B), on the excitations that
-    conserve crystal momentum (k_i = k_a, k_i + k_j = k_a + k_b; Eq. momentum), in
-    ascending order of their real part.  Dense: tiny systems only."""
+    conserve crystal momentum (k_i = k_a, k_i + k_j = k_a + k_b on the k mesh;
+    Eq. momentum), in ascending order of their real part.  Dense: tiny systems only."""
+    m = mesh_of(nk)
     no, nv = h.no, h.nv
-    o, v = no // nk, nv // nk
+    o, v = no // m.size, nv // m.size
     singles, doubles = antisym_basis(no, nv)
     ks = [(i, a) for (i, a) in singles if i // o == a // v]
-    kd = [(i, j, a, b) for (i, j, a, b) in doubles if (i // o + j // o - a // v - b // v) % nk == 0]
+    kd = [(i, j, a, b) for (i, j, a, b) in doubles
+          if m.signed([(1, i // o), (1, j // o), (-1, a // v), (-1, b // v)]) == 0]
     n = len(ks) + len(kd)
     A = np.zeros((n, n), dtype=np.complex128)
     for k in range(n):

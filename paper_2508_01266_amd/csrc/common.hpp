@@ -14,6 +14,37 @@ typedef long long i64;
 extern bool g_dry_run;
 
 
+// Crystal-momentum mesh Z_n0 x Z_n1 x Z_n2: momentum is conserved modulo a
+// reciprocal-lattice vector (Eq. momentum), so k points add componentwise,
+// each component modulo its own extent.  A point is stored by its flat index
+// (j0 * n1 + j1) * n2 + j2; the 1D chain of the paper is the mesh (nk, 1, 1),
+// whose flat index is the plain k index, and takes a single-modulus path.
+struct KMesh {
+    int n0 = 1, n1 = 1, n2 = 1;
+    __host__ __device__ int size() const { return n0 * n1 * n2; }
+    __host__ __device__ bool chain() const { return n1 == 1 && n2 == 1; }
+    // flat index of sa*a + sb*b + sc*c (signs -1, 0 or +1)
+    __host__ __device__ int sum3(int sa, int a, int sb, int b, int sc, int c) const {
+        if (chain()) {
+            const int r = (sa * a + sb * b + sc * c) % n0;
+            return r < 0 ? r + n0 : r;
+        }
+        const int a2 = a % n2, b2 = b % n2, c2 = c % n2;
+        const int a1 = (a / n2) % n1, b1 = (b / n2) % n1, c1 = (c / n2) % n1;
+        const int a0 = a / (n1 * n2), b0 = b / (n1 * n2), c0 = c / (n1 * n2);
+        int r0 = (sa * a0 + sb * b0 + sc * c0) % n0;
+        int r1 = (sa * a1 + sb * b1 + sc * c1) % n1;
+        int r2 = (sa * a2 + sb * b2 + sc * c2) % n2;
+        r0 += r0 < 0 ? n0 : 0;
+        r1 += r1 < 0 ? n1 : 0;
+        r2 += r2 < 0 ? n2 : 0;
+        return (r0 * n1 + r1) * n2 + r2;
+    }
+    // a + b - c: the fourth momentum of a conserving quartet
+    __host__ __device__ int comb(int a, int b, int c) const { return sum3(1, a, 1, b, -1, c); }
+    __host__ __device__ int sub(int a, int b) const { return sum3(1, a, -1, b, 0, 0); }
+};
+
 // Real type -> interleaved complex type used in device memory.
 template <typename T> struct Cx;
 template <> struct Cx<double> { typedef double2 type; };
@@ -102,10 +133,11 @@ struct LadderArgs {
     const void *La;      // [nk][nk][naux][v][v]
     const void *Lb;      // [nk][nk][naux][v][v]
     void *Z;             // output, same layout as Y (accumulated)
-    int nk, nrhs, o, v, naux;
+    int nk, nrhs, o, v, naux;   // nk = km.size()
     double alpha;
     int packed;          // Y antisymmetric in (e,f): form only unique (e,f) and (a,b) pairs
                          // (1: 256-row kernel, 2: pipelined kernel); 0: full ranges
+    KMesh km;            // k mesh of the blocks
 };
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s);

@@ -47,7 +47,8 @@ hipError_t rhs_to_block(const void *in, void *out, int R, i64 B, i64 E, double s
 template <typename T>
 __global__ void k_tau_like(const typename Cx<T>::type *x1, const typename Cx<T>::type *x2,
                            const typename Cx<T>::type *t1, typename Cx<T>::type *out,
-                           int nk, int R, int o, int v, T c, int x1_has_rhs) {
+                           KMesh km, int R, int o, int v, T c, int x1_has_rhs) {
+    const int nk = km.size();
     const i64 inner = (i64)o * o * v * v;
     const i64 n = (i64)nk * nk * nk * R * inner;
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
@@ -60,7 +61,7 @@ __global__ void k_tau_like(const typename Cx<T>::type *x1, const typename Cx<T>:
         const int ka = (int)(q % nk); q /= nk;
         const int kj = (int)(q % nk); q /= nk;
         const int ki = (int)q;
-        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        const int kb = km.comb(ki, kj, ka);
         auto acc = x2[t];
         T sr = 0, si = 0;
         const int rx = x1_has_rhs ? r : 0;
@@ -82,12 +83,13 @@ __global__ void k_tau_like(const typename Cx<T>::type *x1, const typename Cx<T>:
 }
 
 template <typename T>
-hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, int nk, int R, int o, int v,
+hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, KMesh km, int R, int o, int v,
                     double c, int x1_has_rhs, hipStream_t s) {
+    const int nk = km.size();
     const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
     hipLaunchKernelGGL(k_tau_like<T>, dim3(grid_for(n)), dim3(256), 0, s,
                        (const typename Cx<T>::type *)x1, (const typename Cx<T>::type *)x2,
-                       (const typename Cx<T>::type *)t1, (typename Cx<T>::type *)out, nk, R, o, v, (T)c,
+                       (const typename Cx<T>::type *)t1, (typename Cx<T>::type *)out, km, R, o, v, (T)c,
                        x1_has_rhs);
     return hipGetLastError();
 }
@@ -95,7 +97,8 @@ hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, i
 // y2[r][ki,kj,ka][i][j][a][b] = scale * (P_ij P_ab Z)[ki,kj,ka][r][i][j][a][b] - omega_r * x2[r][...]
 template <typename T>
 __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, double2 *y2, const double *omega,
-                         int nk, int R, int o, int v, double scale) {
+                         KMesh km, int R, int o, int v, double scale) {
+    const int nk = km.size();
     const i64 inner = (i64)o * o * v * v;
     const i64 B = (i64)nk * nk * nk;
     const i64 n = B * R * inner;
@@ -109,7 +112,7 @@ __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, doubl
         const i64 blk = q % B;
         const int r = (int)(q / B);
         const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
-        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        const int kb = km.comb(ki, kj, ka);
         auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
             return Z[((((i64)(k0 * nk + k1) * nk + k2) * R + r) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
         };
@@ -133,11 +136,12 @@ __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, doubl
 }
 
 template <typename T>
-hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, int nk, int R, int o, int v,
+hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, KMesh km, int R, int o, int v,
                   double scale, hipStream_t s) {
+    const int nk = km.size();
     const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
     hipLaunchKernelGGL(k_pp_out<T>, dim3(grid_for(n)), dim3(256), 0, s, (const typename Cx<T>::type *)Z,
-                       (const double2 *)x2, (double2 *)y2, omega, nk, R, o, v, scale);
+                       (const double2 *)x2, (double2 *)y2, omega, km, R, o, v, scale);
     return hipGetLastError();
 }
 
@@ -287,11 +291,12 @@ hipError_t scale_copy(void *y, const void *x, double ar, double ai, i64 n, hipSt
 
 // out = in with permuted indices: output dim d is input dim perm[d]; output blocks
 // [k0][k1][k2] with k3 from the output momentum signs sg (both tensors conserve momentum).
-__global__ void k_permute4(const double2 *in, double2 *out, int nk, int e0, int e1, int e2, int e3, int p0, int p1,
+__global__ void k_permute4(const double2 *in, double2 *out, KMesh km, int e0, int e1, int e2, int e3, int p0, int p1,
                            int p2, int p3, int s0, int s1, int s2, int s3) {
     const int ein[4] = {e0, e1, e2, e3}, perm[4] = {p0, p1, p2, p3}, sg[4] = {s0, s1, s2, s3};
     int eo[4];
     for (int d = 0; d < 4; ++d) eo[d] = ein[perm[d]];
+    const int nk = km.size();
     const i64 inner = (i64)e0 * e1 * e2 * e3;
     const i64 n = (i64)nk * nk * nk * inner;
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
@@ -301,8 +306,7 @@ __global__ void k_permute4(const double2 *in, double2 *out, int nk, int e0, int 
         ko[2] = (int)(q % nk); q /= nk;
         ko[1] = (int)(q % nk); q /= nk;
         ko[0] = (int)q;
-        const int sum = sg[0] * ko[0] + sg[1] * ko[1] + sg[2] * ko[2];
-        ko[3] = ((-sg[3] * sum) % nk + nk) % nk;
+        ko[3] = km.sum3(-sg[3] * sg[0], ko[0], -sg[3] * sg[1], ko[1], -sg[3] * sg[2], ko[2]);
         int ii[4], ki[4];
         for (int d = 0; d < 4; ++d) { ii[perm[d]] = io[d]; ki[perm[d]] = ko[d]; }
         const i64 src = (((i64)(ki[0] * nk + ki[1]) * nk + ki[2]) * inner) +
@@ -311,10 +315,11 @@ __global__ void k_permute4(const double2 *in, double2 *out, int nk, int e0, int 
     }
 }
 
-hipError_t permute4(const void *in, void *out, int nk, const int *ext_in, const int *perm, const int *sg_out,
+hipError_t permute4(const void *in, void *out, KMesh km, const int *ext_in, const int *perm, const int *sg_out,
                     hipStream_t s) {
+    const int nk = km.size();
     const i64 n = (i64)nk * nk * nk * ext_in[0] * ext_in[1] * ext_in[2] * ext_in[3];
-    hipLaunchKernelGGL(k_permute4, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)in, (double2 *)out, nk,
+    hipLaunchKernelGGL(k_permute4, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)in, (double2 *)out, km,
                        ext_in[0], ext_in[1], ext_in[2], ext_in[3], perm[0], perm[1], perm[2], perm[3], sg_out[0],
                        sg_out[1], sg_out[2], sg_out[3]);
     return hipGetLastError();
@@ -334,7 +339,8 @@ hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st) {
 
 // out = scale * c(y - y(ij swapped) - y(ab swapped) + y(both swapped)) on caller-layout doubles
 // [R][ki][kj][ka][i][j][a][b] (kb implied), c = complex conjugation when conj != 0.  Out of place.
-__global__ void k_antisym(const double2 *y, double2 *out, int R, int nk, int o, int v, double scale, int conj) {
+__global__ void k_antisym(const double2 *y, double2 *out, int R, KMesh km, int o, int v, double scale, int conj) {
+    const int nk = km.size();
     const i64 B = (i64)nk * nk * nk, inner = (i64)o * o * v * v;
     const i64 n = (i64)R * B * inner;
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
@@ -347,7 +353,7 @@ __global__ void k_antisym(const double2 *y, double2 *out, int R, int nk, int o, 
         const int kj = (int)(q % nk); q /= nk;
         const int ki = (int)(q % nk);
         const i64 r = q / nk;
-        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        const int kb = km.comb(ki, kj, ka);
         auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
             return y[((r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
         };
@@ -358,9 +364,10 @@ __global__ void k_antisym(const double2 *y, double2 *out, int R, int nk, int o, 
     }
 }
 
-hipError_t antisym(const void *y, void *out, int R, int nk, int o, int v, double scale, int conj, hipStream_t s) {
+hipError_t antisym(const void *y, void *out, int R, KMesh km, int o, int v, double scale, int conj, hipStream_t s) {
+    const int nk = km.size();
     const i64 n = (i64)R * nk * nk * nk * o * o * v * v;
-    hipLaunchKernelGGL(k_antisym, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y, (double2 *)out, R, nk, o,
+    hipLaunchKernelGGL(k_antisym, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y, (double2 *)out, R, km, o,
                        v, scale, conj);
     return hipGetLastError();
 }
@@ -379,7 +386,8 @@ hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s) {
 
 // Z[ki,kj,ka][r][i][j][a][b] = scale * (P_ij P_ab y)[r][ki,kj,ka][i][j][a][b]  (caller layout in, block layout out)
 template <typename T>
-__global__ void k_pp_in(const double2 *y, typename Cx<T>::type *Z, int nk, int R, int o, int v, double scale) {
+__global__ void k_pp_in(const double2 *y, typename Cx<T>::type *Z, KMesh km, int R, int o, int v, double scale) {
+    const int nk = km.size();
     const i64 inner = (i64)o * o * v * v;
     const i64 B = (i64)nk * nk * nk;
     const i64 n = B * R * inner;
@@ -393,7 +401,7 @@ __global__ void k_pp_in(const double2 *y, typename Cx<T>::type *Z, int nk, int R
         const int r = (int)(q % R);
         const i64 blk = q / R;
         const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
-        const int kb = ((ki + kj - ka) % nk + nk) % nk;
+        const int kb = km.comb(ki, kj, ka);
         auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
             return y[(((i64)r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
         };
@@ -404,10 +412,11 @@ __global__ void k_pp_in(const double2 *y, typename Cx<T>::type *Z, int nk, int R
 }
 
 template <typename T>
-hipError_t pp_in(const void *y, void *Z, int nk, int R, int o, int v, double scale, hipStream_t s) {
+hipError_t pp_in(const void *y, void *Z, KMesh km, int R, int o, int v, double scale, hipStream_t s) {
+    const int nk = km.size();
     const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
     hipLaunchKernelGGL(k_pp_in<T>, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y,
-                       (typename Cx<T>::type *)Z, nk, R, o, v, scale);
+                       (typename Cx<T>::type *)Z, km, R, o, v, scale);
     return hipGetLastError();
 }
 
@@ -460,13 +469,13 @@ hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hi
 }
 
 #define INST(T)                                                                                              \
-    template hipError_t pp_in<T>(const void *, void *, int, int, int, int, double, hipStream_t);             \
+    template hipError_t pp_in<T>(const void *, void *, KMesh, int, int, int, double, hipStream_t);             \
     template hipError_t add_inplace<T>(void *, const void *, i64, hipStream_t);                              \
     template hipError_t zero_fill<T>(void *, i64, hipStream_t);                                              \
     template hipError_t pair_transpose<T>(const void *, void *, int, int, int, hipStream_t);                                                                                              \
-    template hipError_t tau_like<T>(const void *, const void *, const void *, void *, int, int, int, int,    \
+    template hipError_t tau_like<T>(const void *, const void *, const void *, void *, KMesh, int, int, int,  \
                                     double, int, hipStream_t);                                               \
-    template hipError_t pp_out<T>(const void *, const void *, void *, const double *, int, int, int, int,    \
+    template hipError_t pp_out<T>(const void *, const void *, void *, const double *, KMesh, int, int, int,  \
                                   double, hipStream_t);                                                      \
     template hipError_t s1_out<T>(const void *, const void *, void *, const double *, int, int, int, int,    \
                                   hipStream_t);                                                              \

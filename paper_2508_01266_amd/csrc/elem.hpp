@@ -6,10 +6,10 @@ namespace lrcc {
 template <typename Tin, typename Tout>
 hipError_t rhs_to_block(const void *in, void *out, int R, i64 B, i64 E, double scale, hipStream_t s);
 template <typename T>
-hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, int nk, int R, int o, int v,
+hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, KMesh km, int R, int o, int v,
                     double c, int x1_has_rhs, hipStream_t s);
 template <typename T>
-hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, int nk, int R, int o, int v,
+hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, KMesh km, int R, int o, int v,
                   double scale, hipStream_t s);
 template <typename T>
 hipError_t s1_out(const void *s1, const void *x1, void *y1, const double *omega, int nk, int R, int o, int v,
@@ -29,12 +29,12 @@ hipError_t axis_scatter(const void *in, void *out, int nax, int nk, int n, int p
                         int transpose, hipStream_t s);
 hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st);
 // caller-layout doubles: out = scale * c(P(ij) P(ab) y), c = conjugation when conj != 0 (out of place)
-hipError_t antisym(const void *y, void *out, int R, int nk, int o, int v, double scale, int conj, hipStream_t s);
+hipError_t antisym(const void *y, void *out, int R, KMesh km, int o, int v, double scale, int conj, hipStream_t s);
 // four-index complex128 permutation: output dim d = input dim perm[d]; output momentum signs sg_out
-hipError_t permute4(const void *in, void *out, int nk, const int *ext_in, const int *perm, const int *sg_out,
+hipError_t permute4(const void *in, void *out, KMesh km, const int *ext_in, const int *perm, const int *sg_out,
                     hipStream_t s);
 template <typename T>
-hipError_t pp_in(const void *y, void *Z, int nk, int R, int o, int v, double scale, hipStream_t s);
+hipError_t pp_in(const void *y, void *Z, KMesh km, int R, int o, int v, double scale, hipStream_t s);
 template <typename T>
 hipError_t add_inplace(void *y, const void *x, i64 n, hipStream_t s);
 template <typename T>

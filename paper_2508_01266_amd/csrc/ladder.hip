@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(NTL) ladder_kernel(LadderArgs p) {
     const int b0 = (rest / tilesA) * TB;
     const int blk = blockIdx.y;                       // (ki,kj,ka)
     const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
-    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    const int kb = p.km.comb(ki, kj, ka);
     const int m0 = mt * LTM;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(NTL) ladder_kernel(LadderArgs p) {
     const int rw = 16 * (wave & 1), cw = 16 * (wave >> 1);
 
     for (int ke = 0; ke < nk; ++ke) {
-        const int kf = ((ki + kj - ke) % nk + nk) % nk;
+        const int kf = p.km.comb(ki, kj, ke);
         const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
         const C2 *Lab = La + (i64)(ka * nk + ke) * naux * vv;
         const C2 *Lbb = Lb + (i64)(kb * nk + kf) * naux * vv;
@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(NTB) ladder_kernel_big(LadderArgs p) {
     const int b0 = (rest / tilesA) * TB;
     const int blk = blockIdx.y;
     const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
-    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    const int kb = p.km.comb(ki, kj, ka);
     const int m0 = mt * BTM;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(NTB) ladder_kernel_big(LadderArgs p) {
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     for (int ke = 0; ke < nk; ++ke) {
-        const int kf = ((ki + kj - ke) % nk + nk) % nk;
+        const int kf = p.km.comb(ki, kj, ke);
         const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
         const C2 *Lab = La + (i64)(ka * nk + ke) * naux * vv;
         const C2 *Lbb = Lb + (i64)(kb * nk + kf) * naux * vv;
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(NTP) ladder_kernel_packed(LadderArgs p) {
     const int a0 = ta * TA, b0 = tb * TB;
     const int blk = blockIdx.y;
     const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
-    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    const int kb = p.km.comb(ki, kj, ka);
     // unique output pairs only
     if (ka > kb || (ka == kb && ta > tb)) return;
     const bool diag_out = (ka == kb);
@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(NTP) ladder_kernel_packed(LadderArgs p) {
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     for (int ke = 0; ke < nk; ++ke) {
-        const int kf = ((ki + kj - ke) % nk + nk) % nk;
+        const int kf = p.km.comb(ki, kj, ke);
         if (ke > kf) continue;
         const bool diag_in = (ke == kf);
         const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
@@ -561,7 +561,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     const int ta = rest % tilesA, tb = rest / tilesA;
     const int a0 = ta * TA, b0 = tb * TB;
     const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
-    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+    const int kb = p.km.comb(ki, kj, ka);
     if (ka > kb || (ka == kb && ta > tb)) return;
     const bool diag_out = (ka == kb);
     const int m0 = mt * BM;
@@ -578,7 +578,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     // steps (ke <= kf, e0, f0 >= e0 when ke == kf); the step after `s`, or ke = nk when done
-    auto kf_of = [&](int ke) { return ((ki + kj - ke) % nk + nk) % nk; };
+    auto kf_of = [&](int ke) { return p.km.comb(ki, kj, ke); };
     auto first_valid = [&](int ke) {
         while (ke < nk && ke > kf_of(ke)) ++ke;
         return ke;
@@ -835,12 +835,12 @@ double ladder_executed_flops(const LadderArgs &a, bool fp64) {
     for (int ki = 0; ki < nk; ++ki)
         for (int kj = 0; kj < nk; ++kj)
             for (int ka = 0; ka < nk; ++ka) {
-                const int kb = ((ki + kj - ka) % nk + nk) % nk;
+                const int kb = a.km.comb(ki, kj, ka);
                 if (ka > kb) continue;
                 const double out = ka == kb ? tA * (tA + 1) / 2.0 : (double)tA * tB;
                 double in = 0;
                 for (int ke = 0; ke < nk; ++ke) {
-                    const int kf = ((ki + kj - ke) % nk + nk) % nk;
+                    const int kf = a.km.comb(ki, kj, ke);
                     if (ke > kf) continue;
                     in += ke == kf ? tE * (tE + 1) / 2.0 : (double)tE * tF;
                 }

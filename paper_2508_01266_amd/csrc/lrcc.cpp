@@ -77,6 +77,8 @@ struct lrcc_ctx {
     int dev = 0;
     std::string err;
     int nk = 0, no = 0, nv = 0, naux = 0, n = 0;
+    KMesh km;                                  // k mesh (a 1D chain unless set by lrcc_set_kmesh)
+    bool km_set = false;
     bool ham = false, amp = false;
     DevMem hmem;          // Hamiltonian-level device memory (f64)
     void *fock = nullptr, *Ls = nullptr, *Lcs = nullptr;
@@ -142,6 +144,7 @@ KT make_kt(lrcc_ctx *c, const char *cls, void *p, int nR = 0, std::initializer_l
     t.cls = cls;
     t.nR = nR;
     t.nk = c->nk;
+    t.km = c->km;
     t.no = c->no;
     t.nv = c->nv;
     int i = 0;
@@ -197,7 +200,7 @@ void build_eri(lrcc_ctx *c, Program &P, const KT &out, double scale) {
         for (int k0 = 0; k0 < nk; ++k0)
             for (int k1 = 0; k1 < nk; ++k1)
                 for (int k2 = 0; k2 < nk; ++k2) {
-                    const int k3 = ((k0 + k1 - k2) % nk + nk) % nk;
+                    const int k3 = c->km.comb(k0, k1, k2);
                     const int km = pass == 0 ? k2 : k3, kn = pass == 0 ? k3 : k2;
                     offC.push_back((((i64)k0 * nk + k1) * nk + k2) * out.inner());
                     segA.push_back((i64)(k0 * nk + km) * Lblk + (i64)off(out.cls[0]) * n + off(out.cls[mi]));
@@ -270,7 +273,7 @@ void ladder_slots(lrcc_ctx *c) {
     for (int ka = 0; ka < nk; ++ka)
         for (int kb = ka; kb < nk; ++kb)
             for (int ke = 0; ke < nk; ++ke) {
-                const int kf = ((ka + kb - ke) % nk + nk) % nk;
+                const int kf = c->km.comb(ka, kb, ke);
                 if (ke <= kf) c->wslot[((size_t)ka * nk + kb) * nk + ke] = n++;
             }
     c->nwslot = n;
@@ -319,7 +322,7 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
         for (int ka = 0; ka < nk; ++ka)
             for (int kb = ka; kb < nk; ++kb)
                 for (int ke = 0; ke < nk; ++ke) {
-                    const int kf = ((ka + kb - ke) % nk + nk) % nk;
+                    const int kf = c->km.comb(ka, kb, ke);
                     const int sl = c->wslot[((size_t)ka * nk + kb) * nk + ke];
                     if (sl < 0) continue;
                     offC.push_back(sl * v4);
@@ -390,8 +393,9 @@ void build_state(lrcc_ctx *c) {
     KT tt = alloc_kt<double>(c, m, "oovv");
     {
         void *t1p = S.t1.p, *t2p = S.t2.p, *tau = S.tau.p, *ttp = tt.p;
-        P.ops.push_back([=](hipStream_t s) { return tau_like<double>(t1p, t2p, t1p, tau, nk, 1, o, v, 0.5, 0, s); });
-        P.ops.push_back([=](hipStream_t s) { return tau_like<double>(t1p, t2p, t1p, ttp, nk, 1, o, v, 0.25, 0, s); });
+        const KMesh km = c->km;
+        P.ops.push_back([=](hipStream_t s) { return tau_like<double>(t1p, t2p, t1p, tau, km, 1, o, v, 0.5, 0, s); });
+        P.ops.push_back([=](hipStream_t s) { return tau_like<double>(t1p, t2p, t1p, ttp, km, 1, o, v, 0.25, 0, s); });
     }
     const KT &t1 = S.t1, &t2 = S.t2, &tau = S.tau;
     // F intermediates (full Fock matrix; the diagonal stays inside, Eq. D is only the preconditioner)
@@ -434,8 +438,8 @@ void build_state(lrcc_ctx *c) {
         KT wr = alloc_kt<double>(c, m, "ovvo", 0, {1, -1, 1, -1});
         const int ext[4] = {o, v, v, o}, perm[4] = {0, 2, 1, 3}, sg[4] = {1, -1, 1, -1};
         void *src = S.Wbar.p, *dst = wr.p;
-        const int nk_ = nk;
-        P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, nk_, ext, perm, sg, s); });
+        const KMesh km = c->km;
+        P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, km, ext, perm, sg, s); });
         S.Wbar = wr;
     }
     // Q_ijam = sum_ef tau_ijef <am||ef>
@@ -690,6 +694,7 @@ LadderArgs ladder_args(lrcc_ctx *c, const void *Y, const void *La, const void *L
     LadderArgs la{};
     la.Y = Y; la.La = La; la.Lb = Lb; la.Z = Z;
     la.nk = c->nk; la.nrhs = R; la.o = c->no; la.v = c->nv; la.naux = c->naux;
+    la.km = c->km;
     la.alpha = alpha;
     return la;
 }
@@ -716,7 +721,8 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
             break;
         case SymOp::TAU: {
             void *t1p = S.t1.p, *xa = op.A.p, *xb = op.B.p, *out = op.C.p;
-            P->ops.push_back([=](hipStream_t s) { return tau_like<T>(xa, xb, t1p, out, nk, R, o, v, 1.0, 1, s); });
+            const KMesh km = c->km;
+            P->ops.push_back([=](hipStream_t s) { return tau_like<T>(xa, xb, t1p, out, km, R, o, v, 1.0, 1, s); });
             break;
         }
         case SymOp::LADDER: {
@@ -754,10 +760,10 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
                 for (int ki = 0; ki < nk; ++ki)
                     for (int kj = 0; kj < nk; ++kj)
                         for (int ka = 0; ka < nk; ++ka) {
-                            const int kb = ((ki + kj - ka) % nk + nk) % nk;
+                            const int kb = c->km.comb(ki, kj, ka);
                             if (ka > kb) continue;
                             for (int ke = 0; ke < nk; ++ke) {
-                                const int kf = ((ki + kj - ke) % nk + nk) % nk;
+                                const int kf = c->km.comb(ki, kj, ke);
                                 if (ke > kf) continue;
                                 segA.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
                                 segB.push_back((i64)c->wslot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
@@ -790,7 +796,7 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
     // outputs in the caller layout: y = (A - omega) x, paper normalisation
     P->ops.push_back([=](hipStream_t s) { return s1_out<T>(s1.p, c->io_x1, c->io_y1, c->io_omega, nk, R, o, v, s); });
     P->ops.push_back([=](hipStream_t s) {
-        return pp_out<T>(Z.p, c->io_x2, c->io_y2, c->io_omega, nk, R, o, v, (double)nk, s);
+        return pp_out<T>(Z.p, c->io_x2, c->io_y2, c->io_omega, c->km, R, o, v, (double)nk, s);
     });
     return P;
 }
@@ -811,7 +817,7 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
     KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
     // cotangent of the outputs: s1bar = z1, Zbar = (Nk/4) P(ij)P(ab) z2
     P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, T>(c->io_x1, s1.p, R, nk, (i64)o * v, 1.0, s); });
-    P->ops.push_back([=](hipStream_t s) { return pp_in<T>(c->io_x2, Z.p, nk, R, o, v, 0.25 * nk, s); });
+    P->ops.push_back([=](hipStream_t s) { return pp_in<T>(c->io_x2, Z.p, c->km, R, o, v, 0.25 * nk, s); });
     for (auto it = G.ops.rbegin(); it != G.ops.rend(); ++it) {
         const SymOp &op = *it;
         switch (op.kind) {
@@ -851,7 +857,7 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
     // y1 = x1bar - omega z1 ; y2 = P(ij)P(ab) x2bar / Nk - omega z2
     P->ops.push_back([=](hipStream_t s) { return s1_out<T>(x1.p, c->io_x1, c->io_y1, c->io_omega, nk, R, o, v, s); });
     P->ops.push_back([=](hipStream_t s) {
-        return pp_out<T>(x2.p, c->io_x2, c->io_y2, c->io_omega, nk, R, o, v, 1.0 / nk, s);
+        return pp_out<T>(x2.p, c->io_x2, c->io_y2, c->io_omega, c->km, R, o, v, 1.0 / nk, s);
     });
     return P;
 }
@@ -863,6 +869,8 @@ std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     // "v4": candidate semantics (GEMM: heuristic tile shape first, up to three; ladder: three kernels)
     std::snprintf(b, sizeof b, "v4,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
                   adj ? "adjoint" : "forward", variant);
+    if (!c->km.chain()) return std::string(b) + ",mesh" + std::to_string(c->km.n0) + "x" + std::to_string(c->km.n1) +
+                               "x" + std::to_string(c->km.n2);
     return b;
 }
 
@@ -994,7 +1002,7 @@ struct SolveCtx {
     void prec(const Vecs &out, const Vecs &in) {
         const State<double> &T = c->s64;
         HIPCHK(precond(out.s, out.d, in.s, in.d, (const double *)T.d_o1, (const double *)T.d_v1,
-                       (const double *)T.d_o2, (const double *)T.d_v2, omega, c->nk, R, c->no, c->nv, st));
+                       (const double *)T.d_o2, (const double *)T.d_v2, omega, c->km, R, c->no, c->nv, st));
     }
     // y = (A - omega) x
     void op(const Vecs &y, const Vecs &x, int precision) {
@@ -1297,7 +1305,8 @@ void ensure_alpha_programs(lrcc_ctx *c) {
         contract<double>(*P, Z, "Rijab", t2, "ikab", Gx, "Rkj", -0.5);
         void *xi1 = c->xi1, *xi2 = c->xi2;
         P->ops.push_back([=](hipStream_t s) { return s1_out<double>(s1.p, nullptr, xi1, nullptr, nk, R, o, v, s); });
-        P->ops.push_back([=](hipStream_t s) { return pp_out<double>(Z.p, nullptr, xi2, nullptr, nk, R, o, v, (double)nk, s); });
+        const KMesh km = c->km;
+        P->ops.push_back([=](hipStream_t s) { return pp_out<double>(Z.p, nullptr, xi2, nullptr, km, R, o, v, (double)nk, s); });
         c->prog_xi = std::move(P);
     }
     // right-hand side of the lambda equations: -(S^-1 dE/dT) = -(f_ia + <ij||ab> t_jb, <ij||ab>/Nk)
@@ -1433,7 +1442,7 @@ Program *dens_program(lrcc_ctx *c, int R) {
         void *pa = a1.p, *pz = Zb.p;
         P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, double>(cc->io_x1, pa, R, nk, (i64)o * v, 1.0, s); });
         // xi2 = Nk P(ij)P(ab) Z and the pairing weight 1/4: Z-bar = (Nk/4) P(ij)P(ab) a2
-        P->ops.push_back([=](hipStream_t s) { return pp_in<double>(cc->io_x2, pz, nk, R, o, v, 0.25 * nk, s); });
+        P->ops.push_back([=](hipStream_t s) { return pp_in<double>(cc->io_x2, pz, cc->km, R, o, v, 0.25 * nk, s); });
     }
     // Z = 1/2 t2_ijac Fx_bc - 1/2 t2_ikab Gx_kj
     contract<double>(*P, Fb, "Rbc", Zb, "Rijab", t2, "ijac", 0.5, false);
@@ -2250,7 +2259,7 @@ void eom_roots(lrcc_ctx *c, int nroots, double tol, int max_iter, std::vector<cd
             Vecs u = at(Tb, 0);
             const State<double> &T = c->s64;
             HIPCHK(precond(u.s, u.d, at(Rb, k).s, at(Rb, k).d, (const double *)T.d_o1, (const double *)T.d_v1,
-                           (const double *)T.d_o2, (const double *)T.d_v2, dom, nk, 1, no, nv, st));
+                           (const double *)T.d_o2, (const double *)T.d_v2, dom, c->km, 1, no, nv, st));
             HIPCHK(hipStreamSynchronize(st));
             (void)add(u);
         }
@@ -2321,7 +2330,7 @@ void solve_ccsd(lrcc_ctx *c, double tol, int max_iter, int ndiis, lrcc_solve_rep
         if (rn <= tol) break;
         // Jacobi: t_new = t + Omega / D = t - Omega / (e_a + e_b - e_i - e_j)
         HIPCHK(precond(step.s, step.d, res.s, res.d, (const double *)c->eps_o, (const double *)c->eps_v,
-                       (const double *)c->eps_o, (const double *)c->eps_v, nullptr, nk, 1, o, v, st));
+                       (const double *)c->eps_o, (const double *)c->eps_v, nullptr, c->km, 1, o, v, st));
         Vecs tn = mk();
         S.copy(tn, T);
         S.axpby(tn, step, std::vector<cd>(1, cd(-1.0, 0.0)), 1.0);
@@ -2417,6 +2426,7 @@ void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const 
     c->s32.mem.release();
     c->hmem.release();
     c->nk = nk; c->no = nocc; c->nv = nvir; c->naux = naux; c->n = n;
+    if (!c->km_set) c->km = KMesh{nk, 1, 1};
     const i64 nL = (i64)nk * nk * naux * n * n;
     c->fock = c->hmem.get((size_t)nk * n * n * 16);
     if (!g_dry_run) HIPCHK(hipMemcpy(c->fock, fock, (size_t)nk * n * n * 16, hipMemcpyHostToDevice));
@@ -2514,26 +2524,45 @@ void lrcc_destroy(lrcc_ctx *c) {
 
 const char *lrcc_last_error(const lrcc_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
+}  // extern "C"
+
+// Hermiticity of cnt complex [n][n] blocks (relative tolerance 1e-10) -> LRCC_E_ARG
+static void check_hermitian(const double *m, int cnt, int n, const char *what) {
+    double mx = 0, dev = 0;
+    for (int b = 0; b < cnt; ++b)
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) {
+                const double *x = m + 2 * (((i64)b * n + p) * n + q), *y = m + 2 * (((i64)b * n + q) * n + p);
+                dev = std::max(dev, std::max(std::fabs(x[0] - y[0]), std::fabs(x[1] + y[1])));
+                mx = std::max(mx, std::max(std::fabs(x[0]), std::fabs(x[1])));
+            }
+    if (dev > 1e-10 * std::max(1.0, mx)) throw LrccError(LRCC_E_ARG, std::string(what) + " is not Hermitian");
+}
+
+extern "C" {
+
+lrcc_status lrcc_set_kmesh(lrcc_ctx *c, int n0, int n1, int n2) {
+    return guarded(c, [&] {
+        if (n0 < 1 || n1 < 1 || n2 < 1 || (i64)n0 * n1 * n2 > 46340)
+            throw LrccError(LRCC_E_ARG, "mesh extents must be positive (and n0 n1 n2 at most 46340)");
+        c->km = KMesh{n0, n1, n2};
+        c->km_set = true;
+        c->ham = c->amp = false;
+        c->nfreq = 0;
+        c->lam_valid = false;
+    });
+}
+
 lrcc_status lrcc_set_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const double *fock,
                                  const double *chol, const double *dip) {
     return guarded(c, [&] {
         if (nk < 1 || nocc < 1 || nvir < 1 || naux < 1 || !fock || !chol || !dip)
             throw LrccError(LRCC_E_ARG, "invalid sizes or null pointer");
+        if (c->km_set && c->km.size() != nk)
+            throw LrccError(LRCC_E_SHAPE, "nk differs from the number of points of the k mesh");
         const int n = nocc + nvir;
-        // Hermiticity of fock and dip
-        auto herm = [&](const double *m, int cnt, const char *what) {
-            double mx = 0, dev = 0;
-            for (int b = 0; b < cnt; ++b)
-                for (int p = 0; p < n; ++p)
-                    for (int q = 0; q < n; ++q) {
-                        const double *x = m + 2 * (((i64)b * n + p) * n + q), *y = m + 2 * (((i64)b * n + q) * n + p);
-                        dev = std::max(dev, std::max(std::fabs(x[0] - y[0]), std::fabs(x[1] + y[1])));
-                        mx = std::max(mx, std::max(std::fabs(x[0]), std::fabs(x[1])));
-                    }
-            if (dev > 1e-10 * std::max(1.0, mx)) throw LrccError(LRCC_E_ARG, std::string(what) + " is not Hermitian");
-        };
-        herm(fock, nk, "fock");
-        herm(dip, 3 * nk, "dip");
+        check_hermitian(fock, nk, n, "fock");
+        check_hermitian(dip, 3 * nk, n, "dip");
         // Hermitian pairing chol[k2][k1][Q] = conj(chol[k1][k2][Q])^T
         double mx = 0, dev = 0;
         for (int k1 = 0; k1 < nk; ++k1)
@@ -2565,7 +2594,7 @@ lrcc_status lrcc_set_amplitudes(lrcc_ctx *c, const double *t1, const double *t2)
         for (int ki = 0; ki < nk; ++ki)
             for (int kj = 0; kj < nk; ++kj)
                 for (int ka = 0; ka < nk; ++ka) {
-                    const int kb = ((ki + kj - ka) % nk + nk) % nk;
+                    const int kb = c->km.comb(ki, kj, ka);
                     for (int i = 0; i < o; ++i)
                         for (int j = 0; j < o; ++j)
                             for (int a = 0; a < v; ++a)
@@ -2631,13 +2660,13 @@ lrcc_status lrcc_sigma_vjp_dev(lrcc_ctx *c, int nrhs, const double *omega, const
         // z = (conj g1, P conj g2): the cotangent restricted to antisymmetric doubles, in the
         // pairing sum z1 y1 + 1/4 sum z2 y2 of the transpose product
         HIPCHK(conj_scale(c->vj1, g1, 1.0, n1, st));
-        HIPCHK(antisym(g2, c->vj2, nrhs, nk, o, v, 1.0, 1, st));
+        HIPCHK(antisym(g2, c->vj2, nrhs, c->km, o, v, 1.0, 1, st));
         Program *p = sigma_program(c, precision, nrhs, true);
         c->io_x1 = c->vj1; c->io_x2 = c->vj2; c->io_y1 = c->vw1; c->io_y2 = c->vw2; c->io_omega = omega;
         HIPCHK(run_sigma(c, p, st));
         // back to the Euclidean pairing over full arrays, projected on antisymmetric doubles
         HIPCHK(conj_scale(gx1, c->vw1, 1.0, n1, st));
-        HIPCHK(antisym(c->vw2, gx2, nrhs, nk, o, v, 1.0 / 16.0, 1, st));
+        HIPCHK(antisym(c->vw2, gx2, nrhs, c->km, o, v, 1.0 / 16.0, 1, st));
     });
 }
 
@@ -2751,6 +2780,49 @@ lrcc_status lrcc_solve(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double 
         lrcc_solve_report rep{};
         c->nfreq = 0;
         solve_alpha(c, axis_mask, nfreq, omega, o, rep);
+        if (report) *report = rep;
+    });
+}
+
+lrcc_status lrcc_alpha_velocity_gauge(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega,
+                                      const double *mom, const lrcc_solve_opts *opts, double *alpha,
+                                      lrcc_solve_report *report) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nfreq < 1 || !omega || !mom || !alpha || (axis_mask & ~7u))
+            throw LrccError(LRCC_E_ARG, "invalid frequencies, axis mask or null pointer");
+        for (int j = 0; j < nfreq; ++j)
+            if (!(omega[j] != 0.0) || !std::isfinite(omega[j]))
+                throw LrccError(LRCC_E_ARG, "velocity-gauge frequencies must be finite and non-zero");
+        check_hermitian(mom, 3 * c->nk, c->n, "mom");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        if (o.precision != LRCC_FP64 && o.precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        lrcc_solve_report rep{};
+        // the perturbation operators are read from the dipole buffer by the xi and eta
+        // programs: swap the momentum matrices in for this solve, restore afterwards
+        const size_t bytes = (size_t)3 * c->nk * c->n * c->n * 16;
+        DevMem keep;
+        void *saved = keep.get(bytes);
+        HIPCHK(hipMemcpy(saved, c->dip, bytes, hipMemcpyDeviceToDevice));
+        struct Restore {
+            lrcc_ctx *c;
+            void *saved;
+            size_t bytes;
+            ~Restore() {
+                (void)hipMemcpy(c->dip, saved, bytes, hipMemcpyDeviceToDevice);
+                c->nfreq = 0;   // the stored solutions are those of the momentum operator
+            }
+        } restore{c, saved, bytes};
+        HIPCHK(hipMemcpy(c->dip, mom, bytes, hipMemcpyHostToDevice));
+        std::vector<double> w(nfreq + 1, 0.0);
+        for (int j = 0; j < nfreq; ++j) w[j + 1] = omega[j];
+        c->nfreq = 0;
+        solve_alpha(c, axis_mask, nfreq + 1, w.data(), o, rep);
+        for (int j = 0; j < nfreq; ++j)
+            for (int e = 0; e < 18; ++e)
+                alpha[j * 18 + e] = (c->alpha[(size_t)(j + 1) * 18 + e] - c->alpha[e]) / (omega[j] * omega[j]);
         if (report) *report = rep;
     });
 }
@@ -3042,12 +3114,21 @@ lrcc_status lrcc_ladder_flops(lrcc_ctx *c, int nrhs, int precision, double *exec
 }
 
 lrcc_status lrcc_plan_check(int nk, int nocc, int nvir, int naux, int nrhs, char *msg, int msglen) {
+    return lrcc_plan_check_mesh(nk, 1, 1, nocc, nvir, naux, nrhs, msg, msglen);
+}
+
+lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int naux, int nrhs, char *msg,
+                                 int msglen) {
     if (msg && msglen > 0) msg[0] = 0;
-    if (nk < 1 || nocc < 1 || nvir < 1 || naux < 1 || nrhs < 1) return LRCC_E_ARG;
+    if (n0 < 1 || n1 < 1 || n2 < 1 || (i64)n0 * n1 * n2 > 46340 || nocc < 1 || nvir < 1 || naux < 1 || nrhs < 1)
+        return LRCC_E_ARG;
+    const int nk = n0 * n1 * n2;
     lrcc_status st = LRCC_OK;
     g_dry_run = true;
     try {
         lrcc_ctx c;
+        c.km = KMesh{n0, n1, n2};
+        c.km_set = true;
         setup_hamiltonian(&c, nk, nocc, nvir, naux, nullptr, nullptr, nullptr);
         c.ham = true;
         build_state(&c);

@@ -303,8 +303,6 @@ void make_split(const std::vector<std::vector<char>> &ch, const TInfo &x, const 
     for (int i = 0; i < 3; ++i) { sx.s[i] = stx[i]; sy.s[i] = sty[i]; }
 }
 
-inline int md(int a, int n) { return ((a % n) + n) % n; }
-
 // block index of tensor t for per-label momenta; -1 if the momenta violate t's rule
 i64 block_of(const TInfo &t, const std::map<char, int> &k) {
     const KT &T = *t.t;
@@ -313,12 +311,12 @@ i64 block_of(const TInfo &t, const std::map<char, int> &k) {
     std::vector<int> ks;
     for (int d = 0; d < T.nidx(); ++d) ks.push_back(k.at(t.lab[off + d]));
     if (T.nidx() == 2) {
-        if (md(ks[0] - ks[1], nk) != 0) return -1;
+        if (ks[0] != ks[1]) return -1;
         return ks[0];
     }
-    int s = 0;
-    for (int d = 0; d < 4; ++d) s += T.sg[d] * ks[d];
-    if (md(s, nk) != 0) return -1;
+    // the fourth momentum implied by the first three must be the given one
+    const int k3 = T.km.sum3(-T.sg[3] * T.sg[0], ks[0], -T.sg[3] * T.sg[1], ks[1], -T.sg[3] * T.sg[2], ks[2]);
+    if (k3 != ks[3]) return -1;
     return ((i64)ks[0] * nk + ks[1]) * nk + ks[2];
 }
 
@@ -473,11 +471,10 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
             k[cl[off + 1]] = (int)cb;
         } else {
             int k0 = (int)(cb / (nk * nk)), k1 = (int)((cb / nk) % nk), k2 = (int)(cb % nk);
-            int s = C.sg[0] * k0 + C.sg[1] * k1 + C.sg[2] * k2;
             k[cl[off]] = k0;
             k[cl[off + 1]] = k1;
             k[cl[off + 2]] = k2;
-            k[cl[off + 3]] = md(-C.sg[3] * s, nk);
+            k[cl[off + 3]] = C.km.sum3(-C.sg[3] * C.sg[0], k0, -C.sg[3] * C.sg[1], k1, -C.sg[3] * C.sg[2], k2);
         }
         const size_t before = segA.size();
         for (i64 sidx = 0; sidx < nsum; ++sidx) {

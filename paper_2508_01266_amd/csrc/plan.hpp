@@ -15,7 +15,7 @@ namespace lrcc {
 
 // A momentum-conserving tensor stored as dense blocks (Sec. II.A, Eq. momentum).
 // Indices have class 'o' or 'v'.  Four-index tensors obey
-// sg[0] k0 + sg[1] k1 + sg[2] k2 + sg[3] k3 = 0 (mod nk) and are stored as
+// sg[0] k0 + sg[1] k1 + sg[2] k2 + sg[3] k3 = 0 on the k mesh km and are stored as
 // [k0][k1][k2] blocks (k3 implied); two-index tensors are k-diagonal, [k0]
 // blocks.  An optional right-hand-side axis of extent nR sits at the start of
 // every block: block = [R][d0][d1]...  Elements are interleaved complex.
@@ -24,7 +24,8 @@ struct KT {
     std::string cls;
     int sg[4] = {1, 1, -1, -1};
     int nR = 0;
-    int nk = 0, no = 0, nv = 0;
+    int nk = 0, no = 0, nv = 0;   // nk = km.size()
+    KMesh km;
     int nidx() const { return (int)cls.size(); }
     int ext(int d) const { return cls[d] == 'o' ? no : nv; }
     i64 inner() const {

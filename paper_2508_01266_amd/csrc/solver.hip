@@ -89,8 +89,9 @@ hipError_t batched_axpby(void *y, const void *x, const void *alpha, double beta,
 // singles: out[r][k][i][a] = in / (e_v[k][a] - e_o[k][i] - w_r)
 // doubles: out[r][ki,kj,ka][i][j][a][b] = in / (e_v[ka][a] + e_v[kb][b] - e_o[ki][i] - e_o[kj][j] - w_r)
 __global__ void k_precond(double2 *o1, double2 *o2, const double2 *i1, const double2 *i2, const double *eo,
-                          const double *ev, const double *eo2, const double *ev2, const double *omega, int nk, int R,
-                          int no, int nv) {
+                          const double *ev, const double *eo2, const double *ev2, const double *omega, KMesh km,
+                          int R, int no, int nv) {
+    const int nk = km.size();
     const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
     const i64 N = (i64)R * (n1 + n2);
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
@@ -117,7 +118,7 @@ __global__ void k_precond(double2 *o1, double2 *o2, const double2 *i1, const dou
             const int ka = (int)(q % nk); q /= nk;
             const int kj = (int)(q % nk);
             const int ki = (int)(q / nk);
-            const int kb = ((ki + kj - ka) % nk + nk) % nk;
+            const int kb = km.comb(ki, kj, ka);
             d = ev2[ka * nv + a] + ev2[kb * nv + b] - eo2[ki * no + i] - eo2[kj * no + j] - (omega ? omega[r] : 0.0);
             x = i2[u];
             dst = o2 + u;
@@ -128,13 +129,14 @@ __global__ void k_precond(double2 *o1, double2 *o2, const double2 *i1, const dou
 }
 
 hipError_t precond(void *o1, void *o2, const void *i1, const void *i2, const double *eo, const double *ev,
-                   const double *eo2, const double *ev2, const double *omega, int nk, int R, int no, int nv,
+                   const double *eo2, const double *ev2, const double *omega, KMesh km, int R, int no, int nv,
                    hipStream_t s) {
+    const int nk = km.size();
     const i64 N = (i64)R * ((i64)nk * no * nv + (i64)nk * nk * nk * no * no * nv * nv);
     i64 g = (N + 255) / 256;
     if (g > 262144) g = 262144;
     hipLaunchKernelGGL(k_precond, dim3((unsigned)g), dim3(256), 0, s, (double2 *)o1, (double2 *)o2,
-                       (const double2 *)i1, (const double2 *)i2, eo, ev, eo2, ev2, omega, nk, R, no, nv);
+                       (const double2 *)i1, (const double2 *)i2, eo, ev, eo2, ev2, omega, km, R, no, nv);
     return hipGetLastError();
 }
 

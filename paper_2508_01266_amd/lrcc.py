@@ -57,6 +57,11 @@ def lib():
         L.lrcc_alpha_lambda_bar.restype = ctypes.c_int
         L.lrcc_eom_roots.argtypes = [vp, i, ctypes.c_double, i, vp, ctypes.POINTER(SolveReport)]
         L.lrcc_eom_roots.restype = ctypes.c_int
+        L.lrcc_set_kmesh.argtypes = [vp, i, i, i]
+        L.lrcc_set_kmesh.restype = ctypes.c_int
+        L.lrcc_alpha_velocity_gauge.argtypes = [vp, ctypes.c_uint, i, vp, vp, ctypes.POINTER(SolveOpts), vp,
+                                                ctypes.POINTER(SolveReport)]
+        L.lrcc_alpha_velocity_gauge.restype = ctypes.c_int
         L.lrcc_set_ladder_mode.argtypes = [vp, i]
         L.lrcc_set_ladder_mode.restype = ctypes.c_int
         L.lrcc_set_autotune.argtypes = [vp, i]
@@ -90,6 +95,8 @@ def lib():
             getattr(L, f).restype = ctypes.c_int
         L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
         L.lrcc_plan_check.restype = ctypes.c_int
+        L.lrcc_plan_check_mesh.argtypes = [i, i, i, i, i, i, i, ctypes.c_char_p, i]
+        L.lrcc_plan_check_mesh.restype = ctypes.c_int
         L.lrcc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
         for f in ("lrcc_create", "lrcc_set_hamiltonian", "lrcc_set_amplitudes", "lrcc_apply_sigma",
                   "lrcc_apply_sigma_dev", "lrcc_apply_sigma_adjoint", "lrcc_apply_sigma_adjoint_dev", "lrcc_sizes"):
@@ -125,9 +132,14 @@ def _ptr(a):
 
 
 def plan_check(nk, nocc, nvir, naux, nrhs):
-    """Host-only validation of all launch plans for a problem size (no GPU needed)."""
+    """Host-only validation of all launch plans for a problem size (no GPU needed).
+    nk: number of k points of a 1D chain, or a tuple (n0, n1, n2) of mesh extents."""
     buf = ctypes.create_string_buffer(512)
-    st = lib().lrcc_plan_check(nk, nocc, nvir, naux, nrhs, buf, 512)
+    if np.isscalar(nk):
+        st = lib().lrcc_plan_check(int(nk), nocc, nvir, naux, nrhs, buf, 512)
+    else:
+        d = tuple(int(x) for x in nk) + (1,) * (3 - len(nk))
+        st = lib().lrcc_plan_check_mesh(d[0], d[1], d[2], nocc, nvir, naux, nrhs, buf, 512)
     if st != 0:
         raise LrccError(st, buf.value.decode())
 
@@ -158,6 +170,11 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_kmesh(self, n0, n1=1, n2=1):
+        """k points on an n0 x n1 x n2 mesh (flat index (j0 n1 + j1) n2 + j2); call before
+        set_hamiltonian.  Without it the k points form a 1D chain."""
+        self._check(self._L.lrcc_set_kmesh(self._h, int(n0), int(n1), int(n2)))
 
     def set_hamiltonian(self, nocc, fock, chol, dip):
         """fock [nk][n][n], chol [nk][nk][naux][n][n], dip [3][nk][n][n] (complex128)."""
@@ -225,6 +242,19 @@ class Context:
         alpha = np.zeros((len(om), 3, 3), dtype=np.complex128)
         self._check(self._L.lrcc_get_alpha(self._h, len(om), _ptr(alpha)))
         return alpha, rep.as_dict()
+
+    def alpha_velocity_gauge(self, omegas, mom, axis_mask=7, **opts):
+        """Velocity-gauge polarizability alpha^VG[nfreq][3][3] per cell from the momentum
+        matrices mom [3][nk][n][n] at non-zero frequencies: (a(w) - a(0)) / w^2 with a the
+        response of the momentum operator.  Returns (alpha, report dict)."""
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        m = _c128(mom, (3, self.nk, self.n, self.n))
+        oo = self.solve_options(**opts)
+        rep = SolveReport()
+        a = np.zeros((len(om), 3, 3), dtype=np.complex128)
+        self._check(self._L.lrcc_alpha_velocity_gauge(self._h, int(axis_mask), len(om), _ptr(om), _ptr(m),
+                                                      ctypes.byref(oo), _ptr(a), ctypes.byref(rep)))
+        return a, rep.as_dict()
 
     def alpha_dipole_gradient(self, ifreq, x, y, **opts):
         """d alpha_xy(omega_ifreq) / d mu: complex [3][nk][n][n] such that the change of

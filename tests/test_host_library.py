@@ -39,10 +39,20 @@ def test_plans_in_bounds_edge_sizes(nk, o, v, naux, nrhs):
     plan_check(nk, o, v, naux, nrhs)
 
 
+@pytest.mark.parametrize("mesh,o,v,naux,nrhs", [((2, 2, 1), 2, 3, 5, 3), ((2, 2, 2), 1, 3, 4, 2),
+                                                 ((3, 2, 1), 2, 4, 6, 2), ((2, 2, 2), 8, 40, 144, 12),
+                                                 ((1, 1, 4), 3, 5, 7, 24)])
+def test_plans_in_bounds_on_3d_meshes(mesh, o, v, naux, nrhs):
+    from paper_2508_01266_amd import plan_check
+    plan_check(mesh, o, v, naux, nrhs)
+
+
 def test_plan_check_rejects_bad_sizes():
     from paper_2508_01266_amd import LrccError, plan_check
     with pytest.raises(LrccError):
         plan_check(0, 1, 1, 1, 1)
+    with pytest.raises(LrccError):
+        plan_check((2, 0, 1), 1, 1, 1, 1)
 
 
 def test_create_without_device_reports_error():
