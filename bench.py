@@ -89,6 +89,70 @@ def time_sigma(ctx, x1, x2, y1, y2, om, prec, steps, warmup, torch):
     return (t1 - t0) / steps, prof
 
 
+def mesh_sigma(lr, torch, steps, mesh=(2, 2, 2), nocc=8, nvir=40, naux=144, nfreq=2):
+    """Sigma on a 3D k mesh (n0 x n1 x n2 Monkhorst-Pack points, momenta added componentwise):
+    the batched workload's orbital sizes on the 2 x 2 x 2 mesh, 3 axes x +-omega x nfreq
+    right-hand sides, complex64 and complex128, integrals rebuilt in LDS."""
+    import numpy as np
+    import synth
+    nk = int(np.prod(mesh))
+    rng = synth.rng_for(6, nk, nocc, nvir, extra=mesh)
+    sig = 0.05 * ((12 * 48 ** 0.5) / (nvir * (naux / nk) ** 0.5)) ** 0.5
+    H = synth.hamiltonian(mesh, nocc, nvir, naux, rng, chol_sigma=sig)
+    t1, t2 = synth.random_amplitudes(mesh, nocc, nvir, rng, 0.02, 0.02)
+    R = 6 * nfreq
+    x1, x2 = synth.random_vectors(R, mesh, nocc, nvir, rng, 0.1, 0.1)
+    om = np.array([s * 0.05 * (j + 1) for _ in range(3) for j in range(nfreq) for s in (1, -1)])
+    ctx = lr.Context(0)
+    ctx.set_kmesh(*mesh)
+    ctx.set_hamiltonian(nocc, H['fock'], H['chol'], H['dip'])
+    ctx.set_amplitudes(t1, t2 * nk)
+    dev = torch.device("cuda:0")
+    X1, X2 = torch.from_numpy(x1).to(dev), torch.from_numpy(x2 * nk).to(dev)
+    del x1, x2
+    Y1, Y2 = torch.empty_like(X1), torch.empty_like(X2)
+    OM = torch.from_numpy(om).to(dev)
+    alg = R * sigma_alg_flops(nk, nocc, nvir)
+    out = {"mesh": list(mesh), "nk": nk, "nocc": nocc, "nvir": nvir, "naux": naux, "nrhs": R,
+           "algorithmic_flops_per_step": alg}
+    for prec, name in ((lr.FP32, "f32"), (lr.FP64, "f64")):
+        dt, prof = time_sigma(ctx, X1, X2, Y1, Y2, OM, prec, steps, 1, torch)
+        lad = prof["ladder"][0] / max(prof["ladder"][1], 1) / 1e3
+        out[name] = {"ms_per_step": dt * 1e3, "value": alg / dt / 1e12, "ladder_ms_avg": lad * 1e3,
+                     "ladder_frac": ctx.ladder_flops(R, prec) / lad / 1e12 / PEAK[name]}
+        log(f"mesh {mesh} sigma ({name}): {dt * 1e3:.1f} ms")
+    ctx.close()
+    return out
+
+
+def velocity_gauge_alpha(lr, torch, tol):
+    """Time to the velocity-gauge polarizability on the three-k chain workload (Nk=3, nocc=4,
+    nvir=20, Naux=72): device CCSD, then one batched solve of the momentum response at
+    0 and the two frequencies, mixed and FP64; the length-gauge alpha of the same system
+    beside it."""
+    import numpy as np
+    import synth
+    w = synth.WORKLOADS["c2"]
+    rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift)
+    d = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, synth.rng_for(7, w.nk, w.nocc, w.nvir))['dip'].imag
+    mom = 1j * (d - np.swapaxes(d, -1, -2))
+    ctx = lr.Context(0)
+    ctx.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+    _, _, e, crep = ctx.solve_ccsd(tol=1e-10, max_iter=300)
+    om = [x for x in w.omegas if x != 0.0]
+    out = {"workload": "c2", "omegas": om, "ccsd_energy_per_cell": e}
+    for name, prec in (("mixed", lr.FP32), ("fp64", lr.FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, rep = ctx.alpha_velocity_gauge(om, mom, tol=tol, precision=prec)
+        out[name] = {"seconds": time.perf_counter() - t0, "alpha_vg_diag": [float(a[0, x, x].real) for x in range(3)],
+                     "report": rep}
+        log(f"velocity-gauge alpha ({name}) in {out[name]['seconds']:.2f} s")
+    ctx.close()
+    return out
+
+
 def latency_small(lr, torch, reps=50):
     """Microseconds per sigma on the molecular-limit workload (Nk=1, nocc=4, nvir=12,
     Naux=48; 3 axes x (0, +w, -w) = 9 right-hand sides), eager launches vs one HIP
@@ -216,6 +280,11 @@ def main():
     ap.add_argument("--ccsd-iter", type=int, default=300)
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch variants instead of autotuning")
     ap.add_argument("--uneven", action="store_true", help="also time the twelve-chain uneven batch")
+    ap.add_argument("--mesh", action="store_true", help="also time the sigma on a 2x2x2 k mesh")
+    ap.add_argument("--velocity", action="store_true", help="also time the velocity-gauge alpha (c2)")
+    ap.add_argument("--counters", action="store_true",
+                    help="only one complex64 sigma (heuristic launch variants) and then a plain 2 GiB device "
+                         "copy that calibrates hardware byte counters; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
@@ -234,7 +303,7 @@ def main():
     ctx = lr.Context(0)
     ctx.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
     ctx.set_amplitudes(t1, t2)
-    ctx.set_autotune(not args.no_tune)   # the warm-up application picks the launch variants
+    ctx.set_autotune(not (args.no_tune or args.counters))   # the warm-up application picks the variants
     X1 = torch.from_numpy(x1).to(dev)
     X2 = torch.from_numpy(x2).to(dev)
     sample = (x1[0].copy(), x2[0].copy())
@@ -242,6 +311,17 @@ def main():
     Y2 = torch.empty_like(X2)
     OM = torch.from_numpy(omega).to(dev)
     del x1, x2
+    if args.counters:
+        ctx.apply_sigma_dev(X1, X2, Y1, Y2, OM, lr.FP32, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        log("counters: one complex64 sigma done")
+        a = torch.ones(1 << 28, dtype=torch.float64, device=dev)     # 2 GiB read, 2 GiB written
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("counters: 2 GiB device copy done")
+        ctx.close()
+        return
 
     alg = nrhs * sigma_alg_flops(nk, o, v)
     lad = nrhs * ladder_alg_flops(nk, o, v)
@@ -350,6 +430,13 @@ def main():
                                        for k in res},
             "reports": {k: res[k][2] for k in res},
         }
+    if args.mesh or args.velocity or args.uneven:
+        ctx.close()               # the extra workloads need the memory
+        torch.cuda.empty_cache()
+    if args.mesh:
+        out["mesh_2x2x2"] = mesh_sigma(lr, torch, max(1, args.steps // 2))
+    if args.velocity:
+        out["velocity_gauge_c2"] = velocity_gauge_alpha(lr, torch, args.alpha_tol)
     if args.uneven:
         ctx.close()               # the twelve chains need the memory
         torch.cuda.empty_cache()

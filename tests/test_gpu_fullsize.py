@@ -116,22 +116,22 @@ def test_c4_forward_modes_and_transpose():
         assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
-def test_c4_dipole_gradient_against_finite_difference():
-    """Nk=7, o=10, v=60, Naux=210: device CCSD ground state, alpha_zz(0.0656) and its dipole
-    gradient; alpha is bilinear in mu_z at fixed amplitudes, so the central difference along a
-    Hermitian perturbation is exact up to the solver tolerance."""
+def test_c4s_dipole_gradient_against_finite_difference():
+    """Adjoint workload slice (Nk=3, o=10, v=60, Naux=210): device CCSD ground state,
+    alpha_zz(0.0656) and its dipole gradient; alpha is bilinear in mu_z at fixed amplitudes, so
+    the central difference along a Hermitian perturbation is exact up to the solver tolerance."""
     import paper_2508_01266_amd as lr
-    w = synth.WORKLOADS["c4"]
+    w = synth.WORKLOADS["c4s"]
     rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
     H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=w.chol_sigma)
-    V = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, synth.rng_for(97, 7, 10, 60))['dip']
+    V = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, synth.rng_for(97, w.nk, w.nocc, w.nvir))['dip']
     c = lr.Context(0)
     c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
     t1, t2, e, rep = c.solve_ccsd(tol=1e-9, max_iter=300)
-    print(f"c4 CCSD: E/cell {e:.10f} {rep}", flush=True)
+    print(f"c4s CCSD: E/cell {e:.10f} {rep}", flush=True)
     om = [0.0656]
     a0, r0 = c.solve(om, axis_mask=4, tol=1e-11, precision=lr.FP64)
-    print(f"c4 alpha_zz {a0[0, 2, 2]} {r0}", flush=True)
+    print(f"c4s alpha_zz {a0[0, 2, 2]} {r0}", flush=True)
     g = c.alpha_dipole_gradient(0, 2, 2, tol=1e-11)
     got = np.sum(g[2] * V[2])
     hstep = 0.5
@@ -146,6 +146,6 @@ def test_c4_dipole_gradient_against_finite_difference():
         vals.append(a[0, 2, 2])
         c2.close()
     ref = (vals[0] - vals[1]) / (2 * hstep)
-    print(f"c4 d alpha_zz: gradient {got:.10f} central difference {ref:.10f}", flush=True)
+    print(f"c4s d alpha_zz: gradient {got:.10f} central difference {ref:.10f}", flush=True)
     assert abs(got - ref) < 1e-7 * max(1.0, abs(ref))
     c.close()

@@ -133,13 +133,13 @@ VG_OMEGAS = [0.1, 0.2]
 
 
 def _momentum(case, seed):
-    """Hermitian momentum-like matrices i*(A - A^T)-type: random Hermitian, scaled by i
-    and re-Hermitised (purely imaginary for a real basis, general here)."""
+    """Momentum-like matrices: i times a real antisymmetric matrix per axis and k (the form
+    of momentum integrals in a real basis; Hermitian)."""
     km, o, v, naux = case['km'], case['o'], case['v'], case['naux']
     nk = case['nk']
     extra = () if np.isscalar(km) else synth.mesh_dims(km)
-    m = synth.hamiltonian(km, o, v, naux, synth.rng_for(seed, nk, o, v, extra=extra))['dip'] * 1j
-    return (m + np.conj(np.swapaxes(m, -1, -2))) / 2
+    d = synth.hamiltonian(km, o, v, naux, synth.rng_for(seed, nk, o, v, extra=extra))['dip'].imag
+    return 1j * (d - np.swapaxes(d, -1, -2))
 
 
 @pytest.mark.parametrize("nk,mesh,o,v,naux,seed", VG_CASES)
@@ -148,6 +148,7 @@ def test_velocity_gauge_matches_oracle(nk, mesh, o, v, naux, seed):
     case = make_ccsd_case(nk, o, v, naux, 300 + seed, mesh=mesh)
     mom = _momentum(case, 990 + seed)
     ref, _ = oracle_alpha(case, VG_OMEGAS, ops=mom, velocity=True)
+    assert np.abs(ref).max() > 0.1
     c = _ctx(case)
     for prec, tol in ((lr.FP64, 1e-8), (lr.FP32, 1e-6)):
         a, rep = c.alpha_velocity_gauge(VG_OMEGAS, mom, tol=1e-12, precision=prec)

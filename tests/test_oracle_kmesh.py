@@ -196,8 +196,9 @@ def test_velocity_gauge_two_electron_exact():
     from oracle import solvers
     t1, t2, _, _ = solvers.solve_ccsd(hd, tol=1e-13)
     lam, _, _ = response.solve_lambda((t1, t2), hd)
-    mom = synth.hamiltonian(nk, o, v, 6, synth.rng_for(956, nk, o, v))['dip'] * 1j
-    mom = (mom + np.conj(np.swapaxes(mom, -1, -2))) / 2
+    # momentum matrices of a real basis: i times a real antisymmetric matrix (Hermitian)
+    d = synth.hamiltonian(nk, o, v, 6, synth.rng_for(956, nk, o, v))['dip'].imag
+    mom = 1j * (d - np.swapaxes(d, -1, -2))
     ps = [torch.from_numpy(layout.dense_one_body(mom[x], nk, o, v)) for x in range(3)]
     omegas = [0.1, 0.3]
     a_vg = response.polarizability_velocity((t1, t2), lam, ps, omegas, hd, nk=nk)
@@ -207,3 +208,4 @@ def test_velocity_gauge_two_electron_exact():
             s = fockspace.fci_polarizability(f, g, nk * o, P[X], P[Y], [0.0] + omegas)[0]
             ref = [(s[i + 1] - s[0]) / w ** 2 for i, w in enumerate(omegas)]
             assert np.abs(a_vg[:, X, Y] - np.array(ref)).max() < 1e-8 * max(1.0, np.abs(ref).max())
+    assert np.abs(a_vg).max() > 0.1
