@@ -337,6 +337,7 @@ def main():
     # plus the in-LDS integral rebuild) per second against the matrix-core peak
     lad_exec = ctx.ladder_flops(nrhs, lr.FP32)
     lad_exec64 = ctx.ladder_flops(nrhs, lr.FP64)
+    lad_mfma = ctx.ladder_mfma_flops(nrhs, lr.FP32)
     achieved = lad_exec / lad_avg / 1e12
     traffic = None
     if (args.workload == LADDER_TRAFFIC["workload"] and LADDER_TRAFFIC["bytes"] is not None
@@ -363,6 +364,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["f32"], "traffic": traffic, "kernel": "ladder",
                      "ladder_ms_avg": lad_avg * 1e3, "executed_flops_per_launch": lad_exec,
+                     "mfma_flops_per_launch": lad_mfma, "mfma_frac": lad_mfma / lad_avg / 1e12 / PEAK["f32"],
                      "algorithmic_flops_per_launch": lad, "algorithmic_tflops": lad / lad_avg / 1e12},
         "fp64": {"value": alg / dt64 / 1e12, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
                  "ladder_ms_avg": lad64_avg * 1e3, "ladder_achieved": lad_exec64 / lad64_avg / 1e12,
@@ -396,6 +398,11 @@ def main():
     log(f"stored-integral ladder: complex64 sigma {s32*1e3:.1f} ms, complex128 {s64*1e3:.1f} ms")
     ctx2.close()
     out["latency_c1_9rhs"] = latency_small(lr, torch)
+    # attainable ceilings on this device (project microbenchmarks), beside the published peaks
+    out["peaks_measured"] = lr.measure_peaks(0)
+    out["peaks_measured"]["published"] = {"mfma_f32_tflops": PEAK["f32"], "mfma_f64_tflops": PEAK["f64"],
+                                          "hbm_gbs": 8000.0}
+    log(f"measured peaks {out['peaks_measured']}")
     log(f"c1 latency {out['latency_c1_9rhs']}")
     del X1, X2, Y1, Y2, OM
     torch.cuda.empty_cache()

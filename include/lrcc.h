@@ -183,8 +183,27 @@ lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *exe
 /* Real floating-point operations executed by the ladder launch of one sigma
  * application (the profiling category 1 of lrcc_read_profile): the matrix-core
  * product over the unique momentum/index pairs when the integrals are stored,
- * or the ladder kernel's products including its in-LDS rebuild. */
+ * or the ladder kernel's products including its in-LDS rebuild, for the kernel
+ * variant in use (after autotuning), at 8 real flops per complex multiply-add
+ * formed.  The pipelined kernel forms each complex64 product from three real
+ * matrix-core products (Gauss' method), so its matrix-core instructions do 3/4
+ * of that count there. */
 lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
+/* The same launch counted in real matrix-core flops (the work of its MFMA
+ * instructions): 3/4 of lrcc_ladder_flops for the complex64 pipelined kernel,
+ * equal to it otherwise. */
+lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *mfma);
+
+/* Measurement helper, not an operation of the method: the attainable dense
+ * matrix-core rates of the device (complex-free 16x16x4 fp32 and fp64 MFMA
+ * streams, eight independent accumulators per wave, two waves per SIMD, all
+ * compute units) in TFLOP/s and the bandwidth of a 2 GiB device copy (bytes
+ * read + written per second, GB/s, best of three) -- the ceilings the sigma
+ * kernels' roofline is read against, beside the published peaks.  Allocates
+ * and frees its own device buffers (about 4 GiB).  LRCC_E_ARG for null
+ * outputs, LRCC_E_HIP / LRCC_E_OOM on device errors. */
+lrcc_status lrcc_measure_peaks(int hip_device, double *mfma_f32_tflops, double *mfma_f64_tflops,
+                               double *hbm_copy_gbs);
 
 /* Host-only validation of the launch plans for a problem size: records every
  * kernel of lrcc_set_hamiltonian, lrcc_set_amplitudes and lrcc_apply_sigma (FP64

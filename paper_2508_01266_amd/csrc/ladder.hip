@@ -546,6 +546,9 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     constexpr int YPT = BM * LTK / NTP;            // Y elements per thread per step
     constexpr int LPT = 4 * QCH * 32 / NTP;        // Cholesky elements per thread per chunk
     static_assert(WM * WN == NTP / 64, "8 waves");
+    // complex products as three real matrix-core products in complex64 (the register file
+    // holds the third accumulator set there; complex128 keeps four products)
+    constexpr bool kGauss = sizeof(T) == 4;
     static_assert(YPT * NTP == BM * LTK && LPT * NTP == 4 * QCH * 32, "even loads");
     constexpr int PY = 16, PL = 16, PW = sizeof(T) == 8 ? 9 : 17;
     __shared__ T Wr[LTK][LTN + PW], Wi[LTK][LTN + PW];
@@ -636,11 +639,18 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         }
     };
 
-    v4 accr[FM][FN], acci[FM][FN];
+    // Gauss accumulators (complex64 only): accr = k1, acci = k2, acc3 = k3 of every block
+    v4 accr[FM][FN], acci[FM][FN], acc3[kGauss ? FM : 1][kGauss ? FN : 1];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+    if constexpr (kGauss) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc3[i][j] = v4{0, 0, 0, 0};
+    }
 
     int ke = first_valid(0), e0 = 0, f0 = 0;
     if (ke < nk) load_chunk(ke, e0, f0, 0);
@@ -648,7 +658,9 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         load_y(ke, e0, f0);
         // rebuild: waves 0-3 G1[(a,e)][(b,f)] = sum La(ka,ke)[a][e] Lb(kb,kf)[b][f],
         //          waves 4-7 G2[(a,f)][(b,e)] = sum La(ka,kf)[a][f] Lb(kb,ke)[b][e]
-        v4 gr = v4{0, 0, 0, 0}, gi = v4{0, 0, 0, 0};
+        // complex64: three real products per complex one (Gauss): with k1 = yr (xr + xi),
+        // k2 = xr (yi - yr), k3 = xi (yr + yi): re = k1 - k3, im = k1 + k2
+        v4 gr = v4{0, 0, 0, 0}, gi = v4{0, 0, 0, 0}, g3 = v4{0, 0, 0, 0};
         const int ra = second ? 2 : 0, rb = second ? 3 : 1;
         for (int q0 = 0; q0 < naux; q0 += QCH) {
             store_chunk();
@@ -659,12 +671,22 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
                 const int kr = kk + (lane >> 4), c = lane & 15;
                 const T xr = Lr[ra][kr][rw + c], xi = Li[ra][kr][rw + c];
                 const T yr = Lr[rb][kr][cw + c], yi = Li[rb][kr][cw + c];
-                gr = MfmaL<T>::mma(xr, yr, gr);
-                gr = MfmaL<T>::mma(-xi, yi, gr);
-                gi = MfmaL<T>::mma(xr, yi, gi);
-                gi = MfmaL<T>::mma(xi, yr, gi);
+                if constexpr (kGauss) {
+                    gr = MfmaL<T>::mma(xr + xi, yr, gr);
+                    gi = MfmaL<T>::mma(xr, yi - yr, gi);
+                    g3 = MfmaL<T>::mma(xi, yr + yi, g3);
+                } else {
+                    gr = MfmaL<T>::mma(xr, yr, gr);
+                    gr = MfmaL<T>::mma(-xi, yi, gr);
+                    gi = MfmaL<T>::mma(xr, yi, gi);
+                    gi = MfmaL<T>::mma(xi, yr, gi);
+                }
             }
             __syncthreads();
+        }
+        if constexpr (kGauss) {
+            gi = gr + gi;
+            gr = gr - g3;
         }
         // W[(e,f)][(a,b)] = G1[(a,e)][(b,f)] - G2[(a,f)][(b,e)]: the G1 waves write, then the G2 waves subtract
         if (!second) {
@@ -707,13 +729,28 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
-                    accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
-                    acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
-                    acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
+                    if constexpr (kGauss) {
+                        accr[i][j] = MfmaL<T>::mma(ar[i] + ai[i], br[j], accr[i][j]);
+                        acci[i][j] = MfmaL<T>::mma(ar[i], bi[j] - br[j], acci[i][j]);
+                        acc3[i][j] = MfmaL<T>::mma(ai[i], br[j] + bi[j], acc3[i][j]);
+                    } else {
+                        accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
+                        accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
+                        acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
+                        acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
+                    }
                 }
         }
         __syncthreads();
+    }
+    if constexpr (kGauss) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                acci[i][j] = accr[i][j] + acci[i][j];
+                accr[i][j] = accr[i][j] - acc3[i][j];
+            }
     }
 
     C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
@@ -829,7 +866,9 @@ double ladder_executed_flops(const LadderArgs &a, bool fp64) {
         const double steps = (double)a.nk * a.nk * a.nk * tilesM * tA * tB * a.nk * tE * tF;
         return steps * (main_step + rebuild_step);
     }
-    // packed: count the unique output tiles and unique input tiles actually visited
+    // packed: count the unique output tiles and unique input tiles actually visited (8 real
+    // flops per complex product formed, also where the complex64 pipelined kernel forms it
+    // from three real matrix-core products)
     const int nk = a.nk;
     double steps = 0;
     for (int ki = 0; ki < nk; ++ki)
@@ -847,6 +886,10 @@ double ladder_executed_flops(const LadderArgs &a, bool fp64) {
                 steps += out * in;
             }
     return steps * tilesM * (main_step + 2.0 * rebuild_step);
+}
+
+double ladder_mfma_fraction(const LadderArgs &a, bool fp64) {
+    return (use_big(a) && a.packed == 2 && !fp64) ? 0.75 : 1.0;
 }
 
 template hipError_t launch_ladder<double>(const LadderArgs &, hipStream_t);

@@ -3109,7 +3109,22 @@ lrcc_status lrcc_ladder_flops(lrcc_ctx *c, int nrhs, int precision, double *exec
     return guarded(c, [&] {
         if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
         if (!executed || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
-        *executed = (double)sigma_program(c, precision, nrhs)->tag_flops[TAG_LADDER];
+        Program *P = sigma_program(c, precision, nrhs);
+        // the rebuild-in-LDS ladder: count for the kernel variant in use (the autotuner may
+        // have replaced the one the program was recorded with)
+        *executed = P->ladder_args ? ladder_executed_flops(*P->ladder_args, precision == LRCC_FP64)
+                                   : (double)P->tag_flops[TAG_LADDER];
+    });
+}
+
+lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *c, int nrhs, int precision, double *mfma) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!mfma || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
+        Program *P = sigma_program(c, precision, nrhs);
+        const bool fp64 = precision == LRCC_FP64;
+        *mfma = P->ladder_args ? ladder_executed_flops(*P->ladder_args, fp64) * ladder_mfma_fraction(*P->ladder_args, fp64)
+                               : (double)P->tag_flops[TAG_LADDER];
     });
 }
 

@@ -71,6 +71,8 @@ def lib():
         L.lrcc_sigma_flops.argtypes = [vp, i, i, dp]
         L.lrcc_ladder_flops.argtypes = [vp, i, i, dp]
         L.lrcc_ladder_flops.restype = ctypes.c_int
+        L.lrcc_ladder_mfma_flops.argtypes = [vp, i, i, dp]
+        L.lrcc_ladder_mfma_flops.restype = ctypes.c_int
         for f in ("lrcc_set_profiling", "lrcc_read_profile", "lrcc_sigma_flops"):
             getattr(L, f).restype = ctypes.c_int
         L.lrcc_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -95,6 +97,8 @@ def lib():
             getattr(L, f).restype = ctypes.c_int
         L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
         L.lrcc_plan_check.restype = ctypes.c_int
+        L.lrcc_measure_peaks.argtypes = [i, dp, dp, dp]
+        L.lrcc_measure_peaks.restype = ctypes.c_int
         L.lrcc_plan_check_mesh.argtypes = [i, i, i, i, i, i, i, ctypes.c_char_p, i]
         L.lrcc_plan_check_mesh.restype = ctypes.c_int
         L.lrcc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
@@ -129,6 +133,16 @@ def _c128(a, shape=None):
 
 def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data)
+
+
+def measure_peaks(device=0):
+    """Attainable matrix-core rates (fp32, fp64 TFLOP/s) and device-copy bandwidth (GB/s)
+    measured by the library's microbenchmarks."""
+    f32, f64, bw = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = lib().lrcc_measure_peaks(int(device), ctypes.byref(f32), ctypes.byref(f64), ctypes.byref(bw))
+    if st != 0:
+        raise LrccError(st, "microbenchmark failed")
+    return {"mfma_f32_tflops": f32.value, "mfma_f64_tflops": f64.value, "hbm_copy_gbs": bw.value}
 
 
 def plan_check(nk, nocc, nvir, naux, nrhs):
@@ -344,6 +358,11 @@ class Context:
     def ladder_flops(self, nrhs, precision=FP64):
         out = ctypes.c_double()
         self._check(self._L.lrcc_ladder_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
+        return out.value
+
+    def ladder_mfma_flops(self, nrhs, precision=FP64):
+        out = ctypes.c_double()
+        self._check(self._L.lrcc_ladder_mfma_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
         return out.value
 
     def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None, adjoint=False):

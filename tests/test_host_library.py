@@ -62,3 +62,12 @@ def test_create_without_device_reports_error():
     from paper_2508_01266_amd import Context, LrccError
     with pytest.raises(LrccError):
         Context(0)
+
+
+def test_measure_peaks_without_device_reports_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_2508_01266_amd import LrccError, measure_peaks
+    with pytest.raises(LrccError):
+        measure_peaks(0)
