@@ -195,13 +195,14 @@ lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *ex
 lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *mfma);
 
 /* Measurement helper, not an operation of the method: the attainable dense
- * matrix-core rates of the device (complex-free 16x16x4 fp32 and fp64 MFMA
- * streams, eight independent accumulators per wave, two waves per SIMD, all
- * compute units) in TFLOP/s and the bandwidth of a 2 GiB device copy (bytes
- * read + written per second, GB/s, best of three) -- the ceilings the sigma
- * kernels' roofline is read against, beside the published peaks.  Allocates
- * and frees its own device buffers (about 4 GiB).  LRCC_E_ARG for null
- * outputs, LRCC_E_HIP / LRCC_E_OOM on device errors. */
+ * matrix-core rates of the device (streams of real 16x16x4 fp32 and fp64 MFMA
+ * products on all compute units, best over 1, 2 and 4 waves per SIMD and 8 or
+ * 16 independent accumulators per wave) in TFLOP/s and the bandwidth of a
+ * 2 GiB device copy (bytes read + written per second, GB/s, best of four runs
+ * at two grid sizes) -- the ceilings the sigma kernels' roofline is read
+ * against, beside the published peaks.  Allocates and frees its own device
+ * buffers (about 4 GiB).  LRCC_E_ARG for null outputs, LRCC_E_HIP / LRCC_E_OOM
+ * on device errors. */
 lrcc_status lrcc_measure_peaks(int hip_device, double *mfma_f32_tflops, double *mfma_f64_tflops,
                                double *hbm_copy_gbs);
 
