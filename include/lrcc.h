@@ -185,13 +185,12 @@ lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *exe
  * product over the unique momentum/index pairs when the integrals are stored,
  * or the ladder kernel's products including its in-LDS rebuild, for the kernel
  * variant in use (after autotuning), at 8 real flops per complex multiply-add
- * formed.  The pipelined kernel forms each complex64 product from three real
- * matrix-core products (Gauss' method), so its matrix-core instructions do 3/4
- * of that count there. */
+ * formed. */
 lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
 /* The same launch counted in real matrix-core flops (the work of its MFMA
- * instructions): 3/4 of lrcc_ladder_flops for the complex64 pipelined kernel,
- * equal to it otherwise. */
+ * instructions): the complex64 pipelined kernel forms the complex products of
+ * its integral rebuild from three real matrix-core products (Gauss' method),
+ * which count 6 instead of 8; equal to lrcc_ladder_flops otherwise. */
 lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *mfma);
 
 /* Measurement helper, not an operation of the method: the attainable dense
@@ -300,7 +299,7 @@ lrcc_status lrcc_solve_ccsd(lrcc_ctx *ctx, double tol, int max_iter, double *t1,
  * (chain, k block, tile) work items from an atomic queue, most expensive
  * chains first (uneven batches keep the device busy through the tail), then the
  * remaining steps.  Chains whose ladder is not the rebuild-in-LDS packed
- * kernel (stored integrals, or fewer than 192 (rhs, i, j) rows) run their
+ * kernel (stored integrals, or fewer than 320 (rhs, i, j) rows) run their
  * whole program on their own.  Results are bitwise those of
  * lrcc_apply_sigma_dev per chain.  The group does not own the contexts; destroy
  * it before them.  Arrays are indexed by chain; omega may be NULL.  Errors:

@@ -158,8 +158,8 @@ template <typename T>
 hipError_t launch_ladder_group(const LadderGroup &g, int nblocks, hipStream_t s);
 // real flops the ladder kernel executes (tile padding and LDS rebuild included)
 double ladder_executed_flops(const LadderArgs &a, bool fp64);
-// real matrix-core flops per executed flop of the ladder kernel in use (3/4 where complex
-// products are formed from three real products)
-double ladder_mfma_fraction(const LadderArgs &a, bool fp64);
+// the same launch in real matrix-core flops (complex products formed from three real
+// products count 6)
+double ladder_mfma_flops(const LadderArgs &a, bool fp64);
 
 }  // namespace lrcc

@@ -531,11 +531,13 @@ __global__ void __launch_bounds__(NTP) ladder_kernel_packed(LadderArgs p) {
 
 // Pipelined antisymmetry-packed variant (same arithmetic as ladder_kernel_packed):
 // WM x WN waves over a BM x 64 output tile, BM = 64 WM rows, so the rank-naux
-// integral rebuild (one 16x16 block per wave and step) is amortised over more
-// rows.  Global loads run one stage ahead in registers: the Y tile of a step is
-// fetched while its integral tile is rebuilt, each Cholesky chunk while the
-// previous one is multiplied, and the first chunk of the next step while the
-// current step's main product runs.
+// integral rebuild (eight 16x16 blocks per step, one per wave of the first eight)
+// is amortised over more rows: its cost relative to the main product is
+// 2 Naux / BM.  Global loads run one stage ahead in registers: the Y tile of a
+// step is fetched while its integral tile is rebuilt, each Cholesky chunk while
+// the previous one is multiplied, and the first chunk of the next step while the
+// current step's main product runs.  The load maps are hoisted: every load of a
+// thread has the same position inside its block.
 template <typename T, int WM, int WN, int QCH>
 __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int bx, const int blk) {
     typedef typename Cx<T>::type C2;
@@ -543,13 +545,14 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     constexpr int FM = 4;                          // 16-row blocks per wave
     constexpr int FN = LTN / (WN * 16);            // 16-column blocks per wave
     constexpr int BM = WM * FM * 16;               // rows per tile
-    constexpr int YPT = BM * LTK / NTP;            // Y elements per thread per step
-    constexpr int LPT = 4 * QCH * 32 / NTP;        // Cholesky elements per thread per chunk
-    static_assert(WM * WN == NTP / 64, "8 waves");
-    // complex products as three real matrix-core products in complex64 (the register file
-    // holds the third accumulator set there; complex128 keeps four products)
+    constexpr int NT = WM * WN * 64;               // threads per workgroup
+    constexpr int YPT = BM * LTK / NT;             // Y elements per thread per step
+    constexpr int LPT = 4 * QCH * 32 / NT;         // Cholesky elements per thread per chunk
+    static_assert(WM * WN >= 8, "eight waves rebuild the integral tile");
+    // the rebuild forms complex64 products as three real matrix-core products (complex128,
+    // and the main product in both precisions, keep four)
     constexpr bool kGauss = sizeof(T) == 4;
-    static_assert(YPT * NTP == BM * LTK && LPT * NTP == 4 * QCH * 32, "even loads");
+    static_assert(YPT * NT == BM * LTK && LPT * NT == 4 * QCH * 32, "even loads");
     constexpr int PY = 16, PL = 16, PW = sizeof(T) == 8 ? 9 : 17;
     __shared__ T Wr[LTK][LTN + PW], Wi[LTK][LTN + PW];
     __shared__ T Yr[LTK][BM + PY], Yi[LTK][BM + PY];
@@ -577,7 +580,8 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     const C2 *La = reinterpret_cast<const C2 *>(p.La);
     const C2 *Lb = reinterpret_cast<const C2 *>(p.Lb);
     C2 *Z = reinterpret_cast<C2 *>(p.Z);
-    const int gb = wave & 3, second = wave >> 2;
+    const int gb = wave & 3, second = (wave >> 2) & 1;
+    const bool rebuilder = wave < 8;
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     // steps (ke <= kf, e0, f0 >= e0 when ke == kf); the step after `s`, or ke = nk when done
@@ -595,6 +599,21 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         }
     };
 
+    // every load of a thread sits at the same in-block position: the maps are hoisted
+    static_assert(NT % LTK == 0 && ((QCH * 32) % NT == 0 || NT % (QCH * 32) == 0), "load maps");
+    const int ykk = tid % LTK, ym = tid / LTK;
+    const int ye = ykk / TF, yf = ykk % TF;
+    const int lx = (tid % 32) / 4, ly = tid % 4;
+    // Cholesky load q: matrix lwhich(q), vector row lrow(q) of the chunk
+    auto lwhich = [&](int q) {
+        if constexpr ((QCH * 32) % NT == 0) return (q * NT) / (QCH * 32);
+        else return (tid % NT) / (QCH * 32) + q * (NT / (QCH * 32));
+    };
+    auto lrow = [&](int q) {
+        if constexpr ((QCH * 32) % NT == 0) return ((q * NT) % (QCH * 32) + tid) / 32;
+        else return (tid % (QCH * 32)) / 32;
+    };
+
     C2 lv[LPT], yv[YPT];
     auto load_chunk = [&](int ke, int e0, int f0, int q0) {
         const int kf = kf_of(ke);
@@ -604,12 +623,10 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         const C2 *L3 = Lb + (i64)(kb * nk + ke) * naux * vv;
 #pragma unroll
         for (int q = 0; q < LPT; ++q) {
-            const int idx = tid + NTP * q;
-            const int which = idx / (QCH * 32), rem = idx % (QCH * 32);
-            const int qq = q0 + rem / 32, cc = rem % 32;
-            const int x = cc / 4, y = cc % 4;
-            const int r0 = (which == 0 || which == 2) ? a0 + x : b0 + x;
-            const int c0 = (which == 0 || which == 3) ? e0 + y : f0 + y;
+            const int which = lwhich(q);
+            const int qq = q0 + lrow(q);
+            const int r0 = (which == 0 || which == 2) ? a0 + lx : b0 + lx;
+            const int c0 = (which == 0 || which == 3) ? e0 + ly : f0 + ly;
             const C2 *src = which == 0 ? L0 : which == 1 ? L1 : which == 2 ? L2 : L3;
             C2 val; val.x = 0; val.y = 0;
             if (qq < naux && r0 < v && c0 < v) val = src[(i64)qq * vv + (i64)r0 * v + c0];
@@ -619,38 +636,29 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     auto store_chunk = [&]() {
 #pragma unroll
         for (int q = 0; q < LPT; ++q) {
-            const int idx = tid + NTP * q;
-            const int which = idx / (QCH * 32), rem = idx % (QCH * 32);
-            Lr[which][rem / 32][rem % 32] = lv[q].x;
-            Li[which][rem / 32][rem % 32] = lv[q].y;
+            Lr[lwhich(q)][lrow(q)][tid % 32] = lv[q].x;
+            Li[lwhich(q)][lrow(q)][tid % 32] = lv[q].y;
         }
     };
     auto load_y = [&](int ke, int e0, int f0) {
         const bool diag_in = ke == kf_of(ke);
-        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4;
+        const int e = e0 + ye, f = f0 + yf;
+        const bool ok = e < v && f < v && (!diag_in || e < f);
+        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4 + (i64)e * v + f;
 #pragma unroll
         for (int q = 0; q < YPT; ++q) {
-            const int idx = tid + NTP * q;
-            const int kk = idx % LTK, m = idx / LTK;
-            const int e = e0 + kk / TF, f = f0 + kk % TF;
+            const int m = m0 + ym + q * (NT / LTK);
             C2 val; val.x = 0; val.y = 0;
-            if (m0 + m < M && e < v && f < v && (!diag_in || e < f)) val = Yb[(i64)(m0 + m) * vv + (i64)e * v + f];
+            if (ok && m < M) val = Yb[(i64)m * vv];
             yv[q] = val;
         }
     };
 
-    // Gauss accumulators (complex64 only): accr = k1, acci = k2, acc3 = k3 of every block
-    v4 accr[FM][FN], acci[FM][FN], acc3[kGauss ? FM : 1][kGauss ? FN : 1];
+    v4 accr[FM][FN], acci[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
-    if constexpr (kGauss) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j) acc3[i][j] = v4{0, 0, 0, 0};
-    }
 
     int ke = first_valid(0), e0 = 0, f0 = 0;
     if (ke < nk) load_chunk(ke, e0, f0, 0);
@@ -667,7 +675,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
             __syncthreads();
             if (q0 + QCH < naux) load_chunk(ke, e0, f0, q0 + QCH);
 #pragma unroll 2
-            for (int kk = 0; kk < QCH; kk += 4) {
+            for (int kk = 0; kk < (rebuilder ? QCH : 0); kk += 4) {
                 const int kr = kk + (lane >> 4), c = lane & 15;
                 const T xr = Lr[ra][kr][rw + c], xi = Li[ra][kr][rw + c];
                 const T yr = Lr[rb][kr][cw + c], yi = Li[rb][kr][cw + c];
@@ -689,7 +697,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
             gr = gr - g3;
         }
         // W[(e,f)][(a,b)] = G1[(a,e)][(b,f)] - G2[(a,f)][(b,e)]: the G1 waves write, then the G2 waves subtract
-        if (!second) {
+        if (rebuilder && !second) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ae = rw + MfmaL<T>::row(lane, r);
@@ -699,7 +707,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
             }
         }
         __syncthreads();
-        if (second) {
+        if (rebuilder && second) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int af = rw + MfmaL<T>::row(lane, r);
@@ -710,9 +718,8 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         }
 #pragma unroll
         for (int q = 0; q < YPT; ++q) {
-            const int idx = tid + NTP * q;
-            Yr[idx % LTK][idx / LTK] = yv[q].x;
-            Yi[idx % LTK][idx / LTK] = yv[q].y;
+            Yr[ykk][ym + q * (NT / LTK)] = yv[q].x;
+            Yi[ykk][ym + q * (NT / LTK)] = yv[q].y;
         }
         __syncthreads();
         advance(ke, e0, f0);
@@ -729,28 +736,13 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    if constexpr (kGauss) {
-                        accr[i][j] = MfmaL<T>::mma(ar[i] + ai[i], br[j], accr[i][j]);
-                        acci[i][j] = MfmaL<T>::mma(ar[i], bi[j] - br[j], acci[i][j]);
-                        acc3[i][j] = MfmaL<T>::mma(ai[i], br[j] + bi[j], acc3[i][j]);
-                    } else {
-                        accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
-                        accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
-                        acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
-                        acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
-                    }
+                    accr[i][j] = MfmaL<T>::mma(ar[i], br[j], accr[i][j]);
+                    accr[i][j] = MfmaL<T>::mma(-ai[i], bi[j], accr[i][j]);
+                    acci[i][j] = MfmaL<T>::mma(ar[i], bi[j], acci[i][j]);
+                    acci[i][j] = MfmaL<T>::mma(ai[i], br[j], acci[i][j]);
                 }
         }
         __syncthreads();
-    }
-    if constexpr (kGauss) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                acci[i][j] = accr[i][j] + acci[i][j];
-                accr[i][j] = accr[i][j] - acc3[i][j];
-            }
     }
 
     C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
@@ -775,7 +767,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
 }
 
 template <typename T, int WM, int WN, int QCH>
-__global__ void __launch_bounds__(NTP) ladder_kernel_pipe(LadderArgs p) {
+__global__ void __launch_bounds__(WM * WN * 64) ladder_kernel_pipe(LadderArgs p) {
     ladder_pipe_tile<T, WM, WN, QCH>(p, blockIdx.x, blockIdx.y);
 }
 
@@ -784,8 +776,9 @@ __global__ void __launch_bounds__(NTP) ladder_kernel_pipe(LadderArgs p) {
 // the queue is empty.  The ladders are ordered by decreasing cost per item, so
 // the expensive tiles start first and the cheap ones fill the tail.
 template <typename T, int WM, int WN, int QCH>
-__global__ void __launch_bounds__(NTP) ladder_kernel_pipe_group(LadderGroup g) {
+__global__ void __launch_bounds__(WM * WN * 64) ladder_kernel_pipe_group(LadderGroup g) {
     __shared__ long long item_s;
+
     while (true) {
         if (threadIdx.x == 0) item_s = (long long)atomicAdd(g.counter, 1u);
         __syncthreads();
@@ -805,10 +798,12 @@ __global__ void k_zero_counter(unsigned *c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }
 
-// launch shape of the pipelined kernel per precision (256-row tiles; Cholesky chunks of
-// 32 vectors in complex64 and 8 in complex128, sized to the register file and LDS)
+// launch shape of the pipelined kernel per precision: complex64 384-row tiles of
+// 12 waves (three per SIMD, 168 registers each) with 24-vector Cholesky chunks,
+// complex128 256-row tiles of 8 waves with 8-vector chunks, sized to the register
+// file and LDS
 template <typename T> struct PipeCfg;
-template <> struct PipeCfg<float> { static constexpr int WM = 4, WN = 2, QCH = 32, BM = 256; };
+template <> struct PipeCfg<float> { static constexpr int WM = 6, WN = 2, QCH = 24, BM = 384; };
 template <> struct PipeCfg<double> { static constexpr int WM = 4, WN = 2, QCH = 8, BM = 256; };
 
 template <typename T>
@@ -821,7 +816,7 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
         if (a.packed == 2) {
             typedef PipeCfg<T> C;
             dim3 gp(((M + C::BM - 1) / C::BM) * tA * tB, a.nk * a.nk * a.nk);
-            hipLaunchKernelGGL((ladder_kernel_pipe<T, C::WM, C::WN, C::QCH>), gp, dim3(NTP), 0, s, a);
+            hipLaunchKernelGGL((ladder_kernel_pipe<T, C::WM, C::WN, C::QCH>), gp, dim3(C::WM * C::WN * 64), 0, s, a);
         } else if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
         else hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
     } else {
@@ -843,7 +838,7 @@ template <typename T>
 hipError_t launch_ladder_group(const LadderGroup &g, int nblocks, hipStream_t s) {
     typedef PipeCfg<T> C;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, g.counter);
-    hipLaunchKernelGGL((ladder_kernel_pipe_group<T, C::WM, C::WN, C::QCH>), dim3(nblocks), dim3(NTP), 0, s, g);
+    hipLaunchKernelGGL((ladder_kernel_pipe_group<T, C::WM, C::WN, C::QCH>), dim3(nblocks), dim3(C::WM * C::WN * 64), 0, s, g);
     return hipGetLastError();
 }
 
@@ -852,7 +847,7 @@ template long long ladder_group_tiles<float>(const LadderArgs &);
 template hipError_t launch_ladder_group<double>(const LadderGroup &, int, hipStream_t);
 template hipError_t launch_ladder_group<float>(const LadderGroup &, int, hipStream_t);
 
-double ladder_executed_flops(const LadderArgs &a, bool fp64) {
+double ladder_flop_count(const LadderArgs &a, bool fp64, bool mfma) {
     const int M = a.nrhs * a.o * a.o;
     const bool big = use_big(a);
     const bool pipe = big && a.packed == 2;
@@ -866,9 +861,10 @@ double ladder_executed_flops(const LadderArgs &a, bool fp64) {
         const double steps = (double)a.nk * a.nk * a.nk * tilesM * tA * tB * a.nk * tE * tF;
         return steps * (main_step + rebuild_step);
     }
-    // packed: count the unique output tiles and unique input tiles actually visited (8 real
-    // flops per complex product formed, also where the complex64 pipelined kernel forms it
-    // from three real matrix-core products)
+    // packed: count the unique output tiles and unique input tiles actually visited, at 8 real
+    // flops per complex product formed; in real matrix-core flops (mfma) the complex64
+    // pipelined kernel's rebuild products count 6
+    const double rb = (mfma && pipe && !fp64) ? 0.75 : 1.0;
     const int nk = a.nk;
     double steps = 0;
     for (int ki = 0; ki < nk; ++ki)
@@ -885,12 +881,11 @@ double ladder_executed_flops(const LadderArgs &a, bool fp64) {
                 }
                 steps += out * in;
             }
-    return steps * tilesM * (main_step + 2.0 * rebuild_step);
+    return steps * tilesM * (main_step + 2.0 * rb * rebuild_step);
 }
 
-double ladder_mfma_fraction(const LadderArgs &a, bool fp64) {
-    return (use_big(a) && a.packed == 2 && !fp64) ? 0.75 : 1.0;
-}
+double ladder_executed_flops(const LadderArgs &a, bool fp64) { return ladder_flop_count(a, fp64, false); }
+double ladder_mfma_flops(const LadderArgs &a, bool fp64) { return ladder_flop_count(a, fp64, true); }
 
 template hipError_t launch_ladder<double>(const LadderArgs &, hipStream_t);
 template hipError_t launch_ladder<float>(const LadderArgs &, hipStream_t);

@@ -778,7 +778,9 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
                 break;
             }
             LadderArgs la = ladder_args<T>(c, op.A.p, S.La, S.Lb, op.C.p, R, op.alpha.real());
-            la.packed = c->pack_ladder ? 2 : 0;  // dtau is antisymmetric in (e,f)
+            // dtau is antisymmetric in (e,f): packed kernels; the pipelined one from 320 rows on
+            // (its 384-row tiles would idle more than a sixth of their rows below)
+            la.packed = c->pack_ladder ? ((i64)R * c->no * c->no >= 320 ? 2 : 1) : 0;
             auto lp = std::make_shared<LadderArgs>(la);
             P->ops.push_back([lp](hipStream_t s) { return launch_ladder<T>(*lp, s); });
             P->ladder_args = lp;
@@ -2928,7 +2930,7 @@ static void group_apply(lrcc_group *g, const int *nrhs, const double *const *ome
         prog[i] = sigma_program(c, precision, nrhs[i]);
         key.push_back(nrhs[i]);
         const Program *p = prog[i];
-        if (p->ladder_args && p->ladder_args->packed == 2 && (i64)nrhs[i] * c->no * c->no >= 192) join.push_back(i);
+        if (p->ladder_args && p->ladder_args->packed == 2 && (i64)nrhs[i] * c->no * c->no >= 320) join.push_back(i);
     }
     auto io = [&](int i) {
         lrcc_ctx *c = g->ctx[i];
@@ -3123,8 +3125,7 @@ lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *c, int nrhs, int precision, double 
         if (!mfma || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
         Program *P = sigma_program(c, precision, nrhs);
         const bool fp64 = precision == LRCC_FP64;
-        *mfma = P->ladder_args ? ladder_executed_flops(*P->ladder_args, fp64) * ladder_mfma_fraction(*P->ladder_args, fp64)
-                               : (double)P->tag_flops[TAG_LADDER];
+        *mfma = P->ladder_args ? ladder_mfma_flops(*P->ladder_args, fp64) : (double)P->tag_flops[TAG_LADDER];
     });
 }
 

@@ -7,9 +7,9 @@ from tests.sigma_cases import make_case, oracle_sigma
 
 pytestmark = pytest.mark.gpu
 
-# (nk, o, v, naux, nrhs, seed): >= 192 (rhs, i, j) rows each, so all join the shared launch,
+# (nk, o, v, naux, nrhs, seed): >= 320 (rhs, i, j) rows each, so all join the shared launch,
 # plus one small chain that runs its own ladder
-CHAINS = [(2, 3, 5, 7, 24, 61), (3, 2, 4, 6, 48, 62), (1, 4, 12, 48, 12, 63), (2, 2, 3, 5, 2, 64)]
+CHAINS = [(2, 3, 5, 7, 40, 61), (3, 2, 4, 6, 96, 62), (1, 4, 12, 48, 24, 63), (2, 2, 3, 5, 2, 64)]
 
 
 def test_group_matches_per_chain_and_oracle():

@@ -14,7 +14,8 @@ MESH_CASES = [
     ((2, 2, 1), 2, 3, 5, 3, 1),      # Z2 x Z2: not cyclic
     ((2, 2, 2), 1, 3, 4, 2, 2),      # a 3D mesh, nk = 8
     ((3, 2, 1), 2, 4, 6, 2, 3),      # Z3 x Z2
-    ((2, 2, 1), 3, 5, 7, 24, 4),     # >= 192 (rhs, i, j) rows: 256-row ladder tiles, ragged
+    ((2, 2, 1), 3, 5, 7, 24, 4),     # >= 192 (rhs, i, j) rows: 256-row packed ladder tiles, ragged
+    ((2, 2, 1), 3, 5, 7, 40, 5),     # >= 320 rows: a ragged 384-row pipelined ladder tile
 ]
 MODES = {1: "rebuild", 2: "stored"}
 

@@ -14,8 +14,10 @@ CASES = [
     (2, 3, 5, 7, 3, 3),
     (1, 4, 12, 48, 3, 4),      # molecular-limit workload sizes (c1)
     (3, 4, 20, 72, 2, 5),      # three-k chain workload sizes (c2)
-    (2, 3, 5, 7, 24, 6),       # >= 192 (rhs, i, j) rows: 256-row ladder tiles, ragged
+    (2, 3, 5, 7, 24, 6),       # >= 192 (rhs, i, j) rows: 256-row packed ladder tiles, ragged
     (1, 4, 12, 48, 12, 7),     # c1 sizes with 12 right-hand sides (192 rows)
+    (2, 3, 5, 7, 40, 8),       # >= 320 rows: one ragged 384-row pipelined ladder tile
+    (1, 4, 12, 48, 30, 9),     # c1 sizes, 480 rows: two pipelined tiles, the second ragged
 ]
 
 
