@@ -101,7 +101,8 @@ struct GemmArgs {
     Strides Am, Ak, Bk, Bn, Cm, Cn;
     int aMfast, bNfast;  // tile-load thread maps: 1 = run along m (resp. n)
     int shape;           // tile shape: -1 automatic, 0 = 64x64, 1 = large (128x128 complex64, 128x64
-                         // complex128), 2 = 16x256 (small M), 3 = 128x64 (complex64)
+                         // complex128), 2 = 16x256 (small M), 3 = 128x64 (complex64), 4 = 128x128
+                         // (complex64); 3 and 4 form complex products from three real products
     int alt;             // unused (kept zero)
     double alpha_re, alpha_im;
     int beta;
@@ -123,7 +124,7 @@ struct GemmArgs {
 template <typename T>
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 int gemm_shape(const GemmArgs &g, bool fp64);
-// tile shapes the autotuner tries for g (the heuristic one first, at most 3)
+// tile shapes the autotuner tries for g (the heuristic one first, at most 3, 4 in complex64)
 std::vector<int> gemm_candidates(const GemmArgs &g, bool fp64);
 
 // Ladder: sigma2[ki,kj,ka][R][i][j][a][b] += alpha * sum_{ke} sum_{e,f}

@@ -34,7 +34,9 @@ template <> struct Mfma<float> {
 
 constexpr int TK = 16, NT = 256;
 
-template <typename T, int TM, int TN, int WTM, int WTN, int KIND>
+// G3: complex products from three real matrix-core products (Gauss' method:
+// k1 = br (ar + ai), k2 = ar (bi - br), k3 = ai (br + bi); re = k1 - k3, im = k1 + k2)
+template <typename T, int TM, int TN, int WTM, int WTN, int KIND, bool G3 = false>
 __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     typedef typename Cx<T>::type C2;
     typedef typename Mfma<T>::v4 v4;
@@ -84,11 +86,17 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
         bcol[q] = bok[q] ? split_off32(gn, g.sn, (int)g.Bn.s[0], (int)g.Bn.s[1], (int)g.Bn.s[2]) : 0;
     }
 
-    v4 accr[FM][FN], acci[FM][FN];
+    v4 accr[FM][FN], acci[FM][FN], acc3[G3 ? FM : 1][G3 ? FN : 1];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) { accr[i][j] = v4{0, 0, 0, 0}; acci[i][j] = v4{0, 0, 0, 0}; }
+    if constexpr (G3) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc3[i][j] = v4{0, 0, 0, 0};
+    }
 
     const int sb = g.segBeg[job], se = g.segBeg[job + 1];
     const int ksteps = (g.K + TK - 1) / TK;
@@ -134,13 +142,28 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-                    accr[i][j] = Mfma<T>::mma(-ai[i], bi[j], accr[i][j]);
-                    acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
-                    acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
+                    if constexpr (G3) {
+                        accr[i][j] = Mfma<T>::mma(ar[i] + ai[i], br[j], accr[i][j]);
+                        acci[i][j] = Mfma<T>::mma(ar[i], bi[j] - br[j], acci[i][j]);
+                        acc3[i][j] = Mfma<T>::mma(ai[i], br[j] + bi[j], acc3[i][j]);
+                    } else {
+                        accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
+                        accr[i][j] = Mfma<T>::mma(-ai[i], bi[j], accr[i][j]);
+                        acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
+                        acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
+                    }
                 }
         }
         __syncthreads();
+    }
+    if constexpr (G3) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                acci[i][j] = accr[i][j] + acci[i][j];
+                accr[i][j] = accr[i][j] - acc3[i][j];
+            }
     }
 
     if (g.ksplit > 1) {
@@ -183,7 +206,7 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
             }
 }
 
-template <typename T, int TM, int TN, int WTM, int WTN>
+template <typename T, int TM, int TN, int WTM, int WTN, bool G3 = false>
 hipError_t launch_shape(const GemmArgs &g, hipStream_t s) {
     const int tilesM = (g.M + TM - 1) / TM, tilesN = (g.N + TN - 1) / TN;
     // grid.y is limited to 65535: launch the job list in chunks
@@ -194,8 +217,8 @@ hipError_t launch_shape(const GemmArgs &g, hipStream_t s) {
         c.segBeg = g.segBeg + j0;
         c.job0 = j0;
         dim3 grid(tilesM * tilesN, c.njobs, g.ksplit);
-        if (g.kind == 1) hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 1>), grid, dim3(NT), 0, s, c);
-        else hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 0>), grid, dim3(NT), 0, s, c);
+        if (g.kind == 1) hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 1, G3>), grid, dim3(NT), 0, s, c);
+        else hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 0, G3>), grid, dim3(NT), 0, s, c);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -240,10 +263,13 @@ std::vector<int> gemm_candidates(const GemmArgs &g, bool fp64) {
     GemmArgs h = g;
     h.shape = -1;
     std::vector<int> c{gemm_shape(h, fp64)};
-    const int others[4] = {0, 1, 3, 2};
+    // complex64 large tiles also come with three real products per complex one (4)
+    const int others[5] = {0, 1, 3, 4, 2};
+    const int cap = fp64 ? 3 : 4;
     for (int s : others) {
-        if ((int)c.size() == 3) break;
-        if (s == 3 && fp64) continue;             // complex128 large tile is already 128x64
+        if ((int)c.size() == cap) break;
+        if ((s == 3 || s == 4) && fp64) continue;   // complex128 large tile is already 128x64
+        if (s == 4 && (g.M < 128 || g.N < 128)) continue;
         if (s == 2 && g.M > 32) continue;         // small-M tile only for short M
         if (s != 0 && g.M < 64 && s != 2) continue;
         if (std::find(c.begin(), c.end(), s) == c.end()) c.push_back(s);
@@ -262,7 +288,13 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
         else e = launch_shape<T, 128, 128, 64, 64>(g, s);
         break;
     case 2: e = launch_shape<T, 16, 256, 16, 64>(g, s); break;
-    case 3: e = launch_shape<T, 128, 64, 64, 32>(g, s); break;
+    case 3:   // complex64 only: 128x64 tiles with three real products per complex one
+        e = launch_shape<T, 128, 64, 64, 32, !f64>(g, s);
+        break;
+    case 4:   // complex64 only: 128x128 tiles with three real products per complex one
+        if constexpr (f64) e = launch_shape<T, 128, 64, 64, 32>(g, s);
+        else e = launch_shape<T, 128, 128, 64, 64, true>(g, s);
+        break;
     default: e = launch_shape<T, 64, 64, 32, 32>(g, s); break;
     }
     if (e != hipSuccess || g.ksplit <= 1) return e;

@@ -868,8 +868,9 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
 // file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     char b[128];
-    // "v4": candidate semantics (GEMM: heuristic tile shape first, up to three; ladder: three kernels)
-    std::snprintf(b, sizeof b, "v4,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
+    // "v5": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
+    // ladder: three kernels)
+    std::snprintf(b, sizeof b, "v5,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
                   adj ? "adjoint" : "forward", variant);
     if (!c->km.chain()) return std::string(b) + ",mesh" + std::to_string(c->km.n0) + "x" + std::to_string(c->km.n1) +
                                "x" + std::to_string(c->km.n2);
