@@ -35,11 +35,10 @@ __global__ void __launch_bounds__(kPeakThreads) k_mfma_peak(T *out, int iters, T
     v4 acc[kChains];
 #pragma unroll
     for (int j = 0; j < kChains; ++j) acc[j] = v4{0, 0, 0, 0};
-    T a = seed + (T)(threadIdx.x & 63) * (T)1e-3, b = seed - (T)(threadIdx.x >> 6) * (T)1e-3;
+    const T a = seed + (T)(threadIdx.x & 63) * (T)1e-3, b = seed - (T)(threadIdx.x >> 6) * (T)1e-3;
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int j = 0; j < kChains; ++j) acc[j] = PeakMfma<T>::mma(a, b, acc[j]);
-        a = a * (T)0.999999;
     }
     T s = 0;
 #pragma unroll
