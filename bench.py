@@ -25,8 +25,8 @@ METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1
 # runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the counter's reading for a plain 2 GiB copy
 # (fetch x2.0, write x1.0).  Valid only for the ladder sources it was measured on.
 LADDER_TRAFFIC = {"workload": "c3",
-                  "sources_sha256": "1d227f6a03ba63f9d4e9cc7517dfeaf405c40260ed272e3e93132b1c0f4da6ab",
-                  "bytes": 715.1e9}
+                  "sources_sha256": "b948b1aedbc718e02617bb3eda70f55406e0c714a6b400872e6b9692c3ed0ba3",
+                  "bytes": 700.8e9}
 
 
 def ladder_sources_sha():
