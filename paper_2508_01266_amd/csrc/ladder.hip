@@ -581,7 +581,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     const C2 *Lb = reinterpret_cast<const C2 *>(p.Lb);
     C2 *Z = reinterpret_cast<C2 *>(p.Z);
     const int gb = wave & 3, second = (wave >> 2) & 1;
-    const bool rebuilder = wave < 8;
+    const bool rebuilder = WM * WN == 8 || wave < 8;   // compile-time true with eight waves
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     // steps (ke <= kf, e0, f0 >= e0 when ke == kf); the step after `s`, or ke = nk when done
