@@ -25,8 +25,8 @@ METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1
 # runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the counter's reading for a plain 2 GiB copy
 # (fetch x2.0, write x1.0).  Valid only for the ladder sources it was measured on.
 LADDER_TRAFFIC = {"workload": "c3",
-                  "sources_sha256": "b948b1aedbc718e02617bb3eda70f55406e0c714a6b400872e6b9692c3ed0ba3",
-                  "bytes": 700.8e9}
+                  "sources_sha256": "70768cb8f9a608446e77a307d05bd301b0bdea5c2e8cf2ad6fdba3c89bfb9542",
+                  "bytes": 687.8e9}
 
 
 def ladder_sources_sha():
