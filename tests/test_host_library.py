@@ -71,3 +71,13 @@ def test_measure_peaks_without_device_reports_error():
     from paper_2508_01266_amd import LrccError, measure_peaks
     with pytest.raises(LrccError):
         measure_peaks(0)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
