@@ -7,6 +7,8 @@
 #include "common.hpp"
 #include "elem.hpp"
 
+#include <algorithm>
+
 namespace lrcc {
 
 namespace {
@@ -19,25 +21,37 @@ inline unsigned grid_for(i64 n, int bs = 256) {
 template <typename T> __device__ inline typename Cx<T>::type mk(T x, T y) {
     typename Cx<T>::type r; r.x = x; r.y = y; return r;
 }
+// Row-wise launches: a workgroup takes whole rows of `len` consecutive elements, so the
+// row index (the same for every lane) is split with 64-bit arithmetic once per row and
+// the position inside the row with 32-bit arithmetic; splitting a flat 64-bit element
+// index with 64-bit divisions costs more than the memory traffic of these kernels.
+inline unsigned rows_grid(i64 rows) {
+    return (unsigned)std::max<i64>(1, std::min<i64>(rows, 65536 * 4));
+}
 }
 
 // out[b][r][e] = scale * in[r][b][e]
 template <typename Tin, typename Tout>
 __global__ void k_rhs_to_block(const typename Cx<Tin>::type *in, typename Cx<Tout>::type *out,
                                int R, i64 B, i64 E, double scale) {
-    const i64 n = (i64)R * B * E;
-    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-        const i64 e = t % E, q = t / E;
-        const int r = (int)(q % R);
-        const i64 b = q / R;
-        auto v = in[((i64)r * B + b) * E + e];
-        out[t] = mk<Tout>((Tout)(scale * v.x), (Tout)(scale * v.y));
+    // rows (b, r) of the output, E elements each (E < 2^31, checked by the launcher)
+    const i64 rows = (i64)R * B;
+    for (i64 row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int r = (int)(row % R);
+        const i64 b = row / R;
+        const typename Cx<Tin>::type *src = in + ((i64)r * B + b) * E;
+        typename Cx<Tout>::type *dst = out + row * E;
+        for (int e = threadIdx.x; e < (int)E; e += blockDim.x) {
+            auto v = src[e];
+            dst[e] = mk<Tout>((Tout)(scale * v.x), (Tout)(scale * v.y));
+        }
     }
 }
 
 template <typename Tin, typename Tout>
 hipError_t rhs_to_block(const void *in, void *out, int R, i64 B, i64 E, double scale, hipStream_t s) {
-    hipLaunchKernelGGL((k_rhs_to_block<Tin, Tout>), dim3(grid_for((i64)R * B * E)), dim3(256), 0, s,
+    if (E >= ((i64)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_rhs_to_block<Tin, Tout>), dim3(rows_grid((i64)R * B)), dim3(256), 0, s,
                        (const typename Cx<Tin>::type *)in, (typename Cx<Tout>::type *)out, R, B, E, scale);
     return hipGetLastError();
 }
@@ -48,13 +62,11 @@ template <typename T>
 __global__ void k_tau_like(const typename Cx<T>::type *x1, const typename Cx<T>::type *x2,
                            const typename Cx<T>::type *t1, typename Cx<T>::type *out,
                            KMesh km, int R, int o, int v, T c, int x1_has_rhs) {
-    const int nk = km.size();
-    const i64 inner = (i64)o * o * v * v;
-    const i64 n = (i64)nk * nk * nk * R * inner;
-    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-        i64 q = t;
-        const int b = (int)(q % v); q /= v;
-        const int a = (int)(q % v); q /= v;
+    const int nk = km.size(), vv = v * v;
+    const i64 rows = (i64)nk * nk * nk * R * o * o;
+    for (i64 row = blockIdx.x; row < rows; row += gridDim.x) {
+        // row = (((ki nk + kj) nk + ka) R + r) o + i) o + j, elements (a, b)
+        i64 q = row;
         const int j = (int)(q % o); q /= o;
         const int i = (int)(q % o); q /= o;
         const int r = (int)(q % R); q /= R;
@@ -62,23 +74,28 @@ __global__ void k_tau_like(const typename Cx<T>::type *x1, const typename Cx<T>:
         const int kj = (int)(q % nk); q /= nk;
         const int ki = (int)q;
         const int kb = km.comb(ki, kj, ka);
-        auto acc = x2[t];
-        T sr = 0, si = 0;
         const int rx = x1_has_rhs ? r : 0;
         const int Rx = x1_has_rhs ? R : 1;
         auto X = [&](int k, int ii, int aa) { return x1[(((i64)k * Rx + rx) * o + ii) * v + aa]; };
         auto Tt = [&](int k, int ii, int aa) { return t1[((i64)k * o + ii) * v + aa]; };
-        if (ka == ki) {     // x_ia t_jb + t_ia x_jb  (kb == kj)
-            auto p = X(ki, i, a), q2 = Tt(kj, j, b), u = Tt(ki, i, a), w = X(kj, j, b);
-            sr += p.x * q2.x - p.y * q2.y + u.x * w.x - u.y * w.y;
-            si += p.x * q2.y + p.y * q2.x + u.x * w.y + u.y * w.x;
+        const typename Cx<T>::type *src = x2 + row * vv;
+        typename Cx<T>::type *dst = out + row * vv;
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / v, b = e - a * v;
+            auto acc = src[e];
+            T sr = 0, si = 0;
+            if (ka == ki) {     // x_ia t_jb + t_ia x_jb  (kb == kj)
+                auto p = X(ki, i, a), q2 = Tt(kj, j, b), u = Tt(ki, i, a), w = X(kj, j, b);
+                sr += p.x * q2.x - p.y * q2.y + u.x * w.x - u.y * w.y;
+                si += p.x * q2.y + p.y * q2.x + u.x * w.y + u.y * w.x;
+            }
+            if (kb == ki) {     // - x_ib t_ja - t_ib x_ja  (ka == kj)
+                auto p = X(ki, i, b), q2 = Tt(kj, j, a), u = Tt(ki, i, b), w = X(kj, j, a);
+                sr -= p.x * q2.x - p.y * q2.y + u.x * w.x - u.y * w.y;
+                si -= p.x * q2.y + p.y * q2.x + u.x * w.y + u.y * w.x;
+            }
+            dst[e] = mk<T>(acc.x + c * sr, acc.y + c * si);
         }
-        if (kb == ki) {     // - x_ib t_ja - t_ib x_ja  (ka == kj)
-            auto p = X(ki, i, b), q2 = Tt(kj, j, a), u = Tt(ki, i, b), w = X(kj, j, a);
-            sr -= p.x * q2.x - p.y * q2.y + u.x * w.x - u.y * w.y;
-            si -= p.x * q2.y + p.y * q2.x + u.x * w.y + u.y * w.x;
-        }
-        out[t] = mk<T>(acc.x + c * sr, acc.y + c * si);
     }
 }
 
@@ -86,8 +103,8 @@ template <typename T>
 hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, KMesh km, int R, int o, int v,
                     double c, int x1_has_rhs, hipStream_t s) {
     const int nk = km.size();
-    const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
-    hipLaunchKernelGGL(k_tau_like<T>, dim3(grid_for(n)), dim3(256), 0, s,
+    const i64 rows = (i64)nk * nk * nk * R * o * o;
+    hipLaunchKernelGGL(k_tau_like<T>, dim3(rows_grid(rows)), dim3(256), 0, s,
                        (const typename Cx<T>::type *)x1, (const typename Cx<T>::type *)x2,
                        (const typename Cx<T>::type *)t1, (typename Cx<T>::type *)out, km, R, o, v, (T)c,
                        x1_has_rhs);
@@ -98,40 +115,41 @@ hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, K
 template <typename T>
 __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, double2 *y2, const double *omega,
                          KMesh km, int R, int o, int v, double scale) {
-    const int nk = km.size();
-    const i64 inner = (i64)o * o * v * v;
+    const int nk = km.size(), vv = v * v;
     const i64 B = (i64)nk * nk * nk;
-    const i64 n = B * R * inner;
-    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-        // t indexes the caller layout [r][blk][i][j][a][b]
-        i64 q = t;
-        const int b = (int)(q % v); q /= v;
-        const int a = (int)(q % v); q /= v;
+    const i64 rows = B * R * o * o;
+    for (i64 row = blockIdx.x; row < rows; row += gridDim.x) {
+        // row indexes the caller layout [r][blk][i][j], elements (a, b)
+        i64 q = row;
         const int j = (int)(q % o); q /= o;
         const int i = (int)(q % o); q /= o;
         const i64 blk = q % B;
         const int r = (int)(q / B);
         const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
         const int kb = km.comb(ki, kj, ka);
-        auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
-            return Z[((((i64)(k0 * nk + k1) * nk + k2) * R + r) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
+        auto rowp = [&](int k0, int k1, int k2, int p, int q3) {
+            return Z + ((((i64)(k0 * nk + k1) * nk + k2) * R + r) * o + p) * o * vv + (i64)q3 * vv;
         };
-        auto z1 = at(ki, kj, ka, i, j, a, b);
-        auto z2 = at(kj, ki, ka, j, i, a, b);
-        auto z3 = at(ki, kj, kb, i, j, b, a);
-        auto z4 = at(kj, ki, kb, j, i, b, a);
-        const double zr = (double)z1.x - (double)z2.x - (double)z3.x + (double)z4.x;
-        const double zi = (double)z1.y - (double)z2.y - (double)z3.y + (double)z4.y;
-        double2 out;
-        out.x = scale * zr;
-        out.y = scale * zi;
-        if (omega) {
-            const double w = omega[r];
-            const double2 xv = x2[t];
-            out.x -= w * xv.x;
-            out.y -= w * xv.y;
+        const typename Cx<T>::type *Z1 = rowp(ki, kj, ka, i, j), *Z2 = rowp(kj, ki, ka, j, i);
+        const typename Cx<T>::type *Z3 = rowp(ki, kj, kb, i, j), *Z4 = rowp(kj, ki, kb, j, i);
+        const double w = omega ? omega[r] : 0.0;
+        const double2 *xs = x2 + row * vv;
+        double2 *ys = y2 + row * vv;
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / v, b = e - a * v, et = b * v + a;
+            const auto z1 = Z1[e], z2 = Z2[e], z3 = Z3[et], z4 = Z4[et];
+            const double zr = (double)z1.x - (double)z2.x - (double)z3.x + (double)z4.x;
+            const double zi = (double)z1.y - (double)z2.y - (double)z3.y + (double)z4.y;
+            double2 out;
+            out.x = scale * zr;
+            out.y = scale * zi;
+            if (omega) {
+                const double2 xv = xs[e];
+                out.x -= w * xv.x;
+                out.y -= w * xv.y;
+            }
+            ys[e] = out;
         }
-        y2[t] = out;
     }
 }
 
@@ -139,8 +157,8 @@ template <typename T>
 hipError_t pp_out(const void *Z, const void *x2, void *y2, const double *omega, KMesh km, int R, int o, int v,
                   double scale, hipStream_t s) {
     const int nk = km.size();
-    const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
-    hipLaunchKernelGGL(k_pp_out<T>, dim3(grid_for(n)), dim3(256), 0, s, (const typename Cx<T>::type *)Z,
+    const i64 rows = (i64)nk * nk * nk * R * o * o;
+    hipLaunchKernelGGL(k_pp_out<T>, dim3(rows_grid(rows)), dim3(256), 0, s, (const typename Cx<T>::type *)Z,
                        (const double2 *)x2, (double2 *)y2, omega, km, R, o, v, scale);
     return hipGetLastError();
 }
@@ -340,13 +358,12 @@ hipError_t conj_scale(void *y, const void *x, double s, i64 n, hipStream_t st) {
 // out = scale * c(y - y(ij swapped) - y(ab swapped) + y(both swapped)) on caller-layout doubles
 // [R][ki][kj][ka][i][j][a][b] (kb implied), c = complex conjugation when conj != 0.  Out of place.
 __global__ void k_antisym(const double2 *y, double2 *out, int R, KMesh km, int o, int v, double scale, int conj) {
-    const int nk = km.size();
-    const i64 B = (i64)nk * nk * nk, inner = (i64)o * o * v * v;
-    const i64 n = (i64)R * B * inner;
-    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-        i64 q = t;
-        const int b = (int)(q % v); q /= v;
-        const int a = (int)(q % v); q /= v;
+    const int nk = km.size(), vv = v * v;
+    const i64 B = (i64)nk * nk * nk;
+    const i64 rows = (i64)R * B * o * o;
+    for (i64 row = blockIdx.x; row < rows; row += gridDim.x) {
+        // row = [r][ki][kj][ka][i][j], elements (a, b)
+        i64 q = row;
         const int j = (int)(q % o); q /= o;
         const int i = (int)(q % o); q /= o;
         const int ka = (int)(q % nk); q /= nk;
@@ -354,20 +371,25 @@ __global__ void k_antisym(const double2 *y, double2 *out, int R, KMesh km, int o
         const int ki = (int)(q % nk);
         const i64 r = q / nk;
         const int kb = km.comb(ki, kj, ka);
-        auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
-            return y[((r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
+        auto rowp = [&](int k0, int k1, int k2, int p, int q3) {
+            return y + ((r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * vv + (i64)q3 * vv;
         };
-        const double2 z1 = at(ki, kj, ka, i, j, a, b), z2 = at(kj, ki, ka, j, i, a, b);
-        const double2 z3 = at(ki, kj, kb, i, j, b, a), z4 = at(kj, ki, kb, j, i, b, a);
-        const double re = scale * (z1.x - z2.x - z3.x + z4.x), im = scale * (z1.y - z2.y - z3.y + z4.y);
-        out[t] = make_double2(re, conj ? -im : im);
+        const double2 *Y1 = rowp(ki, kj, ka, i, j), *Y2 = rowp(kj, ki, ka, j, i);
+        const double2 *Y3 = rowp(ki, kj, kb, i, j), *Y4 = rowp(kj, ki, kb, j, i);
+        double2 *dst = out + row * vv;
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / v, b = e - a * v, et = b * v + a;
+            const double2 z1 = Y1[e], z2 = Y2[e], z3 = Y3[et], z4 = Y4[et];
+            const double re = scale * (z1.x - z2.x - z3.x + z4.x), im = scale * (z1.y - z2.y - z3.y + z4.y);
+            dst[e] = make_double2(re, conj ? -im : im);
+        }
     }
 }
 
 hipError_t antisym(const void *y, void *out, int R, KMesh km, int o, int v, double scale, int conj, hipStream_t s) {
     const int nk = km.size();
-    const i64 n = (i64)R * nk * nk * nk * o * o * v * v;
-    hipLaunchKernelGGL(k_antisym, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y, (double2 *)out, R, km, o,
+    const i64 rows = (i64)R * nk * nk * nk * o * o;
+    hipLaunchKernelGGL(k_antisym, dim3(rows_grid(rows)), dim3(256), 0, s, (const double2 *)y, (double2 *)out, R, km, o,
                        v, scale, conj);
     return hipGetLastError();
 }
@@ -387,35 +409,37 @@ hipError_t convert_f64_f32(const void *in, void *out, i64 n, hipStream_t s) {
 // Z[ki,kj,ka][r][i][j][a][b] = scale * (P_ij P_ab y)[r][ki,kj,ka][i][j][a][b]  (caller layout in, block layout out)
 template <typename T>
 __global__ void k_pp_in(const double2 *y, typename Cx<T>::type *Z, KMesh km, int R, int o, int v, double scale) {
-    const int nk = km.size();
-    const i64 inner = (i64)o * o * v * v;
+    const int nk = km.size(), vv = v * v;
     const i64 B = (i64)nk * nk * nk;
-    const i64 n = B * R * inner;
-    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < n; t += (i64)gridDim.x * blockDim.x) {
-        // t indexes the block layout [blk][r][i][j][a][b]
-        i64 q = t;
-        const int b = (int)(q % v); q /= v;
-        const int a = (int)(q % v); q /= v;
+    const i64 rows = B * R * o * o;
+    for (i64 row = blockIdx.x; row < rows; row += gridDim.x) {
+        // row indexes the block layout [blk][r][i][j], elements (a, b)
+        i64 q = row;
         const int j = (int)(q % o); q /= o;
         const int i = (int)(q % o); q /= o;
         const int r = (int)(q % R);
         const i64 blk = q / R;
         const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
         const int kb = km.comb(ki, kj, ka);
-        auto at = [&](int k0, int k1, int k2, int p, int q3, int c, int d) {
-            return y[(((i64)r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * v * v + ((i64)q3 * v + c) * v + d];
+        auto rowp = [&](int k0, int k1, int k2, int p, int q3) {
+            return y + (((i64)r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * vv + (i64)q3 * vv;
         };
-        double2 z1 = at(ki, kj, ka, i, j, a, b), z2 = at(kj, ki, ka, j, i, a, b);
-        double2 z3 = at(ki, kj, kb, i, j, b, a), z4 = at(kj, ki, kb, j, i, b, a);
-        Z[t] = mk<T>((T)(scale * (z1.x - z2.x - z3.x + z4.x)), (T)(scale * (z1.y - z2.y - z3.y + z4.y)));
+        const double2 *Y1 = rowp(ki, kj, ka, i, j), *Y2 = rowp(kj, ki, ka, j, i);
+        const double2 *Y3 = rowp(ki, kj, kb, i, j), *Y4 = rowp(kj, ki, kb, j, i);
+        typename Cx<T>::type *dst = Z + row * vv;
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / v, b = e - a * v, et = b * v + a;
+            const double2 z1 = Y1[e], z2 = Y2[e], z3 = Y3[et], z4 = Y4[et];
+            dst[e] = mk<T>((T)(scale * (z1.x - z2.x - z3.x + z4.x)), (T)(scale * (z1.y - z2.y - z3.y + z4.y)));
+        }
     }
 }
 
 template <typename T>
 hipError_t pp_in(const void *y, void *Z, KMesh km, int R, int o, int v, double scale, hipStream_t s) {
     const int nk = km.size();
-    const i64 n = (i64)nk * nk * nk * R * o * o * v * v;
-    hipLaunchKernelGGL(k_pp_in<T>, dim3(grid_for(n)), dim3(256), 0, s, (const double2 *)y,
+    const i64 rows = (i64)nk * nk * nk * R * o * o;
+    hipLaunchKernelGGL(k_pp_in<T>, dim3(rows_grid(rows)), dim3(256), 0, s, (const double2 *)y,
                        (typename Cx<T>::type *)Z, km, R, o, v, scale);
     return hipGetLastError();
 }

@@ -187,23 +187,55 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
     const T js = g.jscale ? (T)g.jscale[g.job0 + job] : (T)1;
     const T alr = js * (T)g.alpha_re, ali = js * (T)g.alpha_im;
     C2 *Cj = C + g.offC[job];
+    i64 coff[FN];
+    bool cok[FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int j = 0; j < FN; ++j) {
+        const int gn = n0 + wn + 16 * j + (lane & 15);
+        cok[j] = gn < g.N;
+        coff[j] = cok[j] ? split_off(gn, g.sn, g.Cn) : 0;
+    }
+    // Output rows in groups of EG fragment rows.  With beta all reads of C in a group are
+    // issued, unconditionally, before its first write: a write may alias a later read as far
+    // as the compiler knows, so read-add-write element by element would wait out one memory
+    // round trip per element, which bounds the short-K products.
+    constexpr int EG = 1;
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+    for (int i0 = 0; i0 < FM; i0 += EG) {
+        i64 roff[EG][4];
+        bool rok[EG][4];
+#pragma unroll
+        for (int ii = 0; ii < EG; ++ii)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + 16 * i + Mfma<T>::row(lane, r);
-                const int gn = n0 + wn + 16 * j + (lane & 15);
-                if (gm < g.M && gn < g.N) {
-                    const i64 off = split_off(gm, g.sm, g.Cm) + split_off(gn, g.sn, g.Cn);
-                    const T xr = accr[i][j][r], xi = acci[i][j][r];
-                    T vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
-                    if (g.beta) { C2 o = Cj[off]; vr += o.x; vi += o.y; }
-                    C2 w; w.x = vr; w.y = vi;
-                    Cj[off] = w;
-                }
+                const int gm = m0 + wm + 16 * (i0 + ii) + Mfma<T>::row(lane, r);
+                rok[ii][r] = gm < g.M;
+                roff[ii][r] = rok[ii][r] ? split_off(gm, g.sm, g.Cm) : 0;
             }
+        C2 old[EG][FN][4];
+        if (g.beta) {
+#pragma unroll
+            for (int ii = 0; ii < EG; ++ii)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)   // (0, 0) of the block stands in for outside elements
+                        old[ii][j][r] = Cj[rok[ii][r] && cok[j] ? roff[ii][r] + coff[j] : 0];
+        }
+#pragma unroll
+        for (int ii = 0; ii < EG; ++ii)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (!(rok[ii][r] && cok[j])) continue;
+                    const T xr = accr[i0 + ii][j][r], xi = acci[i0 + ii][j][r];
+                    T vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
+                    if (g.beta) { vr += old[ii][j][r].x; vi += old[ii][j][r].y; }
+                    C2 w; w.x = vr; w.y = vi;
+                    Cj[roff[ii][r] + coff[j]] = w;
+                }
+    }
 }
 
 template <typename T, int TM, int TN, int WTM, int WTN, bool G3 = false>

@@ -108,6 +108,7 @@ hipError_t Program::run(hipStream_t s, Profiler *prof) {
             hipError_t e = ops[i](s);
             if (e != hipSuccess) return e;
             (void)hipEventRecord(y, s);
+            if (tags[i] != TAG_NONE) prof->record(tags[i], x, y);   // the profile owns these two
             continue;
         }
         if (timed && tags[i] != TAG_NONE) {
@@ -135,6 +136,7 @@ hipError_t Program::run(hipStream_t s, Profiler *prof) {
             float ms = 0;
             (void)hipEventElapsedTime(&ms, opev[i].first, opev[i].second);
             std::fprintf(stderr, "[lrcc-op] %4zu %10.3f ms  %s\n", i, ms, names[i].c_str());
+            if (tags[i] != TAG_NONE) continue;
             prof->pool.push_back(opev[i].first);
             prof->pool.push_back(opev[i].second);
         }
