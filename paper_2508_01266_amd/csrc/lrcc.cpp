@@ -669,18 +669,25 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
         op.C = Z; op.A = dtau; op.alpha = 0.25; op.actA = true;
         G.ops.push_back(op);
     }
+    // hole-hole terms: Z += Zmn t2 / 16 + Vx tau / 8, Vx_ijmn = x_je <mn||ie> - (i <-> j).
+    // With tau_mnab = t2_mnab + t_ma t_nb - t_mb t_na, Vx tau / 8 is Vx t2 / 8 plus a part
+    // antisymmetric in (a, b), which P(ab) turns into Vx_ijmn t_ma t_nb / 4: the t2 parts share
+    // one product with (Zmn + 2 Vx), and the t1 t1 part joins the Yx t1 product below
+    // (Yx -= Vx t1 / 4), so no product over all (i, j, a, b) is spent on it.
     con(Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false);
+    con(Zmn, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 2.0);
+    con(Zmn, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -2.0);
     con(Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16);
     con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8);
     con(Vx, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 1.0, false);
     con(Vx, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -1.0);
-    con(Z, "Rijab", Vx, "Rijmn", S.tau, "mnab", 1.0 / 8);
     con(Z, "Rijab", S.Q, "ijam", x1, "Rmb", -0.25);
     // ring terms (P(ij)P(ab))
     con(Z, "Rijab", x2, "Rimae", S.Wbar, "mebj", 1.0);
     con(Z, "Rijab", S.R, "iabf", x1, "Rjf", 1.0);
     con(Z, "Rijab", S.S, "ijan", x1, "Rnb", -1.0);
     con(Yx, "Rijan", x1, "Rjf", S.U, "ianf", 1.0, false);
+    con(Yx, "Rijan", Vx, "Rijmn", t1, "ma", -0.25);
     con(Z, "Rijab", Yx, "Rijan", t1, "nb", -1.0);
     con(Z, "Rijab", S.Yp, "ijan", x1, "Rnb", -1.0);
     con(Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);
