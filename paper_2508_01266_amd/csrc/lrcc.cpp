@@ -63,7 +63,7 @@ struct State {
     DevMem mem;
     KT fov, t1, t2, tau;
     KT g_oovv, g_ooov, g_ovov, g_ovvv, g_ovoo;
-    KT Fae, Fmi, Fme, Fbe, Fmj, Wp, Wbar, Q, R, S, U, Yp, H, G2;
+    KT Fae, Fmi, Fme, Fbe, Fmj, Fg, Wp, Wbar, R, S, U, H, G2;
     void *La = nullptr, *Lb = nullptr;      // dressed virtual Cholesky slices (ladder)
     void *LaT = nullptr, *LbT = nullptr;    // pair-transposed copies (adjoint ladder)
     void *d_o1 = nullptr, *d_v1 = nullptr, *d_o2 = nullptr, *d_v2 = nullptr;  // preconditioner diagonals
@@ -412,6 +412,9 @@ void build_state(lrcc_ctx *c) {
     S.Fme = alloc_kt<double>(c, m, "ov");
     kt_copy<double>(P, S.Fme, S.fov);
     contract<double>(P, S.Fme, "me", t1, "nf", oovv, "mnef", 1.0);
+    // Fg_me = sum_nf t_nf <mn||ef> (the t1 t1 part of the X-derivative of Fae and Fmi)
+    S.Fg = alloc_kt<double>(c, m, "ov");
+    contract<double>(P, S.Fg, "me", t1, "nf", oovv, "mnef", 1.0, false);
     S.Fbe = alloc_kt<double>(c, m, "vv");
     kt_copy<double>(P, S.Fbe, S.Fae);
     contract<double>(P, S.Fbe, "be", t1, "mb", S.Fme, "me", -0.5);
@@ -442,28 +445,50 @@ void build_state(lrcc_ctx *c) {
         P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, km, ext, perm, sg, s); });
         S.Wbar = wr;
     }
-    // Q_ijam = sum_ef tau_ijef <am||ef>
-    S.Q = alloc_kt<double>(c, m, "oovo");
-    contract<double>(P, S.Q, "ijam", tau, "ijef", ovvv, "maef", -1.0, false);
     // R_iabf = sum_me t_imae <mb||ef>   (k_i + k_f = k_a + k_b)
     S.R = alloc_kt<double>(c, m, "ovvv", 0, {1, -1, -1, 1});
     contract<double>(P, S.R, "iabf", t2, "imae", ovvv, "mbef", 1.0, false);
-    // S_ijan = sum_me t_imae <mn||ej>
-    S.S = alloc_kt<double>(c, m, "oovo");
-    contract<double>(P, S.S, "ijan", t2, "imae", ooov, "mnje", -1.0, false);
     // U_ianf = sum_me t_imae <mn||ef>   (k_i + k_f = k_a + k_n)
     S.U = alloc_kt<double>(c, m, "ovov", 0, {1, -1, -1, 1});
     contract<double>(P, S.U, "ianf", t2, "imae", oovv, "mnef", 1.0, false);
-    // Yp_ijan = sum_f t_jf U_ianf
-    S.Yp = alloc_kt<double>(c, m, "oovo");
-    contract<double>(P, S.Yp, "ijan", t1, "jf", S.U, "ianf", 1.0, false);
-    // H_abej = 1/2 <ab||ej> - sum_m t_ma <mb||ej>
+    // The doubles terms linear in x1 that share a contraction pattern are summed here, once per
+    // Hamiltonian, so that each pattern costs one product over all (i, j, a, b) per sigma (the
+    // final P(ij)P(ab) antisymmetrisation makes a term and its (i <-> j) image with opposite
+    // sign equivalent):
+    //   S_ijan = sum_me t_imae <mn||ej> + sum_f t_jf U_ianf + 1/4 sum_ef tau_ijef <an||ef>,
+    //     entering as - S_ijan x_nb (the former S, Yp and Q / 4 terms);
+    S.S = alloc_kt<double>(c, m, "oovo");
+    contract<double>(P, S.S, "ijan", t2, "imae", ooov, "mnje", -1.0, false);
+    contract<double>(P, S.S, "ijan", t1, "jf", S.U, "ianf", 1.0);
+    contract<double>(P, S.S, "ijan", tau, "ijef", ovvv, "naef", -0.25);
+    //   H_abej = 1/2 <ab||ej> - sum_m t_ma <mb||ej> - R_jabe, entering as x_ie H_abej (the R
+    //     term R_iabf x_jf is minus its own (i <-> j) image, R_jabf x_if);
     S.H = alloc_kt<double>(c, m, "vvvo");
     build_eri(c, P, S.H, 0.5);
     contract<double>(P, S.H, "abej", t1, "ma", ovvo, "mbej", -1.0);
-    // G2_ijbm = sum_e t_ie <mb||ej>
+    {
+        KT rp = alloc_kt<double>(c, m, "vvvo");
+        const int ext[4] = {o, v, v, v}, perm[4] = {1, 2, 3, 0}, sg[4] = {1, 1, -1, -1};
+        const void *src = S.R.p;
+        void *dst = rp.p, *h = S.H.p;
+        const i64 n = rp.count();
+        const KMesh km = c->km;
+        P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, km, ext, perm, sg, s); });
+        P.ops.push_back([=](hipStream_t s) { return scale_copy(dst, dst, -1.0, 0.0, n, s); });
+        P.ops.push_back([=](hipStream_t s) { return add_inplace<double>(h, dst, n, s); });
+    }
+    //   G2_ijbm = sum_e t_ie <mb||ej> + 1/2 <mb||ij>, entering as - G2_ijbm x_ma.
     S.G2 = alloc_kt<double>(c, m, "oovo");
-    contract<double>(P, S.G2, "ijbm", t1, "ie", ovvo, "mbej", 1.0, false);
+    {
+        const int ext[4] = {o, v, o, o}, perm[4] = {2, 3, 1, 0}, sg[4] = {1, 1, -1, -1};
+        const void *src = c->g_ovoo.p;
+        void *dst = S.G2.p;
+        const i64 n = S.G2.count();
+        const KMesh km = c->km;
+        P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, km, ext, perm, sg, s); });
+        P.ops.push_back([=](hipStream_t s) { return scale_copy(dst, dst, 0.5, 0.0, n, s); });
+    }
+    contract<double>(P, S.G2, "ijbm", t1, "ie", ovvo, "mbej", 1.0);
     // t1-dressed virtual Cholesky slices for the ladder
     const i64 lvv = (i64)nk * nk * naux * v * v;
     S.La = m.get(lvv * 16);
@@ -512,8 +537,8 @@ void build_state(lrcc_ctx *c) {
     cv(F.g_oovv, S.g_oovv); cv(F.g_ooov, S.g_ooov); cv(F.g_ovov, S.g_ovov); cv(F.g_ovvv, S.g_ovvv);
     cv(F.g_ovoo, S.g_ovoo);
     cv(F.Fae, S.Fae); cv(F.Fmi, S.Fmi); cv(F.Fme, S.Fme); cv(F.Fbe, S.Fbe); cv(F.Fmj, S.Fmj);
-    cv(F.Wp, S.Wp); cv(F.Wbar, S.Wbar); cv(F.Q, S.Q); cv(F.R, S.R); cv(F.S, S.S); cv(F.U, S.U);
-    cv(F.Yp, S.Yp); cv(F.H, S.H); cv(F.G2, S.G2);
+    cv(F.Fg, S.Fg); cv(F.Wp, S.Wp); cv(F.Wbar, S.Wbar); cv(F.R, S.R); cv(F.S, S.S); cv(F.U, S.U);
+    cv(F.H, S.H); cv(F.G2, S.G2);
     F.La = F.mem.get(lvv * 8);
     F.Lb = F.mem.get(lvv * 8);
     F.LaT = F.mem.get(lvv * 8);
@@ -623,19 +648,24 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
         G.ops.push_back(op);
     }
     const KT &t1 = S.t1, &t2 = S.t2;
-    // X-dependent one-body intermediates (derivatives of F_ae, F_mi, F_me)
+    // X-dependent one-body intermediates (derivatives of F_ae, F_mi, F_me).  The doubles parts
+    // -(x2 + dtau) <mn||ef> / 4 of dFae (and +1/4 of dFmi) are written as one product with dtau,
+    // -dtau <mn||ef> / 2, plus the x1 t1 part of dtau contracted in closed form:
+    // sum_mnf (dtau - x2)_mnaf <mn||ef> = 2 sum_m (x_ma Fg_me + t_ma dFme_me).
+    if (full) con(dFme, "Rme", x1, "Rnf", S.g_oovv, "mnef", 1.0, false);
     con(dFae, "Rae", x1, "Rma", S.fov, "me", -0.5, false);
     if (full) {
         con(dFae, "Rae", x1, "Rmf", S.g_ovvv, "mafe", 1.0);
-        con(dFae, "Rae", x2, "Rmnaf", S.g_oovv, "mnef", -0.25);
-        con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.25);
+        con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.5);
+        con(dFae, "Rae", x1, "Rma", S.Fg, "me", 0.5);
+        con(dFae, "Rae", t1, "ma", dFme, "Rme", 0.5);
     }
     con(dFmi, "Rmi", x1, "Rie", S.fov, "me", 0.5, false);
     if (full) {
         con(dFmi, "Rmi", x1, "Rne", S.g_ooov, "mnie", 1.0);
-        con(dFmi, "Rmi", x2, "Rinef", S.g_oovv, "mnef", 0.25);
-        con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.25);
-        con(dFme, "Rme", x1, "Rnf", S.g_oovv, "mnef", 1.0, false);
+        con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.5);
+        con(dFmi, "Rmi", x1, "Rie", S.Fg, "me", -0.5);
+        con(dFmi, "Rmi", t1, "ie", dFme, "Rme", -0.5);
     }
     // singles (operator part of Eq. tx1)
     con(s1, "Ria", x1, "Rie", S.Fae, "ae", 1.0, false);
@@ -681,18 +711,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8);
     con(Vx, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 1.0, false);
     con(Vx, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -1.0);
-    con(Z, "Rijab", S.Q, "ijam", x1, "Rmb", -0.25);
     // ring terms (P(ij)P(ab))
     con(Z, "Rijab", x2, "Rimae", S.Wbar, "mebj", 1.0);
-    con(Z, "Rijab", S.R, "iabf", x1, "Rjf", 1.0);
     con(Z, "Rijab", S.S, "ijan", x1, "Rnb", -1.0);
     con(Yx, "Rijan", x1, "Rjf", S.U, "ianf", 1.0, false);
     con(Yx, "Rijan", Vx, "Rijmn", t1, "ma", -0.25);
     con(Z, "Rijab", Yx, "Rijan", t1, "nb", -1.0);
-    con(Z, "Rijab", S.Yp, "ijan", x1, "Rnb", -1.0);
     con(Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);
     con(Z, "Rijab", S.G2, "ijbm", x1, "Rma", -1.0);
-    con(Z, "Rijab", S.g_ovoo, "mbij", x1, "Rma", -0.5);
     return G;
 }
 
