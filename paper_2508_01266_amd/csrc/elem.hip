@@ -2,7 +2,8 @@
 // the caller's rhs-major layout and the internal k-block-major layout, the
 // amplitude products entering tau (Eq. t2 and the perturbed analogue), the
 // final P_IJ P_AB antisymmetrisation with the -omega shift, Cholesky slices,
-// and precision conversion.  Grid-stride loops; consecutive threads touch
+// and precision conversion.  Grid-stride loops (over elements, or over rows of
+// the doubles arrays for the per-sigma kernels); consecutive threads touch
 // consecutive elements of the innermost (unit-stride) index.
 #include "common.hpp"
 #include "elem.hpp"
