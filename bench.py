@@ -412,7 +412,7 @@ def main():
         log("solving ground-state CCSD on the device")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, ecorr, crep = ctx.solve_ccsd(tol=1e-9, max_iter=args.ccsd_iter)
+        t1c, t2c, ecorr, crep = ctx.solve_ccsd(tol=1e-9, max_iter=args.ccsd_iter)
         out["ccsd"] = {"seconds": time.perf_counter() - t0, "energy_per_cell": ecorr, "report": crep}
         log(f"CCSD: {out['ccsd']}")
         res = {}
@@ -437,7 +437,44 @@ def main():
                                        for k in res},
             "reports": {k: res[k][2] for k in res},
         }
-    if args.mesh or args.velocity or args.uneven:
+        # the same solves with the ladder integral blocks stored (ladder mode 2, forward and
+        # transpose products): the one-vector transpose products of the lambda equations and of the
+        # F term are bound by the in-LDS rebuild at 64 rows, which the stored blocks remove
+        ctx.close()
+        ctx = None
+        torch.cuda.empty_cache()
+        cs = lr.Context(0)
+        cs.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+        cs.set_ladder_mode(2)
+        cs.set_amplitudes(t1c, t2c)
+        cs.set_autotune(not args.no_tune)
+        # build and tune the 48-RHS programs outside the timed solves, as for the default context
+        Z1 = torch.zeros((nrhs, nk, o, v), dtype=torch.complex128, device=dev)
+        Z2 = torch.zeros((nrhs, nk, nk, nk, o, o, v, v), dtype=torch.complex128, device=dev)
+        OMz = torch.zeros(nrhs, dtype=torch.float64, device=dev)
+        for prec in (lr.FP32, lr.FP64):
+            cs.apply_sigma_dev(Z1, Z2, Z1.clone(), torch.empty_like(Z2), OMz, prec,
+                               torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        del Z1, Z2, OMz
+        torch.cuda.empty_cache()
+        rs = {}
+        for name, prec in (("mixed", lr.FP32), ("fp64", lr.FP64)):
+            log(f"solving for alpha ({name}, stored ladder integrals)")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            al, rep = cs.solve(list(w.omegas), axis_mask=7, tol=args.alpha_tol, precision=prec, reuse_lambda=0)
+            torch.cuda.synchronize()
+            rs[name] = (time.perf_counter() - t0, al, rep)
+            log(f"alpha ({name}, stored ladder integrals) in {rs[name][0]:.1f} s: {rep}")
+        cs.close()
+        out["alpha"]["stored_integrals"] = {
+            "s_to_alpha_mixed": rs["mixed"][0], "s_to_alpha_fp64": rs["fp64"][0],
+            "max_abs_vs_default_fp64": float(np.abs(rs["fp64"][1] - af).max()),
+            "max_abs_vs_default_mixed": float(np.abs(rs["mixed"][1] - am).max()),
+            "reports": {k: rs[k][2] for k in rs},
+        }
+    if (args.mesh or args.velocity or args.uneven) and ctx is not None:
         ctx.close()               # the extra workloads need the memory
         torch.cuda.empty_cache()
     if args.mesh:
@@ -445,7 +482,8 @@ def main():
     if args.velocity:
         out["velocity_gauge_c2"] = velocity_gauge_alpha(lr, torch, args.alpha_tol)
     if args.uneven:
-        ctx.close()               # the twelve chains need the memory
+        if ctx is not None:
+            ctx.close()           # the twelve chains need the memory
         torch.cuda.empty_cache()
         out["uneven_batch"] = uneven_batch(lr, torch, max(1, args.steps))
     if not args.no_cpu:

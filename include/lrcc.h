@@ -154,7 +154,9 @@ lrcc_status lrcc_read_profile(lrcc_ctx *ctx, double *ms, long long *count);
  * blocks of nvir^4 complex values per precision, rebuilt with the other
  * amplitude-dependent blocks), after which the ladder is one dense matrix-core
  * GEMM; LRCC_E_OOM at lrcc_set_amplitudes if they would take more than half of
- * the free device memory.  The transpose product always rebuilds.  Must precede
+ * the free device memory.  The transpose product reads the same blocks in mode
+ * 2 (a transposed GEMM over the unique momentum pairs into a scratch array of
+ * the doubles' size, then an (e, f)-antisymmetric completion).  Must precede
  * the first lrcc_set_amplitudes or lrcc_solve_ccsd (LRCC_E_STATE afterwards);
  * LRCC_E_ARG for other modes. */
 lrcc_status lrcc_set_ladder_mode(lrcc_ctx *ctx, int mode);

@@ -445,6 +445,40 @@ hipError_t pp_in(const void *y, void *Z, KMesh km, int R, int o, int v, double s
     return hipGetLastError();
 }
 
+// out[blk][r][i][j][a][b] += scale * (in[blk][r][i][j][a][b] - in[blk'][r][i][j][b][a]), blk = (ki,kj,ka),
+// blk' = (ki,kj,kb): the (a,b)-antisymmetric completion of a block-layout doubles array that holds
+// only one block of each (ka, kb) pair
+template <typename T>
+__global__ void k_expand_ab(const typename Cx<T>::type *in, typename Cx<T>::type *out, KMesh km, int R, int o,
+                            int v, T scale) {
+    const int nk = km.size(), vv = v * v;
+    const i64 inblk = (i64)R * o * o;
+    const i64 rows = (i64)nk * nk * nk * inblk;
+    for (i64 row = blockIdx.x; row < rows; row += gridDim.x) {
+        // row = [blk][r][i][j], elements (a, b)
+        const i64 blk = row / inblk, rest = row - blk * inblk;
+        const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
+        const int kb = km.comb(ki, kj, ka);
+        const typename Cx<T>::type *X1 = in + row * vv;
+        const typename Cx<T>::type *X2 = in + ((((i64)ki * nk + kj) * nk + kb) * inblk + rest) * vv;
+        typename Cx<T>::type *dst = out + row * vv;
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / v, b = e - a * v;
+            const auto x1 = X1[e], x2 = X2[b * v + a], y = dst[e];
+            dst[e] = mk<T>(y.x + scale * (x1.x - x2.x), y.y + scale * (x1.y - x2.y));
+        }
+    }
+}
+
+template <typename T>
+hipError_t expand_ab(const void *in, void *out, KMesh km, int R, int o, int v, double scale, hipStream_t s) {
+    const int nk = km.size();
+    const i64 rows = (i64)nk * nk * nk * R * o * o;
+    hipLaunchKernelGGL(k_expand_ab<T>, dim3(rows_grid(rows)), dim3(256), 0, s, (const typename Cx<T>::type *)in,
+                       (typename Cx<T>::type *)out, km, R, o, v, (T)scale);
+    return hipGetLastError();
+}
+
 // y += x (complex, n elements)
 template <typename T>
 __global__ void k_add(typename Cx<T>::type *y, const typename Cx<T>::type *x, i64 n) {
@@ -496,6 +530,7 @@ hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hi
 #define INST(T)                                                                                              \
     template hipError_t pp_in<T>(const void *, void *, KMesh, int, int, int, double, hipStream_t);             \
     template hipError_t add_inplace<T>(void *, const void *, i64, hipStream_t);                              \
+    template hipError_t expand_ab<T>(const void *, void *, KMesh, int, int, int, double, hipStream_t);        \
     template hipError_t zero_fill<T>(void *, i64, hipStream_t);                                              \
     template hipError_t pair_transpose<T>(const void *, void *, int, int, int, hipStream_t);                                                                                              \
     template hipError_t tau_like<T>(const void *, const void *, const void *, void *, KMesh, int, int, int,  \

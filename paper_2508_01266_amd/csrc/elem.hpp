@@ -35,6 +35,10 @@ hipError_t permute4(const void *in, void *out, KMesh km, const int *ext_in, cons
                     hipStream_t s);
 template <typename T>
 hipError_t pp_in(const void *y, void *Z, KMesh km, int R, int o, int v, double scale, hipStream_t s);
+// out += scale * (in - in with (a,b) and ka/kb swapped): completes a doubles array that holds one
+// block of each (ka, kb) pair
+template <typename T>
+hipError_t expand_ab(const void *in, void *out, KMesh km, int R, int o, int v, double scale, hipStream_t s);
 template <typename T>
 hipError_t add_inplace(void *y, const void *x, i64 n, hipStream_t s);
 template <typename T>

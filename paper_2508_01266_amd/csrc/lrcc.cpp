@@ -879,6 +879,69 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
             break;
         }
         case SymOp::LADDER: {
+            if (S.Wst) {
+                // stored integrals, transposed: with Zbar antisymmetric in (a, b),
+                //   dtau_bar(ki,kj,ke) = alpha [sum_{ka<kb} Zbar(ki,kj,ka) W'(ka,kb,ke)^T
+                //                              + 1/2 sum_{ka=kb} Zbar(ki,kj,ka) W'(ka,ka,ke)^T]
+                // for ke <= kf (the stored ke = kf blocks carry W'/2, which the completion below
+                // doubles back); the result goes to a zeroed scratch array and expand_ab adds it and
+                // its (e, f)-antisymmetric (kf, ke) partner blocks to dtau_bar
+                const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv, n = op.A.count();
+                void *tmp = P->alloc((size_t)n * 2 * sizeof(T)), *dst = op.A.p;
+                const KMesh km = c->km;
+                P->ops.push_back([tmp, n](hipStream_t s) { return zero_fill<T>(tmp, n, s); });
+                for (int half = 0; half < 2; ++half) {
+                    GemmArgs g{};
+                    g.shape = -1;
+                    g.kind = 1;
+                    g.A = op.C.p;
+                    g.B = S.Wst;
+                    g.C = tmp;
+                    g.M = R * o * o;
+                    g.N = (int)vv;
+                    g.K = (int)vv;
+                    g.sm = Split{1, g.M};
+                    g.Am = Strides{{0, 0, vv}};
+                    g.Cm = Strides{{0, 0, vv}};
+                    g.sk = Split{1, g.K};
+                    g.Ak = Strides{{0, 0, 1}};
+                    g.Bk = Strides{{0, 0, 1}};
+                    g.sn = Split{1, g.N};
+                    g.Bn = Strides{{0, 0, vv}};
+                    g.Cn = Strides{{0, 0, 1}};
+                    g.aMfast = 0;
+                    g.bNfast = 0;
+                    g.alpha_re = op.alpha.real() * (half ? 0.5 : 1.0);
+                    g.alpha_im = op.alpha.imag() * (half ? 0.5 : 1.0);
+                    g.beta = 1;
+                    std::vector<i64> offC, segA, segB;
+                    std::vector<int> beg{0};
+                    for (int ki = 0; ki < nk; ++ki)
+                        for (int kj = 0; kj < nk; ++kj)
+                            for (int ke = 0; ke < nk; ++ke) {
+                                const int kf = c->km.comb(ki, kj, ke);
+                                if (ke > kf) continue;
+                                const size_t s0 = segA.size();
+                                for (int ka = 0; ka < nk; ++ka) {
+                                    const int kb = c->km.comb(ki, kj, ka);
+                                    if (half ? ka != kb : ka >= kb) continue;
+                                    segA.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
+                                    segB.push_back((i64)c->wslot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
+                                }
+                                if (segA.size() == s0) continue;
+                                offC.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
+                                beg.push_back((int)segA.size());
+                            }
+                    raw_gemm<T>(*P, g, offC, beg, segA, segB, op.C.count(), (i64)c->nwslot * vv * vv, n, {});
+                    P->tag_last(TAG_LADDER);
+                    P->name_last(half ? "ladder (stored integrals, transposed, ka = kb)"
+                                      : "ladder (stored integrals, transposed)");
+                }
+                P->ops.push_back([tmp, dst, km, R, o, v](hipStream_t s) {
+                    return expand_ab<T>(tmp, dst, km, R, o, v, 1.0, s);
+                });
+                break;
+            }
             LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
             P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
             P->last_flops = (i64)ladder_executed_flops(la, sizeof(T) == 8);
@@ -901,10 +964,11 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
 // file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     char b[128];
-    // "v5": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
-    // ladder: three kernels)
-    std::snprintf(b, sizeof b, "v5,%d,%d,%d,%d,%d,%s,%s%d", c->nk, c->no, c->nv, c->naux, R, prec == LRCC_FP64 ? "f64" : "f32",
-                  adj ? "adjoint" : "forward", variant);
+    // "v6": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
+    // ladder: three kernels); the ladder mode changes the program's launches, so it is part of the key
+    std::snprintf(b, sizeof b, "v6,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
+                  prec == LRCC_FP64 ? "f64" : "f32", adj ? "adjoint" : "forward", variant,
+                  c->ladder_mode == 2 ? 2 : 0);
     if (!c->km.chain()) return std::string(b) + ",mesh" + std::to_string(c->km.n0) + "x" + std::to_string(c->km.n1) +
                                "x" + std::to_string(c->km.n2);
     return b;

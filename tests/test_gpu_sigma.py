@@ -89,21 +89,24 @@ def test_sigma_adjoint_fp64_matches_oracle_and_dot_identity(nk, o, v, naux, nrhs
     rng = synth.rng_for(7000 + seed, nk, o, v)
     z1, z2 = synth.random_vectors(nrhs, nk, o, v, rng, 0.1, 0.1)
     z2 = z2 * nk
-    c = _ctx(case)
-    a1, a2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP64)
-    y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
-    for r in range(nrhs):
-        lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
-        rhs = np.sum(a1[r] * case['x1'][r]) + 0.25 * np.sum(a2[r] * case['x2'][r])
-        print(f"dot identity rhs {r}: rel {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
-        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
     ref1, ref2 = oracle_sigma_adjoint(case, z1, z2)
-    e1, e2 = _rel(a1, ref1), _rel(a2, ref2)
-    print(f"adjoint fp64 rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
-    assert e1 < 1e-11 and e2 < 1e-11
-    b1, b2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP32)
-    tol = 4 * nk * v * v * 2.0 ** -24 + 1e-6
-    assert _rel(b1, ref1) < tol and _rel(b2, ref2) < tol
+    print(f"case nk={nk} o={o} v={v} naux={naux} nrhs={nrhs}", flush=True)
+    for mode, name in MODES.items():
+        c = _ctx(case, mode)
+        a1, a2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP64)
+        y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
+        for r in range(nrhs):
+            lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
+            rhs = np.sum(a1[r] * case['x1'][r]) + 0.25 * np.sum(a2[r] * case['x2'][r])
+            print(f"dot identity ({name} ladder) rhs {r}: rel {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+            assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+        e1, e2 = _rel(a1, ref1), _rel(a2, ref2)
+        print(f"adjoint fp64 ({name} ladder) rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
+        assert e1 < 1e-11 and e2 < 1e-11
+        b1, b2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP32)
+        tol = 4 * nk * v * v * 2.0 ** -24 + 1e-6
+        assert _rel(b1, ref1) < tol and _rel(b2, ref2) < tol
+        c.close()
 
 
 def test_graph_replay_matches_eager():
