@@ -961,7 +961,7 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
 }
 
 // Autotuning cache: one line per program, "key choice0 choice1 ..." in a text
-// file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction.
+// file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction,ladder mode.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     char b[128];
     // "v6": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
