@@ -11,10 +11,11 @@ CASES = [(1, 2, 4, 6, 21), (2, 2, 3, 6, 22), (3, 1, 3, 5, 23), (1, 4, 12, 48, 24
 OMEGAS = [0.0, 0.0656]
 
 
-def _ctx(case):
+def _ctx(case, ladder_mode=0):
     import paper_2508_01266_amd as lr
     c = lr.Context(0)
     c.set_hamiltonian(case['o'], case['H']['fock'], case['H']['chol'], case['H']['dip'])
+    c.set_ladder_mode(ladder_mode)
     c.set_amplitudes(case['t1'], case['t2'])
     return c
 
@@ -41,6 +42,15 @@ def test_alpha_matches_oracle(nk, o, v, naux, seed):
     r2 = layout.block_t2(lam[1].numpy(), nk, o, v) / nk
     assert np.abs(l1 - r1).max() < 1e-9 * max(1, np.abs(r1).max())
     assert np.abs(l2 - r2).max() < 1e-9 * max(1, np.abs(r2).max())
+    c.close()
+    # stored ladder integrals: the lambda equations and the F term then read them through the
+    # transposed product
+    c = _ctx(case, 2)
+    s64, _ = c.solve(OMEGAS, tol=1e-11, precision=lr.FP64)
+    errs = np.abs(s64 - ref).max()
+    print(f"fp64 alpha, stored ladder integrals: max abs err {errs:.2e}", flush=True)
+    assert errs < 1e-9
+    c.close()
 
 
 def test_alpha_two_electron_sum_over_states():

@@ -61,16 +61,19 @@ def test_sigma_on_mesh_matches_oracle(mesh, o, v, naux, nrhs, seed):
     rng = synth.rng_for(7300 + seed, nk, o, v, extra=mesh)
     z1, z2 = synth.random_vectors(nrhs, mesh, o, v, rng, 0.1, 0.1)
     z2 = z2 * nk
-    c = _ctx(case)
-    a1, a2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP64)
-    y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
-    for r in range(nrhs):
-        lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
-        rhs = np.sum(a1[r] * case['x1'][r]) + 0.25 * np.sum(a2[r] * case['x2'][r])
-        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
     b1, b2 = oracle_sigma_adjoint(case, z1, z2)
-    assert _rel(a1, b1) < 1e-11 and _rel(a2, b2) < 1e-11
-    c.close()
+    for mode, name in MODES.items():
+        c = _ctx(case, mode)
+        a1, a2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP64)
+        y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
+        for r in range(nrhs):
+            lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
+            rhs = np.sum(a1[r] * case['x1'][r]) + 0.25 * np.sum(a2[r] * case['x2'][r])
+            assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+        e1, e2 = _rel(a1, b1), _rel(a2, b2)
+        print(f"transpose fp64 ({name}) rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
+        assert e1 < 1e-11 and e2 < 1e-11
+        c.close()
 
 
 def _crt(j):
