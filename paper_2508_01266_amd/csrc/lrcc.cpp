@@ -984,9 +984,14 @@ bool tune_lookup(const std::string &key, std::vector<int> &choice) {
     while (std::fgets(line, sizeof line, f)) {
         std::string l(line);
         if (l.compare(0, key.size() + 1, key + " ") != 0) continue;
+        // the choices: whitespace-separated candidate indices after the key
         choice.clear();
-        for (size_t p = key.size(); p < l.size(); ++p)
-            if (l[p] == '0' || l[p] == '1') choice.push_back(l[p] - '0');
+        const char *q = l.c_str() + key.size();
+        char *end = nullptr;
+        for (long x = std::strtol(q, &end, 10); end != q; x = std::strtol(q, &end, 10)) {
+            choice.push_back((int)x);
+            q = end;
+        }
         found = true;
     }
     std::fclose(f);
