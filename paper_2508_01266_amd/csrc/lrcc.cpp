@@ -451,8 +451,8 @@ void build_state(lrcc_ctx *c) {
     // U_ianf = sum_me t_imae <mn||ef>   (k_i + k_f = k_a + k_n)
     S.U = alloc_kt<double>(c, m, "ovov", 0, {1, -1, -1, 1});
     contract<double>(P, S.U, "ianf", t2, "imae", oovv, "mnef", 1.0, false);
-    // The doubles terms linear in x1 that share a contraction pattern are summed here, once per
-    // Hamiltonian, so that each pattern costs one product over all (i, j, a, b) per sigma (the
+    // The doubles terms linear in x1 that share a contraction pattern are summed here, once per set
+    // of amplitudes, so that each pattern costs one product over all (i, j, a, b) per sigma (the
     // final P(ij)P(ab) antisymmetrisation makes a term and its (i <-> j) image with opposite
     // sign equivalent):
     //   S_ijan = sum_me t_imae <mn||ej> + sum_f t_jf U_ianf + 1/4 sum_ef tau_ijef <an||ef>,
