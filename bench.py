@@ -6,7 +6,10 @@ workload, with inputs resident in HBM.  The default workload is the batched
 one: Nk=5, nocc=8, nvir=40, Naux=144, 3 axes x +-omega x 8 frequencies = 48
 right-hand sides in one launch, computed on the matrix cores in complex64
 (split into real fp32 MFMA products).  The FP64 form of the same batch is
-timed beside it.  Prints one JSON line.
+timed beside it.  Prints one JSON line.  --alpha adds the device CCSD and the
+time to converged alpha(omega) (mixed and FP64), first with the ladder integrals
+rebuilt in LDS (the default) and then, in a second context on the same
+amplitudes, with the integral blocks stored (ladder mode 2).
 """
 from __future__ import annotations
 
