@@ -6,10 +6,10 @@ workload, with inputs resident in HBM.  The default workload is the batched
 one: Nk=5, nocc=8, nvir=40, Naux=144, 3 axes x +-omega x 8 frequencies = 48
 right-hand sides in one launch, computed on the matrix cores in complex64
 (split into real fp32 MFMA products).  The FP64 form of the same batch is
-timed beside it.  Prints one JSON line.  --alpha adds the device CCSD and the
-time to converged alpha(omega) (mixed and FP64), first with the ladder integrals
-rebuilt in LDS (the default) and then, in a second context on the same
-amplitudes, with the integral blocks stored (ladder mode 2).
+timed beside it.  Then the device CCSD ground state of the same Hamiltonian and
+the time to converged alpha(omega) for all 48 right-hand sides, mixed and FP64
+(--no-alpha skips it; --alpha-stored repeats both solves with the ladder
+integral blocks stored, ladder mode 2).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -53,6 +53,27 @@ def sigma_alg_flops(nk, o, v):
 
 def ladder_alg_flops(nk, o, v):
     return 8.0 * nk ** 4 * o ** 2 * v ** 4
+
+
+def ladder_unique_flops(nk, o, v, nrhs):
+    """The ladder's own work on a 1D chain: 8 real flops per complex multiply-add over the
+    unique index pairs only.  The ladder input (dtau) and output are antisymmetric in
+    (ki,i) <-> (kj,j), in (ka,a) <-> (kb,b) and in (ke,e) <-> (kf,f), so its independent
+    products are unique rows (ki,i) < (kj,j) x unique outputs (ka,a) < (kb,b) x unique inputs
+    (ke,e) < (kf,f), over momentum-conserving blocks (kb = ki+kj-ka, kf = ki+kj-ke).  The
+    in-LDS rebuild of the integrals and tile padding are excluded (they are overhead)."""
+    pairs_o = o * (o - 1) // 2
+    total = 0
+    for ki in range(nk):
+        for kj in range(ki, nk):
+            rows = nrhs * (o * o if ki < kj else pairs_o)
+            K = (ki + kj) % nk
+            uniq = 0
+            for ka in range(nk):
+                kb = (K - ka) % nk
+                uniq += v * v if ka < kb else (v * (v - 1) // 2 if ka == kb else 0)
+            total += rows * uniq * uniq
+    return 8.0 * total
 
 
 def log(msg):
@@ -278,7 +299,10 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--alpha", action="store_true", help="also time the two converged-alpha solves")
+    ap.add_argument("--no-alpha", action="store_true",
+                    help="skip the time to converged alpha (device CCSD, then the mixed and FP64 solves)")
+    ap.add_argument("--alpha-stored", action="store_true",
+                    help="also time both alpha solves with the ladder integral blocks stored (ladder mode 2)")
     ap.add_argument("--alpha-tol", type=float, default=1e-10)
     ap.add_argument("--ccsd-iter", type=int, default=300)
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch variants instead of autotuning")
@@ -336,12 +360,15 @@ def main():
     lad_avg = lad_ms / max(lad_n, 1) / 1e3
     lad64_ms, lad64_n = prof64["ladder"]
     lad64_avg = lad64_ms / max(lad64_n, 1) / 1e3
-    # roofline of the ladder launch: the products it executes (antisymmetry-packed unique pairs
-    # plus the in-LDS integral rebuild) per second against the matrix-core peak
+    # roofline of the ladder launch: the method's own work (unique antisymmetric index pairs, the
+    # in-LDS integral rebuild counted as overhead) per second against the matrix-core peak; the
+    # products the kernel executes (rebuild and tile padding included) and its matrix-core
+    # instructions are reported beside it
+    lad_unique = ladder_unique_flops(nk, o, v, nrhs)
     lad_exec = ctx.ladder_flops(nrhs, lr.FP32)
     lad_exec64 = ctx.ladder_flops(nrhs, lr.FP64)
     lad_mfma = ctx.ladder_mfma_flops(nrhs, lr.FP32)
-    achieved = lad_exec / lad_avg / 1e12
+    achieved = lad_unique / lad_avg / 1e12
     traffic = None
     if (args.workload == LADDER_TRAFFIC["workload"] and LADDER_TRAFFIC["bytes"] is not None
             and LADDER_TRAFFIC["sources_sha256"] == ladder_sources_sha()):
@@ -366,13 +393,15 @@ def main():
                    "nk": nk, "nocc": o, "nvir": v, "naux": w.naux, "nrhs": nrhs},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["f32"], "traffic": traffic, "kernel": "ladder",
-                     "ladder_ms_avg": lad_avg * 1e3, "executed_flops_per_launch": lad_exec,
+                     "work": "unique antisymmetric pairs (rows, outputs, inputs); integral rebuild is overhead",
+                     "unique_flops_per_launch": lad_unique, "ladder_ms_avg": lad_avg * 1e3,
+                     "executed_flops_per_launch": lad_exec, "executed_frac": lad_exec / lad_avg / 1e12 / PEAK["f32"],
                      "mfma_flops_per_launch": lad_mfma, "mfma_frac": lad_mfma / lad_avg / 1e12 / PEAK["f32"],
-                     "algorithmic_flops_per_launch": lad, "algorithmic_tflops": lad / lad_avg / 1e12},
+                     "full_range_flops_per_launch": lad, "full_range_tflops": lad / lad_avg / 1e12},
         "fp64": {"value": alg / dt64 / 1e12, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
-                 "ladder_ms_avg": lad64_avg * 1e3, "ladder_achieved": lad_exec64 / lad64_avg / 1e12,
-                 "ladder_frac": lad_exec64 / lad64_avg / 1e12 / PEAK["f64"],
-                 "ladder_algorithmic_tflops": lad / lad64_avg / 1e12, "peak": PEAK["f64"]},
+                 "ladder_ms_avg": lad64_avg * 1e3, "ladder_achieved": lad_unique / lad64_avg / 1e12,
+                 "ladder_frac": lad_unique / lad64_avg / 1e12 / PEAK["f64"],
+                 "ladder_executed_frac": lad_exec64 / lad64_avg / 1e12 / PEAK["f64"], "peak": PEAK["f64"]},
         "executed_flops_per_step": {"f32": ctx.sigma_flops(nrhs, lr.FP32), "f64": ctx.sigma_flops(nrhs, lr.FP64)},
         "algorithmic_flops_per_step": alg,
         "speedup_mixed_vs_fp64_sigma": dt64 / dt32,
@@ -391,10 +420,11 @@ def main():
     sl64 = sp64["ladder"][0] / max(sp64["ladder"][1], 1) / 1e3
     out["stored_integrals"] = {
         "ms_per_step": s32 * 1e3, "value": alg / s32 / 1e12, "ladder_ms_avg": sl32 * 1e3,
-        "ladder_achieved": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12,
-        "ladder_frac": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12 / PEAK["f32"],
+        "ladder_achieved": lad_unique / sl32 / 1e12, "ladder_frac": lad_unique / sl32 / 1e12 / PEAK["f32"],
+        "ladder_executed_frac": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12 / PEAK["f32"],
         "fp64_ms_per_step": s64 * 1e3, "fp64_value": alg / s64 / 1e12, "fp64_ladder_ms_avg": sl64 * 1e3,
-        "fp64_ladder_frac": ctx2.ladder_flops(nrhs, lr.FP64) / sl64 / 1e12 / PEAK["f64"],
+        "fp64_ladder_frac": lad_unique / sl64 / 1e12 / PEAK["f64"],
+        "fp64_ladder_executed_frac": ctx2.ladder_flops(nrhs, lr.FP64) / sl64 / 1e12 / PEAK["f64"],
         "note": "ladder mode 2: antisymmetrised integral blocks stored for unique momentum pairs "
                 "(0.9 GB complex64 + 1.8 GB complex128 here); the headline uses the default mode, "
                 "integrals rebuilt in LDS from the Cholesky vectors, nothing of vvvv size stored"}
@@ -409,7 +439,7 @@ def main():
     log(f"c1 latency {out['latency_c1_9rhs']}")
     del X1, X2, Y1, Y2, OM
     torch.cuda.empty_cache()
-    if args.alpha:
+    if not args.no_alpha:
         # the response and lambda equations are posed at converged ground-state amplitudes:
         # solve CCSD on the device first (the random amplitudes above only serve the timing)
         log("solving ground-state CCSD on the device")
@@ -429,20 +459,30 @@ def main():
             res[name] = (time.perf_counter() - t0, al, rep)
             log(f"alpha ({name}) in {res[name][0]:.1f} s: {rep}")
         am, af = res["mixed"][1], res["fp64"][1]
+        dif = np.abs(am - af)
+        out["s_to_alpha_mixed"] = res["mixed"][0]
+        out["s_to_alpha_fp64"] = res["fp64"][0]
         out["alpha"] = {
             "s_to_alpha_mixed": res["mixed"][0], "s_to_alpha_fp64": res["fp64"][0],
             "speedup_mixed_vs_fp64": res["fp64"][0] / res["mixed"][0],
             "tol": args.alpha_tol,
-            "mixed_vs_fp64_max_abs": float(np.abs(am - af).max()),
-            "mixed_vs_fp64_max_rel": float(np.abs(am - af).max() / np.abs(af).max()),
+            "mixed_vs_fp64_max_abs": float(dif.max()),
+            "mixed_vs_fp64_max_rel": float(dif.max() / np.abs(af).max()),
+            # per tensor element alpha_XY: the largest |mixed - fp64| over the frequencies, and
+            # relative to the largest |alpha_XY| over the frequencies
+            "mixed_vs_fp64_per_element_abs": [[float(dif[:, x, y].max()) for y in range(3)] for x in range(3)],
+            "mixed_vs_fp64_per_element_rel": [[float(dif[:, x, y].max() / max(np.abs(af[:, x, y]).max(), 1e-300))
+                                               for y in range(3)] for x in range(3)],
             "alpha_xx_over_freqs_fp64": [float(x) for x in af[:, 0, 0].real],
             "effective_sigma_tflops": {k: res[k][2]["rhs_sigmas"] * sigma_alg_flops(nk, o, v) / res[k][0] / 1e12
                                        for k in res},
             "reports": {k: res[k][2] for k in res},
         }
+    if not args.no_alpha and args.alpha_stored:
         # the same solves with the ladder integral blocks stored (ladder mode 2, forward and
         # transpose products): the one-vector transpose products of the lambda equations and of the
         # F term are bound by the in-LDS rebuild at 64 rows, which the stored blocks remove
+        am, af = res["mixed"][1], res["fp64"][1]
         ctx.close()
         ctx = None
         torch.cuda.empty_cache()

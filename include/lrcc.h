@@ -49,8 +49,12 @@ typedef enum {
     LRCC_E_STATE = 3,    /* call made before the inputs it needs were set               */
     LRCC_E_OOM = 4,      /* device allocation failed or exceeds the memory cap          */
     LRCC_E_HIP = 5,      /* HIP runtime error                                           */
-    LRCC_E_NOCONV = 6,   /* iterative solve did not reach the tolerance                 */
-    LRCC_E_SINGULAR = 7  /* response operator numerically singular at this frequency    */
+    LRCC_E_NOCONV = 6,   /* iterative solve did not reach the tolerance, or a residual
+                            norm is not finite (NaN/Inf in the inputs or iterates)     */
+    LRCC_E_SINGULAR = 7  /* response operator numerically singular at this frequency:
+                            the complex128 Krylov iteration met a Hessenberg pivot
+                            below 1e-12 on a right-hand side that had not converged
+                            (the preconditioned operator is O(1) by construction)   */
 } lrcc_status;
 
 enum { LRCC_FP64 = 0, LRCC_FP32 = 1 };
@@ -60,8 +64,8 @@ typedef struct {
     double tol;            /* stop when ||b - (A - w) x|| <= tol ||b|| for every RHS (default 1e-10);
                               norm: sum |u1|^2 + 1/4 sum |u2|^2 over full arrays                      */
     int max_iter;          /* FP64 GMRES: maximum operator applications (default 400)                */
-    int krylov;            /* GMRES restart length; 0 (default) sizes it from free device memory
-                              (85% of it, 4..60 vectors)                                              */
+    int krylov;            /* GMRES restart length (at most 60); 0 (default) sizes it from free device
+                              memory (85% of it, 4..60 vectors)                                       */
     int precision;         /* LRCC_FP64: GMRES in complex128; LRCC_FP32: complex64 matrix-core inner
                               GMRES corrections inside complex128 iterative refinement                */
     double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4;
@@ -72,11 +76,11 @@ typedef struct {
 } lrcc_solve_opts;
 
 typedef struct {
-    int converged;           /* 1 if every RHS met tol                                               */
+    int converged;           /* 1 if every RHS met tol (0 if any residual norm is NaN or Inf)       */
     int outer;               /* refinement steps (1 for LRCC_FP64)                                    */
     int sigma_fp64;          /* complex128 sigma applications (batched launches)                     */
     int sigma_fp32;          /* complex64 sigma applications (batched launches)                      */
-    double max_rel_residual; /* largest final relative residual over the RHS                         */
+    double max_rel_residual; /* largest final relative residual over the RHS (NaN if any is NaN)     */
     double seconds;          /* wall time of the solve                                               */
     long long rhs_sigmas;    /* full-Jacobian products counted per right-hand side (forward, adjoint,
                                 both precisions): work in units of one single-RHS sigma               */
@@ -255,7 +259,10 @@ void lrcc_solve_opts_default(lrcc_solve_opts *opts);
  * nrhs right-hand sides at once, each with its own frequency.  x holds the
  * initial guess on entry (zeros for none) and the solution on exit.  opts may
  * be NULL (defaults).  Returns LRCC_E_NOCONV (x and report still written) if
- * the tolerance is not reached.  Host-buffer variant (omega host) and device
+ * the tolerance is not reached or a residual norm is not finite (NaN/Inf in b
+ * or x), LRCC_E_SINGULAR (x and report written) if (A - omega_r) is singular
+ * (see the status codes), LRCC_E_OOM if opts->mem_cap_bytes is below the
+ * Krylov vectors' size.  Host-buffer variant (omega host) and device
  * variant (omega, b, x device; enqueued on stream, returns after completion). */
 lrcc_status lrcc_solve_response(lrcc_ctx *ctx, int nrhs, const double *omega,
                                 const double *b1, const double *b2, double *x1, double *x2,
@@ -279,7 +286,10 @@ lrcc_status lrcc_solve_response_dev(lrcc_ctx *ctx, int nrhs, const double *omega
  * refinement (the one-vector lambda solve is always complex128); the residual
  * tolerance, subspace size and memory cap come from
  * opts (NULL: defaults).  Results stay in the context: lrcc_get_alpha,
- * lrcc_get_solution, lrcc_get_lambda. */
+ * lrcc_get_solution, lrcc_get_lambda.  Initial guesses stored with
+ * lrcc_set_guess start the batched solve.  On LRCC_E_NOCONV / LRCC_E_SINGULAR
+ * the report (if given) describes the failing solve and no polarizability is
+ * stored.  LRCC_E_ARG for non-finite frequencies or bad options. */
 lrcc_status lrcc_solve(lrcc_ctx *ctx, unsigned axis_mask, int nfreq, const double *omega,
                        const lrcc_solve_opts *opts, lrcc_solve_report *report);
 
@@ -304,7 +314,9 @@ lrcc_status lrcc_solve_ccsd(lrcc_ctx *ctx, double tol, int max_iter, double *t1,
  * kernel (stored integrals, or fewer than 320 (rhs, i, j) rows) run their
  * whole program on their own.  Results are bitwise those of
  * lrcc_apply_sigma_dev per chain.  The group does not own the contexts; destroy
- * it before them.  Arrays are indexed by chain; omega may be NULL.  Errors:
+ * it before them.  A chain may get a new Hamiltonian, k mesh or amplitudes
+ * between calls: the group's launch tables record each context's state and are
+ * rebuilt when it changed.  Arrays are indexed by chain; omega may be NULL.  Errors:
  * LRCC_E_ARG for null arrays, contexts on different devices or a bad precision,
  * LRCC_E_STATE if a chain has no amplitudes; the message is read with
  * lrcc_group_last_error. */
@@ -360,7 +372,7 @@ lrcc_status lrcc_alpha_velocity_gauge(lrcc_ctx *ctx, unsigned axis_mask, int nfr
 
 /* alpha [nfreq][3][3] complex (zeros for skipped axes) of the last lrcc_solve;
  * nfreq must match it. */
-lrcc_status lrcc_get_alpha(lrcc_ctx *ctx, int nfreq, double *alpha);
+lrcc_status lrcc_get_alpha(const lrcc_ctx *ctx, int nfreq, double *alpha);
 
 /* Gradient of one polarizability element of the last lrcc_solve with respect to
  * the dipole matrices (the perturbation operators of Eq. rhs, Sec. II.B), at
@@ -389,9 +401,42 @@ lrcc_status lrcc_alpha_dipole_gradient(lrcc_ctx *ctx, int ifreq, int x, int y, c
 lrcc_status lrcc_alpha_fock_gradient(lrcc_ctx *ctx, int ifreq, int x, int y, const lrcc_solve_opts *opts,
                                      double *grad);
 
+/* Gradient of one polarizability element of the last lrcc_solve with respect to
+ * the Cholesky vectors of the two-electron integrals (Sec. II.A; they enter the
+ * Jacobian of Eqs. tx1, tx2, the multiplier equations l1, l2 and the response
+ * function of Eq. lrf), at fixed ground-state amplitudes with lambda and the
+ * response amplitudes re-solved:
+ *   d alpha_xy(omega_ifreq) = sum_{k1,k2,Q,p,q} grad[k1][k2][Q][p][q] dL[k1][k2][Q][p][q]
+ * for every perturbation dL that keeps the Hermitian pairing of lrcc_set_hamiltonian
+ * (dL[k2][k1][Q] = conj(dL[k1][k2][Q])^T).  grad: host [nk][nk][naux][n][n] complex.
+ * The parameter derivative of the Jacobian is taken by reverse traversal of the
+ * sigma's term list and of the amplitude-dependent blocks at fixed amplitudes; the
+ * ladder's contribution is formed from the density D_ab,ef = sum u_ijab x_ijef one
+ * momentum block at a time (never stored whole) and contracted with the Cholesky
+ * vectors.  Costs the solves of the Fock gradient plus 14 parameter-derivative
+ * passes of about one sigma each.  Errors as for lrcc_alpha_dipole_gradient. */
+lrcc_status lrcc_alpha_chol_gradient(lrcc_ctx *ctx, int ifreq, int x, int y, const lrcc_solve_opts *opts,
+                                     double *grad);
+
 /* Perturbed amplitudes t^X(sign*omega_ifreq) of the last lrcc_solve (caller
  * layouts with nrhs = 1, per-cell normalisation). */
-lrcc_status lrcc_get_solution(lrcc_ctx *ctx, int axis, int ifreq, int sign, double *x1, double *x2);
+lrcc_status lrcc_get_solution(const lrcc_ctx *ctx, int axis, int ifreq, int sign, double *x1, double *x2);
+
+/* Initial guess for one right-hand side of the NEXT lrcc_solve: the perturbed
+ * amplitudes t^axis(sign*omega_ifreq) start from (x1, x2) instead of zero (the
+ * restart of the iterative solution of Sec. II.C; e.g. the converged amplitudes
+ * of a neighbouring frequency from lrcc_get_solution seed a shifted frequency
+ * grid).  ifreq indexes the frequency list of that next call; x1
+ * [nk][nocc][nvir], x2 [nk][nk][nk][nocc][nocc][nvir][nvir] (HOST buffers, caller
+ * layouts, per-cell normalisation), copied into context-owned device memory
+ * (one amplitude vector per guess; setting the same (axis, ifreq, sign) again
+ * replaces it).  The next lrcc_solve consumes every stored guess (guesses for
+ * axes or frequencies it does not solve are dropped); lrcc_set_hamiltonian and
+ * lrcc_set_kmesh discard them.  The solution does not depend on the guess (up to
+ * the solver tolerance), only the work does.  LRCC_E_ARG for an axis outside
+ * 0..2, ifreq < 0, sign not +-1, null pointers or non-finite values;
+ * LRCC_E_STATE before lrcc_set_hamiltonian. */
+lrcc_status lrcc_set_guess(lrcc_ctx *ctx, int axis, int ifreq, int sign, const double *x1, const double *x2);
 
 /* lambda amplitudes of the last lrcc_solve (layouts of t1/t2; pairing
  * sum l1 x1 + 1/4 sum l2 x2 with amplitudes in the per-cell normalisation). */

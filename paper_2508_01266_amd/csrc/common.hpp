@@ -138,6 +138,12 @@ struct LadderArgs {
     double alpha;
     int packed;          // Y antisymmetric in (e,f): form only unique (e,f) and (a,b) pairs
                          // (1: 256-row kernel, 2: pipelined kernel); 0: full ranges
+    int pack_rows;       // with packed == 2: Y and the result are also antisymmetric in the row pair
+                         // (i,j) and Z goes through P(ij)P(ab) afterwards, so only the unique rows
+                         // (ki,i) < (kj,j) are formed (blocks ki > kj skipped, i < j when ki == kj)
+                         // and written with a further factor 2
+    int order;           // pipelined kernel: 1 = XCD-grouped tile order (the row tiles of one
+                         // (block, a/b tile) run on one XCD), 0 = row tile fastest in the grid
     KMesh km;            // k mesh of the blocks
 };
 template <typename T>

@@ -527,6 +527,53 @@ hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hi
     return hipGetLastError();
 }
 
+// Reverse of chol_slice (no conjugation, scale 1): out[k1][k2][Q][p0+p][q0+q] += in[k1][k2][Q][p][q]
+// (complex128; out is a full [nk][nk][naux][n][n] array)
+__global__ void k_slice_add(const double2 *in, double2 *out, int nk, int naux, int n, int p0, int np, int q0,
+                            int nq) {
+    const i64 N = (i64)nk * nk * naux * np * nq;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int qq = (int)(q % nq); q /= nq;
+        const int pp = (int)(q % np); q /= np;
+        const i64 dst = (q * n + p0 + pp) * n + q0 + qq;   // q = (k1 * nk + k2) * naux + Q
+        const double2 a = out[dst], b = in[t];
+        out[dst] = make_double2(a.x + b.x, a.y + b.y);
+    }
+}
+
+hipError_t slice_add(const void *in, void *out, int nk, int naux, int n, int p0, int np, int q0, int nq,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_slice_add, dim3(grid_for((i64)nk * nk * naux * np * nq)), dim3(256), 0, s,
+                       (const double2 *)in, (double2 *)out, nk, naux, n, p0, np, q0, nq);
+    return hipGetLastError();
+}
+
+// g[ki][kj][ki][i][j][a][b] += c x[ki][i][a] y[kj][j][b]: the k-diagonal singles x, y put into the
+// blocks (ki, kj, ka = ki, kb = kj) of an oovv-class array (complex128)
+__global__ void k_outer_oovv(double2 *g, const double2 *x, const double2 *y, double c, int nk, int o, int v) {
+    const i64 N = (i64)nk * nk * o * o * v * v;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        i64 q = t;
+        const int b = (int)(q % v); q /= v;
+        const int a = (int)(q % v); q /= v;
+        const int j = (int)(q % o); q /= o;
+        const int i = (int)(q % o); q /= o;
+        const int kj = (int)(q % nk);
+        const int ki = (int)(q / nk);
+        const double2 xv = x[((i64)ki * o + i) * v + a], yv = y[((i64)kj * o + j) * v + b];
+        const i64 dst = (((((i64)ki * nk + kj) * nk + ki) * o + i) * o + j) * v * v + (i64)a * v + b;
+        const double2 gv = g[dst];
+        g[dst] = make_double2(gv.x + c * (xv.x * yv.x - xv.y * yv.y), gv.y + c * (xv.x * yv.y + xv.y * yv.x));
+    }
+}
+
+hipError_t outer_oovv(void *g, const void *x, const void *y, double c, int nk, int o, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_outer_oovv, dim3(grid_for((i64)nk * nk * o * o * v * v)), dim3(256), 0, s, (double2 *)g,
+                       (const double2 *)x, (const double2 *)y, c, nk, o, v);
+    return hipGetLastError();
+}
+
 #define INST(T)                                                                                              \
     template hipError_t pp_in<T>(const void *, void *, KMesh, int, int, int, double, hipStream_t);             \
     template hipError_t add_inplace<T>(void *, const void *, i64, hipStream_t);                              \

@@ -45,4 +45,9 @@ template <typename T>
 hipError_t zero_fill(void *y, i64 n, hipStream_t s);
 template <typename T>
 hipError_t pair_transpose(const void *in, void *out, int nk, int naux, int m, hipStream_t s);
+// out[k1][k2][Q][p0+p][q0+q] += in[k1][k2][Q][p][q] (complex128; the reverse of chol_slice)
+hipError_t slice_add(const void *in, void *out, int nk, int naux, int n, int p0, int np, int q0, int nq,
+                     hipStream_t s);
+// g[ki][kj][ki][i][j][a][b] += c x[ki][i][a] y[kj][j][b] (complex128, oovv-class blocks)
+hipError_t outer_oovv(void *g, const void *x, const void *y, double c, int nk, int o, int v, hipStream_t s);
 }  // namespace lrcc

@@ -558,8 +558,8 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     __shared__ T Yr[LTK][BM + PY], Yi[LTK][BM + PY];
     __shared__ T Lr[4][QCH][32 + PL], Li[4][QCH][32 + PL];
 
-    const int nk = p.nk, v = p.v, naux = p.naux;
-    const int M = p.nrhs * p.o * p.o;
+    const int nk = p.nk, v = p.v, naux = p.naux, o = p.o;
+    const int M = p.nrhs * o * o;
     const int tilesM = (M + BM - 1) / BM;
     const int tilesA = (v + TA - 1) / TA;
     const int mt = bx % tilesM;
@@ -570,7 +570,15 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     const int kb = p.km.comb(ki, kj, ka);
     if (ka > kb || (ka == kb && ta > tb)) return;
     const bool diag_out = (ka == kb);
+    // unique rows: all (rhs, i, j) of a block ki < kj; the o(o-1)/2 pairs i < j per right-hand
+    // side of a block ki == kj (compact row index m = rhs * P + pair); none when ki > kj
+    const bool rows_packed = p.pack_rows != 0;
+    if (rows_packed && ki > kj) return;
+    const bool diag_rows = rows_packed && ki == kj;
+    const int P = o * (o - 1) / 2;
+    const int Mr = diag_rows ? p.nrhs * P : M;      // rows of this block
     const int m0 = mt * BM;
+    if (m0 >= Mr) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave % WM) * FM * 16, wn = (wave / WM) * FN * 16;
@@ -582,6 +590,24 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     C2 *Z = reinterpret_cast<C2 *>(p.Z);
     const int gb = wave & 3, second = (wave >> 2) & 1;
     const bool rebuilder = WM * WN == 8 || wave < 8;   // compile-time true with eight waves
+    // row table of the tile: block row (rhs * o + i) * o + j of every tile row, -1 past the end
+    __shared__ int rowtab[BM];
+    for (int t = tid; t < BM; t += NT) {
+        const int m = m0 + t;
+        int ro = -1;
+        if (m < Mr) {
+            if (diag_rows) {
+                const int r = m / P;
+                int q = m - r * P, i = 0;
+                while (q >= o - 1 - i) { q -= o - 1 - i; ++i; }
+                ro = (r * o + i) * o + i + 1 + q;
+            } else {
+                ro = m;
+            }
+        }
+        rowtab[t] = ro;
+    }
+    __syncthreads();
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     // steps (ke <= kf, e0, f0 >= e0 when ke == kf); the step after `s`, or ke = nk when done
@@ -647,9 +673,9 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4 + (i64)e * v + f;
 #pragma unroll
         for (int q = 0; q < YPT; ++q) {
-            const int m = m0 + ym + q * (NT / LTK);
+            const int ro = rowtab[ym + q * (NT / LTK)];
             C2 val; val.x = 0; val.y = 0;
-            if (ok && m < M) val = Yb[(i64)m * vv];
+            if (ok && ro >= 0) val = Yb[(i64)ro * vv];
             yv[q] = val;
         }
     };
@@ -746,18 +772,20 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     }
 
     C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
-    const T al = (T)(2.0 * p.alpha);
+    // unique (a, b) outputs carry 2 alpha, and unique rows a further 2: the P(ij)P(ab) assembly
+    // reproduces the partners from the antisymmetry
+    const T al = (T)((rows_packed ? 4.0 : 2.0) * p.alpha);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm + 16 * i + MfmaL<T>::row(lane, r);
+                const int ro = rowtab[wm + 16 * i + MfmaL<T>::row(lane, r)];
                 const int c = wn + 16 * j + (lane & 15);
                 const int a = a0 + c / TB, b = b0 + c % TB;
-                if (m < M && a < v && b < v && (!diag_out || a < b)) {
-                    const i64 off = (i64)m * vv + (i64)a * v + b;
+                if (ro >= 0 && a < v && b < v && (!diag_out || a < b)) {
+                    const i64 off = (i64)ro * vv + (i64)a * v + b;
                     C2 o2 = Zb[off];
                     o2.x += al * accr[i][j][r];
                     o2.y += al * acci[i][j][r];
@@ -766,9 +794,28 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
             }
 }
 
+// Workgroups are dealt to the eight XCDs round-robin by linear id, and each XCD has its own L2.
+// order 1: the 1D grid is read as (XCD c = id % 8, slot s = id / 8); slot s of XCD c runs row tile
+// s % tilesM of group G = (s / tilesM) * 8 + c, a group being one (k block, a/b tile): the row
+// tiles of a group share the Cholesky chunks of every step (147 KB at Naux = 144) in one L2, and
+// groups (with their early exits: non-unique blocks and tiles, rows past a diagonal block's end)
+// are spread evenly over the XCDs.  order 0: x = row tile + tilesM * a/b tile, y = k block.
+constexpr int kXcd = 8;
+
 template <typename T, int WM, int WN, int QCH>
 __global__ void __launch_bounds__(WM * WN * 64) ladder_kernel_pipe(LadderArgs p) {
-    ladder_pipe_tile<T, WM, WN, QCH>(p, blockIdx.x, blockIdx.y);
+    if (p.order == 1) {
+        constexpr int BM = WM * 4 * 16;
+        const int tilesM = (p.nrhs * p.o * p.o + BM - 1) / BM;
+        const int tAB = ((p.v + TA - 1) / TA) * ((p.v + TB - 1) / TB);
+        const int groups = p.nk * p.nk * p.nk * tAB;
+        const int g = blockIdx.x, c = g % kXcd, s = g / kXcd;
+        const int G = (s / tilesM) * kXcd + c;
+        if (G >= groups) return;
+        ladder_pipe_tile<T, WM, WN, QCH>(p, s % tilesM + tilesM * (G % tAB), G / tAB);
+    } else {
+        ladder_pipe_tile<T, WM, WN, QCH>(p, blockIdx.x, blockIdx.y);
+    }
 }
 
 // Persistent form over several ladders (chains of different shapes): every
@@ -815,7 +862,10 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
         dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
         if (a.packed == 2) {
             typedef PipeCfg<T> C;
-            dim3 gp(((M + C::BM - 1) / C::BM) * tA * tB, a.nk * a.nk * a.nk);
+            const long long tilesMp = (M + C::BM - 1) / C::BM;
+            const long long groups = (long long)a.nk * a.nk * a.nk * tA * tB;
+            dim3 gp(tilesMp * tA * tB, a.nk * a.nk * a.nk);
+            if (a.order == 1) gp = dim3((unsigned)(kXcd * tilesMp * ((groups + kXcd - 1) / kXcd)), 1);
             hipLaunchKernelGGL((ladder_kernel_pipe<T, C::WM, C::WN, C::QCH>), gp, dim3(C::WM * C::WN * 64), 0, s, a);
         } else if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
         else hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
@@ -866,9 +916,13 @@ double ladder_flop_count(const LadderArgs &a, bool fp64, bool mfma) {
     // pipelined kernel's rebuild products count 6
     const double rb = (mfma && pipe && !fp64) ? 0.75 : 1.0;
     const int nk = a.nk;
+    const bool rows = pipe && a.pack_rows;
+    const double tilesD = rows ? (double)(((i64)a.nrhs * (a.o * (a.o - 1) / 2) + tm - 1) / tm) : tilesM;
     double steps = 0;
     for (int ki = 0; ki < nk; ++ki)
-        for (int kj = 0; kj < nk; ++kj)
+        for (int kj = 0; kj < nk; ++kj) {
+            if (rows && ki > kj) continue;
+            const double tiles = rows && ki == kj ? tilesD : tilesM;
             for (int ka = 0; ka < nk; ++ka) {
                 const int kb = a.km.comb(ki, kj, ka);
                 if (ka > kb) continue;
@@ -879,9 +933,10 @@ double ladder_flop_count(const LadderArgs &a, bool fp64, bool mfma) {
                     if (ke > kf) continue;
                     in += ke == kf ? tE * (tE + 1) / 2.0 : (double)tE * tF;
                 }
-                steps += out * in;
+                steps += out * in * tiles;
             }
-    return steps * tilesM * (main_step + 2.0 * rb * rebuild_step);
+        }
+    return steps * (main_step + 2.0 * rb * rebuild_step);
 }
 
 double ladder_executed_flops(const LadderArgs &a, bool fp64) { return ladder_flop_count(a, fp64, false); }

@@ -11,11 +11,14 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <limits>
 #include <complex>
 #include <cstring>
+#include <array>
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lrcc.h"
@@ -75,7 +78,10 @@ struct State {
 
 struct lrcc_ctx {
     int dev = 0;
-    std::string err;
+    mutable std::string err;
+    // bumped whenever recorded programs or the buffers they read are rebuilt (new Hamiltonian,
+    // k mesh or amplitude-dependent state); groups of chains compare it to rebuild their tables
+    unsigned long long gen = 0;
     int nk = 0, no = 0, nv = 0, naux = 0, n = 0;
     KMesh km;                                  // k mesh (a 1D chain unless set by lrcc_set_kmesh)
     bool km_set = false;
@@ -94,11 +100,11 @@ struct lrcc_ctx {
     const double *io_omega = nullptr;
     // host-API staging buffers
     DevMem stage;
-    size_t stage_bytes = 0;
+    size_t stage_b1 = 0, stage_b2 = 0, stage_nrhs = 0;   // capacities of the staging buffers
     void *st_x1 = nullptr, *st_x2 = nullptr, *st_y1 = nullptr, *st_y2 = nullptr, *st_om = nullptr;
     // scratch of the vector-Jacobian product entry (grown on demand)
     DevMem vjpmem;
-    size_t vjp_bytes = 0;
+    i64 vjp_n1 = 0, vjp_n2 = 0;                // capacities (complex elements) of vj1/vw1 and vj2/vw2
     void *vj1 = nullptr, *vj2 = nullptr, *vw1 = nullptr, *vw2 = nullptr;
     Profiler prof;
     bool use_graphs = false;
@@ -132,6 +138,8 @@ struct lrcc_ctx {
     KT dT1, dT2;                               // amplitudes the density programs read (crystal)
     std::map<int, std::unique_ptr<Program>> dens;
     std::map<int, std::unique_ptr<DevMem>> densmem;
+    // initial guesses of the next lrcc_solve, keyed by (axis, ifreq, sign): device [n1 + n2] complex
+    std::map<std::array<int, 3>, std::unique_ptr<DevMem>> guess;
 };
 
 static std::string g_create_err;
@@ -371,6 +379,7 @@ void build_state(lrcc_ctx *c) {
     S.ready = c->s32.ready = false;
     c->progs.clear();
     c->progmem.clear();
+    ++c->gen;
     DevMem &m = S.mem;
     auto Pp = std::make_unique<Program>();
     Program &P = *Pp;
@@ -761,8 +770,9 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
         case SymOp::LADDER: {
             if (S.Wst) {
                 // stored integrals: Z(ki,kj,ka) += alpha' sum_{ke <= kf} Y(ki,kj,ke) W'(ka,kb,ke) for
-                // ka <= kb, alpha' = 2 alpha when ka < kb (the (kb,ka) partner block is left to the
-                // P(ij)P(ab) assembly, which reproduces it from antisymmetry), alpha when ka == kb
+                // ka <= kb and ki <= kj, alpha' = alpha times 2 when ka < kb and 2 when ki < kj (the
+                // (kb,ka) and (kj,ki) partner blocks are left to the P(ij)P(ab) assembly, which
+                // reproduces them from antisymmetry)
                 const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv;
                 GemmArgs g{};
                 g.shape = -1;
@@ -791,7 +801,7 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
                 std::vector<int> beg{0};
                 std::vector<float> js;
                 for (int ki = 0; ki < nk; ++ki)
-                    for (int kj = 0; kj < nk; ++kj)
+                    for (int kj = ki; kj < nk; ++kj)
                         for (int ka = 0; ka < nk; ++ka) {
                             const int kb = c->km.comb(ki, kj, ka);
                             if (ka > kb) continue;
@@ -803,7 +813,7 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
                             }
                             offC.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
                             beg.push_back((int)segA.size());
-                            js.push_back(ka < kb ? 2.0f : 1.0f);
+                            js.push_back((ka < kb ? 2.0f : 1.0f) * (ki < kj ? 2.0f : 1.0f));
                         }
                 raw_gemm<T>(*P, g, offC, beg, segA, segB, op.A.count(), (i64)c->nwslot * vv * vv, op.C.count(), js);
                 P->tag_last(TAG_LADDER);
@@ -814,12 +824,20 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
             // dtau is antisymmetric in (e,f): packed kernels; the pipelined one from 320 rows on
             // (its 384-row tiles would idle more than a sixth of their rows below)
             la.packed = c->pack_ladder ? ((i64)R * c->no * c->no >= 320 ? 2 : 1) : 0;
+            // dtau and the ladder term are antisymmetric in (i, j) too, and Z reaches sigma2 only
+            // through P(ij)P(ab): the pipelined kernel forms the unique rows only
+            la.pack_rows = 1;
+            la.order = 1;
             auto lp = std::make_shared<LadderArgs>(la);
             P->ops.push_back([lp](hipStream_t s) { return launch_ladder<T>(*lp, s); });
             P->ladder_args = lp;
             P->ladder_op = P->ops.size() - 1;
-            // candidates: pipelined packed (0), 256-row packed (1) or full-range (2) ladder
-            P->tunables.push_back({P->ops.size() - 1, 3, [lp](int c) { lp->packed = c == 0 ? 2 : c == 1 ? 1 : 0; }});
+            // candidates: pipelined packed in XCD-grouped (0) or plain (1) tile order, 256-row
+            // packed (2) or full-range (3) ladder
+            P->tunables.push_back({P->ops.size() - 1, 4, [lp](int c) {
+                lp->packed = c <= 1 ? 2 : c == 2 ? 1 : 0;
+                lp->order = c == 0 ? 1 : 0;
+            }});
             P->last_flops = (i64)ladder_executed_flops(la, sizeof(T) == 8);
             P->flops += P->last_flops;
             P->tag_last(TAG_LADDER);
@@ -838,11 +856,33 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
 
 // Transpose product y = (A - omega)^T z with respect to the pairing
 // <u, v> = sum u1 v1 + 1/4 sum u2 v2 (amplitude arrays in the caller's normalisation).
+// Reverse sweep of a recorded term list: every active tensor of G receives its cotangent for
+// the output cotangent z = (*z1src, *z2src) (caller layout, read when the program runs), in
+// the pairing <z, y> = sum z1 y1 + 1/4 sum z2 y2.  The active buffers of G hold cotangents
+// afterwards (x1, x2: the transpose product before the final assembly).
+template <typename T>
+void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Program *P,
+                        const void *const *z1src, const void *const *z2src);
+
 template <typename T>
 Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
     SigmaGraph G = record_sigma<T>(c, S, R, wm, full);
+    emit_reverse_sweep<T>(c, S, R, G, P, &c->io_x1, &c->io_x2);
+    KT x1 = G.x1, x2 = G.x2;
+    // y1 = x1bar - omega z1 ; y2 = P(ij)P(ab) x2bar / Nk - omega z2
+    P->ops.push_back([=](hipStream_t s) { return s1_out<T>(x1.p, c->io_x1, c->io_y1, c->io_omega, nk, R, o, v, s); });
+    P->ops.push_back([=](hipStream_t s) {
+        return pp_out<T>(x2.p, c->io_x2, c->io_y2, c->io_omega, c->km, R, o, v, 1.0 / nk, s);
+    });
+    return P;
+}
+
+template <typename T>
+void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Program *P,
+                        const void *const *z1src, const void *const *z2src) {
+    const int nk = c->nk, o = c->no, v = c->nv;
     // adjoint buffer for every active tensor (the forward buffers are reused as adjoints)
     for (const KT &a : G.active) {
         void *p = a.p;
@@ -851,8 +891,8 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
     }
     KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
     // cotangent of the outputs: s1bar = z1, Zbar = (Nk/4) P(ij)P(ab) z2
-    P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, T>(c->io_x1, s1.p, R, nk, (i64)o * v, 1.0, s); });
-    P->ops.push_back([=](hipStream_t s) { return pp_in<T>(c->io_x2, Z.p, c->km, R, o, v, 0.25 * nk, s); });
+    P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, T>(*z1src, s1.p, R, nk, (i64)o * v, 1.0, s); });
+    P->ops.push_back([=](hipStream_t s) { return pp_in<T>(*z2src, Z.p, c->km, R, o, v, 0.25 * nk, s); });
     for (auto it = G.ops.rbegin(); it != G.ops.rend(); ++it) {
         const SymOp &op = *it;
         switch (op.kind) {
@@ -914,10 +954,14 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
                     g.alpha_re = op.alpha.real() * (half ? 0.5 : 1.0);
                     g.alpha_im = op.alpha.imag() * (half ? 0.5 : 1.0);
                     g.beta = 1;
+                    // only ki <= kj: dtau_bar is read by the transposed tau step alone, whose four
+                    // (i, j) / (a, b) placements make a block (ki, kj) stand for its (kj, ki) partner
+                    // at twice the weight (the transposed P(ij)P(ab) of the forward assembly)
                     std::vector<i64> offC, segA, segB;
                     std::vector<int> beg{0};
+                    std::vector<float> js;
                     for (int ki = 0; ki < nk; ++ki)
-                        for (int kj = 0; kj < nk; ++kj)
+                        for (int kj = ki; kj < nk; ++kj)
                             for (int ke = 0; ke < nk; ++ke) {
                                 const int kf = c->km.comb(ki, kj, ke);
                                 if (ke > kf) continue;
@@ -931,8 +975,9 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
                                 if (segA.size() == s0) continue;
                                 offC.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
                                 beg.push_back((int)segA.size());
+                                js.push_back(ki < kj ? 2.0f : 1.0f);
                             }
-                    raw_gemm<T>(*P, g, offC, beg, segA, segB, op.C.count(), (i64)c->nwslot * vv * vv, n, {});
+                    raw_gemm<T>(*P, g, offC, beg, segA, segB, op.C.count(), (i64)c->nwslot * vv * vv, n, js);
                     P->tag_last(TAG_LADDER);
                     P->name_last(half ? "ladder (stored integrals, transposed, ka = kb)"
                                       : "ladder (stored integrals, transposed)");
@@ -943,6 +988,15 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
                 break;
             }
             LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
+            // Zbar is antisymmetric in both pairs (it is only read in the reverse pass) and so is
+            // the transposed ladder; dtau_bar is read by the transposed tau step alone, which sums
+            // the four pair placements: the pipelined kernel forms unique pairs and rows from 320
+            // rows on (below, the full-range kernel: the packed tiles would idle)
+            if (c->pack_ladder && (i64)R * c->no * c->no >= 320) {
+                la.packed = 2;
+                la.pack_rows = 1;
+                la.order = 1;
+            }
             P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
             P->last_flops = (i64)ladder_executed_flops(la, sizeof(T) == 8);
             P->flops += P->last_flops;
@@ -952,21 +1006,16 @@ Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool f
         }
         }
     }
-    // y1 = x1bar - omega z1 ; y2 = P(ij)P(ab) x2bar / Nk - omega z2
-    P->ops.push_back([=](hipStream_t s) { return s1_out<T>(x1.p, c->io_x1, c->io_y1, c->io_omega, nk, R, o, v, s); });
-    P->ops.push_back([=](hipStream_t s) {
-        return pp_out<T>(x2.p, c->io_x2, c->io_y2, c->io_omega, c->km, R, o, v, 1.0 / nk, s);
-    });
-    return P;
 }
 
 // Autotuning cache: one line per program, "key choice0 choice1 ..." in a text
 // file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction,ladder mode.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
     char b[128];
-    // "v6": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
-    // ladder: three kernels); the ladder mode changes the program's launches, so it is part of the key
-    std::snprintf(b, sizeof b, "v6,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
+    // "v7": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
+    // ladder: four kernel/order variants); the ladder mode changes the program's launches, so it is
+    // part of the key
+    std::snprintf(b, sizeof b, "v7,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
                   prec == LRCC_FP64 ? "f64" : "f32", adj ? "adjoint" : "forward", variant,
                   c->ladder_mode == 2 ? 2 : 0);
     if (!c->km.chain()) return std::string(b) + ",mesh" + std::to_string(c->km.n0) + "x" + std::to_string(c->km.n1) +
@@ -1083,10 +1132,15 @@ struct SolveCtx {
         for (int r = 0; r < R; ++r) a[r] += b[r];
         return a;
     }
+    // NaN for a non-finite inner product, so that a NaN or Inf anywhere in a right-hand side
+    // can never look converged
     std::vector<double> norm(const Vecs &u) {
         auto d = dot(u, u);
         std::vector<double> n(R);
-        for (int r = 0; r < R; ++r) n[r] = std::sqrt(std::max(0.0, d[r].real()));
+        for (int r = 0; r < R; ++r)
+            n[r] = std::isfinite(d[r].real()) && std::isfinite(d[r].imag())
+                       ? std::sqrt(std::max(0.0, d[r].real()))
+                       : std::numeric_limits<double>::quiet_NaN();
         return n;
     }
     // y = beta y + a_r x
@@ -1119,6 +1173,27 @@ struct SolveCtx {
     }
 };
 
+// Largest element, NaN if any element is NaN (std::max_element skips NaN).
+static double max_nan(const std::vector<double> &v) {
+    double m = v.empty() ? 0.0 : -std::numeric_limits<double>::infinity();
+    for (double x : v) {
+        if (std::isnan(x)) return x;
+        m = std::max(m, x);
+    }
+    return m;
+}
+
+// ||r|| / ||b||; NaN when either is not finite (0 for a zero right-hand side)
+static double rel_res(double rn, double bn) {
+    if (!std::isfinite(rn) || !std::isfinite(bn)) return std::numeric_limits<double>::quiet_NaN();
+    return bn > 0 ? rn / bn : 0.0;
+}
+
+// Hessenberg pivots below this (after the Givens rotation) mean that (A - omega), right-
+// preconditioned by the dressed diagonal (D - omega)^-1 (which scales it to O(1)), maps a
+// unit direction of the Krylov space to zero to working precision: singular at that frequency.
+constexpr double kSingularPivot = 1e-12;
+
 // GMRES on (A - omega) x = b starting from x (in/out).  Stops when every
 // right-hand side reaches ||r|| <= tol ||b|| or after max_apply operator
 // applications.  Returns per-RHS relative residual estimates.
@@ -1127,121 +1202,253 @@ static bool verbose() {
     return v != 0;
 }
 
-std::vector<double> gmres(SolveCtx &S, const Vecs &b, const Vecs &x, int precision, double tol, int max_apply,
-                          int m, std::vector<Vecs> &V, const Vecs &w, const Vecs &z, bool x_is_zero) {
-    const int R = S.R;
-    auto bn = S.norm(b);
+// Device workspace of the batched GMRES: a contiguous Krylov basis (vector i of right-hand side r
+// at (Vs + (i R + r) n1, Vd + (i R + r) n2)), the Hessenberg/Givens state of every right-hand
+// side, the Gram-Schmidt coefficients and a pinned status buffer.  With graphs on, every Arnoldi
+// step j is captured once (preconditioner, sigma, two Gram-Schmidt passes, norm, rotation,
+// normalisation, status copy) and replayed for later cycles and refinement steps of the same solve.
+struct GmresWork {
+    int R = 0, m = 0;
+    i64 n1 = 0, n2 = 0;
+    void *Vs = nullptr, *Vd = nullptr;
+    GmresState g{};
+    void *h1 = nullptr, *h2 = nullptr, *hn2 = nullptr, *beta2 = nullptr, *y = nullptr, *part = nullptr;
+    void *ones = nullptr, *minus = nullptr;    // R complex 1 and -1 (axpby coefficients)
+    void *stat_d = nullptr;                    // [3R] device status
+    double *stat_h = nullptr;                  // [3R] pinned host status
+    // (precision, j, tolerance) -> captured Arnoldi step (the tolerance is baked into the rotation
+    // kernel's arguments, and the inner tolerance of the mixed path changes between refinements)
+    std::map<std::tuple<int, int, double>, hipGraphExec_t> steps;
+    Vecs vec(int i) const {
+        Vecs v;
+        v.s = (char *)Vs + (size_t)i * R * n1 * 16;
+        v.d = (char *)Vd + (size_t)i * R * n2 * 16;
+        return v;
+    }
+    ~GmresWork() {
+        for (auto &kv : steps) (void)hipGraphExecDestroy(kv.second);
+        if (stat_h) (void)hipHostFree(stat_h);
+    }
+};
+
+void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, i64 n2, hipStream_t st) {
+    DevMem &M = c->solmem;
+    W.R = R; W.m = m; W.n1 = n1; W.n2 = n2;
+    W.Vs = M.get((size_t)(m + 1) * R * n1 * 16);
+    W.Vd = M.get((size_t)(m + 1) * R * n2 * 16);
+    W.g.R = R;
+    W.g.m = m;
+    W.g.H = (double2 *)M.get((size_t)R * (m + 1) * m * 16);
+    W.g.cs = (double2 *)M.get((size_t)R * m * 16);
+    W.g.sn = (double2 *)M.get((size_t)R * m * 16);
+    W.g.g = (double2 *)M.get((size_t)R * (m + 1) * 16);
+    W.g.scal = (double2 *)M.get((size_t)R * 16);
+    W.g.bn = (double *)M.get((size_t)R * 8);
+    W.g.rel = (double *)M.get((size_t)R * 8);
+    W.g.act = (int *)M.get((size_t)R * 4);
+    W.g.kr = (int *)M.get((size_t)R * 4);
+    W.g.sing = (int *)M.get((size_t)R * 4);
+    W.h1 = M.get((size_t)R * (m + 1) * 16);
+    W.h2 = M.get((size_t)R * (m + 1) * 16);
+    W.hn2 = M.get((size_t)R * 16);
+    W.beta2 = M.get((size_t)R * 16);
+    W.y = M.get((size_t)R * (m + 1) * 16);
+    W.part = M.get((size_t)R * (m + 1) * multidot_blocks(n1 + n2) * 16);   // [R][m+1][blocks] partial sums
+    W.ones = M.get((size_t)R * 16);
+    W.minus = M.get((size_t)R * 16);
+    W.stat_d = M.get((size_t)R * 3 * 8);
+    if (g_dry_run) return;
+    HIPCHK(hipHostMalloc((void **)&W.stat_h, (size_t)R * 3 * 8, hipHostMallocDefault));
+    std::vector<cd> one(R, cd(1.0, 0.0)), mone(R, cd(-1.0, 0.0));
+    HIPCHK(hipMemcpyAsync(W.ones, one.data(), (size_t)R * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(W.minus, mone.data(), (size_t)R * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// Status of every right-hand side after the last cycle start or Arnoldi step (one host sync).
+struct GmresStatus {
+    std::vector<double> rel;
+    std::vector<int> act, sing;
+};
+GmresStatus gmres_read(const GmresWork &W, hipStream_t st, bool launch = true) {
+    if (launch) {
+        HIPCHK(gmres_status(W.g, (double *)W.stat_d, st));
+        HIPCHK(hipMemcpyAsync(W.stat_h, W.stat_d, (size_t)W.R * 3 * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    GmresStatus s;
+    s.rel.resize(W.R);
+    s.act.resize(W.R);
+    s.sing.resize(W.R);
+    for (int r = 0; r < W.R; ++r) {
+        s.rel[r] = W.stat_h[3 * r];
+        s.act[r] = (int)W.stat_h[3 * r + 1];
+        s.sing[r] = (int)W.stat_h[3 * r + 2];
+    }
+    return s;
+}
+
+// One Arnoldi step j on the device: z = M^-1 V_j, w = (A - omega) z, classical Gram-Schmidt
+// against V_0..V_j twice (the second pass restores orthogonality lost to rounding), the column
+// of H and its Givens rotation (k_gmres_step), V_{j+1} = w / h_{j+1,j}, and the status words
+// copied to the pinned host buffer.  Right-hand sides that stopped keep their basis (masked).
+hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double tol, const Vecs &w, const Vecs &z,
+                        bool eager_sigma) {
+    lrcc_ctx *c = S.c;
+    const int R = W.R;
+    const i64 n1 = W.n1, n2 = W.n2;
+    const Vecs vj = W.vec(j), vn = W.vec(j + 1);
+    const State<double> &T = c->s64;
+    hipStream_t st = S.st;
+    hipError_t e;
+    e = precond(z.s, z.d, vj.s, vj.d, (const double *)T.d_o1, (const double *)T.d_v1, (const double *)T.d_o2,
+                (const double *)T.d_v2, S.omega, c->km, R, c->no, c->nv, st);
+    if (e != hipSuccess) return e;
+    Program *p = sigma_program(c, precision, R, S.adjoint);
+    c->io_x1 = z.s; c->io_x2 = z.d; c->io_y1 = w.s; c->io_y2 = w.d; c->io_omega = S.omega;
+    e = eager_sigma ? run_sigma(c, p, st) : p->run(st);
+    if (e != hipSuccess) return e;
+    for (int pass = 0; pass < 2; ++pass) {
+        void *h = pass == 0 ? W.h1 : W.h2;
+        e = multidot(W.Vs, W.Vd, w.s, w.d, R, n1, n2, j + 1, W.part, h, W.m + 1, st);
+        if (e != hipSuccess) return e;
+        e = multiaxpy(w.s, w.d, W.Vs, W.Vd, h, W.m + 1, -1.0, W.g.act, 1.0, R, n1, n2, j + 1, st);
+        if (e != hipSuccess) return e;
+    }
+    e = selfdot(w.s, w.d, R, n1, n2, W.part, W.hn2, st);
+    if (e != hipSuccess) return e;
+    e = gmres_step(W.g, j, W.h1, W.h2, W.hn2, tol, precision == LRCC_FP64 ? kSingularPivot : 0.0, st);
+    if (e != hipSuccess) return e;
+    e = batched_axpby(vn.s, w.s, W.g.scal, 0.0, R, n1, st);
+    if (e != hipSuccess) return e;
+    e = batched_axpby(vn.d, w.d, W.g.scal, 0.0, R, n2, st);
+    if (e != hipSuccess) return e;
+    e = gmres_status(W.g, (double *)W.stat_d, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(W.stat_h, W.stat_d, (size_t)R * 3 * 8, hipMemcpyDeviceToHost, st);
+}
+
+// GMRES on (A - omega) x = b starting from x (in/out), all right-hand sides advanced together
+// (each step one multi-RHS sigma launch), the Krylov state on the device.  Stops when every
+// right-hand side reaches ||r|| <= tol ||b|| (or stopped: singular, non-finite) or after
+// max_apply operator applications.  Returns per-RHS relative residual estimates.
+std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &x, int precision, double tol,
+                          int max_apply, const Vecs &w, const Vecs &z, bool x_is_zero,
+                          std::vector<bool> *singular = nullptr) {
+    lrcc_ctx *c = S.c;
+    const int R = S.R, m = W.m;
+    const i64 n1 = S.n1, n2 = S.n2;
+    hipStream_t st = S.st;
+    // ||b|| once; the singular flags start clear
+    {
+        auto bn = S.norm(b);
+        HIPCHK(hipMemcpyAsync(W.g.bn, bn.data(), (size_t)R * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(W.g.sing, 0, (size_t)R * sizeof(int), st));   // never inside a captured step
+        HIPCHK(hipStreamSynchronize(st));
+    }
     std::vector<double> rel(R, 0.0);
+    std::vector<bool> sing(R, false);
     int applied = 0;
     bool first = true;
+    auto done = [&]() {
+        if (singular) *singular = sing;
+        return rel;
+    };
+    const Vecs v0 = W.vec(0);
     while (true) {
-        // r = b - A x  (into V[0])
-        if (first && x_is_zero) {
-            S.copy(V[0], b);
-        } else {
+        // r = b - A x into V_0, its norm, the cycle's initial state on the device
+        HIPCHK(hipMemcpyAsync(v0.s, b.s, (size_t)R * n1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(v0.d, b.d, (size_t)R * n2 * 16, hipMemcpyDeviceToDevice, st));
+        if (!(first && x_is_zero)) {
             S.op(w, x, precision);
             ++applied;
-            S.copy(V[0], b);
-            S.axpby(V[0], w, std::vector<cd>(R, cd(-1.0, 0.0)), 1.0);
+            HIPCHK(batched_axpby(v0.s, w.s, W.minus, 1.0, R, n1, st));
+            HIPCHK(batched_axpby(v0.d, w.d, W.minus, 1.0, R, n2, st));
         }
         first = false;
-        auto beta = S.norm(V[0]);
-        bool all = true;
+        HIPCHK(selfdot(v0.s, v0.d, R, n1, n2, W.part, W.beta2, st));
+        HIPCHK(gmres_init(W.g, W.beta2, tol, st));
+        GmresStatus gs = gmres_read(W, st);
+        bool all = true, nonfinite = false;
         for (int r = 0; r < R; ++r) {
-            rel[r] = bn[r] > 0 ? beta[r] / bn[r] : 0.0;
-            if (rel[r] > tol) all = false;
+            rel[r] = gs.rel[r];
+            sing[r] = gs.sing[r] != 0;
+            if (!(rel[r] <= tol) && !sing[r]) all = false;
+            if (std::isnan(rel[r])) nonfinite = true;
         }
         if (verbose())
             std::fprintf(stderr, "[lrcc] gmres %s%s R=%d applied=%d max rel residual %.3e\n",
                          precision == LRCC_FP64 ? "fp64" : "fp32", S.adjoint ? " adjoint" : "", R, applied,
-                         *std::max_element(rel.begin(), rel.end()));
-        if (all || applied >= max_apply) return rel;
-        std::vector<cd> inv(R);
-        for (int r = 0; r < R; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
-        S.axpby(V[0], V[0], inv, 0.0);
-        // per-RHS Hessenberg with Givens rotations
-        std::vector<std::vector<cd>> H(R, std::vector<cd>((m + 1) * m, 0.0));
-        std::vector<std::vector<cd>> g(R, std::vector<cd>(m + 1, 0.0)), cs(R, std::vector<cd>(m)), sn(R, std::vector<cd>(m));
-        std::vector<int> kr(R, 0);           // Arnoldi steps that count per RHS
-        std::vector<bool> act(R, true);
-        for (int r = 0; r < R; ++r) {
-            g[r][0] = beta[r];
-            if (rel[r] <= tol || beta[r] == 0) act[r] = false;
-        }
+                         max_nan(rel));
+        // a non-finite residual cannot recover: stop at once (the caller reports it)
+        if (all || nonfinite || applied >= max_apply) return done();
+        HIPCHK(batched_axpby(v0.s, v0.s, W.g.scal, 0.0, R, n1, st));
+        HIPCHK(batched_axpby(v0.d, v0.d, W.g.scal, 0.0, R, n2, st));
         int j = 0;
         for (; j < m && applied < max_apply; ++j) {
-            S.prec(z, V[j]);
-            S.op(w, z, precision);
-            ++applied;
-            for (int i = 0; i <= j; ++i) {
-                auto h = S.dot(V[i], w);
-                std::vector<cd> mh(R);
-                for (int r = 0; r < R; ++r) {
-                    H[r][i * m + j] = h[r];
-                    mh[r] = act[r] ? -h[r] : 0.0;
+            // graph replay of the step once the sigma program has been tuned (the first run of a
+            // program may autotune, which times launches and cannot be captured)
+            Program *p = sigma_program(c, precision, R, S.adjoint);
+            const bool graph = c->use_graphs && st != nullptr && (!c->autotune || p->tuned) && !c->prof.on;
+            if (graph) {
+                auto key = std::make_tuple(precision, j, tol);
+                auto it = W.steps.find(key);
+                if (it == W.steps.end()) {
+                    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    hipError_t er = arnoldi_step(S, W, j, precision, tol, w, z, false);
+                    hipGraph_t gr = nullptr;
+                    hipError_t ee = hipStreamEndCapture(st, &gr);
+                    HIPCHK(er);
+                    HIPCHK(ee);
+                    hipGraphExec_t ex = nullptr;
+                    hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    HIPCHK(ei);
+                    it = W.steps.emplace(key, ex).first;
                 }
-                S.axpby(w, V[i], mh, 1.0);
+                HIPCHK(hipGraphLaunch(it->second, st));
+            } else {
+                HIPCHK(arnoldi_step(S, W, j, precision, tol, w, z, true));
             }
-            auto hn = S.norm(w);
-            std::vector<cd> sc(R);
-            for (int r = 0; r < R; ++r) {
-                H[r][(j + 1) * m + j] = hn[r];
-                sc[r] = (act[r] && hn[r] > 0) ? 1.0 / hn[r] : 0.0;
-            }
-            S.axpby(V[j + 1], w, sc, 0.0);
+            (precision == LRCC_FP64 ? S.nsig64 : S.nsig32)++;
+            S.rhs_sig += R;
+            ++applied;
+            GmresStatus gs2 = gmres_read(W, st, false);
             bool any = false;
             for (int r = 0; r < R; ++r) {
-                if (!act[r]) continue;
-                // apply previous rotations to column j, then a new one
-                for (int i = 0; i < j; ++i) {
-                    cd a = H[r][i * m + j], bb = H[r][(i + 1) * m + j];
-                    H[r][i * m + j] = std::conj(cs[r][i]) * a + std::conj(sn[r][i]) * bb;
-                    H[r][(i + 1) * m + j] = -sn[r][i] * a + cs[r][i] * bb;
-                }
-                cd a = H[r][j * m + j], bb = H[r][(j + 1) * m + j];
-                double den = std::sqrt(std::norm(a) + std::norm(bb));
-                cs[r][j] = den > 0 ? a / den : 1.0;
-                sn[r][j] = den > 0 ? bb / den : 0.0;
-                H[r][j * m + j] = den;
-                H[r][(j + 1) * m + j] = 0.0;
-                cd gj = g[r][j];
-                g[r][j] = std::conj(cs[r][j]) * gj;
-                g[r][j + 1] = -sn[r][j] * gj;
-                kr[r] = j + 1;
-                rel[r] = bn[r] > 0 ? std::abs(g[r][j + 1]) / bn[r] : 0.0;
-                if (rel[r] <= tol || hn[r] == 0) act[r] = false;
-                else any = true;
+                if (gs2.sing[r]) sing[r] = true;
+                rel[r] = gs2.rel[r];
+                any = any || gs2.act[r];
             }
             if (!any) { ++j; break; }
         }
-        // x += M^-1 sum_i y_i V_i
-        std::vector<std::vector<cd>> y(R);
-        int kmax = 0;
-        for (int r = 0; r < R; ++r) {
-            const int k = kr[r];
-            kmax = std::max(kmax, k);
-            y[r].assign(m, 0.0);
-            for (int i = k - 1; i >= 0; --i) {
-                cd acc = g[r][i];
-                for (int l = i + 1; l < k; ++l) acc -= H[r][i * m + l] * y[r][l];
-                y[r][i] = H[r][i * m + i] != cd(0.0) ? acc / H[r][i * m + i] : 0.0;
-            }
-        }
-        S.zero(w);
-        for (int i = 0; i < kmax; ++i) {
-            std::vector<cd> yi(R);
-            for (int r = 0; r < R; ++r) yi[r] = y[r][i];
-            S.axpby(w, V[i], yi, 1.0);
-        }
+        // x += M^-1 sum_i y_i V_i with y = H^-1 g per right-hand side
+        HIPCHK(gmres_solve(W.g, W.y, st));
+        HIPCHK(multiaxpy(w.s, w.d, W.Vs, W.Vd, W.y, m + 1, 1.0, nullptr, 0.0, R, n1, n2, j, st));
         S.prec(z, w);
-        S.axpby(x, z, std::vector<cd>(R, cd(1.0, 0.0)), 1.0);
+        HIPCHK(batched_axpby(x.s, z.s, W.ones, 1.0, R, n1, st));
+        HIPCHK(batched_axpby(x.d, z.d, W.ones, 1.0, R, n2, st));
         x_is_zero = false;
-        if (applied >= max_apply) return rel;  // estimates from the rotations
+        if (applied >= max_apply) {
+            HIPCHK(hipStreamSynchronize(st));
+            return done();  // estimates from the rotations
+        }
+        bool open = false;
+        for (int r = 0; r < R; ++r) open = open || !sing[r];
+        if (!open) {
+            HIPCHK(hipStreamSynchronize(st));
+            return done();
+        }
     }
 }
 
+// Solve (A - omega_r) x_r = b_r (or the transpose).  x holds the initial guess; x_is_zero
+// saves the product with a zero guess.  On return rep.converged is 1 only if every relative
+// residual is finite and <= tol; *singular (if given) is set when FP64 GMRES met a zero
+// pivot on a right-hand side that did not converge.
 void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, const Vecs &x,
-                    const lrcc_solve_opts &o, lrcc_solve_report &rep, hipStream_t st, bool adjoint = false) {
+                    const lrcc_solve_opts &o, lrcc_solve_report &rep, hipStream_t st, bool adjoint = false,
+                    bool x_is_zero = false, bool *singular = nullptr) {
     auto t0 = std::chrono::steady_clock::now();
     SolveCtx S;
     S.c = c; S.R = R; S.st = st; S.omega = omega_dev; S.adjoint = adjoint;
@@ -1259,59 +1466,81 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
         const long long fit = (long long)(0.85 * (double)fr / (double)per) - 3 - (mixed ? 2 : 0);
         m = (int)std::max(4LL, std::min(60LL, fit));
     }
+    m = std::min(m, 60);   // the Gram-Schmidt kernels take at most 64 basis vectors
     const int nvec = (m + 1) + 2 + (mixed ? 2 : 0);
-    const size_t need = per * nvec + (size_t)R * (dot_blocks(S.n2) + 4) * 16 * 2;
+    const size_t need = per * nvec + (size_t)R * (dot_blocks(S.n2) + 4) * 16 * 2 +
+                        (size_t)R * ((m + 1) * multidot_blocks(S.n1 + S.n2) + 4 * (m + 2) + (size_t)(m + 1) * m) * 16;
     if (o.mem_cap_bytes > 0 && need > (size_t)o.mem_cap_bytes)
         throw LrccError(LRCC_E_OOM, "solver work vectors exceed the memory cap");
-    std::vector<Vecs> V(m + 1);
+    GmresWork W;
+    gmres_alloc(c, W, R, m, S.n1, S.n2, st);
     auto mk = [&]() { Vecs v; v.s = c->solmem.get((size_t)R * S.n1 * 16); v.d = c->solmem.get((size_t)R * S.n2 * 16); return v; };
-    for (auto &v : V) v = mk();
     Vecs w = mk(), z = mk();
     S.part = c->solmem.get((size_t)R * dot_blocks(S.n2) * 16);
     S.dout = c->solmem.get((size_t)R * 16);
     S.alpha = c->solmem.get((size_t)R * 16);
     std::vector<double> rel;
+    std::vector<bool> sing;
     rep = lrcc_solve_report{};
     if (!mixed) {
-        rel = gmres(S, b, x, LRCC_FP64, o.tol, o.max_iter, m, V, w, z, false);
+        rel = gmres(S, W, b, x, LRCC_FP64, o.tol, o.max_iter, w, z, x_is_zero, &sing);
         rep.outer = 1;
     } else {
         Vecs r = mk(), dx = mk();
         auto bn = S.norm(b);
         for (int it = 0; it < o.max_outer; ++it) {
-            // FP64 residual r = b - (A - w) x
-            S.op(w, x, LRCC_FP64);
+            // FP64 residual r = b - (A - w) x (r = b for a zero first guess)
             S.copy(r, b);
-            S.axpby(r, w, std::vector<cd>(R, cd(-1.0, 0.0)), 1.0);
+            if (it > 0 || !x_is_zero) {
+                S.op(w, x, LRCC_FP64);
+                S.axpby(r, w, std::vector<cd>(R, cd(-1.0, 0.0)), 1.0);
+            }
             auto rn = S.norm(r);
             rel.assign(R, 0.0);
-            bool all = true;
+            bool all = true, nonfinite = false;
             for (int q = 0; q < R; ++q) {
-                rel[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
-                if (rel[q] > o.tol) all = false;
+                rel[q] = rel_res(rn[q], bn[q]);
+                if (!(rel[q] <= o.tol)) all = false;
+                if (std::isnan(rel[q])) nonfinite = true;
             }
             rep.outer = it + 1;
+            const double worst = max_nan(rel);
             if (verbose())
-                std::fprintf(stderr, "[lrcc] refinement step %d: max rel residual %.3e (krylov %d)\n", it,
-                             *std::max_element(rel.begin(), rel.end()), m);
-            if (all) break;
+                std::fprintf(stderr, "[lrcc] refinement step %d: max rel residual %.3e (krylov %d)\n", it, worst, m);
+            if (all || nonfinite) break;
             // FP32 correction solve (A - w) dx = r to inner_tol, or only as far as the
             // outer tolerance still needs (with a 10x margin) on the last step
-            const double worst = *std::max_element(rel.begin(), rel.end());
             const double itol = std::max(o.inner_tol, std::min(0.5, 0.1 * o.tol / worst));
             S.zero(dx);
-            gmres(S, r, dx, LRCC_FP32, itol, 4 * m, m, V, w, z, true);
+            gmres(S, W, r, dx, LRCC_FP32, itol, 4 * m, w, z, true);
             S.axpby(x, dx, std::vector<cd>(R, cd(1.0, 0.0)), 1.0);
         }
     }
     HIPCHK(hipStreamSynchronize(st));
-    c->solmem.release();   // the Krylov space is not needed after the solve
+    c->solmem.release();   // the Krylov space is not needed after the solve (W's captured steps go with it)
     rep.sigma_fp64 = S.nsig64;
     rep.sigma_fp32 = S.nsig32;
     rep.rhs_sigmas = S.rhs_sig;
-    rep.max_rel_residual = rel.empty() ? 0.0 : *std::max_element(rel.begin(), rel.end());
-    rep.converged = rep.max_rel_residual <= o.tol;
+    rep.max_rel_residual = max_nan(rel);
+    rep.converged = rep.max_rel_residual <= o.tol;   // false for NaN
+    if (singular) {
+        *singular = false;
+        for (size_t q = 0; q < sing.size(); ++q) *singular = *singular || (sing[q] && !(rel[q] <= o.tol));
+    }
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Status for an unconverged solve: LRCC_E_SINGULAR after a zero pivot, else LRCC_E_NOCONV,
+// with the residual (or its non-finiteness) in the message.
+[[noreturn]] void throw_unconverged(const char *what, const lrcc_solve_report &rep, bool singular) {
+    if (singular)
+        throw LrccError(LRCC_E_SINGULAR, std::string(what) + ": the response operator is singular at this "
+                                                             "frequency (zero Krylov pivot)");
+    if (std::isnan(rep.max_rel_residual))
+        throw LrccError(LRCC_E_NOCONV, std::string(what) + ": non-finite residual (NaN or Inf in the "
+                                                           "right-hand side or the iterates)");
+    throw LrccError(LRCC_E_NOCONV, std::string(what) + " did not converge: relative residual " +
+                                       std::to_string(rep.max_rel_residual));
 }
 
 void default_opts(lrcc_solve_opts &o) {
@@ -1521,6 +1750,16 @@ void lambda_product(lrcc_ctx *c, const Vecs &p0, hipStream_t st) {
     HIPCHK(adj->run(st));
 }
 
+// The density programs' amplitude copies are filled from the context's amplitudes by
+// whole-array copies: refuse a mismatch (a state left from another shape) instead of
+// writing past them.
+void check_density_shape(lrcc_ctx *c) {
+    const State<double> &S = c->s64;
+    if (c->dT1.count() != S.t1.count() || c->dT2.count() != S.t2.count() || c->dT1.nk != c->nk ||
+        c->dT1.no != c->no || c->dT1.nv != c->nv)
+        throw LrccError(LRCC_E_STATE, "density buffers do not match the current amplitude shape");
+}
+
 // One-body density of R amplitude-space vectors a (caller layout, per-cell
 // normalisation) with respect to the perturbation operator of Eq. rhs:
 //   D_r[k][p][q] = d <a_r, xi^V> / d V[k][p][q]     (pairing sum a1 xi1 + 1/4 sum a2 xi2)
@@ -1535,6 +1774,7 @@ Program *dens_program(lrcc_ctx *c, int R) {
         c->dT1 = alloc_kt<double>(c, c->gmem, "ov");
         c->dT2 = alloc_kt<double>(c, c->gmem, "oovv");
     }
+    check_density_shape(c);
     auto mem = std::make_unique<DevMem>();
     DevMem &m = *mem;
     auto P = std::make_unique<Program>();
@@ -1641,8 +1881,12 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         // corrections only add refinement steps here)
         lrcc_solve_opts ol = o;
         ol.precision = LRCC_FP64;
-        solve_response(c, 1, (const double *)zero_om, b, lam, ol, r1, st, true);
-        if (!r1.converged) throw LrccError(LRCC_E_NOCONV, "lambda equations did not converge");
+        bool sing = false;
+        solve_response(c, 1, (const double *)zero_om, b, lam, ol, r1, st, true, true, &sing);
+        if (!r1.converged) {
+            rep = r1;
+            throw_unconverged("lambda equations", r1, sing);
+        }
         c->lam_valid = true;
     }
     phase("lambda");
@@ -1669,10 +1913,32 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     HIPCHK(hipMemcpy(dom, om.data(), R * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(X.s, 0, (size_t)R * n1 * 16));
     HIPCHK(hipMemset(X.d, 0, (size_t)R * n2 * 16));
+    // initial guesses (lrcc_set_guess) for the solved axes and frequencies; all are consumed
+    bool guessed = false;
+    for (const auto &gs : c->guess) {
+        const int ax = gs.first[0], j = gs.first[1], sg = gs.first[2];
+        const int a = (int)(std::find(axes.begin(), axes.end(), ax) - axes.begin());
+        if (a >= nax || j >= nfreq) continue;
+        const Vecs dst = sub(X, (j * 2 + (sg > 0 ? 0 : 1)) * nax + a);
+        const char *src = (const char *)gs.second->ptrs[0];
+        HIPCHK(hipMemcpyAsync(dst.s, src, (size_t)n1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(dst.d, src + (size_t)n1 * 16, (size_t)n2 * 16, hipMemcpyDeviceToDevice, st));
+        guessed = true;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    c->guess.clear();
     lrcc_solve_report r2{};
-    solve_response(c, R, (const double *)dom, B, X, o, r2, st);
+    bool sing = false;
+    solve_response(c, R, (const double *)dom, B, X, o, r2, st, false, !guessed, &sing);
     c->nrhs_sol = R;
-    if (!r2.converged) throw LrccError(LRCC_E_NOCONV, "response equations did not converge");
+    if (!r2.converged) {
+        rep = r2;
+        rep.sigma_fp64 += r1.sigma_fp64;
+        rep.sigma_fp32 += r1.sigma_fp32;
+        rep.rhs_sigmas += r1.rhs_sigmas;
+        c->nfreq = 0;   // no polarizability from unconverged amplitudes
+        throw_unconverged("response equations", r2, sing);
+    }
     // eta^X = A_X^T lambda + (X_ov, 0)
     std::vector<Vecs> eta(nax);
     for (int a = 0; a < nax; ++a) {
@@ -1798,8 +2064,9 @@ void alpha_lambda_bar(lrcc_ctx *c, const lrcc_solve_opts &o, double *out, lrcc_s
     HIPCHK(hipMemcpy(dom, om.data(), R * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(Lb.s, 0, (size_t)R * n1 * 16));
     HIPCHK(hipMemset(Lb.d, 0, (size_t)R * n2 * 16));
-    solve_response(c, R, (const double *)dom, B, Lb, o, rep, st, true);
-    if (!rep.converged) throw LrccError(LRCC_E_NOCONV, "perturbed lambda equations did not converge");
+    bool sing = false;
+    solve_response(c, R, (const double *)dom, B, Lb, o, rep, st, true, true, &sing);
+    if (!rep.converged) throw_unconverged("perturbed lambda equations", rep, sing);
     std::vector<double> al((size_t)nfreq * 9 * 2, 0.0);
     for (int j = 0; j < nfreq; ++j)
         for (int x = 0; x < nax; ++x)
@@ -1892,14 +2159,16 @@ void alpha_dip_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, 
     HIPCHK(hipMemset(A.s, 0, (size_t)nb * n1 * 16));
     HIPCHK(hipMemset(A.d, 0, (size_t)nb * n2 * 16));
     lrcc_solve_report r{};
-    solve_response(c, nb, (const double *)dom, B, A, o, r, st, true);
-    if (!r.converged) throw LrccError(LRCC_E_NOCONV, "adjoint response equations did not converge");
+    bool sing = false;
+    solve_response(c, nb, (const double *)dom, B, A, o, r, st, true, true, &sing);
+    if (!r.converged) throw_unconverged("adjoint response equations", r, sing);
     // densities: D_xi of the adjoint vectors at T, D_eta of the response vectors
     State<double> &S = c->s64;
     const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
     const size_t nd = (size_t)nk * n * n;
     void *dd = tmp.get((size_t)nb * nd * 16);
     Program *dn = dens_program(c, nb), *d1 = dens_program(c, 1);   // (allocate dT1, dT2 on first use)
+    check_density_shape(c);
     HIPCHK(hipMemcpyAsync(c->dT1.p, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(c->dT2.p, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
     c->io_x1 = A.s; c->io_x2 = A.d; c->io_y1 = dd;
@@ -1966,6 +2235,7 @@ void alpha_dip_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, 
 //
 // Shifted amplitudes T + sx x + sy y into the density program's copy (crystal T2).
 void dens_shift(lrcc_ctx *c, SolveCtx &D, const Vecs *x, double sx, const Vecs *y, double sy, hipStream_t st) {
+    check_density_shape(c);
     State<double> &S = c->s64;
     const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
     const int nk = c->nk;
@@ -2069,8 +2339,19 @@ void omega2_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &x, const Vecs &y, const
 //            + <lambda, dOmega''[t^X(-w), t^Y(w)]>,     dg = (df_ov, 0),
 // where <u, dA t> = d/de D_xi(u; T + e t) . df and the last term is the mixed
 // second derivative of D_xi(lambda; .) . df.  g(-w) likewise, conjugated.
-void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, double *out) {
-    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
+// The adjoint vectors of a polarizability gradient at frequency index j (shared by the Fock and
+// Cholesky gradients): the four transpose solutions
+//   A[0] = (A + w)^-T (eta^Y + F(., t^Y(w))),   A[1] = (A - w)^-T (eta^Y + F(., t^Y(-w))),
+//   A[2] = (A - w)^-T (eta^X + F(., t^X(-w))),  A[3] = (A + w)^-T (eta^X + F(., t^X(w))),
+// and the lambda sensitivities Z[sg] = A^-1 w(sg), w(+) = Omega''[t^X(-w), t^Y(w)] + A_X t^Y(w)
+// + A_Y t^X(-w) (w(-) with w -> -w).  Allocated in tmp; D is a one-vector dot context.
+struct GradAdjoints {
+    Vecs A, Z;
+    int ax = 0, ay = 0, nax = 0;
+};
+
+GradAdjoints grad_adjoints(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, DevMem &tmp, SolveCtx &D) {
+    const int nk = c->nk, no = c->no, nv = c->nv;
     const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
     const auto &axes = c->axes;
     const int nax = (int)axes.size();
@@ -2083,24 +2364,23 @@ void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o,
         throw LrccError(LRCC_E_STATE, "lrcc_solve must precede the gradient");
     hipStream_t st = c->own_stream;
     const double w = c->last_omega[j];
-    DevMem tmp;
     auto vec = [&](int R) { Vecs v; v.s = tmp.get((size_t)R * n1 * 16); v.d = tmp.get((size_t)R * n2 * 16); return v; };
     auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
     Vecs sol{c->sol1, c->sol2};
     auto tsol = [&](int sg, int a) { return sub(sol, (j * 2 + sg) * nax + a); };  // sg 0: +w, 1: -w
-    SolveCtx D;
     D.c = c; D.R = 1; D.n1 = n1; D.n2 = n2; D.st = st;
     D.part = tmp.get((size_t)dot_blocks(n2) * 16 * 2);
     D.dout = tmp.get(32);
     D.alpha = tmp.get(32);
     (void)dens_program(c, 1);   // allocates the density program's amplitude copy
-    // transpose right-hand sides as in the dipole gradient (all four: X and Y enter symmetrically)
-    //   0: eta^Y + F(., t^Y(w)),  (A + w)^T      1: eta^Y + F(., t^Y(-w)), (A - w)^T
-    //   2: eta^X + F(., t^X(-w)), (A - w)^T      3: eta^X + F(., t^X(w)),  (A + w)^T
     Vecs tv[4] = {tsol(0, ay), tsol(1, ay), tsol(1, ax), tsol(0, ax)};
     const bool same = X == Y;
     const double wsolve[4] = {-w, w, w, -w};
-    Vecs B = vec(4), A = vec(4), W = vec(2), Z = vec(2);
+    GradAdjoints G;
+    G.ax = ax; G.ay = ay; G.nax = nax;
+    Vecs B = vec(4), W = vec(2);
+    G.A = vec(4);
+    G.Z = vec(2);
     {
         Vecs etaY = vec(1), etaX = same ? etaY : vec(1);
         eta_vector(c, Y, etaY, st);
@@ -2145,15 +2425,31 @@ void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o,
     void *dom = tmp.get(4 * 8), *zom = tmp.get(2 * 8);
     HIPCHK(hipMemcpy(dom, wsolve, 4 * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(zom, 0, 2 * 8));
-    HIPCHK(hipMemset(A.s, 0, (size_t)4 * n1 * 16));
-    HIPCHK(hipMemset(A.d, 0, (size_t)4 * n2 * 16));
-    HIPCHK(hipMemset(Z.s, 0, (size_t)2 * n1 * 16));
-    HIPCHK(hipMemset(Z.d, 0, (size_t)2 * n2 * 16));
+    HIPCHK(hipMemset(G.A.s, 0, (size_t)4 * n1 * 16));
+    HIPCHK(hipMemset(G.A.d, 0, (size_t)4 * n2 * 16));
+    HIPCHK(hipMemset(G.Z.s, 0, (size_t)2 * n1 * 16));
+    HIPCHK(hipMemset(G.Z.d, 0, (size_t)2 * n2 * 16));
     lrcc_solve_report r{};
-    solve_response(c, 4, (const double *)dom, B, A, o, r, st, true);
-    if (!r.converged) throw LrccError(LRCC_E_NOCONV, "adjoint response equations did not converge");
-    solve_response(c, 2, (const double *)zom, W, Z, o, r, st, false);
-    if (!r.converged) throw LrccError(LRCC_E_NOCONV, "lambda-sensitivity equations did not converge");
+    bool sing = false;
+    solve_response(c, 4, (const double *)dom, B, G.A, o, r, st, true, true, &sing);
+    if (!r.converged) throw_unconverged("adjoint response equations", r, sing);
+    solve_response(c, 2, (const double *)zom, W, G.Z, o, r, st, false, true, &sing);
+    if (!r.converged) throw_unconverged("lambda-sensitivity equations", r, sing);
+    return G;
+}
+
+void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, double *out) {
+    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    hipStream_t st = c->own_stream;
+    DevMem tmp;
+    SolveCtx D;
+    GradAdjoints GA = grad_adjoints(c, j, X, Y, o, tmp, D);
+    const int ax = GA.ax, ay = GA.ay, nax = GA.nax;
+    auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
+    Vecs sol{c->sol1, c->sol2};
+    auto tsol = [&](int sg, int a) { return sub(sol, (j * 2 + sg) * nax + a); };
+    const Vecs &A = GA.A, &Z = GA.Z;
     // densities
     const size_t nd = (size_t)nk * n * n;
     void *dd = tmp.get(nd * 16);
@@ -2184,6 +2480,491 @@ void alpha_fock_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o,
             for (int qq = 0; qq < n; ++qq)
                 g[((size_t)k * n + p) * n + qq] =
                     -0.5 / nk * (G[0][((size_t)k * n + p) * n + qq] + std::conj(G[1][((size_t)k * n + qq) * n + p]));
+    std::memcpy(out, g.data(), g.size() * 16);
+}
+
+// ---------------------------------------------------------------- gradient with respect to the Cholesky vectors
+// alpha depends on the two-electron integrals through the Jacobian, the multipliers and the energy.
+// With h any Hamiltonian parameter that enters the residual linearly (as f does) the derivative of
+// g(w) at fixed amplitudes is
+//   d g = dE''[tX(-w), tY(w)] + <lambda, dOmega''[tX(-w), tY(w)]> - <aY, dA tY(w)> - <aX, dA tX(-w)>
+//         - <lambda, dA z> + <db, z>,
+// (aX, aY, z as in the Fock gradient; b the right-hand side of the lambda equations).  Every term is
+// a contraction of the parameter cotangent of the sigma, Gamma(u, t; T) = d <u, A(T) t> / dh, or a
+// closed form in <ij||ab>: <u, dA t> = Gamma(u, t; T) . dh, and <lambda, dOmega''[x, y]> is the exact
+// 4-point derivative of Gamma(lambda, y; T + e x) in e (A is cubic in T).  Gamma is obtained in
+// three linear stages, all on the device: (1) the sigma's term list, run forward on t and backward on
+// u, gives the cotangents of the blocks it reads (integral classes, amplitude-dependent blocks, the
+// t1-dressed virtual Cholesky slices; the ladder's density D_ab,ef = sum_rij ubar_ijab dtau_ijef is
+// formed one momentum block at a time and contracted with the other slice at once, never stored
+// whole); (2) the amplitude-dependent blocks are linear in the integrals at fixed T, so their
+// cotangents flow back to the integral classes (at the amplitudes of the evaluation point); (3) the
+// classes are bilinear in the scaled Cholesky vectors, whose cotangents follow by transposed GEMMs.
+
+// Cotangent buffers (complex128): the amplitude-dependent blocks the sigma reads (cleared for every
+// evaluation point), the integral classes and the scaled Cholesky arrays (accumulated).
+struct HamBar {
+    DevMem mem;
+    KT fov, Fae, Fmi, Fme, Fg, Fbe, Fmj, Wp, Wbar, S, U, H, G2;
+    KT oooo, ooov, oovv, ovov, ovvo, ovvv, ovoo;
+    void *La = nullptr, *Lb = nullptr;           // [nk][nk][naux][v][v]
+    void *Ls = nullptr, *Lcs = nullptr;          // [nk][nk][naux][n][n]
+    i64 nl = 0, nlvv = 0;
+    std::vector<std::pair<void *, i64>> blocks, classes;   // (pointer, complex count) for clearing
+};
+
+void hambar_alloc(lrcc_ctx *c, HamBar &B) {
+    const State<double> &S = c->s64;
+    auto like = [&](KT &dst, const KT &src, std::vector<std::pair<void *, i64>> &list) {
+        dst = src;
+        dst.p = B.mem.get(src.count() * 16);
+        list.push_back({dst.p, src.count()});
+    };
+    like(B.fov, S.fov, B.blocks); like(B.Fae, S.Fae, B.blocks); like(B.Fmi, S.Fmi, B.blocks);
+    like(B.Fme, S.Fme, B.blocks); like(B.Fg, S.Fg, B.blocks); like(B.Fbe, S.Fbe, B.blocks);
+    like(B.Fmj, S.Fmj, B.blocks); like(B.Wp, S.Wp, B.blocks); like(B.Wbar, S.Wbar, B.blocks);
+    like(B.S, S.S, B.blocks); like(B.U, S.U, B.blocks); like(B.H, S.H, B.blocks); like(B.G2, S.G2, B.blocks);
+    like(B.oooo, c->g_oooo, B.classes); like(B.ooov, c->g_ooov, B.classes); like(B.oovv, c->g_oovv, B.classes);
+    like(B.ovov, c->g_ovov, B.classes); like(B.ovvo, c->g_ovvo, B.classes); like(B.ovvv, c->g_ovvv, B.classes);
+    like(B.ovoo, c->g_ovoo, B.classes);
+    B.nlvv = (i64)c->nk * c->nk * c->naux * c->nv * c->nv;
+    B.nl = (i64)c->nk * c->nk * c->naux * c->n * c->n;
+    B.La = B.mem.get(B.nlvv * 16);
+    B.Lb = B.mem.get(B.nlvv * 16);
+    B.blocks.push_back({B.La, B.nlvv});
+    B.blocks.push_back({B.Lb, B.nlvv});
+    B.Ls = B.mem.get(B.nl * 16);
+    B.Lcs = B.mem.get(B.nl * 16);
+    B.classes.push_back({B.Ls, B.nl});
+    B.classes.push_back({B.Lcs, B.nl});
+}
+
+void hambar_clear(const std::vector<std::pair<void *, i64>> &list, hipStream_t st) {
+    for (const auto &e : list) HIPCHK(zero_fill<double>(e.first, e.second, st));
+}
+
+// the cotangent buffer of a tensor the sigma reads, or null for amplitudes (t1, t2, tau)
+const KT *bar_of(lrcc_ctx *c, const HamBar &B, const KT &t) {
+    const State<double> &S = c->s64;
+    const std::pair<const void *, const KT *> map[] = {
+        {S.fov.p, &B.fov}, {S.Fae.p, &B.Fae}, {S.Fmi.p, &B.Fmi}, {S.Fme.p, &B.Fme}, {S.Fg.p, &B.Fg},
+        {S.Fbe.p, &B.Fbe}, {S.Fmj.p, &B.Fmj}, {S.Wp.p, &B.Wp}, {S.Wbar.p, &B.Wbar}, {S.S.p, &B.S},
+        {S.U.p, &B.U}, {S.H.p, &B.H}, {S.G2.p, &B.G2}, {c->g_oovv.p, &B.oovv}, {c->g_ooov.p, &B.ooov},
+        {c->g_ovov.p, &B.ovov}, {c->g_ovvv.p, &B.ovvv}};
+    for (const auto &m : map)
+        if (m.first == t.p) return m.second;
+    if (t.p == S.t1.p || t.p == S.t2.p || t.p == S.tau.p) return nullptr;
+    throw LrccError(LRCC_E_STATE, "parameter gradient: the sigma reads a block without a cotangent");
+}
+
+// One complex128 GEMM job: C[m][n] (+)= alpha sum_k A[m][k] B[k][n] with two-level index splits.
+void gemm1(Program &P, const void *A, i64 offA, i64 sizeA, const void *Bm, i64 offB, i64 sizeB, void *C, i64 offC,
+           i64 sizeC, Split sm, Strides Am, Strides Cm, Split sn, Strides Bn, Strides Cn, Split sk, Strides Ak,
+           Strides Bk, double alpha, int beta) {
+    GemmArgs g{};
+    g.shape = -1;
+    g.A = A;
+    g.B = Bm;
+    g.C = C;
+    g.M = sm.d1 * sm.d2;
+    g.N = sn.d1 * sn.d2;
+    g.K = sk.d1 * sk.d2;
+    g.sm = sm; g.Am = Am; g.Cm = Cm;
+    g.sn = sn; g.Bn = Bn; g.Cn = Cn;
+    g.sk = sk; g.Ak = Ak; g.Bk = Bk;
+    g.aMfast = 1;
+    g.bNfast = 1;
+    g.alpha_re = alpha;
+    g.beta = beta;
+    raw_gemm<double>(P, g, {offC}, {0, 1}, {offA}, {offB}, sizeA, sizeB, sizeC);
+}
+
+// Cotangents of the ladder slices: with Z += alpha sum Y W(La, Lb) (full index ranges, as the
+// full-range kernel forms it) and the cotangent Zbar of Z, per momentum block (ki, kj, ka, ke)
+//   D[(a,b),(e,f)] = sum_{r,i,j} Zbar[ki,kj,ka][r][i][j][a][b] Y[ki,kj,ke][r][i][j][e][f],
+//   Labar[ka][ke][Q][a][e] += alpha sum_{b,f} D Lb[kb][kf][Q][b][f],
+//   Lbbar[kb][kf][Q][b][f] += alpha sum_{a,e} D La[ka][ke][Q][a][e];
+// D (v^4) lives in one scratch block, rebuilt for every momentum block.
+void ladder_param_vjp(lrcc_ctx *c, Program &P, const KT &Y, const KT &Zb, double alpha, const void *La,
+                      const void *Lb, void *Lab, void *Lbb, int R) {
+    const int nk = c->nk, o = c->no, v = c->nv, naux = c->naux;
+    const i64 vv = (i64)v * v, v3 = vv * v, blk = (i64)R * o * o * vv, nl = (i64)nk * nk * naux * vv;
+    void *D = P.alloc((size_t)vv * vv * 16);
+    const i64 nD = vv * vv;
+    for (int ki = 0; ki < nk; ++ki)
+        for (int kj = 0; kj < nk; ++kj)
+            for (int ka = 0; ka < nk; ++ka) {
+                const int kb = c->km.comb(ki, kj, ka);
+                for (int ke = 0; ke < nk; ++ke) {
+                    const int kf = c->km.comb(ki, kj, ke);
+                    const i64 oz = (((i64)ki * nk + kj) * nk + ka) * blk, oy = (((i64)ki * nk + kj) * nk + ke) * blk;
+                    // D[m=(a,b)][n=(e,f)] = sum_k Zbar[k][m] Y[k][n], k = (r, i, j)
+                    gemm1(P, Zb.p, oz, Zb.count(), Y.p, oy, Y.count(), D, 0, nD,
+                          Split{1, (int)vv}, Strides{{0, 0, 1}}, Strides{{0, 0, vv}},
+                          Split{1, (int)vv}, Strides{{0, 0, 1}}, Strides{{0, 0, 1}},
+                          Split{1, (int)(R * o * o)}, Strides{{0, 0, vv}}, Strides{{0, 0, vv}}, 1.0, 0);
+                    // Labar[ka][ke][Q][(a,e)] += alpha sum_{(b,f)} D[a][b][e][f] Lb[kb][kf][Q][b][f]
+                    const i64 oae = ((i64)ka * nk + ke) * naux * vv, obf = ((i64)kb * nk + kf) * naux * vv;
+                    gemm1(P, D, 0, nD, Lb, obf, nl, Lab, oae, nl,
+                          Split{v, v}, Strides{{0, v3, v}}, Strides{{0, v, 1}},
+                          Split{1, naux}, Strides{{0, 0, vv}}, Strides{{0, 0, vv}},
+                          Split{v, v}, Strides{{0, vv, 1}}, Strides{{0, v, 1}}, alpha, 1);
+                    // Lbbar[kb][kf][Q][(b,f)] += alpha sum_{(a,e)} D[a][b][e][f] La[ka][ke][Q][a][e]
+                    gemm1(P, D, 0, nD, La, oae, nl, Lbb, obf, nl,
+                          Split{v, v}, Strides{{0, vv, 1}}, Strides{{0, v, 1}},
+                          Split{1, naux}, Strides{{0, 0, vv}}, Strides{{0, 0, vv}},
+                          Split{v, v}, Strides{{0, v3, v}}, Strides{{0, v, 1}}, alpha, 1);
+                }
+            }
+}
+
+// Program: Gamma(u, t; T) accumulated into the block cotangents of B.  Reads t from io_x1/io_x2
+// and u from io_y1/io_y2 (caller layouts, one vector each, per-cell normalisation).
+Program *build_param_vjp(lrcc_ctx *c, HamBar &B, DevMem &wm) {
+    State<double> &S = c->s64;
+    const int nk = c->nk, o = c->no, v = c->nv, R = 1;
+    auto P = new Program();
+    SigmaGraph Gf = record_sigma<double>(c, S, R, wm);   // forward values
+    SigmaGraph Ga = record_sigma<double>(c, S, R, wm);   // cotangents
+    // forward: the only active operands paired with Hamiltonian blocks are x1, x2 and dtau
+    {
+        KT x1 = Gf.x1, x2 = Gf.x2;
+        P->ops.push_back([=](hipStream_t s) { return rhs_to_block<double, double>(c->io_x1, x1.p, R, nk, (i64)o * v, 1.0, s); });
+        P->ops.push_back([=](hipStream_t s) {
+            return rhs_to_block<double, double>(c->io_x2, x2.p, R, (i64)nk * nk * nk, (i64)o * o * v * v, 1.0 / nk, s);
+        });
+        const SymOp &tau = Gf.ops.at(0);
+        if (tau.kind != SymOp::TAU) throw LrccError(LRCC_E_STATE, "parameter gradient: unexpected term list");
+        void *t1p = S.t1.p, *xa = tau.A.p, *xb = tau.B.p, *out = tau.C.p;
+        const KMesh km = c->km;
+        P->ops.push_back([=](hipStream_t s) { return tau_like<double>(xa, xb, t1p, out, km, R, o, v, 1.0, 1, s); });
+    }
+    emit_reverse_sweep<double>(c, S, R, Ga, P, (const void *const *)&c->io_y1, (const void *const *)&c->io_y2);
+    auto fwd_ok = [&](const KT &a) { return a.p == Gf.x1.p || a.p == Gf.x2.p || a.p == Gf.ops[0].C.p; };
+    for (size_t q = 0; q < Gf.ops.size(); ++q) {
+        const SymOp &f = Gf.ops[q], &a = Ga.ops[q];
+        if (f.kind == SymOp::CON) {
+            const KT &act = f.actA ? f.A : f.B, &par = f.actA ? f.B : f.A;
+            const std::string &al = f.actA ? f.al : f.bl, &pl = f.actA ? f.bl : f.al;
+            const KT *pb = bar_of(c, B, par);
+            if (!pb) continue;
+            if (!fwd_ok(act)) throw LrccError(LRCC_E_STATE, "parameter gradient: forward value missing");
+            contract<double>(*P, *pb, pl, act, al, a.C, a.cl, f.alpha, true);
+        } else if (f.kind == SymOp::LADDER) {
+            ladder_param_vjp(c, *P, f.A, a.C, f.alpha.real(), S.La, S.Lb, B.La, B.Lb, R);
+        }
+    }
+    return P;
+}
+
+// The integrals' cotangent flowing to the scaled Cholesky arrays: for a class array
+// g[k0][k1][k2][d0][d1][d2][d3] = scale [sum_Q Ls[k0][k2][Q][d0][d2] Lcs[k1][k3][Q][d1][d3]
+//                                        - sum_Q Ls[k0][k3][Q][d0][d3] Lcs[k1][k2][Q][d1][d2]]
+// (as built for the stored classes), Lsbar and Lcsbar += the transposed products with gbar.
+void eri_vjp(lrcc_ctx *c, Program &P, const KT &gb, double scale, void *Lsb, void *Lcsb) {
+    const int nk = c->nk, n = c->n, naux = c->naux;
+    auto off = [&](char cl) { return cl == 'o' ? 0 : c->no; };
+    const i64 Lblk = (i64)naux * n * n, nl = (i64)nk * nk * Lblk, nn = (i64)n * n;
+    i64 str[4];
+    str[3] = 1;
+    for (int d = 2; d >= 0; --d) str[d] = str[d + 1] * gb.ext(d + 1);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int mi = pass == 0 ? 2 : 3, ni = pass == 0 ? 3 : 2;
+        const double sc = pass == 0 ? scale : -scale;
+        for (int side = 0; side < 2; ++side) {
+            // side 0: Lsbar[k0][km][Q][d0][dmi] += sc sum_{d1,dni} gbar Lcs[k1][kn][Q][d1][dni]
+            // side 1: Lcsbar[k1][kn][Q][d1][dni] += sc sum_{d0,dmi} gbar Ls[k0][km][Q][d0][dmi]
+            const int r0 = side == 0 ? 0 : 1, r1 = side == 0 ? mi : ni;     // output index dims of gbar
+            const int s0 = side == 0 ? 1 : 0, s1 = side == 0 ? ni : mi;     // summed index dims of gbar
+            GemmArgs g{};
+            g.shape = -1;
+            g.A = gb.p;
+            g.B = side == 0 ? c->Lcs : c->Ls;
+            g.C = side == 0 ? Lsb : Lcsb;
+            g.M = gb.ext(r0) * gb.ext(r1);
+            g.N = naux;
+            g.K = gb.ext(s0) * gb.ext(s1);
+            g.sm = Split{gb.ext(r0), gb.ext(r1)};
+            g.Am = Strides{{0, str[r0], str[r1]}};
+            g.Cm = Strides{{0, n, 1}};
+            g.sn = Split{1, naux};
+            g.Bn = Strides{{0, 0, nn}};
+            g.Cn = Strides{{0, 0, nn}};
+            g.sk = Split{gb.ext(s0), gb.ext(s1)};
+            g.Ak = Strides{{0, str[s0], str[s1]}};
+            g.Bk = Strides{{0, n, 1}};
+            g.aMfast = 0;
+            g.bNfast = 0;
+            g.alpha_re = sc;
+            g.beta = 1;
+            // jobs: output Cholesky blocks; segments: the class blocks feeding them
+            std::map<std::pair<int, int>, std::vector<std::pair<i64, i64>>> jobs;
+            for (int k0 = 0; k0 < nk; ++k0)
+                for (int k1 = 0; k1 < nk; ++k1)
+                    for (int k2 = 0; k2 < nk; ++k2) {
+                        const int k3 = c->km.comb(k0, k1, k2);
+                        const int km = pass == 0 ? k2 : k3, kn = pass == 0 ? k3 : k2;
+                        const i64 ga = (((i64)k0 * nk + k1) * nk + k2) * gb.inner();
+                        if (side == 0)
+                            jobs[{k0, km}].push_back({ga, (i64)(k1 * nk + kn) * Lblk + (i64)off(gb.cls[1]) * n + off(gb.cls[ni])});
+                        else
+                            jobs[{k1, kn}].push_back({ga, (i64)(k0 * nk + km) * Lblk + (i64)off(gb.cls[0]) * n + off(gb.cls[mi])});
+                    }
+            std::vector<i64> offC, segA, segB;
+            std::vector<int> beg{0};
+            for (const auto &j : jobs) {
+                const char cr0 = gb.cls[r0], cr1 = gb.cls[r1];
+                offC.push_back((i64)(j.first.first * nk + j.first.second) * Lblk + (i64)off(cr0) * n + off(cr1));
+                for (const auto &sg : j.second) {
+                    segA.push_back(sg.first);
+                    segB.push_back(sg.second);
+                }
+                beg.push_back((int)segA.size());
+            }
+            raw_gemm<double>(P, g, offC, beg, segA, segB, gb.count(), nl, nl);
+        }
+    }
+}
+
+// Program: the block cotangents of B flow back to the integral classes and the scaled Cholesky
+// arrays at the context's current amplitudes (the reverse of the amplitude-dependent blocks).
+Program *build_state_reverse(lrcc_ctx *c, HamBar &B, DevMem &wm) {
+    State<double> &S = c->s64;
+    const int nk = c->nk, o = c->no, v = c->nv, n = c->n, naux = c->naux;
+    auto P = new Program();
+    const KT &t1 = S.t1, &t2 = S.t2, &tau = S.tau;
+    const KMesh km = c->km;
+    // tilde tau (tau with half the t1 t1 part), as in the forward blocks
+    KT tt = alloc_kt<double>(c, wm, "oovv");
+    {
+        void *t1p = t1.p, *t2p = t2.p, *ttp = tt.p;
+        P->ops.push_back([=](hipStream_t s) { return tau_like<double>(t1p, t2p, t1p, ttp, km, 1, o, v, 0.25, 0, s); });
+    }
+    auto zero = [&](const KT &t) {
+        void *p = t.p;
+        const i64 cnt = t.count();
+        P->ops.push_back([=](hipStream_t s) { return zero_fill<double>(p, cnt, s); });
+    };
+    auto add = [&](const KT &dst, const KT &src, double a) {
+        void *d = dst.p;
+        const void *sp = src.p;
+        const i64 cnt = src.count();
+        void *tmp = a == 1.0 ? nullptr : P->alloc((size_t)cnt * 16);
+        P->ops.push_back([=](hipStream_t s) {
+            if (!tmp) return add_inplace<double>(d, sp, cnt, s);
+            hipError_t e = scale_copy(tmp, sp, a, 0.0, cnt, s);
+            return e != hipSuccess ? e : add_inplace<double>(d, tmp, cnt, s);
+        });
+    };
+    // dst += a * permute4(src) (dst in the output layout of the permutation)
+    auto padd = [&](const KT &dst, const KT &src, std::array<int, 4> ext, std::array<int, 4> perm, double a) {
+        KT tmp = dst;
+        tmp.p = P->alloc((size_t)dst.count() * 16);
+        const void *sp = src.p;
+        void *tp = tmp.p;
+        const std::array<int, 4> sg{dst.sg[0], dst.sg[1], dst.sg[2], dst.sg[3]};
+        P->ops.push_back([=](hipStream_t s) { return permute4(sp, tp, km, ext.data(), perm.data(), sg.data(), s); });
+        add(dst, tmp, a);
+    };
+    // G2_ijbm = 1/2 permute(ovoo) + t_ie <mb||ej>
+    contract<double>(*P, B.ovvo, "mbej", t1, "ie", B.G2, "ijbm", 1.0);
+    padd(B.ovoo, B.G2, {o, o, v, o}, {3, 2, 0, 1}, 0.5);
+    // H_abej = 1/2 <ab||ej> - t_ma <mb||ej> - permute(R)
+    eri_vjp(c, *P, B.H, 0.5, B.Ls, B.Lcs);
+    contract<double>(*P, B.ovvo, "mbej", t1, "ma", B.H, "abej", -1.0);
+    KT Rb = alloc_kt<double>(c, wm, "ovvv", 0, {1, -1, -1, 1});
+    zero(Rb);
+    padd(Rb, B.H, {v, v, v, o}, {3, 0, 1, 2}, -1.0);
+    // S_ijan = -t_imae <mn||je> + t_jf U_ianf - 1/4 tau_ijef <na||ef>
+    contract<double>(*P, B.ooov, "mnje", t2, "imae", B.S, "ijan", -1.0);
+    contract<double>(*P, B.U, "ianf", t1, "jf", B.S, "ijan", 1.0);
+    contract<double>(*P, B.ovvv, "naef", tau, "ijef", B.S, "ijan", -0.25);
+    // U_ianf = t_imae <mn||ef> ; R_iabf = t_imae <mb||ef>
+    contract<double>(*P, B.oovv, "mnef", t2, "imae", B.U, "ianf", 1.0);
+    contract<double>(*P, B.ovvv, "mbef", t2, "imae", Rb, "iabf", 1.0);
+    // Wbar (ring layout [m][e][b][j]) = permute of Wbar0 (ovvo):
+    //   Wbar0 = <mb||ej> + t_jf <mb||ef> + t_nb <mn||je> - t_jnfb <mn||ef> - t_nb (t_jf <mn||ef>)
+    KT W0 = alloc_kt<double>(c, wm, "ovvo");
+    zero(W0);
+    padd(W0, B.Wbar, {o, v, v, o}, {0, 2, 1, 3}, 1.0);
+    add(B.ovvo, W0, 1.0);
+    contract<double>(*P, B.ovvv, "mbef", t1, "jf", W0, "mbej", 1.0);
+    contract<double>(*P, B.ooov, "mnje", t1, "nb", W0, "mbej", 1.0);
+    contract<double>(*P, B.oovv, "mnef", t2, "jnfb", W0, "mbej", -1.0);
+    KT yb = alloc_kt<double>(c, wm, "oovo");
+    contract<double>(*P, yb, "mnej", t1, "nb", W0, "mbej", -1.0, false);
+    contract<double>(*P, B.oovv, "mnef", t1, "jf", yb, "mnej", 1.0);
+    // W'_mnij = <mn||ij> + P(ij) t_je <mn||ie> + 1/2 tau_ijef <mn||ef>
+    add(B.oooo, B.Wp, 1.0);
+    contract<double>(*P, B.ooov, "mnie", t1, "je", B.Wp, "mnij", 1.0);
+    contract<double>(*P, B.ooov, "mnie", t1, "je", B.Wp, "mnji", -1.0);
+    contract<double>(*P, B.oovv, "mnef", tau, "ijef", B.Wp, "mnij", 0.5);
+    // Fbar_mj = F_mi + 1/2 t_je F_me ; Fbar_be = F_ae - 1/2 t_mb F_me (accumulated into copies)
+    KT Fmi = B.Fmi, Fae = B.Fae, Fme = B.Fme;
+    add(Fmi, B.Fmj, 1.0);
+    contract<double>(*P, Fme, "me", t1, "je", B.Fmj, "mj", 0.5);
+    add(Fae, B.Fbe, 1.0);
+    contract<double>(*P, Fme, "me", t1, "mb", B.Fbe, "be", -0.5);
+    // Fg_me = t_nf <mn||ef> ; F_me = f_me + t_nf <mn||ef>
+    contract<double>(*P, B.oovv, "mnef", t1, "nf", B.Fg, "me", 1.0);
+    contract<double>(*P, B.oovv, "mnef", t1, "nf", Fme, "me", 1.0);
+    // F_mi = f_mi + 1/2 t_ie f_me + t_ne <mn||ie> + 1/2 ttau_inef <mn||ef>
+    contract<double>(*P, B.ooov, "mnie", t1, "ne", Fmi, "mi", 1.0);
+    contract<double>(*P, B.oovv, "mnef", tt, "inef", Fmi, "mi", 0.5);
+    // F_ae = f_ae - 1/2 f_me t_ma + t_mf <ma||fe> - 1/2 ttau_mnaf <mn||ef>
+    contract<double>(*P, B.ovvv, "mafe", t1, "mf", Fae, "ae", 1.0);
+    contract<double>(*P, B.oovv, "mnef", tt, "mnaf", Fae, "ae", -0.5);
+    // dressed virtual slices: La = Ls_vv - t1 . Ls_ov, Lb = Lcs_vv - t1 . Lcs_ov
+    for (int w = 0; w < 2; ++w) {
+        const void *lb = w == 0 ? B.La : B.Lb;
+        void *dst = w == 0 ? B.Ls : B.Lcs;
+        P->ops.push_back([=](hipStream_t s) { return slice_add(lb, dst, nk, naux, n, o, v, o, v, s); });
+        // dst[k1][k2][Q][m][o+e] += - sum_a t1[k1][m][a] lb[k1][k2][Q][a][e]
+        GemmArgs g{};
+        g.shape = -1;
+        g.A = t1.p;
+        g.B = lb;
+        g.C = dst;
+        g.M = o;
+        g.N = v;
+        g.K = v;
+        g.sm = Split{1, o};
+        g.Am = Strides{{0, 0, v}};
+        g.Cm = Strides{{0, 0, n}};
+        g.sk = Split{1, v};
+        g.Ak = Strides{{0, 0, 1}};
+        g.Bk = Strides{{0, 0, v}};
+        g.sn = Split{1, v};
+        g.Bn = Strides{{0, 0, 1}};
+        g.Cn = Strides{{0, 0, 1}};
+        g.aMfast = 0;
+        g.bNfast = 1;
+        g.alpha_re = -1.0;
+        g.beta = 1;
+        std::vector<i64> offC, segA, segB;
+        std::vector<int> beg{0};
+        for (int k1 = 0; k1 < nk; ++k1)
+            for (int k2 = 0; k2 < nk; ++k2)
+                for (int q = 0; q < naux; ++q) {
+                    offC.push_back((((i64)k1 * nk + k2) * naux + q) * n * n + o);
+                    segA.push_back((i64)k1 * o * v);
+                    segB.push_back((((i64)k1 * nk + k2) * naux + q) * v * v);
+                    beg.push_back((int)segA.size());
+                }
+        raw_gemm<double>(*P, g, offC, beg, segA, segB, (i64)nk * o * v, B.nlvv, B.nl);
+    }
+    return P;
+}
+
+// Program: the integral classes' cotangents flow to the scaled Cholesky arrays.
+Program *build_class_reverse(lrcc_ctx *c, HamBar &B) {
+    auto P = new Program();
+    for (const KT *g : {&B.oooo, &B.ooov, &B.oovv, &B.ovov, &B.ovvo, &B.ovvv, &B.ovoo})
+        eri_vjp(c, *P, *g, 1.0, B.Ls, B.Lcs);
+    return P;
+}
+
+// d alpha_XY(w_j) / d L at fixed amplitudes (lambda and the response amplitudes re-solved), for
+// perturbations dL that keep the Hermitian pairing dL[k2][k1][Q] = conj(dL[k1][k2][Q])^T:
+//   d alpha = sum grad[k1][k2][Q][p][q] dL[k1][k2][Q][p][q].
+// The scaled arrays are Ls = L / sqrt(Nk) and Lcs[k1][k2][Q][p][q] = conj(L[k2][k1][Q][q][p]) / sqrt(Nk),
+// so under the pairing dLs = dLcs = dL / sqrt(Nk) and the gradient is (Lsbar + Lcsbar) / sqrt(Nk).
+void alpha_chol_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, double *out) {
+    const int nk = c->nk, no = c->no, nv = c->nv, n = c->n, naux = c->naux;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * no * no * nv * nv;
+    hipStream_t st = c->own_stream;
+    DevMem tmp;
+    SolveCtx D;
+    GradAdjoints GA = grad_adjoints(c, j, X, Y, o, tmp, D);
+    const int ax = GA.ax, ay = GA.ay, nax = GA.nax;
+    auto vec = [&](int R) { Vecs v; v.s = tmp.get((size_t)R * n1 * 16); v.d = tmp.get((size_t)R * n2 * 16); return v; };
+    auto sub = [&](const Vecs &v, int r) { Vecs u; u.s = (char *)v.s + (size_t)r * n1 * 16; u.d = (char *)v.d + (size_t)r * n2 * 16; return u; };
+    Vecs sol{c->sol1, c->sol2};
+    auto tsol = [&](int sg, int a) { return sub(sol, (j * 2 + sg) * nax + a); };
+    const Vecs &A = GA.A, &Z = GA.Z;
+    State<double> &S = c->s64;
+    const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
+    void *T1 = tmp.get(nt1 * 16), *T2 = tmp.get(nt2 * 16);
+    HIPCHK(hipMemcpyAsync(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HamBar B;
+    hambar_alloc(c, B);
+    DevMem wm;
+    std::unique_ptr<Program> pv(build_param_vjp(c, B, wm)), sr(build_state_reverse(c, B, wm)),
+        cr(build_class_reverse(c, B));
+    Vecs u = vec(1);
+    void *z2tmp = tmp.get(n2 * 16);
+    Vecs lam{c->lam1, c->lam2};
+    // Gamma(cu * uu, t; T at the current amplitudes) into the block cotangents
+    auto gamma = [&](const Vecs &uu, double cu, const Vecs &t) {
+        HIPCHK(scale_copy(u.s, uu.s, cu, 0.0, n1, st));
+        HIPCHK(scale_copy(u.d, uu.d, cu, 0.0, n2, st));
+        c->io_x1 = t.s; c->io_x2 = t.d; c->io_y1 = u.s; c->io_y2 = u.d; c->io_omega = nullptr;
+        HIPCHK(pv->run(st));
+    };
+    // amplitudes T + e x (T2 in crystal normalisation: x2 / Nk)
+    auto shift = [&](const Vecs *x, double e) {
+        HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice, st));
+        if (x) {
+            HIPCHK(scale_copy(u.s, x->s, e, 0.0, n1, st));
+            HIPCHK(add_inplace<double>(S.t1.p, u.s, nt1, st));
+            HIPCHK(scale_copy(u.d, x->d, e / nk, 0.0, n2, st));
+            HIPCHK(add_inplace<double>(S.t2.p, u.d, nt2, st));
+        }
+        run_precompute(c, false, st);
+    };
+    const size_t nl = (size_t)nk * nk * naux * n * n;
+    std::vector<cd> G[2], ls(nl), lcs(nl);
+    for (int sg = 0; sg < 2; ++sg) {
+        // sg 0: g(w): aX = A[0] along t^X(-w), aY = A[2] along t^Y(w); sg 1: g(-w) likewise
+        const Vecs tx = tsol(1 - sg, ax), ty = tsol(sg, ay);
+        const Vecs aX = sub(A, sg == 0 ? 0 : 1), aY = sub(A, sg == 0 ? 2 : 3);
+        const Vecs zz = sub(Z, sg);
+        hambar_clear(B.classes, st);
+        hambar_clear(B.blocks, st);
+        // - <aY, dA tY> - <aX, dA tX> - <lambda, dA z> at T
+        gamma(aY, -1.0, ty);
+        gamma(aX, -1.0, tx);
+        gamma(lam, -1.0, zz);
+        HIPCHK(sr->run(st));
+        // <lambda, dOmega''[tX, tY]> = d/de Gamma(lambda, tY; T + e tX): 4-point derivative, exact
+        // for the cubic dependence of A on T
+        const double h = step_for(D, tx);
+        const int shifts[4] = {-2, -1, 1, 2};
+        const double coef[4] = {1.0, -8.0, 8.0, -1.0};
+        for (int k = 0; k < 4; ++k) {
+            shift(&tx, shifts[k] * h);
+            hambar_clear(B.blocks, st);
+            gamma(lam, coef[k] / (12.0 * h), ty);
+            HIPCHK(sr->run(st));
+        }
+        shift(nullptr, 0.0);
+        // energy terms: dE''[tX, tY] = sum d<ij||ab> tX_ia tY_jb and <db, z> with
+        // b = -(f_ia + <ij||ab> t_jb, <ij||ab> / Nk): -z_ia t_jb - z_ijab / (4 Nk)
+        HIPCHK(outer_oovv(B.oovv.p, tx.s, ty.s, 1.0, nk, no, nv, st));
+        HIPCHK(outer_oovv(B.oovv.p, zz.s, S.t1.p, -1.0, nk, no, nv, st));
+        HIPCHK(scale_copy(z2tmp, zz.d, -0.25 / nk, 0.0, n2, st));
+        HIPCHK(add_inplace<double>(B.oovv.p, z2tmp, n2, st));
+        HIPCHK(cr->run(st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(ls.data(), B.Ls, nl * 16, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(lcs.data(), B.Lcs, nl * 16, hipMemcpyDeviceToHost));
+        G[sg].resize(nl);
+        const double r = 1.0 / std::sqrt((double)nk);
+        for (size_t e = 0; e < nl; ++e) G[sg][e] = (ls[e] + lcs[e]) * r;
+    }
+    run_precompute(c, true, st);   // amplitudes restored: every block of both precisions
+    // alpha = -1/(2 Nk) [g(w) + conj(g(-w))]; conj(dL[k1][k2][Q][p][q]) = dL[k2][k1][Q][q][p]
+    std::vector<cd> g(nl);
+    auto at = [&](int k1, int k2, int q, int p, int r) { return ((((size_t)k1 * nk + k2) * naux + q) * n + p) * n + r; };
+    for (int k1 = 0; k1 < nk; ++k1)
+        for (int k2 = 0; k2 < nk; ++k2)
+            for (int q = 0; q < naux; ++q)
+                for (int p = 0; p < n; ++p)
+                    for (int r = 0; r < n; ++r)
+                        g[at(k1, k2, q, p, r)] = -0.5 / nk * (G[0][at(k1, k2, q, p, r)] + std::conj(G[1][at(k2, k1, q, r, p)]));
     std::memcpy(out, g.data(), g.size() * 16);
 }
 
@@ -2525,6 +3306,26 @@ void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const 
     c->prog_epp.reset();
     c->amem.release();
     c->solv.release();
+    c->sol1 = c->sol2 = nullptr;
+    c->sol_bytes = 0;
+    c->nfreq = 0;
+    c->nrhs_sol = 0;
+    c->axes.clear();
+    c->alpha.clear();
+    c->last_omega.clear();
+    // one-body density programs and their amplitude copies (sized by the old shape)
+    c->dens.clear();
+    c->densmem.clear();
+    c->gmem.release();
+    c->dT1 = KT{};
+    c->dT2 = KT{};
+    // staging and vector-Jacobian scratch (sized by the old shape)
+    c->stage.release();
+    c->stage_b1 = c->stage_b2 = c->stage_nrhs = 0;
+    c->vjpmem.release();
+    c->vjp_n1 = c->vjp_n2 = 0;
+    c->guess.clear();
+    ++c->gen;
     c->lam_valid = false;
     c->s64.ready = c->s32.ready = false;
     c->s64.mem.release();
@@ -2655,6 +3456,8 @@ lrcc_status lrcc_set_kmesh(lrcc_ctx *c, int n0, int n1, int n2) {
         c->ham = c->amp = false;
         c->nfreq = 0;
         c->lam_valid = false;
+        c->guess.clear();
+        ++c->gen;
     });
 }
 
@@ -2754,12 +3557,13 @@ lrcc_status lrcc_sigma_vjp_dev(lrcc_ctx *c, int nrhs, const double *omega, const
         if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
         const int nk = c->nk, o = c->no, v = c->nv;
         const i64 n1 = (i64)nrhs * nk * o * v, n2 = (i64)nrhs * nk * nk * nk * o * o * v * v;
-        const size_t need = (size_t)(2 * n1 + 2 * n2) * 16;
-        if (need > c->vjp_bytes) {
+        if (n1 > c->vjp_n1 || n2 > c->vjp_n2) {
+            // each buffer must hold its own part: grow both when either is too small
             c->vjpmem.release();
-            c->vj1 = c->vjpmem.get(n1 * 16); c->vj2 = c->vjpmem.get(n2 * 16);
-            c->vw1 = c->vjpmem.get(n1 * 16); c->vw2 = c->vjpmem.get(n2 * 16);
-            c->vjp_bytes = need;
+            c->vjp_n1 = std::max(n1, c->vjp_n1);
+            c->vjp_n2 = std::max(n2, c->vjp_n2);
+            c->vj1 = c->vjpmem.get(c->vjp_n1 * 16); c->vj2 = c->vjpmem.get(c->vjp_n2 * 16);
+            c->vw1 = c->vjpmem.get(c->vjp_n1 * 16); c->vw2 = c->vjpmem.get(c->vjp_n2 * 16);
         }
         hipStream_t st = (hipStream_t)stream;
         // z = (conj g1, P conj g2): the cotangent restricted to antisymmetric doubles, in the
@@ -2795,13 +3599,15 @@ static lrcc_status apply_host(lrcc_ctx *c, int nrhs, const double *omega, const 
         if (nrhs < 1 || !x1 || !x2 || !y1 || !y2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
         const int nk = c->nk, o = c->no, v = c->nv;
         const size_t b1 = (size_t)nrhs * nk * o * v * 16, b2 = (size_t)nrhs * nk * nk * nk * o * o * v * v * 16;
-        const size_t need = 2 * b1 + 2 * b2 + (size_t)nrhs * 8;
-        if (need > c->stage_bytes) {
+        if (b1 > c->stage_b1 || b2 > c->stage_b2 || (size_t)nrhs > c->stage_nrhs) {
+            // each staging buffer must hold its own part: grow all when any is too small
             c->stage.release();
-            c->st_x1 = c->stage.get(b1); c->st_y1 = c->stage.get(b1);
-            c->st_x2 = c->stage.get(b2); c->st_y2 = c->stage.get(b2);
-            c->st_om = c->stage.get((size_t)nrhs * 8);
-            c->stage_bytes = need;
+            c->stage_b1 = std::max(b1, c->stage_b1);
+            c->stage_b2 = std::max(b2, c->stage_b2);
+            c->stage_nrhs = std::max((size_t)nrhs, c->stage_nrhs);
+            c->st_x1 = c->stage.get(c->stage_b1); c->st_y1 = c->stage.get(c->stage_b1);
+            c->st_x2 = c->stage.get(c->stage_b2); c->st_y2 = c->stage.get(c->stage_b2);
+            c->st_om = c->stage.get(c->stage_nrhs * 8);
         }
         HIPCHK(hipMemcpy(c->st_x1, x1, b1, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->st_x2, x2, b2, hipMemcpyHostToDevice));
@@ -2841,11 +3647,10 @@ lrcc_status lrcc_solve_response_dev(lrcc_ctx *c, int nrhs, const double *omega, 
             if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
             st = c->own_stream;
         }
-        solve_response(c, nrhs, omega, b, x, o, rep, st);
+        bool sing = false;
+        solve_response(c, nrhs, omega, b, x, o, rep, st, false, false, &sing);
         if (report) *report = rep;
-        if (!rep.converged)
-            throw LrccError(LRCC_E_NOCONV, "response solve stopped at relative residual " +
-                                               std::to_string(rep.max_rel_residual));
+        if (!rep.converged) throw_unconverged("response solve", rep, sing);
     });
 }
 
@@ -2866,10 +3671,11 @@ lrcc_status lrcc_solve_response(lrcc_ctx *c, int nrhs, const double *omega, cons
         if (omega) for (int r = 0; r < nrhs; ++r) om[r] = omega[r];
         HIPCHK(hipMemcpy(dom, om.data(), nrhs * 8, hipMemcpyHostToDevice));
         lrcc_status st = lrcc_solve_response_dev(c, nrhs, (const double *)dom, db1, db2, dx1, dx2, opts, report, nullptr);
-        if (st != LRCC_OK && st != LRCC_E_NOCONV) throw LrccError(st, c->err);
+        const bool unconverged = st == LRCC_E_NOCONV || st == LRCC_E_SINGULAR;
+        if (st != LRCC_OK && !unconverged) throw LrccError(st, c->err);
         HIPCHK(hipMemcpy(x1, dx1, s1, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(x2, dx2, s2, hipMemcpyDeviceToHost));
-        if (st == LRCC_E_NOCONV) throw LrccError(st, c->err);
+        if (unconverged) throw LrccError(st, c->err);
     });
 }
 
@@ -2882,9 +3688,17 @@ lrcc_status lrcc_solve(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double 
         default_opts(o);
         if (opts) o = *opts;
         if (o.precision != LRCC_FP64 && o.precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        if (!(o.tol > 0) || o.krylov < 0 || o.max_iter < 1) throw LrccError(LRCC_E_ARG, "bad solver options");
+        for (int j = 0; j < nfreq; ++j)
+            if (!std::isfinite(omega[j])) throw LrccError(LRCC_E_ARG, "frequencies must be finite");
         lrcc_solve_report rep{};
         c->nfreq = 0;
-        solve_alpha(c, axis_mask, nfreq, omega, o, rep);
+        try {
+            solve_alpha(c, axis_mask, nfreq, omega, o, rep);
+        } catch (LrccError &) {
+            if (report) *report = rep;   // the report of the failing solve
+            throw;
+        }
         if (report) *report = rep;
     });
 }
@@ -2964,6 +3778,18 @@ lrcc_status lrcc_alpha_dipole_gradient(lrcc_ctx *c, int ifreq, int x, int y, con
     });
 }
 
+lrcc_status lrcc_alpha_chol_gradient(lrcc_ctx *c, int ifreq, int x, int y, const lrcc_solve_opts *opts,
+                                     double *grad) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!grad || x < 0 || x > 2 || y < 0 || y > 2) throw LrccError(LRCC_E_ARG, "invalid axis or null pointer");
+        lrcc_solve_opts o;
+        default_opts(o);
+        if (opts) o = *opts;
+        alpha_chol_grad(c, ifreq, x, y, o, grad);
+    });
+}
+
 lrcc_status lrcc_alpha_fock_gradient(lrcc_ctx *c, int ifreq, int x, int y, const lrcc_solve_opts *opts,
                                     double *grad) {
     return guarded(c, [&] {
@@ -2979,9 +3805,12 @@ lrcc_status lrcc_alpha_fock_gradient(lrcc_ctx *c, int ifreq, int x, int y, const
 struct lrcc_group {
     std::vector<lrcc_ctx *> ctx;
     std::string err;
-    // per (precision, nrhs list): device tables of the joint ladder launch
+    // per (precision, nrhs and joined flag per chain): device tables of the joint ladder launch,
+    // with the generations of the chains' contexts they were built from (the tables copy the
+    // chains' buffer addresses and shapes, which a new Hamiltonian, mesh or state replaces)
     std::map<std::vector<int>, std::unique_ptr<DevMem>> tabmem;
     std::map<std::vector<int>, LadderGroup> tab;
+    std::map<std::vector<int>, std::vector<unsigned long long>> tabgen;
     unsigned *counter = nullptr;
     DevMem mem;
     int nblocks = 0;
@@ -3031,10 +3860,14 @@ static void group_apply(lrcc_group *g, const int *nrhs, const double *const *ome
         if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called on every chain");
         if (nrhs[i] < 1 || !x1[i] || !x2[i] || !y1[i] || !y2[i]) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
         prog[i] = sigma_program(c, precision, nrhs[i]);
-        key.push_back(nrhs[i]);
         const Program *p = prog[i];
-        if (p->ladder_args && p->ladder_args->packed == 2 && (i64)nrhs[i] * c->no * c->no >= 320) join.push_back(i);
+        const bool j = p->ladder_args && p->ladder_args->packed == 2 && (i64)nrhs[i] * c->no * c->no >= 320;
+        if (j) join.push_back(i);
+        key.push_back(nrhs[i]);
+        key.push_back(j ? 1 : 0);
     }
+    std::vector<unsigned long long> gens(n);
+    for (int i = 0; i < n; ++i) gens[i] = g->ctx[i]->gen;
     auto io = [&](int i) {
         lrcc_ctx *c = g->ctx[i];
         c->io_x1 = x1[i]; c->io_x2 = x2[i]; c->io_y1 = y1[i]; c->io_y2 = y2[i]; c->io_omega = omega ? omega[i] : nullptr;
@@ -3048,6 +3881,13 @@ static void group_apply(lrcc_group *g, const int *nrhs, const double *const *ome
     }
     if (!join.empty()) {
         auto it = g->tab.find(key);
+        if (it != g->tab.end() && g->tabgen[key] != gens) {
+            // a chain's programs were rebuilt since this table was made: its addresses are stale
+            g->tab.erase(it);
+            g->tabmem.erase(key);
+            g->tabgen.erase(key);
+            it = g->tab.end();
+        }
         if (it == g->tab.end()) {
             // ladders by decreasing cost per item
             std::vector<int> order = join;
@@ -3076,6 +3916,7 @@ static void group_apply(lrcc_group *g, const int *nrhs, const double *const *ome
             lg.total = start.back();
             lg.counter = g->counter;
             g->tabmem[key] = std::move(mem);
+            g->tabgen[key] = gens;
             it = g->tab.emplace(key, lg).first;
         }
         HIPCHK(launch_ladder_group<T>(it->second, g->nblocks, st));
@@ -3138,7 +3979,8 @@ lrcc_status lrcc_alpha_lambda_bar(lrcc_ctx *c, int nfreq, const lrcc_solve_opts 
     });
 }
 
-lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {
+lrcc_status lrcc_get_alpha(const lrcc_ctx *cc, int nfreq, double *alpha) {
+    lrcc_ctx *c = const_cast<lrcc_ctx *>(cc);   // only the error text is written
     return guarded(c, [&] {
         if (!alpha) throw LrccError(LRCC_E_ARG, "null output");
         if (c->nfreq == 0 || nfreq != c->nfreq) throw LrccError(LRCC_E_STATE, "no polarizability for that many frequencies");
@@ -3146,7 +3988,8 @@ lrcc_status lrcc_get_alpha(lrcc_ctx *c, int nfreq, double *alpha) {
     });
 }
 
-lrcc_status lrcc_get_solution(lrcc_ctx *c, int axis, int ifreq, int sign, double *x1, double *x2) {
+lrcc_status lrcc_get_solution(const lrcc_ctx *cc, int axis, int ifreq, int sign, double *x1, double *x2) {
+    lrcc_ctx *c = const_cast<lrcc_ctx *>(cc);   // only the error text is written
     return guarded(c, [&] {
         if (!x1 || !x2 || (sign != 1 && sign != -1)) throw LrccError(LRCC_E_ARG, "bad argument");
         if (c->nfreq == 0 || ifreq < 0 || ifreq >= c->nfreq) throw LrccError(LRCC_E_STATE, "no solution stored");
@@ -3158,6 +4001,25 @@ lrcc_status lrcc_get_solution(lrcc_ctx *c, int axis, int ifreq, int sign, double
         const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
         HIPCHK(hipMemcpy(x1, (char *)c->sol1 + (size_t)r * n1 * 16, n1 * 16, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(x2, (char *)c->sol2 + (size_t)r * n2 * 16, n2 * 16, hipMemcpyDeviceToHost));
+    });
+}
+
+lrcc_status lrcc_set_guess(lrcc_ctx *c, int axis, int ifreq, int sign, const double *x1, const double *x2) {
+    return guarded(c, [&] {
+        if (!x1 || !x2 || axis < 0 || axis > 2 || ifreq < 0 || (sign != 1 && sign != -1))
+            throw LrccError(LRCC_E_ARG, "bad axis, frequency index, sign or null pointer");
+        if (!c->ham) throw LrccError(LRCC_E_STATE, "set_hamiltonian must be called first");
+        const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
+        for (const double *x : {x1, x2}) {
+            const i64 cnt = 2 * (x == x1 ? n1 : n2);
+            for (i64 q = 0; q < cnt; ++q)
+                if (!std::isfinite(x[q])) throw LrccError(LRCC_E_ARG, "guess holds a non-finite value");
+        }
+        auto m = std::make_unique<DevMem>();
+        char *d = (char *)m->get((size_t)(n1 + n2) * 16);
+        HIPCHK(hipMemcpy(d, x1, (size_t)n1 * 16, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d + (size_t)n1 * 16, x2, (size_t)n2 * 16, hipMemcpyHostToDevice));
+        c->guess[{axis, ifreq, sign}] = std::move(m);
     });
 }
 

@@ -178,4 +178,260 @@ hipError_t combine(void *Y, const void *V, const void *C, int R, int m, i64 n, d
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ device-resident GMRES
+// Vectors of one Krylov space: vector i, right-hand side r is (s + (i*R + r)*n1, d + (i*R + r)*n2).
+// Inner products weight the doubles by 1/4 (every independent amplitude counts once).
+
+namespace {
+constexpr int MD = 256;        // threads of the multi-dot and multi-axpy kernels
+constexpr int MDV = 8;         // basis vectors per multi-dot workgroup
+}
+
+// part[(r*k + i)*nblk + b] = sum over chunk b of conj(V_i[r]) w[r] (singles weight 1, doubles 1/4)
+__global__ void __launch_bounds__(MD) k_multidot_partial(const double2 *Vs, const double2 *Vd, const double2 *ws,
+                                                         const double2 *wd, int R, i64 n1, i64 n2, int k, int nblk,
+                                                         double2 *part) {
+    __shared__ double sr[MDV][MD], si[MDV][MD];
+    const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MDV, t = threadIdx.x;
+    const int nv = min(MDV, k - i0);
+    double ar[MDV], ai[MDV];
+#pragma unroll
+    for (int q = 0; q < MDV; ++q) { ar[q] = 0; ai[q] = 0; }
+    const i64 N = n1 + n2;
+    for (i64 e = (i64)b * MD + t; e < N; e += (i64)nblk * MD) {
+        const bool single = e < n1;
+        const i64 off = single ? (i64)r * n1 + e : (i64)r * n2 + (e - n1);
+        const double2 y = single ? ws[off] : wd[off];
+        const double wt = single ? 1.0 : 0.25;
+#pragma unroll
+        for (int q = 0; q < MDV; ++q) {
+            if (q < nv) {
+                const i64 vo = single ? (i64)(i0 + q) * R * n1 + off : (i64)(i0 + q) * R * n2 + off;
+                const double2 x = single ? Vs[vo] : Vd[vo];
+                ar[q] += wt * (x.x * y.x + x.y * y.y);
+                ai[q] += wt * (x.x * y.y - x.y * y.x);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MDV; ++q) { sr[q][t] = ar[q]; si[q][t] = ai[q]; }
+    __syncthreads();
+    for (int st = MD / 2; st > 0; st >>= 1) {
+        if (t < st)
+#pragma unroll
+            for (int q = 0; q < MDV; ++q) { sr[q][t] += sr[q][t + st]; si[q][t] += si[q][t + st]; }
+        __syncthreads();
+    }
+    if (t < nv) part[((i64)r * k + i0 + t) * nblk + b] = make_double2(sr[t][0], si[t][0]);
+}
+
+// out[r*ostride + i] = sum_b part[(r*k + i)*nblk + b]  (fixed order)
+__global__ void k_multidot_final(const double2 *part, int R, int k, int nblk, double2 *out, int ostride) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= R * k) return;
+    const int r = q / k, i = q - r * k;
+    double ar = 0, ai = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const double2 x = part[(i64)q * nblk + b];
+        ar += x.x;
+        ai += x.y;
+    }
+    out[(i64)r * ostride + i] = make_double2(ar, ai);
+}
+
+int multidot_blocks(i64 n) {
+    i64 b = (n + MD * 16 - 1) / (MD * 16);
+    return (int)std::max<i64>(1, std::min<i64>(b, 512));
+}
+
+hipError_t multidot(const void *Vs, const void *Vd, const void *ws, const void *wd, int R, i64 n1, i64 n2, int k,
+                    void *part, void *out, int ostride, hipStream_t s) {
+    const int nblk = multidot_blocks(n1 + n2);
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, R, (k + MDV - 1) / MDV), dim3(MD), 0, s, (const double2 *)Vs,
+                       (const double2 *)Vd, (const double2 *)ws, (const double2 *)wd, R, n1, n2, k, nblk,
+                       (double2 *)part);
+    hipLaunchKernelGGL(k_multidot_final, dim3((R * k + 63) / 64), dim3(64), 0, s, (const double2 *)part, R, k, nblk,
+                       (double2 *)out, ostride);
+    return hipGetLastError();
+}
+
+// w[r] = beta w[r] + sum_{i<k} c_r,i V_i[r], c_r,i = sign * C[r*cstride + i], zero where mask[r] == 0
+// (mask may be null); singles and doubles in one launch (grid y = right-hand side)
+__global__ void __launch_bounds__(MD) k_multiaxpy(double2 *ws, double2 *wd, const double2 *Vs, const double2 *Vd,
+                                                  const double2 *C, int cstride, double sign, const int *mask,
+                                                  double beta, int R, i64 n1, i64 n2, int k) {
+    __shared__ double2 c[64];
+    const int r = blockIdx.y;
+    const bool on = !mask || mask[r] != 0;
+    for (int i = threadIdx.x; i < k; i += MD) {
+        const double2 x = C[(i64)r * cstride + i];
+        c[i] = on ? make_double2(sign * x.x, sign * x.y) : make_double2(0, 0);
+    }
+    __syncthreads();
+    const i64 N = n1 + n2;
+    for (i64 e = (i64)blockIdx.x * MD + threadIdx.x; e < N; e += (i64)gridDim.x * MD) {
+        const bool single = e < n1;
+        const i64 off = single ? (i64)r * n1 + e : (i64)r * n2 + (e - n1);
+        double2 *wp = single ? ws + off : wd + off;
+        double2 acc = beta == 0.0 ? make_double2(0, 0) : *wp;
+        acc.x *= beta;
+        acc.y *= beta;
+        for (int i = 0; i < k; ++i) {
+            const i64 vo = single ? (i64)i * R * n1 + off : (i64)i * R * n2 + off;
+            const double2 x = single ? Vs[vo] : Vd[vo];
+            acc.x += c[i].x * x.x - c[i].y * x.y;
+            acc.y += c[i].x * x.y + c[i].y * x.x;
+        }
+        *wp = acc;
+    }
+}
+
+hipError_t multiaxpy(void *ws, void *wd, const void *Vs, const void *Vd, const void *C, int cstride, double sign,
+                     const int *mask, double beta, int R, i64 n1, i64 n2, int k, hipStream_t s) {
+    if (k > 64) return hipErrorInvalidValue;
+    const i64 g = std::max<i64>(1, std::min<i64>((n1 + n2 + MD - 1) / MD, 4096));
+    hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)g, R), dim3(MD), 0, s, (double2 *)ws, (double2 *)wd,
+                       (const double2 *)Vs, (const double2 *)Vd, (const double2 *)C, cstride, sign, mask, beta, R,
+                       n1, n2, k);
+    return hipGetLastError();
+}
+
+static __device__ double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+static __device__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+static __device__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Start of a GMRES cycle for right-hand side r (one thread each): beta = ||r0||, relative residual,
+// active flag, g = (beta, 0, ...), and the scale 1/beta of the first basis vector.
+__global__ void k_gmres_init(GmresState g, const double2 *beta2, double tol) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= g.R) return;
+    const double b2 = beta2[r].x, bi = beta2[r].y;
+    const bool fin = isfinite(b2) && isfinite(bi);
+    const double beta = fin ? sqrt(fmax(0.0, b2)) : nan("");
+    const double bn = g.bn[r];
+    double rel = (!fin || !isfinite(bn)) ? nan("") : (bn > 0 ? beta / bn : 0.0);
+    g.rel[r] = rel;
+    for (int i = 0; i <= g.m; ++i) g.g[(i64)r * (g.m + 1) + i] = make_double2(i == 0 && fin ? beta : 0.0, 0.0);
+    g.kr[r] = 0;
+    const bool act = fin && rel > tol && beta > 0 && !g.sing[r];
+    g.act[r] = act ? 1 : 0;
+    g.scal[r] = make_double2(act ? 1.0 / beta : 0.0, 0.0);
+}
+
+// Arnoldi step j for right-hand side r: column j of the Hessenberg matrix from the two
+// Gram-Schmidt passes, the previous Givens rotations applied to it, a new rotation, the residual
+// estimate, and the scale 1/h_{j+1,j} of the next basis vector.  A pivot at or below `sing_pivot`
+// (> 0 only in complex128) marks the right-hand side singular and stops it.
+__global__ void k_gmres_step(GmresState g, int j, const double2 *h1, const double2 *h2, const double2 *hn2, double tol,
+                             double sing_pivot) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= g.R) return;
+    const int m = g.m, ld = m + 1;
+    double2 *H = g.H + (i64)r * (m + 1) * m, *cs = g.cs + (i64)r * m, *sn = g.sn + (i64)r * m;
+    double2 *gg = g.g + (i64)r * ld;
+    if (!g.act[r]) {
+        g.scal[r] = make_double2(0, 0);
+        return;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double2 a = h1[(i64)r * ld + i], b = h2[(i64)r * ld + i];
+        H[i * m + j] = make_double2(a.x + b.x, a.y + b.y);
+    }
+    const double n2 = hn2[r].x;
+    if (!isfinite(n2) || !isfinite(hn2[r].y)) {
+        g.rel[r] = nan("");
+        g.act[r] = 0;
+        g.scal[r] = make_double2(0, 0);
+        return;
+    }
+    const double hn = sqrt(fmax(0.0, n2));
+    H[(j + 1) * m + j] = make_double2(hn, 0.0);
+    for (int i = 0; i < j; ++i) {
+        const double2 a = H[i * m + j], b = H[(i + 1) * m + j];
+        const double2 t0 = cmul(cconj(cs[i]), a), t1 = cmul(cconj(sn[i]), b);
+        const double2 u0 = cmul(sn[i], a), u1 = cmul(cs[i], b);
+        H[i * m + j] = make_double2(t0.x + t1.x, t0.y + t1.y);
+        H[(i + 1) * m + j] = make_double2(u1.x - u0.x, u1.y - u0.y);
+    }
+    const double2 a = H[j * m + j], b = H[(j + 1) * m + j];
+    const double den = sqrt(cabs2(a) + cabs2(b));
+    if (sing_pivot > 0 && den <= sing_pivot) {
+        g.sing[r] = 1;
+        g.act[r] = 0;
+        g.scal[r] = make_double2(0, 0);
+        return;
+    }
+    cs[j] = den > 0 ? make_double2(a.x / den, a.y / den) : make_double2(1, 0);
+    sn[j] = den > 0 ? make_double2(b.x / den, b.y / den) : make_double2(0, 0);
+    H[j * m + j] = make_double2(den, 0);
+    H[(j + 1) * m + j] = make_double2(0, 0);
+    const double2 gj = gg[j];
+    gg[j] = cmul(cconj(cs[j]), gj);
+    const double2 ng = cmul(sn[j], gj);
+    gg[j + 1] = make_double2(-ng.x, -ng.y);
+    g.kr[r] = j + 1;
+    const double bn = g.bn[r];
+    const double rel = bn > 0 ? sqrt(cabs2(gg[j + 1])) / bn : 0.0;
+    g.rel[r] = rel;
+    const bool act = !(rel <= tol || hn == 0 || isnan(rel));
+    g.act[r] = act ? 1 : 0;
+    g.scal[r] = make_double2(act && hn > 0 ? 1.0 / hn : 0.0, 0.0);
+}
+
+// End of a cycle: y = H^-1 g on the first kr[r] steps (back substitution), coefficients y[r][i].
+__global__ void k_gmres_solve(GmresState g, double2 *y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= g.R) return;
+    const int m = g.m, k = g.kr[r];
+    const double2 *H = g.H + (i64)r * (m + 1) * m, *gg = g.g + (i64)r * (m + 1);
+    double2 *yr = y + (i64)r * (m + 1);
+    for (int i = 0; i <= m; ++i) yr[i] = make_double2(0, 0);
+    for (int i = k - 1; i >= 0; --i) {
+        double2 acc = gg[i];
+        for (int l = i + 1; l < k; ++l) {
+            const double2 t = cmul(H[i * m + l], yr[l]);
+            acc.x -= t.x;
+            acc.y -= t.y;
+        }
+        const double2 d = H[i * m + i];
+        const double dd = cabs2(d);
+        yr[i] = dd > 0 ? make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd)
+                       : make_double2(0, 0);
+    }
+}
+
+// rel[r] -> status words for the host: (rel, act, sing) packed per right-hand side
+__global__ void k_gmres_status(GmresState g, double *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= g.R) return;
+    out[3 * r] = g.rel[r];
+    out[3 * r + 1] = g.act[r];
+    out[3 * r + 2] = g.sing[r];
+}
+
+hipError_t gmres_init(const GmresState &g, const void *beta2, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_init, dim3((g.R + 63) / 64), dim3(64), 0, s, g, (const double2 *)beta2, tol);
+    return hipGetLastError();
+}
+hipError_t gmres_step(const GmresState &g, int j, const void *h1, const void *h2, const void *hn2, double tol,
+                      double sing_pivot, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_step, dim3((g.R + 63) / 64), dim3(64), 0, s, g, j, (const double2 *)h1,
+                       (const double2 *)h2, (const double2 *)hn2, tol, sing_pivot);
+    return hipGetLastError();
+}
+hipError_t gmres_solve(const GmresState &g, void *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_solve, dim3((g.R + 63) / 64), dim3(64), 0, s, g, (double2 *)y);
+    return hipGetLastError();
+}
+hipError_t gmres_status(const GmresState &g, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmres_status, dim3((g.R + 63) / 64), dim3(64), 0, s, g, out);
+    return hipGetLastError();
+}
+
+// per-right-hand-side norms^2 into out[r] (as complex, real part) via the multi-dot of w with itself
+hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, hipStream_t s) {
+    // V_0 = w with a one-vector "space": stride arguments make vector 0 the vector itself
+    return multidot(ws, wd, ws, wd, R, n1, n2, 1, part, out, 1, s);
+}
+
 }  // namespace lrcc

@@ -16,4 +16,32 @@ hipError_t precond(void *o1, void *o2, const void *i1, const void *i2, const dou
 hipError_t diag_real(const void *F, double *d, int nk, int n, hipStream_t s);
 // Y[r] = beta Y[r] + sum_i C[r][i] V[i]  (complex128; V: [m][n], Y: [R][n], C: device [R][m])
 hipError_t combine(void *Y, const void *V, const void *C, int R, int m, i64 n, double beta, hipStream_t s);
+
+// Device-resident GMRES state of R right-hand sides with restart length m (device arrays).
+struct GmresState {
+    int R, m;
+    double2 *H;      // [R][(m+1)*m] Hessenberg matrices (rotated: upper triangular)
+    double2 *cs, *sn;// [R][m] Givens rotations
+    double2 *g;      // [R][m+1] rotated right-hand side of the least-squares problem
+    double2 *scal;   // [R] scale of the next basis vector (0 for inactive right-hand sides)
+    double *bn;      // [R] ||b||
+    double *rel;     // [R] relative residual estimate (NaN for a non-finite one)
+    int *act;        // [R] 1 while the right-hand side iterates
+    int *kr;         // [R] Arnoldi steps that count for the right-hand side in this cycle
+    int *sing;       // [R] 1 after a zero pivot (singular operator)
+};
+// Krylov vectors: vector i of right-hand side r at (Vs + (i*R + r)*n1, Vd + (i*R + r)*n2).
+// out[r*ostride + i] = <V_i[r], w[r]> (conjugate-linear in V, doubles weighted 1/4), i < k
+int multidot_blocks(i64 n);
+hipError_t multidot(const void *Vs, const void *Vd, const void *ws, const void *wd, int R, i64 n1, i64 n2, int k,
+                    void *part, void *out, int ostride, hipStream_t s);
+hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, hipStream_t s);
+// w[r] = beta w[r] + sign * sum_{i<k} C[r*cstride + i] V_i[r] (masked rows: w[r] = beta w[r]); k <= 64
+hipError_t multiaxpy(void *ws, void *wd, const void *Vs, const void *Vd, const void *C, int cstride, double sign,
+                     const int *mask, double beta, int R, i64 n1, i64 n2, int k, hipStream_t s);
+hipError_t gmres_init(const GmresState &g, const void *beta2, double tol, hipStream_t s);
+hipError_t gmres_step(const GmresState &g, int j, const void *h1, const void *h2, const void *hn2, double tol,
+                      double sing_pivot, hipStream_t s);
+hipError_t gmres_solve(const GmresState &g, void *y, hipStream_t s);
+hipError_t gmres_status(const GmresState &g, double *out, hipStream_t s);
 }  // namespace lrcc

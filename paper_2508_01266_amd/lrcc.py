@@ -89,10 +89,14 @@ def lib():
         L.lrcc_alpha_dipole_gradient.restype = ctypes.c_int
         L.lrcc_alpha_fock_gradient.argtypes = [vp, i, i, i, ctypes.POINTER(SolveOpts), vp]
         L.lrcc_alpha_fock_gradient.restype = ctypes.c_int
+        L.lrcc_alpha_chol_gradient.argtypes = [vp, i, i, i, ctypes.POINTER(SolveOpts), vp]
+        L.lrcc_alpha_chol_gradient.restype = ctypes.c_int
         L.lrcc_solve_ccsd.argtypes = [vp, ctypes.c_double, i, vp, vp, dp, ctypes.POINTER(SolveReport)]
         L.lrcc_solve_ccsd.restype = ctypes.c_int
         L.lrcc_get_solution.argtypes = [vp, i, i, i, vp, vp]
         L.lrcc_get_lambda.argtypes = [vp, vp, vp]
+        L.lrcc_set_guess.argtypes = [vp, i, i, i, vp, vp]
+        L.lrcc_set_guess.restype = ctypes.c_int
         for f in ("lrcc_solve", "lrcc_get_alpha", "lrcc_get_solution", "lrcc_get_lambda"):
             getattr(L, f).restype = ctypes.c_int
         L.lrcc_plan_check.argtypes = [i, i, i, i, i, ctypes.c_char_p, i]
@@ -288,6 +292,15 @@ class Context:
         self._check(self._L.lrcc_alpha_fock_gradient(self._h, int(ifreq), int(x), int(y), ctypes.byref(oo), _ptr(g)))
         return g
 
+    def alpha_chol_gradient(self, ifreq, x, y, **opts):
+        """d alpha_xy(omega_ifreq) / d L at fixed amplitudes (lambda and the response re-solved):
+        complex [nk][nk][naux][n][n] with d alpha = sum(grad * dL) for perturbations dL that keep the
+        Hermitian pairing of the Cholesky vectors.  Needs a preceding solve()."""
+        oo = self.solve_options(**opts)
+        g = np.zeros((self.nk, self.nk, self.naux, self.n, self.n), dtype=np.complex128)
+        self._check(self._L.lrcc_alpha_chol_gradient(self._h, int(ifreq), int(x), int(y), ctypes.byref(oo), _ptr(g)))
+        return g
+
     def alpha_lambda_bar(self, nfreq, **opts):
         """alpha [nfreq][3][3] of the last solve() from the non-symmetric (perturbed-lambda) form."""
         oo = self.solve_options(**opts)
@@ -322,6 +335,13 @@ class Context:
         x2 = np.zeros((nk, nk, nk, o, o, v, v), dtype=np.complex128)
         self._check(self._L.lrcc_get_solution(self._h, int(axis), int(ifreq), int(sign), _ptr(x1), _ptr(x2)))
         return x1, x2
+
+    def set_guess(self, axis, ifreq, sign, x1, x2):
+        """Initial guess for t^axis(sign * omega_ifreq) of the next solve() (caller layouts, nrhs = 1)."""
+        nk, o, v = self.nk, self.no, self.nv
+        a = _c128(x1, (nk, o, v))
+        b = _c128(x2, (nk, nk, nk, o, o, v, v))
+        self._check(self._L.lrcc_set_guess(self._h, int(axis), int(ifreq), int(sign), _ptr(a), _ptr(b)))
 
     def get_lambda(self):
         nk, o, v = self.nk, self.no, self.nv

@@ -6,6 +6,13 @@ import torch
 import synth
 from oracle import ccsd, layout, response
 
+# Bound on the max-norm relative error of a complex64 sigma (matrix-core products in fp32,
+# inputs and outputs complex128) against the complex128 oracle.  The error is set by fp32
+# rounding of the products and sums: about 1e-7 at the small sizes and 3e-7 at the batched
+# Nk=5, o=8, v=40 workload; 1e-5 leaves a factor of about 30, far below what any defect
+# confined to the complex64 path (a wrong term, a dropped block) would produce.
+FP32_REL = 1e-5
+
 
 def _rng(base, nk, o, v, mesh):
     """Per-case generator; a 3D mesh adds its extents to the seed."""
@@ -14,12 +21,31 @@ def _rng(base, nk, o, v, mesh):
     return synth.rng_for(base, nk, o, v, extra=synth.mesh_dims(mesh))
 
 
-def make_case(nk, o, v, naux, nrhs, seed, tscale=0.02, band_shift=True, mesh=None):
-    """mesh: None (1D chain of nk points) or k-mesh extents whose product is nk."""
+def _noncanonical(H, nk, o, v, seed, scale):
+    """Add a Hermitian k-diagonal part with off-diagonal (occupied-virtual, occupied-occupied,
+    virtual-virtual) elements to the Fock matrix: complex Gaussian N(0, scale^2) entries made
+    Hermitian with (A + A^H)/2, drawn from a generator of their own so that the other inputs of
+    a case do not change."""
+    if not scale:
+        return H
+    rng = synth.rng_for(4000 + seed, nk, o, v)
+    n = o + v
+    H = dict(H)
+    H['fock'] = H['fock'].copy()
+    for k in range(nk):
+        a = scale * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+        H['fock'][k] += (a + a.conj().T) / 2
+    return H
+
+
+def make_case(nk, o, v, naux, nrhs, seed, tscale=0.02, band_shift=True, mesh=None, noncanonical=0.0):
+    """mesh: None (1D chain of nk points) or k-mesh extents whose product is nk; noncanonical:
+    scale of a Hermitian off-diagonal part added to the Fock matrix (0: diagonal f)."""
     km = nk if mesh is None else tuple(mesh)
     assert synth.mesh_size(km) == nk
     rng = _rng(500 + seed, nk, o, v, mesh)
     H = synth.hamiltonian(km, o, v, naux, rng, band_shift=band_shift)
+    H = _noncanonical(H, nk, o, v, seed, noncanonical)
     t1k, t2k_cr = synth.random_amplitudes(km, o, v, rng, tscale, tscale)
     x1k, x2k_cr = synth.random_vectors(nrhs, km, o, v, rng, 0.1, 0.1)
     omega = np.linspace(-0.1, 0.1, nrhs) if nrhs > 1 else np.array([0.0656])
@@ -95,13 +121,15 @@ def oracle_solve(case, b1, b2, tol=1e-12):
     return x1, x2
 
 
-def make_ccsd_case(nk, o, v, naux, seed, band_shift=True, chol_sigma=0.05, mesh=None):
-    """Synthetic chain (or 3D k mesh) with converged CCSD amplitudes (oracle) and its lambda."""
+def make_ccsd_case(nk, o, v, naux, seed, band_shift=True, chol_sigma=0.05, mesh=None, noncanonical=0.0):
+    """Synthetic chain (or 3D k mesh) with converged CCSD amplitudes (oracle) and its lambda;
+    noncanonical as for make_case."""
     from oracle import solvers
     km = nk if mesh is None else tuple(mesh)
     assert synth.mesh_size(km) == nk
     rng = _rng(600 + seed, nk, o, v, mesh)
     H = synth.hamiltonian(km, o, v, naux, rng, band_shift=band_shift, chol_sigma=chol_sigma)
+    H = _noncanonical(H, nk, o, v, 100 + seed, noncanonical)
     f = layout.dense_one_body(H['fock'], km, o, v)
     g = layout.dense_eri(H['chol'], km, o, v)
     h = ccsd.DenseHam.from_numpy(f, g, nk * o)

@@ -68,13 +68,15 @@ def _oracle_alpha_fock(case, fock):
 
 
 @pytest.mark.parametrize("x,y", [(2, 2), (0, 1)])
-@pytest.mark.parametrize("nk,o,v,naux,seed", [(1, 2, 4, 6, 21), (2, 2, 3, 6, 22)])
-def test_alpha_fock_gradient_matches_oracle(nk, o, v, naux, seed, x, y):
+@pytest.mark.parametrize("nk,o,v,naux,seed,nc", [(1, 2, 4, 6, 21, 0.0), (2, 2, 3, 6, 22, 0.0),
+                                                 (1, 2, 4, 6, 27, 0.05)])
+def test_alpha_fock_gradient_matches_oracle(nk, o, v, naux, seed, nc, x, y):
     """d alpha / d f at fixed amplitudes against a 5-point central difference of the oracle's
-    alpha (lambda and the response amplitudes re-solved at every displaced Fock matrix)."""
+    alpha (lambda and the response amplitudes re-solved at every displaced Fock matrix); nc > 0:
+    a non-canonical Fock matrix."""
     import paper_2508_01266_amd as lr
-    print(f"case nk={nk} o={o} v={v} naux={naux} alpha_{x}{y}", flush=True)
-    case = make_ccsd_case(nk, o, v, naux, seed)
+    print(f"case nk={nk} o={o} v={v} naux={naux} noncanonical={nc} alpha_{x}{y}", flush=True)
+    case = make_ccsd_case(nk, o, v, naux, seed, noncanonical=nc)
     H = case['H']
     # a Hermitian, k-diagonal perturbation of the Fock matrix
     dF = 0.1 * synth.hamiltonian(nk, o, v, naux, synth.rng_for(800 + seed, nk, o, v))['dip'][0]
@@ -92,4 +94,98 @@ def test_alpha_fock_gradient_matches_oracle(nk, o, v, naux, seed, x, y):
         print(f"omega {OMEGAS[j]}: d alpha {got:.10f} oracle {ref[j]:.10f} err {err:.2e}", flush=True)
         # 5-point difference error O(h^4) plus solver tolerance / h
         assert err < 1e-7 * max(1.0, abs(ref[j]))
+    c.close()
+
+
+def _oracle_alpha_chol(case, chol):
+    """Oracle alpha with the Cholesky vectors replaced, amplitudes fixed, lambda re-solved."""
+    from oracle import ccsd, layout, response
+    nk, o, v = case['nk'], case['o'], case['v']
+    f = layout.dense_one_body(case['H']['fock'], nk, o, v)
+    g = layout.dense_eri(chol, nk, o, v)
+    h = ccsd.DenseHam.from_numpy(f, g, nk * o)
+    lam, _, _ = response.solve_lambda(case['t'], h)
+    ops = [torch.from_numpy(layout.dense_one_body(case['H']['dip'][x], nk, o, v)) for x in range(3)]
+    al, _ = response.polarizability(case['t'], lam, ops, OMEGAS, h, nk=nk)
+    return al
+
+
+@pytest.mark.parametrize("x,y", [(2, 2), (0, 1)])
+@pytest.mark.parametrize("nk,o,v,naux,seed,nc", [(1, 2, 4, 6, 21, 0.0), (2, 2, 3, 6, 22, 0.0),
+                                                 (3, 1, 3, 5, 23, 0.0), (1, 2, 4, 6, 27, 0.05)])
+def test_alpha_chol_gradient_matches_oracle(nk, o, v, naux, seed, nc, x, y):
+    """d alpha / d L at fixed amplitudes against a 5-point central difference of the oracle's alpha
+    (lambda and the response amplitudes re-solved at every displaced L) along a perturbation with
+    the Hermitian pairing of the Cholesky vectors (drawn like them)."""
+    import paper_2508_01266_amd as lr
+    print(f"case nk={nk} o={o} v={v} naux={naux} noncanonical={nc} alpha_{x}{y}", flush=True)
+    case = make_ccsd_case(nk, o, v, naux, seed, noncanonical=nc)
+    H = case['H']
+    dL = synth.hamiltonian(nk, o, v, naux, synth.rng_for(850 + seed, nk, o, v))['chol']
+    h = 1e-3
+    vals = [_oracle_alpha_chol(case, H['chol'] + s * h * dL)[:, x, y] for s in (-2, -1, 1, 2)]
+    ref = (vals[0] - 8 * vals[1] + 8 * vals[2] - vals[3]) / (12 * h)
+    c = lr.Context(0)
+    c.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+    c.set_amplitudes(case['t1'], case['t2'])
+    c.solve(OMEGAS, tol=1e-12, precision=lr.FP64)
+    for j in range(len(OMEGAS)):
+        g = c.alpha_chol_gradient(j, x, y, tol=1e-12, precision=lr.FP64)
+        got = np.sum(g * dL)
+        err = abs(got - ref[j])
+        print(f"omega {OMEGAS[j]}: d alpha {got:.10f} oracle {ref[j]:.10f} err {err:.2e}", flush=True)
+        # 5-point difference error O(h^4) plus solver tolerance / h
+        assert err < 1e-7 * max(1.0, abs(ref[j]))
+    # the stored ladder integrals (mode 2) give the same gradient
+    c2 = lr.Context(0)
+    c2.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+    c2.set_ladder_mode(2)
+    c2.set_amplitudes(case['t1'], case['t2'])
+    c2.solve(OMEGAS, tol=1e-12, precision=lr.FP64)
+    g2 = c2.alpha_chol_gradient(1, x, y, tol=1e-12, precision=lr.FP64)
+    assert abs(np.sum(g2 * dL) - ref[1]) < 1e-7 * max(1.0, abs(ref[1]))
+    c.close()
+    c2.close()
+
+
+def test_alpha_autograd_function_gradients():
+    """alpha(f, L, mu) through torch.autograd: the gradients of a real loss, taken by the backward
+    pass from the three gradient entry points, reproduce the central difference of the same loss
+    evaluated by the library's forward solves along admissible perturbations (Hermitian f and mu,
+    L with its Hermitian pairing), amplitudes held fixed."""
+    import paper_2508_01266_amd as lr
+    from paper_2508_01266_amd import autograd
+    nk, o, v, naux, seed = 2, 2, 3, 6, 22
+    case = make_ccsd_case(nk, o, v, naux, seed)
+    H = case['H']
+    dev = torch.device("cuda:0")
+    om = [0.0656]
+    T = lambda a, g=False: torch.tensor(a, dtype=torch.complex128, device=dev, requires_grad=g)
+    f, L, mu = T(H['fock'], True), T(H['chol'], True), T(H['dip'], True)
+    t1, t2 = T(case['t1']), T(case['t2'])
+    c = lr.Context(0)
+    opts = dict(tol=1e-12, precision=lr.FP64)
+
+    def loss_of(a):
+        return a[0, 2, 2].real + 0.3 * a[0, 0, 1].imag - 0.2 * a[0, 1, 2].real
+
+    a = autograd.alpha(c, o, f, L, mu, t1, t2, om, **opts)
+    loss = loss_of(a)
+    loss.backward()
+    rng = synth.rng_for(870, nk, o, v)
+    P = synth.hamiltonian(nk, o, v, naux, rng)
+    dirs = {"fock": (0.1 * P['dip'][0], f), "chol": (P['chol'], L), "dip": (P['dip'], mu)}
+    for name, (d, leaf) in dirs.items():
+        pred = float(np.real(np.sum(np.conj(leaf.grad.cpu().numpy()) * d)))
+        h = 1e-4
+        vals = []
+        for s in (-1, 1):
+            ins = {"fock": H['fock'], "chol": H['chol'], "dip": H['dip']}
+            ins[name] = ins[name] + s * h * d
+            with torch.no_grad():
+                a2 = autograd.alpha(c, o, T(ins["fock"]), T(ins["chol"]), T(ins["dip"]), t1, t2, om, **opts)
+            vals.append(float(loss_of(a2)))
+        fd = (vals[1] - vals[0]) / (2 * h)
+        print(f"{name}: autograd {pred:.10f} central difference {fd:.10f}", flush=True)
+        assert abs(pred - fd) < 1e-6 * max(1.0, abs(fd))
     c.close()

@@ -5,6 +5,8 @@ v=60, Naux=210) forward and transpose."""
 import numpy as np
 import pytest
 
+from tests.sigma_cases import FP32_REL
+
 import synth
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -58,7 +60,7 @@ def test_batched_workload_sampled_rhs():
         r1, r2 = _oracle_one(w, H, t1, t2, x1[r], x2[r], om[r])
         for (mode, prec), (y1, y2) in out.items():
             e1, e2 = _rel(y1[i], r1), _rel(y2[i], r2)
-            tol = 1e-11 if prec == lr.FP64 else 4 * w.nk * w.nvir ** 2 * 2.0 ** -24
+            tol = 1e-11 if prec == lr.FP64 else FP32_REL
             print(f"c3 48-rhs launch, rhs {r}, ladder mode {mode}, prec {prec}: rel err singles {e1:.2e} "
                   f"doubles {e2:.2e} (tol {tol:.1e})", flush=True)
             assert e1 < tol and e2 < tol
@@ -150,4 +152,42 @@ def test_c4s_dipole_gradient_against_finite_difference():
     ref = (vals[0] - vals[1]) / (2 * hstep)
     print(f"c4s d alpha_zz: gradient {got:.10f} central difference {ref:.10f}", flush=True)
     assert abs(got - ref) < 1e-7 * max(1.0, abs(ref))
+    c.close()
+
+
+def test_c4s_fock_gradient_against_central_difference():
+    """Adjoint workload slice (Nk=3, o=10, v=60, Naux=210): d alpha_zz(0.0656) / d f at the device
+    CCSD amplitudes against the central difference of alpha_zz at f +- h df with h = 1e-5 (the
+    amplitudes held at their input values and lambda re-solved, as the gradient is defined),
+    along a Hermitian k-diagonal df with off-diagonal elements.  The oracle's own gradient at
+    this size would take hours of host time (each oracle alpha needs tens of its ~10 s k-blocked
+    residual evaluations per solve); the small sizes compare it with the oracle directly."""
+    import paper_2508_01266_amd as lr
+    w = synth.WORKLOADS["c4s"]
+    rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+    H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=w.chol_sigma)
+    dF = 0.1 * synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, synth.rng_for(96, w.nk, w.nocc, w.nvir))['dip'][0]
+    c = lr.Context(0)
+    c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+    t1, t2, e, rep = c.solve_ccsd(tol=1e-10, max_iter=300)
+    print(f"c4s CCSD: E/cell {e:.10f} {rep}", flush=True)
+    om = [0.0656]
+    a0, r0 = c.solve(om, axis_mask=4, tol=1e-12, precision=lr.FP64)
+    g = c.alpha_fock_gradient(0, 2, 2, tol=1e-12)
+    got = np.sum(g * dF)
+    h = 1e-5
+    vals = []
+    for sgn in (1, -1):
+        c2 = lr.Context(0)
+        c2.set_hamiltonian(w.nocc, H['fock'] + sgn * h * dF, H['chol'], H['dip'])
+        c2.set_amplitudes(t1, t2)
+        a, _ = c2.solve(om, axis_mask=4, tol=1e-12, precision=lr.FP64)
+        vals.append(a[0, 2, 2])
+        c2.close()
+    ref = (vals[0] - vals[1]) / (2 * h)
+    err = abs(got - ref)
+    print(f"c4s d alpha_zz / df . dF: gradient {got:.10f} central difference (h=1e-5) {ref:.10f} "
+          f"err {err:.2e}", flush=True)
+    # O(h^2) truncation (~1e-10 relative) plus the solver tolerance divided by h (1e-12 |alpha| / 1e-5)
+    assert err < 1e-5 * max(1.0, abs(ref))
     c.close()

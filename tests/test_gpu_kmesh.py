@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.sigma_cases import make_case, make_ccsd_case, oracle_alpha, oracle_sigma, oracle_sigma_adjoint
+from tests.sigma_cases import FP32_REL, make_case, make_ccsd_case, oracle_alpha, oracle_sigma, oracle_sigma_adjoint
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def test_sigma_on_mesh_matches_oracle(mesh, o, v, naux, nrhs, seed):
     case = make_case(nk, o, v, naux, nrhs, 300 + seed, mesh=mesh)
     print(f"mesh {mesh} o={o} v={v} naux={naux} nrhs={nrhs}", flush=True)
     ref1, ref2 = oracle_sigma(case)
-    tol32 = 4 * nk * v * v * 2.0 ** -24 + 1e-6
+    tol32 = FP32_REL
     for mode, name in MODES.items():
         c = _ctx(case, mode)
         y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)

@@ -3,7 +3,7 @@ exact-stencil Jacobian-vector product, element by element."""
 import numpy as np
 import pytest
 
-from tests.sigma_cases import make_case, oracle_sigma
+from tests.sigma_cases import FP32_REL, make_case, oracle_sigma
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +60,7 @@ def test_sigma_fp32_matches_oracle(nk, o, v, naux, nrhs, seed):
     import paper_2508_01266_amd as lr
     case = make_case(nk, o, v, naux, nrhs, seed)
     ref1, ref2 = oracle_sigma(case)
-    # complex64 accumulation over the longest contraction (K = nk*v*v of the ladder)
-    tol = 4 * nk * v * v * 2.0 ** -24 + 1e-6
+    tol = FP32_REL
     for mode, name in MODES.items():
         c = _ctx(case, mode)
         y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP32)
@@ -104,7 +103,7 @@ def test_sigma_adjoint_fp64_matches_oracle_and_dot_identity(nk, o, v, naux, nrhs
         print(f"adjoint fp64 ({name} ladder) rel err singles {e1:.2e} doubles {e2:.2e}", flush=True)
         assert e1 < 1e-11 and e2 < 1e-11
         b1, b2 = c.apply_sigma_adjoint(z1, z2, case['omega'], lr.FP32)
-        tol = 4 * nk * v * v * 2.0 ** -24 + 1e-6
+        tol = FP32_REL
         assert _rel(b1, ref1) < tol and _rel(b2, ref2) < tol
         c.close()
 
@@ -127,7 +126,7 @@ def test_every_launch_variant_matches_oracle(tmp_path, monkeypatch, prec_name):
     z2 = z2 * nk
     adj1, adj2 = oracle_sigma_adjoint(case, z1, z2)
     prec = lr.FP64 if prec_name == "fp64" else lr.FP32
-    tol = 1e-11 if prec_name == "fp64" else 4 * nk * v * v * 2.0 ** -24 + 1e-6
+    tol = 1e-11 if prec_name == "fp64" else FP32_REL
     c = _ctx(case)
     c.set_autotune(True)
     c.apply_sigma(case['x1'], case['x2'], case['omega'], prec)
@@ -204,3 +203,32 @@ def test_autotuned_variants_match_and_cache(tmp_path, monkeypatch):
     z1, z2 = c2.apply_sigma(case['x1'], case['x2'], case['omega'], lr.FP64)
     assert _rel(z1, ref1) < 1e-11 and _rel(z2, ref2) < 1e-11
     assert cache.read_text() == text       # second context read the cache, tuned nothing new
+
+
+# non-canonical Fock matrices: off-diagonal f_ov, f_oo and f_vv enter F_ae, F_mi, F_me and the
+# singles driver; the oracle's residual keeps the full f
+NONCANONICAL = [(1, 2, 4, 6, 2, 41), (2, 3, 5, 7, 3, 42), (3, 2, 3, 5, 40, 43)]
+
+
+@pytest.mark.parametrize("nk,o,v,naux,nrhs,seed", NONCANONICAL)
+def test_sigma_noncanonical_fock_matches_oracle(nk, o, v, naux, nrhs, seed):
+    import paper_2508_01266_amd as lr
+    from tests.sigma_cases import oracle_sigma_adjoint
+    case = make_case(nk, o, v, naux, nrhs, seed, noncanonical=0.05)
+    f = case['H']['fock']
+    off = max(np.abs(f[k] - np.diag(np.diag(f[k]))).max() for k in range(nk))
+    print(f"case nk={nk} o={o} v={v} nrhs={nrhs}: largest off-diagonal |f| {off:.3f}", flush=True)
+    assert off > 0.01
+    ref1, ref2 = oracle_sigma(case)
+    z1, z2 = case['x1'][::-1].copy(), case['x2'][::-1].copy()
+    adj1, adj2 = oracle_sigma_adjoint(case, z1, z2)
+    for mode, name in MODES.items():
+        c = _ctx(case, mode)
+        for prec, tol in ((lr.FP64, 1e-11), (lr.FP32, FP32_REL)):
+            y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], prec)
+            g1, g2 = c.apply_sigma_adjoint(z1, z2, case['omega'], prec)
+            e = (_rel(y1, ref1), _rel(y2, ref2), _rel(g1, adj1), _rel(g2, adj2))
+            print(f"{name} ladder, precision {prec}: sigma {e[0]:.1e} {e[1]:.1e} transpose {e[2]:.1e} {e[3]:.1e}",
+                  flush=True)
+            assert max(e) < tol
+        c.close()
