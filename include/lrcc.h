@@ -142,6 +142,25 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
                                  const void *x1, const void *x2, void *y1, void *y2,
                                  int precision, void *stream);
 
+/* lrcc_apply_sigma_dev for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sigma, with the program's work tensors and launch tables placed in a
+ * static device array of the library (256 MiB; each device the library runs on
+ * holds one until the process ends) instead of context-owned allocations.  The
+ * call allocates nothing: it synchronizes `stream` (the previous call on it may
+ * still read the array), records the program into the array (launch tables by
+ * synchronous host-to-device copies), and enqueues it on `stream`; no autotuning,
+ * graph replay or profiling events.  Every call on a device shares that device's
+ * array and overwrites it: calls that overlap on one device (other streams, other
+ * threads, other contexts) race.  The context's amplitude-dependent blocks come
+ * from lrcc_set_amplitudes as for the other calls.  LRCC_E_OOM, before any launch,
+ * when the work tensors of nrhs right-hand sides exceed the array (about
+ * 3 nrhs nk^3 o^2 v^2 complex elements of the precision, plus tables); other
+ * errors as for lrcc_apply_sigma_dev.  Results equal lrcc_apply_sigma_dev's with
+ * the same launch variants. */
+lrcc_status lrcc_apply_sigma_dev_noalloc(lrcc_ctx *ctx, int nrhs, const double *omega, const void *x1,
+                                         const void *x2, void *y1, void *y2, int precision, void *stream);
+
 /* Kernel timing with HIP events recorded on the launch stream.  While enabled,
  * every sigma application records an event pair around each ladder launch and
  * around the whole application.  lrcc_read_profile waits for the recorded

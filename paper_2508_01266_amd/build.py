@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblrcc.so")
-SOURCES = ["gemm.hip", "ladder.hip", "elem.hip", "solver.hip", "peak.hip", "plan.cpp", "eig.cpp", "lrcc.cpp"]
+SOURCES = ["gemm.hip", "ladder.hip", "elem.hip", "solver.hip", "peak.hip", "noalloc.hip", "plan.cpp", "eig.cpp",
+           "lrcc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

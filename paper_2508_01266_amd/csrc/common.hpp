@@ -13,6 +13,18 @@ typedef long long i64;
 // copies or launches happen, and every recorded GEMM is bounds-checked.
 extern bool g_dry_run;
 
+// Device-memory arena: between arena_begin and arena_end, dev_alloc hands out 256-byte-aligned
+// pieces of [base, base + size) instead of calling hipMalloc (LRCC_E_OOM past the end), and
+// dev_free ignores pointers inside any registered arena.
+void arena_register(void *base, size_t size);
+void arena_begin(void *base, size_t size);
+void arena_end();
+size_t arena_used();
+bool in_arena(const void *p);
+// The static device array of the no-allocation entry point on device `dev` (its address from
+// hipGetSymbolAddress, taken once per device with that device current) and its size.
+void *noalloc_scratch(int dev, size_t *bytes);
+
 
 // Crystal-momentum mesh Z_n0 x Z_n1 x Z_n2: momentum is conserved modulo a
 // reciprocal-lattice vector (Eq. momentum), so k points add componentwise,

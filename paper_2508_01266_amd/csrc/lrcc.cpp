@@ -54,7 +54,7 @@ struct DevMem {
     }
     void release() {
         if (!dry)
-            for (void *p : ptrs) (void)hipFree(p);
+            for (void *p : ptrs) dev_free(p);   // (pieces of a static arena are not freed)
         ptrs.clear();
     }
     ~DevMem() { release(); }
@@ -3534,6 +3534,34 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *c, int nrhs, const double *omega, con
         Program *p = sigma_program(c, precision, nrhs);
         c->io_x1 = x1; c->io_x2 = x2; c->io_y1 = y1; c->io_y2 = y2; c->io_omega = omega;
         HIPCHK(run_sigma(c, p, (hipStream_t)stream));
+    });
+}
+
+lrcc_status lrcc_apply_sigma_dev_noalloc(lrcc_ctx *c, int nrhs, const double *omega, const void *x1,
+                                         const void *x2, void *y1, void *y2, int precision, void *stream) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (nrhs < 1 || !x1 || !x2 || !y1 || !y2) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
+        if (precision != LRCC_FP64 && precision != LRCC_FP32) throw LrccError(LRCC_E_ARG, "unknown precision");
+        hipStream_t st = (hipStream_t)stream;
+        size_t cap = 0;
+        void *base = noalloc_scratch(c->dev, &cap);
+        // the previous call on this stream may still read the array the recording overwrites
+        HIPCHK(hipStreamSynchronize(st));
+        // record the sigma program with every device allocation taken from the static array
+        std::unique_ptr<Program> p;
+        DevMem wm;
+        arena_begin(base, cap);
+        try {
+            p.reset(precision == LRCC_FP64 ? build_sigma<double>(c, c->s64, nrhs, wm)
+                                           : build_sigma<float>(c, c->s32, nrhs, wm));
+        } catch (...) {
+            arena_end();
+            throw;
+        }
+        arena_end();
+        c->io_x1 = x1; c->io_x2 = x2; c->io_y1 = y1; c->io_y2 = y2; c->io_omega = omega;
+        HIPCHK(p->run(st));
     });
 }
 

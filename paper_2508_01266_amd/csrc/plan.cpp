@@ -22,8 +22,36 @@ namespace {
 std::uintptr_t g_fake_next = 0x100000;
 }
 
+namespace {
+struct ArenaState {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+};
+ArenaState g_arena;                                   // active arena (base null: none)
+std::vector<std::pair<const char *, size_t>> g_arenas;   // every registered arena range
+}
+
+void arena_register(void *base, size_t size) { g_arenas.push_back({(const char *)base, size}); }
+void arena_begin(void *base, size_t size) { g_arena = ArenaState{(char *)base, size, 0}; }
+void arena_end() { g_arena = ArenaState{}; }
+size_t arena_used() { return g_arena.used; }
+bool in_arena(const void *p) {
+    for (const auto &a : g_arenas)
+        if ((const char *)p >= a.first && (const char *)p < a.first + a.second) return true;
+    return false;
+}
+
 void *dev_alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
+    if (g_arena.base) {
+        const size_t need = (bytes + 255) / 256 * 256;
+        if (g_arena.used + need > g_arena.size)
+            throw LrccError(4, "the work tensors need more than the " + std::to_string(g_arena.size) +
+                                   "-byte static device array");
+        void *p = g_arena.base + g_arena.used;
+        g_arena.used += need;
+        return p;
+    }
     if (g_dry_run) {
         void *p = reinterpret_cast<void *>(g_fake_next);
         g_fake_next += (bytes + 4095) / 4096 * 4096 + 4096;
@@ -36,7 +64,7 @@ void *dev_alloc(size_t bytes) {
 }
 
 void dev_free(void *p) {
-    if (!g_dry_run && p) {
+    if (!g_dry_run && p && !in_arena(p)) {
         hipError_t e = hipFree(p);
         (void)e;
     }

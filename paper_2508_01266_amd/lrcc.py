@@ -39,6 +39,8 @@ def lib():
         L.lrcc_set_amplitudes.argtypes = [vp, vp, vp]
         L.lrcc_apply_sigma.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
         L.lrcc_apply_sigma_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
+        L.lrcc_apply_sigma_dev_noalloc.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
+        L.lrcc_apply_sigma_dev_noalloc.restype = ctypes.c_int
         L.lrcc_apply_sigma_adjoint.argtypes = [vp, i, vp, vp, vp, vp, vp, i]
         L.lrcc_apply_sigma_adjoint_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
         L.lrcc_sigma_vjp_dev.argtypes = [vp, i, vp, vp, vp, vp, vp, i, vp]
@@ -391,6 +393,16 @@ class Context:
         f = self._L.lrcc_apply_sigma_adjoint_dev if adjoint else self._L.lrcc_apply_sigma_dev
         st = f(
             self._h, R, None if omega is None else ctypes.c_void_p(omega.data_ptr()),
+            ctypes.c_void_p(x1.data_ptr()), ctypes.c_void_p(x2.data_ptr()),
+            ctypes.c_void_p(y1.data_ptr()), ctypes.c_void_p(y2.data_ptr()), int(precision),
+            None if stream is None else ctypes.c_void_p(stream))
+        self._check(st)
+
+    def apply_sigma_dev_noalloc(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None):
+        """lrcc_apply_sigma_dev without device allocation (work tensors in the library's static
+        device array); torch tensors as for apply_sigma_dev."""
+        st = self._L.lrcc_apply_sigma_dev_noalloc(
+            self._h, x1.shape[0], None if omega is None else ctypes.c_void_p(omega.data_ptr()),
             ctypes.c_void_p(x1.data_ptr()), ctypes.c_void_p(x2.data_ptr()),
             ctypes.c_void_p(y1.data_ptr()), ctypes.c_void_p(y2.data_ptr()), int(precision),
             None if stream is None else ctypes.c_void_p(stream))
