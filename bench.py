@@ -8,8 +8,9 @@ right-hand sides in one launch, computed on the matrix cores in complex64
 (split into real fp32 MFMA products).  The FP64 form of the same batch is
 timed beside it.  Then the device CCSD ground state of the same Hamiltonian and
 the time to converged alpha(omega) for all 48 right-hand sides, mixed and FP64
-(--no-alpha skips it; --alpha-stored repeats both solves with the ladder
-integral blocks stored, ladder mode 2).  Prints one JSON line.
+(--no-alpha skips it; --alpha-modes 2,3 repeats both solves in other ladder
+modes).  The sigma is also timed with the ladder integral blocks stored (ladder
+mode 2) and built one momentum class at a time (mode 3).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,19 +27,32 @@ METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1
 
 # HBM traffic of one complex64 ladder launch on the batched workload, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the counter's reading for a plain 2 GiB copy
-# (fetch x2.0, write x1.0).  Valid only for the ladder sources it was measured on.
-LADDER_TRAFFIC = {"workload": "c3",
+# (fetch x2.0, write x1.0).  Valid only for the ladder path and kernel sources it was measured on.
+LADDER_TRAFFIC = {"workload": "c3", "ladder_path": 1,
                   "sources_sha256": "70768cb8f9a608446e77a307d05bd301b0bdea5c2e8cf2ad6fdba3c89bfb9542",
                   "bytes": 687.8e9}
 
 
-def ladder_sources_sha():
+LADDER_PATH_TEXT = {1: "ladder integrals rebuilt in LDS from the Cholesky vectors",
+                    2: "ladder integral blocks stored for the unique momentum pairs",
+                    3: "ladder integral blocks built from the Cholesky vectors one momentum class at a time "
+                       "in every application"}
+LADDER_KERNEL = {1: "ladder_kernel_pipe (one launch, integrals rebuilt in LDS)",
+                 2: "gemm_kernel<..., 1, ...> over the stored blocks (one launch)",
+                 3: "gemm_kernel<..., 1, ...> over the class-built blocks (one launch per momentum class)"}
+
+
+def ladder_sources_sha(path):
+    """sha256 of the kernel sources of a ladder path: the ladder kernels (path 1) or the GEMM
+    kernel (paths 2 and 3), with the shared header."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("ladder.hip", "common.hpp"):
+    for f in ("ladder.hip" if path == 1 else "gemm.hip", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2508_01266_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
 PEAK = {"f32": 157.3, "f64": 78.6}          # MI355X dense matrix-core TFLOP/s
 
 
@@ -110,7 +124,11 @@ def time_sigma(ctx, x1, x2, y1, y2, om, prec, steps, warmup, torch):
     t1 = time.perf_counter()
     ctx.set_profiling(False)
     prof = ctx.read_profile()
-    return (t1 - t0) / steps, prof
+    # per application: seconds of the ladder products (one launch with the integrals rebuilt in
+    # LDS or stored, one per momentum class when the blocks are built by class), launches, and
+    # seconds of the class builds of the blocks
+    return ((t1 - t0) / steps, prof["ladder"][0] / 1e3 / steps, prof["ladder"][1] / steps,
+            prof["ladder_build"][0] / 1e3 / steps)
 
 
 def mesh_sigma(lr, torch, steps, mesh=(2, 2, 2), nocc=8, nvir=40, naux=144, nfreq=2):
@@ -140,10 +158,10 @@ def mesh_sigma(lr, torch, steps, mesh=(2, 2, 2), nocc=8, nvir=40, naux=144, nfre
     out = {"mesh": list(mesh), "nk": nk, "nocc": nocc, "nvir": nvir, "naux": naux, "nrhs": R,
            "algorithmic_flops_per_step": alg}
     for prec, name in ((lr.FP32, "f32"), (lr.FP64, "f64")):
-        dt, prof = time_sigma(ctx, X1, X2, Y1, Y2, OM, prec, steps, 1, torch)
-        lad = prof["ladder"][0] / max(prof["ladder"][1], 1) / 1e3
-        out[name] = {"ms_per_step": dt * 1e3, "value": alg / dt / 1e12, "ladder_ms_avg": lad * 1e3,
-                     "ladder_frac": ctx.ladder_flops(R, prec) / lad / 1e12 / PEAK[name]}
+        dt, lad, _, bld = time_sigma(ctx, X1, X2, Y1, Y2, OM, prec, steps, 1, torch)
+        out[name] = {"ms_per_step": dt * 1e3, "value": alg / dt / 1e12, "ladder_ms_per_step": lad * 1e3,
+                     "ladder_build_ms_per_step": bld * 1e3, "ladder_path": ctx.ladder_path(R, prec),
+                     "ladder_executed_frac": ctx.ladder_flops(R, prec) / lad / 1e12 / PEAK[name]}
         log(f"mesh {mesh} sigma ({name}): {dt * 1e3:.1f} ms")
     ctx.close()
     return out
@@ -215,55 +233,65 @@ def latency_small(lr, torch, reps=50):
 
 def uneven_batch(lr, torch, steps):
     """Uneven batch of twelve chains (Nk in {3,5,7,9}, 12 right-hand sides each): complex64
-    sigma of every chain, one after another vs all together with one persistent ladder launch."""
+    sigma of every chain with the integrals rebuilt in LDS (ladder mode 1), one after another vs
+    all together with one persistent ladder launch; then one after another in the default mode."""
     import numpy as np
     import synth
     chains = synth.uneven_batch()
     dev = torch.device("cuda:0")
-    ctxs, X1, X2, Y1, Y2, OM = [], [], [], [], [], []
-    alg = 0.0
-    for i, w in enumerate(chains):
-        rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir, (i,))
-        H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=0.02)
-        t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
-        x1, x2 = synth.random_vectors(12, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
-        c = lr.Context(0)
-        c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
-        c.set_amplitudes(t1, t2 * w.nk)
-        ctxs.append(c)
-        X1.append(torch.from_numpy(x1).to(dev)); X2.append(torch.from_numpy(x2 * w.nk).to(dev))
-        Y1.append(torch.empty_like(X1[-1])); Y2.append(torch.empty_like(X2[-1]))
-        om = np.array([f for _ in range(3) for f in w.omegas])
-        OM.append(torch.from_numpy(om).to(dev))
-        alg += 12 * sigma_alg_flops(w.nk, w.nocc, w.nvir)
-        log(f"chain {i}: Nk={w.nk} nocc={w.nocc} nvir={w.nvir} Naux={w.naux}")
     st = torch.cuda.current_stream().cuda_stream
-    g = lr.Group(ctxs)
-
-    def seq():
-        for i, c in enumerate(ctxs):
-            c.apply_sigma_dev(X1[i], X2[i], Y1[i], Y2[i], OM[i], lr.FP32, st)
-
-    def grp():
-        g.apply_sigma_dev(X1, X2, Y1, Y2, OM, lr.FP32, st)
-
     out = {}
-    for name, fn in (("one_after_another", seq), ("one_persistent_ladder", grp)):
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+    for mode in (1, 0):
+        ctxs, X1, X2, Y1, Y2, OM = [], [], [], [], [], []
+        alg = 0.0
+        for i, w in enumerate(chains):
+            rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir, (i,))
+            H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=0.02)
+            t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
+            x1, x2 = synth.random_vectors(12, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
+            c = lr.Context(0)
+            c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+            c.set_ladder_mode(mode)
+            c.set_amplitudes(t1, t2 * w.nk)
+            ctxs.append(c)
+            X1.append(torch.from_numpy(x1).to(dev)); X2.append(torch.from_numpy(x2 * w.nk).to(dev))
+            Y1.append(torch.empty_like(X1[-1])); Y2.append(torch.empty_like(X2[-1]))
+            om = np.array([f for _ in range(3) for f in w.omegas])
+            OM.append(torch.from_numpy(om).to(dev))
+            alg += 12 * sigma_alg_flops(w.nk, w.nocc, w.nvir)
+            if mode == 1:
+                log(f"chain {i}: Nk={w.nk} nocc={w.nocc} nvir={w.nvir} Naux={w.naux}")
+        g = lr.Group(ctxs)
+
+        def seq():
+            for i, c in enumerate(ctxs):
+                c.apply_sigma_dev(X1[i], X2[i], Y1[i], Y2[i], OM[i], lr.FP32, st)
+
+        def grp():
+            g.apply_sigma_dev(X1, X2, Y1, Y2, OM, lr.FP32, st)
+
+        legs = (("one_after_another", seq), ("one_persistent_ladder", grp)) if mode == 1 else \
+            (("one_after_another_default_mode", seq),)
+        for name, fn in legs:
             fn()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        out[name] = {"ms_per_step": dt * 1e3, "tflops_algorithmic": alg / dt / 1e12}
-        log(f"uneven batch, {name}: {dt * 1e3:.1f} ms")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            out[name] = {"ms_per_step": dt * 1e3, "tflops_algorithmic": alg / dt / 1e12}
+            log(f"uneven batch, {name}: {dt * 1e3:.1f} ms")
+        if mode == 0:
+            out["default_mode_ladder_paths"] = [c.ladder_path(12, lr.FP32) for c in ctxs]
+        g.close()
+        for c in ctxs:
+            c.close()
+        del X1, X2, Y1, Y2, OM
+        torch.cuda.empty_cache()
     out["chains"] = [[w.nk, w.nocc, w.nvir, w.naux] for w in chains]
     out["nrhs_per_chain"] = 12
     out["speedup"] = out["one_after_another"]["ms_per_step"] / out["one_persistent_ladder"]["ms_per_step"]
-    g.close()
-    for c in ctxs:
-        c.close()
     return out
 
 
@@ -301,8 +329,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-alpha", action="store_true",
                     help="skip the time to converged alpha (device CCSD, then the mixed and FP64 solves)")
-    ap.add_argument("--alpha-stored", action="store_true",
-                    help="also time both alpha solves with the ladder integral blocks stored (ladder mode 2)")
+    ap.add_argument("--alpha-modes", type=lambda t: [int(x) for x in t.split(",") if x], default=[],
+                    help="comma-separated ladder modes (2 stored, 3 built by momentum class) in which both "
+                         "alpha solves are timed again after the headline mode")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="time the headline ladder path only (no other ladder paths, latency probe or peaks)")
+    ap.add_argument("--ladder-mode", type=int, default=0,
+                    help="ladder mode of the headline context (0 automatic, 1 rebuilt in LDS, 2 stored, "
+                         "3 built by momentum class)")
     ap.add_argument("--alpha-tol", type=float, default=1e-10)
     ap.add_argument("--ccsd-iter", type=int, default=300)
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch variants instead of autotuning")
@@ -329,6 +363,7 @@ def main():
     dev = torch.device("cuda:0")
     ctx = lr.Context(0)
     ctx.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+    ctx.set_ladder_mode(args.ladder_mode)
     ctx.set_amplitudes(t1, t2)
     ctx.set_autotune(not (args.no_tune or args.counters))   # the warm-up application picks the variants
     X1 = torch.from_numpy(x1).to(dev)
@@ -353,25 +388,24 @@ def main():
     alg = nrhs * sigma_alg_flops(nk, o, v)
     lad = nrhs * ladder_alg_flops(nk, o, v)
     log("context ready; timing complex64 sigma")
-    dt32, prof32 = time_sigma(ctx, X1, X2, Y1, Y2, OM, lr.FP32, args.steps, args.warmup, torch)
+    dt32, lad_s, lad_n, bld_s = time_sigma(ctx, X1, X2, Y1, Y2, OM, lr.FP32, args.steps, args.warmup, torch)
     log(f"complex64 sigma {dt32*1e3:.1f} ms; timing complex128 sigma")
-    dt64, prof64 = time_sigma(ctx, X1, X2, Y1, Y2, OM, lr.FP64, args.fp64_steps, 1, torch)
-    lad_ms, lad_n = prof32["ladder"]
-    lad_avg = lad_ms / max(lad_n, 1) / 1e3
-    lad64_ms, lad64_n = prof64["ladder"]
-    lad64_avg = lad64_ms / max(lad64_n, 1) / 1e3
-    # roofline of the ladder launch: the method's own work (unique antisymmetric index pairs, the
-    # in-LDS integral rebuild counted as overhead) per second against the matrix-core peak; the
-    # products the kernel executes (rebuild and tile padding included) and its matrix-core
-    # instructions are reported beside it
+    dt64, lad64_s, lad64_n, bld64_s = time_sigma(ctx, X1, X2, Y1, Y2, OM, lr.FP64, args.fp64_steps, 1, torch)
+    path, path64 = ctx.ladder_path(nrhs, lr.FP32), ctx.ladder_path(nrhs, lr.FP64)
+    # roofline of the ladder products: the method's own work (unique antisymmetric index pairs)
+    # per second of the ladder launches against the matrix-core peak.  Integral rebuilds are
+    # overhead: inside the kernel with the integrals rebuilt in LDS, separate launches (reported
+    # beside, and in frac_with_builds) when the blocks are built by momentum class.  The products
+    # the launches execute (rebuild and padding included) and their matrix-core instructions are
+    # reported beside it
     lad_unique = ladder_unique_flops(nk, o, v, nrhs)
     lad_exec = ctx.ladder_flops(nrhs, lr.FP32)
     lad_exec64 = ctx.ladder_flops(nrhs, lr.FP64)
     lad_mfma = ctx.ladder_mfma_flops(nrhs, lr.FP32)
-    achieved = lad_unique / lad_avg / 1e12
+    achieved = lad_unique / lad_s / 1e12
     traffic = None
     if (args.workload == LADDER_TRAFFIC["workload"] and LADDER_TRAFFIC["bytes"] is not None
-            and LADDER_TRAFFIC["sources_sha256"] == ladder_sources_sha()):
+            and LADDER_TRAFFIC["ladder_path"] == path and LADDER_TRAFFIC["sources_sha256"] == ladder_sources_sha(path)):
         traffic = LADDER_TRAFFIC["bytes"]
     out = {
         "metric": METRIC,
@@ -388,55 +422,73 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: 1D chain Nk={nk}, nocc={o}, nvir={v}, Naux={w.naux}, "
                                f"{nrhs} right-hand sides (3 axes x +-omega x {len(w.omegas)} frequencies) "
-                               f"in one sigma launch, complex64 on the matrix cores, ladder integrals rebuilt "
-                               f"in LDS from the Cholesky vectors",
-                   "nk": nk, "nocc": o, "nvir": v, "naux": w.naux, "nrhs": nrhs},
+                               f"in one sigma launch, complex64 on the matrix cores, {LADDER_PATH_TEXT[path]}",
+                   "nk": nk, "nocc": o, "nvir": v, "naux": w.naux, "nrhs": nrhs,
+                   "ladder_mode": args.ladder_mode, "ladder_path": path},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32"], "traffic": traffic, "kernel": "ladder",
-                     "work": "unique antisymmetric pairs (rows, outputs, inputs); integral rebuild is overhead",
-                     "unique_flops_per_launch": lad_unique, "ladder_ms_avg": lad_avg * 1e3,
-                     "executed_flops_per_launch": lad_exec, "executed_frac": lad_exec / lad_avg / 1e12 / PEAK["f32"],
-                     "mfma_flops_per_launch": lad_mfma, "mfma_frac": lad_mfma / lad_avg / 1e12 / PEAK["f32"],
-                     "full_range_flops_per_launch": lad, "full_range_tflops": lad / lad_avg / 1e12},
+                     "frac": achieved / PEAK["f32"], "traffic": traffic, "kernel": LADDER_KERNEL[path],
+                     "work": "unique antisymmetric pairs (rows, outputs, inputs); integral rebuilds are overhead",
+                     "unique_flops_per_step": lad_unique, "launches_per_step": lad_n,
+                     "ladder_ms_avg": lad_s / lad_n * 1e3, "ladder_ms_per_step": lad_s * 1e3,
+                     "build_ms_per_step": bld_s * 1e3,
+                     "frac_with_builds": lad_unique / (lad_s + bld_s) / 1e12 / PEAK["f32"],
+                     "executed_flops_per_step": lad_exec, "executed_frac": lad_exec / lad_s / 1e12 / PEAK["f32"],
+                     "mfma_flops_per_step": lad_mfma, "mfma_frac": lad_mfma / lad_s / 1e12 / PEAK["f32"],
+                     "full_range_flops_per_step": lad, "full_range_tflops": lad / lad_s / 1e12},
         "fp64": {"value": alg / dt64 / 1e12, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
-                 "ladder_ms_avg": lad64_avg * 1e3, "ladder_achieved": lad_unique / lad64_avg / 1e12,
-                 "ladder_frac": lad_unique / lad64_avg / 1e12 / PEAK["f64"],
-                 "ladder_executed_frac": lad_exec64 / lad64_avg / 1e12 / PEAK["f64"], "peak": PEAK["f64"]},
+                 "ladder_path": path64, "ladder_ms_per_step": lad64_s * 1e3, "build_ms_per_step": bld64_s * 1e3,
+                 "ladder_achieved": lad_unique / lad64_s / 1e12,
+                 "ladder_frac": lad_unique / lad64_s / 1e12 / PEAK["f64"],
+                 "ladder_frac_with_builds": lad_unique / (lad64_s + bld64_s) / 1e12 / PEAK["f64"],
+                 "ladder_executed_frac": lad_exec64 / lad64_s / 1e12 / PEAK["f64"], "peak": PEAK["f64"]},
         "executed_flops_per_step": {"f32": ctx.sigma_flops(nrhs, lr.FP32), "f64": ctx.sigma_flops(nrhs, lr.FP64)},
         "algorithmic_flops_per_step": alg,
         "speedup_mixed_vs_fp64_sigma": dt64 / dt32,
     }
     log(f"complex128 sigma {dt64*1e3:.1f} ms")
-    # the same sigma with the ladder integrals stored (unique momentum pairs, antisymmetrised)
-    # instead of rebuilt in LDS: one dense matrix-core GEMM for the ladder
-    ctx2 = lr.Context(0)
-    ctx2.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
-    ctx2.set_ladder_mode(2)
-    ctx2.set_amplitudes(t1, t2)
-    ctx2.set_autotune(not args.no_tune)
-    s32, sp32 = time_sigma(ctx2, X1, X2, Y1, Y2, OM, lr.FP32, args.steps, args.warmup, torch)
-    s64, sp64 = time_sigma(ctx2, X1, X2, Y1, Y2, OM, lr.FP64, args.fp64_steps, 1, torch)
-    sl32 = sp32["ladder"][0] / max(sp32["ladder"][1], 1) / 1e3
-    sl64 = sp64["ladder"][0] / max(sp64["ladder"][1], 1) / 1e3
-    out["stored_integrals"] = {
-        "ms_per_step": s32 * 1e3, "value": alg / s32 / 1e12, "ladder_ms_avg": sl32 * 1e3,
-        "ladder_achieved": lad_unique / sl32 / 1e12, "ladder_frac": lad_unique / sl32 / 1e12 / PEAK["f32"],
-        "ladder_executed_frac": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12 / PEAK["f32"],
-        "fp64_ms_per_step": s64 * 1e3, "fp64_value": alg / s64 / 1e12, "fp64_ladder_ms_avg": sl64 * 1e3,
-        "fp64_ladder_frac": lad_unique / sl64 / 1e12 / PEAK["f64"],
-        "fp64_ladder_executed_frac": ctx2.ladder_flops(nrhs, lr.FP64) / sl64 / 1e12 / PEAK["f64"],
-        "note": "ladder mode 2: antisymmetrised integral blocks stored for unique momentum pairs "
-                "(0.9 GB complex64 + 1.8 GB complex128 here); the headline uses the default mode, "
-                "integrals rebuilt in LDS from the Cholesky vectors, nothing of vvvv size stored"}
-    log(f"stored-integral ladder: complex64 sigma {s32*1e3:.1f} ms, complex128 {s64*1e3:.1f} ms")
-    ctx2.close()
-    out["latency_c1_9rhs"] = latency_small(lr, torch)
-    # attainable ceilings on this device (project microbenchmarks), beside the published peaks
-    out["peaks_measured"] = lr.measure_peaks(0)
-    out["peaks_measured"]["published"] = {"mfma_f32_tflops": PEAK["f32"], "mfma_f64_tflops": PEAK["f64"],
-                                          "hbm_gbs": 8000.0}
-    log(f"measured peaks {out['peaks_measured']}")
-    log(f"c1 latency {out['latency_c1_9rhs']}")
+    # the same sigma along the other ladder paths: integrals rebuilt in LDS (1), stored for the
+    # unique momentum pairs once per amplitudes (2), built one momentum class at a time in every
+    # application (3)
+    notes = {1: "integrals rebuilt in LDS from the t1-dressed Cholesky vectors inside the ladder kernel; "
+                "nothing of vvvv size in memory",
+             2: "antisymmetrised integral blocks stored for unique momentum pairs, built once per "
+                "amplitudes (0.9 GB complex64 + 1.8 GB complex128 here)",
+             3: "the same blocks built in every application, one momentum class ka + kb at a time, into "
+                "a scratch array of one class (184 MB complex64, 368 MB complex128 here) that the class's "
+                "GEMM consumes"}
+    for mode, key in ((1, "rebuilt_in_lds"), (2, "stored_integrals"), (3, "class_integrals")):
+        if mode == path or args.no_legs:
+            continue
+        ctx2 = lr.Context(0)
+        ctx2.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
+        ctx2.set_ladder_mode(mode)
+        ctx2.set_amplitudes(t1, t2)
+        ctx2.set_autotune(not args.no_tune)
+        s32, sl32, _, sb32 = time_sigma(ctx2, X1, X2, Y1, Y2, OM, lr.FP32, args.steps, args.warmup, torch)
+        s64, sl64, _, sb64 = time_sigma(ctx2, X1, X2, Y1, Y2, OM, lr.FP64, args.fp64_steps, 1, torch)
+        out[key] = {
+            "ladder_mode": mode,
+            "ms_per_step": s32 * 1e3, "value": alg / s32 / 1e12, "ladder_ms_per_step": sl32 * 1e3,
+            "build_ms_per_step": sb32 * 1e3,
+            "ladder_achieved": lad_unique / sl32 / 1e12, "ladder_frac": lad_unique / sl32 / 1e12 / PEAK["f32"],
+            "ladder_frac_with_builds": lad_unique / (sl32 + sb32) / 1e12 / PEAK["f32"],
+            "ladder_executed_frac": ctx2.ladder_flops(nrhs, lr.FP32) / sl32 / 1e12 / PEAK["f32"],
+            "fp64_ms_per_step": s64 * 1e3, "fp64_value": alg / s64 / 1e12, "fp64_ladder_ms_per_step": sl64 * 1e3,
+            "fp64_build_ms_per_step": sb64 * 1e3,
+            "fp64_ladder_frac": lad_unique / sl64 / 1e12 / PEAK["f64"],
+            "fp64_ladder_frac_with_builds": lad_unique / (sl64 + sb64) / 1e12 / PEAK["f64"],
+            "fp64_ladder_executed_frac": ctx2.ladder_flops(nrhs, lr.FP64) / sl64 / 1e12 / PEAK["f64"],
+            "note": f"ladder mode {mode}: {notes[mode]}"}
+        log(f"ladder mode {mode}: complex64 sigma {s32*1e3:.1f} ms, complex128 {s64*1e3:.1f} ms")
+        ctx2.close()
+    if not args.no_legs:
+        out["latency_c1_9rhs"] = latency_small(lr, torch)
+        # attainable ceilings on this device (project microbenchmarks), beside the published peaks
+        out["peaks_measured"] = lr.measure_peaks(0)
+        out["peaks_measured"]["published"] = {"mfma_f32_tflops": PEAK["f32"], "mfma_f64_tflops": PEAK["f64"],
+                                              "hbm_gbs": 8000.0}
+        log(f"measured peaks {out['peaks_measured']}")
+        log(f"c1 latency {out['latency_c1_9rhs']}")
     del X1, X2, Y1, Y2, OM
     torch.cuda.empty_cache()
     if not args.no_alpha:
@@ -478,17 +530,20 @@ def main():
                                        for k in res},
             "reports": {k: res[k][2] for k in res},
         }
-    if not args.no_alpha and args.alpha_stored:
-        # the same solves with the ladder integral blocks stored (ladder mode 2, forward and
-        # transpose products): the one-vector transpose products of the lambda equations and of the
-        # F term are bound by the in-LDS rebuild at 64 rows, which the stored blocks remove
+    for mode in ([] if args.no_alpha else args.alpha_modes):
+        # the same solves in another ladder mode: the one-vector transpose products of the lambda
+        # equations and of the F term are bound by the integral rebuild at one right-hand side,
+        # which stored blocks (2) remove and class-built blocks (3) share over every row pair
+        if mode == args.ladder_mode:
+            continue
         am, af = res["mixed"][1], res["fp64"][1]
-        ctx.close()
-        ctx = None
+        if ctx is not None:
+            ctx.close()
+            ctx = None
         torch.cuda.empty_cache()
         cs = lr.Context(0)
         cs.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
-        cs.set_ladder_mode(2)
+        cs.set_ladder_mode(mode)
         cs.set_amplitudes(t1c, t2c)
         cs.set_autotune(not args.no_tune)
         # build and tune the 48-RHS programs outside the timed solves, as for the default context
@@ -503,15 +558,15 @@ def main():
         torch.cuda.empty_cache()
         rs = {}
         for name, prec in (("mixed", lr.FP32), ("fp64", lr.FP64)):
-            log(f"solving for alpha ({name}, stored ladder integrals)")
+            log(f"solving for alpha ({name}, ladder mode {mode})")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             al, rep = cs.solve(list(w.omegas), axis_mask=7, tol=args.alpha_tol, precision=prec, reuse_lambda=0)
             torch.cuda.synchronize()
             rs[name] = (time.perf_counter() - t0, al, rep)
-            log(f"alpha ({name}, stored ladder integrals) in {rs[name][0]:.1f} s: {rep}")
+            log(f"alpha ({name}, ladder mode {mode}) in {rs[name][0]:.1f} s: {rep}")
         cs.close()
-        out["alpha"]["stored_integrals"] = {
+        out["alpha"][f"ladder_mode_{mode}"] = {
             "s_to_alpha_mixed": rs["mixed"][0], "s_to_alpha_fp64": rs["fp64"][0],
             "max_abs_vs_default_fp64": float(np.abs(rs["fp64"][1] - af).max()),
             "max_abs_vs_default_mixed": float(np.abs(rs["mixed"][1] - am).max()),

@@ -84,6 +84,8 @@ typedef struct {
     double seconds;          /* wall time of the solve                                               */
     long long rhs_sigmas;    /* full-Jacobian products counted per right-hand side (forward, adjoint,
                                 both precisions): work in units of one single-RHS sigma               */
+    double phase_seconds[3]; /* lrcc_solve: wall time of the lambda solve, of the batched response
+                                solve (with eta), and of the F term and the contraction; 0 elsewhere */
 } lrcc_solve_report;
 
 /* Create a context on HIP device `hip_device`. *out is NULL on failure. */
@@ -156,8 +158,10 @@ lrcc_status lrcc_apply_sigma_dev(lrcc_ctx *ctx, int nrhs, const double *omega,
  * from lrcc_set_amplitudes as for the other calls.  LRCC_E_OOM, before any launch,
  * when the work tensors of nrhs right-hand sides exceed the array (about
  * 3 nrhs nk^3 o^2 v^2 complex elements of the precision, plus tables); other
- * errors as for lrcc_apply_sigma_dev.  Results equal lrcc_apply_sigma_dev's with
- * the same launch variants. */
+ * errors as for lrcc_apply_sigma_dev.  In the automatic ladder mode the call
+ * takes the integrals-rebuilt-in-LDS path (mode 1; mode 3 would put a momentum
+ * class of integral blocks in the array too).  Results equal
+ * lrcc_apply_sigma_dev's with the same ladder path and launch variants. */
 lrcc_status lrcc_apply_sigma_dev_noalloc(lrcc_ctx *ctx, int nrhs, const double *omega, const void *x1,
                                          const void *x2, void *y1, void *y2, int precision, void *stream);
 
@@ -165,23 +169,35 @@ lrcc_status lrcc_apply_sigma_dev_noalloc(lrcc_ctx *ctx, int nrhs, const double *
  * every sigma application records an event pair around each ladder launch and
  * around the whole application.  lrcc_read_profile waits for the recorded
  * events and returns, per category, the summed milliseconds and the number of
- * timed launches: index 0 unused, 1 = ladder kernel, 2 = whole sigma
- * application (arrays of 3); it then clears the record. */
+ * timed launches: index 0 unused, 1 = ladder products (one launch per
+ * application with the integrals rebuilt in LDS or stored, one per momentum
+ * class in ladder mode 3), 2 = whole sigma application, 3 = the integral-block
+ * builds of ladder mode 3 (two per momentum class) (arrays of 4); it then
+ * clears the record. */
 lrcc_status lrcc_set_profiling(lrcc_ctx *ctx, int enable);
 lrcc_status lrcc_read_profile(lrcc_ctx *ctx, double *ms, long long *count);
 
 /* How the ladder term (the vvvv contraction of Eq. tx2) obtains its integrals.
- * 0 (default) or 1: rebuilt in LDS from the t1-dressed Cholesky vectors inside
- * the ladder kernel, so nothing of vvvv size is ever stored.  2: stored blocks,
+ * 0 (default): automatic, per sigma program: mode 3 when one momentum class of
+ * blocks in the program's precision takes at most an eighth of the free device
+ * memory, else mode 1 (and mode 1 inside lrcc_apply_sigma_dev_noalloc).  1:
+ * rebuilt in LDS from the t1-dressed Cholesky vectors inside the ladder kernel,
+ * so nothing of vvvv size is ever stored.  2: stored blocks,
  * the antisymmetrised integrals for the unique momentum pairs (about Nk^3/4
  * blocks of nvir^4 complex values per precision, rebuilt with the other
  * amplitude-dependent blocks), after which the ladder is one dense matrix-core
  * GEMM; LRCC_E_OOM at lrcc_set_amplitudes if they would take more than half of
  * the free device memory.  The transpose product reads the same blocks in mode
  * 2 (a transposed GEMM over the unique momentum pairs into a scratch array of
- * the doubles' size, then an (e, f)-antisymmetric completion).  Must precede
- * the first lrcc_set_amplitudes or lrcc_solve_ccsd (LRCC_E_STATE afterwards);
- * LRCC_E_ARG for other modes. */
+ * the doubles' size, then an (e, f)-antisymmetric completion).  3: the same
+ * blocks built in every sigma application, one momentum class K = ka + kb at a
+ * time, into a scratch array of the largest class (about 1/Nk of the mode-2
+ * blocks) that the class's GEMM consumes before the next class is built; each
+ * block is rebuilt once per application for all row pairs ki + kj = K and all
+ * right-hand sides.  The per-sigma profile (lrcc_read_profile) counts the
+ * class builds and GEMMs as ladder launches.  Must precede the first
+ * lrcc_set_amplitudes or lrcc_solve_ccsd (LRCC_E_STATE afterwards); LRCC_E_ARG
+ * for other modes. */
 lrcc_status lrcc_set_ladder_mode(lrcc_ctx *ctx, int mode);
 
 /* Autotuning of launch variants: when enabled, the first application of each
@@ -205,18 +221,24 @@ lrcc_status lrcc_set_graphs(lrcc_ctx *ctx, int enable);
  * integral rebuild; streaming kernels excluded). */
 lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
 
-/* Real floating-point operations executed by the ladder launch of one sigma
+/* Real floating-point operations executed by the ladder products of one sigma
  * application (the profiling category 1 of lrcc_read_profile): the matrix-core
- * product over the unique momentum/index pairs when the integrals are stored,
- * or the ladder kernel's products including its in-LDS rebuild, for the kernel
- * variant in use (after autotuning), at 8 real flops per complex multiply-add
- * formed. */
+ * products over the unique momentum/index pairs when the integral blocks are
+ * stored or built one momentum class at a time (the class builds, category 3,
+ * are not included), or the ladder kernel's products including its in-LDS
+ * rebuild for the kernel variant in use (after autotuning); 8 real flops per
+ * complex multiply-add formed. */
 lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
-/* The same launch counted in real matrix-core flops (the work of its MFMA
+/* The same launches counted in real matrix-core flops (the work of their MFMA
  * instructions): the complex64 pipelined kernel forms the complex products of
  * its integral rebuild from three real matrix-core products (Gauss' method),
  * which count 6 instead of 8; equal to lrcc_ladder_flops otherwise. */
 lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *mfma);
+/* Ladder path of the sigma program for nrhs right-hand sides and this precision
+ * (recording it if needed): 1 integrals rebuilt in LDS, 2 stored blocks, 3 blocks
+ * built one momentum class at a time (lrcc_set_ladder_mode; mode 0 resolves to
+ * 3 or 1).  LRCC_E_STATE before amplitudes. */
+lrcc_status lrcc_ladder_path(lrcc_ctx *ctx, int nrhs, int precision, int *path);
 
 /* Measurement helper, not an operation of the method: the attainable dense
  * matrix-core rates of the device (streams of real 16x16x4 fp32 and fp64 MFMA
@@ -329,9 +351,9 @@ lrcc_status lrcc_solve_ccsd(lrcc_ctx *ctx, double tol, int max_iter, double *t1,
  * then the ladders of all chains as ONE persistent launch that takes
  * (chain, k block, tile) work items from an atomic queue, most expensive
  * chains first (uneven batches keep the device busy through the tail), then the
- * remaining steps.  Chains whose ladder is not the rebuild-in-LDS packed
- * kernel (stored integrals, or fewer than 320 (rhs, i, j) rows) run their
- * whole program on their own.  Results are bitwise those of
+ * remaining steps.  Chains whose ladder is not the rebuild-in-LDS pipelined
+ * kernel (stored integrals, or fewer than 128 unique (rhs, i, j) rows in every
+ * momentum class ki + kj) run their whole program on their own.  Results are bitwise those of
  * lrcc_apply_sigma_dev per chain.  The group does not own the contexts; destroy
  * it before them.  A chain may get a new Hamiltonian, k mesh or amplitudes
  * between calls: the group's launch tables record each context's state and are

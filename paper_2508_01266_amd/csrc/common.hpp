@@ -20,6 +20,7 @@ void arena_register(void *base, size_t size);
 void arena_begin(void *base, size_t size);
 void arena_end();
 size_t arena_used();
+bool arena_active();
 bool in_arena(const void *p);
 // The static device array of the no-allocation entry point on device `dev` (its address from
 // hipGetSymbolAddress, taken once per device with that device current) and its size.
@@ -156,8 +157,23 @@ struct LadderArgs {
                          // and written with a further factor 2
     int order;           // pipelined kernel: 1 = XCD-grouped tile order (the row tiles of one
                          // (block, a/b tile) run on one XCD), 0 = row tile fastest in the grid
+    int mrows;           // pipelined kernel with pack_rows: rows of the largest momentum class (set
+                         // by the launcher; see ladder_class_rows)
     KMesh km;            // k mesh of the blocks
 };
+// With pack_rows the pipelined kernel's row tiles run over momentum classes: class K holds the
+// unique rows of every block (ki, kj) with ki <= kj and ki + kj = K (all of them share the
+// integral tiles of a step), block after block in increasing ki.
+__host__ __device__ inline int ladder_class_rows(const LadderArgs &p, int K) {
+    const int nk = p.km.size(), P = p.o * (p.o - 1) / 2;
+    int rows = 0;
+    for (int ki = 0; ki < nk; ++ki) {
+        const int kj = p.km.sub(K, ki);
+        if (ki < kj) rows += p.nrhs * p.o * p.o;
+        else if (ki == kj) rows += p.nrhs * P;
+    }
+    return rows;
+}
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s);
 
@@ -172,7 +188,12 @@ struct LadderGroup {
     unsigned *counter;        // work-queue counter (zeroed by the launcher on the stream)
 };
 template <typename T>
-long long ladder_group_tiles(const LadderArgs &a);
+long long ladder_group_tiles(const LadderArgs &a, long long *blocks);
+// the pipelined kernel's arguments with mrows filled in, and that row count
+LadderArgs ladder_prepared(const LadderArgs &a);
+int ladder_rows_max(const LadderArgs &a);
+// the pipelined kernel is used from this many rows in the largest momentum class on
+constexpr int kPipeMinRows = 128;
 template <typename T>
 hipError_t launch_ladder_group(const LadderGroup &g, int nblocks, hipStream_t s);
 // real flops the ladder kernel executes (tile padding and LDS rebuild included)

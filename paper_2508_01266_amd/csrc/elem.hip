@@ -113,6 +113,12 @@ hipError_t tau_like(const void *x1, const void *x2, const void *t1, void *out, K
 }
 
 // y2[r][ki,kj,ka][i][j][a][b] = scale * (P_ij P_ab Z)[ki,kj,ka][r][i][j][a][b] - omega_r * x2[r][...]
+// The four rows (ki,kj,ka,i,j), (kj,ki,ka,j,i), (ki,kj,kb,i,j), (kj,ki,kb,j,i) of one orbit of the
+// antisymmetriser read the same four rows of Z: with P, Q, R, S those rows and A = P - Q - R^T + S^T
+// (transposes in (a, b)) they are A, -A, -A^T and A^T.  The workgroup of the orbit's first row
+// ((ki, i) <= (kj, j), ka <= kb) writes all of its distinct rows, so Z is read about once per output
+// (the transposed reads of a row hit the cache lines its direct reads brought in); the other
+// workgroups return at once.
 template <typename T>
 __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, double2 *y2, const double *omega,
                          KMesh km, int R, int o, int v, double scale) {
@@ -128,28 +134,44 @@ __global__ void k_pp_out(const typename Cx<T>::type *Z, const double2 *x2, doubl
         const int r = (int)(q / B);
         const int ka = (int)(blk % nk), kj = (int)((blk / nk) % nk), ki = (int)(blk / (nk * nk));
         const int kb = km.comb(ki, kj, ka);
-        auto rowp = [&](int k0, int k1, int k2, int p, int q3) {
+        const int pi = ki * o + i, pj = kj * o + j;
+        if (pi > pj || ka > kb) continue;
+        const bool two_pairs = pi != pj, two_blocks = ka != kb;
+        auto zrow = [&](int k0, int k1, int k2, int p, int q3) {
             return Z + ((((i64)(k0 * nk + k1) * nk + k2) * R + r) * o + p) * o * vv + (i64)q3 * vv;
         };
-        const typename Cx<T>::type *Z1 = rowp(ki, kj, ka, i, j), *Z2 = rowp(kj, ki, ka, j, i);
-        const typename Cx<T>::type *Z3 = rowp(ki, kj, kb, i, j), *Z4 = rowp(kj, ki, kb, j, i);
+        auto yrow = [&](int k0, int k1, int k2, int p, int q3) {
+            return (((i64)r * B + ((i64)k0 * nk + k1) * nk + k2) * o + p) * o * vv + (i64)q3 * vv;
+        };
+        const typename Cx<T>::type *P = zrow(ki, kj, ka, i, j), *Q = zrow(kj, ki, ka, j, i);
+        const typename Cx<T>::type *Rz = zrow(ki, kj, kb, i, j), *S = zrow(kj, ki, kb, j, i);
+        const i64 o0 = row * vv, o1 = yrow(kj, ki, ka, j, i), o2 = yrow(ki, kj, kb, i, j), o3 = yrow(kj, ki, kb, j, i);
         const double w = omega ? omega[r] : 0.0;
-        const double2 *xs = x2 + row * vv;
-        double2 *ys = y2 + row * vv;
-        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
-            const int a = e / v, b = e - a * v, et = b * v + a;
-            const auto z1 = Z1[e], z2 = Z2[e], z3 = Z3[et], z4 = Z4[et];
-            const double zr = (double)z1.x - (double)z2.x - (double)z3.x + (double)z4.x;
-            const double zi = (double)z1.y - (double)z2.y - (double)z3.y + (double)z4.y;
+        auto put = [&](i64 off, int e, double zr, double zi) {
             double2 out;
             out.x = scale * zr;
             out.y = scale * zi;
             if (omega) {
-                const double2 xv = xs[e];
+                const double2 xv = x2[off + e];
                 out.x -= w * xv.x;
                 out.y -= w * xv.y;
             }
-            ys[e] = out;
+            y2[off + e] = out;
+        };
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / v, b = e - a * v, et = b * v + a;
+            const auto p = P[e], qd = Q[e], rt = Rz[et], st = S[et];
+            const double ar = (double)p.x - (double)qd.x - (double)rt.x + (double)st.x;
+            const double ai = (double)p.y - (double)qd.y - (double)rt.y + (double)st.y;
+            put(o0, e, ar, ai);
+            if (two_pairs) put(o1, e, -ar, -ai);
+            if (two_blocks) {
+                const auto pt = P[et], qt = Q[et], rd = Rz[e], sd = S[e];
+                const double tr = (double)pt.x - (double)qt.x - (double)rd.x + (double)sd.x;
+                const double ti = (double)pt.y - (double)qt.y - (double)rd.y + (double)sd.y;
+                put(o2, e, -tr, -ti);
+                if (two_pairs) put(o3, e, tr, ti);
+            }
         }
     }
 }

@@ -559,24 +559,30 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     __shared__ T Lr[4][QCH][32 + PL], Li[4][QCH][32 + PL];
 
     const int nk = p.nk, v = p.v, naux = p.naux, o = p.o;
-    const int M = p.nrhs * o * o;
-    const int tilesM = (M + BM - 1) / BM;
+    const int M = p.nrhs * o * o;                  // rows of one (ki, kj, k) block of Y and Z
+    const bool rows_packed = p.pack_rows != 0;
+    const int tilesM = ((rows_packed ? p.mrows : M) + BM - 1) / BM;
     const int tilesA = (v + TA - 1) / TA;
     const int mt = bx % tilesM;
     const int rest = bx / tilesM;
     const int ta = rest % tilesA, tb = rest / tilesA;
     const int a0 = ta * TA, b0 = tb * TB;
-    const int ki = blk / (nk * nk), kj = (blk / nk) % nk, ka = blk % nk;
-    const int kb = p.km.comb(ki, kj, ka);
+    // block: (K = ki + kj, ka) over the unique rows of class K (rows_packed), else (ki, kj, ka)
+    int K, ka, ki = 0, kj = 0;
+    if (rows_packed) {
+        K = blk / nk;
+        ka = blk % nk;
+    } else {
+        ki = blk / (nk * nk);
+        kj = (blk / nk) % nk;
+        ka = blk % nk;
+        K = p.km.sum3(1, ki, 1, kj, 0, 0);
+    }
+    const int kb = p.km.sub(K, ka);
     if (ka > kb || (ka == kb && ta > tb)) return;
     const bool diag_out = (ka == kb);
-    // unique rows: all (rhs, i, j) of a block ki < kj; the o(o-1)/2 pairs i < j per right-hand
-    // side of a block ki == kj (compact row index m = rhs * P + pair); none when ki > kj
-    const bool rows_packed = p.pack_rows != 0;
-    if (rows_packed && ki > kj) return;
-    const bool diag_rows = rows_packed && ki == kj;
     const int P = o * (o - 1) / 2;
-    const int Mr = diag_rows ? p.nrhs * P : M;      // rows of this block
+    const int Mr = rows_packed ? ladder_class_rows(p, K) : M;   // rows of this block
     const int m0 = mt * BM;
     if (m0 >= Mr) return;
 
@@ -590,19 +596,33 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     C2 *Z = reinterpret_cast<C2 *>(p.Z);
     const int gb = wave & 3, second = (wave >> 2) & 1;
     const bool rebuilder = WM * WN == 8 || wave < 8;   // compile-time true with eight waves
-    // row table of the tile: block row (rhs * o + i) * o + j of every tile row, -1 past the end
+    // row table of the tile, in rows of vv elements: (ki * nk + kj) * nk * M (the row's block, the
+    // third momentum added per step) + (rhs * o + i) * o + j; -1 past the end.  Class rows: the unique
+    // rows of block (ki, kj) for every ki <= kj with ki + kj = K, in increasing ki: all (rhs, i, j)
+    // when ki < kj, the o(o-1)/2 pairs i < j per right-hand side when ki == kj
     __shared__ int rowtab[BM];
     for (int t = tid; t < BM; t += NT) {
-        const int m = m0 + t;
-        int ro = -1;
+        int m = m0 + t, ro = -1;
         if (m < Mr) {
-            if (diag_rows) {
-                const int r = m / P;
-                int q = m - r * P, i = 0;
-                while (q >= o - 1 - i) { q -= o - 1 - i; ++i; }
-                ro = (r * o + i) * o + i + 1 + q;
+            if (rows_packed) {
+                int bi = 0, bj = 0;
+                for (int k = 0; k < nk; ++k) {
+                    const int kk = p.km.sub(K, k);
+                    if (k > kk) continue;
+                    const int cnt = k < kk ? M : p.nrhs * P;
+                    if (m < cnt) { bi = k; bj = kk; break; }
+                    m -= cnt;
+                }
+                int r0 = m;
+                if (bi == bj) {
+                    const int r = m / P;
+                    int q = m - r * P, i = 0;
+                    while (q >= o - 1 - i) { q -= o - 1 - i; ++i; }
+                    r0 = (r * o + i) * o + i + 1 + q;
+                }
+                ro = (bi * nk + bj) * nk * M + r0;
             } else {
-                ro = m;
+                ro = (ki * nk + kj) * nk * M + m;
             }
         }
         rowtab[t] = ro;
@@ -611,7 +631,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
     const int rw = 16 * (gb & 1), cw = 16 * (gb >> 1);
 
     // steps (ke <= kf, e0, f0 >= e0 when ke == kf); the step after `s`, or ke = nk when done
-    auto kf_of = [&](int ke) { return p.km.comb(ki, kj, ke); };
+    auto kf_of = [&](int ke) { return p.km.sub(K, ke); };
     auto first_valid = [&](int ke) {
         while (ke < nk && ke > kf_of(ke)) ++ke;
         return ke;
@@ -670,7 +690,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         const bool diag_in = ke == kf_of(ke);
         const int e = e0 + ye, f = f0 + yf;
         const bool ok = e < v && f < v && (!diag_in || e < f);
-        const C2 *Yb = Y + ((i64)(ki * nk + kj) * nk + ke) * blk4 + (i64)e * v + f;
+        const C2 *Yb = Y + (i64)ke * blk4 + (i64)e * v + f;
 #pragma unroll
         for (int q = 0; q < YPT; ++q) {
             const int ro = rowtab[ym + q * (NT / LTK)];
@@ -771,7 +791,7 @@ __device__ __forceinline__ void ladder_pipe_tile(const LadderArgs &p, const int 
         __syncthreads();
     }
 
-    C2 *Zb = Z + ((i64)(ki * nk + kj) * nk + ka) * blk4;
+    C2 *Zb = Z + (i64)ka * blk4;
     // unique (a, b) outputs carry 2 alpha, and unique rows a further 2: the P(ij)P(ab) assembly
     // reproduces the partners from the antisymmetry
     const T al = (T)((rows_packed ? 4.0 : 2.0) * p.alpha);
@@ -806,9 +826,9 @@ template <typename T, int WM, int WN, int QCH>
 __global__ void __launch_bounds__(WM * WN * 64) ladder_kernel_pipe(LadderArgs p) {
     if (p.order == 1) {
         constexpr int BM = WM * 4 * 16;
-        const int tilesM = (p.nrhs * p.o * p.o + BM - 1) / BM;
+        const int tilesM = ((p.pack_rows ? p.mrows : p.nrhs * p.o * p.o) + BM - 1) / BM;
         const int tAB = ((p.v + TA - 1) / TA) * ((p.v + TB - 1) / TB);
-        const int groups = p.nk * p.nk * p.nk * tAB;
+        const int groups = (p.pack_rows ? p.nk * p.nk : p.nk * p.nk * p.nk) * tAB;
         const int g = blockIdx.x, c = g % kXcd, s = g / kXcd;
         const int G = (s / tilesM) * kXcd + c;
         if (G >= groups) return;
@@ -853,21 +873,44 @@ template <typename T> struct PipeCfg;
 template <> struct PipeCfg<float> { static constexpr int WM = 6, WN = 2, QCH = 24, BM = 384; };
 template <> struct PipeCfg<double> { static constexpr int WM = 4, WN = 2, QCH = 8, BM = 256; };
 
+// The launch arguments of the pipelined kernel with the largest class's row count filled in.
+LadderArgs ladder_prepared(const LadderArgs &a) {
+    LadderArgs b = a;
+    b.mrows = 0;
+    if (b.pack_rows)
+        for (int K = 0; K < b.km.size(); ++K) b.mrows = std::max(b.mrows, ladder_class_rows(b, K));
+    return b;
+}
+
+int ladder_rows_max(const LadderArgs &a) { return ladder_prepared(a).mrows; }
+
+// (row tiles, blocks) of the pipelined kernel's grid
+template <typename T>
+static void pipe_grid(const LadderArgs &b, long long &tilesM, long long &blocks) {
+    const long long rows = b.pack_rows ? b.mrows : (long long)b.nrhs * b.o * b.o;
+    tilesM = (rows + PipeCfg<T>::BM - 1) / PipeCfg<T>::BM;
+    blocks = (long long)b.nk * b.nk * (b.pack_rows ? 1 : b.nk);
+}
+
 template <typename T>
 hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
     const int M = a.nrhs * a.o * a.o;
     const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
-    if (use_big(a)) {
+    if (a.packed == 2) {
+        typedef PipeCfg<T> C;
+        const LadderArgs b = ladder_prepared(a);
+        // row offsets are 32-bit in units of v*v elements
+        if ((long long)b.nk * b.nk * b.nk * M >= (1LL << 31)) return hipErrorInvalidValue;
+        long long tilesMp, blocks;
+        pipe_grid<T>(b, tilesMp, blocks);
+        const long long groups = blocks * tA * tB;
+        dim3 gp((unsigned)(tilesMp * tA * tB), (unsigned)blocks);
+        if (b.order == 1) gp = dim3((unsigned)(kXcd * tilesMp * ((groups + kXcd - 1) / kXcd)), 1);
+        hipLaunchKernelGGL((ladder_kernel_pipe<T, C::WM, C::WN, C::QCH>), gp, dim3(C::WM * C::WN * 64), 0, s, b);
+    } else if (use_big(a)) {
         const int tilesM = (M + BTM - 1) / BTM;
         dim3 grid(tilesM * tA * tB, a.nk * a.nk * a.nk);
-        if (a.packed == 2) {
-            typedef PipeCfg<T> C;
-            const long long tilesMp = (M + C::BM - 1) / C::BM;
-            const long long groups = (long long)a.nk * a.nk * a.nk * tA * tB;
-            dim3 gp(tilesMp * tA * tB, a.nk * a.nk * a.nk);
-            if (a.order == 1) gp = dim3((unsigned)(kXcd * tilesMp * ((groups + kXcd - 1) / kXcd)), 1);
-            hipLaunchKernelGGL((ladder_kernel_pipe<T, C::WM, C::WN, C::QCH>), gp, dim3(C::WM * C::WN * 64), 0, s, a);
-        } else if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
+        if (a.packed) hipLaunchKernelGGL(ladder_kernel_packed<T>, grid, dim3(NTP), 0, s, a);
         else hipLaunchKernelGGL(ladder_kernel_big<T>, grid, dim3(NTB), 0, s, a);
     } else {
         const int tilesM = (M + LTM - 1) / LTM;
@@ -878,10 +921,13 @@ hipError_t launch_ladder(const LadderArgs &a, hipStream_t s) {
 }
 
 template <typename T>
-long long ladder_group_tiles(const LadderArgs &a) {
-    const int M = a.nrhs * a.o * a.o;
+long long ladder_group_tiles(const LadderArgs &a, long long *blocks) {
+    const LadderArgs b = ladder_prepared(a);
     const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB;
-    return (long long)((M + PipeCfg<T>::BM - 1) / PipeCfg<T>::BM) * tA * tB;
+    long long tilesM, nb;
+    pipe_grid<T>(b, tilesM, nb);
+    if (blocks) *blocks = nb;
+    return tilesM * tA * tB;
 }
 
 template <typename T>
@@ -892,15 +938,15 @@ hipError_t launch_ladder_group(const LadderGroup &g, int nblocks, hipStream_t s)
     return hipGetLastError();
 }
 
-template long long ladder_group_tiles<double>(const LadderArgs &);
-template long long ladder_group_tiles<float>(const LadderArgs &);
+template long long ladder_group_tiles<double>(const LadderArgs &, long long *);
+template long long ladder_group_tiles<float>(const LadderArgs &, long long *);
 template hipError_t launch_ladder_group<double>(const LadderGroup &, int, hipStream_t);
 template hipError_t launch_ladder_group<float>(const LadderGroup &, int, hipStream_t);
 
 double ladder_flop_count(const LadderArgs &a, bool fp64, bool mfma) {
     const int M = a.nrhs * a.o * a.o;
-    const bool big = use_big(a);
-    const bool pipe = big && a.packed == 2;
+    const bool pipe = a.packed == 2;
+    const bool big = pipe || use_big(a);
     const int tm = pipe ? (fp64 ? PipeCfg<double>::BM : PipeCfg<float>::BM) : big ? BTM : LTM;
     const double tilesM = (M + tm - 1) / tm;
     const int tA = (a.v + TA - 1) / TA, tB = (a.v + TB - 1) / TB, tE = (a.v + TE - 1) / TE, tF = (a.v + TF - 1) / TF;
@@ -917,24 +963,26 @@ double ladder_flop_count(const LadderArgs &a, bool fp64, bool mfma) {
     const double rb = (mfma && pipe && !fp64) ? 0.75 : 1.0;
     const int nk = a.nk;
     const bool rows = pipe && a.pack_rows;
-    const double tilesD = rows ? (double)(((i64)a.nrhs * (a.o * (a.o - 1) / 2) + tm - 1) / tm) : tilesM;
+    // blocks: momentum classes K = ki + kj with the unique rows of all their (ki <= kj) pairs, or
+    // every (ki, kj) pair with all its rows
     double steps = 0;
-    for (int ki = 0; ki < nk; ++ki)
-        for (int kj = 0; kj < nk; ++kj) {
-            if (rows && ki > kj) continue;
-            const double tiles = rows && ki == kj ? tilesD : tilesM;
+    for (int K = 0; K < nk; ++K)
+        for (int ki = 0; ki < (rows ? 1 : nk); ++ki) {
+            const int kj = a.km.sub(K, ki);
+            const double tiles = rows ? (double)((ladder_class_rows(a, K) + tm - 1) / tm) : tilesM;
             for (int ka = 0; ka < nk; ++ka) {
-                const int kb = a.km.comb(ki, kj, ka);
+                const int kb = a.km.sub(K, ka);
                 if (ka > kb) continue;
                 const double out = ka == kb ? tA * (tA + 1) / 2.0 : (double)tA * tB;
                 double in = 0;
                 for (int ke = 0; ke < nk; ++ke) {
-                    const int kf = a.km.comb(ki, kj, ke);
+                    const int kf = a.km.sub(K, ke);
                     if (ke > kf) continue;
                     in += ke == kf ? tE * (tE + 1) / 2.0 : (double)tE * tF;
                 }
                 steps += out * in * tiles;
             }
+            (void)kj;
         }
     return steps * (main_step + 2.0 * rb * rebuild_step);
 }

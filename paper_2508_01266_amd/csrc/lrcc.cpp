@@ -109,9 +109,13 @@ struct lrcc_ctx {
     Profiler prof;
     bool use_graphs = false;
     bool pack_ladder = true;                   // antisymmetry-packed forward ladder for large batches
-    int ladder_mode = 0;                       // 0, 1: rebuild integrals in LDS; 2: stored integral blocks
+    int ladder_mode = 0;                       // 0: automatic (3 if one class of blocks fits, else 1);
+                                               // 1: rebuild integrals in LDS; 2: stored integral blocks;
+                                               // 3: blocks of one momentum class at a time, per sigma
     std::vector<int> wslot;                    // (ka, kb, ke) -> slot of the stored blocks, -1 if not stored
     int nwslot = 0;
+    std::vector<int> wcls;                     // (ka, kb, ke) -> slot within its class ka + kb, -1 if none
+    int ncls_slots = 0;                        // most slots of one class
     bool autotune = false;
     hipStream_t own_stream = nullptr;          // non-null stream for solver work (graph capture)
     std::unique_ptr<Program> pre64, pre32;     // amplitude-dependent blocks (f64) and their f32 copies
@@ -274,21 +278,50 @@ void build_dressing(lrcc_ctx *c, Program &P, void *slice_src, void *out, const v
 //   K(k1,k2,k3,k4)[a][e][b][f] = sum_Q La[k1][k2][Q][a][e] Lb[k3][k4][Q][b][f],
 // with s = 1/2 when ke == kf and 1 otherwise, so that for Y antisymmetric in
 // (e,f) the ladder of every output block is sum over ke <= kf of Y(ke) W'.
+// The blocks of one momentum class K = ka + kb (the outputs of the row pairs ki + kj = K)
+// also get slots numbered within the class, for the class-at-a-time ladder (mode 3).
 void ladder_slots(lrcc_ctx *c) {
     const int nk = c->nk;
     c->wslot.assign((size_t)nk * nk * nk, -1);
+    c->wcls.assign((size_t)nk * nk * nk, -1);
+    std::vector<int> per(nk, 0);
     int n = 0;
     for (int ka = 0; ka < nk; ++ka)
         for (int kb = ka; kb < nk; ++kb)
             for (int ke = 0; ke < nk; ++ke) {
                 const int kf = c->km.comb(ka, kb, ke);
-                if (ke <= kf) c->wslot[((size_t)ka * nk + kb) * nk + ke] = n++;
+                if (ke > kf) continue;
+                const size_t at = ((size_t)ka * nk + kb) * nk + ke;
+                c->wslot[at] = n++;
+                c->wcls[at] = per[c->km.sum3(1, ka, 1, kb, 0, 0)]++;
             }
     c->nwslot = n;
+    c->ncls_slots = *std::max_element(per.begin(), per.end());
 }
 
+// Momentum class of a pair: k1 + k2.
+static int kclass(const lrcc_ctx *c, int k1, int k2) { return c->km.sum3(1, k1, 1, k2, 0, 0); }
+
+// Ladder path of a sigma program: 2 stored blocks (Wst set), 3 blocks built one momentum class at a
+// time, 1 integrals rebuilt in LDS.  Mode 0 (automatic) takes 3 when one class of blocks of
+// elem_bytes per element takes at most an eighth of the free device memory, else 1; inside the
+// static array of the no-allocation entry point it takes 1 (the array is small).
+static int ladder_path(lrcc_ctx *c, const void *Wst, size_t elem_bytes) {
+    if (Wst) return 2;
+    if (c->ladder_mode == 3) return 3;
+    if (c->ladder_mode != 0 || arena_active()) return 1;
+    if (g_dry_run) return 3;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 1;
+    const size_t v2 = (size_t)c->nv * c->nv;
+    return (size_t)c->ncls_slots * v2 * v2 * elem_bytes <= fr / 8 ? 3 : 1;
+}
+
+// cls < 0: every unique block into its slot of W (nwslot blocks); cls >= 0: the blocks of
+// momentum class cls into their class slots (ncls_slots blocks).
 template <typename T>
-void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void *W) {
+void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void *W, int cls = -1,
+                  int tag = TAG_NONE) {
     const int nk = c->nk, v = c->nv, naux = c->naux;
     const i64 vv = (i64)v * v, v4 = vv * vv, lsz = (i64)nk * nk * naux * vv;
     for (int part = 0; part < 2; ++part) {
@@ -331,7 +364,8 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
             for (int kb = ka; kb < nk; ++kb)
                 for (int ke = 0; ke < nk; ++ke) {
                     const int kf = c->km.comb(ka, kb, ke);
-                    const int sl = c->wslot[((size_t)ka * nk + kb) * nk + ke];
+                    if (cls >= 0 && kclass(c, ka, kb) != cls) continue;
+                    const int sl = (cls < 0 ? c->wslot : c->wcls)[((size_t)ka * nk + kb) * nk + ke];
                     if (sl < 0) continue;
                     offC.push_back(sl * v4);
                     const int k2 = part == 0 ? ke : kf, k4 = part == 0 ? kf : ke;
@@ -340,7 +374,8 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
                     beg.push_back((int)segA.size());
                     js.push_back(ke == kf ? 0.5f : 1.0f);
                 }
-        raw_gemm<T>(P, g, offC, beg, segA, segB, lsz, lsz, (i64)c->nwslot * v4, js);
+        raw_gemm<T>(P, g, offC, beg, segA, segB, lsz, lsz, (i64)(cls < 0 ? c->nwslot : c->ncls_slots) * v4, js);
+        if (tag != TAG_NONE) P.tag_last(tag);
         P.name_last(part == 0 ? "ladder integrals (direct)" : "ladder integrals (exchange)");
     }
 }
@@ -349,7 +384,7 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
 // that path too).  Mode 2 refuses blocks that would take more than half of the
 // free device memory.
 bool store_ladder(lrcc_ctx *c, size_t elem_bytes, size_t also) {
-    if (g_dry_run) return true;
+    if (g_dry_run) return c->ladder_mode != 3;
     if (c->ladder_mode != 2) return false;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
@@ -768,66 +803,80 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
             break;
         }
         case SymOp::LADDER: {
-            if (S.Wst) {
+            const bool by_class = ladder_path(c, S.Wst, 2 * sizeof(T)) == 3 && S.La && S.Lb;
+            P->ladder_path = S.Wst ? 2 : by_class ? 3 : 1;
+            if (S.Wst || by_class) {
                 // stored integrals: Z(ki,kj,ka) += alpha' sum_{ke <= kf} Y(ki,kj,ke) W'(ka,kb,ke) for
                 // ka <= kb and ki <= kj, alpha' = alpha times 2 when ka < kb and 2 when ki < kj (the
                 // (kb,ka) and (kj,ki) partner blocks are left to the P(ij)P(ab) assembly, which
-                // reproduces them from antisymmetry)
+                // reproduces them from antisymmetry).  By class (mode 3): for each momentum class
+                // K = ki + kj = ka + kb, the class's blocks W' are built into a scratch array of
+                // ncls_slots blocks and consumed by that class's GEMM before the next class
                 const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv;
-                GemmArgs g{};
-                g.shape = -1;
-                g.kind = 1;
-                g.A = op.A.p;
-                g.B = S.Wst;
-                g.C = op.C.p;
-                g.M = R * o * o;
-                g.N = (int)vv;
-                g.K = (int)vv;
-                g.sm = Split{1, g.M};
-                g.Am = Strides{{0, 0, vv}};
-                g.Cm = Strides{{0, 0, vv}};
-                g.sk = Split{1, g.K};
-                g.Ak = Strides{{0, 0, 1}};
-                g.Bk = Strides{{0, 0, vv}};
-                g.sn = Split{1, g.N};
-                g.Bn = Strides{{0, 0, 1}};
-                g.Cn = Strides{{0, 0, 1}};
-                g.aMfast = 0;
-                g.bNfast = 1;
-                g.alpha_re = op.alpha.real();
-                g.alpha_im = op.alpha.imag();
-                g.beta = 1;
-                std::vector<i64> offC, segA, segB;
-                std::vector<int> beg{0};
-                std::vector<float> js;
-                for (int ki = 0; ki < nk; ++ki)
-                    for (int kj = ki; kj < nk; ++kj)
-                        for (int ka = 0; ka < nk; ++ka) {
-                            const int kb = c->km.comb(ki, kj, ka);
-                            if (ka > kb) continue;
-                            for (int ke = 0; ke < nk; ++ke) {
-                                const int kf = c->km.comb(ki, kj, ke);
-                                if (ke > kf) continue;
-                                segA.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
-                                segB.push_back((i64)c->wslot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
+                const i64 wblocks = by_class ? c->ncls_slots : c->nwslot;
+                void *Wb = by_class ? P->alloc((size_t)wblocks * vv * vv * 2 * sizeof(T)) : S.Wst;
+                for (int K = by_class ? 0 : -1; K < (by_class ? nk : 0); ++K) {
+                    if (by_class) build_wstore<T>(c, *P, S.La, S.Lb, Wb, K, TAG_BUILD);
+                    GemmArgs g{};
+                    g.shape = -1;
+                    g.kind = 1;
+                    g.A = op.A.p;
+                    g.B = Wb;
+                    g.C = op.C.p;
+                    g.M = R * o * o;
+                    g.N = (int)vv;
+                    g.K = (int)vv;
+                    g.sm = Split{1, g.M};
+                    g.Am = Strides{{0, 0, vv}};
+                    g.Cm = Strides{{0, 0, vv}};
+                    g.sk = Split{1, g.K};
+                    g.Ak = Strides{{0, 0, 1}};
+                    g.Bk = Strides{{0, 0, vv}};
+                    g.sn = Split{1, g.N};
+                    g.Bn = Strides{{0, 0, 1}};
+                    g.Cn = Strides{{0, 0, 1}};
+                    g.aMfast = 0;
+                    g.bNfast = 1;
+                    g.alpha_re = op.alpha.real();
+                    g.alpha_im = op.alpha.imag();
+                    g.beta = 1;
+                    const std::vector<int> &slot = by_class ? c->wcls : c->wslot;
+                    std::vector<i64> offC, segA, segB;
+                    std::vector<int> beg{0};
+                    std::vector<float> js;
+                    for (int ki = 0; ki < nk; ++ki)
+                        for (int kj = ki; kj < nk; ++kj) {
+                            if (K >= 0 && kclass(c, ki, kj) != K) continue;
+                            for (int ka = 0; ka < nk; ++ka) {
+                                const int kb = c->km.comb(ki, kj, ka);
+                                if (ka > kb) continue;
+                                for (int ke = 0; ke < nk; ++ke) {
+                                    const int kf = c->km.comb(ki, kj, ke);
+                                    if (ke > kf) continue;
+                                    segA.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
+                                    segB.push_back((i64)slot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
+                                }
+                                offC.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
+                                beg.push_back((int)segA.size());
+                                js.push_back((ka < kb ? 2.0f : 1.0f) * (ki < kj ? 2.0f : 1.0f));
                             }
-                            offC.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
-                            beg.push_back((int)segA.size());
-                            js.push_back((ka < kb ? 2.0f : 1.0f) * (ki < kj ? 2.0f : 1.0f));
                         }
-                raw_gemm<T>(*P, g, offC, beg, segA, segB, op.A.count(), (i64)c->nwslot * vv * vv, op.C.count(), js);
-                P->tag_last(TAG_LADDER);
-                P->name_last("ladder (stored integrals)");
+                    raw_gemm<T>(*P, g, offC, beg, segA, segB, op.A.count(), wblocks * vv * vv, op.C.count(), js);
+                    P->tag_last(TAG_LADDER);
+                    P->name_last(by_class ? "ladder (class integrals)" : "ladder (stored integrals)");
+                }
                 break;
             }
             LadderArgs la = ladder_args<T>(c, op.A.p, S.La, S.Lb, op.C.p, R, op.alpha.real());
             // dtau is antisymmetric in (e,f): packed kernels; the pipelined one from 320 rows on
             // (its 384-row tiles would idle more than a sixth of their rows below)
-            la.packed = c->pack_ladder ? ((i64)R * c->no * c->no >= 320 ? 2 : 1) : 0;
             // dtau and the ladder term are antisymmetric in (i, j) too, and Z reaches sigma2 only
-            // through P(ij)P(ab): the pipelined kernel forms the unique rows only
+            // through P(ij)P(ab): the pipelined kernel forms the unique rows only, the rows of all
+            // (ki <= kj) pairs with one ki + kj in one stream of tiles (they share the integrals);
+            // it is used from kPipeMinRows rows per class on (below, its tiles would mostly idle)
             la.pack_rows = 1;
             la.order = 1;
+            la.packed = c->pack_ladder ? (ladder_rows_max(la) >= kPipeMinRows ? 2 : 1) : 0;
             auto lp = std::make_shared<LadderArgs>(la);
             P->ops.push_back([lp](hipStream_t s) { return launch_ladder<T>(*lp, s); });
             P->ladder_args = lp;
@@ -919,68 +968,82 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
             break;
         }
         case SymOp::LADDER: {
-            if (S.Wst) {
+            const bool by_class = ladder_path(c, S.Wst, 2 * sizeof(T)) == 3 && S.La && S.Lb;
+            P->ladder_path = S.Wst ? 2 : by_class ? 3 : 1;
+            if (S.Wst || by_class) {
                 // stored integrals, transposed: with Zbar antisymmetric in (a, b),
                 //   dtau_bar(ki,kj,ke) = alpha [sum_{ka<kb} Zbar(ki,kj,ka) W'(ka,kb,ke)^T
                 //                              + 1/2 sum_{ka=kb} Zbar(ki,kj,ka) W'(ka,ka,ke)^T]
                 // for ke <= kf (the stored ke = kf blocks carry W'/2, which the completion below
                 // doubles back); the result goes to a zeroed scratch array and expand_ab adds it and
-                // its (e, f)-antisymmetric (kf, ke) partner blocks to dtau_bar
+                // its (e, f)-antisymmetric (kf, ke) partner blocks to dtau_bar.  By class (mode 3):
+                // the blocks of one momentum class at a time in a scratch array, as in the forward
+                // product
                 const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv, n = op.A.count();
                 void *tmp = P->alloc((size_t)n * 2 * sizeof(T)), *dst = op.A.p;
+                const i64 wblocks = by_class ? c->ncls_slots : c->nwslot;
+                void *Wb = by_class ? P->alloc((size_t)wblocks * vv * vv * 2 * sizeof(T)) : S.Wst;
+                const std::vector<int> &slot = by_class ? c->wcls : c->wslot;
                 const KMesh km = c->km;
                 P->ops.push_back([tmp, n](hipStream_t s) { return zero_fill<T>(tmp, n, s); });
-                for (int half = 0; half < 2; ++half) {
-                    GemmArgs g{};
-                    g.shape = -1;
-                    g.kind = 1;
-                    g.A = op.C.p;
-                    g.B = S.Wst;
-                    g.C = tmp;
-                    g.M = R * o * o;
-                    g.N = (int)vv;
-                    g.K = (int)vv;
-                    g.sm = Split{1, g.M};
-                    g.Am = Strides{{0, 0, vv}};
-                    g.Cm = Strides{{0, 0, vv}};
-                    g.sk = Split{1, g.K};
-                    g.Ak = Strides{{0, 0, 1}};
-                    g.Bk = Strides{{0, 0, 1}};
-                    g.sn = Split{1, g.N};
-                    g.Bn = Strides{{0, 0, vv}};
-                    g.Cn = Strides{{0, 0, 1}};
-                    g.aMfast = 0;
-                    g.bNfast = 0;
-                    g.alpha_re = op.alpha.real() * (half ? 0.5 : 1.0);
-                    g.alpha_im = op.alpha.imag() * (half ? 0.5 : 1.0);
-                    g.beta = 1;
-                    // only ki <= kj: dtau_bar is read by the transposed tau step alone, whose four
-                    // (i, j) / (a, b) placements make a block (ki, kj) stand for its (kj, ki) partner
-                    // at twice the weight (the transposed P(ij)P(ab) of the forward assembly)
-                    std::vector<i64> offC, segA, segB;
-                    std::vector<int> beg{0};
-                    std::vector<float> js;
-                    for (int ki = 0; ki < nk; ++ki)
-                        for (int kj = ki; kj < nk; ++kj)
-                            for (int ke = 0; ke < nk; ++ke) {
-                                const int kf = c->km.comb(ki, kj, ke);
-                                if (ke > kf) continue;
-                                const size_t s0 = segA.size();
-                                for (int ka = 0; ka < nk; ++ka) {
-                                    const int kb = c->km.comb(ki, kj, ka);
-                                    if (half ? ka != kb : ka >= kb) continue;
-                                    segA.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
-                                    segB.push_back((i64)c->wslot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
+                for (int K = by_class ? 0 : -1; K < (by_class ? nk : 0); ++K) {
+                    if (by_class) build_wstore<T>(c, *P, S.La, S.Lb, Wb, K, TAG_BUILD);
+                    for (int half = 0; half < 2; ++half) {
+                        GemmArgs g{};
+                        g.shape = -1;
+                        g.kind = 1;
+                        g.A = op.C.p;
+                        g.B = Wb;
+                        g.C = tmp;
+                        g.M = R * o * o;
+                        g.N = (int)vv;
+                        g.K = (int)vv;
+                        g.sm = Split{1, g.M};
+                        g.Am = Strides{{0, 0, vv}};
+                        g.Cm = Strides{{0, 0, vv}};
+                        g.sk = Split{1, g.K};
+                        g.Ak = Strides{{0, 0, 1}};
+                        g.Bk = Strides{{0, 0, 1}};
+                        g.sn = Split{1, g.N};
+                        g.Bn = Strides{{0, 0, vv}};
+                        g.Cn = Strides{{0, 0, 1}};
+                        g.aMfast = 0;
+                        g.bNfast = 0;
+                        g.alpha_re = op.alpha.real() * (half ? 0.5 : 1.0);
+                        g.alpha_im = op.alpha.imag() * (half ? 0.5 : 1.0);
+                        g.beta = 1;
+                        // only ki <= kj: dtau_bar is read by the transposed tau step alone, whose four
+                        // (i, j) / (a, b) placements make a block (ki, kj) stand for its (kj, ki)
+                        // partner at twice the weight (the transposed P(ij)P(ab) of the forward
+                        // assembly)
+                        std::vector<i64> offC, segA, segB;
+                        std::vector<int> beg{0};
+                        std::vector<float> js;
+                        for (int ki = 0; ki < nk; ++ki)
+                            for (int kj = ki; kj < nk; ++kj) {
+                                if (K >= 0 && kclass(c, ki, kj) != K) continue;
+                                for (int ke = 0; ke < nk; ++ke) {
+                                    const int kf = c->km.comb(ki, kj, ke);
+                                    if (ke > kf) continue;
+                                    const size_t s0 = segA.size();
+                                    for (int ka = 0; ka < nk; ++ka) {
+                                        const int kb = c->km.comb(ki, kj, ka);
+                                        if (half ? ka != kb : ka >= kb) continue;
+                                        segA.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
+                                        segB.push_back((i64)slot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
+                                    }
+                                    if (segA.size() == s0) continue;
+                                    offC.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
+                                    beg.push_back((int)segA.size());
+                                    js.push_back(ki < kj ? 2.0f : 1.0f);
                                 }
-                                if (segA.size() == s0) continue;
-                                offC.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
-                                beg.push_back((int)segA.size());
-                                js.push_back(ki < kj ? 2.0f : 1.0f);
                             }
-                    raw_gemm<T>(*P, g, offC, beg, segA, segB, op.C.count(), (i64)c->nwslot * vv * vv, n, js);
-                    P->tag_last(TAG_LADDER);
-                    P->name_last(half ? "ladder (stored integrals, transposed, ka = kb)"
-                                      : "ladder (stored integrals, transposed)");
+                        if (offC.empty()) continue;
+                        raw_gemm<T>(*P, g, offC, beg, segA, segB, op.C.count(), wblocks * vv * vv, n, js);
+                        P->tag_last(TAG_LADDER);
+                        P->name_last(half ? "ladder (stored integrals, transposed, ka = kb)"
+                                          : "ladder (stored integrals, transposed)");
+                    }
                 }
                 P->ops.push_back([tmp, dst, km, R, o, v](hipStream_t s) {
                     return expand_ab<T>(tmp, dst, km, R, o, v, 1.0, s);
@@ -990,13 +1053,12 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
             LadderArgs la = ladder_args<T>(c, op.C.p, S.LaT, S.LbT, op.A.p, R, op.alpha.real());
             // Zbar is antisymmetric in both pairs (it is only read in the reverse pass) and so is
             // the transposed ladder; dtau_bar is read by the transposed tau step alone, which sums
-            // the four pair placements: the pipelined kernel forms unique pairs and rows from 320
-            // rows on (below, the full-range kernel: the packed tiles would idle)
-            if (c->pack_ladder && (i64)R * c->no * c->no >= 320) {
-                la.packed = 2;
-                la.pack_rows = 1;
-                la.order = 1;
-            }
+            // the four pair placements: the pipelined kernel forms unique pairs and class rows from
+            // kPipeMinRows rows per class on (below, the full-range kernel: the tiles would idle)
+            la.pack_rows = 1;
+            la.order = 1;
+            if (!(c->pack_ladder && ladder_rows_max(la) >= kPipeMinRows)) la.pack_rows = 0;
+            else la.packed = 2;
             P->ops.push_back([=](hipStream_t s) { return launch_ladder<T>(la, s); });
             P->last_flops = (i64)ladder_executed_flops(la, sizeof(T) == 8);
             P->flops += P->last_flops;
@@ -1009,15 +1071,14 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
 }
 
 // Autotuning cache: one line per program, "key choice0 choice1 ..." in a text
-// file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction,ladder mode.
-std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant) {
+// file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction,ladder path.
+std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant, int path) {
     char b[128];
-    // "v7": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
-    // ladder: four kernel/order variants); the ladder mode changes the program's launches, so it is
-    // part of the key
-    std::snprintf(b, sizeof b, "v7,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
-                  prec == LRCC_FP64 ? "f64" : "f32", adj ? "adjoint" : "forward", variant,
-                  c->ladder_mode == 2 ? 2 : 0);
+    // "v8": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
+    // ladder: four kernel/order variants); the ladder path (1 rebuilt in LDS, 2 stored, 3 built by
+    // momentum class) changes the program's launches, so it is part of the key
+    std::snprintf(b, sizeof b, "v8,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
+                  prec == LRCC_FP64 ? "f64" : "f32", adj ? "adjoint" : "forward", variant, path);
     if (!c->km.chain()) return std::string(b) + ",mesh" + std::to_string(c->km.n0) + "x" + std::to_string(c->km.n1) +
                                "x" + std::to_string(c->km.n2);
     return b;
@@ -1096,7 +1157,7 @@ Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false, int v
     else
         p = prec == LRCC_FP64 ? build_sigma_adjoint<double>(c, c->s64, R, *mem)
                               : build_sigma_adjoint<float>(c, c->s32, R, *mem);
-    p->tune_key = tune_key(c, prec, R, adjoint, variant);
+    p->tune_key = tune_key(c, prec, R, adjoint, variant, p->ladder_path);
     c->progs[key].reset(p);
     c->progmem[key] = std::move(mem);
     return p;
@@ -1194,9 +1255,7 @@ static double rel_res(double rn, double bn) {
 // unit direction of the Krylov space to zero to working precision: singular at that frequency.
 constexpr double kSingularPivot = 1e-12;
 
-// GMRES on (A - omega) x = b starting from x (in/out).  Stops when every
-// right-hand side reaches ||r|| <= tol ||b|| or after max_apply operator
-// applications.  Returns per-RHS relative residual estimates.
+// LRCC_VERBOSE set: progress lines of the solvers on stderr.
 static bool verbose() {
     static int v = std::getenv("LRCC_VERBOSE") ? 1 : 0;
     return v != 0;
@@ -1824,11 +1883,13 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     ensure_alpha_programs(c);
     if (!c->own_stream) HIPCHK(hipStreamCreate(&c->own_stream));
     hipStream_t st = c->own_stream;
-    auto phase = [&](const char *what) {
-        if (!verbose()) return;
+    double ph[3] = {0, 0, 0}, t_last = 0;
+    auto phase = [&](int k, const char *what) {
         (void)hipStreamSynchronize(st);
-        std::fprintf(stderr, "[lrcc] alpha: %s done at %.2f s\n", what,
-                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        ph[k] = t - t_last;
+        t_last = t;
+        if (verbose()) std::fprintf(stderr, "[lrcc] alpha: %s done at %.2f s\n", what, t);
     };
     // axes with a non-zero dipole (the paper skips vanishing components, Sec. II.B)
     std::vector<int> axes;
@@ -1889,7 +1950,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         }
         c->lam_valid = true;
     }
-    phase("lambda");
+    phase(0, "lambda");
     // perturbation vectors and the batched response solve: rhs r = (j*2 + sign)*nax + a
     HIPCHK(c->prog_xi->run(st));
     const int R = nfreq * 2 * nax;
@@ -1945,7 +2006,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         eta[a] = vec(1);
         eta_vector(c, axes[a], eta[a], st);
     }
-    phase("response");
+    phase(1, "response");
     // eta . t for every axis and solution
     std::vector<cd> et((size_t)nax * R);
     for (int a = 0; a < nax; ++a)
@@ -1971,7 +2032,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         HIPCHK(hipMemcpy(S.t2.p, T2, nt2 * 16, hipMemcpyDeviceToDevice));
         run_precompute(c, true, st);
     }
-    phase("eta and F");
+    phase(2, "eta and F");
     // assemble alpha
     auto rid = [&](int j, int sg, int a) { return (j * 2 + sg) * nax + a; };
     for (int j = 0; j < nfreq; ++j)
@@ -1993,6 +2054,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
     rep.max_rel_residual = std::max(r1.max_rel_residual, r2.max_rel_residual);
     rep.rhs_sigmas = r1.rhs_sigmas + r2.rhs_sigmas + extra_rhs_sig;
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < 3; ++k) rep.phase_seconds[k] = ph[k];
 }
 
 
@@ -3889,7 +3951,7 @@ static void group_apply(lrcc_group *g, const int *nrhs, const double *const *ome
         if (nrhs[i] < 1 || !x1[i] || !x2[i] || !y1[i] || !y2[i]) throw LrccError(LRCC_E_ARG, "invalid nrhs or null pointer");
         prog[i] = sigma_program(c, precision, nrhs[i]);
         const Program *p = prog[i];
-        const bool j = p->ladder_args && p->ladder_args->packed == 2 && (i64)nrhs[i] * c->no * c->no >= 320;
+        const bool j = p->ladder_args && p->ladder_args->packed == 2;
         if (j) join.push_back(i);
         key.push_back(nrhs[i]);
         key.push_back(j ? 1 : 0);
@@ -3927,10 +3989,11 @@ static void group_apply(lrcc_group *g, const int *nrhs, const double *const *ome
             std::vector<LadderArgs> args;
             std::vector<long long> start{0}, tiles;
             for (int i : order) {
-                const LadderArgs &a = *prog[i]->ladder_args;
+                const LadderArgs a = ladder_prepared(*prog[i]->ladder_args);
+                long long blocks = 0;
                 args.push_back(a);
-                tiles.push_back(ladder_group_tiles<T>(a));
-                start.push_back(start.back() + tiles.back() * (long long)a.nk * a.nk * a.nk);
+                tiles.push_back(ladder_group_tiles<T>(a, &blocks));
+                start.push_back(start.back() + tiles.back() * blocks);
             }
             auto mem = std::make_unique<DevMem>();
             LadderGroup lg{};
@@ -4063,7 +4126,7 @@ lrcc_status lrcc_get_lambda(lrcc_ctx *c, double *l1, double *l2) {
 
 lrcc_status lrcc_set_ladder_mode(lrcc_ctx *c, int mode) {
     return guarded(c, [&] {
-        if (mode < 0 || mode > 2) throw LrccError(LRCC_E_ARG, "ladder mode must be 0, 1 or 2");
+        if (mode < 0 || mode > 3) throw LrccError(LRCC_E_ARG, "ladder mode must be 0, 1, 2 or 3");
         if (c->s64.ready) throw LrccError(LRCC_E_STATE, "the ladder mode is fixed once amplitudes are set");
         c->ladder_mode = mode;
     });
@@ -4112,6 +4175,14 @@ lrcc_status lrcc_ladder_flops(lrcc_ctx *c, int nrhs, int precision, double *exec
     });
 }
 
+lrcc_status lrcc_ladder_path(lrcc_ctx *c, int nrhs, int precision, int *path) {
+    return guarded(c, [&] {
+        if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
+        if (!path || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
+        *path = sigma_program(c, precision, nrhs)->ladder_path;
+    });
+}
+
 lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *c, int nrhs, int precision, double *mfma) {
     return guarded(c, [&] {
         if (!c->amp) throw LrccError(LRCC_E_STATE, "set_amplitudes must be called first");
@@ -4151,6 +4222,15 @@ lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int
         for (int x = 0; x < 3; ++x) (void)sigma_program(&c, LRCC_FP64, 1, true, 1 + x);
         (void)dens_program(&c, 1);
         (void)dens_program(&c, 4);
+        // the class-at-a-time ladder (mode 3) records other launches
+        c.ladder_mode = 3;
+        c.progs.clear();
+        c.progmem.clear();
+        for (int adj = 0; adj < 2; ++adj) {
+            (void)sigma_program(&c, LRCC_FP64, nrhs, adj != 0);
+            (void)sigma_program(&c, LRCC_FP32, nrhs, adj != 0);
+            (void)sigma_program(&c, LRCC_FP64, 1, adj != 0);
+        }
     } catch (LrccError &e) {
         st = (lrcc_status)e.code;
         if (msg && msglen > 0) snprintf(msg, msglen, "%s", e.what());

@@ -35,6 +35,7 @@ void arena_register(void *base, size_t size) { g_arenas.push_back({(const char *
 void arena_begin(void *base, size_t size) { g_arena = ArenaState{(char *)base, size, 0}; }
 void arena_end() { g_arena = ArenaState{}; }
 size_t arena_used() { return g_arena.used; }
+bool arena_active() { return g_arena.base != nullptr; }
 bool in_arena(const void *p) {
     for (const auto &a : g_arenas)
         if ((const char *)p >= a.first && (const char *)p < a.first + a.second) return true;

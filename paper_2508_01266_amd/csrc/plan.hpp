@@ -48,7 +48,7 @@ struct LrccError : std::runtime_error {
 
 // Event timing of recorded launches: pairs of events recorded on the launch
 // stream around every op with a given tag (and around whole program runs).
-enum { TAG_NONE = 0, TAG_LADDER = 1, TAG_PROGRAM = 2, NTAGS = 3 };
+enum { TAG_NONE = 0, TAG_LADDER = 1, TAG_PROGRAM = 2, TAG_BUILD = 3, NTAGS = 4 };
 struct Profiler {
     bool on = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
@@ -87,7 +87,7 @@ struct Program {
     std::vector<void *> owned;
     i64 flops = 0;       // executed real flops of the recorded GEMMs and ladder
     i64 last_flops = 0;  // executed flops of the op recorded last
-    i64 tag_flops[NTAGS] = {0, 0, 0};
+    i64 tag_flops[NTAGS] = {0, 0, 0, 0};
     void tag_last(int t) {
         tags.resize(ops.size(), TAG_NONE);
         tags.back() = t;
@@ -95,6 +95,9 @@ struct Program {
     }
     hipError_t run(hipStream_t s, Profiler *prof = nullptr);
     hipError_t run_range(hipStream_t s, size_t begin, size_t end);
+    // ladder path of a sigma program: 1 integrals rebuilt in LDS, 2 stored blocks, 3 blocks built
+    // one momentum class at a time (0: no ladder term)
+    int ladder_path = 0;
     // the rebuild-in-LDS ladder launch of a sigma program (for multi-chain launches)
     std::shared_ptr<LadderArgs> ladder_args;
     size_t ladder_op = (size_t)-1;

@@ -75,6 +75,8 @@ def lib():
         L.lrcc_ladder_flops.restype = ctypes.c_int
         L.lrcc_ladder_mfma_flops.argtypes = [vp, i, i, dp]
         L.lrcc_ladder_mfma_flops.restype = ctypes.c_int
+        L.lrcc_ladder_path.argtypes = [vp, i, i, ctypes.POINTER(i)]
+        L.lrcc_ladder_path.restype = ctypes.c_int
         for f in ("lrcc_set_profiling", "lrcc_read_profile", "lrcc_sigma_flops"):
             getattr(L, f).restype = ctypes.c_int
         L.lrcc_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -124,10 +126,12 @@ class SolveOpts(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int), ("outer", ctypes.c_int), ("sigma_fp64", ctypes.c_int),
                 ("sigma_fp32", ctypes.c_int), ("max_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("rhs_sigmas", ctypes.c_longlong)]
+                ("rhs_sigmas", ctypes.c_longlong), ("phase_seconds", ctypes.c_double * 3)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["phase_seconds"] = list(d["phase_seconds"])
+        return d
 
 
 def _c128(a, shape=None):
@@ -353,7 +357,8 @@ class Context:
         return l1, l2
 
     def set_ladder_mode(self, mode):
-        """0 automatic, 1 integrals rebuilt in LDS, 2 stored integral blocks (before set_amplitudes)."""
+        """0 automatic, 1 integrals rebuilt in LDS, 2 stored integral blocks, 3 integral blocks built
+        one momentum class at a time in every application (before set_amplitudes)."""
         self._check(self._L.lrcc_set_ladder_mode(self._h, int(mode)))
 
     def set_autotune(self, on=True):
@@ -366,11 +371,12 @@ class Context:
         self._check(self._L.lrcc_set_profiling(self._h, int(bool(on))))
 
     def read_profile(self):
-        """{'ladder': (ms_total, launches), 'sigma': (ms_total, applications)} since the last read."""
-        ms = (ctypes.c_double * 3)()
-        cnt = (ctypes.c_longlong * 3)()
+        """{'ladder': (ms_total, launches), 'sigma': (ms_total, applications), 'ladder_build': (ms_total,
+        launches)} since the last read."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_longlong * 4)()
         self._check(self._L.lrcc_read_profile(self._h, ms, cnt))
-        return {"ladder": (ms[1], cnt[1]), "sigma": (ms[2], cnt[2])}
+        return {"ladder": (ms[1], cnt[1]), "sigma": (ms[2], cnt[2]), "ladder_build": (ms[3], cnt[3])}
 
     def sigma_flops(self, nrhs, precision=FP64):
         out = ctypes.c_double()
@@ -385,6 +391,12 @@ class Context:
     def ladder_mfma_flops(self, nrhs, precision=FP64):
         out = ctypes.c_double()
         self._check(self._L.lrcc_ladder_mfma_flops(self._h, int(nrhs), int(precision), ctypes.byref(out)))
+        return out.value
+
+    def ladder_path(self, nrhs, precision=FP64):
+        """1 integrals rebuilt in LDS, 2 stored blocks, 3 blocks built one momentum class at a time."""
+        out = ctypes.c_int()
+        self._check(self._L.lrcc_ladder_path(self._h, int(nrhs), int(precision), ctypes.byref(out)))
         return out.value
 
     def apply_sigma_dev(self, x1, x2, y1, y2, omega=None, precision=FP64, stream=None, adjoint=False):

@@ -47,14 +47,15 @@ def test_alpha_matches_oracle(nk, o, v, naux, seed):
     assert np.abs(l1 - r1).max() < 1e-9 * max(1, np.abs(r1).max())
     assert np.abs(l2 - r2).max() < 1e-9 * max(1, np.abs(r2).max())
     c.close()
-    # stored ladder integrals: the lambda equations and the F term then read them through the
-    # transposed product
-    c = _ctx(case, 2)
-    s64, _ = c.solve(OMEGAS, tol=1e-11, precision=lr.FP64)
-    errs = np.abs(s64 - ref).max()
-    print(f"fp64 alpha, stored ladder integrals: max abs err {errs:.2e}", flush=True)
-    assert errs < 1e-9
-    c.close()
+    # stored ladder integrals (2) and integrals built one momentum class at a time (3): the lambda
+    # equations and the F term then read them through the transposed product
+    for mode in (2, 3):
+        c = _ctx(case, mode)
+        s64, _ = c.solve(OMEGAS, tol=1e-11, precision=lr.FP64)
+        errs = np.abs(s64 - ref).max()
+        print(f"fp64 alpha, ladder mode {mode}: max abs err {errs:.2e}", flush=True)
+        assert errs < 1e-9
+        c.close()
 
 
 def test_alpha_two_electron_sum_over_states():

@@ -39,13 +39,13 @@ def _rel(a, b):
 
 
 def test_batched_workload_sampled_rhs():
-    """All 48 right-hand sides in one launch, both precisions, both ladder modes (integrals
-    stored / rebuilt in LDS), with the autotuned launch variants the benchmark times; sampled
-    right-hand sides against the k-blocked oracle."""
+    """All 48 right-hand sides in one launch, both precisions, the three ladder modes (integrals
+    stored / built one momentum class at a time / rebuilt in LDS), with the autotuned launch
+    variants the benchmark times; sampled right-hand sides against the k-blocked oracle."""
     import paper_2508_01266_amd as lr
     w, H, t1, t2, x1, x2, om = _inputs("c3", 48)
     out = {}
-    for mode in (2, 1):
+    for mode in (2, 3, 1):
         c = lr.Context(0)
         c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
         c.set_ladder_mode(mode)
@@ -90,34 +90,37 @@ def test_large_orbital_slice_forward_and_transpose():
 
 
 def test_c4_forward_modes_and_transpose():
-    """Nk=7, o=10, v=60, Naux=210 (2 RHS): the two independent ladder paths (integrals rebuilt
-    in LDS, stored integral blocks) agree, and the transpose product satisfies the dot identity
-    with the forward product (properties that hold at any size; the oracle is too slow here)."""
+    """Nk=7, o=10, v=60, Naux=210 (2 RHS): the independent ladder paths (integrals rebuilt in
+    LDS, stored integral blocks, blocks built one momentum class at a time) agree, and the
+    transpose product satisfies the dot identity with the forward product in the rebuilt and
+    by-class modes (properties that hold at any size; the oracle is too slow here)."""
     import paper_2508_01266_amd as lr
     w, H, t1, t2, x1, x2, om = _inputs("c4", 2)
-    ys = {}
-    for mode in (1, 2):
+    ys, adj = {}, {}
+    rng = synth.rng_for(98, 7, 10, 60)
+    z1, z2 = synth.random_vectors(2, 7, 10, 60, rng, 0.1, 0.1)
+    z2 = z2 * 7
+    for mode in (1, 2, 3):
         c = lr.Context(0)
         c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
         c.set_ladder_mode(mode)
         c.set_amplitudes(t1, t2)
         ys[mode] = c.apply_sigma(x1, x2, om, lr.FP64)
-        if mode == 1:
-            rng = synth.rng_for(98, 7, 10, 60)
-            z1, z2 = synth.random_vectors(2, 7, 10, 60, rng, 0.1, 0.1)
-            z2 = z2 * 7
-            a1, a2 = c.apply_sigma_adjoint(z1, z2, om, lr.FP64)
+        if mode != 2:
+            adj[mode] = c.apply_sigma_adjoint(z1, z2, om, lr.FP64)
         c.close()
         print(f"c4 ladder mode {mode}: forward done", flush=True)
-    e1, e2 = _rel(ys[1][0], ys[2][0]), _rel(ys[1][1], ys[2][1])
-    print(f"c4 rebuilt vs stored ladder integrals: rel diff singles {e1:.2e} doubles {e2:.2e}", flush=True)
-    assert e1 < 1e-11 and e2 < 1e-11
-    y1, y2 = ys[1]
-    for r in range(2):
-        lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
-        rhs = np.sum(a1[r] * x1[r]) + 0.25 * np.sum(a2[r] * x2[r])
-        print(f"c4 dot identity rhs {r}: {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
-        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    for m in (2, 3):
+        e1, e2 = _rel(ys[1][0], ys[m][0]), _rel(ys[1][1], ys[m][1])
+        print(f"c4 rebuilt vs ladder mode {m}: rel diff singles {e1:.2e} doubles {e2:.2e}", flush=True)
+        assert e1 < 1e-11 and e2 < 1e-11
+    for m, (a1, a2) in adj.items():
+        y1, y2 = ys[m]
+        for r in range(2):
+            lhs = np.sum(z1[r] * y1[r]) + 0.25 * np.sum(z2[r] * y2[r])
+            rhs = np.sum(a1[r] * x1[r]) + 0.25 * np.sum(a2[r] * x2[r])
+            print(f"c4 dot identity, ladder mode {m}, rhs {r}: {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+            assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
 def test_c4s_dipole_gradient_against_finite_difference():

@@ -7,9 +7,11 @@ from tests.sigma_cases import make_case, oracle_sigma
 
 pytestmark = pytest.mark.gpu
 
-# (nk, o, v, naux, nrhs, seed): >= 320 (rhs, i, j) rows each, so all join the shared launch,
-# plus one small chain that runs its own ladder
+# (nk, o, v, naux, nrhs, seed): >= 320 (rhs, i, j) rows each, so all join the shared launch (the
+# ladder with its integrals rebuilt in LDS, mode 1), plus one small chain in the default mode (its
+# blocks built by momentum class) that runs its own program
 CHAINS = [(2, 3, 5, 7, 40, 61), (3, 2, 4, 6, 96, 62), (1, 4, 12, 48, 24, 63), (2, 2, 3, 5, 2, 64)]
+MODES = [1, 1, 1, 0]
 # complex64 sigma against the complex128 oracle: max-norm relative error bound (the measured
 # error of these sizes is near 1e-7; rounding of the longest contractions, K <= 500, stays far below)
 FP32_REL = 1e-5
@@ -21,11 +23,14 @@ def test_group_matches_per_chain_and_oracle():
     dev = torch.device("cuda:0")
     cases = [make_case(*c) for c in CHAINS]
     ctxs = []
-    for case in cases:
+    for case, mode in zip(cases, MODES):
         c = lr.Context(0)
         c.set_hamiltonian(case['o'], case['H']['fock'], case['H']['chol'], case['H']['dip'])
+        c.set_ladder_mode(mode)
         c.set_amplitudes(case['t1'], case['t2'])
         ctxs.append(c)
+    print("ladder paths:", [c.ladder_path(case['x1'].shape[0], lr.FP32) for c, case in zip(ctxs, cases)],
+          flush=True)
     X1 = [torch.from_numpy(c['x1']).to(dev) for c in cases]
     X2 = [torch.from_numpy(c['x2']).to(dev) for c in cases]
     OM = [torch.from_numpy(c['omega']).to(dev) for c in cases]

@@ -17,7 +17,7 @@ MESH_CASES = [
     ((2, 2, 1), 3, 5, 7, 24, 4),     # >= 192 (rhs, i, j) rows: 256-row packed ladder tiles, ragged
     ((2, 2, 1), 3, 5, 7, 40, 5),     # >= 320 rows: a ragged 384-row pipelined ladder tile
 ]
-MODES = {1: "rebuild", 2: "stored"}
+MODES = {1: "rebuild", 2: "stored", 3: "by class"}
 
 
 def _ctx(case, mode=0, amplitudes=True):
@@ -199,13 +199,13 @@ def test_eom_roots_on_mesh_match_oracle():
 
 
 def test_group_of_mesh_and_chain_contexts():
-    """A 2 x 2 x 2 mesh and a chain applied together in one persistent ladder launch give
-    bitwise the per-context sigmas."""
+    """A 2 x 2 x 2 mesh and a chain applied together in one persistent ladder launch (integrals
+    rebuilt in LDS, ladder mode 1) give bitwise the per-context sigmas."""
     import torch
     import paper_2508_01266_amd as lr
     dev = torch.device("cuda:0")
     cases = [make_case(8, 2, 3, 5, 96, 350, mesh=(2, 2, 2)), make_case(3, 2, 4, 6, 96, 351)]
-    ctxs = [_ctx(cs) for cs in cases]
+    ctxs = [_ctx(cs, 1) for cs in cases]
     X1 = [torch.from_numpy(cs['x1']).to(dev) for cs in cases]
     X2 = [torch.from_numpy(cs['x2']).to(dev) for cs in cases]
     OM = [torch.from_numpy(cs['omega']).to(dev) for cs in cases]

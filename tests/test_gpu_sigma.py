@@ -18,6 +18,8 @@ CASES = [
     (1, 4, 12, 48, 12, 7),     # c1 sizes with 12 right-hand sides (192 rows)
     (2, 3, 5, 7, 40, 8),       # >= 320 rows: one ragged 384-row pipelined ladder tile
     (1, 4, 12, 48, 30, 9),     # c1 sizes, 480 rows: two pipelined tiles, the second ragged
+    (5, 8, 4, 10, 1, 10),      # one right-hand side, 156 unique rows per momentum class (ki <= kj pairs
+                               # with one ki + kj share the pipelined tiles), as the one-vector products
 ]
 
 
@@ -35,8 +37,8 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-# ladder integrals rebuilt in LDS (1) and stored blocks (2)
-MODES = {1: "rebuild", 2: "stored"}
+# ladder integrals rebuilt in LDS (1), stored blocks (2), blocks built one momentum class at a time (3)
+MODES = {1: "rebuild", 2: "stored", 3: "by class"}
 
 
 @pytest.mark.parametrize("nk,o,v,naux,nrhs,seed", CASES)

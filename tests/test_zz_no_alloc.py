@@ -13,9 +13,12 @@ pytestmark = pytest.mark.gpu
 
 
 def _ctx(case):
+    # ladder mode 1 (integrals rebuilt in LDS), the path the no-allocation call takes in the
+    # automatic mode, so that both entry points run the same launches
     import paper_2508_01266_amd as lr
     c = lr.Context(0)
     c.set_hamiltonian(case['o'], case['H']['fock'], case['H']['chol'], case['H']['dip'])
+    c.set_ladder_mode(1)
     c.set_amplitudes(case['t1'], case['t2'])
     return c
 
