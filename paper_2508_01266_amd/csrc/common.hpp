@@ -65,14 +65,35 @@ template <> struct Cx<float> { typedef float2 type; };
 
 // Three-level split of a GEMM index: idx = (i0*d1 + i1)*d2 + i2 and the
 // address contribution is i0*s[0] + i1*s[1] + i2*s[2] (units: complex elements).
-// Three-level index split idx = (i0 * d1 + i1) * d2 + i2.  The divisions use
-// multiply-high magic numbers (exact for 0 <= idx < 2^31): x / d = (x * m) >> (31 + l)
-// with l = ceil(log2 d), m = ceil(2^(31+l) / d); set by split_magic before a launch.
+// The divisions use multiply-high magic numbers (exact for 0 <= idx < 2^31):
+// x / d = (x * m) >> (31 + l) with l = ceil(log2 d), m = ceil(2^(31+l) / d); set by
+// split_magic before a launch.
+// Triangle split (tri = n > 1, made by tri_split): (i1, i2) runs over the n(n-1)/2 pairs
+// p < q of an n x n block, packed as a d1 x d2 rectangle by pairing row r of the strict
+// upper triangle with a complementary row (n even: rows r and n-1-r, d1 = n/2, d2 = n-1;
+// n odd: rows r and n-2-r, d1 = (n-1)/2, d2 = n); the contribution is
+// i0*s[0] + p*s[1] + q*s[2].
 struct Split {
     int d1, d2;
     unsigned m1 = 0, m2 = 0;   // magic multipliers for d1, d2
     int l1 = 0, l2 = 0;        // their shifts
+    int tri = 0;               // n of a triangle split, 0 for a plain one
 };
+inline Split tri_split(int n) {
+    Split s{(n & 1) ? (n - 1) / 2 : n / 2, (n & 1) ? n : n - 1};
+    s.tri = n;
+    return s;
+}
+// pair (p, q), p < q, of the packed position (r, c) of a triangle split of n
+__host__ __device__ inline void tri_pair(int r, int c, int n, int &p, int &q) {
+    if (c < n - 1 - r) {
+        p = r;
+        q = r + 1 + c;
+    } else {
+        p = n - 1 - (n & 1) - r;
+        q = c + 1 - (n & 1);
+    }
+}
 struct Strides {
     i64 s[3];
 };
@@ -90,15 +111,22 @@ __host__ __device__ inline int fdiv(int x, unsigned m, int l) {
     return (int)(((unsigned long long)(unsigned)x * m) >> (31 + l));
 }
 // 32-bit form for offsets inside one operand block (bounded on the host)
+// TRI: the split may be a triangle split (checked at run time); false: a plain split (the
+// GEMM's reduction index inside its K loop, where the check would cost every load)
+template <bool TRI = true>
 __host__ __device__ inline int split_off32(int idx, Split sp, int s0, int s1, int s2) {
     const int q = fdiv(idx, sp.m2, sp.l2);
     const int q0 = fdiv(q, sp.m1, sp.l1);
-    return q0 * s0 + (q - q0 * sp.d1) * s1 + (idx - q * sp.d2) * s2;
+    int i1 = q - q0 * sp.d1, i2 = idx - q * sp.d2;
+    if (TRI && sp.tri) tri_pair(i1, i2, sp.tri, i1, i2);
+    return q0 * s0 + i1 * s1 + i2 * s2;
 }
 __host__ __device__ inline i64 split_off(int idx, Split sp, Strides st) {
     const int q = fdiv(idx, sp.m2, sp.l2);
     const int q0 = fdiv(q, sp.m1, sp.l1);
-    return (i64)q0 * st.s[0] + (i64)(q - q0 * sp.d1) * st.s[1] + (i64)(idx - q * sp.d2) * st.s[2];
+    int i1 = q - q0 * sp.d1, i2 = idx - q * sp.d2;
+    if (sp.tri) tri_pair(i1, i2, sp.tri, i1, i2);
+    return (i64)q0 * st.s[0] + (i64)i1 * st.s[1] + (i64)i2 * st.s[2];
 }
 
 // One strided complex GEMM over a list of output blocks ("jobs").
@@ -131,7 +159,8 @@ struct GemmArgs {
     int ksplit;
     void *part;
     const float *jscale; // per-job multiplier of alpha (full job list), or null
-    int kind;            // 0 generic, 1 stored-integral ladder (a separate kernel symbol for profiling)
+    int kind;            // 0 generic, 1 ladder over integral blocks (a separate kernel symbol for
+                         // profiling; the launcher takes instance 2 when sk is a triangle split)
 };
 
 template <typename T>

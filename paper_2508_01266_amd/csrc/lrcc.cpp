@@ -317,10 +317,32 @@ static int ladder_path(lrcc_ctx *c, const void *Wst, size_t elem_bytes) {
     return (size_t)c->ncls_slots * v2 * v2 * elem_bytes <= fr / 8 ? 3 : 1;
 }
 
-// cls < 0: every unique block into its slot of W (nwslot blocks); cls >= 0: the blocks of
-// momentum class cls into their class slots (ncls_slots blocks).
+// Slot of block (ka, kb, ke) in an integral-block array: the global slot (cls0 < 0), or, in the
+// array of the momentum classes cls0, cls0 + 1, ... (ncls_slots blocks each), the slot within its
+// class after those of the classes before it.
+static i64 block_slot(const lrcc_ctx *c, int cls0, int ka, int kb, int ke) {
+    const size_t at = ((size_t)ka * c->nk + kb) * c->nk + ke;
+    if (cls0 < 0) return c->wslot[at];
+    return c->wcls[at] < 0 ? -1 : (i64)(kclass(c, ka, kb) - cls0) * c->ncls_slots + c->wcls[at];
+}
+// whether momentum class k is in [cls0, cls0 + ncls) (every class for cls0 < 0)
+static bool in_classes(int k, int cls0, int ncls) { return cls0 < 0 || (k >= cls0 && k < cls0 + ncls); }
+
+// Momentum classes per batch of the class-built ladder (mode 3): as many as fit in an eighth of
+// the free device memory, at most 4 GiB (one class at least).
+static int class_batch(lrcc_ctx *c, size_t elem_bytes) {
+    const size_t v2 = (size_t)c->nv * c->nv, per = (size_t)c->ncls_slots * v2 * v2 * elem_bytes;
+    size_t fr = 0, tot = 0;
+    if (g_dry_run) return std::min(c->nk, 2);      // plan checks: several batches, the last ragged
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 1;
+    const size_t budget = std::min(fr / 8, (size_t)4 << 30);
+    return (int)std::max<size_t>(1, std::min<size_t>(c->nk, budget / std::max<size_t>(per, 1)));
+}
+
+// cls0 < 0: every unique block into its slot of W (nwslot blocks); cls0 >= 0: the blocks of the
+// momentum classes cls0 .. cls0 + ncls - 1 into their slots of a class array (block_slot).
 template <typename T>
-void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void *W, int cls = -1,
+void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void *W, int cls0 = -1, int ncls = 0,
                   int tag = TAG_NONE) {
     const int nk = c->nk, v = c->nv, naux = c->naux;
     const i64 vv = (i64)v * v, v4 = vv * vv, lsz = (i64)nk * nk * naux * vv;
@@ -364,8 +386,8 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
             for (int kb = ka; kb < nk; ++kb)
                 for (int ke = 0; ke < nk; ++ke) {
                     const int kf = c->km.comb(ka, kb, ke);
-                    if (cls >= 0 && kclass(c, ka, kb) != cls) continue;
-                    const int sl = (cls < 0 ? c->wslot : c->wcls)[((size_t)ka * nk + kb) * nk + ke];
+                    if (!in_classes(kclass(c, ka, kb), cls0, ncls)) continue;
+                    const i64 sl = block_slot(c, cls0, ka, kb, ke);
                     if (sl < 0) continue;
                     offC.push_back(sl * v4);
                     const int k2 = part == 0 ? ke : kf, k4 = part == 0 ? kf : ke;
@@ -374,7 +396,7 @@ void build_wstore(lrcc_ctx *c, Program &P, const void *La, const void *Lb, void 
                     beg.push_back((int)segA.size());
                     js.push_back(ke == kf ? 0.5f : 1.0f);
                 }
-        raw_gemm<T>(P, g, offC, beg, segA, segB, lsz, lsz, (i64)(cls < 0 ? c->nwslot : c->ncls_slots) * v4, js);
+        raw_gemm<T>(P, g, offC, beg, segA, segB, lsz, lsz, (i64)(cls0 < 0 ? c->nwslot : ncls * c->ncls_slots) * v4, js);
         if (tag != TAG_NONE) P.tag_last(tag);
         P.name_last(part == 0 ? "ladder integrals (direct)" : "ladder integrals (exchange)");
     }
@@ -776,6 +798,102 @@ LadderArgs ladder_args(lrcc_ctx *c, const void *Y, const void *La, const void *L
     return la;
 }
 
+// Ladder products over stored or class-built integral blocks W'(ka,kb,ke)[e][f][a][b] (ka <= kb,
+// ke <= kf; the ke = kf blocks hold W'/2), for the row pairs ki <= kj of the momentum classes
+// cls0 .. cls0 + ncls - 1 (all classes, global slots, for cls0 < 0).  Every index pair that the antisymmetry makes redundant is skipped: rows
+// (r, i < j) of the diagonal blocks ki = kj, columns a < b of the blocks ka = kb and reduction
+// terms e < f of the blocks ke = kf are addressed through triangle splits, so the launches form
+// only unique (rows, outputs, inputs) products up to the off-diagonal blocks' own i >= j, a >= b,
+// e >= f halves, which are the partners' values.  One launch per combination of diagonal and
+// off-diagonal rows, columns and reduction blocks (they differ in M, N, K).
+//  forward:   Z(ki,kj,ka)[rows][ab] += 4 alpha sum_{ke <= kf} Y(ki,kj,ke)[rows][ef] W'(ka,kb,ke)
+//             (x2 more for ke = kf: the e < f terms of W'/2); the factor 4 = 2 for the (kj,ki) /
+//             i > j partner rows and 2 for the (kb,ka) / a > b partner columns, which the
+//             P(ij)P(ab) assembly reproduces from antisymmetry;
+//  transpose: T(ki,kj,ke)[rows][ef] += 2 alpha sum_{ka <= kb} Zbar(ki,kj,ka)[rows][ab] W'(ka,kb,ke)^T
+//             (x2 more for the e < f columns of ke = kf, whose e > f half stays zero); the ka = kb
+//             terms a < b give the full-range sum of Zbar W'^T / 2; the rows carry 2 for their
+//             partners, T is completed by expand_ab.
+template <typename T>
+void ladder_block_gemms(lrcc_ctx *c, Program &P, bool transpose, const void *A, const void *W, i64 wblocks,
+                        void *C, i64 sizeA, i64 sizeC, int R, int cls0, int ncls, std::complex<double> alpha,
+                        const char *name) {
+    const int nk = c->nk, o = c->no, v = c->nv;
+    const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv;
+    const i64 Po = (i64)o * (o - 1) / 2, Pv = (i64)v * (v - 1) / 2;
+    for (int rdiag = 0; rdiag < 2; ++rdiag)
+        for (int ndiag = 0; ndiag < 2; ++ndiag)
+            for (int kdiag = 0; kdiag < 2; ++kdiag) {
+                if ((rdiag && Po == 0) || ((ndiag || kdiag) && Pv == 0)) continue;
+                GemmArgs g{};
+                g.shape = -1;
+                g.kind = 1;
+                g.A = A;
+                g.B = W;
+                g.C = C;
+                // rows (r, i, j): all o^2 of an off-diagonal pair, i < j of a diagonal one
+                if (rdiag) {
+                    g.M = (int)(R * Po);
+                    g.sm = tri_split(o);
+                    g.Am = g.Cm = Strides{{(i64)o * o * vv, (i64)o * vv, vv}};
+                } else {
+                    g.M = R * o * o;
+                    g.sm = Split{1, g.M};
+                    g.Am = g.Cm = Strides{{0, 0, vv}};
+                }
+                // columns: (a, b) forward, (e, f) transposed; reduction: the other pair
+                const Split full{1, (int)vv}, tri = tri_split(v);
+                g.N = (int)(ndiag ? Pv : vv);
+                g.sn = ndiag ? tri : full;
+                g.K = (int)(kdiag ? Pv : vv);
+                g.sk = kdiag ? tri : full;
+                const Strides pair_in_row = ndiag ? Strides{{0, v, 1}} : Strides{{0, 0, 1}};
+                g.Cn = pair_in_row;
+                g.Ak = kdiag ? Strides{{0, v, 1}} : Strides{{0, 0, 1}};
+                if (!transpose) {
+                    g.Bk = kdiag ? Strides{{0, v * vv, vv}} : Strides{{0, 0, vv}};
+                    g.Bn = ndiag ? Strides{{0, v, 1}} : Strides{{0, 0, 1}};
+                    g.bNfast = 1;
+                } else {
+                    g.Bk = kdiag ? Strides{{0, v, 1}} : Strides{{0, 0, 1}};
+                    g.Bn = ndiag ? Strides{{0, v * vv, vv}} : Strides{{0, 0, vv}};
+                    g.bNfast = 0;
+                }
+                g.aMfast = 0;
+                const double f = transpose ? 2.0 * (ndiag ? 2.0 : 1.0) : 4.0 * (kdiag ? 2.0 : 1.0);
+                g.alpha_re = alpha.real() * f;
+                g.alpha_im = alpha.imag() * f;
+                g.beta = 1;
+                std::vector<i64> offC, segA, segB;
+                std::vector<int> beg{0};
+                for (int ki = 0; ki < nk; ++ki)
+                    for (int kj = ki; kj < nk; ++kj) {
+                        if ((ki == kj) != (rdiag == 1) || !in_classes(kclass(c, ki, kj), cls0, ncls)) continue;
+                        // output blocks: ka <= kb forward, ke <= kf transposed; reduction: the other
+                        for (int kn = 0; kn < nk; ++kn) {
+                            const int kn2 = c->km.comb(ki, kj, kn);
+                            if (kn > kn2 || (kn == kn2) != (ndiag == 1)) continue;
+                            const size_t s0 = segA.size();
+                            for (int kr = 0; kr < nk; ++kr) {
+                                const int kr2 = c->km.comb(ki, kj, kr);
+                                if (kr > kr2 || (kr == kr2) != (kdiag == 1)) continue;
+                                const int ka = transpose ? kr : kn, kb = transpose ? kr2 : kn2;
+                                const int ke = transpose ? kn : kr;
+                                segA.push_back((((i64)ki * nk + kj) * nk + kr) * inner);
+                                segB.push_back(block_slot(c, cls0, ka, kb, ke) * vv * vv);
+                            }
+                            if (segA.size() == s0) continue;
+                            offC.push_back((((i64)ki * nk + kj) * nk + kn) * inner);
+                            beg.push_back((int)segA.size());
+                        }
+                    }
+                if (offC.empty()) continue;
+                raw_gemm<T>(P, g, offC, beg, segA, segB, sizeA, wblocks * vv * vv, sizeC);
+                P.tag_last(TAG_LADDER);
+                P.name_last(name);
+            }
+}
+
 template <typename T>
 Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
     const int nk = c->nk, o = c->no, v = c->nv;
@@ -806,64 +924,20 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
             const bool by_class = ladder_path(c, S.Wst, 2 * sizeof(T)) == 3 && S.La && S.Lb;
             P->ladder_path = S.Wst ? 2 : by_class ? 3 : 1;
             if (S.Wst || by_class) {
-                // stored integrals: Z(ki,kj,ka) += alpha' sum_{ke <= kf} Y(ki,kj,ke) W'(ka,kb,ke) for
-                // ka <= kb and ki <= kj, alpha' = alpha times 2 when ka < kb and 2 when ki < kj (the
-                // (kb,ka) and (kj,ki) partner blocks are left to the P(ij)P(ab) assembly, which
-                // reproduces them from antisymmetry).  By class (mode 3): for each momentum class
+                // stored integrals: Z(ki,kj,ka) += alpha' sum_{ke <= kf} Y(ki,kj,ke) W'(ka,kb,ke) for the
+                // unique pairs (ladder_block_gemms).  By class (mode 3): for each momentum class
                 // K = ki + kj = ka + kb, the class's blocks W' are built into a scratch array of
-                // ncls_slots blocks and consumed by that class's GEMM before the next class
-                const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv;
-                const i64 wblocks = by_class ? c->ncls_slots : c->nwslot;
+                // ncls_slots blocks and consumed by that class's products before the next class
+                const i64 vv = (i64)v * v;
+                const int nb = by_class ? class_batch(c, 2 * sizeof(T)) : nk;
+                const i64 wblocks = by_class ? (i64)nb * c->ncls_slots : c->nwslot;
                 void *Wb = by_class ? P->alloc((size_t)wblocks * vv * vv * 2 * sizeof(T)) : S.Wst;
-                for (int K = by_class ? 0 : -1; K < (by_class ? nk : 0); ++K) {
-                    if (by_class) build_wstore<T>(c, *P, S.La, S.Lb, Wb, K, TAG_BUILD);
-                    GemmArgs g{};
-                    g.shape = -1;
-                    g.kind = 1;
-                    g.A = op.A.p;
-                    g.B = Wb;
-                    g.C = op.C.p;
-                    g.M = R * o * o;
-                    g.N = (int)vv;
-                    g.K = (int)vv;
-                    g.sm = Split{1, g.M};
-                    g.Am = Strides{{0, 0, vv}};
-                    g.Cm = Strides{{0, 0, vv}};
-                    g.sk = Split{1, g.K};
-                    g.Ak = Strides{{0, 0, 1}};
-                    g.Bk = Strides{{0, 0, vv}};
-                    g.sn = Split{1, g.N};
-                    g.Bn = Strides{{0, 0, 1}};
-                    g.Cn = Strides{{0, 0, 1}};
-                    g.aMfast = 0;
-                    g.bNfast = 1;
-                    g.alpha_re = op.alpha.real();
-                    g.alpha_im = op.alpha.imag();
-                    g.beta = 1;
-                    const std::vector<int> &slot = by_class ? c->wcls : c->wslot;
-                    std::vector<i64> offC, segA, segB;
-                    std::vector<int> beg{0};
-                    std::vector<float> js;
-                    for (int ki = 0; ki < nk; ++ki)
-                        for (int kj = ki; kj < nk; ++kj) {
-                            if (K >= 0 && kclass(c, ki, kj) != K) continue;
-                            for (int ka = 0; ka < nk; ++ka) {
-                                const int kb = c->km.comb(ki, kj, ka);
-                                if (ka > kb) continue;
-                                for (int ke = 0; ke < nk; ++ke) {
-                                    const int kf = c->km.comb(ki, kj, ke);
-                                    if (ke > kf) continue;
-                                    segA.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
-                                    segB.push_back((i64)slot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
-                                }
-                                offC.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
-                                beg.push_back((int)segA.size());
-                                js.push_back((ka < kb ? 2.0f : 1.0f) * (ki < kj ? 2.0f : 1.0f));
-                            }
-                        }
-                    raw_gemm<T>(*P, g, offC, beg, segA, segB, op.A.count(), wblocks * vv * vv, op.C.count(), js);
-                    P->tag_last(TAG_LADDER);
-                    P->name_last(by_class ? "ladder (class integrals)" : "ladder (stored integrals)");
+                for (int K0 = by_class ? 0 : -1; K0 < (by_class ? nk : 0); K0 += by_class ? nb : 1) {
+                    const int ncl = by_class ? std::min(nb, nk - K0) : 0;
+                    if (by_class) build_wstore<T>(c, *P, S.La, S.Lb, Wb, K0, ncl, TAG_BUILD);
+                    ladder_block_gemms<T>(c, *P, false, op.A.p, Wb, wblocks, op.C.p, op.A.count(), op.C.count(), R,
+                                          K0, ncl, op.alpha,
+                                          by_class ? "ladder (class integrals)" : "ladder (stored integrals)");
                 }
                 break;
             }
@@ -971,79 +1045,25 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
             const bool by_class = ladder_path(c, S.Wst, 2 * sizeof(T)) == 3 && S.La && S.Lb;
             P->ladder_path = S.Wst ? 2 : by_class ? 3 : 1;
             if (S.Wst || by_class) {
-                // stored integrals, transposed: with Zbar antisymmetric in (a, b),
+                // stored integrals, transposed (ladder_block_gemms): with Zbar antisymmetric in (a, b),
                 //   dtau_bar(ki,kj,ke) = alpha [sum_{ka<kb} Zbar(ki,kj,ka) W'(ka,kb,ke)^T
                 //                              + 1/2 sum_{ka=kb} Zbar(ki,kj,ka) W'(ka,ka,ke)^T]
-                // for ke <= kf (the stored ke = kf blocks carry W'/2, which the completion below
-                // doubles back); the result goes to a zeroed scratch array and expand_ab adds it and
-                // its (e, f)-antisymmetric (kf, ke) partner blocks to dtau_bar.  By class (mode 3):
-                // the blocks of one momentum class at a time in a scratch array, as in the forward
-                // product
-                const i64 vv = (i64)v * v, inner = (i64)R * o * o * vv, n = op.A.count();
+                // for ke <= kf, into a zeroed scratch array; expand_ab adds it and its (e, f)-
+                // antisymmetric (kf, ke) partner blocks to dtau_bar.  By class (mode 3): the blocks
+                // of one momentum class at a time in a scratch array, as in the forward product
+                const i64 vv = (i64)v * v, n = op.A.count();
                 void *tmp = P->alloc((size_t)n * 2 * sizeof(T)), *dst = op.A.p;
-                const i64 wblocks = by_class ? c->ncls_slots : c->nwslot;
+                const int nb = by_class ? class_batch(c, 2 * sizeof(T)) : nk;
+                const i64 wblocks = by_class ? (i64)nb * c->ncls_slots : c->nwslot;
                 void *Wb = by_class ? P->alloc((size_t)wblocks * vv * vv * 2 * sizeof(T)) : S.Wst;
-                const std::vector<int> &slot = by_class ? c->wcls : c->wslot;
                 const KMesh km = c->km;
                 P->ops.push_back([tmp, n](hipStream_t s) { return zero_fill<T>(tmp, n, s); });
-                for (int K = by_class ? 0 : -1; K < (by_class ? nk : 0); ++K) {
-                    if (by_class) build_wstore<T>(c, *P, S.La, S.Lb, Wb, K, TAG_BUILD);
-                    for (int half = 0; half < 2; ++half) {
-                        GemmArgs g{};
-                        g.shape = -1;
-                        g.kind = 1;
-                        g.A = op.C.p;
-                        g.B = Wb;
-                        g.C = tmp;
-                        g.M = R * o * o;
-                        g.N = (int)vv;
-                        g.K = (int)vv;
-                        g.sm = Split{1, g.M};
-                        g.Am = Strides{{0, 0, vv}};
-                        g.Cm = Strides{{0, 0, vv}};
-                        g.sk = Split{1, g.K};
-                        g.Ak = Strides{{0, 0, 1}};
-                        g.Bk = Strides{{0, 0, 1}};
-                        g.sn = Split{1, g.N};
-                        g.Bn = Strides{{0, 0, vv}};
-                        g.Cn = Strides{{0, 0, 1}};
-                        g.aMfast = 0;
-                        g.bNfast = 0;
-                        g.alpha_re = op.alpha.real() * (half ? 0.5 : 1.0);
-                        g.alpha_im = op.alpha.imag() * (half ? 0.5 : 1.0);
-                        g.beta = 1;
-                        // only ki <= kj: dtau_bar is read by the transposed tau step alone, whose four
-                        // (i, j) / (a, b) placements make a block (ki, kj) stand for its (kj, ki)
-                        // partner at twice the weight (the transposed P(ij)P(ab) of the forward
-                        // assembly)
-                        std::vector<i64> offC, segA, segB;
-                        std::vector<int> beg{0};
-                        std::vector<float> js;
-                        for (int ki = 0; ki < nk; ++ki)
-                            for (int kj = ki; kj < nk; ++kj) {
-                                if (K >= 0 && kclass(c, ki, kj) != K) continue;
-                                for (int ke = 0; ke < nk; ++ke) {
-                                    const int kf = c->km.comb(ki, kj, ke);
-                                    if (ke > kf) continue;
-                                    const size_t s0 = segA.size();
-                                    for (int ka = 0; ka < nk; ++ka) {
-                                        const int kb = c->km.comb(ki, kj, ka);
-                                        if (half ? ka != kb : ka >= kb) continue;
-                                        segA.push_back((((i64)ki * nk + kj) * nk + ka) * inner);
-                                        segB.push_back((i64)slot[((size_t)ka * nk + kb) * nk + ke] * vv * vv);
-                                    }
-                                    if (segA.size() == s0) continue;
-                                    offC.push_back((((i64)ki * nk + kj) * nk + ke) * inner);
-                                    beg.push_back((int)segA.size());
-                                    js.push_back(ki < kj ? 2.0f : 1.0f);
-                                }
-                            }
-                        if (offC.empty()) continue;
-                        raw_gemm<T>(*P, g, offC, beg, segA, segB, op.C.count(), wblocks * vv * vv, n, js);
-                        P->tag_last(TAG_LADDER);
-                        P->name_last(half ? "ladder (stored integrals, transposed, ka = kb)"
-                                          : "ladder (stored integrals, transposed)");
-                    }
+                for (int K0 = by_class ? 0 : -1; K0 < (by_class ? nk : 0); K0 += by_class ? nb : 1) {
+                    const int ncl = by_class ? std::min(nb, nk - K0) : 0;
+                    if (by_class) build_wstore<T>(c, *P, S.La, S.Lb, Wb, K0, ncl, TAG_BUILD);
+                    ladder_block_gemms<T>(c, *P, true, op.C.p, Wb, wblocks, tmp, op.C.count(), n, R, K0, ncl, op.alpha,
+                                          by_class ? "ladder (class integrals, transposed)"
+                                                   : "ladder (stored integrals, transposed)");
                 }
                 P->ops.push_back([tmp, dst, km, R, o, v](hipStream_t s) {
                     return expand_ab<T>(tmp, dst, km, R, o, v, 1.0, s);

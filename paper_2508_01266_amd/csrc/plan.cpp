@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <set>
 
 namespace lrcc {
 
@@ -354,10 +355,30 @@ i64 block_of(const TInfo &t, const std::map<char, int> &k) {
 }  // namespace
 
 namespace {
+// largest offset a split forms (strides are non-negative; a triangle split of n reaches the pair
+// (n-2, n-1))
 i64 max_off(int total, Split sp, Strides st) {
     if (total <= 0) return 0;
     const int e0 = total / (sp.d1 * sp.d2);
-    return (i64)(e0 - 1) * st.s[0] + (i64)(sp.d1 - 1) * st.s[1] + (i64)(sp.d2 - 1) * st.s[2];
+    const int m1 = sp.tri ? sp.tri - 2 : sp.d1 - 1, m2 = sp.tri ? sp.tri - 1 : sp.d2 - 1;
+    return (i64)(e0 - 1) * st.s[0] + (i64)m1 * st.s[1] + (i64)m2 * st.s[2];
+}
+
+// A triangle split must visit every pair p < q of its n x n block exactly once (checked once per n).
+void check_tri(const Split &sp) {
+    if (!sp.tri) return;
+    static std::set<int> ok;
+    if (ok.count(sp.tri)) return;
+    const int n = sp.tri;
+    if (n < 2 || sp.d1 * sp.d2 != n * (n - 1) / 2) throw LrccError(1, "bad triangle split");
+    std::vector<char> seen((size_t)n * n, 0);
+    for (int r = 0; r < sp.d1; ++r)
+        for (int c = 0; c < sp.d2; ++c) {
+            int p, q;
+            tri_pair(r, c, n, p, q);
+            if (!(0 <= p && p < q && q < n) || seen[(size_t)p * n + q]++) throw LrccError(1, "bad triangle split");
+        }
+    ok.insert(n);
 }
 }  // namespace
 
@@ -369,8 +390,12 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
     if (g.njobs == 0) return;
     if (!jscale.empty() && jscale.size() != offC.size()) throw LrccError(1, "per-job scale list of the wrong length");
     // every address formed by the kernel stays inside the operands
+    if (g.M <= 0 || g.N <= 0) return;                // no outputs
     if (g.M % (g.sm.d1 * g.sm.d2) || g.N % (g.sn.d1 * g.sn.d2) || g.K % (g.sk.d1 * g.sk.d2))
         throw LrccError(1, "GEMM split does not divide its dimension");
+    check_tri(g.sm);
+    check_tri(g.sn);
+    check_tri(g.sk);
     for (const Strides *st : {&g.Am, &g.Ak, &g.Bk, &g.Bn, &g.Cm, &g.Cn})
         for (int i = 0; i < 3; ++i)
             if (st->s[i] < 0) throw LrccError(1, "negative GEMM stride");

@@ -194,3 +194,32 @@ def test_c4s_fock_gradient_against_central_difference():
     # O(h^2) truncation (~1e-10 relative) plus the solver tolerance divided by h (1e-12 |alpha| / 1e-5)
     assert err < 1e-5 * max(1.0, abs(ref))
     c.close()
+
+
+def test_cholesky_scale_reading_on_batched_workload():
+    """The Cholesky scale of the batched workload (Nk=5, o=8, v=40, Naux=144): with the small
+    workloads' N(0, 0.05^2) entries the random two-electron coupling outweighs the orbital-energy
+    gaps and the device CCSD iteration does not converge, so there are no ground-state amplitudes
+    to pose the response equations at; with the reduced scale the ground state converges and so
+    does the response solve (the reading the synthetic inputs take for the larger workloads)."""
+    import paper_2508_01266_amd as lr
+    w = synth.WORKLOADS["c3"]
+    out = {}
+    for sig in (0.05, w.chol_sigma):
+        rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir)
+        H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=sig)
+        c = lr.Context(0)
+        c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+        try:
+            _, _, e, rep = c.solve_ccsd(tol=1e-9, max_iter=80)
+            a, arep = c.solve([0.0656], axis_mask=4, tol=1e-10, precision=lr.FP64)
+            out[sig] = (e, rep, a[0, 2, 2], arep)
+            print(f"sigma {sig:.4f}: CCSD E/cell {e:.8f} in {rep['outer']} iterations, alpha_zz {a[0, 2, 2]:.6f} "
+                  f"after {arep['sigma_fp64']} operator applications", flush=True)
+        except lr.LrccError as err:
+            out[sig] = err
+            print(f"sigma {sig:.4f}: {err}", flush=True)
+        c.close()
+    assert isinstance(out[0.05], lr.LrccError) and out[0.05].status == 6
+    e, rep, a, arep = out[w.chol_sigma]
+    assert rep['converged'] and arep['converged'] and np.isfinite(a)
