@@ -25,12 +25,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1 GPU"
 
-# HBM traffic of one complex64 ladder launch on the batched workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the counter's reading for a plain 2 GiB copy
-# (fetch x2.0, write x1.0).  Valid only for the ladder path and kernel sources it was measured on.
-LADDER_TRAFFIC = {"workload": "c3", "ladder_path": 1,
-                  "sources_sha256": "70768cb8f9a608446e77a307d05bd301b0bdea5c2e8cf2ad6fdba3c89bfb9542",
-                  "bytes": 687.8e9}
+# HBM traffic of the complex64 ladder launches of one application on the batched workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the counter's reading for a plain
+# 2 GiB copy (fetch x2.0, write x1.0).  Valid only for the ladder path and kernel sources it was
+# measured on.
+LADDER_TRAFFIC = {  # ladder path -> measured HBM bytes per application of the complex64 sigma
+    3: {"workload": "c3", "sources_sha256": "1a790315750aff30f3fcf5de834870d87ba46255ef17594a0960ee8690ec81cc",
+        "bytes": 40.6e9},
+    1: {"workload": "c3", "sources_sha256": "6c4c3d9cd1892f1c96e47795d021fce848b106ebe75fd82d99a5eba1c67645eb",
+        "bytes": 188.6e9},
+}
 
 
 LADDER_PATH_TEXT = {1: "ladder integrals rebuilt in LDS from the Cholesky vectors",
@@ -345,8 +349,9 @@ def main():
     ap.add_argument("--mesh", action="store_true", help="also time the sigma on a 2x2x2 k mesh")
     ap.add_argument("--velocity", action="store_true", help="also time the velocity-gauge alpha (c2)")
     ap.add_argument("--counters", action="store_true",
-                    help="only one complex64 sigma (heuristic launch variants) and then a plain 2 GiB device "
-                         "copy that calibrates hardware byte counters; prints no JSON line")
+                    help="only one complex64 sigma (the tuned launch variants: from the cache that "
+                         "LRCC_TUNE_CACHE names, else timed first) and then a plain 2 GiB device copy that "
+                         "calibrates hardware byte counters; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
@@ -366,7 +371,9 @@ def main():
     ctx.set_hamiltonian(o, H['fock'], H['chol'], H['dip'])
     ctx.set_ladder_mode(args.ladder_mode)
     ctx.set_amplitudes(t1, t2)
-    ctx.set_autotune(not (args.no_tune or args.counters))   # the warm-up application picks the variants
+    # the warm-up application picks the launch variants (with LRCC_TUNE_CACHE naming the cache of a
+    # timed run, --counters applies that run's choices without timing candidates)
+    ctx.set_autotune(not args.no_tune)
     X1 = torch.from_numpy(x1).to(dev)
     X2 = torch.from_numpy(x2).to(dev)
     sample = (x1[0].copy(), x2[0].copy())
@@ -405,9 +412,9 @@ def main():
     lad_mfma = ctx.ladder_mfma_flops(nrhs, lr.FP32)
     achieved = lad_unique / lad_s / 1e12
     traffic = None
-    if (args.workload == LADDER_TRAFFIC["workload"] and LADDER_TRAFFIC["bytes"] is not None
-            and LADDER_TRAFFIC["ladder_path"] == path and LADDER_TRAFFIC["sources_sha256"] == ladder_sources_sha(path)):
-        traffic = LADDER_TRAFFIC["bytes"]
+    tr = LADDER_TRAFFIC.get(path)
+    if tr and args.workload == tr["workload"] and tr["sources_sha256"] == ladder_sources_sha(path):
+        traffic = tr["bytes"]
     out = {
         "metric": METRIC,
         "value": alg / dt32 / 1e12,

@@ -231,8 +231,9 @@ lrcc_status lrcc_sigma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *exe
 lrcc_status lrcc_ladder_flops(lrcc_ctx *ctx, int nrhs, int precision, double *executed);
 /* The same launches counted in real matrix-core flops (the work of their MFMA
  * instructions): the complex64 pipelined kernel forms the complex products of
- * its integral rebuild from three real matrix-core products (Gauss' method),
- * which count 6 instead of 8; equal to lrcc_ladder_flops otherwise. */
+ * its integral rebuild, and the complex64 GEMM tiles with three real products
+ * (when the autotuner picks them) all their complex products, from three real
+ * matrix-core products (Gauss' method), which count 6 instead of 8. */
 lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *ctx, int nrhs, int precision, double *mfma);
 /* Ladder path of the sigma program for nrhs right-hand sides and this precision
  * (recording it if needed): 1 integrals rebuilt in LDS, 2 stored blocks, 3 blocks

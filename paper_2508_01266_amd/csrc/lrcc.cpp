@@ -109,6 +109,7 @@ struct lrcc_ctx {
     Profiler prof;
     bool use_graphs = false;
     bool pack_ladder = true;                   // antisymmetry-packed forward ladder for large batches
+    bool pack_pairs = true;                    // hole-hole products of the forward sigma on unique pairs
     int ladder_mode = 0;                       // 0: automatic (3 if one class of blocks fits, else 1);
                                                // 1: rebuild integrals in LDS; 2: stored integral blocks;
                                                // 3: blocks of one momentum class at a time, per sigma
@@ -663,6 +664,8 @@ struct SymOp {
     cd alpha = 1.0;
     bool acc = true;
     bool actA = false, actB = false;
+    std::string pack;   // forward product: antisymmetric label pairs run on unique pairs (contract)
+    std::string exact;  // of those, the output pairs written with their true values
 };
 
 struct SigmaGraph {
@@ -685,13 +688,15 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
         return false;
     };
     auto con = [&](const KT &C, const char *cl, const KT &Aa, const char *al, const KT &Bb, const char *bl,
-                   cd alpha, bool acc = true) {
+                   cd alpha, bool acc = true, const char *pack = "", const char *exact = "") {
         SymOp op;
         op.kind = SymOp::CON;
         op.C = C; op.A = Aa; op.B = Bb;
         op.cl = cl; op.al = al; op.bl = bl;
         op.alpha = alpha;
         op.acc = acc;
+        op.pack = pack;
+        op.exact = exact;
         op.actA = is_act(Aa);
         op.actB = is_act(Bb);
         if (op.actA == op.actB) throw LrccError(LRCC_E_ARG, std::string("term not linear in X: ") + cl);
@@ -770,11 +775,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     // antisymmetric in (a, b), which P(ab) turns into Vx_ijmn t_ma t_nb / 4: the t2 parts share
     // one product with (Zmn + 2 Vx), and the t1 t1 part joins the Yx t1 product below
     // (Yx -= Vx t1 / 4), so no product over all (i, j, a, b) is spent on it.
-    con(Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false);
+    // Every operand of these three products is antisymmetric in each of its index pairs, and
+    // Z enters sigma2 only through P(ij)P(ab): the forward products run on unique pairs (ij, mn,
+    // ef, ab), Zmn being defined on the unique (ij, mn) pairs that its one consumer reads.
+    con(Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false, "ijmnef", "im");
     con(Zmn, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 2.0);
     con(Zmn, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -2.0);
-    con(Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16);
-    con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8);
+    con(Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16, true, "ijabmn");
+    con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8, true, "ijabmn");
     con(Vx, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 1.0, false);
     con(Vx, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -1.0);
     // ring terms (P(ij)P(ab))
@@ -909,7 +917,8 @@ Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = tr
     for (const SymOp &op : G.ops) {
         switch (op.kind) {
         case SymOp::CON:
-            contract<T>(*P, op.C, op.cl, op.A, op.al, op.B, op.bl, op.alpha, op.acc);
+            contract<T>(*P, op.C, op.cl, op.A, op.al, op.B, op.bl, op.alpha, op.acc, c->pack_pairs ? op.pack : "",
+                        op.exact);
             break;
         case SymOp::COPY:
             kt_copy<T>(*P, op.C, op.A);
@@ -4209,7 +4218,7 @@ lrcc_status lrcc_ladder_mfma_flops(lrcc_ctx *c, int nrhs, int precision, double 
         if (!mfma || nrhs < 1) throw LrccError(LRCC_E_ARG, "bad argument");
         Program *P = sigma_program(c, precision, nrhs);
         const bool fp64 = precision == LRCC_FP64;
-        *mfma = P->ladder_args ? ladder_mfma_flops(*P->ladder_args, fp64) : (double)P->tag_flops[TAG_LADDER];
+        *mfma = P->ladder_args ? ladder_mfma_flops(*P->ladder_args, fp64) : P->tag_mfma_flops(TAG_LADDER);
     });
 }
 

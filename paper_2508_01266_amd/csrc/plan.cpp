@@ -6,6 +6,7 @@
 // result by output block, and describes the dense block products as one
 // strided batched GEMM whose index groups read the blocks in place.
 #include "plan.hpp"
+#include "elem.hpp"
 
 #include <algorithm>
 #include <memory>
@@ -41,6 +42,16 @@ bool in_arena(const void *p) {
     for (const auto &a : g_arenas)
         if ((const char *)p >= a.first && (const char *)p < a.first + a.second) return true;
     return false;
+}
+
+double Program::tag_mfma_flops(int t) const {
+    double f = 0;
+    for (const auto &kv : gemm_ops) {
+        if (kv.first >= tags.size() || tags[kv.first] != t) continue;
+        const int sh = gemm_shape(*kv.second.args, kv.second.fp64);
+        f += (double)kv.second.flops * ((sh == 3 || sh == 4) && !kv.second.fp64 ? 0.75 : 1.0);
+    }
+    return f;
 }
 
 void *dev_alloc(size_t bytes) {
@@ -458,18 +469,158 @@ void raw_gemm(Program &P, GemmArgs g, const std::vector<i64> &offC, const std::v
     P.flops += P.last_flops;
     auto gp = std::make_shared<GemmArgs>(g);
     P.ops.push_back([gp](hipStream_t s) { return launch_gemm<T>(*gp, s); });
+    P.gemm_ops[P.ops.size() - 1] = Program::GemmOp{gp, sizeof(T) == 8, P.last_flops};
     // candidates: tile shapes, the heuristic one first
     const std::vector<int> cand = gemm_candidates(g, sizeof(T) == 8);
     P.tunables.push_back({P.ops.size() - 1, (int)cand.size(), [gp, cand](int c) { gp->shape = c == 0 ? -1 : cand[c]; }});
 }
 
+// momenta of every label of C's block cb (the fourth from C's conservation rule)
+void job_momenta(const KT &C, const TInfo &tc, const std::string &cl, i64 cb, std::map<char, int> &k) {
+    const int nk = C.nk, off = tc.hasR ? 1 : 0;
+    if (C.nidx() == 2) {
+        k[cl[off]] = (int)cb;
+        k[cl[off + 1]] = (int)cb;
+        return;
+    }
+    const int k0 = (int)(cb / (nk * nk)), k1 = (int)((cb / nk) % nk), k2 = (int)(cb % nk);
+    k[cl[off]] = k0;
+    k[cl[off + 1]] = k1;
+    k[cl[off + 2]] = k2;
+    k[cl[off + 3]] = C.km.sum3(-C.sg[3] * C.sg[0], k0, -C.sg[3] * C.sg[1], k1, -C.sg[3] * C.sg[2], k2);
+}
+
+// contract() over unique antisymmetric pairs: one launch per combination of diagonal /
+// off-diagonal momentum blocks of the packed pairs (their index groups then differ in size)
+template <typename T>
+void contract_packed(Program &P, const KT &C, const std::string &cl, const KT &A, const std::string &al,
+                     const KT &B, const std::string &bl, std::complex<double> alpha, bool accumulate,
+                     const std::string &pack, const std::string &exact, const GemmArgs &g0, const TInfo &ta,
+                     const TInfo &tb, const TInfo &tc,
+                     const std::vector<char> &Ml, const std::vector<char> &Nl, const std::vector<char> &Kl,
+                     const std::vector<char> &sum_k, const std::string &what) {
+    struct Pair {
+        char p, q;
+        int grp;   // 0: M (C and A), 1: N (C and B), 2: K (A and B)
+    };
+    std::vector<Pair> pk;
+    if (pack.size() % 2) throw LrccError(1, "pack needs label pairs: " + what);
+    auto has = [](const std::vector<char> &v, char c) { return std::find(v.begin(), v.end(), c) != v.end(); };
+    for (size_t i = 0; i < pack.size(); i += 2) {
+        const char p = pack[i], q = pack[i + 1];
+        int grp = -1;
+        if (has(Ml, p) && has(Ml, q)) grp = 0;
+        else if (has(Nl, p) && has(Nl, q)) grp = 1;
+        else if (has(Kl, p) && has(Kl, q)) grp = 2;
+        if (grp < 0) throw LrccError(1, std::string("packed pair ") + p + q + " not in one index group: " + what);
+        for (const Pair &o : pk)
+            if (o.grp == grp) throw LrccError(1, "two packed pairs in one index group: " + what);
+        pk.push_back({p, q, grp});
+    }
+    // the triangle form of a group holding a pair: (other label, p, q) with at most one other label
+    auto tri_group = [&](const Pair &pr, const std::vector<char> &labels, const TInfo &x, const TInfo &y, Split &sp,
+                         Strides &sx, Strides &sy, int &total) {
+        std::vector<char> rest;
+        for (char c : labels)
+            if (c != pr.p && c != pr.q) rest.push_back(c);
+        if (rest.size() > 1) throw LrccError(1, "packed pair with more than one other label in its group: " + what);
+        const int n = x.extent[pos(x, pr.p)];
+        if (x.extent[pos(x, pr.q)] != n || n < 2) throw LrccError(1, "packed pair of unequal or short extents: " + what);
+        sp = tri_split(n);
+        const i64 rx = rest.empty() ? 0 : x.stride[pos(x, rest[0])], ry = rest.empty() ? 0 : y.stride[pos(y, rest[0])];
+        sx = Strides{{rx, x.stride[pos(x, pr.p)], x.stride[pos(x, pr.q)]}};
+        sy = Strides{{ry, y.stride[pos(y, pr.p)], y.stride[pos(y, pr.q)]}};
+        total = (rest.empty() ? 1 : x.extent[pos(x, rest[0])]) * (n * (n - 1) / 2);
+    };
+    const int np = (int)pk.size(), nk = C.nk;
+    i64 nsum = 1;
+    for (size_t i = 0; i < sum_k.size(); ++i) nsum *= nk;
+    // jobs and segments per variant (bit i set: pair i on its diagonal momentum blocks)
+    std::vector<std::vector<i64>> offC(1 << np), segA(1 << np), segB(1 << np);
+    std::vector<std::vector<int>> segBeg(1 << np, std::vector<int>{0});
+    for (i64 cb = 0; cb < C.nblocks(); ++cb) {
+        std::map<char, int> k;
+        job_momenta(C, tc, cl, cb, k);
+        int jbits = 0;
+        bool skip = false;
+        for (int i = 0; i < np; ++i) {
+            if (pk[i].grp == 2) continue;
+            const int kp = k.at(pk[i].p), kq = k.at(pk[i].q);
+            if (kp > kq) skip = true;
+            if (kp == kq) jbits |= 1 << i;
+        }
+        if (skip) continue;
+        std::vector<size_t> before(1 << np);
+        for (int m = 0; m < (1 << np); ++m) before[m] = segA[m].size();
+        for (i64 sidx = 0; sidx < nsum; ++sidx) {
+            i64 q = sidx;
+            for (char c : sum_k) { k[c] = (int)(q % nk); q /= nk; }
+            const i64 ba = block_of(ta, k), bb = block_of(tb, k);
+            if (ba < 0 || bb < 0) continue;
+            int bits = jbits;
+            bool sk = false;
+            for (int i = 0; i < np; ++i) {
+                if (pk[i].grp != 2) continue;
+                const int kp = k.at(pk[i].p), kq = k.at(pk[i].q);
+                if (kp > kq) sk = true;
+                if (kp == kq) bits |= 1 << i;
+            }
+            if (sk) continue;
+            segA[bits].push_back(ba * A.inner());
+            segB[bits].push_back(bb * B.inner());
+        }
+        for (int m = 0; m < (1 << np); ++m) {
+            if (segA[m].size() == before[m]) continue;
+            offC[m].push_back(cb * C.inner());
+            segBeg[m].push_back((int)segA[m].size());
+        }
+    }
+    if (!accumulate) {
+        // the packed launches write C in parts: clear it once, then accumulate
+        void *cp = C.p;
+        const i64 n = C.count();
+        P.ops.push_back([cp, n](hipStream_t s) { return zero_fill<T>(cp, n, s); });
+    }
+    for (int m = 0; m < (1 << np); ++m) {
+        if (offC[m].empty()) continue;
+        // a pair over a single index has no p < q: its diagonal blocks contribute nothing
+        bool empty = false;
+        for (int i = 0; i < np; ++i) {
+            const TInfo &x = pk[i].grp == 1 ? tb : ta;
+            if ((m >> i & 1) && x.extent[pos(x, pk[i].p)] < 2) empty = true;
+        }
+        if (empty) continue;
+        GemmArgs g = g0;
+        g.beta = 1;
+        double f = 1;
+        for (const Pair &pr : pk)
+            if (pr.grp == 2 || exact.find(pr.p) == std::string::npos) f *= 2;
+        g.alpha_re = alpha.real() * f;
+        g.alpha_im = alpha.imag() * f;
+        for (int i = 0; i < np; ++i) {
+            if (!(m >> i & 1)) continue;
+            if (pk[i].grp == 0) tri_group(pk[i], Ml, ta, tc, g.sm, g.Am, g.Cm, g.M);
+            else if (pk[i].grp == 1) tri_group(pk[i], Nl, tb, tc, g.sn, g.Bn, g.Cn, g.N);
+            else tri_group(pk[i], Kl, ta, tb, g.sk, g.Ak, g.Bk, g.K);
+        }
+        g.aMfast = (g.Am.s[2] == 1) || (g.Ak.s[2] != 1);
+        g.bNfast = (g.Bn.s[2] == 1) || (g.Bk.s[2] != 1);
+        raw_gemm<T>(P, g, offC[m], segBeg[m], segA[m], segB[m], A.count(), B.count(), C.count());
+        char nm[200];
+        std::snprintf(nm, sizeof nm, "gemm %s packed %s (diagonal mask %d) M=%d N=%d K=%d jobs=%zu segs=%zu",
+                      what.c_str(), pack.c_str(), m, g.M, g.N, g.K, offC[m].size(), segA[m].size());
+        P.name_last(nm);
+    }
+}
+
 template <typename T>
 void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const std::string &al, const KT &B,
-              const std::string &bl, std::complex<double> alpha, bool accumulate) {
+              const std::string &bl, std::complex<double> alpha, bool accumulate, const std::string &pack,
+              const std::string &exact) {
     // the GEMM stores run along its N index: put the output's unit-stride index there
     // (operand order does not change a complex product)
     if (al.find(cl.back()) != std::string::npos && bl.find(cl.back()) == std::string::npos) {
-        contract<T>(P, C, cl, B, bl, A, al, alpha, accumulate);
+        contract<T>(P, C, cl, B, bl, A, al, alpha, accumulate, pack, exact);
         return;
     }
     TInfo tc = info(C, cl), ta = info(A, al), tb = info(B, bl);
@@ -512,6 +663,11 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
     g.alpha_re = alpha.real();
     g.alpha_im = alpha.imag();
     g.beta = accumulate ? 1 : 0;
+    if (!pack.empty()) {
+        contract_packed<T>(P, C, cl, A, al, B, bl, alpha, accumulate, pack, exact, g, ta, tb, tc, Ml, Nl, Kl, sum_k,
+                           what);
+        return;
+    }
 
     const int nk = C.nk;
     std::vector<i64> offC, segA, segB;
@@ -558,9 +714,11 @@ void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const
 }
 
 template void contract<double>(Program &, const KT &, const std::string &, const KT &, const std::string &,
-                               const KT &, const std::string &, std::complex<double>, bool);
+                               const KT &, const std::string &, std::complex<double>, bool, const std::string &,
+                               const std::string &);
 template void contract<float>(Program &, const KT &, const std::string &, const KT &, const std::string &,
-                              const KT &, const std::string &, std::complex<double>, bool);
+                              const KT &, const std::string &, std::complex<double>, bool, const std::string &,
+                              const std::string &);
 template void raw_gemm<double>(Program &, GemmArgs, const std::vector<i64> &, const std::vector<int> &,
                                const std::vector<i64> &, const std::vector<i64> &, i64, i64, i64,
                                const std::vector<float> &);

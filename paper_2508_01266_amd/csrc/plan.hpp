@@ -95,6 +95,16 @@ struct Program {
     }
     hipError_t run(hipStream_t s, Profiler *prof = nullptr);
     hipError_t run_range(hipStream_t s, size_t begin, size_t end);
+    // the recorded GEMM launches (op index -> arguments as tuned, precision, executed flops)
+    struct GemmOp {
+        std::shared_ptr<GemmArgs> args;
+        bool fp64;
+        i64 flops;
+    };
+    std::map<size_t, GemmOp> gemm_ops;
+    // real flops of the matrix-core instructions of the GEMM launches with tag t: 8 per complex
+    // multiply-add formed, 6 for the tiles that form complex products from three real ones
+    double tag_mfma_flops(int t) const;
     // ladder path of a sigma program: 1 integrals rebuilt in LDS, 2 stored blocks, 3 blocks built
     // one momentum class at a time (0: no ladder term)
     int ladder_path = 0;
@@ -113,9 +123,17 @@ struct Program {
 
 // C[cl] (+)= alpha * sum A[al] B[bl]; labels are one character per index, 'R'
 // for the right-hand-side axis (first in a label string when present).
+// pack: label pairs ("pq" per pair, at most one pair per GEMM index group) over which
+// the launches run on unique pairs only: momentum blocks k_p <= k_q, and p < q inside the
+// diagonal blocks k_p = k_q (triangle splits).  A summed pair must be antisymmetric in both
+// operands (factor 2).  An output pair leaves C defined only on those unique pairs (the
+// others are not written; with accumulate false C is zeroed first): with factor 2 for a
+// consumer that antisymmetrises C in the pair, or with its true values when the pair's first
+// label is in `exact`, for a consumer that reads C through the same packing.
 template <typename T>
 void contract(Program &P, const KT &C, const std::string &cl, const KT &A, const std::string &al, const KT &B,
-              const std::string &bl, std::complex<double> alpha, bool accumulate = true);
+              const std::string &bl, std::complex<double> alpha, bool accumulate = true,
+              const std::string &pack = "", const std::string &exact = "");
 
 // Raw strided GEMM with explicit job/segment lists (host vectors are uploaded).
 // sizeA/B/C are the element counts of the operands: every address the GEMM can
