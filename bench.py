@@ -239,61 +239,73 @@ def latency_small(lr, torch, reps=50):
 def uneven_batch(lr, torch, steps):
     """Uneven batch of twelve chains (Nk in {3,5,7,9}, 12 right-hand sides each): complex64
     sigma of every chain with the integrals rebuilt in LDS (ladder mode 1), one after another vs
-    all together with one persistent ladder launch; then one after another in the default mode."""
+    all together with one persistent ladder launch; then one after another in the default mode
+    (each chain's context alone on the device: the class-built blocks of twelve resident chains
+    would not fit beside their work tensors)."""
     import numpy as np
     import synth
     chains = synth.uneven_batch()
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream().cuda_stream
     out = {}
-    for mode in (1, 0):
-        ctxs, X1, X2, Y1, Y2, OM = [], [], [], [], [], []
-        alg = 0.0
-        for i, w in enumerate(chains):
-            rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir, (i,))
-            H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=0.02)
-            t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
-            x1, x2 = synth.random_vectors(12, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
-            c = lr.Context(0)
-            c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
-            c.set_ladder_mode(mode)
-            c.set_amplitudes(t1, t2 * w.nk)
-            ctxs.append(c)
-            X1.append(torch.from_numpy(x1).to(dev)); X2.append(torch.from_numpy(x2 * w.nk).to(dev))
-            Y1.append(torch.empty_like(X1[-1])); Y2.append(torch.empty_like(X2[-1]))
-            om = np.array([f for _ in range(3) for f in w.omegas])
-            OM.append(torch.from_numpy(om).to(dev))
-            alg += 12 * sigma_alg_flops(w.nk, w.nocc, w.nvir)
-            if mode == 1:
-                log(f"chain {i}: Nk={w.nk} nocc={w.nocc} nvir={w.nvir} Naux={w.naux}")
-        g = lr.Group(ctxs)
 
-        def seq():
-            for i, c in enumerate(ctxs):
-                c.apply_sigma_dev(X1[i], X2[i], Y1[i], Y2[i], OM[i], lr.FP32, st)
+    def make(i, w, mode):
+        rng = synth.rng_for(w.cfg_id, w.nk, w.nocc, w.nvir, (i,))
+        H = synth.hamiltonian(w.nk, w.nocc, w.nvir, w.naux, rng, band_shift=w.band_shift, chol_sigma=0.02)
+        t1, t2 = synth.random_amplitudes(w.nk, w.nocc, w.nvir, rng, 0.02, 0.02)
+        x1, x2 = synth.random_vectors(12, w.nk, w.nocc, w.nvir, rng, 0.1, 0.1)
+        c = lr.Context(0)
+        c.set_hamiltonian(w.nocc, H['fock'], H['chol'], H['dip'])
+        c.set_ladder_mode(mode)
+        c.set_amplitudes(t1, t2 * w.nk)
+        X1, X2 = torch.from_numpy(x1).to(dev), torch.from_numpy(x2 * w.nk).to(dev)
+        om = np.array([f for _ in range(3) for f in w.omegas])
+        return c, X1, X2, torch.empty_like(X1), torch.empty_like(X2), torch.from_numpy(om).to(dev)
 
-        def grp():
-            g.apply_sigma_dev(X1, X2, Y1, Y2, OM, lr.FP32, st)
-
-        legs = (("one_after_another", seq), ("one_persistent_ladder", grp)) if mode == 1 else \
-            (("one_after_another_default_mode", seq),)
-        for name, fn in legs:
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
             fn()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                fn()
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / steps
-            out[name] = {"ms_per_step": dt * 1e3, "tflops_algorithmic": alg / dt / 1e12}
-            log(f"uneven batch, {name}: {dt * 1e3:.1f} ms")
-        if mode == 0:
-            out["default_mode_ladder_paths"] = [c.ladder_path(12, lr.FP32) for c in ctxs]
-        g.close()
-        for c in ctxs:
-            c.close()
-        del X1, X2, Y1, Y2, OM
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    alg = sum(12 * sigma_alg_flops(w.nk, w.nocc, w.nvir) for w in chains)
+    ctxs, X1, X2, Y1, Y2, OM = [], [], [], [], [], []
+    for i, w in enumerate(chains):
+        c, x1, x2, y1, y2, om = make(i, w, 1)
+        ctxs.append(c); X1.append(x1); X2.append(x2); Y1.append(y1); Y2.append(y2); OM.append(om)
+        log(f"chain {i}: Nk={w.nk} nocc={w.nocc} nvir={w.nvir} Naux={w.naux}")
+    g = lr.Group(ctxs)
+
+    def seq():
+        for i, c in enumerate(ctxs):
+            c.apply_sigma_dev(X1[i], X2[i], Y1[i], Y2[i], OM[i], lr.FP32, st)
+
+    def grp():
+        g.apply_sigma_dev(X1, X2, Y1, Y2, OM, lr.FP32, st)
+
+    for name, fn in (("one_after_another", seq), ("one_persistent_ladder", grp)):
+        dt = timed(fn)
+        out[name] = {"ms_per_step": dt * 1e3, "tflops_algorithmic": alg / dt / 1e12}
+        log(f"uneven batch, {name}: {dt * 1e3:.1f} ms")
+    g.close()
+    for c in ctxs:
+        c.close()
+    del X1, X2, Y1, Y2, OM
+    torch.cuda.empty_cache()
+    total, paths = 0.0, []
+    for i, w in enumerate(chains):
+        c, x1, x2, y1, y2, om = make(i, w, 0)
+        total += timed(lambda: c.apply_sigma_dev(x1, x2, y1, y2, om, lr.FP32, st))
+        paths.append(c.ladder_path(12, lr.FP32))
+        c.close()
+        del x1, x2, y1, y2, om
         torch.cuda.empty_cache()
+    out["one_after_another_default_mode"] = {"ms_per_step": total * 1e3, "tflops_algorithmic": alg / total / 1e12,
+                                             "ladder_paths": paths}
+    log(f"uneven batch, one after another in the default mode: {total * 1e3:.1f} ms")
     out["chains"] = [[w.nk, w.nocc, w.nvir, w.naux] for w in chains]
     out["nrhs_per_chain"] = 12
     out["speedup"] = out["one_after_another"]["ms_per_step"] / out["one_persistent_ladder"]["ms_per_step"]

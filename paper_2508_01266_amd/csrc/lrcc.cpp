@@ -330,13 +330,13 @@ static i64 block_slot(const lrcc_ctx *c, int cls0, int ka, int kb, int ke) {
 static bool in_classes(int k, int cls0, int ncls) { return cls0 < 0 || (k >= cls0 && k < cls0 + ncls); }
 
 // Momentum classes per batch of the class-built ladder (mode 3): as many as fit in an eighth of
-// the free device memory, at most 4 GiB (one class at least).
+// the free device memory, at most 2 GiB (one class at least; every sigma program holds its own).
 static int class_batch(lrcc_ctx *c, size_t elem_bytes) {
     const size_t v2 = (size_t)c->nv * c->nv, per = (size_t)c->ncls_slots * v2 * v2 * elem_bytes;
     size_t fr = 0, tot = 0;
     if (g_dry_run) return std::min(c->nk, 2);      // plan checks: several batches, the last ragged
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 1;
-    const size_t budget = std::min(fr / 8, (size_t)4 << 30);
+    const size_t budget = std::min(fr / 8, (size_t)2 << 30);
     return (int)std::max<size_t>(1, std::min<size_t>(c->nk, budget / std::max<size_t>(per, 1)));
 }
 
@@ -666,6 +666,7 @@ struct SymOp {
     bool actA = false, actB = false;
     std::string pack;   // forward product: antisymmetric label pairs run on unique pairs (contract)
     std::string exact;  // of those, the output pairs written with their true values
+    std::string tpack;  // the same for the transposed product of the active operand
 };
 
 struct SigmaGraph {
@@ -688,7 +689,8 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
         return false;
     };
     auto con = [&](const KT &C, const char *cl, const KT &Aa, const char *al, const KT &Bb, const char *bl,
-                   cd alpha, bool acc = true, const char *pack = "", const char *exact = "") {
+                   cd alpha, bool acc = true, const char *pack = "", const char *exact = "",
+                   const char *tpack = "") {
         SymOp op;
         op.kind = SymOp::CON;
         op.C = C; op.A = Aa; op.B = Bb;
@@ -697,6 +699,7 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
         op.acc = acc;
         op.pack = pack;
         op.exact = exact;
+        op.tpack = tpack;
         op.actA = is_act(Aa);
         op.actB = is_act(Bb);
         if (op.actA == op.actB) throw LrccError(LRCC_E_ARG, std::string("term not linear in X: ") + cl);
@@ -778,11 +781,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     // Every operand of these three products is antisymmetric in each of its index pairs, and
     // Z enters sigma2 only through P(ij)P(ab): the forward products run on unique pairs (ij, mn,
     // ef, ab), Zmn being defined on the unique (ij, mn) pairs that its one consumer reads.
-    con(Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false, "ijmnef", "im");
+    // Transposed: dtau_bar is read by the transposed tau step alone, which antisymmetrises its rows
+    // (ij); Z_bar is antisymmetric in both pairs; Zmn_bar is also read in full by the transposes of
+    // the x1 terms, so it stays complete.
+    con(Zmn, "Rijmn", dtau, "Rijef", S.g_oovv, "mnef", 1.0, false, "ijmnef", "im", "ijmn");
     con(Zmn, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 2.0);
     con(Zmn, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -2.0);
-    con(Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16, true, "ijabmn");
-    con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8, true, "ijabmn");
+    con(Z, "Rijab", Zmn, "Rijmn", t2, "mnab", 1.0 / 16, true, "ijabmn", "", "ab");
+    con(Z, "Rijab", S.Wp, "mnij", dtau, "Rmnab", 1.0 / 8, true, "ijabmn", "", "mnij");
     con(Vx, "Rijmn", x1, "Rje", S.g_ooov, "mnie", 1.0, false);
     con(Vx, "Rjimn", x1, "Rje", S.g_ooov, "mnie", -1.0);
     // ring terms (P(ij)P(ab))
@@ -1028,10 +1034,12 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
     for (auto it = G.ops.rbegin(); it != G.ops.rend(); ++it) {
         const SymOp &op = *it;
         switch (op.kind) {
-        case SymOp::CON:
-            if (op.actA) contract<T>(*P, op.A, op.al, op.C, op.cl, op.B, op.bl, op.alpha, true);
-            if (op.actB) contract<T>(*P, op.B, op.bl, op.A, op.al, op.C, op.cl, op.alpha, true);
+        case SymOp::CON: {
+            const std::string tp = c->pack_pairs ? op.tpack : "";
+            if (op.actA) contract<T>(*P, op.A, op.al, op.C, op.cl, op.B, op.bl, op.alpha, true, tp);
+            if (op.actB) contract<T>(*P, op.B, op.bl, op.A, op.al, op.C, op.cl, op.alpha, true, tp);
             break;
+        }
         case SymOp::COPY: {
             void *a = op.A.p, *cc = op.C.p;
             i64 n = op.A.count();
@@ -1103,10 +1111,10 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
 // file (the path in LRCC_TUNE_CACHE); the key is nk,o,v,naux,nrhs,precision,direction,ladder path.
 std::string tune_key(lrcc_ctx *c, int prec, int R, bool adj, int variant, int path) {
     char b[128];
-    // "v8": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
+    // "v9": candidate semantics (GEMM: heuristic tile shape first, up to three, four in complex64;
     // ladder: four kernel/order variants); the ladder path (1 rebuilt in LDS, 2 stored, 3 built by
     // momentum class) changes the program's launches, so it is part of the key
-    std::snprintf(b, sizeof b, "v8,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
+    std::snprintf(b, sizeof b, "v9,%d,%d,%d,%d,%d,%s,%s%d,ladder%d", c->nk, c->no, c->nv, c->naux, R,
                   prec == LRCC_FP64 ? "f64" : "f32", adj ? "adjoint" : "forward", variant, path);
     if (!c->km.chain()) return std::string(b) + ",mesh" + std::to_string(c->km.n0) + "x" + std::to_string(c->km.n1) +
                                "x" + std::to_string(c->km.n2);

@@ -49,7 +49,8 @@ double Program::tag_mfma_flops(int t) const {
     for (const auto &kv : gemm_ops) {
         if (kv.first >= tags.size() || tags[kv.first] != t) continue;
         const int sh = gemm_shape(*kv.second.args, kv.second.fp64);
-        f += (double)kv.second.flops * ((sh == 3 || sh == 4) && !kv.second.fp64 ? 0.75 : 1.0);
+        const bool g3 = !kv.second.fp64 && (sh == 3 || sh == 4);
+        f += (double)kv.second.flops * (g3 ? 0.75 : 1.0);
     }
     return f;
 }

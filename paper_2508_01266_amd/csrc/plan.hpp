@@ -64,7 +64,7 @@ struct Profiler {
 // variant (candidate 0 or 1).
 struct Tunable {
     size_t op;
-    int ncand;                           // number of valid candidates (1 or 2)
+    int ncand;                           // number of valid candidates
     std::function<void(int)> set;
 };
 

@@ -113,8 +113,9 @@ def test_sigma_adjoint_fp64_matches_oracle_and_dot_identity(nk, o, v, naux, nrhs
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
 def test_every_launch_variant_matches_oracle(tmp_path, monkeypatch, prec_name):
     """Every launch variant the autotuner can pick (GEMM tile shapes including the complex64 tiles
-    with three real products, ladder kernels), forced for every op through the tuning cache,
-    gives the oracle's forward and transpose products."""
+    with three real products; the ladder kernels of the in-LDS
+    path), forced for every op through the tuning cache, gives the oracle's forward and transpose
+    products, in the default ladder path and with the integrals rebuilt in LDS."""
     import synth
     import paper_2508_01266_amd as lr
     from tests.sigma_cases import oracle_sigma_adjoint
@@ -129,25 +130,27 @@ def test_every_launch_variant_matches_oracle(tmp_path, monkeypatch, prec_name):
     adj1, adj2 = oracle_sigma_adjoint(case, z1, z2)
     prec = lr.FP64 if prec_name == "fp64" else lr.FP32
     tol = 1e-11 if prec_name == "fp64" else FP32_REL
-    c = _ctx(case)
-    c.set_autotune(True)
-    c.apply_sigma(case['x1'], case['x2'], case['omega'], prec)
-    c.apply_sigma_adjoint(z1, z2, case['omega'], prec)
-    c.close()
-    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
-    assert any("forward" in ln[0] for ln in lines) and any("adjoint" in ln[0] for ln in lines)
-    for cand in range(4):
-        # candidate index `cand` for every tunable launch (clamped to each op's number of variants)
-        cache.write_text("".join(" ".join([ln[0]] + [str(cand)] * (len(ln) - 1)) + "\n" for ln in lines))
-        c = _ctx(case)
+    for mode in (0, 1):
+        cache.write_text("")
+        c = _ctx(case, mode)
         c.set_autotune(True)
-        y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], prec)
-        a1, a2 = c.apply_sigma_adjoint(z1, z2, case['omega'], prec)
+        c.apply_sigma(case['x1'], case['x2'], case['omega'], prec)
+        c.apply_sigma_adjoint(z1, z2, case['omega'], prec)
         c.close()
-        e = (_rel(y1, ref1), _rel(y2, ref2), _rel(a1, adj1), _rel(a2, adj2))
-        print(f"{prec_name} variant {cand} for every op: rel err forward {e[0]:.1e} {e[1]:.1e} "
-              f"transpose {e[2]:.1e} {e[3]:.1e}", flush=True)
-        assert max(e) < tol
+        lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
+        assert any("forward" in ln[0] for ln in lines) and any("adjoint" in ln[0] for ln in lines)
+        for cand in range(4):
+            # candidate index `cand` for every tunable launch (clamped to each op's number of variants)
+            cache.write_text("".join(" ".join([ln[0]] + [str(cand)] * (len(ln) - 1)) + "\n" for ln in lines))
+            c = _ctx(case, mode)
+            c.set_autotune(True)
+            y1, y2 = c.apply_sigma(case['x1'], case['x2'], case['omega'], prec)
+            a1, a2 = c.apply_sigma_adjoint(z1, z2, case['omega'], prec)
+            c.close()
+            e = (_rel(y1, ref1), _rel(y2, ref2), _rel(a1, adj1), _rel(a2, adj2))
+            print(f"{prec_name} ladder mode {mode}, variant {cand} for every op: rel err forward {e[0]:.1e} "
+                  f"{e[1]:.1e} transpose {e[2]:.1e} {e[3]:.1e}", flush=True)
+            assert max(e) < tol
 
 
 def test_graph_replay_matches_eager():
