@@ -30,9 +30,9 @@ METRIC = "sigma-vector TFLOP/s + s to converged α(ω), mixed-batched vs FP64, 1
 # 2 GiB copy (fetch x2.0, write x1.0).  Valid only for the ladder path and kernel sources it was
 # measured on.
 LADDER_TRAFFIC = {  # ladder path -> measured HBM bytes per application of the complex64 sigma
-    3: {"workload": "c3", "sources_sha256": "1a790315750aff30f3fcf5de834870d87ba46255ef17594a0960ee8690ec81cc",
+    3: {"workload": "c3", "sources_sha256": "27b805843d1d6dd5d287c163d32cdadf2b8a817b279502c7d141fb47a5640af4",
         "bytes": 40.6e9},
-    1: {"workload": "c3", "sources_sha256": "6c4c3d9cd1892f1c96e47795d021fce848b106ebe75fd82d99a5eba1c67645eb",
+    1: {"workload": "c3", "sources_sha256": "984e5f970a1f2d74bea898efacb6b789c5a66e58c32d231fc99c73581dd474cb",
         "bytes": 188.6e9},
 }
 

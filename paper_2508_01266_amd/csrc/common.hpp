@@ -160,7 +160,8 @@ struct GemmArgs {
     void *part;
     const float *jscale; // per-job multiplier of alpha (full job list), or null
     int kind;            // 0 generic, 1 ladder over integral blocks (a separate kernel symbol for
-                         // profiling; the launcher takes instance 2 when sk is a triangle split)
+                         // profiling); the launcher takes instances 2 (generic) and 3 (ladder) when
+                         // sk is a triangle split
 };
 
 template <typename T>

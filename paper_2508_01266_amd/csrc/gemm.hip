@@ -112,13 +112,13 @@ __global__ void __launch_bounds__(NT) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int gk = k0 + ak[q];
-            if (aok[q] && gk < g.K) va[q] = As[arow[q] + split_off32<KIND == 2>(gk, g.sk, ak0, ak1, ak2)];
+            if (aok[q] && gk < g.K) va[q] = As[arow[q] + split_off32<(KIND >= 2)>(gk, g.sk, ak0, ak1, ak2)];
             else { va[q].x = 0; va[q].y = 0; }
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
             const int gk = k0 + bk[q];
-            if (bok[q] && gk < g.K) vb[q] = Bs[bcol[q] + split_off32<KIND == 2>(gk, g.sk, bk0, bk1, bk2)];
+            if (bok[q] && gk < g.K) vb[q] = Bs[bcol[q] + split_off32<(KIND >= 2)>(gk, g.sk, bk0, bk1, bk2)];
             else { vb[q].x = 0; vb[q].y = 0; }
         }
     };
@@ -249,8 +249,10 @@ hipError_t launch_shape(const GemmArgs &g, hipStream_t s) {
         c.segBeg = g.segBeg + j0;
         c.job0 = j0;
         dim3 grid(tilesM * tilesN, c.njobs, g.ksplit);
-        // KIND 2: a ladder product whose reduction index is a triangle split
-        if (g.sk.tri) hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 2, G3>), grid, dim3(NT), 0, s, c);
+        // KIND 2 (generic) and 3 (ladder): the reduction index is a triangle split
+        if (g.sk.tri && g.kind == 1)
+            hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 3, G3>), grid, dim3(NT), 0, s, c);
+        else if (g.sk.tri) hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 2, G3>), grid, dim3(NT), 0, s, c);
         else if (g.kind == 1) hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 1, G3>), grid, dim3(NT), 0, s, c);
         else hipLaunchKernelGGL((gemm_kernel<T, TM, TN, WTM, WTN, 0, G3>), grid, dim3(NT), 0, s, c);
         hipError_t e = hipGetLastError();
