@@ -633,9 +633,30 @@ void upload_amplitudes(lrcc_ctx *c, const double *t1h, const double *t2h) {
     HIPCHK(hipMemcpy(S.t2.p, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
+bool tune_lookup(const std::string &key, std::vector<int> &choice);
+void tune_store(const std::string &key, const std::vector<int> &choice);
+
+// With autotuning on, the first run of an amplitude-dependent program picks its GEMM tiles (the
+// programs recompute every block from the amplitudes, so repeated runs leave the same values).
+static void tune_pre(lrcc_ctx *c, Program *p, const char *which, hipStream_t st) {
+    if (!c->autotune || p->tuned || p->tunables.empty() || g_dry_run) return;
+    char b[160];
+    std::snprintf(b, sizeof b, "v9,%s,%d,%d,%d,%d,ladder%d,mesh%dx%dx%d", which, c->nk, c->no, c->nv, c->naux,
+                  c->ladder_mode, c->km.n0, c->km.n1, c->km.n2);
+    std::vector<int> choice;
+    if (tune_lookup(b, choice)) {
+        p->apply(choice);
+        return;
+    }
+    HIPCHK(p->autotune(st, choice));
+    tune_store(b, choice);
+}
+
 // Recompute every amplitude-dependent block from the device amplitudes.
 void run_precompute(lrcc_ctx *c, bool fp32, hipStream_t st = nullptr) {
     static const bool timed = std::getenv("LRCC_PRE_TIMES") != nullptr;   // per-op timing report
+    tune_pre(c, c->pre64.get(), "pre64", st);
+    if (fp32) tune_pre(c, c->pre32.get(), "pre32", st);
     if (timed) {
         const bool was = c->prof.on;
         c->prof.on = true;
