@@ -751,14 +751,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     con(dFae, "Rae", x1, "Rma", S.fov, "me", -0.5, false);
     if (full) {
         con(dFae, "Rae", x1, "Rmf", S.g_ovvv, "mafe", 1.0);
-        con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.5);
+        con(dFae, "Rae", dtau, "Rmnaf", S.g_oovv, "mnef", -0.5, true, "mn", "", "mn");
         con(dFae, "Rae", x1, "Rma", S.Fg, "me", 0.5);
         con(dFae, "Rae", t1, "ma", dFme, "Rme", 0.5);
     }
     con(dFmi, "Rmi", x1, "Rie", S.fov, "me", 0.5, false);
     if (full) {
         con(dFmi, "Rmi", x1, "Rne", S.g_ooov, "mnie", 1.0);
-        con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.5);
+        con(dFmi, "Rmi", dtau, "Rinef", S.g_oovv, "mnef", 0.5, true, "ef");
         con(dFmi, "Rmi", x1, "Rie", S.Fg, "me", -0.5);
         con(dFmi, "Rmi", t1, "ie", dFme, "Rme", -0.5);
     }
@@ -771,8 +771,8 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     if (full) {
         con(s1, "Ria", t2, "imae", dFme, "Rme", 1.0);
         con(s1, "Ria", x1, "Rnf", S.g_ovov, "naif", -1.0);
-        con(s1, "Ria", x2, "Rimef", S.g_ovvv, "maef", -0.5);
-        con(s1, "Ria", x2, "Rmnae", S.g_ooov, "nmie", 0.5);
+        con(s1, "Ria", x2, "Rimef", S.g_ovvv, "maef", -0.5, true, "ef", "", "ef");
+        con(s1, "Ria", x2, "Rmnae", S.g_ooov, "nmie", 0.5, true, "mn", "", "mn");
     }
     // dressed one-body derivatives entering the doubles
     copy(dFbe, dFae);
@@ -782,11 +782,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     con(dFmj, "Rmj", x1, "Rje", S.Fme, "me", 0.5);
     if (full) con(dFmj, "Rmj", t1, "je", dFme, "Rme", 0.5);
     // doubles (operator part of Eq. tx2): Z collects every term, sigma2 = P(ij)P(ab) Z.
-    // Terms antisymmetric in both pairs enter with 1/4, in one pair with 1/2.
+    // Terms antisymmetric in both pairs enter with 1/4, in one pair with 1/2.  Products whose
+    // operands are antisymmetric in a summed pair, or whose output pair reaches sigma2 (or the
+    // transposed output) only antisymmetrised, run on unique pairs (pack / transposed pack: see
+    // contract); dtau_bar's (e, f) pair is read unsymmetrised and is never packed.
     con(Z, "Rijab", x2, "Rijae", S.Fbe, "be", 0.5, false);
     con(Z, "Rijab", t2, "ijae", dFbe, "Rbe", 0.5);
-    con(Z, "Rijab", x2, "Rimab", S.Fmj, "mj", -0.5);
-    con(Z, "Rijab", t2, "imab", dFmj, "Rmj", -0.5);
+    con(Z, "Rijab", x2, "Rimab", S.Fmj, "mj", -0.5, true, "ab", "", "ab");
+    con(Z, "Rijab", t2, "imab", dFmj, "Rmj", -0.5, true, "ab", "", "ab");
     if (!full) return G;  // one-body (perturbation) operator: no two-electron terms
     {
         SymOp op;

@@ -518,20 +518,26 @@ void contract_packed(Program &P, const KT &C, const std::string &cl, const KT &A
             if (o.grp == grp) throw LrccError(1, "two packed pairs in one index group: " + what);
         pk.push_back({p, q, grp});
     }
-    // the triangle form of a group holding a pair: (other label, p, q) with at most one other label
+    // the triangle form of a group holding a pair: (others, p, q), the other labels forming one run
+    // adjacent (same order) in both tensors, so that they index as one level
     auto tri_group = [&](const Pair &pr, const std::vector<char> &labels, const TInfo &x, const TInfo &y, Split &sp,
                          Strides &sx, Strides &sy, int &total) {
         std::vector<char> rest;
         for (char c : labels)
             if (c != pr.p && c != pr.q) rest.push_back(c);
-        if (rest.size() > 1) throw LrccError(1, "packed pair with more than one other label in its group: " + what);
+        std::sort(rest.begin(), rest.end(), [&](char a, char b) { return pos(x, a) < pos(x, b); });
+        for (size_t i = 1; i < rest.size(); ++i)
+            if (pos(x, rest[i]) != pos(x, rest[i - 1]) + 1 || pos(y, rest[i]) != pos(y, rest[i - 1]) + 1)
+                throw LrccError(1, "packed pair whose other labels are not one adjacent run: " + what);
         const int n = x.extent[pos(x, pr.p)];
         if (x.extent[pos(x, pr.q)] != n || n < 2) throw LrccError(1, "packed pair of unequal or short extents: " + what);
         sp = tri_split(n);
-        const i64 rx = rest.empty() ? 0 : x.stride[pos(x, rest[0])], ry = rest.empty() ? 0 : y.stride[pos(y, rest[0])];
+        int ext = 1;
+        for (char c : rest) ext *= x.extent[pos(x, c)];
+        const i64 rx = rest.empty() ? 0 : x.stride[pos(x, rest.back())], ry = rest.empty() ? 0 : y.stride[pos(y, rest.back())];
         sx = Strides{{rx, x.stride[pos(x, pr.p)], x.stride[pos(x, pr.q)]}};
         sy = Strides{{ry, y.stride[pos(y, pr.p)], y.stride[pos(y, pr.q)]}};
-        total = (rest.empty() ? 1 : x.extent[pos(x, rest[0])]) * (n * (n - 1) / 2);
+        total = ext * (n * (n - 1) / 2);
     };
     const int np = (int)pk.size(), nk = C.nk;
     i64 nsum = 1;
