@@ -1325,7 +1325,7 @@ static bool verbose() {
 // Device workspace of the batched GMRES: a contiguous Krylov basis (vector i of right-hand side r
 // at (Vs + (i R + r) n1, Vd + (i R + r) n2)), the Hessenberg/Givens state of every right-hand
 // side, the Gram-Schmidt coefficients and a pinned status buffer.  With graphs on, every Arnoldi
-// step j is captured once (preconditioner, sigma, two Gram-Schmidt passes, norm, rotation,
+// step j is captured once (preconditioner, sigma, two Gram-Schmidt passes (one in complex64), norm, rotation,
 // normalisation, status copy) and replayed for later cycles and refinement steps of the same solve.
 struct GmresWork {
     int R = 0, m = 0;
@@ -1428,7 +1428,10 @@ hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double 
     c->io_x1 = z.s; c->io_x2 = z.d; c->io_y1 = w.s; c->io_y2 = w.d; c->io_omega = S.omega;
     e = eager_sigma ? run_sigma(c, p, st) : p->run(st);
     if (e != hipSuccess) return e;
-    for (int pass = 0; pass < 2; ++pass) {
+    // classical Gram-Schmidt with one re-orthogonalisation; the complex64 inner solves of the
+    // refinement (to a relative 1e-4 or so, corrected by the complex128 residual) take one pass
+    const int passes = precision == LRCC_FP32 ? 1 : 2;
+    for (int pass = 0; pass < passes; ++pass) {
         void *h = pass == 0 ? W.h1 : W.h2;
         e = multidot(W.Vs, W.Vd, w.s, w.d, R, n1, n2, j + 1, W.part, h, W.m + 1, st);
         if (e != hipSuccess) return e;
@@ -1437,7 +1440,8 @@ hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double 
     }
     e = selfdot(w.s, w.d, R, n1, n2, W.part, W.hn2, st);
     if (e != hipSuccess) return e;
-    e = gmres_step(W.g, j, W.h1, W.h2, W.hn2, tol, precision == LRCC_FP64 ? kSingularPivot : 0.0, st);
+    e = gmres_step(W.g, j, W.h1, passes == 2 ? W.h2 : nullptr, W.hn2, tol, precision == LRCC_FP64 ? kSingularPivot : 0.0,
+                   st);
     if (e != hipSuccess) return e;
     e = batched_axpby(vn.s, w.s, W.g.scal, 0.0, R, n1, st);
     if (e != hipSuccess) return e;

@@ -334,7 +334,7 @@ __global__ void k_gmres_step(GmresState g, int j, const double2 *h1, const doubl
         return;
     }
     for (int i = 0; i <= j; ++i) {
-        const double2 a = h1[(i64)r * ld + i], b = h2[(i64)r * ld + i];
+        const double2 a = h1[(i64)r * ld + i], b = h2 ? h2[(i64)r * ld + i] : make_double2(0, 0);
         H[i * m + j] = make_double2(a.x + b.x, a.y + b.y);
     }
     const double n2 = hn2[r].x;

@@ -40,6 +40,7 @@ hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *
 hipError_t multiaxpy(void *ws, void *wd, const void *Vs, const void *Vd, const void *C, int cstride, double sign,
                      const int *mask, double beta, int R, i64 n1, i64 n2, int k, hipStream_t s);
 hipError_t gmres_init(const GmresState &g, const void *beta2, double tol, hipStream_t s);
+// h2: the second Gram-Schmidt pass's coefficients, or null after a single pass
 hipError_t gmres_step(const GmresState &g, int j, const void *h1, const void *h2, const void *hn2, double tol,
                       double sing_pivot, hipStream_t s);
 hipError_t gmres_solve(const GmresState &g, void *y, hipStream_t s);
