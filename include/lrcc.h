@@ -298,7 +298,11 @@ void lrcc_solve_opts_default(lrcc_solve_opts *opts);
 /* Solve the perturbed-amplitude equations (Eqs. tx1, tx2 in operator form,
  * the Jacobi/DIIS iteration of Sec. II.C replaced by preconditioned GMRES with
  * the same orbital-energy denominators of Eq. D): (A - omega_r) x_r = b_r for
- * nrhs right-hand sides at once, each with its own frequency.  x holds the
+ * nrhs right-hand sides at once, each with its own frequency.  The doubles of
+ * b and x are antisymmetric under (ki,i)<->(kj,j) and (ka,a)<->(kb,b), as every
+ * doubles amplitude vector (the Krylov basis keeps one k block per orbit of
+ * those swaps; a part of b2 outside that subspace is not in the operator's
+ * range and is not solved for).  x holds the
  * initial guess on entry (zeros for none) and the solution on exit.  opts may
  * be NULL (defaults).  Returns LRCC_E_NOCONV (x and report still written) if
  * the tolerance is not reached or a residual norm is not finite (NaN/Inf in b

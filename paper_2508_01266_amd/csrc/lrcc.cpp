@@ -1280,10 +1280,11 @@ struct SolveCtx {
         HIPCHK(hipMemsetAsync(y.s, 0, R * n1 * 16, st));
         HIPCHK(hipMemsetAsync(y.d, 0, R * n2 * 16, st));
     }
-    void prec(const Vecs &out, const Vecs &in) {
+    // out = M^-1 in for a Krylov-space vector in with packed doubles
+    void unpack_prec(const Vecs &out, const Vecs &in, const PackMap &pm) {
         const State<double> &T = c->s64;
-        HIPCHK(precond(out.s, out.d, in.s, in.d, (const double *)T.d_o1, (const double *)T.d_v1,
-                       (const double *)T.d_o2, (const double *)T.d_v2, omega, c->km, R, c->no, c->nv, st));
+        HIPCHK(unpack_precond(out.s, out.d, in.s, in.d, pm, (const double *)T.d_o1, (const double *)T.d_v1,
+                              (const double *)T.d_o2, (const double *)T.d_v2, omega, c->km, R, c->no, c->nv, st));
     }
     // y = (A - omega) x
     void op(const Vecs &y, const Vecs &x, int precision) {
@@ -1322,14 +1323,18 @@ static bool verbose() {
     return v != 0;
 }
 
-// Device workspace of the batched GMRES: a contiguous Krylov basis (vector i of right-hand side r
-// at (Vs + (i R + r) n1, Vd + (i R + r) n2)), the Hessenberg/Givens state of every right-hand
+// Device workspace of the batched GMRES: a contiguous Krylov basis with packed doubles (one k
+// block per antisymmetry orbit, PackMap; vector i of right-hand side r at (Vs + (i R + r) n1,
+// Vd + (i R + r) n2) with n2 the packed length), the Hessenberg/Givens state of every right-hand
 // side, the Gram-Schmidt coefficients and a pinned status buffer.  With graphs on, every Arnoldi
-// step j is captured once (preconditioner, sigma, two Gram-Schmidt passes (one in complex64), norm, rotation,
-// normalisation, status copy) and replayed for later cycles and refinement steps of the same solve.
+// step j is captured once (unpacking preconditioner, sigma, packing, two Gram-Schmidt passes (one
+// in complex64), norm, rotation, normalisation, status copy) and replayed for later cycles and
+// refinement steps of the same solve.
 struct GmresWork {
     int R = 0, m = 0;
-    i64 n1 = 0, n2 = 0;
+    i64 n1 = 0, n2 = 0;   // singles and packed doubles per right-hand side
+    i64 blk = 0;          // elements of one doubles k block (o o v v)
+    PackMap pm;
     void *Vs = nullptr, *Vd = nullptr;
     GmresState g{};
     void *h1 = nullptr, *h2 = nullptr, *hn2 = nullptr, *beta2 = nullptr, *y = nullptr, *part = nullptr;
@@ -1351,9 +1356,27 @@ struct GmresWork {
     }
 };
 
-void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, i64 n2, hipStream_t st) {
+// Packed length of the doubles of one right-hand side (PackMap) for the context's k mesh.
+i64 packed_doubles(const lrcc_ctx *c) {
+    std::vector<int> canon, map;
+    std::vector<double> scale;
+    return (i64)pack_tables(c->km, canon, map, scale) * c->no * c->no * c->nv * c->nv;
+}
+
+void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, hipStream_t st) {
     DevMem &M = c->solmem;
+    std::vector<int> canon, map;
+    std::vector<double> scale;
+    W.pm.np = pack_tables(c->km, canon, map, scale);
+    W.pm.nfull = (int)map.size();
+    W.blk = (i64)c->no * c->no * c->nv * c->nv;
+    const i64 n2 = (i64)W.pm.np * W.blk;
     W.R = R; W.m = m; W.n1 = n1; W.n2 = n2;
+    int *canon_d = (int *)M.get(canon.size() * sizeof(int)), *map_d = (int *)M.get(map.size() * sizeof(int));
+    double *scale_d = (double *)M.get(scale.size() * sizeof(double));
+    W.pm.canon = canon_d;
+    W.pm.map = map_d;
+    W.pm.scale = scale_d;
     W.Vs = M.get((size_t)(m + 1) * R * n1 * 16);
     W.Vd = M.get((size_t)(m + 1) * R * n2 * 16);
     W.g.R = R;
@@ -1378,6 +1401,9 @@ void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, i64 n2, hipStr
     W.minus = M.get((size_t)R * 16);
     W.stat_d = M.get((size_t)R * 3 * 8);
     if (g_dry_run) return;
+    HIPCHK(hipMemcpyAsync(canon_d, canon.data(), canon.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(map_d, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(scale_d, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipHostMalloc((void **)&W.stat_h, (size_t)R * 3 * 8, hipHostMallocDefault));
     std::vector<cd> one(R, cd(1.0, 0.0)), mone(R, cd(-1.0, 0.0));
     HIPCHK(hipMemcpyAsync(W.ones, one.data(), (size_t)R * 16, hipMemcpyHostToDevice, st));
@@ -1408,10 +1434,11 @@ GmresStatus gmres_read(const GmresWork &W, hipStream_t st, bool launch = true) {
     return s;
 }
 
-// One Arnoldi step j on the device: z = M^-1 V_j, w = (A - omega) z, classical Gram-Schmidt
-// against V_0..V_j twice (the second pass restores orthogonality lost to rounding), the column
-// of H and its Givens rotation (k_gmres_step), V_{j+1} = w / h_{j+1,j}, and the status words
-// copied to the pinned host buffer.  Right-hand sides that stopped keep their basis (masked).
+// One Arnoldi step j on the device: z = M^-1 V_j (unpacked), w = (A - omega) z, V_{j+1} = w packed,
+// classical Gram-Schmidt of V_{j+1} against V_0..V_j twice (the second pass restores
+// orthogonality lost to rounding), the column of H and its Givens rotation (k_gmres_step),
+// V_{j+1} /= h_{j+1,j}, and the status words copied to the pinned host buffer.  Right-hand sides
+// that stopped keep their basis (masked).
 hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double tol, const Vecs &w, const Vecs &z,
                         bool eager_sigma) {
     lrcc_ctx *c = S.c;
@@ -1421,31 +1448,33 @@ hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double 
     const State<double> &T = c->s64;
     hipStream_t st = S.st;
     hipError_t e;
-    e = precond(z.s, z.d, vj.s, vj.d, (const double *)T.d_o1, (const double *)T.d_v1, (const double *)T.d_o2,
-                (const double *)T.d_v2, S.omega, c->km, R, c->no, c->nv, st);
+    e = unpack_precond(z.s, z.d, vj.s, vj.d, W.pm, (const double *)T.d_o1, (const double *)T.d_v1,
+                       (const double *)T.d_o2, (const double *)T.d_v2, S.omega, c->km, R, c->no, c->nv, st);
     if (e != hipSuccess) return e;
     Program *p = sigma_program(c, precision, R, S.adjoint);
     c->io_x1 = z.s; c->io_x2 = z.d; c->io_y1 = w.s; c->io_y2 = w.d; c->io_omega = S.omega;
     e = eager_sigma ? run_sigma(c, p, st) : p->run(st);
+    if (e != hipSuccess) return e;
+    e = pack_vec(vn.s, vn.d, w.s, w.d, nullptr, nullptr, W.pm, R, n1, W.blk, st);
     if (e != hipSuccess) return e;
     // classical Gram-Schmidt with one re-orthogonalisation; the complex64 inner solves of the
     // refinement (to a relative 1e-4 or so, corrected by the complex128 residual) take one pass
     const int passes = precision == LRCC_FP32 ? 1 : 2;
     for (int pass = 0; pass < passes; ++pass) {
         void *h = pass == 0 ? W.h1 : W.h2;
-        e = multidot(W.Vs, W.Vd, w.s, w.d, R, n1, n2, j + 1, W.part, h, W.m + 1, st);
+        e = multidot(W.Vs, W.Vd, vn.s, vn.d, R, n1, n2, j + 1, W.part, h, W.m + 1, 1.0, st);
         if (e != hipSuccess) return e;
-        e = multiaxpy(w.s, w.d, W.Vs, W.Vd, h, W.m + 1, -1.0, W.g.act, 1.0, R, n1, n2, j + 1, st);
+        e = multiaxpy(vn.s, vn.d, W.Vs, W.Vd, h, W.m + 1, -1.0, W.g.act, 1.0, R, n1, n2, j + 1, st);
         if (e != hipSuccess) return e;
     }
-    e = selfdot(w.s, w.d, R, n1, n2, W.part, W.hn2, st);
+    e = selfdot(vn.s, vn.d, R, n1, n2, W.part, W.hn2, 1.0, st);
     if (e != hipSuccess) return e;
     e = gmres_step(W.g, j, W.h1, passes == 2 ? W.h2 : nullptr, W.hn2, tol, precision == LRCC_FP64 ? kSingularPivot : 0.0,
                    st);
     if (e != hipSuccess) return e;
-    e = batched_axpby(vn.s, w.s, W.g.scal, 0.0, R, n1, st);
+    e = batched_axpby(vn.s, vn.s, W.g.scal, 0.0, R, n1, st);
     if (e != hipSuccess) return e;
-    e = batched_axpby(vn.d, w.d, W.g.scal, 0.0, R, n2, st);
+    e = batched_axpby(vn.d, vn.d, W.g.scal, 0.0, R, n2, st);
     if (e != hipSuccess) return e;
     e = gmres_status(W.g, (double *)W.stat_d, st);
     if (e != hipSuccess) return e;
@@ -1461,7 +1490,7 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
                           std::vector<bool> *singular = nullptr) {
     lrcc_ctx *c = S.c;
     const int R = S.R, m = W.m;
-    const i64 n1 = S.n1, n2 = S.n2;
+    const i64 n1 = S.n1, n2p = W.n2;
     hipStream_t st = S.st;
     // ||b|| once; the singular flags start clear
     {
@@ -1480,17 +1509,16 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
     };
     const Vecs v0 = W.vec(0);
     while (true) {
-        // r = b - A x into V_0, its norm, the cycle's initial state on the device
-        HIPCHK(hipMemcpyAsync(v0.s, b.s, (size_t)R * n1 * 16, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(v0.d, b.d, (size_t)R * n2 * 16, hipMemcpyDeviceToDevice, st));
+        // r = b - A x packed into V_0, its norm, the cycle's initial state on the device
         if (!(first && x_is_zero)) {
             S.op(w, x, precision);
             ++applied;
-            HIPCHK(batched_axpby(v0.s, w.s, W.minus, 1.0, R, n1, st));
-            HIPCHK(batched_axpby(v0.d, w.d, W.minus, 1.0, R, n2, st));
+            HIPCHK(pack_vec(v0.s, v0.d, b.s, b.d, w.s, w.d, W.pm, R, n1, W.blk, st));
+        } else {
+            HIPCHK(pack_vec(v0.s, v0.d, b.s, b.d, nullptr, nullptr, W.pm, R, n1, W.blk, st));
         }
         first = false;
-        HIPCHK(selfdot(v0.s, v0.d, R, n1, n2, W.part, W.beta2, st));
+        HIPCHK(selfdot(v0.s, v0.d, R, n1, n2p, W.part, W.beta2, 1.0, st));
         HIPCHK(gmres_init(W.g, W.beta2, tol, st));
         GmresStatus gs = gmres_read(W, st);
         bool all = true, nonfinite = false;
@@ -1507,7 +1535,7 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
         // a non-finite residual cannot recover: stop at once (the caller reports it)
         if (all || nonfinite || applied >= max_apply) return done();
         HIPCHK(batched_axpby(v0.s, v0.s, W.g.scal, 0.0, R, n1, st));
-        HIPCHK(batched_axpby(v0.d, v0.d, W.g.scal, 0.0, R, n2, st));
+        HIPCHK(batched_axpby(v0.d, v0.d, W.g.scal, 0.0, R, n2p, st));
         int j = 0;
         for (; j < m && applied < max_apply; ++j) {
             // graph replay of the step once the sigma program has been tuned (the first run of a
@@ -1546,12 +1574,14 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
             }
             if (!any) { ++j; break; }
         }
-        // x += M^-1 sum_i y_i V_i with y = H^-1 g per right-hand side
+        // x += M^-1 sum_i y_i V_i with y = H^-1 g per right-hand side; the sum goes to slot j,
+        // whose vector V_j is not in the span the solution takes (and the next cycle restarts)
         HIPCHK(gmres_solve(W.g, W.y, st));
-        HIPCHK(multiaxpy(w.s, w.d, W.Vs, W.Vd, W.y, m + 1, 1.0, nullptr, 0.0, R, n1, n2, j, st));
-        S.prec(z, w);
+        const Vecs u = W.vec(j);
+        HIPCHK(multiaxpy(u.s, u.d, W.Vs, W.Vd, W.y, m + 1, 1.0, nullptr, 0.0, R, n1, n2p, j, st));
+        S.unpack_prec(z, u, W.pm);
         HIPCHK(batched_axpby(x.s, z.s, W.ones, 1.0, R, n1, st));
-        HIPCHK(batched_axpby(x.d, z.d, W.ones, 1.0, R, n2, st));
+        HIPCHK(batched_axpby(x.d, z.d, W.ones, 1.0, R, S.n2, st));
         x_is_zero = false;
         if (applied >= max_apply) {
             HIPCHK(hipStreamSynchronize(st));
@@ -1579,7 +1609,10 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
     S.n1 = (i64)c->nk * c->no * c->nv;
     S.n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
     const bool mixed = o.precision == LRCC_FP32;
-    const size_t per = (size_t)R * (S.n1 + S.n2) * 16;
+    const i64 n2p = packed_doubles(c);
+    const size_t per = (size_t)R * (S.n1 + S.n2) * 16;     // a full work vector
+    const size_t perk = (size_t)R * (S.n1 + n2p) * 16;     // a Krylov vector (packed doubles)
+    const int nwork = 2 + (mixed ? 2 : 0);
     c->solmem.release();
     int m = o.krylov;
     if (m <= 0) {
@@ -1587,17 +1620,16 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
         // single-vector buffers of the alpha contraction), between 4 and 60 vectors
         size_t fr = 0, tot = 0;
         if (!g_dry_run) HIPCHK(hipMemGetInfo(&fr, &tot));
-        const long long fit = (long long)(0.85 * (double)fr / (double)per) - 3 - (mixed ? 2 : 0);
+        const long long fit = (long long)((0.85 * (double)fr - (double)(per * nwork)) / (double)perk) - 1;
         m = (int)std::max(4LL, std::min(60LL, fit));
     }
     m = std::min(m, 60);   // the Gram-Schmidt kernels take at most 64 basis vectors
-    const int nvec = (m + 1) + 2 + (mixed ? 2 : 0);
-    const size_t need = per * nvec + (size_t)R * (dot_blocks(S.n2) + 4) * 16 * 2 +
-                        (size_t)R * ((m + 1) * multidot_blocks(S.n1 + S.n2) + 4 * (m + 2) + (size_t)(m + 1) * m) * 16;
+    const size_t need = perk * (m + 1) + per * nwork + (size_t)R * (dot_blocks(S.n2) + 4) * 16 * 2 +
+                        (size_t)R * ((m + 1) * multidot_blocks(S.n1 + n2p) + 4 * (m + 2) + (size_t)(m + 1) * m) * 16;
     if (o.mem_cap_bytes > 0 && need > (size_t)o.mem_cap_bytes)
         throw LrccError(LRCC_E_OOM, "solver work vectors exceed the memory cap");
     GmresWork W;
-    gmres_alloc(c, W, R, m, S.n1, S.n2, st);
+    gmres_alloc(c, W, R, m, S.n1, st);
     auto mk = [&]() { Vecs v; v.s = c->solmem.get((size_t)R * S.n1 * 16); v.d = c->solmem.get((size_t)R * S.n2 * 16); return v; };
     Vecs w = mk(), z = mk();
     S.part = c->solmem.get((size_t)R * dot_blocks(S.n2) * 16);

@@ -140,6 +140,145 @@ hipError_t precond(void *o1, void *o2, const void *i1, const void *i2, const dou
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ packed Krylov vectors
+// The doubles of every vector the solver handles are antisymmetric under (ki,i) <-> (kj,j) and
+// (ka,a) <-> (kb,b) (the amplitudes of Eq. tx2, and the operator maps them to such), so the
+// Krylov basis keeps one k block per orbit of those swaps: the blocks with ki <= kj and
+// ka <= kb, whole, scaled by sqrt(w) with w = (full blocks in the orbit) / 4, so that the plain
+// inner product of packed vectors equals the 1/4-weighted one of the full vectors.
+
+int pack_tables(const KMesh &km, std::vector<int> &canon, std::vector<int> &map, std::vector<double> &scale) {
+    const int nk = km.size();
+    std::vector<int> pidx((size_t)nk * nk * nk, -1);
+    canon.clear();
+    scale.clear();
+    map.assign((size_t)nk * nk * nk, 0);
+    for (int ki = 0; ki < nk; ++ki)
+        for (int kj = ki; kj < nk; ++kj)
+            for (int ka = 0; ka < nk; ++ka) {
+                const int kb = km.comb(ki, kj, ka);
+                if (ka > kb) continue;
+                const int f = (ki * nk + kj) * nk + ka;
+                pidx[f] = (int)canon.size();
+                canon.push_back(f);
+                scale.push_back(std::sqrt((ki < kj ? 1.0 : 0.5) * (ka < kb ? 1.0 : 0.5)));
+            }
+    for (int ki = 0; ki < nk; ++ki)
+        for (int kj = 0; kj < nk; ++kj)
+            for (int ka = 0; ka < nk; ++ka) {
+                const int kb = km.comb(ki, kj, ka);
+                const int fc = (std::min(ki, kj) * nk + std::max(ki, kj)) * nk + std::min(ka, kb);
+                map[(size_t)(ki * nk + kj) * nk + ka] = 4 * pidx[fc] + 2 * (ki > kj) + (ka > kb);
+            }
+    return (int)canon.size();
+}
+
+// singles: o1 = a1 - b1; doubles: o2[r][p] = scale[p] (a2 - b2)[r][canon[p]] (b may be null)
+__global__ void k_pack(double2 *o1, double2 *o2, const double2 *a1, const double2 *a2, const double2 *b1,
+                       const double2 *b2, const int *canon, const double *scale, int R, i64 n1, int np, i64 blk,
+                       i64 n2) {
+    const i64 n2p = (i64)np * blk, N1 = (i64)R * n1;
+    const i64 N = N1 + (i64)R * n2p;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        if (t < N1) {
+            double2 x = a1[t];
+            if (b1) {
+                const double2 y = b1[t];
+                x.x -= y.x;
+                x.y -= y.y;
+            }
+            o1[t] = x;
+        } else {
+            const i64 u = t - N1;
+            const int r = (int)(u / n2p);
+            const i64 q = u - (i64)r * n2p;
+            const int p = (int)(q / blk);
+            const i64 src = (i64)r * n2 + (i64)canon[p] * blk + (q - (i64)p * blk);
+            double2 x = a2[src];
+            if (b2) {
+                const double2 y = b2[src];
+                x.x -= y.x;
+                x.y -= y.y;
+            }
+            const double sc = scale[p];
+            o2[u] = make_double2(sc * x.x, sc * x.y);
+        }
+    }
+}
+
+hipError_t pack_vec(void *o1, void *o2p, const void *a1, const void *a2, const void *b1, const void *b2,
+                    const PackMap &pm, int R, i64 n1, i64 blk, hipStream_t s) {
+    const i64 n2 = (i64)pm.nfull * blk;
+    const i64 N = (i64)R * (n1 + (i64)pm.np * blk);
+    i64 g = (N + 255) / 256;
+    if (g > 262144) g = 262144;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s, (double2 *)o1, (double2 *)o2p,
+                       (const double2 *)a1, (const double2 *)a2, (const double2 *)b1, (const double2 *)b2, pm.canon,
+                       pm.scale, R, n1, pm.np, blk, n2);
+    return hipGetLastError();
+}
+
+// The preconditioned full vector of a packed one: doubles element (ki,kj,ka)(i,j,a,b) from the
+// orbit's block at the swapped indices, with the sign of the swaps and 1/scale, both parts
+// divided by the denominators of k_precond.
+__global__ void k_unpack_precond(double2 *o1, double2 *o2, const double2 *i1, const double2 *i2p, const int *map,
+                                 const double *scale, const double *eo, const double *ev, const double *eo2,
+                                 const double *ev2, const double *omega, KMesh km, int R, int no, int nv, int np) {
+    const int nk = km.size();
+    const i64 blk = (i64)no * no * nv * nv;
+    const i64 n1 = (i64)nk * no * nv, n2 = (i64)nk * nk * nk * blk, n2p = (i64)np * blk;
+    const i64 N = (i64)R * (n1 + n2);
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        double d;
+        double2 x;
+        double2 *dst;
+        if (t < (i64)R * n1) {
+            const int r = (int)(t / n1);
+            i64 q = t % n1;
+            const int a = (int)(q % nv); q /= nv;
+            const int i = (int)(q % no);
+            const int k = (int)(q / no);
+            d = ev[k * nv + a] - eo[k * no + i] - (omega ? omega[r] : 0.0);
+            x = i1[t];
+            dst = o1 + t;
+        } else {
+            const i64 u = t - (i64)R * n1;
+            const int r = (int)(u / n2);
+            i64 q = u % n2;
+            const int b = (int)(q % nv); q /= nv;
+            const int a = (int)(q % nv); q /= nv;
+            const int j = (int)(q % no); q /= no;
+            const int i = (int)(q % no); q /= no;
+            const int f = (int)q;
+            const int ka = f % nk, kj = (f / nk) % nk, ki = f / (nk * nk);
+            const int kb = km.comb(ki, kj, ka);
+            const int m = map[f], p = m >> 2;
+            const bool fi = (m & 2) != 0, fa = (m & 1) != 0;
+            const int ii = fi ? j : i, jj = fi ? i : j, aa = fa ? b : a, bb = fa ? a : b;
+            const double2 y = i2p[(i64)r * n2p + (i64)p * blk + (((i64)ii * no + jj) * nv + aa) * nv + bb];
+            const double sg = (fi != fa ? -1.0 : 1.0) / scale[p];
+            x = make_double2(sg * y.x, sg * y.y);
+            d = ev2[ka * nv + a] + ev2[kb * nv + b] - eo2[ki * no + i] - eo2[kj * no + j] - (omega ? omega[r] : 0.0);
+            dst = o2 + u;
+        }
+        if (fabs(d) < 1e-2) d = d < 0 ? -1e-2 : 1e-2;   // guard near-zero dressed denominators
+        *dst = make_double2(x.x / d, x.y / d);
+    }
+}
+
+hipError_t unpack_precond(void *o1, void *o2, const void *i1, const void *i2p, const PackMap &pm, const double *eo,
+                          const double *ev, const double *eo2, const double *ev2, const double *omega, KMesh km,
+                          int R, int no, int nv, hipStream_t s) {
+    const int nk = km.size();
+    const i64 N = (i64)R * ((i64)nk * no * nv + (i64)nk * nk * nk * no * no * nv * nv);
+    i64 g = (N + 255) / 256;
+    if (g > 262144) g = 262144;
+    hipLaunchKernelGGL(k_unpack_precond, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s, (double2 *)o1,
+                       (double2 *)o2, (const double2 *)i1, (const double2 *)i2p, pm.map, pm.scale, eo, ev, eo2, ev2,
+                       omega, km, R, no, nv, pm.np);
+    return hipGetLastError();
+}
+
 // d[k][p] = Re F[k][p][p] for a k-diagonal complex matrix [nk][n][n]
 __global__ void k_diag_real(const double2 *F, double *d, int nk, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,17 +319,18 @@ hipError_t combine(void *Y, const void *V, const void *C, int R, int m, i64 n, d
 
 // ------------------------------------------------------------------ device-resident GMRES
 // Vectors of one Krylov space: vector i, right-hand side r is (s + (i*R + r)*n1, d + (i*R + r)*n2).
-// Inner products weight the doubles by 1/4 (every independent amplitude counts once).
+// Inner products weight the doubles by dw (1/4 for full antisymmetric doubles, where every
+// independent amplitude then counts once; 1 for packed doubles, which carry the weight).
 
 namespace {
 constexpr int MD = 256;        // threads of the multi-dot and multi-axpy kernels
 constexpr int MDV = 8;         // basis vectors per multi-dot workgroup
 }
 
-// part[(r*k + i)*nblk + b] = sum over chunk b of conj(V_i[r]) w[r] (singles weight 1, doubles 1/4)
+// part[(r*k + i)*nblk + b] = sum over chunk b of conj(V_i[r]) w[r] (singles weight 1, doubles dw)
 __global__ void __launch_bounds__(MD) k_multidot_partial(const double2 *Vs, const double2 *Vd, const double2 *ws,
                                                          const double2 *wd, int R, i64 n1, i64 n2, int k, int nblk,
-                                                         double2 *part) {
+                                                         double dw, double2 *part) {
     __shared__ double sr[MDV][MD], si[MDV][MD];
     const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MDV, t = threadIdx.x;
     const int nv = min(MDV, k - i0);
@@ -202,7 +342,7 @@ __global__ void __launch_bounds__(MD) k_multidot_partial(const double2 *Vs, cons
         const bool single = e < n1;
         const i64 off = single ? (i64)r * n1 + e : (i64)r * n2 + (e - n1);
         const double2 y = single ? ws[off] : wd[off];
-        const double wt = single ? 1.0 : 0.25;
+        const double wt = single ? 1.0 : dw;
 #pragma unroll
         for (int q = 0; q < MDV; ++q) {
             if (q < nv) {
@@ -245,10 +385,10 @@ int multidot_blocks(i64 n) {
 }
 
 hipError_t multidot(const void *Vs, const void *Vd, const void *ws, const void *wd, int R, i64 n1, i64 n2, int k,
-                    void *part, void *out, int ostride, hipStream_t s) {
+                    void *part, void *out, int ostride, double dw, hipStream_t s) {
     const int nblk = multidot_blocks(n1 + n2);
     hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, R, (k + MDV - 1) / MDV), dim3(MD), 0, s, (const double2 *)Vs,
-                       (const double2 *)Vd, (const double2 *)ws, (const double2 *)wd, R, n1, n2, k, nblk,
+                       (const double2 *)Vd, (const double2 *)ws, (const double2 *)wd, R, n1, n2, k, nblk, dw,
                        (double2 *)part);
     hipLaunchKernelGGL(k_multidot_final, dim3((R * k + 63) / 64), dim3(64), 0, s, (const double2 *)part, R, k, nblk,
                        (double2 *)out, ostride);
@@ -429,9 +569,10 @@ hipError_t gmres_status(const GmresState &g, double *out, hipStream_t s) {
 }
 
 // per-right-hand-side norms^2 into out[r] (as complex, real part) via the multi-dot of w with itself
-hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, hipStream_t s) {
+hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, double dw,
+                   hipStream_t s) {
     // V_0 = w with a one-vector "space": stride arguments make vector 0 the vector itself
-    return multidot(ws, wd, ws, wd, R, n1, n2, 1, part, out, 1, s);
+    return multidot(ws, wd, ws, wd, R, n1, n2, 1, part, out, 1, dw, s);
 }
 
 }  // namespace lrcc
