@@ -355,6 +355,8 @@ def main():
                     help="ladder mode of the headline context (0 automatic, 1 rebuilt in LDS, 2 stored, "
                          "3 built by momentum class)")
     ap.add_argument("--alpha-tol", type=float, default=1e-10)
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="relative tolerance of the complex64 correction solves (default: the library's)")
     ap.add_argument("--ccsd-iter", type=int, default=300)
     ap.add_argument("--no-tune", action="store_true", help="heuristic launch variants instead of autotuning")
     ap.add_argument("--uneven", action="store_true", help="also time the twelve-chain uneven batch")
@@ -525,8 +527,9 @@ def main():
             log(f"solving for alpha ({name})")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            extra = {"inner_tol": args.inner_tol} if args.inner_tol else {}
             al, rep = ctx.solve(list(w.omegas), axis_mask=7, tol=args.alpha_tol, precision=prec,
-                                reuse_lambda=0)
+                                reuse_lambda=0, **extra)
             torch.cuda.synchronize()
             res[name] = (time.perf_counter() - t0, al, rep)
             log(f"alpha ({name}) in {res[name][0]:.1f} s: {rep}")
@@ -538,6 +541,7 @@ def main():
             "s_to_alpha_mixed": res["mixed"][0], "s_to_alpha_fp64": res["fp64"][0],
             "speedup_mixed_vs_fp64": res["fp64"][0] / res["mixed"][0],
             "tol": args.alpha_tol,
+            "inner_tol": args.inner_tol if args.inner_tol else ctx.solve_options().inner_tol,
             "mixed_vs_fp64_max_abs": float(dif.max()),
             "mixed_vs_fp64_max_rel": float(dif.max() / np.abs(af).max()),
             # per tensor element alpha_XY: the largest |mixed - fp64| over the frequencies, and

@@ -68,7 +68,7 @@ typedef struct {
                               memory (85% of it, 4..60 vectors)                                       */
     int precision;         /* LRCC_FP64: GMRES in complex128; LRCC_FP32: complex64 matrix-core inner
                               GMRES corrections inside complex128 iterative refinement                */
-    double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-4;
+    double inner_tol;      /* relative tolerance of each complex64 correction solve (default 1e-5;
                               at most 4 restart cycles per refinement step)                          */
     int max_outer;         /* maximum refinement steps (default 30)                                  */
     long long mem_cap_bytes; /* > 0: refuse (LRCC_E_OOM) if solver vectors would exceed this         */

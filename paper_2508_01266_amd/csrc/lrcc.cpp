@@ -120,6 +120,9 @@ struct lrcc_ctx {
     bool autotune = false;
     hipStream_t own_stream = nullptr;          // non-null stream for solver work (graph capture)
     std::unique_ptr<Program> pre64, pre32;     // amplitude-dependent blocks (f64) and their f32 copies
+    // pre64 op ranges that form R_iabf and subtract it from H_abej: skipped by the lean
+    // precompute, whose H lacks the R part (the lean sigma forms that term from x1 directly)
+    std::vector<std::pair<size_t, size_t>> pre64_lean_skip;
     void *eps_o = nullptr, *eps_v = nullptr;   // diagonal of fock per k (preconditioner)
     DevMem solmem;                             // solver work vectors
     bool lam_valid = false;
@@ -513,8 +516,11 @@ void build_state(lrcc_ctx *c) {
         S.Wbar = wr;
     }
     // R_iabf = sum_me t_imae <mb||ef>   (k_i + k_f = k_a + k_b)
+    c->pre64_lean_skip.clear();
     S.R = alloc_kt<double>(c, m, "ovvv", 0, {1, -1, -1, 1});
+    const size_t r_begin = P.ops.size();
     contract<double>(P, S.R, "iabf", t2, "imae", ovvv, "mbef", 1.0, false);
+    c->pre64_lean_skip.push_back({r_begin, P.ops.size()});
     // U_ianf = sum_me t_imae <mn||ef>   (k_i + k_f = k_a + k_n)
     S.U = alloc_kt<double>(c, m, "ovov", 0, {1, -1, -1, 1});
     contract<double>(P, S.U, "ianf", t2, "imae", oovv, "mnef", 1.0, false);
@@ -540,9 +546,11 @@ void build_state(lrcc_ctx *c) {
         void *dst = rp.p, *h = S.H.p;
         const i64 n = rp.count();
         const KMesh km = c->km;
+        const size_t h_begin = P.ops.size();
         P.ops.push_back([=](hipStream_t s) { return permute4(src, dst, km, ext, perm, sg, s); });
         P.ops.push_back([=](hipStream_t s) { return scale_copy(dst, dst, -1.0, 0.0, n, s); });
         P.ops.push_back([=](hipStream_t s) { return add_inplace<double>(h, dst, n, s); });
+        c->pre64_lean_skip.push_back({h_begin, P.ops.size()});
     }
     //   G2_ijbm = sum_e t_ie <mb||ej> + 1/2 <mb||ij>, entering as - G2_ijbm x_ma.
     S.G2 = alloc_kt<double>(c, m, "oovo");
@@ -653,10 +661,23 @@ static void tune_pre(lrcc_ctx *c, Program *p, const char *which, hipStream_t st)
 }
 
 // Recompute every amplitude-dependent block from the device amplitudes.
-void run_precompute(lrcc_ctx *c, bool fp32, hipStream_t st = nullptr) {
+// lean: the complex128 blocks without R_iabf (H_abej then lacks its R part), for the lean sigma
+// programs only; a later full run restores every block.
+void run_precompute(lrcc_ctx *c, bool fp32, hipStream_t st = nullptr, bool lean = false) {
     static const bool timed = std::getenv("LRCC_PRE_TIMES") != nullptr;   // per-op timing report
     tune_pre(c, c->pre64.get(), "pre64", st);
     if (fp32) tune_pre(c, c->pre32.get(), "pre32", st);
+    if (lean) {
+        size_t at = 0;
+        for (const auto &r : c->pre64_lean_skip) {
+            HIPCHK(c->pre64->run_range(st, at, r.first));
+            at = r.second;
+        }
+        HIPCHK(c->pre64->run_range(st, at, c->pre64->ops.size()));
+        if (fp32) HIPCHK(c->pre32->run(st));
+        HIPCHK(hipStreamSynchronize(st));
+        return;
+    }
     if (timed) {
         const bool was = c->prof.on;
         c->prof.on = true;
@@ -697,10 +718,10 @@ struct SigmaGraph {
 };
 
 template <typename T>
-SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
+SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, bool lean = false) {
     SigmaGraph G;
-    auto A = [&](const char *cls) {
-        KT t = alloc_kt<T>(c, wm, cls, R);
+    auto A = [&](const char *cls, std::initializer_list<int> sg = {1, 1, -1, -1}) {
+        KT t = alloc_kt<T>(c, wm, cls, R, sg);
         G.active.push_back(t);
         return t;
     };
@@ -822,6 +843,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     con(Yx, "Rijan", Vx, "Rijmn", t1, "ma", -0.25);
     con(Z, "Rijab", Yx, "Rijan", t1, "nb", -1.0);
     con(Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);
+    if (lean) {
+        // H from the lean precompute lacks -R_jabe = -sum_mf t_jmaf <mb||fe>: with few right-hand
+        // sides the term is cheaper from x1 than R is once (o^2 v^3 + o^3 v^3 per vector against
+        // o^2 v^4): Q_ibmf = sum_e x_ie <mb||fe> (k_i + k_f = k_b + k_m), Z -= t_jmaf Q_ibmf
+        KT Q = A("ovov", {1, -1, -1, 1});
+        con(Q, "Ribmf", x1, "Rie", S.g_ovvv, "mbfe", 1.0, false);
+        con(Z, "Rijab", t2, "jmaf", Q, "Ribmf", -1.0);
+    }
     con(Z, "Rijab", S.G2, "ijbm", x1, "Rma", -1.0);
     return G;
 }
@@ -933,10 +962,10 @@ void ladder_block_gemms(lrcc_ctx *c, Program &P, bool transpose, const void *A, 
 }
 
 template <typename T>
-Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
+Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, bool lean = false) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
-    SigmaGraph G = record_sigma<T>(c, S, R, wm, full);
+    SigmaGraph G = record_sigma<T>(c, S, R, wm, full, lean);
     const i64 nb3 = (i64)nk * nk * nk;
     KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
     // caller layout -> internal (paper -> crystal normalisation for doubles)
@@ -1027,10 +1056,10 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
                         const void *const *z1src, const void *const *z2src);
 
 template <typename T>
-Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true) {
+Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, bool lean = false) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
-    SigmaGraph G = record_sigma<T>(c, S, R, wm, full);
+    SigmaGraph G = record_sigma<T>(c, S, R, wm, full, lean);
     emit_reverse_sweep<T>(c, S, R, G, P, &c->io_x1, &c->io_x2);
     KT x1 = G.x1, x2 = G.x2;
     // y1 = x1bar - omega z1 ; y2 = P(ij)P(ab) x2bar / Nk - omega z2
@@ -1202,14 +1231,20 @@ hipError_t run_sigma(lrcc_ctx *c, Program *p, hipStream_t st) {
 }
 
 // variant 0: the CCSD Jacobian; variant 1+x: the Jacobian of the one-body
-// perturbation residual for dipole axis x (Fock matrix -> mu_x, no two-electron part).
+// perturbation residual for dipole axis x (Fock matrix -> mu_x, no two-electron part);
+// kLeanSigma: the CCSD Jacobian (complex128) on the blocks of the lean precompute.
+constexpr int kLeanSigma = -1;
 Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false, int variant = 0) {
     auto key = std::make_pair(variant * 4 + prec * 2 + (adjoint ? 1 : 0), R);
     auto it = c->progs.find(key);
     if (it != c->progs.end()) return it->second.get();
     auto mem = std::make_unique<DevMem>();
     Program *p;
-    if (variant > 0) {
+    if (variant == kLeanSigma) {
+        if (prec != LRCC_FP64) throw LrccError(LRCC_E_ARG, "the lean sigma is FP64 only");
+        p = adjoint ? build_sigma_adjoint<double>(c, c->s64, R, *mem, true, true)
+                    : build_sigma<double>(c, c->s64, R, *mem, true, true);
+    } else if (variant > 0) {
         if (prec != LRCC_FP64) throw LrccError(LRCC_E_ARG, "perturbation operators are FP64 only");
         State<double> &X = c->xs[variant - 1];
         p = adjoint ? build_sigma_adjoint<double>(c, X, R, *mem, false) : build_sigma<double>(c, X, R, *mem, false);
@@ -1458,7 +1493,7 @@ hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double 
     e = pack_vec(vn.s, vn.d, w.s, w.d, nullptr, nullptr, W.pm, R, n1, W.blk, st);
     if (e != hipSuccess) return e;
     // classical Gram-Schmidt with one re-orthogonalisation; the complex64 inner solves of the
-    // refinement (to a relative 1e-4 or so, corrected by the complex128 residual) take one pass
+    // refinement (to a relative 1e-5 or so, corrected by the complex128 residual) take one pass
     const int passes = precision == LRCC_FP32 ? 1 : 2;
     for (int pass = 0; pass < passes; ++pass) {
         void *h = pass == 0 ? W.h1 : W.h2;
@@ -1704,7 +1739,7 @@ void default_opts(lrcc_solve_opts &o) {
     o.max_iter = 400;
     o.krylov = 0;
     o.precision = LRCC_FP64;
-    o.inner_tol = 1e-4;
+    o.inner_tol = 1e-5;
     o.max_outer = 30;
     o.mem_cap_bytes = 0;
     o.reuse_lambda = 1;
@@ -1845,7 +1880,8 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
     const i64 n1 = D.n1, n2 = D.n2;
     State<double> &S = c->s64;
     const i64 nt1 = S.t1.count(), nt2 = S.t2.count();
-    Program *adj = sigma_program(c, LRCC_FP64, 1, true);
+    // shifted points: the lean blocks and the matching transpose program (one vector)
+    Program *adj = sigma_program(c, LRCC_FP64, 1, true, kLeanSigma);
     const double coef5[4] = {1.0 / 12.0, -8.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0};
     const int shift5[4] = {-2, -1, 1, 2};
     const double coef3[3] = {-2.0 / 6.0, 6.0 / 6.0, -1.0 / 6.0};
@@ -1883,11 +1919,17 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
         HIPCHK(batched_axpby(S.t2.p, y.d, D.alpha, 1.0, 1, nt2, st));
-        run_precompute(c, false, st);
+        const auto tp0 = std::chrono::steady_clock::now();
+        run_precompute(c, false, st, true);
+        const auto tp1 = std::chrono::steady_clock::now();
         c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
         HIPCHK(adj->run(st));
         std::vector<cd> w(1, cd(coef[k] / h, 0.0));
         HIPCHK(hipStreamSynchronize(st));
+        if (verbose())
+            std::fprintf(stderr, "[lrcc] F stencil point %d: blocks %.2f ms, transpose product %.2f ms\n", k,
+                         std::chrono::duration<double, std::milli>(tp1 - tp0).count(),
+                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp1).count());
         HIPCHK(hipMemcpy(D.alpha, w.data(), 16, hipMemcpyHostToDevice));
         HIPCHK(batched_axpby(Fy.s, q.s, D.alpha, 1.0, 1, n1, st));
         HIPCHK(batched_axpby(Fy.d, q.d, D.alpha, 1.0, 1, n2, st));
@@ -4315,6 +4357,8 @@ lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int
         (void)sigma_program(&c, LRCC_FP64, nrhs, true);
         (void)sigma_program(&c, LRCC_FP32, nrhs, true);
         (void)sigma_program(&c, LRCC_FP64, 1, true);
+        (void)sigma_program(&c, LRCC_FP64, 1, true, kLeanSigma);
+        (void)sigma_program(&c, LRCC_FP64, 1, false, kLeanSigma);
         ensure_alpha_programs(&c);
         for (int x = 0; x < 3; ++x) (void)sigma_program(&c, LRCC_FP64, 1, true, 1 + x);
         (void)dens_program(&c, 1);
@@ -4327,6 +4371,7 @@ lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int
             (void)sigma_program(&c, LRCC_FP64, nrhs, adj != 0);
             (void)sigma_program(&c, LRCC_FP32, nrhs, adj != 0);
             (void)sigma_program(&c, LRCC_FP64, 1, adj != 0);
+            (void)sigma_program(&c, LRCC_FP64, 1, adj != 0, kLeanSigma);
         }
     } catch (LrccError &e) {
         st = (lrcc_status)e.code;
