@@ -1315,11 +1315,12 @@ struct SolveCtx {
         HIPCHK(hipMemsetAsync(y.s, 0, R * n1 * 16, st));
         HIPCHK(hipMemsetAsync(y.d, 0, R * n2 * 16, st));
     }
-    // out = M^-1 in for a Krylov-space vector in with packed doubles
-    void unpack_prec(const Vecs &out, const Vecs &in, const PackMap &pm) {
+    // out = M^-1 in for a Krylov-space vector in with packed doubles (complex64 storage for f32)
+    void unpack_prec(const Vecs &out, const Vecs &in, const PackMap &pm, int f32) {
         const State<double> &T = c->s64;
         HIPCHK(unpack_precond(out.s, out.d, in.s, in.d, pm, (const double *)T.d_o1, (const double *)T.d_v1,
-                              (const double *)T.d_o2, (const double *)T.d_v2, omega, c->km, R, c->no, c->nv, st));
+                              (const double *)T.d_o2, (const double *)T.d_v2, omega, c->km, R, c->no, c->nv, f32,
+                              st));
     }
     // y = (A - omega) x
     void op(const Vecs &y, const Vecs &x, int precision) {
@@ -1360,7 +1361,8 @@ static bool verbose() {
 
 // Device workspace of the batched GMRES: a contiguous Krylov basis with packed doubles (one k
 // block per antisymmetry orbit, PackMap; vector i of right-hand side r at (Vs + (i R + r) n1,
-// Vd + (i R + r) n2) with n2 the packed length), the Hessenberg/Givens state of every right-hand
+// Vd + (i R + r) n2) with n2 the packed length; complex128, or complex64 for the inner solves of
+// the mixed refinement), the Hessenberg/Givens state of every right-hand
 // side, the Gram-Schmidt coefficients and a pinned status buffer.  With graphs on, every Arnoldi
 // step j is captured once (unpacking preconditioner, sigma, packing, two Gram-Schmidt passes (one
 // in complex64), norm, rotation, normalisation, status copy) and replayed for later cycles and
@@ -1369,6 +1371,8 @@ struct GmresWork {
     int R = 0, m = 0;
     i64 n1 = 0, n2 = 0;   // singles and packed doubles per right-hand side
     i64 blk = 0;          // elements of one doubles k block (o o v v)
+    int f32 = 0;          // Krylov vectors stored in complex64 (the complex64 inner solves), else complex128
+    size_t vb = 16;       // bytes per stored complex element
     PackMap pm;
     void *Vs = nullptr, *Vd = nullptr;
     GmresState g{};
@@ -1381,8 +1385,8 @@ struct GmresWork {
     std::map<std::tuple<int, int, double>, hipGraphExec_t> steps;
     Vecs vec(int i) const {
         Vecs v;
-        v.s = (char *)Vs + (size_t)i * R * n1 * 16;
-        v.d = (char *)Vd + (size_t)i * R * n2 * 16;
+        v.s = (char *)Vs + (size_t)i * R * n1 * vb;
+        v.d = (char *)Vd + (size_t)i * R * n2 * vb;
         return v;
     }
     ~GmresWork() {
@@ -1398,7 +1402,7 @@ i64 packed_doubles(const lrcc_ctx *c) {
     return (i64)pack_tables(c->km, canon, map, scale) * c->no * c->no * c->nv * c->nv;
 }
 
-void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, hipStream_t st) {
+void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, int f32, hipStream_t st) {
     DevMem &M = c->solmem;
     std::vector<int> canon, map;
     std::vector<double> scale;
@@ -1407,13 +1411,15 @@ void gmres_alloc(lrcc_ctx *c, GmresWork &W, int R, int m, i64 n1, hipStream_t st
     W.blk = (i64)c->no * c->no * c->nv * c->nv;
     const i64 n2 = (i64)W.pm.np * W.blk;
     W.R = R; W.m = m; W.n1 = n1; W.n2 = n2;
+    W.f32 = f32;
+    W.vb = f32 ? 8 : 16;
     int *canon_d = (int *)M.get(canon.size() * sizeof(int)), *map_d = (int *)M.get(map.size() * sizeof(int));
     double *scale_d = (double *)M.get(scale.size() * sizeof(double));
     W.pm.canon = canon_d;
     W.pm.map = map_d;
     W.pm.scale = scale_d;
-    W.Vs = M.get((size_t)(m + 1) * R * n1 * 16);
-    W.Vd = M.get((size_t)(m + 1) * R * n2 * 16);
+    W.Vs = M.get((size_t)(m + 1) * R * n1 * W.vb);
+    W.Vd = M.get((size_t)(m + 1) * R * n2 * W.vb);
     W.g.R = R;
     W.g.m = m;
     W.g.H = (double2 *)M.get((size_t)R * (m + 1) * m * 16);
@@ -1484,32 +1490,32 @@ hipError_t arnoldi_step(SolveCtx &S, GmresWork &W, int j, int precision, double 
     hipStream_t st = S.st;
     hipError_t e;
     e = unpack_precond(z.s, z.d, vj.s, vj.d, W.pm, (const double *)T.d_o1, (const double *)T.d_v1,
-                       (const double *)T.d_o2, (const double *)T.d_v2, S.omega, c->km, R, c->no, c->nv, st);
+                       (const double *)T.d_o2, (const double *)T.d_v2, S.omega, c->km, R, c->no, c->nv, W.f32, st);
     if (e != hipSuccess) return e;
     Program *p = sigma_program(c, precision, R, S.adjoint);
     c->io_x1 = z.s; c->io_x2 = z.d; c->io_y1 = w.s; c->io_y2 = w.d; c->io_omega = S.omega;
     e = eager_sigma ? run_sigma(c, p, st) : p->run(st);
     if (e != hipSuccess) return e;
-    e = pack_vec(vn.s, vn.d, w.s, w.d, nullptr, nullptr, W.pm, R, n1, W.blk, st);
+    e = pack_vec(vn.s, vn.d, w.s, w.d, nullptr, nullptr, W.pm, R, n1, W.blk, W.f32, st);
     if (e != hipSuccess) return e;
     // classical Gram-Schmidt with one re-orthogonalisation; the complex64 inner solves of the
     // refinement (to a relative 1e-5 or so, corrected by the complex128 residual) take one pass
     const int passes = precision == LRCC_FP32 ? 1 : 2;
     for (int pass = 0; pass < passes; ++pass) {
         void *h = pass == 0 ? W.h1 : W.h2;
-        e = multidot(W.Vs, W.Vd, vn.s, vn.d, R, n1, n2, j + 1, W.part, h, W.m + 1, 1.0, st);
+        e = multidot(W.Vs, W.Vd, vn.s, vn.d, R, n1, n2, j + 1, W.part, h, W.m + 1, 1.0, W.f32, st);
         if (e != hipSuccess) return e;
-        e = multiaxpy(vn.s, vn.d, W.Vs, W.Vd, h, W.m + 1, -1.0, W.g.act, 1.0, R, n1, n2, j + 1, st);
+        e = multiaxpy(vn.s, vn.d, W.Vs, W.Vd, h, W.m + 1, -1.0, W.g.act, 1.0, R, n1, n2, j + 1, W.f32, st);
         if (e != hipSuccess) return e;
     }
-    e = selfdot(vn.s, vn.d, R, n1, n2, W.part, W.hn2, 1.0, st);
+    e = selfdot(vn.s, vn.d, R, n1, n2, W.part, W.hn2, 1.0, W.f32, st);
     if (e != hipSuccess) return e;
     e = gmres_step(W.g, j, W.h1, passes == 2 ? W.h2 : nullptr, W.hn2, tol, precision == LRCC_FP64 ? kSingularPivot : 0.0,
                    st);
     if (e != hipSuccess) return e;
-    e = batched_axpby(vn.s, vn.s, W.g.scal, 0.0, R, n1, st);
+    e = basis_axpby(vn.s, vn.s, W.g.scal, 0.0, R, n1, W.f32, st);
     if (e != hipSuccess) return e;
-    e = batched_axpby(vn.d, vn.d, W.g.scal, 0.0, R, n2, st);
+    e = basis_axpby(vn.d, vn.d, W.g.scal, 0.0, R, n2, W.f32, st);
     if (e != hipSuccess) return e;
     e = gmres_status(W.g, (double *)W.stat_d, st);
     if (e != hipSuccess) return e;
@@ -1548,12 +1554,12 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
         if (!(first && x_is_zero)) {
             S.op(w, x, precision);
             ++applied;
-            HIPCHK(pack_vec(v0.s, v0.d, b.s, b.d, w.s, w.d, W.pm, R, n1, W.blk, st));
+            HIPCHK(pack_vec(v0.s, v0.d, b.s, b.d, w.s, w.d, W.pm, R, n1, W.blk, W.f32, st));
         } else {
-            HIPCHK(pack_vec(v0.s, v0.d, b.s, b.d, nullptr, nullptr, W.pm, R, n1, W.blk, st));
+            HIPCHK(pack_vec(v0.s, v0.d, b.s, b.d, nullptr, nullptr, W.pm, R, n1, W.blk, W.f32, st));
         }
         first = false;
-        HIPCHK(selfdot(v0.s, v0.d, R, n1, n2p, W.part, W.beta2, 1.0, st));
+        HIPCHK(selfdot(v0.s, v0.d, R, n1, n2p, W.part, W.beta2, 1.0, W.f32, st));
         HIPCHK(gmres_init(W.g, W.beta2, tol, st));
         GmresStatus gs = gmres_read(W, st);
         bool all = true, nonfinite = false;
@@ -1569,8 +1575,8 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
                          max_nan(rel));
         // a non-finite residual cannot recover: stop at once (the caller reports it)
         if (all || nonfinite || applied >= max_apply) return done();
-        HIPCHK(batched_axpby(v0.s, v0.s, W.g.scal, 0.0, R, n1, st));
-        HIPCHK(batched_axpby(v0.d, v0.d, W.g.scal, 0.0, R, n2p, st));
+        HIPCHK(basis_axpby(v0.s, v0.s, W.g.scal, 0.0, R, n1, W.f32, st));
+        HIPCHK(basis_axpby(v0.d, v0.d, W.g.scal, 0.0, R, n2p, W.f32, st));
         int j = 0;
         for (; j < m && applied < max_apply; ++j) {
             // graph replay of the step once the sigma program has been tuned (the first run of a
@@ -1613,8 +1619,8 @@ std::vector<double> gmres(SolveCtx &S, GmresWork &W, const Vecs &b, const Vecs &
         // whose vector V_j is not in the span the solution takes (and the next cycle restarts)
         HIPCHK(gmres_solve(W.g, W.y, st));
         const Vecs u = W.vec(j);
-        HIPCHK(multiaxpy(u.s, u.d, W.Vs, W.Vd, W.y, m + 1, 1.0, nullptr, 0.0, R, n1, n2p, j, st));
-        S.unpack_prec(z, u, W.pm);
+        HIPCHK(multiaxpy(u.s, u.d, W.Vs, W.Vd, W.y, m + 1, 1.0, nullptr, 0.0, R, n1, n2p, j, W.f32, st));
+        S.unpack_prec(z, u, W.pm, W.f32);
         HIPCHK(batched_axpby(x.s, z.s, W.ones, 1.0, R, n1, st));
         HIPCHK(batched_axpby(x.d, z.d, W.ones, 1.0, R, S.n2, st));
         x_is_zero = false;
@@ -1646,7 +1652,9 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
     const bool mixed = o.precision == LRCC_FP32;
     const i64 n2p = packed_doubles(c);
     const size_t per = (size_t)R * (S.n1 + S.n2) * 16;     // a full work vector
-    const size_t perk = (size_t)R * (S.n1 + n2p) * 16;     // a Krylov vector (packed doubles)
+    // a Krylov vector (packed doubles): complex64 for the inner solves of the mixed refinement, whose
+    // tolerance (1e-5 by default) is far above complex64 rounding
+    const size_t perk = (size_t)R * (S.n1 + n2p) * (mixed ? 8 : 16);
     const int nwork = 2 + (mixed ? 2 : 0);
     c->solmem.release();
     int m = o.krylov;
@@ -1664,7 +1672,7 @@ void solve_response(lrcc_ctx *c, int R, const double *omega_dev, const Vecs &b, 
     if (o.mem_cap_bytes > 0 && need > (size_t)o.mem_cap_bytes)
         throw LrccError(LRCC_E_OOM, "solver work vectors exceed the memory cap");
     GmresWork W;
-    gmres_alloc(c, W, R, m, S.n1, st);
+    gmres_alloc(c, W, R, m, S.n1, mixed ? 1 : 0, st);
     auto mk = [&]() { Vecs v; v.s = c->solmem.get((size_t)R * S.n1 * 16); v.d = c->solmem.get((size_t)R * S.n2 * 16); return v; };
     Vecs w = mk(), z = mk();
     S.part = c->solmem.get((size_t)R * dot_blocks(S.n2) * 16);

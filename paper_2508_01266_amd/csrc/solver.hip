@@ -15,6 +15,16 @@ namespace {
 constexpr int DB = 256;
 }
 
+// Krylov vectors are kept in complex128 (double2) or, for the complex64 inner solves of the
+// mixed refinement, in complex64 (float2); the arithmetic on them is complex128 either way.
+static __device__ __forceinline__ double2 ld2(const double2 *p, i64 i) { return p[i]; }
+static __device__ __forceinline__ double2 ld2(const float2 *p, i64 i) {
+    const float2 v = p[i];
+    return make_double2(v.x, v.y);
+}
+static __device__ __forceinline__ void st2(double2 *p, i64 i, double2 v) { p[i] = v; }
+static __device__ __forceinline__ void st2(float2 *p, i64 i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
 // part[r][b] = sum over the fixed chunk b of conj(u_r) * v_r
 __global__ void __launch_bounds__(DB) k_dot_partial(const double2 *u, const double2 *v, i64 n, int nblk, double2 *part,
                                                      int conj_u) {
@@ -75,6 +85,32 @@ __global__ void k_axpby(double2 *y, const double2 *x, const double2 *alpha, doub
         yv.y = beta * yv.y + a.x * xv.y + a.y * xv.x;
         y[t] = yv;
     }
+}
+
+// y_r = beta * y_r + alpha_r * x_r on Krylov-vector storage (complex128 or complex64)
+template <typename V>
+__global__ void k_basis_axpby(V *y, const V *x, const double2 *alpha, double beta, int R, i64 n) {
+    const i64 N = (i64)R * n;
+    for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
+        const int r = (int)(t / n);
+        const double2 a = alpha[r], xv = ld2(x, t);
+        double2 yv = beta == 0.0 ? make_double2(0, 0) : ld2(y, t);
+        yv.x = beta * yv.x + a.x * xv.x - a.y * xv.y;
+        yv.y = beta * yv.y + a.x * xv.y + a.y * xv.x;
+        st2(y, t, yv);
+    }
+}
+
+hipError_t basis_axpby(void *y, const void *x, const void *alpha, double beta, int R, i64 n, int f32, hipStream_t s) {
+    i64 g = ((i64)R * n + 255) / 256;
+    g = std::max<i64>(1, std::min<i64>(g, 262144));
+    if (f32)
+        hipLaunchKernelGGL(k_basis_axpby<float2>, dim3((unsigned)g), dim3(256), 0, s, (float2 *)y, (const float2 *)x,
+                           (const double2 *)alpha, beta, R, n);
+    else
+        hipLaunchKernelGGL(k_basis_axpby<double2>, dim3((unsigned)g), dim3(256), 0, s, (double2 *)y,
+                           (const double2 *)x, (const double2 *)alpha, beta, R, n);
+    return hipGetLastError();
 }
 
 hipError_t batched_axpby(void *y, const void *x, const void *alpha, double beta, int R, i64 n, hipStream_t s) {
@@ -174,9 +210,9 @@ int pack_tables(const KMesh &km, std::vector<int> &canon, std::vector<int> &map,
 }
 
 // singles: o1 = a1 - b1; doubles: o2[r][p] = scale[p] (a2 - b2)[r][canon[p]] (b may be null)
-__global__ void k_pack(double2 *o1, double2 *o2, const double2 *a1, const double2 *a2, const double2 *b1,
-                       const double2 *b2, const int *canon, const double *scale, int R, i64 n1, int np, i64 blk,
-                       i64 n2) {
+template <typename V>
+__global__ void k_pack(V *o1, V *o2, const double2 *a1, const double2 *a2, const double2 *b1, const double2 *b2,
+                       const int *canon, const double *scale, int R, i64 n1, int np, i64 blk, i64 n2) {
     const i64 n2p = (i64)np * blk, N1 = (i64)R * n1;
     const i64 N = N1 + (i64)R * n2p;
     for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < N; t += (i64)gridDim.x * blockDim.x) {
@@ -187,7 +223,7 @@ __global__ void k_pack(double2 *o1, double2 *o2, const double2 *a1, const double
                 x.x -= y.x;
                 x.y -= y.y;
             }
-            o1[t] = x;
+            st2(o1, t, x);
         } else {
             const i64 u = t - N1;
             const int r = (int)(u / n2p);
@@ -201,27 +237,34 @@ __global__ void k_pack(double2 *o1, double2 *o2, const double2 *a1, const double
                 x.y -= y.y;
             }
             const double sc = scale[p];
-            o2[u] = make_double2(sc * x.x, sc * x.y);
+            st2(o2, u, make_double2(sc * x.x, sc * x.y));
         }
     }
 }
 
 hipError_t pack_vec(void *o1, void *o2p, const void *a1, const void *a2, const void *b1, const void *b2,
-                    const PackMap &pm, int R, i64 n1, i64 blk, hipStream_t s) {
+                    const PackMap &pm, int R, i64 n1, i64 blk, int f32, hipStream_t s) {
     const i64 n2 = (i64)pm.nfull * blk;
     const i64 N = (i64)R * (n1 + (i64)pm.np * blk);
     i64 g = (N + 255) / 256;
     if (g > 262144) g = 262144;
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s, (double2 *)o1, (double2 *)o2p,
-                       (const double2 *)a1, (const double2 *)a2, (const double2 *)b1, (const double2 *)b2, pm.canon,
-                       pm.scale, R, n1, pm.np, blk, n2);
+    const dim3 grid((unsigned)std::max<i64>(g, 1));
+    if (f32)
+        hipLaunchKernelGGL(k_pack<float2>, grid, dim3(256), 0, s, (float2 *)o1, (float2 *)o2p, (const double2 *)a1,
+                           (const double2 *)a2, (const double2 *)b1, (const double2 *)b2, pm.canon, pm.scale, R, n1,
+                           pm.np, blk, n2);
+    else
+        hipLaunchKernelGGL(k_pack<double2>, grid, dim3(256), 0, s, (double2 *)o1, (double2 *)o2p, (const double2 *)a1,
+                           (const double2 *)a2, (const double2 *)b1, (const double2 *)b2, pm.canon, pm.scale, R, n1,
+                           pm.np, blk, n2);
     return hipGetLastError();
 }
 
 // The preconditioned full vector of a packed one: doubles element (ki,kj,ka)(i,j,a,b) from the
 // orbit's block at the swapped indices, with the sign of the swaps and 1/scale, both parts
 // divided by the denominators of k_precond.
-__global__ void k_unpack_precond(double2 *o1, double2 *o2, const double2 *i1, const double2 *i2p, const int *map,
+template <typename V>
+__global__ void k_unpack_precond(double2 *o1, double2 *o2, const V *i1, const V *i2p, const int *map,
                                  const double *scale, const double *eo, const double *ev, const double *eo2,
                                  const double *ev2, const double *omega, KMesh km, int R, int no, int nv, int np) {
     const int nk = km.size();
@@ -239,7 +282,7 @@ __global__ void k_unpack_precond(double2 *o1, double2 *o2, const double2 *i1, co
             const int i = (int)(q % no);
             const int k = (int)(q / no);
             d = ev[k * nv + a] - eo[k * no + i] - (omega ? omega[r] : 0.0);
-            x = i1[t];
+            x = ld2(i1, t);
             dst = o1 + t;
         } else {
             const i64 u = t - (i64)R * n1;
@@ -255,7 +298,7 @@ __global__ void k_unpack_precond(double2 *o1, double2 *o2, const double2 *i1, co
             const int m = map[f], p = m >> 2;
             const bool fi = (m & 2) != 0, fa = (m & 1) != 0;
             const int ii = fi ? j : i, jj = fi ? i : j, aa = fa ? b : a, bb = fa ? a : b;
-            const double2 y = i2p[(i64)r * n2p + (i64)p * blk + (((i64)ii * no + jj) * nv + aa) * nv + bb];
+            const double2 y = ld2(i2p, (i64)r * n2p + (i64)p * blk + (((i64)ii * no + jj) * nv + aa) * nv + bb);
             const double sg = (fi != fa ? -1.0 : 1.0) / scale[p];
             x = make_double2(sg * y.x, sg * y.y);
             d = ev2[ka * nv + a] + ev2[kb * nv + b] - eo2[ki * no + i] - eo2[kj * no + j] - (omega ? omega[r] : 0.0);
@@ -268,14 +311,20 @@ __global__ void k_unpack_precond(double2 *o1, double2 *o2, const double2 *i1, co
 
 hipError_t unpack_precond(void *o1, void *o2, const void *i1, const void *i2p, const PackMap &pm, const double *eo,
                           const double *ev, const double *eo2, const double *ev2, const double *omega, KMesh km,
-                          int R, int no, int nv, hipStream_t s) {
+                          int R, int no, int nv, int f32, hipStream_t s) {
     const int nk = km.size();
     const i64 N = (i64)R * ((i64)nk * no * nv + (i64)nk * nk * nk * no * no * nv * nv);
     i64 g = (N + 255) / 256;
     if (g > 262144) g = 262144;
-    hipLaunchKernelGGL(k_unpack_precond, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s, (double2 *)o1,
-                       (double2 *)o2, (const double2 *)i1, (const double2 *)i2p, pm.map, pm.scale, eo, ev, eo2, ev2,
-                       omega, km, R, no, nv, pm.np);
+    const dim3 grid((unsigned)std::max<i64>(g, 1));
+    if (f32)
+        hipLaunchKernelGGL(k_unpack_precond<float2>, grid, dim3(256), 0, s, (double2 *)o1, (double2 *)o2,
+                           (const float2 *)i1, (const float2 *)i2p, pm.map, pm.scale, eo, ev, eo2, ev2, omega, km, R,
+                           no, nv, pm.np);
+    else
+        hipLaunchKernelGGL(k_unpack_precond<double2>, grid, dim3(256), 0, s, (double2 *)o1, (double2 *)o2,
+                           (const double2 *)i1, (const double2 *)i2p, pm.map, pm.scale, eo, ev, eo2, ev2, omega, km,
+                           R, no, nv, pm.np);
     return hipGetLastError();
 }
 
@@ -328,9 +377,9 @@ constexpr int MDV = 8;         // basis vectors per multi-dot workgroup
 }
 
 // part[(r*k + i)*nblk + b] = sum over chunk b of conj(V_i[r]) w[r] (singles weight 1, doubles dw)
-__global__ void __launch_bounds__(MD) k_multidot_partial(const double2 *Vs, const double2 *Vd, const double2 *ws,
-                                                         const double2 *wd, int R, i64 n1, i64 n2, int k, int nblk,
-                                                         double dw, double2 *part) {
+template <typename V>
+__global__ void __launch_bounds__(MD) k_multidot_partial(const V *Vs, const V *Vd, const V *ws, const V *wd, int R,
+                                                         i64 n1, i64 n2, int k, int nblk, double dw, double2 *part) {
     __shared__ double sr[MDV][MD], si[MDV][MD];
     const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MDV, t = threadIdx.x;
     const int nv = min(MDV, k - i0);
@@ -341,13 +390,13 @@ __global__ void __launch_bounds__(MD) k_multidot_partial(const double2 *Vs, cons
     for (i64 e = (i64)b * MD + t; e < N; e += (i64)nblk * MD) {
         const bool single = e < n1;
         const i64 off = single ? (i64)r * n1 + e : (i64)r * n2 + (e - n1);
-        const double2 y = single ? ws[off] : wd[off];
+        const double2 y = single ? ld2(ws, off) : ld2(wd, off);
         const double wt = single ? 1.0 : dw;
 #pragma unroll
         for (int q = 0; q < MDV; ++q) {
             if (q < nv) {
                 const i64 vo = single ? (i64)(i0 + q) * R * n1 + off : (i64)(i0 + q) * R * n2 + off;
-                const double2 x = single ? Vs[vo] : Vd[vo];
+                const double2 x = single ? ld2(Vs, vo) : ld2(Vd, vo);
                 ar[q] += wt * (x.x * y.x + x.y * y.y);
                 ai[q] += wt * (x.x * y.y - x.y * y.x);
             }
@@ -385,11 +434,16 @@ int multidot_blocks(i64 n) {
 }
 
 hipError_t multidot(const void *Vs, const void *Vd, const void *ws, const void *wd, int R, i64 n1, i64 n2, int k,
-                    void *part, void *out, int ostride, double dw, hipStream_t s) {
+                    void *part, void *out, int ostride, double dw, int f32, hipStream_t s) {
     const int nblk = multidot_blocks(n1 + n2);
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, R, (k + MDV - 1) / MDV), dim3(MD), 0, s, (const double2 *)Vs,
-                       (const double2 *)Vd, (const double2 *)ws, (const double2 *)wd, R, n1, n2, k, nblk, dw,
-                       (double2 *)part);
+    const dim3 grid(nblk, R, (k + MDV - 1) / MDV);
+    if (f32)
+        hipLaunchKernelGGL(k_multidot_partial<float2>, grid, dim3(MD), 0, s, (const float2 *)Vs, (const float2 *)Vd,
+                           (const float2 *)ws, (const float2 *)wd, R, n1, n2, k, nblk, dw, (double2 *)part);
+    else
+        hipLaunchKernelGGL(k_multidot_partial<double2>, grid, dim3(MD), 0, s, (const double2 *)Vs,
+                           (const double2 *)Vd, (const double2 *)ws, (const double2 *)wd, R, n1, n2, k, nblk, dw,
+                           (double2 *)part);
     hipLaunchKernelGGL(k_multidot_final, dim3((R * k + 63) / 64), dim3(64), 0, s, (const double2 *)part, R, k, nblk,
                        (double2 *)out, ostride);
     return hipGetLastError();
@@ -397,9 +451,10 @@ hipError_t multidot(const void *Vs, const void *Vd, const void *ws, const void *
 
 // w[r] = beta w[r] + sum_{i<k} c_r,i V_i[r], c_r,i = sign * C[r*cstride + i], zero where mask[r] == 0
 // (mask may be null); singles and doubles in one launch (grid y = right-hand side)
-__global__ void __launch_bounds__(MD) k_multiaxpy(double2 *ws, double2 *wd, const double2 *Vs, const double2 *Vd,
-                                                  const double2 *C, int cstride, double sign, const int *mask,
-                                                  double beta, int R, i64 n1, i64 n2, int k) {
+template <typename V>
+__global__ void __launch_bounds__(MD) k_multiaxpy(V *ws, V *wd, const V *Vs, const V *Vd, const double2 *C,
+                                                  int cstride, double sign, const int *mask, double beta, int R, i64 n1,
+                                                  i64 n2, int k) {
     __shared__ double2 c[64];
     const int r = blockIdx.y;
     const bool on = !mask || mask[r] != 0;
@@ -412,27 +467,32 @@ __global__ void __launch_bounds__(MD) k_multiaxpy(double2 *ws, double2 *wd, cons
     for (i64 e = (i64)blockIdx.x * MD + threadIdx.x; e < N; e += (i64)gridDim.x * MD) {
         const bool single = e < n1;
         const i64 off = single ? (i64)r * n1 + e : (i64)r * n2 + (e - n1);
-        double2 *wp = single ? ws + off : wd + off;
-        double2 acc = beta == 0.0 ? make_double2(0, 0) : *wp;
+        V *wp = single ? ws + off : wd + off;
+        double2 acc = beta == 0.0 ? make_double2(0, 0) : ld2(wp, 0);
         acc.x *= beta;
         acc.y *= beta;
         for (int i = 0; i < k; ++i) {
             const i64 vo = single ? (i64)i * R * n1 + off : (i64)i * R * n2 + off;
-            const double2 x = single ? Vs[vo] : Vd[vo];
+            const double2 x = single ? ld2(Vs, vo) : ld2(Vd, vo);
             acc.x += c[i].x * x.x - c[i].y * x.y;
             acc.y += c[i].x * x.y + c[i].y * x.x;
         }
-        *wp = acc;
+        st2(wp, 0, acc);
     }
 }
 
 hipError_t multiaxpy(void *ws, void *wd, const void *Vs, const void *Vd, const void *C, int cstride, double sign,
-                     const int *mask, double beta, int R, i64 n1, i64 n2, int k, hipStream_t s) {
+                     const int *mask, double beta, int R, i64 n1, i64 n2, int k, int f32, hipStream_t s) {
     if (k > 64) return hipErrorInvalidValue;
     const i64 g = std::max<i64>(1, std::min<i64>((n1 + n2 + MD - 1) / MD, 4096));
-    hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)g, R), dim3(MD), 0, s, (double2 *)ws, (double2 *)wd,
-                       (const double2 *)Vs, (const double2 *)Vd, (const double2 *)C, cstride, sign, mask, beta, R,
-                       n1, n2, k);
+    if (f32)
+        hipLaunchKernelGGL(k_multiaxpy<float2>, dim3((unsigned)g, R), dim3(MD), 0, s, (float2 *)ws, (float2 *)wd,
+                           (const float2 *)Vs, (const float2 *)Vd, (const double2 *)C, cstride, sign, mask, beta, R,
+                           n1, n2, k);
+    else
+        hipLaunchKernelGGL(k_multiaxpy<double2>, dim3((unsigned)g, R), dim3(MD), 0, s, (double2 *)ws, (double2 *)wd,
+                           (const double2 *)Vs, (const double2 *)Vd, (const double2 *)C, cstride, sign, mask, beta,
+                           R, n1, n2, k);
     return hipGetLastError();
 }
 
@@ -569,10 +629,10 @@ hipError_t gmres_status(const GmresState &g, double *out, hipStream_t s) {
 }
 
 // per-right-hand-side norms^2 into out[r] (as complex, real part) via the multi-dot of w with itself
-hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, double dw,
+hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, double dw, int f32,
                    hipStream_t s) {
     // V_0 = w with a one-vector "space": stride arguments make vector 0 the vector itself
-    return multidot(ws, wd, ws, wd, R, n1, n2, 1, part, out, 1, dw, s);
+    return multidot(ws, wd, ws, wd, R, n1, n2, 1, part, out, 1, dw, f32, s);
 }
 
 }  // namespace lrcc

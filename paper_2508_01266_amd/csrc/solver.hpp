@@ -9,6 +9,10 @@ int dot_blocks(i64 n);
 hipError_t batched_dot(const void *u, const void *v, int R, i64 n, double scale, void *part, void *out, hipStream_t s,
                        int conj_u = 1);
 hipError_t batched_axpby(void *y, const void *x, const void *alpha, double beta, int R, i64 n, hipStream_t s);
+// Krylov vectors (and the vectors orthogonalised against them) are stored in complex128, or in
+// complex64 with f32 = 1 (the complex64 inner solves); arithmetic is complex128 in both.
+// y = beta y + alpha_r x on that storage
+hipError_t basis_axpby(void *y, const void *x, const void *alpha, double beta, int R, i64 n, int f32, hipStream_t s);
 // singles divided by (ev - eo - w), doubles by (ev2 + ev2 - eo2 - eo2 - w)
 hipError_t precond(void *o1, void *o2, const void *i1, const void *i2, const double *eo, const double *ev,
                    const double *eo2, const double *ev2, const double *omega, KMesh km, int R, int no, int nv,
@@ -30,11 +34,11 @@ int pack_tables(const KMesh &km, std::vector<int> &canon, std::vector<int> &map,
 // packed = a - b (b1, b2 may be null): singles [R][n1] copied, doubles [R][nfull][blk] gathered
 // into [R][np][blk] and scaled
 hipError_t pack_vec(void *o1, void *o2p, const void *a1, const void *a2, const void *b1, const void *b2,
-                    const PackMap &pm, int R, i64 n1, i64 blk, hipStream_t s);
+                    const PackMap &pm, int R, i64 n1, i64 blk, int f32, hipStream_t s);
 // full = the preconditioner (as precond) applied to the unpacked vector (antisymmetry signs filled in)
 hipError_t unpack_precond(void *o1, void *o2, const void *i1, const void *i2p, const PackMap &pm, const double *eo,
                           const double *ev, const double *eo2, const double *ev2, const double *omega, KMesh km,
-                          int R, int no, int nv, hipStream_t s);
+                          int R, int no, int nv, int f32, hipStream_t s);
 // Y[r] = beta Y[r] + sum_i C[r][i] V[i]  (complex128; V: [m][n], Y: [R][n], C: device [R][m])
 hipError_t combine(void *Y, const void *V, const void *C, int R, int m, i64 n, double beta, hipStream_t s);
 
@@ -56,12 +60,12 @@ struct GmresState {
 // antisymmetric doubles, 1 for packed ones), i < k
 int multidot_blocks(i64 n);
 hipError_t multidot(const void *Vs, const void *Vd, const void *ws, const void *wd, int R, i64 n1, i64 n2, int k,
-                    void *part, void *out, int ostride, double dw, hipStream_t s);
-hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, double dw,
+                    void *part, void *out, int ostride, double dw, int f32, hipStream_t s);
+hipError_t selfdot(const void *ws, const void *wd, int R, i64 n1, i64 n2, void *part, void *out, double dw, int f32,
                    hipStream_t s);
 // w[r] = beta w[r] + sign * sum_{i<k} C[r*cstride + i] V_i[r] (masked rows: w[r] = beta w[r]); k <= 64
 hipError_t multiaxpy(void *ws, void *wd, const void *Vs, const void *Vd, const void *C, int cstride, double sign,
-                     const int *mask, double beta, int R, i64 n1, i64 n2, int k, hipStream_t s);
+                     const int *mask, double beta, int R, i64 n1, i64 n2, int k, int f32, hipStream_t s);
 hipError_t gmres_init(const GmresState &g, const void *beta2, double tol, hipStream_t s);
 // h2: the second Gram-Schmidt pass's coefficients, or null after a single pass
 hipError_t gmres_step(const GmresState &g, int j, const void *h1, const void *h2, const void *hn2, double tol,
