@@ -717,8 +717,12 @@ struct SigmaGraph {
     KT x1, x2, Z, s1;
 };
 
+// Term sets of record_sigma: the full Jacobian; the lean one, without the term -x_ie R_jabe (for
+// the blocks of the lean precompute, whose H_abej lacks R); that term alone.
+enum SigmaTerms { TERMS_ALL = 0, TERMS_LEAN = 1, TERMS_R = 2 };
+
 template <typename T>
-SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, bool lean = false) {
+SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, int terms = TERMS_ALL) {
     SigmaGraph G;
     auto A = [&](const char *cls, std::initializer_list<int> sg = {1, 1, -1, -1}) {
         KT t = alloc_kt<T>(c, wm, cls, R, sg);
@@ -757,6 +761,14 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     KT dFae = A("vv"), dFmi = A("oo"), dFme = A("ov"), dFbe = A("vv"), dFmj = A("oo");
     KT Zmn = A("oooo"), Vx = A("oooo"), Yx = A("oovo");
     G.x1 = x1; G.x2 = x2; G.Z = Z; G.s1 = s1;
+    if (terms == TERMS_R) {
+        // -x_ie R_jabe = -sum_mf t_jmaf Q_ibmf, Q_ibmf = sum_e x_ie <mb||fe> (k_i + k_f = k_b + k_m):
+        // linear in t2, so its change along a direction y of the amplitudes is this term with t2 = y2
+        KT Q = A("ovov", {1, -1, -1, 1});
+        con(Q, "Ribmf", x1, "Rie", S.g_ovvv, "mbfe", 1.0, false);
+        con(Z, "Rijab", S.t2, "jmaf", Q, "Ribmf", -1.0, false);
+        return G;
+    }
     if (full) {
         SymOp op;
         op.kind = SymOp::TAU;
@@ -842,15 +854,7 @@ SigmaGraph record_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full =
     con(Yx, "Rijan", x1, "Rjf", S.U, "ianf", 1.0, false);
     con(Yx, "Rijan", Vx, "Rijmn", t1, "ma", -0.25);
     con(Z, "Rijab", Yx, "Rijan", t1, "nb", -1.0);
-    con(Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);
-    if (lean) {
-        // H from the lean precompute lacks -R_jabe = -sum_mf t_jmaf <mb||fe>: with few right-hand
-        // sides the term is cheaper from x1 than R is once (o^2 v^3 + o^3 v^3 per vector against
-        // o^2 v^4): Q_ibmf = sum_e x_ie <mb||fe> (k_i + k_f = k_b + k_m), Z -= t_jmaf Q_ibmf
-        KT Q = A("ovov", {1, -1, -1, 1});
-        con(Q, "Ribmf", x1, "Rie", S.g_ovvv, "mbfe", 1.0, false);
-        con(Z, "Rijab", t2, "jmaf", Q, "Ribmf", -1.0);
-    }
+    con(Z, "Rijab", x1, "Rie", S.H, "abej", 1.0);   // with TERMS_LEAN, H lacks its R part
     con(Z, "Rijab", S.G2, "ijbm", x1, "Rma", -1.0);
     return G;
 }
@@ -962,10 +966,10 @@ void ladder_block_gemms(lrcc_ctx *c, Program &P, bool transpose, const void *A, 
 }
 
 template <typename T>
-Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, bool lean = false) {
+Program *build_sigma(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, int terms = TERMS_ALL) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
-    SigmaGraph G = record_sigma<T>(c, S, R, wm, full, lean);
+    SigmaGraph G = record_sigma<T>(c, S, R, wm, full, terms);
     const i64 nb3 = (i64)nk * nk * nk;
     KT x1 = G.x1, x2 = G.x2, Z = G.Z, s1 = G.s1;
     // caller layout -> internal (paper -> crystal normalisation for doubles)
@@ -1056,10 +1060,11 @@ void emit_reverse_sweep(lrcc_ctx *c, State<T> &S, int R, const SigmaGraph &G, Pr
                         const void *const *z1src, const void *const *z2src);
 
 template <typename T>
-Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true, bool lean = false) {
+Program *build_sigma_adjoint(lrcc_ctx *c, State<T> &S, int R, DevMem &wm, bool full = true,
+                             int terms = TERMS_ALL) {
     const int nk = c->nk, o = c->no, v = c->nv;
     auto P = new Program();
-    SigmaGraph G = record_sigma<T>(c, S, R, wm, full, lean);
+    SigmaGraph G = record_sigma<T>(c, S, R, wm, full, terms);
     emit_reverse_sweep<T>(c, S, R, G, P, &c->io_x1, &c->io_x2);
     KT x1 = G.x1, x2 = G.x2;
     // y1 = x1bar - omega z1 ; y2 = P(ij)P(ab) x2bar / Nk - omega z2
@@ -1232,18 +1237,20 @@ hipError_t run_sigma(lrcc_ctx *c, Program *p, hipStream_t st) {
 
 // variant 0: the CCSD Jacobian; variant 1+x: the Jacobian of the one-body
 // perturbation residual for dipole axis x (Fock matrix -> mu_x, no two-electron part);
-// kLeanSigma: the CCSD Jacobian (complex128) on the blocks of the lean precompute.
-constexpr int kLeanSigma = -1;
+// kLeanSigma: the CCSD Jacobian (complex128) without the term -x_ie R_jabe, on the blocks of the
+// lean precompute; kRTermSigma: that term alone (complex128).
+constexpr int kLeanSigma = -1, kRTermSigma = -2;
 Program *sigma_program(lrcc_ctx *c, int prec, int R, bool adjoint = false, int variant = 0) {
     auto key = std::make_pair(variant * 4 + prec * 2 + (adjoint ? 1 : 0), R);
     auto it = c->progs.find(key);
     if (it != c->progs.end()) return it->second.get();
     auto mem = std::make_unique<DevMem>();
     Program *p;
-    if (variant == kLeanSigma) {
+    if (variant == kLeanSigma || variant == kRTermSigma) {
         if (prec != LRCC_FP64) throw LrccError(LRCC_E_ARG, "the lean sigma is FP64 only");
-        p = adjoint ? build_sigma_adjoint<double>(c, c->s64, R, *mem, true, true)
-                    : build_sigma<double>(c, c->s64, R, *mem, true, true);
+        const int terms = variant == kLeanSigma ? TERMS_LEAN : TERMS_R;
+        p = adjoint ? build_sigma_adjoint<double>(c, c->s64, R, *mem, true, terms)
+                    : build_sigma<double>(c, c->s64, R, *mem, true, terms);
     } else if (variant > 0) {
         if (prec != LRCC_FP64) throw LrccError(LRCC_E_ARG, "perturbation operators are FP64 only");
         State<double> &X = c->xs[variant - 1];
@@ -1881,7 +1888,9 @@ void eta_vector(lrcc_ctx *c, int x, const Vecs &out, hipStream_t st) {
 // re-runs the amplitude-dependent blocks when all stencils are done.
 // With p0 = A(T)^T lambda at the unshifted amplitudes (the same for every y), three
 // shifted points suffice: p'(0) = (6 p(h) - 2 p(-h) - p(2h) - 3 p(0)) / (6h) is exact for
-// the cubic p(e) = A(T + e y)^T lambda.
+// the cubic p(e) = A(T + e y)^T lambda.  The stencil runs on the lean transpose (lean blocks,
+// without the term -x_ie R_jabe, and p0 without it, from lambda_product); that term, linear
+// in t2, adds its exact derivative once per direction.
 void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vecs &q, const void *T1,
               const void *T2, hipStream_t st, const Vecs *p0 = nullptr) {
     const int nk = c->nk;
@@ -1916,6 +1925,17 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         HIPCHK(hipMemsetAsync(Fy.s, 0, n1 * 16, st));
         HIPCHK(hipMemsetAsync(Fy.d, 0, n2 * 16, st));
     }
+    // The term -x_ie R_jabe of the transpose is linear in t2 and depends on nothing else that
+    // moves: its part of the derivative is the term with t2 = y2 (crystal normalisation y2 / Nk),
+    // formed once; the stencil points run the lean transpose without it.
+    {
+        Program *rt = sigma_program(c, LRCC_FP64, 1, true, kRTermSigma);
+        HIPCHK(scale_copy(S.t2.p, y.d, 1.0 / nk, 0.0, nt2, st));
+        c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
+        HIPCHK(rt->run(st));
+        HIPCHK(add_inplace<double>(Fy.s, q.s, n1, st));
+        HIPCHK(add_inplace<double>(Fy.d, q.d, n2, st));
+    }
     for (int k = 0; k < npt; ++k) {
         // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
         HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
@@ -1949,11 +1969,20 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
     HIPCHK(add_inplace<double>(Fy.s, c->ubuf, n1, st));
 }
 
-// p0 = A(T)^T lambda at the current amplitudes (shared by every F stencil)
-void lambda_product(lrcc_ctx *c, const Vecs &p0, hipStream_t st) {
+// p0 = A(T)^T lambda without the term -x_ie R_jabe (the lean transpose of the F stencils) at the
+// current amplitudes, shared by every F stencil: the full product minus that term; q is scratch.
+void lambda_product(lrcc_ctx *c, const Vecs &p0, const Vecs &q, hipStream_t st) {
+    const i64 n1 = (i64)c->nk * c->no * c->nv, n2 = (i64)c->nk * c->nk * c->nk * c->no * c->no * c->nv * c->nv;
     Program *adj = sigma_program(c, LRCC_FP64, 1, true);
     c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = p0.s; c->io_y2 = p0.d; c->io_omega = nullptr;
     HIPCHK(adj->run(st));
+    Program *rt = sigma_program(c, LRCC_FP64, 1, true, kRTermSigma);
+    c->io_y1 = q.s; c->io_y2 = q.d;
+    HIPCHK(rt->run(st));
+    HIPCHK(scale_copy(q.s, q.s, -1.0, 0.0, n1, st));
+    HIPCHK(scale_copy(q.d, q.d, -1.0, 0.0, n2, st));
+    HIPCHK(add_inplace<double>(p0.s, q.s, n1, st));
+    HIPCHK(add_inplace<double>(p0.d, q.d, n2, st));
 }
 
 // The density programs' amplitude copies are filled from the context's amplitudes by
@@ -2167,7 +2196,7 @@ void solve_alpha(lrcc_ctx *c, unsigned axis_mask, int nfreq, const double *omega
         HIPCHK(hipMemcpy(T1, S.t1.p, nt1 * 16, hipMemcpyDeviceToDevice));
         HIPCHK(hipMemcpy(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice));
         Vecs Fy = vec(1), q = vec(1), p0 = vec(1);
-        lambda_product(c, p0, st);
+        lambda_product(c, p0, q, st);
         ++extra_rhs_sig;
         for (int j = 0; j < nfreq; ++j)
             for (int b = 0; b < nax; ++b) {
@@ -2253,7 +2282,7 @@ void alpha_lambda_bar(lrcc_ctx *c, const lrcc_solve_opts &o, double *out, lrcc_s
         HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         Vecs q = vec(1), p0 = vec(1);
-        lambda_product(c, p0, st);
+        lambda_product(c, p0, q, st);
         for (int j = 0; j < nfreq; ++j)
             for (int sg = 0; sg < 2; ++sg)
                 for (int a = 0; a < nax; ++a) {
@@ -2352,7 +2381,7 @@ void alpha_dip_grad(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_opts &o, 
         HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         Vecs q = vec(1), p0 = vec(1);
-        lambda_product(c, p0, st);
+        lambda_product(c, p0, q, st);
         for (int b = 0; b < nb; ++b) {
             Vecs bb = sub(B, b);
             f_vector(c, D, tv[b], bb, q, T1, T2, st, &p0);
@@ -2601,7 +2630,7 @@ GradAdjoints grad_adjoints(lrcc_ctx *c, int j, int X, int Y, const lrcc_solve_op
         HIPCHK(hipMemcpyAsync(T2, S.t2.p, nt2 * 16, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         Vecs q = vec(1), p0 = vec(1);
-        lambda_product(c, p0, st);
+        lambda_product(c, p0, q, st);
         for (int b = 0; b < 4; ++b) {
             Vecs bb = sub(B, b);
             f_vector(c, D, tv[b], bb, q, T1, T2, st, &p0);
@@ -4367,6 +4396,7 @@ lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int
         (void)sigma_program(&c, LRCC_FP64, 1, true);
         (void)sigma_program(&c, LRCC_FP64, 1, true, kLeanSigma);
         (void)sigma_program(&c, LRCC_FP64, 1, false, kLeanSigma);
+        (void)sigma_program(&c, LRCC_FP64, 1, true, kRTermSigma);
         ensure_alpha_programs(&c);
         for (int x = 0; x < 3; ++x) (void)sigma_program(&c, LRCC_FP64, 1, true, 1 + x);
         (void)dens_program(&c, 1);
@@ -4380,6 +4410,7 @@ lrcc_status lrcc_plan_check_mesh(int n0, int n1, int n2, int nocc, int nvir, int
             (void)sigma_program(&c, LRCC_FP32, nrhs, adj != 0);
             (void)sigma_program(&c, LRCC_FP64, 1, adj != 0);
             (void)sigma_program(&c, LRCC_FP64, 1, adj != 0, kLeanSigma);
+            if (adj) (void)sigma_program(&c, LRCC_FP64, 1, true, kRTermSigma);
         }
     } catch (LrccError &e) {
         st = (lrcc_status)e.code;
