@@ -123,6 +123,15 @@ struct lrcc_ctx {
     // pre64 op ranges that form R_iabf and subtract it from H_abej: skipped by the lean
     // precompute, whose H lacks the R part (the lean sigma forms that term from x1 directly)
     std::vector<std::pair<size_t, size_t>> pre64_lean_skip;
+    // pre64 op ranges of U_ianf and of the t2 term of W-bar (into its first-layout buffer pre64_Wraw):
+    // both linear in t2 alone.  With lin_on, the lean precompute replaces them by B(T) + lin_eps B(y)
+    // from the buffers linU_* / linW_* (filled at T once per F evaluation and at y per direction).
+    std::pair<size_t, size_t> pre64_U{0, 0}, pre64_Wt{0, 0};
+    void *pre64_Wraw = nullptr;
+    i64 n_U = 0, n_Wraw = 0;
+    void *linU_T = nullptr, *linU_y = nullptr, *linW_T = nullptr, *linW_y = nullptr, *lin_tmp = nullptr;
+    bool lin_T_ready = false, lin_on = false;
+    double lin_eps = 0;
     void *eps_o = nullptr, *eps_v = nullptr;   // diagonal of fock per k (preconditioner)
     DevMem solmem;                             // solver work vectors
     bool lam_valid = false;
@@ -502,7 +511,11 @@ void build_state(lrcc_ctx *c) {
     kt_copy<double>(P, S.Wbar, ovvo);
     contract<double>(P, S.Wbar, "mbej", t1, "jf", ovvv, "mbef", 1.0);
     contract<double>(P, S.Wbar, "mbej", t1, "nb", ooov, "mnje", 1.0);
+    c->pre64_Wraw = S.Wbar.p;
+    c->n_Wraw = S.Wbar.count();
+    c->pre64_Wt.first = P.ops.size();
     contract<double>(P, S.Wbar, "mbej", t2, "jnfb", oovv, "mnef", -1.0);
+    c->pre64_Wt.second = P.ops.size();
     KT ytmp = alloc_kt<double>(c, m, "oovo");
     contract<double>(P, ytmp, "mnej", t1, "jf", oovv, "mnef", 1.0, false);
     contract<double>(P, S.Wbar, "mbej", t1, "nb", ytmp, "mnej", -1.0);
@@ -523,7 +536,10 @@ void build_state(lrcc_ctx *c) {
     c->pre64_lean_skip.push_back({r_begin, P.ops.size()});
     // U_ianf = sum_me t_imae <mn||ef>   (k_i + k_f = k_a + k_n)
     S.U = alloc_kt<double>(c, m, "ovov", 0, {1, -1, -1, 1});
+    c->n_U = S.U.count();
+    c->pre64_U.first = P.ops.size();
     contract<double>(P, S.U, "ianf", t2, "imae", oovv, "mnef", 1.0, false);
+    c->pre64_U.second = P.ops.size();
     // The doubles terms linear in x1 that share a contraction pattern are summed here, once per set
     // of amplitudes, so that each pattern costs one product over all (i, j, a, b) per sigma (the
     // final P(ij)P(ab) antisymmetrisation makes a term and its (i <-> j) image with opposite
@@ -668,16 +684,35 @@ void run_precompute(lrcc_ctx *c, bool fp32, hipStream_t st = nullptr, bool lean 
     tune_pre(c, c->pre64.get(), "pre64", st);
     if (fp32) tune_pre(c, c->pre32.get(), "pre32", st);
     if (lean) {
+        // skipped ranges (kind 0) and, with lin_on, the blocks linear in t2 formed from their parts
+        // at T and along y (kind 1: U, kind 2: the t2 term of W-bar)
+        std::vector<std::tuple<size_t, size_t, int>> segs;
+        for (const auto &r : c->pre64_lean_skip) segs.emplace_back(r.first, r.second, 0);
+        if (c->lin_on) {
+            segs.emplace_back(c->pre64_U.first, c->pre64_U.second, 1);
+            segs.emplace_back(c->pre64_Wt.first, c->pre64_Wt.second, 2);
+        }
+        std::sort(segs.begin(), segs.end());
+        const State<double> &S = c->s64;
         size_t at = 0;
-        for (const auto &r : c->pre64_lean_skip) {
-            HIPCHK(c->pre64->run_range(st, at, r.first));
-            at = r.second;
+        for (const auto &g : segs) {
+            HIPCHK(c->pre64->run_range(st, at, std::get<0>(g)));
+            if (std::get<2>(g) == 1) {
+                HIPCHK(scale_copy(S.U.p, c->linU_y, c->lin_eps, 0.0, c->n_U, st));
+                HIPCHK(add_inplace<double>(S.U.p, c->linU_T, c->n_U, st));
+            } else if (std::get<2>(g) == 2) {
+                HIPCHK(scale_copy(c->lin_tmp, c->linW_y, c->lin_eps, 0.0, c->n_Wraw, st));
+                HIPCHK(add_inplace<double>(c->pre64_Wraw, c->lin_tmp, c->n_Wraw, st));
+                HIPCHK(add_inplace<double>(c->pre64_Wraw, c->linW_T, c->n_Wraw, st));
+            }
+            at = std::get<1>(g);
         }
         HIPCHK(c->pre64->run_range(st, at, c->pre64->ops.size()));
         if (fp32) HIPCHK(c->pre32->run(st));
         HIPCHK(hipStreamSynchronize(st));
         return;
     }
+    c->lin_T_ready = c->lin_on = false;   // the parts at T belong to the amplitudes they were taken at
     if (timed) {
         const bool was = c->prof.on;
         c->prof.on = true;
@@ -1936,6 +1971,16 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         HIPCHK(add_inplace<double>(Fy.s, q.s, n1, st));
         HIPCHK(add_inplace<double>(Fy.d, q.d, n2, st));
     }
+    // U_ianf and the t2 term of W-bar are linear in t2 alone: their parts along y (t2 = y2 / Nk still
+    // in place), once; each stencil point then forms B(T) + e B(y) instead of building B
+    if (c->lin_T_ready) {
+        HIPCHK(c->pre64->run_range(st, c->pre64_U.first, c->pre64_U.second));
+        HIPCHK(hipMemcpyAsync(c->linU_y, S.U.p, (size_t)c->n_U * 16, hipMemcpyDeviceToDevice, st));
+        HIPCHK(zero_fill<double>(c->pre64_Wraw, c->n_Wraw, st));
+        HIPCHK(c->pre64->run_range(st, c->pre64_Wt.first, c->pre64_Wt.second));
+        HIPCHK(hipMemcpyAsync(c->linW_y, c->pre64_Wraw, (size_t)c->n_Wraw * 16, hipMemcpyDeviceToDevice, st));
+        c->lin_on = true;
+    }
     for (int k = 0; k < npt; ++k) {
         // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
         HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
@@ -1948,6 +1993,7 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         HIPCHK(hipMemcpy(D.alpha, a2.data(), 16, hipMemcpyHostToDevice));
         HIPCHK(batched_axpby(S.t2.p, y.d, D.alpha, 1.0, 1, nt2, st));
         const auto tp0 = std::chrono::steady_clock::now();
+        c->lin_eps = shift[k] * h;
         run_precompute(c, false, st, true);
         const auto tp1 = std::chrono::steady_clock::now();
         c->io_x1 = c->lam1; c->io_x2 = c->lam2; c->io_y1 = q.s; c->io_y2 = q.d; c->io_omega = nullptr;
@@ -1963,6 +2009,7 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         HIPCHK(batched_axpby(Fy.d, q.d, D.alpha, 1.0, 1, n2, st));
         HIPCHK(hipStreamSynchronize(st));
     }
+    c->lin_on = false;
     // energy part: sum <ij||ab> x_ia y_jb
     HIPCHK(hipMemcpyAsync(c->ybuf, y.s, n1 * 16, hipMemcpyDeviceToDevice, st));
     HIPCHK(c->prog_epp->run(st));
@@ -1983,6 +2030,22 @@ void lambda_product(lrcc_ctx *c, const Vecs &p0, const Vecs &q, hipStream_t st) 
     HIPCHK(scale_copy(q.d, q.d, -1.0, 0.0, n2, st));
     HIPCHK(add_inplace<double>(p0.s, q.s, n1, st));
     HIPCHK(add_inplace<double>(p0.d, q.d, n2, st));
+    // the blocks linear in t2 alone at T, for the lean precompute of the stencil points: U as the
+    // full precompute left it, the t2 term of W-bar formed alone in its (scratch) first-layout buffer
+    const State<double> &S = c->s64;
+    if (!c->linU_T) {
+        c->linU_T = c->amem.get((size_t)c->n_U * 16);
+        c->linU_y = c->amem.get((size_t)c->n_U * 16);
+        c->linW_T = c->amem.get((size_t)c->n_Wraw * 16);
+        c->linW_y = c->amem.get((size_t)c->n_Wraw * 16);
+        c->lin_tmp = c->amem.get((size_t)c->n_Wraw * 16);
+    }
+    HIPCHK(hipMemcpyAsync(c->linU_T, S.U.p, (size_t)c->n_U * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(zero_fill<double>(c->pre64_Wraw, c->n_Wraw, st));
+    HIPCHK(c->pre64->run_range(st, c->pre64_Wt.first, c->pre64_Wt.second));
+    HIPCHK(hipMemcpyAsync(c->linW_T, c->pre64_Wraw, (size_t)c->n_Wraw * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->lin_T_ready = true;
 }
 
 // The density programs' amplitude copies are filled from the context's amplitudes by
@@ -3543,6 +3606,8 @@ void setup_hamiltonian(lrcc_ctx *c, int nk, int nocc, int nvir, int naux, const 
     c->prog_grad.reset();
     c->prog_epp.reset();
     c->amem.release();
+    c->linU_T = c->linU_y = c->linW_T = c->linW_y = c->lin_tmp = nullptr;
+    c->lin_T_ready = c->lin_on = false;
     c->solv.release();
     c->sol1 = c->sol2 = nullptr;
     c->sol_bytes = 0;
