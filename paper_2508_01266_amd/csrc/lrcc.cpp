@@ -1979,8 +1979,8 @@ void f_vector(lrcc_ctx *c, SolveCtx &D, const Vecs &y, const Vecs &Fy, const Vec
         HIPCHK(zero_fill<double>(c->pre64_Wraw, c->n_Wraw, st));
         HIPCHK(c->pre64->run_range(st, c->pre64_Wt.first, c->pre64_Wt.second));
         HIPCHK(hipMemcpyAsync(c->linW_y, c->pre64_Wraw, (size_t)c->n_Wraw * 16, hipMemcpyDeviceToDevice, st));
-        c->lin_on = true;
     }
+    c->lin_on = c->lin_T_ready;   // without the parts at T the stencil points build both blocks
     for (int k = 0; k < npt; ++k) {
         // T' = T + shift*h*y  (T2 stored in crystal normalisation: y2 / Nk)
         HIPCHK(hipMemcpyAsync(S.t1.p, T1, nt1 * 16, hipMemcpyDeviceToDevice, st));
