@@ -220,3 +220,32 @@ def test_excitation_energies_equal_two_electron_spectrum(nk, o, v):
     if nk == 1:
         assert len(w) == len(exc)
         assert np.abs(np.sort(w.real) - np.sort(exc)).max() < 1e-10
+
+
+@pytest.mark.parametrize("nk,o,v", [(1, 2, 3), (2, 1, 2)])
+def test_residual_degree_in_singles_and_doubles(nk, o, v):
+    """The CCSD residual (Eqs. t1, t2), evaluated in determinant space, is a polynomial of degree 4 in
+    the amplitudes but of degree 2 along the doubles alone: along T + e y the 5th differences vanish,
+    and along a pure-doubles y the 3rd do.  So A(T) = dOmega/dT is cubic in T (the F stencil with the
+    unshifted product and three shifted points is exact) and linear in t2 at fixed t1 (the blocks that
+    depend on t2 alone change by e B(y) along y)."""
+    s = tiny_system(nk, o, v, tscale=0.1, noncanonical=0.05)
+    t1, t2 = (a.numpy() for a in s['t'])
+    y1, y2 = (a.numpy() for a in random_direction(s, 0.5))
+
+    def differences(d1, d2, h=0.5, n=6):
+        vals = []
+        for k in range(n):
+            b1, b2, _ = fockspace.brute_residual(s['f'], s['g'], nk * o, t1 + k * h * d1, t2 + k * h * d2)
+            vals.append(np.concatenate([b1.ravel(), b2.ravel()]))
+        out = []
+        for _ in range(n):
+            out.append(np.abs(vals[0]).max())
+            vals = [vals[i + 1] - vals[i] for i in range(len(vals) - 1)]
+        return out
+
+    gen, dbl, sgl = differences(y1, y2), differences(0 * y1, y2), differences(y1, 0 * y2)
+    print(f"nk={nk}: general {gen}\n  doubles {dbl}\n  singles {sgl}", flush=True)
+    assert gen[4] > 1e-4 and gen[5] < 1e-10 * gen[4]
+    assert sgl[4] > 1e-4 and sgl[5] < 1e-10 * sgl[4]
+    assert dbl[2] > 1e-4 and dbl[3] < 1e-10 * dbl[2] and dbl[4] < 1e-10 * dbl[2]
